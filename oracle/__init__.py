@@ -1,0 +1,9 @@
+"""FP64 CPU oracle for the modal heat-current path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the package smoke check and
+the benchmark's CPU-baseline leg, never by the library.  It shares no code
+with the GPU path.
+"""
+from . import modal, fft_lattice  # noqa: F401
+from .modal import *  # noqa: F401,F403
+from .fft_lattice import binned_current_fft  # noqa: F401
