@@ -1,0 +1,239 @@
+/*
+ * mhc.h -- C ABI of libmodalhc: the modal heat-current hot path of
+ * velocity-decomposition spectral thermal conductivity (HNEMA and GKMA) on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gabourie, Fan, Ala-Nissila, Pop, "Spectral Decomposition of
+ * Thermal Conductivity: Comparing Velocity Decomposition Methods in
+ * Homogeneous Molecular Dynamics Simulations", arXiv:2102.03691.
+ *
+ * Per sampled MD step s the library computes
+ *   Xdot_n(s)   = sum_i sqrt(m_i) e_{i,n} . v_i(s)                (Eq. 13)
+ *   J_n^mu(s)   = (sum_i m_i^{-1/2} (W_i(s) e_{i,n})^mu) Xdot_n(s) (Eq. 16)
+ *   J_b^mu(s)   = sum over the modes n of frequency bin b of J_n^mu(s)
+ *   J^mu(s)     = sum_i sum_nu W_i^{mu nu}(s) v_i^nu(s)             (Eq. 10)
+ * and accumulates either the HNEMA time average <J_b^mu> (Eq. 19 numerator,
+ * Sec. II.B.ii) or the GKMA correlation <J_b^mu(t+tau) J^nu(t)> and its
+ * running time integral (Eq. 17, Sec. II.B.i).  Dividing by T V F_e or by
+ * k_B T^2 V to obtain kappa is left to the caller (scalar prefactors).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Units      amu, Angstrom, fs, eV for the physics helpers; the kernels
+ *             are unit-agnostic.  Outputs are float64.
+ *  Indexing   atom i in [0, N); dof j = 3*i + alpha; mode n in [0, M), M <= 3N.
+ *  Virial     W_i^{mu nu} stored row-major W[mu][nu]; the first index is the
+ *             heat-current direction: (W v)^mu = sum_nu W^{mu nu} v^nu.
+ *  Ownership  The caller owns every pointer it passes.  Load calls copy
+ *             before returning.  mhc_push with on_device = 0 copies the host
+ *             data before returning; with on_device = 1 the device pointers
+ *             must stay valid until the work queued on the context stream has
+ *             completed (mhc_synchronize, or any read call).  The library owns
+ *             all device memory it allocates and frees it in mhc_destroy.
+ *  Errors     Every call returns an mhc_status; no C++ exception crosses the
+ *             ABI.  A failed call leaves the context as it was (except for
+ *             MHC_ERR_HIP, which is sticky: later calls report it until
+ *             mhc_destroy).  mhc_last_error gives a message.
+ *  Threads    A context is used by one host thread at a time.
+ *  Streams    Work is queued on the context's HIP stream in call order;
+ *             calls return before the GPU has finished unless stated.
+ */
+#ifndef MHC_H
+#define MHC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHC_ABI_VERSION 1
+
+typedef struct mhc_ctx mhc_ctx;
+
+typedef enum {
+  MHC_OK = 0,
+  MHC_ERR_INVALID_ARG = 1,  /* bad pointer, size, range or value            */
+  MHC_ERR_STATE = 2,        /* call not allowed in the context's state      */
+  MHC_ERR_OOM = 3,          /* device or host allocation failed             */
+  MHC_ERR_HIP = 4,          /* HIP runtime error (sticky)                   */
+  MHC_ERR_UNSUPPORTED = 5,  /* valid request this build does not implement  */
+  MHC_ERR_NONFINITE = 6     /* non-finite input found (check_finite = 1)    */
+} mhc_status;
+
+/* Arithmetic of the two contractions of Eqs. 13 and 16.  Sums over steps,
+ * bins and lags are float64 in every mode.
+ *   FP32    float32 eigenvectors and operands, float32 accumulation
+ *   BF16X3  split bfloat16: E = E_hi + E_lo and x = x_hi + x_lo, the product
+ *           is hi*hi + hi*lo + lo*hi on bf16 matrix cores with float32
+ *           accumulation (the lo*lo term is dropped)                          */
+typedef enum {
+  MHC_PREC_FP32 = 0,
+  MHC_PREC_BF16X3 = 1
+} mhc_precision;
+
+enum { MHC_HNEMA = 1, MHC_GKMA = 2 };   /* methods bitmask */
+
+typedef struct {
+  int32_t methods;       /* MHC_HNEMA | MHC_GKMA (at least one)                     */
+  int32_t precision;     /* mhc_precision                                           */
+  int32_t t_block;       /* steps per contraction: 1 = per-step matrix-vector path,
+                            otherwise 32..512 and a multiple of 32 (T-batched GEMM)  */
+  int32_t corr_len;      /* GKMA lags L (tau = 0..L-1), 1..65536; ignored for HNEMA  */
+  double dt;             /* sample interval for the GKMA integral (> 0)             */
+  int32_t check_finite;  /* 1: mhc_push rejects non-finite v or W (host inputs only) */
+  int32_t reserved[3];   /* must be zero                                            */
+} mhc_run_config;
+
+/* ---------------------------------------------------------------- lifetime */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * queue work on (NULL: the library creates and owns one).  The stream must
+ * belong to `device` and outlive the context.
+ * Errors: INVALID_ARG (out == NULL), HIP (no such device / runtime failure). */
+mhc_status mhc_create(int device, void *hip_stream, mhc_ctx **out);
+
+/* Wait for queued work, free all device memory, destroy the context.
+ * NULL is accepted and ignored. */
+mhc_status mhc_destroy(mhc_ctx *ctx);
+
+/* Message of the last failed call on ctx (never NULL; owned by ctx, valid
+ * until the next call on ctx).  With ctx == NULL: the last mhc_create error. */
+const char *mhc_last_error(const mhc_ctx *ctx);
+
+/* Static name of a status code. */
+const char *mhc_status_string(mhc_status status);
+
+/* Library ABI version (MHC_ABI_VERSION of the build). */
+int mhc_abi_version(void);
+
+/* ------------------------------------------------------------------ loading
+ * Order: load_system -> set_bins* -> configure -> load_eigvec_rows (any
+ * number of calls, any row order) -> finalize.  Any other order gives STATE. */
+
+/* Atoms and modes of the system (Sec. II.B: 3N modes; Sec. III.C allows a
+ * subset of M < 3N modes).
+ *   n_atoms   N >= 1
+ *   mass_amu  [N] host array of masses > 0 (finite)
+ *   n_modes   M, 1 <= M <= 3N
+ *   freq_thz  [M] host array of mode frequencies (finite; used for binning)
+ * Errors: INVALID_ARG, STATE (already loaded), OOM. */
+mhc_status mhc_load_system(mhc_ctx *ctx, int64_t n_atoms, const double *mass_amu,
+                           int64_t n_modes, const double *freq_thz);
+
+/* Explicit bin map (Sec. III.A bins by frequency; Sec. III.C.ii bins by mode
+ * count -- any grouping works).
+ *   n_bins       nb, 1 <= nb <= 1<<20
+ *   bin_of_mode  [M] host array, values in [-1, nb); -1 excludes the mode
+ * Errors: INVALID_ARG, STATE (no system, or eigenvector rows already loaded). */
+mhc_status mhc_set_bins(mhc_ctx *ctx, int32_t n_bins, const int32_t *bin_of_mode);
+
+/* Uniform frequency bins on [f_lo, f_hi]: width d = (f_hi - f_lo)/nb,
+ * b = min(floor((f - f_lo)/d + 1e-9), nb - 1) in float64 (ties at an edge
+ * go to the upper bin, f == f_hi to the last bin), f outside [f_lo, f_hi]
+ * excluded.  Same rule as mhc_bins_uniform.  Errors as mhc_set_bins, plus
+ * INVALID_ARG unless f_hi > f_lo (both finite). */
+mhc_status mhc_set_bins_uniform(mhc_ctx *ctx, int32_t n_bins, double f_lo, double f_hi);
+
+/* Host-only helper, no context and no GPU: the bin map mhc_set_bins_uniform
+ * would build.  out_bins [n_modes] is written.  Errors: INVALID_ARG. */
+mhc_status mhc_bins_uniform(int64_t n_modes, const double *freq_thz, int32_t n_bins,
+                            double f_lo, double f_hi, int32_t *out_bins);
+
+/* Run configuration (see mhc_run_config).  Allowed after load_system and
+ * before the first eigenvector row.  Errors: INVALID_ARG, STATE. */
+mhc_status mhc_configure(mhc_ctx *ctx, const mhc_run_config *cfg);
+
+/* Rows mode0 .. mode0+n_rows-1 of E^T (Eqs. 13-16 eigenvectors e_{i,n}):
+ *   rows  [n_rows][3N] float64, row n holds e_{i,n}^alpha at column 3*i+alpha;
+ *         a host pointer (on_device = 0) or a device pointer on the context's
+ *         device (on_device = 1).  Real bases only (e* = e).
+ * The rows are converted on the GPU to the configured storage format and
+ * placed in bin-sorted order; rows of excluded modes are ignored.  Device
+ * memory for the whole basis is allocated on the first call.
+ * Errors: INVALID_ARG (range, pointer), STATE, OOM (basis does not fit). */
+mhc_status mhc_load_eigvec_rows(mhc_ctx *ctx, int64_t mode0, int64_t n_rows,
+                                const double *rows, int on_device);
+
+/* Check that every binned mode's row was loaded, allocate the per-block
+ * work buffers and accumulators, and clear the accumulators.
+ * Errors: STATE (missing rows / wrong order), OOM. */
+mhc_status mhc_finalize(mhc_ctx *ctx);
+
+/* --------------------------------------------------------------- stepping */
+
+/* Push n_steps consecutive samples.
+ *   v  [n_steps][N][3]     float32 velocities (A/fs)
+ *   W  [n_steps][N][3][3]  float32 per-atom virials (eV), W[mu][nu]
+ * Host pointers (on_device = 0) are copied before the call returns; device
+ * pointers (on_device = 1) are read asynchronously on the context stream.
+ * Steps are processed in blocks of t_block; a trailing partial block is
+ * processed as a shorter block, so results do not depend on how a
+ * trajectory is split into calls.
+ * Errors: INVALID_ARG, STATE (not finalized), NONFINITE (check_finite and a
+ * host input holds NaN/Inf; nothing is pushed), OOM, HIP. */
+mhc_status mhc_push(mhc_ctx *ctx, int32_t n_steps, const float *v, const float *W, int on_device);
+
+/* Wait for all queued work of the context. Errors: HIP. */
+mhc_status mhc_synchronize(mhc_ctx *ctx);
+
+/* ---------------------------------------------------------------- reading
+ * Read calls synchronize the context stream and write host arrays. */
+
+/* HNEMA (Eq. 19 numerator): time averages since the last reset.
+ *   avg        [nb][3]  <J_b^mu>        (NULL: skip)
+ *   total_avg  [3]      <J^mu> of Eq. 10 (NULL: skip)
+ *   n_samples  number of samples S       (NULL: skip)
+ * With S = 0 the averages are zero.  Errors: STATE (HNEMA not enabled). */
+mhc_status mhc_read_hnema(mhc_ctx *ctx, double *avg, double *total_avg, int64_t *n_samples);
+
+/* GKMA (Eq. 17): for tau = 0 .. L-1
+ *   corr      [L][nb][3][3]  C_b^{mu nu}(tau) = <J_b^mu(t+tau) J^nu(t)>, the
+ *                            average over the S - tau available origins
+ *                            (zero when S <= tau)                  (NULL: skip)
+ *   integral  [L][nb][3][3]  trapezoid running integral of corr over tau with
+ *                            step dt, integral[0] = 0              (NULL: skip)
+ *   hcacf     [L][3][3]      <J^mu(t+tau) J^nu(t)> of the total current (NULL: skip)
+ *   n_samples S                                                    (NULL: skip)
+ * Errors: STATE (GKMA not enabled). */
+mhc_status mhc_read_gkma(mhc_ctx *ctx, double *corr, double *integral, double *hcacf,
+                         int64_t *n_samples);
+
+/* Binned modal currents of the most recent block, per step:
+ *   jb  [t_count][nb][3] float64 J_b^mu(s) for the last t_count pushed steps
+ *       of the last block (t_count <= the size of that block)
+ * Available when GKMA is enabled (the per-step series exists only then).
+ * Errors: STATE, INVALID_ARG (t_count larger than the last block). */
+mhc_status mhc_read_block_currents(mhc_ctx *ctx, int32_t t_count, double *jb);
+
+/* Clear accumulators, sample count and the GKMA history; keep the basis. */
+mhc_status mhc_reset(mhc_ctx *ctx);
+
+/* Accumulator state (sums, compensation terms, sample count, GKMA history):
+ * mhc_save_state with buf == NULL sets *len to the size needed; otherwise
+ * writes *len bytes.  mhc_load_state restores a buffer saved from a context
+ * with the same system, bins and configuration.
+ * Errors: INVALID_ARG (size / format mismatch), STATE. */
+mhc_status mhc_save_state(mhc_ctx *ctx, void *buf, size_t *len);
+mhc_status mhc_load_state(mhc_ctx *ctx, const void *buf, size_t len);
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* Enable (1) or disable (0, the default) HIP-event timing of the dominant
+ * contraction kernel (one event pair per launch on the context stream).
+ * Errors: INVALID_ARG. */
+mhc_status mhc_set_timing(mhc_ctx *ctx, int enable);
+
+/* Launch count and summed duration (milliseconds) of the timed contraction
+ * launches since the last call; synchronizes the stream and resets the
+ * counters.  Errors: HIP. */
+mhc_status mhc_kernel_timing(mhc_ctx *ctx, int64_t *launches, double *total_ms);
+
+/* Bytes of device memory held by the context (basis, buffers, accumulators). */
+mhc_status mhc_device_bytes(mhc_ctx *ctx, int64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHC_H */

@@ -1,0 +1,13 @@
+"""modalhc: MI355X-native modal heat-current library (HNEMA / GKMA).
+
+Thin Python binding over the C ABI of ``libmodalhc.so`` (include/mhc.h).
+This module only marshals arguments: every step of the computation runs in
+the library's HIP kernels.  PyTorch is used, when present, only to pass
+device pointers and the current HIP stream.  There is no fallback: if the
+library is missing, every entry point raises.
+"""
+from ._lib import (  # noqa: F401
+    HNEMA, GKMA, PREC_FP32, PREC_BF16X3, MhcError, ModalHC, bins_uniform, library, library_path,
+    status_string,
+)
+from .physics import hnema_kappa, gkma_kappa  # noqa: F401

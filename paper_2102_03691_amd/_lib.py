@@ -1,0 +1,254 @@
+"""ctypes binding of libmodalhc (include/mhc.h): argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import _build
+
+HNEMA, GKMA = 1, 2
+PREC_FP32, PREC_BF16X3 = 0, 1
+
+_STATUS = {0: "MHC_OK", 1: "MHC_ERR_INVALID_ARG", 2: "MHC_ERR_STATE", 3: "MHC_ERR_OOM",
+           4: "MHC_ERR_HIP", 5: "MHC_ERR_UNSUPPORTED", 6: "MHC_ERR_NONFINITE"}
+
+
+class MhcError(RuntimeError):
+    """A library call returned a status other than MHC_OK."""
+
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RunConfig(C.Structure):
+    _fields_ = [("methods", C.c_int32), ("precision", C.c_int32), ("t_block", C.c_int32),
+                ("corr_len", C.c_int32), ("dt", C.c_double), ("check_finite", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def library():
+    """Load libmodalhc.so (built in-tree by _build.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2102_03691_amd._build.build() "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "mhc_create": (i32, [C.c_int, vp, P(vp)]),
+        "mhc_destroy": (i32, [vp]),
+        "mhc_last_error": (C.c_char_p, [vp]),
+        "mhc_status_string": (C.c_char_p, [i32]),
+        "mhc_abi_version": (C.c_int, []),
+        "mhc_load_system": (i32, [vp, i64, vp, i64, vp]),
+        "mhc_set_bins": (i32, [vp, i32, vp]),
+        "mhc_set_bins_uniform": (i32, [vp, i32, dbl, dbl]),
+        "mhc_bins_uniform": (i32, [i64, vp, i32, dbl, dbl, vp]),
+        "mhc_configure": (i32, [vp, P(RunConfig)]),
+        "mhc_load_eigvec_rows": (i32, [vp, i64, i64, vp, C.c_int]),
+        "mhc_finalize": (i32, [vp]),
+        "mhc_push": (i32, [vp, i32, vp, vp, C.c_int]),
+        "mhc_synchronize": (i32, [vp]),
+        "mhc_read_hnema": (i32, [vp, vp, vp, P(i64)]),
+        "mhc_read_gkma": (i32, [vp, vp, vp, vp, P(i64)]),
+        "mhc_read_block_currents": (i32, [vp, i32, vp]),
+        "mhc_reset": (i32, [vp]),
+        "mhc_save_state": (i32, [vp, vp, P(C.c_size_t)]),
+        "mhc_load_state": (i32, [vp, vp, C.c_size_t]),
+        "mhc_set_timing": (i32, [vp, C.c_int]),
+        "mhc_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
+        "mhc_device_bytes": (i32, [vp, P(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return library().mhc_status_string(status).decode()
+
+
+def _ptr(a) -> int:
+    return a.ctypes.data if isinstance(a, np.ndarray) else int(a.data_ptr())
+
+
+def bins_uniform(freq, n_bins: int, f_lo: float, f_hi: float) -> np.ndarray:
+    """Host-only bin map (no GPU): the rule mhc_set_bins_uniform applies."""
+    f = np.ascontiguousarray(freq, dtype=np.float64)
+    out = np.empty(f.shape[0], dtype=np.int32)
+    st = library().mhc_bins_uniform(f.shape[0], _ptr(f), int(n_bins), float(f_lo), float(f_hi), _ptr(out))
+    if st:
+        raise MhcError(st, "mhc_bins_uniform")
+    return out
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class ModalHC:
+    """One system (basis, bins, configuration, accumulators) on one GPU.
+
+    Device inputs are torch tensors on the context's device (passed by
+    pointer); host inputs are numpy arrays.  By default work is queued on
+    torch's current stream of that device, so it orders with torch ops.
+    """
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = library()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        st = self._lib.mhc_create(int(device), C.c_void_p(int(stream) if stream else 0), C.byref(h))
+        if st:
+            raise MhcError(st, self._lib.mhc_last_error(None).decode())
+        self._h = h
+        self.device = device
+        self.nb = None
+        self.n_atoms = None
+        self.cfg = None
+
+    # -- plumbing
+    def _check(self, st, what):
+        if st:
+            raise MhcError(st, f"{what}: {self._lib.mhc_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mhc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- loading
+    def load_system(self, mass, freq):
+        m = np.ascontiguousarray(mass, dtype=np.float64)
+        f = np.ascontiguousarray(freq, dtype=np.float64)
+        self._check(self._lib.mhc_load_system(self._h, m.shape[0], _ptr(m), f.shape[0], _ptr(f)), "load_system")
+        self.n_atoms = m.shape[0]
+        self.n_modes = f.shape[0]
+
+    def set_bins(self, n_bins, bins):
+        b = np.ascontiguousarray(bins, dtype=np.int32)
+        self._check(self._lib.mhc_set_bins(self._h, int(n_bins), _ptr(b)), "set_bins")
+        self.nb = int(n_bins)
+
+    def set_bins_uniform(self, n_bins, f_lo, f_hi):
+        self._check(self._lib.mhc_set_bins_uniform(self._h, int(n_bins), float(f_lo), float(f_hi)), "set_bins_uniform")
+        self.nb = int(n_bins)
+
+    def configure(self, methods=HNEMA, precision=PREC_FP32, t_block=1, corr_len=0, dt=1.0, check_finite=False):
+        cfg = RunConfig(int(methods), int(precision), int(t_block), int(corr_len), float(dt), int(bool(check_finite)))
+        self._check(self._lib.mhc_configure(self._h, C.byref(cfg)), "configure")
+        self.cfg = dict(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=dt)
+
+    def load_eigvec_rows(self, mode0, rows):
+        """rows: E^T rows [n, 3N] float64, numpy (host) or torch (device)."""
+        if _is_torch(rows):
+            assert rows.dtype.is_floating_point and rows.element_size() == 8 and rows.is_contiguous()
+            self._check(self._lib.mhc_load_eigvec_rows(self._h, int(mode0), rows.shape[0], _ptr(rows), 1),
+                        "load_eigvec_rows")
+        else:
+            r = np.ascontiguousarray(rows, dtype=np.float64)
+            self._check(self._lib.mhc_load_eigvec_rows(self._h, int(mode0), r.shape[0], _ptr(r), 0),
+                        "load_eigvec_rows")
+
+    def finalize(self):
+        self._check(self._lib.mhc_finalize(self._h), "finalize")
+
+    # -- stepping
+    def push(self, v, W):
+        """v [S, N, 3] and W [S, N, 3, 3] float32 (numpy host or torch device)."""
+        if _is_torch(v):
+            assert v.is_contiguous() and W.is_contiguous() and v.element_size() == 4 and W.element_size() == 4
+            assert v.shape[0] == W.shape[0] and v.numel() == v.shape[0] * self.n_atoms * 3
+            assert W.numel() == W.shape[0] * self.n_atoms * 9
+            self._check(self._lib.mhc_push(self._h, v.shape[0], _ptr(v), _ptr(W), 1), "push")
+        else:
+            vv = np.ascontiguousarray(v, dtype=np.float32)
+            WW = np.ascontiguousarray(W, dtype=np.float32)
+            assert vv.shape[0] == WW.shape[0] and vv.size == vv.shape[0] * self.n_atoms * 3
+            assert WW.size == WW.shape[0] * self.n_atoms * 9
+            self._check(self._lib.mhc_push(self._h, vv.shape[0], _ptr(vv), _ptr(WW), 0), "push")
+
+    def synchronize(self):
+        self._check(self._lib.mhc_synchronize(self._h), "synchronize")
+
+    # -- reading
+    def read_hnema(self):
+        avg = np.empty((self.nb, 3), dtype=np.float64)
+        tot = np.empty(3, dtype=np.float64)
+        n = C.c_int64()
+        self._check(self._lib.mhc_read_hnema(self._h, _ptr(avg), _ptr(tot), C.byref(n)), "read_hnema")
+        return avg, tot, n.value
+
+    def read_gkma(self):
+        L = int(self.cfg["corr_len"])
+        corr = np.empty((L, self.nb, 3, 3), dtype=np.float64)
+        integ = np.empty_like(corr)
+        hc = np.empty((L, 3, 3), dtype=np.float64)
+        n = C.c_int64()
+        self._check(self._lib.mhc_read_gkma(self._h, _ptr(corr), _ptr(integ), _ptr(hc), C.byref(n)), "read_gkma")
+        return {"corr": corr, "integral": integ, "hcacf": hc, "n_samples": n.value}
+
+    def read_block_currents(self, t_count):
+        out = np.empty((t_count, self.nb, 3), dtype=np.float64)
+        self._check(self._lib.mhc_read_block_currents(self._h, int(t_count), _ptr(out)), "read_block_currents")
+        return out
+
+    def reset(self):
+        self._check(self._lib.mhc_reset(self._h), "reset")
+
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        self._check(self._lib.mhc_save_state(self._h, None, C.byref(n)), "save_state")
+        buf = C.create_string_buffer(n.value)
+        self._check(self._lib.mhc_save_state(self._h, buf, C.byref(n)), "save_state")
+        return buf.raw[: n.value]
+
+    def load_state(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(self._lib.mhc_load_state(self._h, buf, len(data)), "load_state")
+
+    # -- diagnostics
+    def set_timing(self, enable=True):
+        self._check(self._lib.mhc_set_timing(self._h, int(bool(enable))), "set_timing")
+
+    def kernel_timing(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(self._lib.mhc_kernel_timing(self._h, C.byref(n), C.byref(ms)), "kernel_timing")
+        return n.value, ms.value
+
+    def device_bytes(self):
+        b = C.c_int64()
+        self._check(self._lib.mhc_device_bytes(self._h, C.byref(b)), "device_bytes")
+        return b.value

@@ -1,0 +1,249 @@
+// Frequency binning, float64 time accumulation and the GKMA correlation.
+//
+//   J_b^mu(t) = sum_{n in b} J_n^mu(t)                 (frequency bins, Sec. III.A)
+//   HNEMA:  S_b^mu += sum_t J_b^mu(t), S^mu += sum_t J^mu(t)   (Eq. 19 numerator)
+//   GKMA:   C_b^{mu nu}(tau) += sum_t J_b^mu(t) J^nu(t - tau)  (Eq. 17 integrand)
+// Modes are stored in bin-sorted slots, so bin b is the contiguous slot range
+// [bin_off[b], bin_off[b+1]).  All sums are float64 in a fixed order (no
+// atomics), so results are reproducible bit for bit; long running sums use
+// Neumaier compensation.
+#include "mhc_common.h"
+#include "mhc_numeric.h"
+
+namespace mhc {
+
+// Fixed-order sum of one double per thread over a 256-thread work-group.
+// Every thread receives the result.
+__device__ __forceinline__ double block_sum256(double x, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = x;
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ reduce
+__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  if (b < a.nb) {
+    const int64_t lo = a.bin_off[b], hi = a.bin_off[b + 1];
+    const int64_t n = hi - lo;
+    if (!a.layout_g) {
+      // HNEMA-only: parts [p][slot][mu], already summed over each part's steps
+      double s3[3] = {0.0, 0.0, 0.0};
+      const int per_part = (int)(n * 3);
+      for (int p = 0; p < a.n_parts; ++p) {
+        const float* base = a.in + ((int64_t)p * a.M_pad + lo) * 3;
+        int mu = tid % 3;                       // e % 3, and 256 % 3 == 1
+        for (int e = tid; e < per_part; e += 256) {
+          const double val = (double)base[e];
+          if (mu == 0) s3[0] += val; else if (mu == 1) s3[1] += val; else s3[2] += val;
+          mu = (mu == 2) ? 0 : mu + 1;
+        }
+      }
+#pragma unroll
+      for (int mu = 0; mu < 3; ++mu) {
+        const double tot = block_sum256(s3[mu], sh);
+        if (tid == 0) neumaier_add(a.hsum[b * 3 + mu], a.hcomp[b * 3 + mu], tot);
+      }
+    } else {
+      // GKMA: per-step binned currents X[(b*3+mu)][t]
+      double h3[3] = {0.0, 0.0, 0.0};
+      for (int t = tid; t < a.t_count; t += 256) {
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const float* col = a.in + ((int64_t)mu * a.M_pad + lo) * a.ld + t;
+          double s = 0.0;
+          for (int64_t q = 0; q < n; ++q) s += (double)col[q * a.ld];
+          a.X[((int64_t)b * 3 + mu) * a.ld + t] = s;
+          h3[mu] += s;
+        }
+      }
+      if (a.hsum) {
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+          const double tot = block_sum256(h3[mu], sh);
+          if (tid == 0) neumaier_add(a.hsum[b * 3 + mu], a.hcomp[b * 3 + mu], tot);
+        }
+      }
+    }
+    return;
+  }
+  // last work-group: total current of Eq. 10 per step (float64 partials over atom chunks)
+  double h3[3] = {0.0, 0.0, 0.0};
+  for (int t = tid; t < a.t_count; t += 256) {
+    double j[3] = {0.0, 0.0, 0.0};
+    const double* jp = a.jt_part + (int64_t)t * a.n_chunks * 3;
+    for (int c = 0; c < a.n_chunks; ++c) {
+      j[0] += jp[c * 3 + 0];
+      j[1] += jp[c * 3 + 1];
+      j[2] += jp[c * 3 + 2];
+    }
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      h3[mu] += j[mu];
+      if (a.X) {
+        a.X[((int64_t)a.nb * 3 + mu) * a.ld + t] = j[mu];
+        a.ring[((a.t0 + t) % a.ring_len) * 3 + mu] = j[mu];
+      }
+    }
+  }
+  if (a.tsum) {
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const double tot = block_sum256(h3[mu], sh);
+      if (tid == 0) neumaier_add(a.tsum[mu], a.tcomp[mu], tot);
+    }
+  }
+}
+
+hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a) {
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)(a.nb + 1)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- correlation
+// Work-group tile: 64 rows r x 64 lags tau (x 3 nu); thread = 4 rows x 4 lags.
+// X and the needed window of the history ring are staged in LDS per chunk of
+// 64 steps; along t the 4 lags of a thread slide over the ring one entry per
+// step, so each step costs 4 X reads + 3 ring reads for 48 FMAs.
+constexpr int CT = 64;   // steps per chunk
+constexpr int CR = 64;   // rows per tile
+constexpr int CL = 64;   // lags per tile
+
+__global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
+                                              int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
+                                              double* __restrict__ csum, double* __restrict__ ccomp) {
+  __shared__ double xs[CT][CR + 2];          // xs[t][r]
+  __shared__ double rs[CT + CL][3];          // ring window
+  const int tid = threadIdx.x;
+  const int tr = tid & 15;
+  const int tt = tid >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * CR;
+  const int tau0 = blockIdx.y * CL;
+  double acc[4][4][3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < 3; ++n) acc[i][k][n] = 0.0;
+
+  for (int tc = 0; tc < t_count; tc += CT) {
+    // stage X rows r0.. (t-major in LDS)
+    for (int idx = tid; idx < CR * CT; idx += 256) {
+      const int j = idx % CT, i = idx / CT;
+      const int64_t r = r0 + i;
+      const int tg = tc + j;
+      xs[j][i] = (r < R3 && tg < t_count) ? X[r * ldx + tg] : 0.0;
+    }
+    // ring window: q in [0, CT + CL) <-> global time g = t0 + tc - tau0 - (CL - 1) + q
+    for (int idx = tid; idx < (CT + CL) * 3; idx += 256) {
+      const int q = idx / 3, nu = idx % 3;
+      const int64_t g = t0 + tc - tau0 - (CL - 1) + q;
+      const bool ok = g >= 0 && g < t0 + t_count;
+      rs[q][nu] = ok ? ring[(g % ring_len) * 3 + nu] : 0.0;
+    }
+    __syncthreads();
+    // lag of slot k: tau = tau0 + 4*tt + k; step j reads q = j + CL - 1 - 4*tt - k
+    double win[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < 3; ++n) win[k][n] = rs[CL - 1 - 4 * tt - k][n];
+    for (int j = 0; j < CT; ++j) {
+      double x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = xs[j][4 * tr + i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int n = 0; n < 3; ++n) acc[i][k][n] = fma(x[i], win[k][n], acc[i][k][n]);
+      if (j + 1 < CT) {
+#pragma unroll
+        for (int k = 3; k > 0; --k)
+#pragma unroll
+          for (int n = 0; n < 3; ++n) win[k][n] = win[k - 1][n];
+#pragma unroll
+        for (int n = 0; n < 3; ++n) win[0][n] = rs[j + 1 + CL - 1 - 4 * tt][n];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = r0 + 4 * tr + i;
+    if (r >= R3) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int tau = tau0 + 4 * tt + k;
+      if (tau >= L) continue;
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        const int64_t o = ((int64_t)tau * R3 + r) * 3 + n;
+        double sm = csum[o], cp = ccomp[o];
+        neumaier_add(sm, cp, acc[i][k][n]);
+        csum[o] = sm;
+        ccomp[o] = cp;
+      }
+    }
+  }
+}
+
+hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
+                       const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp) {
+  if (t_count <= 0) return hipSuccess;
+  dim3 grid((unsigned)((R3 + CR - 1) / CR), (unsigned)((L + CL - 1) / CL));
+  hipLaunchKernelGGL(k_corr, grid, dim3(256), 0, s, X, ldx, t_count, R3, L, ring, ring_len, t0, csum, ccomp);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- read-out
+__global__ void __launch_bounds__(256) k_corr_finish(const double* __restrict__ csum, const double* __restrict__ ccomp,
+                                                     int64_t R3, int L, int64_t S, double dt,
+                                                     double* __restrict__ corr, double* __restrict__ integral) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // series (r, nu)
+  if (q >= R3 * 3) return;
+  double G = 0.0, prev = 0.0;
+  for (int tau = 0; tau < L; ++tau) {
+    const int64_t o = (int64_t)tau * R3 * 3 + q;
+    const int64_t cnt = S - tau;
+    const double c = (cnt > 0) ? (csum[o] + ccomp[o]) / (double)cnt : 0.0;
+    corr[o] = c;
+    if (tau > 0) G += dt * 0.5 * (prev + c);
+    integral[o] = G;
+    prev = c;
+  }
+}
+
+hipError_t launch_corr_finish(hipStream_t s, const double* csum, const double* ccomp, int64_t R3, int L, int64_t S,
+                              double dt, double* corr, double* integral) {
+  const int64_t n = R3 * 3;
+  hipLaunchKernelGGL(k_corr_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, csum, ccomp, R3, L, S, dt,
+                     corr, integral);
+  return hipGetLastError();
+}
+
+__global__ void k_hnema_finish(const double* __restrict__ sum, const double* __restrict__ comp, int64_t n, int64_t S,
+                               double* __restrict__ avg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) avg[i] = (S > 0) ? (sum[i] + comp[i]) / (double)S : 0.0;
+}
+
+hipError_t launch_hnema_finish(hipStream_t s, const double* sum, const double* comp, int64_t n, int64_t S,
+                               double* avg) {
+  hipLaunchKernelGGL(k_hnema_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sum, comp, n, S, avg);
+  return hipGetLastError();
+}
+
+}  // namespace mhc

@@ -1,0 +1,324 @@
+// The two contractions of the method and the modal-current epilogue:
+//   Xdot_n(t)   = sum_j E[j][n] u_j(t)        (Eq. 13)
+//   A_n^mu(t)   = sum_j E[j][n] w^mu_j(t)     (bracket of Eq. 16)
+//   J_n^mu(t)   = Xdot_n(t) A_n^mu(t)         (Eq. 16)
+// done as one product of E^T (slots x dofs) with the four stacked channels
+// (u, w^x, w^y, w^z) of the B operand, so Xdot and the three A^mu of a
+// (mode, step) pair land in the same lane and register of four accumulators.
+//
+// Two paths:
+//   * per-step FP32 matrix-vector product (t_block = 1): E is streamed from
+//     HBM once per step;
+//   * T-batched matrix-core GEMM (FP32 or split-BF16): E tiles are staged
+//     through LDS and reused across the 4 channels and all steps of a tile.
+#include "mhc_common.h"
+
+namespace mhc {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Row of the 32x32 accumulator held in register j of lane l (column = l % 32).
+__device__ __forceinline__ int acc_row(int j, int half) { return 8 * (j >> 2) + 4 * half + (j & 3); }
+
+// ----------------------------------------------------------- per-step FP32
+// Work-group = one row block of 32 slots, 8 waves; wave w owns a contiguous
+// eighth of the dof chunks.  Each lane accumulates 4 channel partial sums of
+// its row over its dofs; the 64 lanes x 8 waves are combined in fixed order.
+constexpr int GEMV_WAVES = 8;
+
+__global__ void __launch_bounds__(64 * GEMV_WAVES)
+k_gemv_f32(const f32x4* __restrict__ E, const float* __restrict__ B, int n_steps, int64_t M_pad,
+           int64_t K_pad, float* __restrict__ out, int layout_g, int64_t ld) {
+  __shared__ float red[GEMV_WAVES][32][4];
+  const int rb = blockIdx.x;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int r = lane & 31;
+  const int64_t KC = K_pad >> 3;
+  const int64_t per_wave = KC / GEMV_WAVES;
+  const int64_t kc0 = wave * per_wave;
+  const f32x4* Ew = E + ((int64_t)rb * KC + kc0) * 64 + lane;
+  for (int t = 0; t < n_steps; ++t) {
+    const float* Bt = B + (int64_t)t * 4 * K_pad + kc0 * 8 + 4 * half;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll 8
+    for (int64_t i = 0; i < per_wave; ++i) {
+      const f32x4 e = __builtin_nontemporal_load(Ew + i * 64);
+      const f32x4 b0 = *reinterpret_cast<const f32x4*>(Bt + i * 8);
+      const f32x4 b1 = *reinterpret_cast<const f32x4*>(Bt + K_pad + i * 8);
+      const f32x4 b2 = *reinterpret_cast<const f32x4*>(Bt + 2 * K_pad + i * 8);
+      const f32x4 b3 = *reinterpret_cast<const f32x4*>(Bt + 3 * K_pad + i * 8);
+      a0 = fmaf(e.x, b0.x, a0); a0 = fmaf(e.y, b0.y, a0); a0 = fmaf(e.z, b0.z, a0); a0 = fmaf(e.w, b0.w, a0);
+      a1 = fmaf(e.x, b1.x, a1); a1 = fmaf(e.y, b1.y, a1); a1 = fmaf(e.z, b1.z, a1); a1 = fmaf(e.w, b1.w, a1);
+      a2 = fmaf(e.x, b2.x, a2); a2 = fmaf(e.y, b2.y, a2); a2 = fmaf(e.z, b2.z, a2); a2 = fmaf(e.w, b2.w, a2);
+      a3 = fmaf(e.x, b3.x, a3); a3 = fmaf(e.y, b3.y, a3); a3 = fmaf(e.z, b3.z, a3); a3 = fmaf(e.w, b3.w, a3);
+    }
+    a0 += __shfl_xor(a0, 32);
+    a1 += __shfl_xor(a1, 32);
+    a2 += __shfl_xor(a2, 32);
+    a3 += __shfl_xor(a3, 32);
+    if (half == 0) {
+      red[wave][r][0] = a0; red[wave][r][1] = a1; red[wave][r][2] = a2; red[wave][r][3] = a3;
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+      float x = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+      for (int w = 0; w < GEMV_WAVES; ++w) {
+        x += red[w][threadIdx.x][0];
+        ax += red[w][threadIdx.x][1];
+        ay += red[w][threadIdx.x][2];
+        az += red[w][threadIdx.x][3];
+      }
+      const int64_t slot = (int64_t)rb * 32 + threadIdx.x;
+      if (!layout_g) {
+        float* o = out + ((int64_t)t * M_pad + slot) * 3;
+        o[0] = x * ax; o[1] = x * ay; o[2] = x * az;
+      } else {
+        out[(0 * M_pad + slot) * ld + t] = x * ax;
+        out[(1 * M_pad + slot) * ld + t] = x * ay;
+        out[(2 * M_pad + slot) * ld + t] = x * az;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_steps, int64_t M_pad,
+                           int64_t K_pad, float* out, int layout_g, int64_t ld) {
+  if (n_steps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemv_f32, dim3((unsigned)(M_pad / 32)), dim3(64 * GEMV_WAVES), 0, s,
+                     reinterpret_cast<const f32x4*>(E), B, n_steps, M_pad, K_pad, out, layout_g, ld);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ matrix cores
+// Work-group = 4 waves arranged WM x WT; each wave owns MB row blocks (32 slots
+// each) and one t-block of 32 steps, for all four channels: 4*MB accumulators
+// of 32x32 floats.  A operand (E) stages of SU 16-byte units per row block
+// are double-buffered in LDS; B fragments are read by each wave straight
+// from global memory (L2), one chunk ahead.
+//
+// Both A and B are laid out per row/column block as [stage][SU] u32x4 with
+//   BF16: unit (chunk*2 + hi/lo)*64 + lane   (chunk = 16 dofs)
+//   FP32: unit chunk*64 + lane               (chunk = 8 dofs)
+template <int PREC, int WM, int WT, int MB, int SU>
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, int ntb,
+       float* __restrict__ out, int layout_g, int64_t M_pad, int n_mtiles, int n_ntiles) {
+  static_assert(WM * WT == 4, "4 waves");
+  constexpr int RBW = WM * MB;                                   // row blocks per work-group
+  constexpr bool BF = (PREC == PREC_BF16X3);
+  constexpr int UPC = BF ? 128 : 64;                             // units per chunk
+  constexpr int CPS = SU / UPC;                                  // chunks per stage
+  constexpr int A_PER_THR = RBW * SU / 256;
+  static_assert(RBW * SU % 256 == 0, "stage split");
+  __shared__ u32x4 lds[2][RBW][SU];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int half = lane >> 5;
+  const int wm = wave / WT;
+  const int wt = wave % WT;
+
+  // XCD-aware tile order: consecutive work-group ids go to different XCDs
+  // (round-robin dispatch), so give each XCD a contiguous range of tiles.
+  const int n_tiles = n_mtiles * n_ntiles;
+  const int id = blockIdx.x;
+  const int lin = (n_tiles % 8 == 0) ? (id % 8) * (n_tiles / 8) + id / 8 : id;
+  const int mtile = lin / n_ntiles;
+  const int ntile = lin % n_ntiles;
+  const int64_t rb0 = (int64_t)mtile * RBW;
+  const int tb = ntile * WT + wt;
+  const int64_t per_blk = 8 * K_pad;                              // units per row/column block
+  const int n_stages = (int)(per_blk / SU);
+  const int n_chunks = n_stages * CPS;
+
+  const u32x4* Ebase = E + rb0 * per_blk;
+  u32x4 a_st[A_PER_THR];
+  auto load_A = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < A_PER_THR; ++q) {
+      const int idx = tid + 256 * q;
+      const int rbl = idx / SU, w = idx % SU;
+      a_st[q] = __builtin_nontemporal_load(Ebase + rbl * per_blk + (int64_t)s * SU + w);
+    }
+  };
+  auto store_A = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < A_PER_THR; ++q) {
+      const int idx = tid + 256 * q;
+      lds[buf][idx / SU][idx % SU] = a_st[q];
+    }
+  };
+
+  const u32x4* Bc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Bc[c] = B + ((int64_t)c * ntb + tb) * per_blk + lane;
+
+  constexpr int NBF = BF ? 8 : 4;        // B units per chunk per lane
+  auto load_B = [&](int kc, u32x4* dst) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if constexpr (BF) {
+        dst[2 * c + 0] = Bc[c][(int64_t)kc * 128];
+        dst[2 * c + 1] = Bc[c][(int64_t)kc * 128 + 64];
+      } else {
+        dst[c] = Bc[c][(int64_t)kc * 64];
+      }
+    }
+  };
+
+  f32x16 acc[MB][4];
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
+
+  load_A(0);
+  store_A(0);
+  u32x4 bcur[NBF], bnext[NBF];
+  load_B(0, bcur);
+  __syncthreads();
+
+  for (int s = 0; s < n_stages; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < n_stages) load_A(s + 1);
+#pragma unroll
+    for (int kk = 0; kk < CPS; ++kk) {
+      const int kc = s * CPS + kk;
+      if (kc + 1 < n_chunks) load_B(kc + 1, bnext);
+      if constexpr (BF) {
+        bf16x8 ah[MB], al[MB];
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb) {
+          ah[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 0) * 64 + lane]);
+          al[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 1) * 64 + lane]);
+        }
+        // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                ah[rb], __builtin_bit_cast(bf16x8, bcur[2 * c]), acc[rb][c], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                ah[rb], __builtin_bit_cast(bf16x8, bcur[2 * c + 1]), acc[rb][c], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                al[rb], __builtin_bit_cast(bf16x8, bcur[2 * c]), acc[rb][c], 0, 0, 0);
+      } else {
+        f32x4 a[MB];
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+          a[rb] = __builtin_bit_cast(f32x4, lds[buf][wm * MB + rb][kk * 64 + lane]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                  a[rb][e], __builtin_bit_cast(f32x4, bcur[c])[e], acc[rb][c], 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < NBF; ++q) bcur[q] = bnext[q];
+    }
+    if (s + 1 < n_stages) store_A(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------- epilogue
+  if (!layout_g) {
+    // HNEMA: sum J_n^mu over the tile's steps -> out[ntile][slot][mu]
+    float* red = reinterpret_cast<float*>(&lds[0][0][0]);    // [WT][RBW*32][3]
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        float p0 = acc[rb][0][j] * acc[rb][1][j];
+        float p1 = acc[rb][0][j] * acc[rb][2][j];
+        float p2 = acc[rb][0][j] * acc[rb][3][j];
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+          p0 += __shfl_xor(p0, off);
+          p1 += __shfl_xor(p1, off);
+          p2 += __shfl_xor(p2, off);
+        }
+        if ((lane & 31) == 0) {
+          const int row = (wm * MB + rb) * 32 + acc_row(j, half);
+          float* rp = red + ((int64_t)wt * RBW * 32 + row) * 3;
+          rp[0] = p0; rp[1] = p1; rp[2] = p2;
+        }
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < RBW * 32 * 3; idx += 256) {
+      float sacc = 0.f;
+#pragma unroll
+      for (int w = 0; w < WT; ++w) sacc += red[w * RBW * 32 * 3 + idx];
+      out[((int64_t)ntile * M_pad + rb0 * 32) * 3 + idx] = sacc;
+    }
+  } else {
+    // GKMA: per-step J_n^mu(t) -> out[mu][slot][t]
+    const int64_t ld = (int64_t)ntb * 32;
+    const int64_t t = (int64_t)tb * 32 + (lane & 31);
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t slot = (rb0 + wm * MB + rb) * 32 + acc_row(j, half);
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu)
+          out[((int64_t)mu * M_pad + slot) * ld + t] = acc[rb][0][j] * acc[rb][1 + mu][j];
+      }
+    }
+  }
+}
+
+template <int PREC>
+static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
+                                   int ntb, float* out, int layout_g, int* n_parts) {
+  const u32x4* Ev = reinterpret_cast<const u32x4*>(E);
+  const u32x4* Bv = reinterpret_cast<const u32x4*>(B);
+  if (ntb % 4 == 0) {
+    // 128 slots x 4 t-blocks per work-group
+    const int n_m = (int)(M_pad / 128), n_n = ntb / 4;
+    *n_parts = n_n;
+    hipLaunchKernelGGL((k_gemm<PREC, 1, 4, 4, 512>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
+                       layout_g, M_pad, n_m, n_n);
+  } else if (ntb % 2 == 0) {
+    const int n_m = (int)(M_pad / 256), n_n = ntb / 2;
+    *n_parts = n_n;
+    hipLaunchKernelGGL((k_gemm<PREC, 2, 2, 4, 256>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
+                       layout_g, M_pad, n_m, n_n);
+  } else {
+    const int n_m = (int)(M_pad / 256), n_n = ntb;
+    *n_parts = n_n;
+    hipLaunchKernelGGL((k_gemm<PREC, 4, 1, 2, 256>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
+                       layout_g, M_pad, n_m, n_n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
+                       int ntb, float* out, int layout_g, int* n_parts) {
+  if (prec == PREC_BF16X3) return launch_gemm_prec<PREC_BF16X3>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts);
+  return launch_gemm_prec<PREC_FP32>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts);
+}
+
+}  // namespace mhc

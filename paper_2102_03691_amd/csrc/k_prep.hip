@@ -1,0 +1,222 @@
+// Load-time basis conversion and per-block input preparation.
+//
+// Basis: E^T rows arrive in float64 (eigenvectors e_{i,n}, Sec. II.B) and are
+// stored once in the contraction's operand format and fragment layout
+// (see mhc_common.h), in bin-sorted slot order.
+//
+// Inputs: per step, u_j = sqrt(m_i) v_i^alpha (Eq. 13) and
+// w^mu_j = W_i^{mu alpha} / sqrt(m_i) (the bracket of Eq. 16), j = 3i + alpha,
+// written as the B operand of the contraction; the total potential heat
+// current J^mu = sum_i sum_nu W_i^{mu nu} v_i^nu (Eq. 10) is summed in float64
+// per chunk of atoms.
+#include "mhc_common.h"
+#include "mhc_numeric.h"
+
+namespace mhc {
+
+// ------------------------------------------------------------ basis store
+// One thread per output piece: FP32 piece = 4 floats, BF16 piece = 8 hi + 8 lo.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ rows, int64_t n_rows,
+                                                     int64_t K, const int32_t* __restrict__ slot_of_row,
+                                                     void* __restrict__ E, int64_t K_pad) {
+  constexpr int PW = (PREC == PREC_FP32) ? 4 : 8;     // dofs per piece
+  const int64_t pieces = K_pad / PW;
+  const int64_t r = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rows || p >= pieces) return;
+  const int32_t slot = slot_of_row[r];
+  if (slot < 0) return;
+  const int64_t k0 = p * PW;
+  const double* row = rows + r * K;
+  const int64_t rb = slot >> 5;
+  const int rr = slot & 31;
+  if constexpr (PREC == PREC_FP32) {
+    const int64_t kc = k0 >> 3;
+    const int h = (int)((k0 >> 2) & 1);
+    const int lane = rr + 32 * h;
+    float4 o;
+    o.x = (k0 + 0 < K) ? (float)row[k0 + 0] : 0.f;
+    o.y = (k0 + 1 < K) ? (float)row[k0 + 1] : 0.f;
+    o.z = (k0 + 2 < K) ? (float)row[k0 + 2] : 0.f;
+    o.w = (k0 + 3 < K) ? (float)row[k0 + 3] : 0.f;
+    float4* dst = reinterpret_cast<float4*>(E);
+    dst[(rb * (K_pad >> 3) + kc) * 64 + lane] = o;
+  } else {
+    const int64_t kc = k0 >> 4;
+    const int h = (int)((k0 >> 3) & 1);
+    const int lane = rr + 32 * h;
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      uint16_t h0, l0, h1, l1;
+      split_bf16_from_f64((k0 + e < K) ? row[k0 + e] : 0.0, h0, l0);
+      split_bf16_from_f64((k0 + e + 1 < K) ? row[k0 + e + 1] : 0.0, h1, l1);
+      hi[e / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      lo[e / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+    uint4* dst = reinterpret_cast<uint4*>(E);
+    const int64_t base = ((rb * (K_pad >> 4) + kc) * 2) * 64;
+    dst[base + lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    dst[base + 64 + lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+  }
+}
+
+hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows, int64_t K,
+                              const int32_t* slot_of_row, void* E, int64_t K_pad) {
+  if (n_rows <= 0) return hipSuccess;
+  const int PW = (prec == PREC_FP32) ? 4 : 8;
+  const int64_t pieces = K_pad / PW;
+  dim3 grid((unsigned)((pieces + 255) / 256), (unsigned)n_rows);
+  if (prec == PREC_FP32)
+    hipLaunchKernelGGL(k_basis_store<PREC_FP32>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad);
+  else
+    hipLaunchKernelGGL(k_basis_store<PREC_BF16X3>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- input prep
+// Work-group = 32 atoms (96 dofs) x 32 steps, 256 threads.
+// Phase A: thread (tl = tid / 8, sub = tid % 8) handles atoms sub, sub+8, ...
+//          of step tl: channels into LDS and the Eq. 10 partial in float64.
+// Phase B: the LDS tile is written out in the operand layout.
+constexpr int PREP_T = 32;
+constexpr int PREP_K = 3 * ATOMS_PER_PREP;   // 96 dofs
+
+template <int MODE>   // 0 = plain, 1 = FP32 fragments, 2 = BF16 fragments
+__global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v, const float* __restrict__ W,
+                                                    const float* __restrict__ sqrt_m,
+                                                    const float* __restrict__ inv_sqrt_m, int64_t N,
+                                                    int t_count, int t_pad, void* __restrict__ B,
+                                                    int64_t K_pad, double* __restrict__ jt_part) {
+  __shared__ float ch[4][PREP_T][PREP_K + 4];
+  const int tid = threadIdx.x;
+  const int chunk = blockIdx.x;
+  const int n_chunks = gridDim.x;
+  const int tb = blockIdx.y;
+  const int tl = tid >> 3;
+  const int sub = tid & 7;
+  const int t = tb * PREP_T + tl;
+  const int64_t i0 = (int64_t)chunk * ATOMS_PER_PREP;
+
+  double j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < ATOMS_PER_PREP / 8; ++q) {
+    const int a = sub + 8 * q;
+    const int64_t i = i0 + a;
+    float u[3] = {0.f, 0.f, 0.f}, w[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    if (t < t_count && i < N) {
+      const float* vp = v + ((int64_t)t * N + i) * 3;
+      const float* Wp = W + ((int64_t)t * N + i) * 9;
+      const float vx = vp[0], vy = vp[1], vz = vp[2];
+      const float sm = sqrt_m[i], ism = inv_sqrt_m[i];
+      float Wl[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Wl[c] = Wp[c];
+      u[0] = sm * vx; u[1] = sm * vy; u[2] = sm * vz;
+#pragma unroll
+      for (int mu = 0; mu < 3; ++mu)
+#pragma unroll
+        for (int nu = 0; nu < 3; ++nu) w[mu][nu] = Wl[3 * mu + nu] * ism;
+      // Eq. 10 in float64: J^mu += sum_nu W^{mu nu} v^nu
+      const double dvx = vx, dvy = vy, dvz = vz;
+      j0 += (double)Wl[0] * dvx + (double)Wl[1] * dvy + (double)Wl[2] * dvz;
+      j1 += (double)Wl[3] * dvx + (double)Wl[4] * dvy + (double)Wl[5] * dvz;
+      j2 += (double)Wl[6] * dvx + (double)Wl[7] * dvy + (double)Wl[8] * dvz;
+    }
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      ch[0][tl][3 * a + al] = u[al];
+      ch[1][tl][3 * a + al] = w[0][al];
+      ch[2][tl][3 * a + al] = w[1][al];
+      ch[3][tl][3 * a + al] = w[2][al];
+    }
+  }
+  // fixed-order reduction over the 8 threads of a step
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) {
+    j0 += __shfl_xor(j0, off);
+    j1 += __shfl_xor(j1, off);
+    j2 += __shfl_xor(j2, off);
+  }
+  if (sub == 0 && t < t_pad) {
+    double* jp = jt_part + ((int64_t)t * n_chunks + chunk) * 3;
+    jp[0] = j0; jp[1] = j1; jp[2] = j2;
+  }
+  __syncthreads();
+
+  const int64_t k_base = (int64_t)chunk * PREP_K;
+  if constexpr (MODE == 0) {
+    // plain [t][4][K_pad]: 4 * 32 * 96 floats, coalesced along k
+    for (int idx = tid; idx < 4 * PREP_T * PREP_K; idx += 256) {
+      const int k = idx % PREP_K;
+      const int c = (idx / PREP_K) & 3;
+      const int tt = idx / (4 * PREP_K);
+      const int tg = tb * PREP_T + tt;
+      if (tg >= t_count) continue;
+      float* Bp = reinterpret_cast<float*>(B);
+      Bp[((int64_t)tg * 4 + c) * K_pad + k_base + k] = ch[c][tt][k];
+    }
+  } else if constexpr (MODE == 1) {
+    // FP32 fragments: piece = (c, 4-dof group g, column tt): 4 * 24 * 32 pieces
+    const int ntb = t_pad / 32;
+    const int64_t KC = K_pad >> 3;
+    float4* Bp = reinterpret_cast<float4*>(B);
+    for (int idx = tid; idx < 4 * (PREP_K / 4) * PREP_T; idx += 256) {
+      const int tt = idx & 31;
+      const int g = (idx >> 5) % (PREP_K / 4);
+      const int c = (idx >> 5) / (PREP_K / 4);
+      const int64_t k = k_base + 4 * g;
+      const int64_t kc = k >> 3;
+      const int h = (int)((k >> 2) & 1);
+      const int64_t cb = (int64_t)c * ntb + tb;
+      float4 o = make_float4(ch[c][tt][4 * g], ch[c][tt][4 * g + 1], ch[c][tt][4 * g + 2], ch[c][tt][4 * g + 3]);
+      Bp[(cb * KC + kc) * 64 + tt + 32 * h] = o;
+    }
+  } else {
+    // BF16 fragments: piece = (c, 8-dof group g, column tt), hi and lo
+    const int ntb = t_pad / 32;
+    const int64_t KC = K_pad >> 4;
+    uint4* Bp = reinterpret_cast<uint4*>(B);
+    for (int idx = tid; idx < 4 * (PREP_K / 8) * PREP_T; idx += 256) {
+      const int tt = idx & 31;
+      const int g = (idx >> 5) % (PREP_K / 8);
+      const int c = (idx >> 5) / (PREP_K / 8);
+      const int64_t k = k_base + 8 * g;
+      const int64_t kc = k >> 4;
+      const int h = (int)((k >> 3) & 1);
+      const int64_t cb = (int64_t)c * ntb + tb;
+      uint32_t hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        uint16_t h0, l0, h1, l1;
+        split_bf16_from_f32(ch[c][tt][8 * g + e], h0, l0);
+        split_bf16_from_f32(ch[c][tt][8 * g + e + 1], h1, l1);
+        hi[e / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        lo[e / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      }
+      const int64_t base = ((cb * KC + kc) * 2) * 64 + tt + 32 * h;
+      Bp[base] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+      Bp[base + 64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    }
+  }
+}
+
+hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
+                             const float* sqrt_m, const float* inv_sqrt_m, int64_t N, int t_count,
+                             int t_pad, void* B, int64_t K_pad, double* jt_part) {
+  const int n_chunks = (int)((N + ATOMS_PER_PREP - 1) / ATOMS_PER_PREP);
+  dim3 grid((unsigned)n_chunks, (unsigned)((t_pad + PREP_T - 1) / PREP_T));
+  if (plain)
+    hipLaunchKernelGGL(k_input_prep<0>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
+                       B, K_pad, jt_part);
+  else if (prec == PREC_FP32)
+    hipLaunchKernelGGL(k_input_prep<1>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
+                       B, K_pad, jt_part);
+  else
+    hipLaunchKernelGGL(k_input_prep<2>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
+                       B, K_pad, jt_part);
+  return hipGetLastError();
+}
+
+}  // namespace mhc

@@ -1,0 +1,792 @@
+// Host side of libmodalhc: the C ABI declared in include/mhc.h.
+//
+// Responsibilities: argument validation, the load/configure/finalize state
+// machine, the bin-sorted slot order of the modes, device memory, and the
+// per-block launch sequence
+//   input prep -> contraction (per-step or T-batched) -> bin reduce /
+//   float64 accumulate -> (GKMA) correlation update.
+// No arithmetic of the method runs here; every step is a HIP kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mhc.h"
+#include "mhc_common.h"
+
+using namespace mhc;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct mhc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  mhc_status sticky = MHC_OK;
+
+  // system
+  bool has_system = false;
+  int64_t N = 0, K = 0, M = 0;
+  std::vector<double> mass, freq;
+  // bins
+  bool has_bins = false;
+  int32_t nb = 0;
+  std::vector<int32_t> bins;
+  // configuration
+  bool configured = false;
+  mhc_run_config cfg{};
+  // loading
+  bool rows_started = false, finalized = false;
+  int64_t K_pad = 0, M_used = 0, M_pad = 0;
+  std::vector<int32_t> slot_of_mode, bin_off;
+  std::vector<uint8_t> row_loaded;
+
+  // device memory
+  std::vector<DevBuf> allocs;
+  void* dE = nullptr;
+  double* d_rows = nullptr;   // staging for host eigenvector rows
+  int64_t rows_cap = 0;
+  int32_t* d_slot = nullptr;
+  float* d_sqrtm = nullptr;
+  float* d_isqrtm = nullptr;
+  int32_t* d_bin_off = nullptr;
+
+  // per-block work buffers
+  int chunk = 0;       // steps per processed block
+  int t_pad = 0;       // columns of the B operand
+  int n_atom_chunks = 0;
+  void* dB = nullptr;
+  float* dJ = nullptr;
+  double* d_jt = nullptr;
+  float* d_v = nullptr;
+  float* d_W = nullptr;
+  double *d_hsum = nullptr, *d_hcomp = nullptr, *d_tsum = nullptr, *d_tcomp = nullptr;
+  double* dX = nullptr;
+  double* d_ring = nullptr;
+  int64_t ring_len = 0;
+  int64_t R3 = 0;
+  double *d_csum = nullptr, *d_ccomp = nullptr;
+  double* d_out = nullptr;
+  int64_t n_samples = 0;
+  int last_block = 0;
+
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // pairs
+  size_t ev_used = 0;
+  int64_t bytes = 0;
+};
+
+namespace {
+
+mhc_status fail(mhc_ctx* c, mhc_status st, const std::string& msg) {
+  if (c) {
+    c->err = msg;
+    if (st == MHC_ERR_HIP) c->sticky = MHC_ERR_HIP;
+  }
+  return st;
+}
+
+mhc_status hip_fail(mhc_ctx* c, hipError_t e, const char* where) {
+  return fail(c, MHC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, where)                                   \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, (where));   \
+  } while (0)
+
+mhc_status enter(mhc_ctx* c) {
+  if (!c) return MHC_ERR_INVALID_ARG;
+  if (c->sticky != MHC_OK) return c->sticky;
+  c->err.clear();
+  return MHC_OK;
+}
+
+// Allocate device memory owned by the context.  On failure nothing is kept.
+mhc_status dev_alloc(mhc_ctx* ctx, size_t bytes, void** out, const char* what) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MHC_ERR_OOM, std::string("device allocation failed: ") + what + " (" +
+                                      std::to_string(bytes) + " bytes)");
+  }
+  ctx->allocs.push_back({p, bytes});
+  ctx->bytes += (int64_t)bytes;
+  *out = p;
+  return MHC_OK;
+}
+
+void free_all(mhc_ctx* c) {
+  for (auto& a : c->allocs) (void)hipFree(a.p);
+  c->allocs.clear();
+  c->bytes = 0;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+bool all_finite(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+bool all_finite_f(const float* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+bool uniform_bins(int64_t n_modes, const double* f, int32_t nb, double lo, double hi, int32_t* out) {
+  if (n_modes < 1 || !f || !out || nb < 1 || nb > (1 << 20)) return false;
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo)) return false;
+  const double d = (hi - lo) / nb;
+  for (int64_t n = 0; n < n_modes; ++n) {
+    const double x = f[n];
+    if (!(x >= lo && x <= hi)) {
+      out[n] = -1;
+      continue;
+    }
+    double b = std::floor((x - lo) / d + 1e-9);
+    out[n] = (int32_t)std::min<double>(b, (double)(nb - 1));
+  }
+  return true;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int mhc_abi_version(void) { return MHC_ABI_VERSION; }
+
+const char* mhc_status_string(mhc_status s) {
+  switch (s) {
+    case MHC_OK: return "MHC_OK";
+    case MHC_ERR_INVALID_ARG: return "MHC_ERR_INVALID_ARG";
+    case MHC_ERR_STATE: return "MHC_ERR_STATE";
+    case MHC_ERR_OOM: return "MHC_ERR_OOM";
+    case MHC_ERR_HIP: return "MHC_ERR_HIP";
+    case MHC_ERR_UNSUPPORTED: return "MHC_ERR_UNSUPPORTED";
+    case MHC_ERR_NONFINITE: return "MHC_ERR_NONFINITE";
+  }
+  return "MHC_ERR_UNKNOWN";
+}
+
+const char* mhc_last_error(const mhc_ctx* ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->err.c_str();
+}
+
+mhc_status mhc_bins_uniform(int64_t n_modes, const double* freq_thz, int32_t n_bins, double f_lo, double f_hi,
+                            int32_t* out_bins) {
+  return uniform_bins(n_modes, freq_thz, n_bins, f_lo, f_hi, out_bins) ? MHC_OK : MHC_ERR_INVALID_ARG;
+}
+
+mhc_status mhc_create(int device, void* hip_stream, mhc_ctx** out) {
+  g_create_error.clear();
+  if (!out) {
+    g_create_error = "out is NULL";
+    return MHC_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) {
+    (void)hipGetLastError();
+    g_create_error = std::string("no HIP device: ") + (e != hipSuccess ? hipGetErrorString(e) : "count = 0");
+    return MHC_ERR_HIP;
+  }
+  if (device < 0 || device >= n) {
+    g_create_error = "device index out of range";
+    return MHC_ERR_INVALID_ARG;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return MHC_ERR_HIP;
+  }
+  mhc_ctx* c = new (std::nothrow) mhc_ctx();
+  if (!c) {
+    g_create_error = "host allocation failed";
+    return MHC_ERR_OOM;
+  }
+  c->device = device;
+  if (hip_stream) {
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    e = hipStreamCreate(&c->stream);   // blocking: ordered with the null stream
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+      delete c;
+      return MHC_ERR_HIP;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return MHC_OK;
+}
+
+mhc_status mhc_destroy(mhc_ctx* ctx) {
+  if (!ctx) return MHC_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return MHC_OK;
+}
+
+mhc_status mhc_load_system(mhc_ctx* ctx, int64_t n_atoms, const double* mass_amu, int64_t n_modes,
+                           const double* freq_thz) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (ctx->has_system) return fail(ctx, MHC_ERR_STATE, "system already loaded");
+  if (n_atoms < 1 || n_atoms > (int64_t(1) << 26)) return fail(ctx, MHC_ERR_INVALID_ARG, "n_atoms out of range");
+  if (n_modes < 1 || n_modes > 3 * n_atoms) return fail(ctx, MHC_ERR_INVALID_ARG, "n_modes must be in [1, 3N]");
+  if (!mass_amu || !freq_thz) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL mass or frequency array");
+  for (int64_t i = 0; i < n_atoms; ++i)
+    if (!std::isfinite(mass_amu[i]) || !(mass_amu[i] > 0.0))
+      return fail(ctx, MHC_ERR_INVALID_ARG, "masses must be finite and > 0");
+  if (!all_finite(freq_thz, n_modes)) return fail(ctx, MHC_ERR_INVALID_ARG, "non-finite frequency");
+  ctx->N = n_atoms;
+  ctx->K = 3 * n_atoms;
+  ctx->M = n_modes;
+  ctx->mass.assign(mass_amu, mass_amu + n_atoms);
+  ctx->freq.assign(freq_thz, freq_thz + n_modes);
+  ctx->has_system = true;
+  return MHC_OK;
+}
+
+static mhc_status set_bins_impl(mhc_ctx* ctx, int32_t nb, std::vector<int32_t>&& b) {
+  ctx->nb = nb;
+  ctx->bins = std::move(b);
+  ctx->has_bins = true;
+  return MHC_OK;
+}
+
+mhc_status mhc_set_bins(mhc_ctx* ctx, int32_t n_bins, const int32_t* bin_of_mode) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->has_system || ctx->rows_started) return fail(ctx, MHC_ERR_STATE, "set_bins needs a system and no rows yet");
+  if (n_bins < 1 || n_bins > (1 << 20)) return fail(ctx, MHC_ERR_INVALID_ARG, "n_bins out of range");
+  if (!bin_of_mode) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL bin map");
+  for (int64_t n = 0; n < ctx->M; ++n)
+    if (bin_of_mode[n] < -1 || bin_of_mode[n] >= n_bins) return fail(ctx, MHC_ERR_INVALID_ARG, "bin id out of range");
+  return set_bins_impl(ctx, n_bins, std::vector<int32_t>(bin_of_mode, bin_of_mode + ctx->M));
+}
+
+mhc_status mhc_set_bins_uniform(mhc_ctx* ctx, int32_t n_bins, double f_lo, double f_hi) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->has_system || ctx->rows_started) return fail(ctx, MHC_ERR_STATE, "set_bins needs a system and no rows yet");
+  std::vector<int32_t> b(ctx->M);
+  if (!uniform_bins(ctx->M, ctx->freq.data(), n_bins, f_lo, f_hi, b.data()))
+    return fail(ctx, MHC_ERR_INVALID_ARG, "bad bin count or range");
+  return set_bins_impl(ctx, n_bins, std::move(b));
+}
+
+mhc_status mhc_configure(mhc_ctx* ctx, const mhc_run_config* cfg) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->has_system || ctx->rows_started) return fail(ctx, MHC_ERR_STATE, "configure needs a system and no rows yet");
+  if (!cfg) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL config");
+  if (cfg->methods < 1 || cfg->methods > 3) return fail(ctx, MHC_ERR_INVALID_ARG, "methods must be HNEMA, GKMA or both");
+  if (cfg->precision != MHC_PREC_FP32 && cfg->precision != MHC_PREC_BF16X3)
+    return fail(ctx, MHC_ERR_INVALID_ARG, "unknown precision");
+  if (cfg->t_block != 1 && (cfg->t_block < 32 || cfg->t_block > 512 || cfg->t_block % 32))
+    return fail(ctx, MHC_ERR_INVALID_ARG, "t_block must be 1 or a multiple of 32 in [32, 512]");
+  if (cfg->t_block == 1 && cfg->precision != MHC_PREC_FP32)
+    return fail(ctx, MHC_ERR_UNSUPPORTED, "the per-step path (t_block = 1) is FP32 only");
+  if ((cfg->methods & MHC_GKMA) && (cfg->corr_len < 1 || cfg->corr_len > 65536))
+    return fail(ctx, MHC_ERR_INVALID_ARG, "corr_len must be in [1, 65536]");
+  if ((cfg->methods & MHC_GKMA) && !(std::isfinite(cfg->dt) && cfg->dt > 0.0))
+    return fail(ctx, MHC_ERR_INVALID_ARG, "dt must be finite and > 0");
+  if (cfg->check_finite != 0 && cfg->check_finite != 1) return fail(ctx, MHC_ERR_INVALID_ARG, "check_finite is 0 or 1");
+  if (cfg->reserved[0] || cfg->reserved[1] || cfg->reserved[2])
+    return fail(ctx, MHC_ERR_INVALID_ARG, "reserved fields must be zero");
+  ctx->cfg = *cfg;
+  ctx->configured = true;
+  return MHC_OK;
+}
+
+// Build the bin-sorted slot order and allocate the basis on the first row load.
+static mhc_status start_rows(mhc_ctx* ctx) {
+  const int64_t M = ctx->M, nb = ctx->nb;
+  std::vector<int64_t> count(nb + 1, 0);
+  for (int64_t n = 0; n < M; ++n)
+    if (ctx->bins[n] >= 0) count[ctx->bins[n] + 1]++;
+  std::vector<int32_t> off(nb + 1, 0);
+  for (int64_t b = 0; b < nb; ++b) off[b + 1] = (int32_t)(off[b] + count[b + 1]);
+  std::vector<int32_t> fill(off.begin(), off.end() - 1);
+  std::vector<int32_t> slot(M, -1);
+  for (int64_t n = 0; n < M; ++n) {     // stable: modes keep their order inside a bin
+    const int32_t b = ctx->bins[n];
+    if (b >= 0) slot[n] = fill[b]++;
+  }
+  const int64_t M_used = off[nb];
+  // input prep writes whole 32-atom (96-dof) groups, so cover them
+  const int64_t K_pad = round_up(3 * round_up(ctx->N, ATOMS_PER_PREP), K_ALIGN);
+  const int64_t M_pad = round_up(std::max<int64_t>(M_used, 1), M_ALIGN);
+  const size_t e_bytes = (size_t)M_pad * (size_t)K_pad * 4;   // fp32, or bf16 hi + lo
+  void* dE = nullptr;
+  mhc_status st = dev_alloc(ctx, e_bytes, &dE, "eigenvectors");
+  if (st) return st;
+  HIP_TRY(hipMemsetAsync(dE, 0, e_bytes, ctx->stream), "zero basis");
+  // staging for host rows (about 64 MiB) and slot ids
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(M, (int64_t(64) << 20) / (8 * ctx->K)));
+  void* drows = nullptr;
+  void* dslot = nullptr;
+  if ((st = dev_alloc(ctx, (size_t)cap * ctx->K * 8, &drows, "row staging"))) return st;
+  if ((st = dev_alloc(ctx, (size_t)std::max<int64_t>(cap, 1 << 16) * 4, &dslot, "row slots"))) return st;
+  ctx->dE = dE;
+  ctx->d_rows = reinterpret_cast<double*>(drows);
+  ctx->rows_cap = cap;
+  ctx->d_slot = reinterpret_cast<int32_t*>(dslot);
+  ctx->slot_of_mode = std::move(slot);
+  ctx->bin_off = std::move(off);
+  ctx->M_used = M_used;
+  ctx->K_pad = K_pad;
+  ctx->M_pad = M_pad;
+  ctx->row_loaded.assign(M, 0);
+  ctx->rows_started = true;
+  return MHC_OK;
+}
+
+mhc_status mhc_load_eigvec_rows(mhc_ctx* ctx, int64_t mode0, int64_t n_rows, const double* rows, int on_device) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->has_system || !ctx->has_bins || !ctx->configured || ctx->finalized)
+    return fail(ctx, MHC_ERR_STATE, "eigenvector rows need system, bins and configuration, before finalize");
+  if (mode0 < 0 || n_rows < 0 || mode0 + n_rows > ctx->M) return fail(ctx, MHC_ERR_INVALID_ARG, "row range outside [0, M)");
+  if (n_rows == 0) return MHC_OK;
+  if (!rows) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL rows");
+  if (on_device != 0 && on_device != 1) return fail(ctx, MHC_ERR_INVALID_ARG, "on_device is 0 or 1");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  if (!ctx->rows_started) {
+    if ((st = start_rows(ctx))) return st;
+  }
+  const int prec = ctx->cfg.precision == MHC_PREC_BF16X3 ? PREC_BF16X3 : PREC_FP32;
+  const int64_t step = on_device ? std::min<int64_t>(n_rows, 1 << 16) : ctx->rows_cap;
+  std::vector<int32_t> slots;
+  for (int64_t r0 = 0; r0 < n_rows; r0 += step) {
+    const int64_t nr = std::min(step, n_rows - r0);
+    slots.resize(nr);
+    for (int64_t r = 0; r < nr; ++r) slots[r] = ctx->slot_of_mode[mode0 + r0 + r];
+    HIP_TRY(hipMemcpyAsync(ctx->d_slot, slots.data(), nr * 4, hipMemcpyHostToDevice, ctx->stream), "copy slots");
+    const double* src = rows + r0 * ctx->K;
+    if (!on_device) {
+      HIP_TRY(hipMemcpyAsync(ctx->d_rows, src, (size_t)nr * ctx->K * 8, hipMemcpyHostToDevice, ctx->stream),
+              "copy rows");
+      src = ctx->d_rows;
+    }
+    HIP_TRY(launch_basis_store(ctx->stream, prec, src, nr, ctx->K, ctx->d_slot, ctx->dE, ctx->K_pad),
+            "basis store");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "basis store sync");
+  }
+  for (int64_t r = 0; r < n_rows; ++r) ctx->row_loaded[mode0 + r] = 1;
+  return MHC_OK;
+}
+
+static int t_pad_of(const mhc_run_config& c) { return c.t_block == 1 ? 256 : c.t_block; }
+
+mhc_status mhc_finalize(mhc_ctx* ctx) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->rows_started || ctx->finalized) return fail(ctx, MHC_ERR_STATE, "finalize needs loaded rows, once");
+  for (int64_t n = 0; n < ctx->M; ++n)
+    if (ctx->slot_of_mode[n] >= 0 && !ctx->row_loaded[n])
+      return fail(ctx, MHC_ERR_STATE, "eigenvector row " + std::to_string(n) + " was not loaded");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const auto& c = ctx->cfg;
+  const bool gk = c.methods & MHC_GKMA;
+  const bool hn = c.methods & MHC_HNEMA;
+  const int chunk = t_pad_of(c);
+  const int t_pad = chunk;
+  const int64_t N = ctx->N, K_pad = ctx->K_pad, M_pad = ctx->M_pad, nb = ctx->nb;
+  const int n_ac = (int)((N + ATOMS_PER_PREP - 1) / ATOMS_PER_PREP);
+  const int64_t n_parts = (c.t_block == 1) ? chunk : std::max(1, t_pad / 32);
+  size_t j_bytes = (size_t)n_parts * M_pad * 3 * 4;
+  if (gk) j_bytes = std::max(j_bytes, (size_t)3 * M_pad * t_pad * 4);
+  const int64_t R3 = 3 * (nb + 1);
+  const int L = gk ? c.corr_len : 0;
+  void *pB, *pJ, *pjt, *pv, *pW, *psm, *pism, *poff, *pacc, *pout;
+  if ((st = dev_alloc(ctx, (size_t)16 * t_pad * K_pad, &pB, "B operand"))) return st;
+  if ((st = dev_alloc(ctx, j_bytes, &pJ, "modal currents"))) return st;
+  if ((st = dev_alloc(ctx, (size_t)t_pad * n_ac * 3 * 8, &pjt, "total-current partials"))) return st;
+  if ((st = dev_alloc(ctx, (size_t)chunk * N * 3 * 4, &pv, "velocity staging"))) return st;
+  if ((st = dev_alloc(ctx, (size_t)chunk * N * 9 * 4, &pW, "virial staging"))) return st;
+  if ((st = dev_alloc(ctx, (size_t)N * 4, &psm, "sqrt m"))) return st;
+  if ((st = dev_alloc(ctx, (size_t)N * 4, &pism, "1/sqrt m"))) return st;
+  if ((st = dev_alloc(ctx, (size_t)(nb + 1) * 4, &poff, "bin offsets"))) return st;
+  const size_t acc_doubles = (size_t)(4 * nb * 3 + 4 * 3);
+  if ((st = dev_alloc(ctx, acc_doubles * 8, &pacc, "HNEMA sums"))) return st;
+  size_t out_doubles = (size_t)nb * 3 + 3;
+  if (gk) {
+    void *pX, *pring, *pc;
+    const int64_t ring_len = (int64_t)L - 1 + t_pad;
+    if ((st = dev_alloc(ctx, (size_t)R3 * t_pad * 8, &pX, "binned series"))) return st;
+    if ((st = dev_alloc(ctx, (size_t)ring_len * 3 * 8, &pring, "history ring"))) return st;
+    if ((st = dev_alloc(ctx, (size_t)2 * L * R3 * 3 * 8, &pc, "correlation sums"))) return st;
+    ctx->dX = reinterpret_cast<double*>(pX);
+    ctx->d_ring = reinterpret_cast<double*>(pring);
+    ctx->ring_len = ring_len;
+    ctx->d_csum = reinterpret_cast<double*>(pc);
+    ctx->d_ccomp = ctx->d_csum + (size_t)L * R3 * 3;
+    out_doubles = std::max(out_doubles, (size_t)2 * L * R3 * 3);
+    HIP_TRY(hipMemsetAsync(pX, 0, (size_t)R3 * t_pad * 8, ctx->stream), "zero series");
+    HIP_TRY(hipMemsetAsync(pring, 0, (size_t)ring_len * 3 * 8, ctx->stream), "zero ring");
+  }
+  if ((st = dev_alloc(ctx, out_doubles * 8, &pout, "read-out"))) return st;
+  // masses
+  std::vector<float> sm(N), ism(N);
+  for (int64_t i = 0; i < N; ++i) {
+    const double r = std::sqrt(ctx->mass[i]);
+    sm[i] = (float)r;
+    ism[i] = (float)(1.0 / r);
+  }
+  HIP_TRY(hipMemcpyAsync(psm, sm.data(), N * 4, hipMemcpyHostToDevice, ctx->stream), "copy sqrt m");
+  HIP_TRY(hipMemcpyAsync(pism, ism.data(), N * 4, hipMemcpyHostToDevice, ctx->stream), "copy 1/sqrt m");
+  HIP_TRY(hipMemcpyAsync(poff, ctx->bin_off.data(), (nb + 1) * 4, hipMemcpyHostToDevice, ctx->stream), "copy bins");
+  HIP_TRY(hipMemsetAsync(pB, 0, (size_t)16 * t_pad * K_pad, ctx->stream), "zero B");
+  HIP_TRY(hipMemsetAsync(pJ, 0, j_bytes, ctx->stream), "zero J");
+  HIP_TRY(hipMemsetAsync(pjt, 0, (size_t)t_pad * n_ac * 3 * 8, ctx->stream), "zero partials");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "finalize sync");
+
+  ctx->chunk = chunk;
+  ctx->t_pad = t_pad;
+  ctx->n_atom_chunks = n_ac;
+  ctx->dB = pB;
+  ctx->dJ = reinterpret_cast<float*>(pJ);
+  ctx->d_jt = reinterpret_cast<double*>(pjt);
+  ctx->d_v = reinterpret_cast<float*>(pv);
+  ctx->d_W = reinterpret_cast<float*>(pW);
+  ctx->d_sqrtm = reinterpret_cast<float*>(psm);
+  ctx->d_isqrtm = reinterpret_cast<float*>(pism);
+  ctx->d_bin_off = reinterpret_cast<int32_t*>(poff);
+  double* acc = reinterpret_cast<double*>(pacc);
+  ctx->d_hsum = hn ? acc : nullptr;
+  ctx->d_hcomp = hn ? acc + nb * 3 : nullptr;
+  ctx->d_tsum = hn ? acc + 2 * nb * 3 : nullptr;
+  ctx->d_tcomp = hn ? acc + 2 * nb * 3 + 3 : nullptr;
+  ctx->R3 = R3;
+  ctx->d_out = reinterpret_cast<double*>(pout);
+  ctx->finalized = true;
+  return mhc_reset(ctx);
+}
+
+mhc_status mhc_reset(mhc_ctx* ctx) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "reset needs a finalized context");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const int64_t nb = ctx->nb;
+  if (ctx->d_hsum) HIP_TRY(hipMemsetAsync(ctx->d_hsum, 0, (size_t)(2 * nb * 3 + 6) * 8, ctx->stream), "zero sums");
+  if (ctx->d_csum)
+    HIP_TRY(hipMemsetAsync(ctx->d_csum, 0, (size_t)2 * ctx->cfg.corr_len * ctx->R3 * 3 * 8, ctx->stream), "zero corr");
+  if (ctx->d_ring) HIP_TRY(hipMemsetAsync(ctx->d_ring, 0, (size_t)ctx->ring_len * 3 * 8, ctx->stream), "zero ring");
+  ctx->n_samples = 0;
+  ctx->last_block = 0;
+  return MHC_OK;
+}
+
+static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_count) {
+  const auto& c = ctx->cfg;
+  const bool gk = c.methods & MHC_GKMA;
+  const bool per_step = c.t_block == 1;
+  const int prec = c.precision == MHC_PREC_BF16X3 ? PREC_BF16X3 : PREC_FP32;
+  HIP_TRY(launch_input_prep(ctx->stream, prec, per_step ? 1 : 0, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count,
+                            ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt),
+          "input prep");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    if (ctx->ev_used + 2 > ctx->ev.size()) {
+      for (int q = 0; q < 2; ++q) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e), "event create");
+        ctx->ev.push_back(e);
+      }
+    }
+    e0 = ctx->ev[ctx->ev_used];
+    e1 = ctx->ev[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    HIP_TRY(hipEventRecord(e0, ctx->stream), "event record");
+  }
+  int n_parts = 0;
+  const int64_t ld = ctx->t_pad;
+  if (per_step) {
+    HIP_TRY(launch_gemv_f32(ctx->stream, reinterpret_cast<const float*>(ctx->dE),
+                            reinterpret_cast<const float*>(ctx->dB), t_count, ctx->M_pad, ctx->K_pad, ctx->dJ,
+                            gk ? 1 : 0, ld),
+            "per-step contraction");
+    n_parts = t_count;
+  } else {
+    HIP_TRY(launch_gemm(ctx->stream, prec, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
+                        gk ? 1 : 0, &n_parts),
+            "batched contraction");
+  }
+  if (ctx->timing) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
+  ReduceArgs a{};
+  a.in = ctx->dJ;
+  a.layout_g = gk ? 1 : 0;
+  a.n_parts = n_parts;
+  a.M_pad = ctx->M_pad;
+  a.ld = ld;
+  a.t_count = t_count;
+  a.bin_off = ctx->d_bin_off;
+  a.nb = ctx->nb;
+  a.jt_part = ctx->d_jt;
+  a.n_chunks = ctx->n_atom_chunks;
+  a.hsum = ctx->d_hsum;
+  a.hcomp = ctx->d_hcomp;
+  a.tsum = ctx->d_tsum;
+  a.tcomp = ctx->d_tcomp;
+  a.X = gk ? ctx->dX : nullptr;
+  a.ring = ctx->d_ring;
+  a.ring_len = ctx->ring_len;
+  a.t0 = ctx->n_samples;
+  HIP_TRY(launch_reduce(ctx->stream, a), "bin reduce");
+  if (gk) {
+    HIP_TRY(launch_corr(ctx->stream, ctx->dX, ld, t_count, ctx->R3, c.corr_len, ctx->d_ring, ctx->ring_len,
+                        ctx->n_samples, ctx->d_csum, ctx->d_ccomp),
+            "correlation");
+  }
+  ctx->n_samples += t_count;
+  ctx->last_block = t_count;
+  return MHC_OK;
+}
+
+mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* W, int on_device) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "push needs a finalized context");
+  if (n_steps < 0) return fail(ctx, MHC_ERR_INVALID_ARG, "n_steps < 0");
+  if (on_device != 0 && on_device != 1) return fail(ctx, MHC_ERR_INVALID_ARG, "on_device is 0 or 1");
+  if (n_steps == 0) return MHC_OK;
+  if (!v || !W) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL v or W");
+  const int64_t N = ctx->N;
+  if (!on_device && ctx->cfg.check_finite) {
+    if (!all_finite_f(v, (int64_t)n_steps * N * 3) || !all_finite_f(W, (int64_t)n_steps * N * 9))
+      return fail(ctx, MHC_ERR_NONFINITE, "non-finite velocity or virial");
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  for (int32_t s0 = 0; s0 < n_steps; s0 += ctx->chunk) {
+    const int tc = std::min(ctx->chunk, n_steps - s0);
+    const float* vp = v + (int64_t)s0 * N * 3;
+    const float* Wp = W + (int64_t)s0 * N * 9;
+    if (!on_device) {
+      HIP_TRY(hipMemcpyAsync(ctx->d_v, vp, (size_t)tc * N * 3 * 4, hipMemcpyHostToDevice, ctx->stream), "copy v");
+      HIP_TRY(hipMemcpyAsync(ctx->d_W, Wp, (size_t)tc * N * 9 * 4, hipMemcpyHostToDevice, ctx->stream), "copy W");
+      vp = ctx->d_v;
+      Wp = ctx->d_W;
+    }
+    if ((st = run_block(ctx, vp, Wp, tc))) return st;
+  }
+  if (!on_device) HIP_TRY(hipStreamSynchronize(ctx->stream), "push sync");
+  return MHC_OK;
+}
+
+mhc_status mhc_synchronize(mhc_ctx* ctx) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
+  return MHC_OK;
+}
+
+mhc_status mhc_read_hnema(mhc_ctx* ctx, double* avg, double* total_avg, int64_t* n_samples) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized || !(ctx->cfg.methods & MHC_HNEMA)) return fail(ctx, MHC_ERR_STATE, "HNEMA not enabled");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const int64_t n = ctx->nb * 3;
+  HIP_TRY(launch_hnema_finish(ctx->stream, ctx->d_hsum, ctx->d_hcomp, n, ctx->n_samples, ctx->d_out), "finish");
+  HIP_TRY(launch_hnema_finish(ctx->stream, ctx->d_tsum, ctx->d_tcomp, 3, ctx->n_samples, ctx->d_out + n), "finish");
+  std::vector<double> h(n + 3);
+  HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, (n + 3) * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
+  if (avg) std::memcpy(avg, h.data(), n * 8);
+  if (total_avg) std::memcpy(total_avg, h.data() + n, 24);
+  if (n_samples) *n_samples = ctx->n_samples;
+  return MHC_OK;
+}
+
+mhc_status mhc_read_gkma(mhc_ctx* ctx, double* corr, double* integral, double* hcacf, int64_t* n_samples) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized || !(ctx->cfg.methods & MHC_GKMA)) return fail(ctx, MHC_ERR_STATE, "GKMA not enabled");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const int L = ctx->cfg.corr_len;
+  const int64_t R3 = ctx->R3, nb = ctx->nb;
+  const size_t per = (size_t)L * R3 * 3;
+  HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_csum, ctx->d_ccomp, R3, L, ctx->n_samples, ctx->cfg.dt, ctx->d_out,
+                             ctx->d_out + per),
+          "finish");
+  std::vector<double> h(2 * per);
+  HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, 2 * per * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
+  for (int tau = 0; tau < L; ++tau) {
+    const double* src = h.data() + (size_t)tau * R3 * 3;
+    if (corr) std::memcpy(corr + (size_t)tau * nb * 9, src, nb * 9 * 8);
+    if (hcacf) std::memcpy(hcacf + (size_t)tau * 9, src + nb * 9, 9 * 8);
+    if (integral) std::memcpy(integral + (size_t)tau * nb * 9, h.data() + per + (size_t)tau * R3 * 3, nb * 9 * 8);
+  }
+  if (n_samples) *n_samples = ctx->n_samples;
+  return MHC_OK;
+}
+
+mhc_status mhc_read_block_currents(mhc_ctx* ctx, int32_t t_count, double* jb) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized || !(ctx->cfg.methods & MHC_GKMA)) return fail(ctx, MHC_ERR_STATE, "GKMA not enabled");
+  if (t_count < 0 || t_count > ctx->last_block) return fail(ctx, MHC_ERR_INVALID_ARG, "t_count exceeds the last block");
+  if (t_count == 0) return MHC_OK;
+  if (!jb) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL output");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const int64_t nb = ctx->nb, ld = ctx->t_pad;
+  std::vector<double> h((size_t)3 * nb * ld);
+  HIP_TRY(hipMemcpyAsync(h.data(), ctx->dX, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
+  const int first = ctx->last_block - t_count;
+  for (int t = 0; t < t_count; ++t)
+    for (int64_t b = 0; b < nb; ++b)
+      for (int mu = 0; mu < 3; ++mu) jb[((size_t)t * nb + b) * 3 + mu] = h[(size_t)(b * 3 + mu) * ld + first + t];
+  return MHC_OK;
+}
+
+// ------------------------------------------------------------ save / load
+namespace {
+struct StateHeader {
+  uint64_t magic;
+  int64_t N, M, nb, L, ring_len, R3, n_samples;
+  int32_t methods, precision, t_block, last_block;
+};
+constexpr uint64_t kMagic = 0x4D48435354415431ull;  // "MHCSTAT1"
+}  // namespace
+
+static size_t state_bytes(const mhc_ctx* c) {
+  size_t n = sizeof(StateHeader);
+  if (c->d_hsum) n += (size_t)(2 * c->nb * 3 + 6) * 8;
+  if (c->d_csum) n += (size_t)2 * c->cfg.corr_len * c->R3 * 3 * 8 + (size_t)c->ring_len * 3 * 8;
+  return n;
+}
+
+mhc_status mhc_save_state(mhc_ctx* ctx, void* buf, size_t* len) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "save needs a finalized context");
+  if (!len) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL len");
+  const size_t need = state_bytes(ctx);
+  if (!buf) {
+    *len = need;
+    return MHC_OK;
+  }
+  if (*len < need) return fail(ctx, MHC_ERR_INVALID_ARG, "buffer too small");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  StateHeader hd{kMagic, ctx->N, ctx->M, ctx->nb, ctx->cfg.corr_len, ctx->ring_len, ctx->R3, ctx->n_samples,
+                 ctx->cfg.methods, ctx->cfg.precision, ctx->cfg.t_block, ctx->last_block};
+  char* p = reinterpret_cast<char*>(buf);
+  std::memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  if (ctx->d_hsum) {
+    const size_t n = (size_t)(2 * ctx->nb * 3 + 6) * 8;
+    HIP_TRY(hipMemcpyAsync(p, ctx->d_hsum, n, hipMemcpyDeviceToHost, ctx->stream), "save");
+    p += n;
+  }
+  if (ctx->d_csum) {
+    const size_t n = (size_t)2 * ctx->cfg.corr_len * ctx->R3 * 3 * 8;
+    HIP_TRY(hipMemcpyAsync(p, ctx->d_csum, n, hipMemcpyDeviceToHost, ctx->stream), "save");
+    p += n;
+    const size_t r = (size_t)ctx->ring_len * 3 * 8;
+    HIP_TRY(hipMemcpyAsync(p, ctx->d_ring, r, hipMemcpyDeviceToHost, ctx->stream), "save");
+    p += r;
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "save sync");
+  *len = need;
+  return MHC_OK;
+}
+
+mhc_status mhc_load_state(mhc_ctx* ctx, const void* buf, size_t len) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "load needs a finalized context");
+  if (!buf || len != state_bytes(ctx)) return fail(ctx, MHC_ERR_INVALID_ARG, "state size mismatch");
+  StateHeader hd;
+  std::memcpy(&hd, buf, sizeof hd);
+  if (hd.magic != kMagic || hd.N != ctx->N || hd.M != ctx->M || hd.nb != ctx->nb || hd.L != ctx->cfg.corr_len ||
+      hd.ring_len != ctx->ring_len || hd.R3 != ctx->R3 || hd.methods != ctx->cfg.methods || hd.n_samples < 0)
+    return fail(ctx, MHC_ERR_INVALID_ARG, "state from a different system or configuration");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const char* p = reinterpret_cast<const char*>(buf) + sizeof hd;
+  if (ctx->d_hsum) {
+    const size_t n = (size_t)(2 * ctx->nb * 3 + 6) * 8;
+    HIP_TRY(hipMemcpyAsync(ctx->d_hsum, p, n, hipMemcpyHostToDevice, ctx->stream), "load");
+    p += n;
+  }
+  if (ctx->d_csum) {
+    const size_t n = (size_t)2 * ctx->cfg.corr_len * ctx->R3 * 3 * 8;
+    HIP_TRY(hipMemcpyAsync(ctx->d_csum, p, n, hipMemcpyHostToDevice, ctx->stream), "load");
+    p += n;
+    const size_t r = (size_t)ctx->ring_len * 3 * 8;
+    HIP_TRY(hipMemcpyAsync(ctx->d_ring, p, r, hipMemcpyHostToDevice, ctx->stream), "load");
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "load sync");
+  ctx->n_samples = hd.n_samples;
+  ctx->last_block = 0;
+  return MHC_OK;
+}
+
+// ------------------------------------------------------------ diagnostics
+mhc_status mhc_set_timing(mhc_ctx* ctx, int enable) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (enable != 0 && enable != 1) return fail(ctx, MHC_ERR_INVALID_ARG, "enable is 0 or 1");
+  ctx->timing = enable == 1;
+  return MHC_OK;
+}
+
+mhc_status mhc_kernel_timing(mhc_ctx* ctx, int64_t* launches, double* total_ms) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "timing sync");
+  double tot = 0.0;
+  for (size_t q = 0; q + 1 < ctx->ev_used; q += 2) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[q], ctx->ev[q + 1]), "elapsed");
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)(ctx->ev_used / 2);
+  if (total_ms) *total_ms = tot;
+  ctx->ev_used = 0;
+  return MHC_OK;
+}
+
+mhc_status mhc_device_bytes(mhc_ctx* ctx, int64_t* bytes) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!bytes) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL bytes");
+  *bytes = ctx->bytes;
+  return MHC_OK;
+}
+
+}  // extern "C"

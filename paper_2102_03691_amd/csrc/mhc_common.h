@@ -1,0 +1,94 @@
+// Internal declarations shared by the host library and the HIP kernels of
+// libmodalhc.  Not part of the public ABI (see include/mhc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mhc {
+
+// ---------------------------------------------------------------- layouts
+// Row block = 32 slots (modes in bin-sorted order); the contraction dimension
+// (dofs, K) is split into chunks whose size matches one matrix-core operand:
+//   FP32   chunk of 8 dofs:  fragment [64 lanes][4 floats]   (1 KiB)
+//   BF16   chunk of 16 dofs: fragment [64 lanes][8 bf16]     (1 KiB) x {hi, lo}
+// Inside a fragment, lane l carries row (l % 32) and dofs
+//   FP32: k = 8*kc + 4*(l/32) + e,  e = 0..3
+//   BF16: k = 16*kc + 8*(l/32) + e, e = 0..7
+// Eigenvectors (A operand) and activations (B operand) use the same map, so
+// every matrix-core product pairs equal k on both sides.
+//
+//   E  FP32   [M_pad/32][K_pad/8][64][4]            float
+//   E  BF16   [M_pad/32][K_pad/16][2 (hi,lo)][64][8] bf16
+//   B  plain  [T][4][K_pad]                           float  (per-step path)
+//   B  FP32   [4*NTB][K_pad/8][64][4]                 float  (cb = c*NTB + tb)
+//   B  BF16   [4*NTB][K_pad/16][2][64][8]             bf16
+// Channels c: 0 = u = sqrt(m) v, 1..3 = w^mu = W^{mu .} / sqrt(m).
+constexpr int K_ALIGN = 64;     // K_pad multiple
+constexpr int M_ALIGN = 256;    // M_pad multiple
+constexpr int ATOMS_PER_PREP = 32;  // atoms per input-prep work-group (96 dofs)
+
+enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1 };
+
+// ------------------------------------------------------------- launchers
+// Every launcher queues work on `s` and returns the launch status.
+
+// Convert n_rows float64 E^T rows (device, row r = mode r0 + r) into the
+// storage layout.  slot_of_row[r] is the destination slot (-1 = skip).
+hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows,
+                              int64_t K, const int32_t* slot_of_row, void* E, int64_t K_pad);
+
+// Input preparation for one block of t_pad columns (t_count real steps):
+// B operand in the layout of `prec` (or plain when plain != 0) and the
+// per-atom-chunk partial total currents jt_part[t][chunk][3] (float64).
+hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
+                             const float* sqrt_m, const float* inv_sqrt_m, int64_t N,
+                             int t_count, int t_pad, void* B, int64_t K_pad, double* jt_part);
+
+// Per-step matrix-vector path (FP32): for steps t = 0..n_steps-1 of a plain
+// B buffer, J_n^mu = Xdot_n A_n^mu for every slot.  Output either
+//   hnema: out[t][M_pad][3]   (layout_g == 0)
+//   gkma : out[3][M_pad][ld]  at column t (layout_g == 1)
+hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_steps, int64_t M_pad,
+                           int64_t K_pad, float* out, int layout_g, int64_t ld);
+
+// T-batched matrix-core contraction with fused modal-current epilogue.
+//   ntb     t-blocks of 32 steps in the block (t_pad = 32*ntb)
+//   hnema:  out[ntile][M_pad][3]   sum over the tile's steps
+//   gkma :  out[3][M_pad][t_pad]
+// Returns the number of column tiles through *n_parts.
+hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad,
+                       int64_t K_pad, int ntb, float* out, int layout_g, int* n_parts);
+
+// Bin reduction + float64 accumulation.
+//   HNEMA-only: part sums in[n_parts][M_pad][3] -> hsum/hcomp[nb][3] (Neumaier)
+//   GKMA:       per-step in[3][M_pad][ld]      -> X[(b*3+mu)][ld] float64, and
+//               (if hsum) the HNEMA sums of the same steps.
+//   The last work-group reduces jt_part[t][n_chunks][3] into the totals:
+//   X rows 3*nb..3*nb+2 (GKMA), the history ring (GKMA), tsum/tcomp (HNEMA).
+struct ReduceArgs {
+  const float* in; int layout_g; int n_parts; int64_t M_pad; int64_t ld; int t_count;
+  const int32_t* bin_off; int nb;
+  const double* jt_part; int n_chunks;
+  double* hsum; double* hcomp; double* tsum; double* tcomp;  // HNEMA (may be null)
+  double* X;                                                 // GKMA (may be null)
+  double* ring; int64_t ring_len; int64_t t0;                // GKMA history
+};
+hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a);
+
+// GKMA correlation update: for r < R3 = 3(nb+1), tau < L, nu < 3
+//   C[tau][r][nu] += sum_{t < t_count, t0+t-tau >= 0} X[r][t] * ring[(t0+t-tau) % ring_len][nu]
+// accumulated with Neumaier compensation into csum/ccomp.
+hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
+                       const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp);
+
+// Read-out of the GKMA accumulators: C = (csum + ccomp) / max(S - tau, 1)
+// (zero when S <= tau) and its trapezoid running integral with step dt.
+hipError_t launch_corr_finish(hipStream_t s, const double* csum, const double* ccomp, int64_t R3,
+                              int L, int64_t S, double dt, double* corr, double* integral);
+
+// Read-out of the HNEMA accumulators: avg = (sum + comp) / S (zero when S = 0).
+hipError_t launch_hnema_finish(hipStream_t s, const double* sum, const double* comp, int64_t n,
+                               int64_t S, double* avg);
+
+}  // namespace mhc

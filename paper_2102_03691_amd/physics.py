@@ -1,0 +1,20 @@
+"""Scalar prefactors that turn the library's outputs into thermal conductivity.
+
+Eq. 19: kappa_b^{mu nu} F_e^nu = <J_b^mu> / (T V), so for a driving force
+along one axis kappa_b^{mu x} = <J_b^mu> / (T V F_e).
+Eq. 17: kappa_b^{mu nu}(tau) = G_b^{mu nu}(tau) / (k_B T^2 V), G the running
+integral of the modal-current / total-current correlation.
+Units: eV, Angstrom, fs, K in; W/(m K) out.
+"""
+KB_EV_PER_K = 8.617333262e-5
+_EV_PER_FS_A_K_IN_W_PER_M_K = 1.602176634e-19 / (1e-15 * 1e-10)
+
+
+def hnema_kappa(avg, temperature, volume_a3, fe_per_a):
+    """kappa from an HNEMA average <J> (eV A/fs) for a drive F_e (1/A)."""
+    return avg / (temperature * volume_a3 * fe_per_a) * _EV_PER_FS_A_K_IN_W_PER_M_K
+
+
+def gkma_kappa(integral, temperature, volume_a3):
+    """kappa(tau) from the GKMA running integral ((eV A/fs)^2 fs)."""
+    return integral / (KB_EV_PER_K * temperature ** 2 * volume_a3) * _EV_PER_FS_A_K_IN_W_PER_M_K

@@ -1,0 +1,77 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, validates arguments, and its host-only bin rule matches the oracle's."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2102_03691_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mhc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhc_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib.library()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version_and_status_strings():
+    lib = _lib.library()
+    assert lib.mhc_abi_version() == 1
+    for code, name in _lib._STATUS.items():
+        assert lib.mhc_status_string(code).decode() == name
+
+
+@pytest.mark.parametrize("dims,nb", [((4, 4, 4), 100), ((16, 16, 16), 500), ((48, 48, 4), 1000),
+                                     ((6, 6, 6), 37), ((10, 10, 10), 500)])
+def test_uniform_bins_match_oracle_exactly(dims, nb):
+    lat = synth.BlochLattice(dims)
+    f = lat.frequencies
+    got = _lib.bins_uniform(f, nb, 0.0, lat.f_max)
+    want = oracle.bin_of_mode(f, nb, 0.0, lat.f_max)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_uniform_bins_edges_and_exclusion():
+    f = np.array([0.0, 1.999, 2.0, np.nextafter(2.0, 0), 7.999, 8.0, -0.1, 8.1, 5.0])
+    np.testing.assert_array_equal(_lib.bins_uniform(f, 4, 0.0, 8.0), oracle.bin_of_mode(f, 4, 0.0, 8.0))
+
+
+def test_uniform_bins_rejects_bad_arguments():
+    f = np.ones(3)
+    for nb, lo, hi in [(0, 0.0, 1.0), (4, 1.0, 1.0), (4, 2.0, 1.0), (4, 0.0, float("nan"))]:
+        with pytest.raises(_lib.MhcError):
+            _lib.bins_uniform(f, nb, lo, hi)
+
+
+def test_null_context_and_null_pointers_are_invalid_arg():
+    lib = _lib.library()
+    assert lib.mhc_load_system(None, 1, None, 1, None) == 1
+    assert lib.mhc_push(None, 1, None, None, 0) == 1
+    assert lib.mhc_finalize(None) == 1
+    assert lib.mhc_create(0, None, None) == 1
+    assert lib.mhc_destroy(None) == 0
+
+
+def test_create_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _lib.library()
+    h = C.c_void_p()
+    assert lib.mhc_create(0, None, C.byref(h)) == 4
+    assert h.value is None
+    assert b"HIP" in lib.mhc_last_error(None) or len(lib.mhc_last_error(None)) > 0
