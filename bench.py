@@ -1,0 +1,212 @@
+"""Throughput of the modal heat-current hot path on one MI355X.
+
+One bench step = one pass of the whole path over one block of T sampled MD
+steps: input prep -> projection GEMM with fused modal-current epilogue ->
+frequency binning -> float64 HNEMA accumulation (and, for GKMA workloads,
+the float64 correlation update).  Inputs are generated in device memory
+before the timed region.
+
+Metric: atom*mode*steps/s = N_atoms * N_modes * (MD steps processed) / time.
+
+Prints one JSON line (see the design notes for the field definitions).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "modal heat-current atom*mode*steps/s, split-BF16 vs FP32 at ≤1e-4 rel err"
+
+# MI355X published peaks
+PEAK_BF16_FLOPS = 2.5e15
+PEAK_FP32_MFMA_FLOPS = 157.3e12
+PEAK_HBM_BPS = 8.0e12
+
+WORKLOADS = {
+    # name: (dims, t_block, precision, methods, n_bins, corr_len, default bench steps)
+    "slab48x48x4_hnema_bf16x3_t128": ((48, 48, 4), 128, 1, 1, 1000, 0, 156),
+    "slab48x48x4_hnema_fp32_t128": ((48, 48, 4), 128, 0, 1, 1000, 0, 20),
+    "sc16_hnema_fp32_t1": ((16, 16, 16), 1, 0, 1, 500, 0, 40),
+    "rod4x4x1500_gkma_bf16x3_t256": ((4, 4, 1500), 256, 1, 3, 1000, 2000, 20),
+}
+DEFAULT = "slab48x48x4_hnema_bf16x3_t128"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_context(lat, t_block, precision, methods, nb, corr_len, device=0):
+    import torch
+    import synth
+    from paper_2102_03691_amd import ModalHC
+    h = ModalHC(device)
+    m = synth.masses(lat.n_atoms)
+    h.load_system(m, lat.frequencies)
+    h.set_bins_uniform(nb, 0.0, lat.f_max)
+    h.configure(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=1.0)
+    M = lat.n_modes
+    chunk = max(1, min(M, (512 << 20) // (8 * 3 * lat.n_atoms)))
+    for r0 in range(0, M, chunk):
+        n = min(chunk, M - r0)
+        rows = lat.eig_rows_torch(r0, n, device=f"cuda:{device}")
+        h.load_eigvec_rows(r0, rows)
+        del rows
+    torch.cuda.synchronize()
+    h.finalize()
+    return h, m
+
+
+def time_pushes(h, blocks_v, blocks_W, n_warm, n_steps):
+    import torch
+    for i in range(n_warm):
+        h.push(blocks_v[i % len(blocks_v)], blocks_W[i % len(blocks_W)])
+    h.synchronize()
+    h.kernel_timing()                       # drop warm-up launches
+    h.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_steps):
+        j = (n_warm + i) % len(blocks_v)
+        h.push(blocks_v[j], blocks_W[j])
+    h.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kms = h.kernel_timing()
+    h.set_timing(False)
+    return t1 - t0, launches, kms
+
+
+def cpu_baseline(dims, t_block, nb, budget_s=12.0):
+    """The FP64 oracle on a bounded sample of the same workload.
+
+    Same lattice and block length; the oracle's Eq. 13/16 projection and the
+    binning are applied to consecutive chunks of modes (rows of E^T) until
+    about ``budget_s`` seconds of CPU work have been timed.  The oracle's cost
+    is linear in the number of modes, so the rate carries over to the whole
+    basis.  Generating the eigenvector rows is input preparation, not timed.
+    """
+    import oracle
+    import synth
+    lat = synth.BlochLattice(dims)
+    m = synth.masses(lat.n_atoms)
+    T = max(t_block, 128)
+    v, W = synth.gen_steps(0, m, 0, T)
+    bins = oracle.bin_of_mode(lat.frequencies, nb, 0.0, lat.f_max)
+    rows_per = min(lat.n_modes, 2048)
+    done_units, spent, r0 = 0, 0.0, 0
+    while r0 < lat.n_modes and spent < budget_s:
+        n = min(rows_per, lat.n_modes - r0)
+        Ec = lat.eig_rows(r0, n).T                     # [3N, n] columns of E
+        t0 = time.perf_counter()
+        Jn = oracle.modal_currents(Ec, m, v, W)
+        oracle.binned_current(Jn, bins[r0:r0 + n], nb)
+        spent += time.perf_counter() - t0
+        done_units += lat.n_atoms * n * T
+        r0 += n
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": done_units / spent, "unit": "atom*mode*steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{r0} of {lat.n_modes} modes x {T} steps of the same lattice (float64 numpy/BLAS), "
+                      f"{spent:.1f} s of CPU work"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design "
+              "note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    dims, t_block, prec, methods, nb, L, default_steps = WORKLOADS[args.workload]
+    K = args.steps or default_steps
+    lat = synth.BlochLattice(dims)
+    N, M = lat.n_atoms, lat.n_modes
+    log(f"workload {args.workload}: N={N} M={M} T={t_block} prec={prec} steps={K} warmup={args.warmup}")
+    h, m = make_context(lat, t_block, prec, methods, nb, L)
+    md_per_step = t_block if t_block > 1 else 256      # per-step path: 256 MD steps per launch
+    # inputs resident in HBM before the timed region (distinct block per bench step, cycled if huge)
+    bytes_per_block = md_per_step * N * 12 * 4
+    n_blocks = max(1, min(K + args.warmup, int(24e9 // bytes_per_block)))
+    v, W = synth.gen_steps_torch(1, m, n_blocks * md_per_step, device="cuda:0")
+    bv = [v[i * md_per_step:(i + 1) * md_per_step] for i in range(n_blocks)]
+    bW = [W[i * md_per_step:(i + 1) * md_per_step] for i in range(n_blocks)]
+    log(f"inputs: {n_blocks} blocks resident ({n_blocks * bytes_per_block / 1e9:.2f} GB)")
+    wall, launches, kms = time_pushes(h, bv, bW, args.warmup, K)
+    units = float(N) * M * md_per_step * K
+    value = units / wall
+    avg_ms = kms / max(launches, 1)
+    units_per_launch = float(N) * M * md_per_step
+    if prec == 1:
+        flops = 72.0 * units_per_launch          # three bf16 products, 24 FLOP each
+        roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_BF16_FLOPS / 1e12,
+                "unit": "TFLOP/s"}
+    elif t_block > 1:
+        flops = 24.0 * units_per_launch
+        roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_FP32_MFMA_FLOPS / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        byts = 12.0 * units_per_launch               # E streamed once per MD step: 3 dofs x 4 B per atom*mode
+        roof = {"bound": "hbm", "achieved": byts / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_BPS / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "k_gemm" if t_block > 1 else "k_gemv_f32"
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches"] = launches
+    del bv, bW, v, W
+    h.close()
+    torch.cuda.empty_cache()
+
+    out = {"metric": METRIC, "value": value, "unit": "atom*mode*steps/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": {0: "f32", 1: "bf16x3"}[prec], "data": "synthetic",
+           "config": {"workload": args.workload, "atoms": N, "modes": M, "md_steps_per_step": md_per_step,
+                      "t_block": t_block, "bins": nb, "corr_len": L,
+                      "precision": {0: "fp32 operands, fp32 accumulate",
+                                    1: "split-bf16 hi*hi+hi*lo+lo*hi, fp32 accumulate"}[prec]
+                      + "; fp64 bins and time sums",
+                      "parallelism": "single GPU"},
+           "roofline": roof}
+
+    if not args.no_fp32_baseline and not (prec == 0 and t_block == 1):
+        log("plain per-step FP32 path on the same lattice")
+        h2, m2 = make_context(lat, 1, 0, 1, nb, 0)
+        n_md = 256
+        v2, W2 = synth.gen_steps_torch(2, m2, n_md, device="cuda:0")
+        wall2, l2, k2 = time_pushes(h2, [v2], [W2], 0, 1)
+        h2.close()
+        del v2, W2
+        torch.cuda.empty_cache()
+        v_fp32 = float(N) * M * n_md / wall2
+        out["fp32_per_step"] = {"value": v_fp32, "unit": "atom*mode*steps/s", "md_steps": n_md,
+                                "ms_per_md_step": wall2 / n_md * 1e3,
+                                "hbm_GBps": 12.0 * N * M * n_md / (k2 * 1e-3) / 1e9 if k2 > 0 else None}
+        out["speedup_vs_fp32_per_step"] = value / v_fp32
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(dims, t_block, nb)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,22 +77,16 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
     }
     return;
   }
-  // last work-group: total current of Eq. 10 per step (float64 partials over atom chunks)
+  // last work-group: per-step total current of Eq. 10 (already summed over atoms)
   double h3[3] = {0.0, 0.0, 0.0};
   for (int t = tid; t < a.t_count; t += 256) {
-    double j[3] = {0.0, 0.0, 0.0};
-    const double* jp = a.jt_part + (int64_t)t * a.n_chunks * 3;
-    for (int c = 0; c < a.n_chunks; ++c) {
-      j[0] += jp[c * 3 + 0];
-      j[1] += jp[c * 3 + 1];
-      j[2] += jp[c * 3 + 2];
-    }
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
-      h3[mu] += j[mu];
+      const double j = a.jtot[t * 3 + mu];
+      h3[mu] += j;
       if (a.X) {
-        a.X[((int64_t)a.nb * 3 + mu) * a.ld + t] = j[mu];
-        a.ring[((a.t0 + t) % a.ring_len) * 3 + mu] = j[mu];
+        a.X[((int64_t)a.nb * 3 + mu) * a.ld + t] = j;
+        a.ring[((a.t0 + t) % a.ring_len) * 3 + mu] = j;
       }
     }
   }
@@ -103,6 +97,38 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
       if (tid == 0) neumaier_add(a.tsum[mu], a.tcomp[mu], tot);
     }
   }
+}
+
+// Eq. 10 summed over atoms: one wave per step adds the float64 partials of
+// the atom chunks in a fixed order.
+__global__ void __launch_bounds__(64) k_total(const double* __restrict__ jt_part, int n_chunks,
+                                              double* __restrict__ jtot) {
+  const int t = blockIdx.x;
+  const int lane = threadIdx.x;
+  double j0 = 0.0, j1 = 0.0, j2 = 0.0;
+  const double* p = jt_part + (int64_t)t * n_chunks * 3;
+  for (int c = lane; c < n_chunks; c += 64) {
+    j0 += p[c * 3 + 0];
+    j1 += p[c * 3 + 1];
+    j2 += p[c * 3 + 2];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    j0 += __shfl_xor(j0, off);
+    j1 += __shfl_xor(j1, off);
+    j2 += __shfl_xor(j2, off);
+  }
+  if (lane == 0) {
+    jtot[t * 3 + 0] = j0;
+    jtot[t * 3 + 1] = j1;
+    jtot[t * 3 + 2] = j2;
+  }
+}
+
+hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int t_count, double* jtot) {
+  if (t_count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_total, dim3((unsigned)t_count), dim3(64), 0, s, jt_part, n_chunks, jtot);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a) {

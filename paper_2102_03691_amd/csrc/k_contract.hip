@@ -99,14 +99,26 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 // ------------------------------------------------------------ matrix cores
 // Work-group = 4 waves arranged WM x WT; each wave owns MB row blocks (32 slots
 // each) and one t-block of 32 steps, for all four channels: 4*MB accumulators
-// of 32x32 floats.  A operand (E) stages of SU 16-byte units per row block
-// are double-buffered in LDS; B fragments are read by each wave straight
-// from global memory (L2), one chunk ahead.
+// of 32x32 floats.
 //
-// Both A and B are laid out per row/column block as [stage][SU] u32x4 with
-//   BF16: unit (chunk*2 + hi/lo)*64 + lane   (chunk = 16 dofs)
-//   FP32: unit chunk*64 + lane               (chunk = 8 dofs)
-template <int PREC, int WM, int WT, int MB, int SU>
+// Both operands are laid out per row/column block as [stage][SU] u32x4 with
+// a stage of 32 dofs (SU = 256 units of 16 bytes):
+//   BF16: unit (chunk*2 + hi/lo)*64 + lane   (chunk = 16 dofs, 2 per stage)
+//   FP32: unit chunk*64 + lane               (chunk = 8 dofs, 4 per stage)
+//
+// Pipeline (branch-free, unrolled by two stages so the two A staging sets are
+// static).  At the top of stage s a wave issues its share of the A fragments
+// of stage s+2 (E streamed from HBM) into staging registers; it then runs the
+// MFMAs of stage s chunk by chunk (A from LDS, B from registers), refilling
+// each chunk's B registers with the same chunk of stage s+1 as soon as they
+// are consumed; finally it stores the A fragments of stage s+1 (issued one
+// stage earlier) into the other LDS buffer and synchronizes.  Loads retire in
+// issue order, so every wait the compiler inserts leaves the newer loads in
+// flight: B (L2-resident activations) has one stage of MFMAs to arrive, A
+// (HBM) two.
+constexpr int SU = 256;
+
+template <int PREC, int WM, int WT, int MB>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
 k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, int ntb,
        float* __restrict__ out, int layout_g, int64_t M_pad, int n_mtiles, int n_ntiles) {
@@ -115,8 +127,9 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, 
   constexpr bool BF = (PREC == PREC_BF16X3);
   constexpr int UPC = BF ? 128 : 64;                             // units per chunk
   constexpr int CPS = SU / UPC;                                  // chunks per stage
+  constexpr int NBF = BF ? 8 : 4;                                // B units per chunk per lane
+  constexpr int NBS = NBF * CPS;                                 // B units per stage per lane
   constexpr int A_PER_THR = RBW * SU / 256;
-  static_assert(RBW * SU % 256 == 0, "stage split");
   __shared__ u32x4 lds[2][RBW][SU];
 
   const int tid = threadIdx.x;
@@ -136,40 +149,35 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, 
   const int64_t rb0 = (int64_t)mtile * RBW;
   const int tb = ntile * WT + wt;
   const int64_t per_blk = 8 * K_pad;                              // units per row/column block
-  const int n_stages = (int)(per_blk / SU);
-  const int n_chunks = n_stages * CPS;
+  const int n_stages = (int)(per_blk / SU);                      // even (K_pad % 64 == 0)
 
   const u32x4* Ebase = E + rb0 * per_blk;
-  u32x4 a_st[A_PER_THR];
-  auto load_A = [&](int s) {
+  auto load_A = [&](int s, u32x4* dst) {
 #pragma unroll
     for (int q = 0; q < A_PER_THR; ++q) {
       const int idx = tid + 256 * q;
-      const int rbl = idx / SU, w = idx % SU;
-      a_st[q] = __builtin_nontemporal_load(Ebase + rbl * per_blk + (int64_t)s * SU + w);
+      dst[q] = __builtin_nontemporal_load(Ebase + (idx / SU) * per_blk + (int64_t)s * SU + idx % SU);
     }
   };
-  auto store_A = [&](int buf) {
+  auto store_A = [&](int buf, const u32x4* src) {
 #pragma unroll
     for (int q = 0; q < A_PER_THR; ++q) {
       const int idx = tid + 256 * q;
-      lds[buf][idx / SU][idx % SU] = a_st[q];
+      lds[buf][idx / SU][idx % SU] = src[q];
     }
   };
-
-  const u32x4* Bc[4];
+  const u32x4* Bw[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) Bc[c] = B + ((int64_t)c * ntb + tb) * per_blk + lane;
-
-  constexpr int NBF = BF ? 8 : 4;        // B units per chunk per lane
-  auto load_B = [&](int kc, u32x4* dst) {
+  for (int c = 0; c < 4; ++c) Bw[c] = B + ((int64_t)c * ntb + tb) * per_blk + lane;
+  auto load_B = [&](int s, int kk, u32x4* dst) {     // chunk kk of stage s
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
+      const int64_t u = (int64_t)s * SU + kk * UPC;
       if constexpr (BF) {
-        dst[2 * c + 0] = Bc[c][(int64_t)kc * 128];
-        dst[2 * c + 1] = Bc[c][(int64_t)kc * 128 + 64];
+        dst[2 * c + 0] = Bw[c][u];
+        dst[2 * c + 1] = Bw[c][u + 64];
       } else {
-        dst[c] = Bc[c][(int64_t)kc * 64];
+        dst[c] = Bw[c][u];
       }
     }
   };
@@ -182,19 +190,12 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, 
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
 
-  load_A(0);
-  store_A(0);
-  u32x4 bcur[NBF], bnext[NBF];
-  load_B(0, bcur);
-  __syncthreads();
-
-  for (int s = 0; s < n_stages; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < n_stages) load_A(s + 1);
+  // MFMAs of stage s (A from LDS buffer `buf`, B from `bs`); after chunk kk
+  // is consumed its registers are refilled with chunk kk of stage `s_next`.
+  auto compute = [&](int buf, u32x4* bs, int s_next) {
 #pragma unroll
     for (int kk = 0; kk < CPS; ++kk) {
-      const int kc = s * CPS + kk;
-      if (kc + 1 < n_chunks) load_B(kc + 1, bnext);
+      u32x4* bc = bs + kk * NBF;
       if constexpr (BF) {
         bf16x8 ah[MB], al[MB];
 #pragma unroll
@@ -208,19 +209,19 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, 
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                ah[rb], __builtin_bit_cast(bf16x8, bcur[2 * c]), acc[rb][c], 0, 0, 0);
+                ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                ah[rb], __builtin_bit_cast(bf16x8, bcur[2 * c + 1]), acc[rb][c], 0, 0, 0);
+                ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c + 1]), acc[rb][c], 0, 0, 0);
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                al[rb], __builtin_bit_cast(bf16x8, bcur[2 * c]), acc[rb][c], 0, 0, 0);
+                al[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
       } else {
         f32x4 a[MB];
 #pragma unroll
@@ -233,12 +234,38 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, 
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                  a[rb][e], __builtin_bit_cast(f32x4, bcur[c])[e], acc[rb][c], 0, 0, 0);
+                  a[rb][e], __builtin_bit_cast(f32x4, bc[c])[e], acc[rb][c], 0, 0, 0);
       }
-#pragma unroll
-      for (int q = 0; q < NBF; ++q) bcur[q] = bnext[q];
+      // keep the issue order: this chunk's MFMAs, then its refill loads
+      __builtin_amdgcn_sched_barrier(0);
+      load_B(s_next, kk, bc);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (s + 1 < n_stages) store_A(buf ^ 1);
+  };
+
+  // prologue: A(0) -> LDS buffer 0, A(1) in staging set 1, B(0) in registers
+  u32x4 ast0[A_PER_THR], ast1[A_PER_THR];
+  u32x4 bq[NBS];
+  load_A(0, ast0);
+#pragma unroll
+  for (int kk = 0; kk < CPS; ++kk) load_B(0, kk, bq + kk * NBF);
+  load_A(1, ast1);
+  store_A(0, ast0);
+  __syncthreads();
+
+  const int last = n_stages - 1;
+  for (int s = 0; s < n_stages; s += 2) {
+    // even stage s: B(s) in bq, A(s+1) in ast1, A(s) in LDS buffer 0
+    load_A(min(s + 2, last), ast0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0, bq, min(s + 1, last));
+    store_A(1, ast1);
+    __syncthreads();
+    // odd stage s+1: B(s+1) in bq, A(s+2) in ast0, A(s+1) in LDS buffer 1
+    load_A(min(s + 3, last), ast1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(1, bq, min(s + 2, last));
+    store_A(0, ast0);
     __syncthreads();
   }
 
@@ -299,17 +326,17 @@ static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, 
     // 128 slots x 4 t-blocks per work-group
     const int n_m = (int)(M_pad / 128), n_n = ntb / 4;
     *n_parts = n_n;
-    hipLaunchKernelGGL((k_gemm<PREC, 1, 4, 4, 512>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
+    hipLaunchKernelGGL((k_gemm<PREC, 1, 4, 4>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
                        layout_g, M_pad, n_m, n_n);
   } else if (ntb % 2 == 0) {
     const int n_m = (int)(M_pad / 256), n_n = ntb / 2;
     *n_parts = n_n;
-    hipLaunchKernelGGL((k_gemm<PREC, 2, 2, 4, 256>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
+    hipLaunchKernelGGL((k_gemm<PREC, 2, 2, 4>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
                        layout_g, M_pad, n_m, n_n);
   } else {
     const int n_m = (int)(M_pad / 256), n_n = ntb;
     *n_parts = n_n;
-    hipLaunchKernelGGL((k_gemm<PREC, 4, 1, 2, 256>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
+    hipLaunchKernelGGL((k_gemm<PREC, 4, 1, 2>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
                        layout_g, M_pad, n_m, n_n);
   }
   return hipGetLastError();

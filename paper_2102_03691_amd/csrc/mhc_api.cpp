@@ -73,6 +73,7 @@ struct mhc_ctx {
   void* dB = nullptr;
   float* dJ = nullptr;
   double* d_jt = nullptr;
+  double* d_jtot = nullptr;
   float* d_v = nullptr;
   float* d_W = nullptr;
   double *d_hsum = nullptr, *d_hcomp = nullptr, *d_tsum = nullptr, *d_tcomp = nullptr;
@@ -433,6 +434,8 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
   if ((st = dev_alloc(ctx, (size_t)16 * t_pad * K_pad, &pB, "B operand"))) return st;
   if ((st = dev_alloc(ctx, j_bytes, &pJ, "modal currents"))) return st;
   if ((st = dev_alloc(ctx, (size_t)t_pad * n_ac * 3 * 8, &pjt, "total-current partials"))) return st;
+  void* pjtot = nullptr;
+  if ((st = dev_alloc(ctx, (size_t)t_pad * 3 * 8, &pjtot, "total current"))) return st;
   if ((st = dev_alloc(ctx, (size_t)chunk * N * 3 * 4, &pv, "velocity staging"))) return st;
   if ((st = dev_alloc(ctx, (size_t)chunk * N * 9 * 4, &pW, "virial staging"))) return st;
   if ((st = dev_alloc(ctx, (size_t)N * 4, &psm, "sqrt m"))) return st;
@@ -478,6 +481,7 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
   ctx->dB = pB;
   ctx->dJ = reinterpret_cast<float*>(pJ);
   ctx->d_jt = reinterpret_cast<double*>(pjt);
+  ctx->d_jtot = reinterpret_cast<double*>(pjtot);
   ctx->d_v = reinterpret_cast<float*>(pv);
   ctx->d_W = reinterpret_cast<float*>(pW);
   ctx->d_sqrtm = reinterpret_cast<float*>(psm);
@@ -545,6 +549,7 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
             "batched contraction");
   }
   if (ctx->timing) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
+  HIP_TRY(launch_total(ctx->stream, ctx->d_jt, ctx->n_atom_chunks, t_count, ctx->d_jtot), "total current");
   ReduceArgs a{};
   a.in = ctx->dJ;
   a.layout_g = gk ? 1 : 0;
@@ -554,8 +559,7 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
   a.t_count = t_count;
   a.bin_off = ctx->d_bin_off;
   a.nb = ctx->nb;
-  a.jt_part = ctx->d_jt;
-  a.n_chunks = ctx->n_atom_chunks;
+  a.jtot = ctx->d_jtot;
   a.hsum = ctx->d_hsum;
   a.hcomp = ctx->d_hcomp;
   a.tsum = ctx->d_tsum;

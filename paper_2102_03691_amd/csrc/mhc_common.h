@@ -64,17 +64,20 @@ hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, in
 //   HNEMA-only: part sums in[n_parts][M_pad][3] -> hsum/hcomp[nb][3] (Neumaier)
 //   GKMA:       per-step in[3][M_pad][ld]      -> X[(b*3+mu)][ld] float64, and
 //               (if hsum) the HNEMA sums of the same steps.
-//   The last work-group reduces jt_part[t][n_chunks][3] into the totals:
+//   The last work-group distributes the per-step totals jtot[t][3]:
 //   X rows 3*nb..3*nb+2 (GKMA), the history ring (GKMA), tsum/tcomp (HNEMA).
 struct ReduceArgs {
   const float* in; int layout_g; int n_parts; int64_t M_pad; int64_t ld; int t_count;
   const int32_t* bin_off; int nb;
-  const double* jt_part; int n_chunks;
+  const double* jtot;
   double* hsum; double* hcomp; double* tsum; double* tcomp;  // HNEMA (may be null)
   double* X;                                                 // GKMA (may be null)
   double* ring; int64_t ring_len; int64_t t0;                // GKMA history
 };
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a);
+
+// Per-step total current: jtot[t][mu] = sum over atom chunks of jt_part[t][chunk][mu].
+hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int t_count, double* jtot);
 
 // GKMA correlation update: for r < R3 = 3(nb+1), tau < L, nu < 3
 //   C[tau][r][nu] += sum_{t < t_count, t0+t-tau >= 0} X[r][t] * ring[(t0+t-tau) % ring_len][nu]
