@@ -10,6 +10,7 @@ from . import _build
 
 HNEMA, GKMA = 1, 2
 PREC_FP32, PREC_BF16X3 = 0, 1
+SCHED_AUTO, SCHED_TILES, SCHED_STREAMK = 0, 1, 2
 
 _STATUS = {0: "MHC_OK", 1: "MHC_ERR_INVALID_ARG", 2: "MHC_ERR_STATE", 3: "MHC_ERR_OOM",
            4: "MHC_ERR_HIP", 5: "MHC_ERR_UNSUPPORTED", 6: "MHC_ERR_NONFINITE"}
@@ -26,7 +27,7 @@ class MhcError(RuntimeError):
 class RunConfig(C.Structure):
     _fields_ = [("methods", C.c_int32), ("precision", C.c_int32), ("t_block", C.c_int32),
                 ("corr_len", C.c_int32), ("dt", C.c_double), ("check_finite", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("schedule", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 _lib = None
@@ -165,10 +166,13 @@ class ModalHC:
         self._check(self._lib.mhc_set_bins_uniform(self._h, int(n_bins), float(f_lo), float(f_hi)), "set_bins_uniform")
         self.nb = int(n_bins)
 
-    def configure(self, methods=HNEMA, precision=PREC_FP32, t_block=1, corr_len=0, dt=1.0, check_finite=False):
-        cfg = RunConfig(int(methods), int(precision), int(t_block), int(corr_len), float(dt), int(bool(check_finite)))
+    def configure(self, methods=HNEMA, precision=PREC_FP32, t_block=1, corr_len=0, dt=1.0, check_finite=False,
+                  schedule=SCHED_AUTO):
+        cfg = RunConfig(int(methods), int(precision), int(t_block), int(corr_len), float(dt), int(bool(check_finite)),
+                        int(schedule))
         self._check(self._lib.mhc_configure(self._h, C.byref(cfg)), "configure")
-        self.cfg = dict(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=dt)
+        self.cfg = dict(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=dt,
+                        schedule=schedule)
 
     def load_eigvec_rows(self, mode0, rows):
         """rows: E^T rows [n, 3N] float64, numpy (host) or torch (device)."""

@@ -11,6 +11,8 @@
 //     HBM once per step;
 //   * T-batched matrix-core GEMM (FP32 or split-BF16): E tiles are staged
 //     through LDS and reused across the 4 channels and all steps of a tile.
+#include <algorithm>
+
 #include "mhc_common.h"
 
 namespace mhc {
@@ -99,7 +101,7 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 // ------------------------------------------------------------ matrix cores
 // Work-group = 4 waves arranged WM x WT; each wave owns MB row blocks (32 slots
 // each) and one t-block of 32 steps, for all four channels: 4*MB accumulators
-// of 32x32 floats.
+// of 32x32 floats.  A tile is WM*MB row blocks x WT t-blocks.
 //
 // Both operands are laid out per row/column block as [stage][SU] u32x4 with
 // a stage of 32 dofs (SU = 256 units of 16 bytes):
@@ -116,163 +118,34 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 // issue order, so every wait the compiler inserts leaves the newer loads in
 // flight: B (L2-resident activations) has one stage of MFMAs to arrive, A
 // (HBM) two.
+//
+// Scheduling (stream-K): the tiles x stages iteration space is cut into G
+// equal contiguous ranges, one per work-group, so every CU gets the same
+// number of MFMAs whatever the tile count.  A work-group walks its range tile
+// segment by tile segment; a segment that covers a whole tile goes straight
+// to the epilogue, a partial one is written (in accumulator register order)
+// to a workspace slot.  k_gemm_fixup then adds the partials of each split
+// tile in work-group order and runs the same epilogue, so no work-group ever
+// waits on another and the result is deterministic.  With ipw = n_stages and
+// G = n_tiles this is the plain one-tile-per-work-group schedule.
 constexpr int SU = 256;
 
-template <int PREC, int WM, int WT, int MB>
-__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
-k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, int ntb,
-       float* __restrict__ out, int layout_g, int64_t M_pad, int n_mtiles, int n_ntiles) {
-  static_assert(WM * WT == 4, "4 waves");
-  constexpr int RBW = WM * MB;                                   // row blocks per work-group
-  constexpr bool BF = (PREC == PREC_BF16X3);
-  constexpr int UPC = BF ? 128 : 64;                             // units per chunk
-  constexpr int CPS = SU / UPC;                                  // chunks per stage
-  constexpr int NBF = BF ? 8 : 4;                                // B units per chunk per lane
-  constexpr int NBS = NBF * CPS;                                 // B units per stage per lane
-  constexpr int A_PER_THR = RBW * SU / 256;
-  __shared__ u32x4 lds[2][RBW][SU];
+struct GemmGeom {
+  int64_t K_pad, M_pad;
+  int ntb, n_ntiles, n_stages;
+  int64_t total_iters, ipw;   // iteration space and iterations per work-group
+  int layout_g;
+};
 
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  const int lane = tid & 63;
-  const int half = lane >> 5;
-  const int wm = wave / WT;
-  const int wt = wave % WT;
-
-  // XCD-aware tile order: consecutive work-group ids go to different XCDs
-  // (round-robin dispatch), so give each XCD a contiguous range of tiles.
-  const int n_tiles = n_mtiles * n_ntiles;
-  const int id = blockIdx.x;
-  const int lin = (n_tiles % 8 == 0) ? (id % 8) * (n_tiles / 8) + id / 8 : id;
-  const int mtile = lin / n_ntiles;
-  const int ntile = lin % n_ntiles;
-  const int64_t rb0 = (int64_t)mtile * RBW;
-  const int tb = ntile * WT + wt;
-  const int64_t per_blk = 8 * K_pad;                              // units per row/column block
-  const int n_stages = (int)(per_blk / SU);                      // even (K_pad % 64 == 0)
-
-  const u32x4* Ebase = E + rb0 * per_blk;
-  auto load_A = [&](int s, u32x4* dst) {
-#pragma unroll
-    for (int q = 0; q < A_PER_THR; ++q) {
-      const int idx = tid + 256 * q;
-      dst[q] = __builtin_nontemporal_load(Ebase + (idx / SU) * per_blk + (int64_t)s * SU + idx % SU);
-    }
-  };
-  auto store_A = [&](int buf, const u32x4* src) {
-#pragma unroll
-    for (int q = 0; q < A_PER_THR; ++q) {
-      const int idx = tid + 256 * q;
-      lds[buf][idx / SU][idx % SU] = src[q];
-    }
-  };
-  const u32x4* Bw[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) Bw[c] = B + ((int64_t)c * ntb + tb) * per_blk + lane;
-  auto load_B = [&](int s, int kk, u32x4* dst) {     // chunk kk of stage s
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t u = (int64_t)s * SU + kk * UPC;
-      if constexpr (BF) {
-        dst[2 * c + 0] = Bw[c][u];
-        dst[2 * c + 1] = Bw[c][u + 64];
-      } else {
-        dst[c] = Bw[c][u];
-      }
-    }
-  };
-
-  f32x16 acc[MB][4];
-#pragma unroll
-  for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
-
-  // MFMAs of stage s (A from LDS buffer `buf`, B from `bs`); after chunk kk
-  // is consumed its registers are refilled with chunk kk of stage `s_next`.
-  auto compute = [&](int buf, u32x4* bs, int s_next) {
-#pragma unroll
-    for (int kk = 0; kk < CPS; ++kk) {
-      u32x4* bc = bs + kk * NBF;
-      if constexpr (BF) {
-        bf16x8 ah[MB], al[MB];
-#pragma unroll
-        for (int rb = 0; rb < MB; ++rb) {
-          ah[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 0) * 64 + lane]);
-          al[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 1) * 64 + lane]);
-        }
-        // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
-#pragma unroll
-        for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
-#pragma unroll
-        for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c + 1]), acc[rb][c], 0, 0, 0);
-#pragma unroll
-        for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                al[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
-      } else {
-        f32x4 a[MB];
-#pragma unroll
-        for (int rb = 0; rb < MB; ++rb)
-          a[rb] = __builtin_bit_cast(f32x4, lds[buf][wm * MB + rb][kk * 64 + lane]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                  a[rb][e], __builtin_bit_cast(f32x4, bc[c])[e], acc[rb][c], 0, 0, 0);
-      }
-      // keep the issue order: this chunk's MFMAs, then its refill loads
-      __builtin_amdgcn_sched_barrier(0);
-      load_B(s_next, kk, bc);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  };
-
-  // prologue: A(0) -> LDS buffer 0, A(1) in staging set 1, B(0) in registers
-  u32x4 ast0[A_PER_THR], ast1[A_PER_THR];
-  u32x4 bq[NBS];
-  load_A(0, ast0);
-#pragma unroll
-  for (int kk = 0; kk < CPS; ++kk) load_B(0, kk, bq + kk * NBF);
-  load_A(1, ast1);
-  store_A(0, ast0);
-  __syncthreads();
-
-  const int last = n_stages - 1;
-  for (int s = 0; s < n_stages; s += 2) {
-    // even stage s: B(s) in bq, A(s+1) in ast1, A(s) in LDS buffer 0
-    load_A(min(s + 2, last), ast0);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(0, bq, min(s + 1, last));
-    store_A(1, ast1);
-    __syncthreads();
-    // odd stage s+1: B(s+1) in bq, A(s+2) in ast0, A(s+1) in LDS buffer 1
-    load_A(min(s + 3, last), ast1);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(1, bq, min(s + 2, last));
-    store_A(0, ast0);
-    __syncthreads();
-  }
-
-  // ---------------------------------------------------------- epilogue
-  if (!layout_g) {
+// Epilogue of one finished tile (accumulators complete).
+template <int WM, int WT, int MB>
+__device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __restrict__ out, const GemmGeom& g,
+                                              int64_t rb0, int ntile, float* red) {
+  constexpr int RBW = WM * MB;
+  const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, wave = tid >> 6;
+  const int wm = wave / WT, wt = wave % WT;
+  if (!g.layout_g) {
     // HNEMA: sum J_n^mu over the tile's steps -> out[ntile][slot][mu]
-    float* red = reinterpret_cast<float*>(&lds[0][0][0]);    // [WT][RBW*32][3]
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
 #pragma unroll
@@ -298,12 +171,13 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, 
       float sacc = 0.f;
 #pragma unroll
       for (int w = 0; w < WT; ++w) sacc += red[w * RBW * 32 * 3 + idx];
-      out[((int64_t)ntile * M_pad + rb0 * 32) * 3 + idx] = sacc;
+      out[((int64_t)ntile * g.M_pad + rb0 * 32) * 3 + idx] = sacc;
     }
+    __syncthreads();
   } else {
     // GKMA: per-step J_n^mu(t) -> out[mu][slot][t]
-    const int64_t ld = (int64_t)ntb * 32;
-    const int64_t t = (int64_t)tb * 32 + (lane & 31);
+    const int64_t ld = (int64_t)g.ntb * 32;
+    const int64_t t = (int64_t)(ntile * WT + wt) * 32 + (lane & 31);
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
 #pragma unroll
@@ -311,41 +185,292 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, int64_t K_pad, 
         const int64_t slot = (rb0 + wm * MB + rb) * 32 + acc_row(j, half);
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu)
-          out[((int64_t)mu * M_pad + slot) * ld + t] = acc[rb][0][j] * acc[rb][1 + mu][j];
+          out[((int64_t)mu * g.M_pad + slot) * ld + t] = acc[rb][0][j] * acc[rb][1 + mu][j];
       }
     }
   }
 }
 
-template <int PREC>
-static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
-                                   int ntb, float* out, int layout_g, int* n_parts) {
-  const u32x4* Ev = reinterpret_cast<const u32x4*>(E);
-  const u32x4* Bv = reinterpret_cast<const u32x4*>(B);
-  if (ntb % 4 == 0) {
-    // 128 slots x 4 t-blocks per work-group
-    const int n_m = (int)(M_pad / 128), n_n = ntb / 4;
-    *n_parts = n_n;
-    hipLaunchKernelGGL((k_gemm<PREC, 1, 4, 4>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
-                       layout_g, M_pad, n_m, n_n);
-  } else if (ntb % 2 == 0) {
-    const int n_m = (int)(M_pad / 256), n_n = ntb / 2;
-    *n_parts = n_n;
-    hipLaunchKernelGGL((k_gemm<PREC, 2, 2, 4>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
-                       layout_g, M_pad, n_m, n_n);
-  } else {
-    const int n_m = (int)(M_pad / 256), n_n = ntb;
-    *n_parts = n_n;
-    hipLaunchKernelGGL((k_gemm<PREC, 4, 1, 2>), dim3(n_m * n_n), dim3(256), 0, s, Ev, Bv, K_pad, ntb, out,
-                       layout_g, M_pad, n_m, n_n);
+// Work-group id -> position in the iteration space.  Consecutive ids go to
+// different XCDs (round-robin dispatch); give each XCD a contiguous range.
+__device__ __forceinline__ int64_t wg_linear(int id, int G) {
+  return (G % 8 == 0) ? (int64_t)(id % 8) * (G / 8) + id / 8 : id;
+}
+
+template <int PREC, int WM, int WT, int MB>
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restrict__ out,
+       float* __restrict__ ws, GemmGeom g) {
+  static_assert(WM * WT == 4, "4 waves");
+  constexpr int RBW = WM * MB;                                   // row blocks per work-group
+  constexpr bool BF = (PREC == PREC_BF16X3);
+  constexpr int UPC = BF ? 128 : 64;                             // units per chunk
+  constexpr int CPS = SU / UPC;                                  // chunks per stage
+  constexpr int NBF = BF ? 8 : 4;                                // B units per chunk per lane
+  constexpr int NBS = NBF * CPS;                                 // B units per stage per lane
+  constexpr int A_PER_THR = RBW * SU / 256;
+  constexpr int NREG = MB * 4 * 16;                              // accumulator floats per lane
+  __shared__ u32x4 lds[2][RBW][SU];
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave-uniform
+  const int lane = tid & 63;
+  const int wm = wave / WT;
+  const int wt = wave % WT;
+  const int64_t per_blk = 8 * g.K_pad;                           // units per row/column block
+  const int n_stages = g.n_stages;                               // even (K_pad % 64 == 0)
+
+  const int64_t gl = wg_linear(blockIdx.x, gridDim.x);
+  const int64_t it_begin = gl * g.ipw;
+  const int64_t it_end = min(g.total_iters, it_begin + g.ipw);
+
+  f32x16 acc[MB][4];
+  u32x4 ast0[A_PER_THR], ast1[A_PER_THR];
+  u32x4 bq[NBS];
+
+  for (int64_t it = it_begin; it < it_end;) {
+    const int64_t tile = it / n_stages;
+    const int s0 = (int)(it - tile * n_stages);
+    const int s1 = (int)min((int64_t)n_stages, s0 + (it_end - it));
+    const int mtile = (int)(tile / g.n_ntiles);
+    const int ntile = (int)(tile % g.n_ntiles);
+    const int64_t rb0 = (int64_t)mtile * RBW;
+    const int tb = ntile * WT + wt;
+
+    const u32x4* Ebase = E + rb0 * per_blk;
+    auto load_A = [&](int s, u32x4* dst) {
+#pragma unroll
+      for (int q = 0; q < A_PER_THR; ++q) {
+        const int idx = tid + 256 * q;
+        dst[q] = __builtin_nontemporal_load(Ebase + (idx / SU) * per_blk + (int64_t)s * SU + idx % SU);
+      }
+    };
+    auto store_A = [&](int buf, const u32x4* src) {
+#pragma unroll
+      for (int q = 0; q < A_PER_THR; ++q) {
+        const int idx = tid + 256 * q;
+        lds[buf][idx / SU][idx % SU] = src[q];
+      }
+    };
+    const u32x4* Bw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Bw[c] = B + ((int64_t)c * g.ntb + tb) * per_blk + lane;
+    auto load_B = [&](int s, int kk, u32x4* dst) {     // chunk kk of stage s
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t u = (int64_t)s * SU + kk * UPC;
+        if constexpr (BF) {
+          dst[2 * c + 0] = Bw[c][u];
+          dst[2 * c + 1] = Bw[c][u + 64];
+        } else {
+          dst[c] = Bw[c][u];
+        }
+      }
+    };
+    // MFMAs of one stage (A from LDS buffer `buf`, B from `bs`); after chunk
+    // kk is consumed its registers are refilled with chunk kk of `s_next`.
+    auto compute = [&](int buf, u32x4* bs, int s_next) {
+#pragma unroll
+      for (int kk = 0; kk < CPS; ++kk) {
+        u32x4* bc = bs + kk * NBF;
+        if constexpr (BF) {
+          bf16x8 ah[MB], al[MB];
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb) {
+            ah[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 0) * 64 + lane]);
+            al[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 1) * 64 + lane]);
+          }
+          // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c + 1]), acc[rb][c], 0, 0, 0);
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  al[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
+        } else {
+          f32x4 a[MB];
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb)
+            a[rb] = __builtin_bit_cast(f32x4, lds[buf][wm * MB + rb][kk * 64 + lane]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+                acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                    a[rb][e], __builtin_bit_cast(f32x4, bc[c])[e], acc[rb][c], 0, 0, 0);
+        }
+        // keep the issue order: this chunk's MFMAs, then its refill loads
+        __builtin_amdgcn_sched_barrier(0);
+        load_B(s_next, kk, bc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
+
+    // prologue: A(s0) -> LDS buffer 0, A(s0+1) in staging set 1, B(s0) in registers
+    const int last = s1 - 1;
+    load_A(s0, ast0);
+#pragma unroll
+    for (int kk = 0; kk < CPS; ++kk) load_B(s0, kk, bq + kk * NBF);
+    load_A(min(s0 + 1, last), ast1);
+    store_A(0, ast0);
+    __syncthreads();
+
+    int s = s0;
+    for (; s + 1 < s1; s += 2) {
+      // even stage s: B(s) in bq, A(s+1) in ast1, A(s) in LDS buffer 0
+      load_A(min(s + 2, last), ast0);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0, bq, min(s + 1, last));
+      store_A(1, ast1);
+      __syncthreads();
+      // odd stage s+1: B(s+1) in bq, A(s+2) in ast0, A(s+1) in LDS buffer 1
+      load_A(min(s + 3, last), ast1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1, bq, min(s + 2, last));
+      store_A(0, ast0);
+      __syncthreads();
+    }
+    if (s < s1) {
+      // odd stage count: the last stage sits in LDS buffer 0, its B in bq
+      compute(0, bq, last);
+      __syncthreads();
+    }
+
+    if (s0 == 0 && s1 == n_stages) {
+      gemm_epilogue<WM, WT, MB>(acc, out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+    } else {
+      // partial tile: slot 0 = this work-group's first segment, 1 = its last
+      float* w = ws + ((gl * 2 + (it == it_begin ? 0 : 1)) * NREG) * 256 + tid;
+#pragma unroll
+      for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) w[((rb * 4 + c) * 16 + j) * 256] = acc[rb][c][j];
+    }
+    it += s1 - s0;
+    __syncthreads();
   }
+}
+
+// Sum the workspace partials of every split tile in work-group order and run
+// the epilogue.  Tiles finished inside k_gemm are skipped.
+template <int WM, int WT, int MB>
+__global__ void __launch_bounds__(256) k_gemm_fixup(float* __restrict__ out, const float* __restrict__ ws,
+                                                   GemmGeom g) {
+  constexpr int RBW = WM * MB;
+  constexpr int NREG = MB * 4 * 16;
+  __shared__ float red[4 * RBW * 32 * 3];
+  const int64_t tile = blockIdx.x;
+  const int64_t first_it = tile * g.n_stages, last_it = first_it + g.n_stages - 1;
+  const int64_t g0 = first_it / g.ipw, g1 = last_it / g.ipw;
+  if (g0 == g1) return;
+  const int tid = threadIdx.x;
+  f32x16 acc[MB][4];
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
+  for (int64_t gl = g0; gl <= g1; ++gl) {
+    const int slot = (gl * g.ipw >= first_it) ? 0 : 1;
+    const float* w = ws + ((gl * 2 + slot) * NREG) * 256 + tid;
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[rb][c][j] += w[((rb * 4 + c) * 16 + j) * 256];
+  }
+  const int mtile = (int)(tile / g.n_ntiles), ntile = (int)(tile % g.n_ntiles);
+  gemm_epilogue<WM, WT, MB>(acc, out, g, (int64_t)mtile * RBW, ntile, red);
+}
+
+template <int PREC, int WM, int WT, int MB>
+static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B, float* out, float* ws,
+                                    int64_t ws_floats, GemmGeom g, int n_mtiles, int n_cu, int sched) {
+  constexpr int NREG = MB * 4 * 16;
+  const int64_t n_tiles = (int64_t)n_mtiles * g.n_ntiles;
+  g.total_iters = n_tiles * g.n_stages;
+  int64_t G = n_tiles;
+  g.ipw = g.n_stages;
+  // Stream-K only on request: work-groups that start at different k-stages no
+  // longer share the activation k-slices in L2 (the tiled schedule marches
+  // all work-groups of an XCD through k together), and on the 27648-mode
+  // slab that extra MALL traffic costs more than the idle CUs it recovers.
+  bool sk = (sched == 2);
+  if (sk) {
+    G = std::min<int64_t>(n_cu, std::max<int64_t>(1, g.total_iters / 4));
+    g.ipw = (g.total_iters + G - 1) / G;
+    G = (g.total_iters + g.ipw - 1) / g.ipw;
+    if (G * 2 * NREG * 256 > ws_floats || G == n_tiles) {
+      sk = false;
+      G = n_tiles;
+      g.ipw = g.n_stages;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm<PREC, WM, WT, MB>), dim3((unsigned)G), dim3(256), 0, s,
+                     reinterpret_cast<const u32x4*>(E), reinterpret_cast<const u32x4*>(B), out, ws, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !sk) return e;
+  hipLaunchKernelGGL((k_gemm_fixup<WM, WT, MB>), dim3((unsigned)n_tiles), dim3(256), 0, s, out, ws, g);
   return hipGetLastError();
 }
 
+template <int PREC>
+static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t K_pad, int ntb,
+                                   float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats, int n_cu,
+                                   int sched) {
+  GemmGeom g{};
+  g.K_pad = K_pad;
+  g.M_pad = M_pad;
+  g.ntb = ntb;
+  g.n_stages = (int)(K_pad / 32);
+  g.layout_g = layout_g;
+  if (ntb % 4 == 0) {
+    // 128 slots x 4 t-blocks per tile
+    g.n_ntiles = ntb / 4;
+    *n_parts = g.n_ntiles;
+    return launch_gemm_shape<PREC, 1, 4, 4>(s, E, B, out, ws, ws_floats, g, (int)(M_pad / 128), n_cu, sched);
+  } else if (ntb % 2 == 0) {
+    g.n_ntiles = ntb / 2;
+    *n_parts = g.n_ntiles;
+    return launch_gemm_shape<PREC, 2, 2, 4>(s, E, B, out, ws, ws_floats, g, (int)(M_pad / 256), n_cu, sched);
+  }
+  g.n_ntiles = ntb;
+  *n_parts = g.n_ntiles;
+  return launch_gemm_shape<PREC, 4, 1, 2>(s, E, B, out, ws, ws_floats, g, (int)(M_pad / 256), n_cu, sched);
+}
+
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
-                       int ntb, float* out, int layout_g, int* n_parts) {
-  if (prec == PREC_BF16X3) return launch_gemm_prec<PREC_BF16X3>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts);
-  return launch_gemm_prec<PREC_FP32>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts);
+                       int ntb, float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats, int n_cu,
+                       int sched) {
+  if (prec == PREC_BF16X3)
+    return launch_gemm_prec<PREC_BF16X3>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, n_cu,
+                                         sched);
+  return launch_gemm_prec<PREC_FP32>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, n_cu, sched);
 }
 
 }  // namespace mhc

@@ -83,6 +83,9 @@ struct mhc_ctx {
   int64_t R3 = 0;
   double *d_csum = nullptr, *d_ccomp = nullptr;
   double* d_out = nullptr;
+  float* d_ws = nullptr;      // stream-K workspace
+  int64_t ws_floats = 0;
+  int n_cu = 256;
   int64_t n_samples = 0;
   int last_block = 0;
 
@@ -323,7 +326,9 @@ mhc_status mhc_configure(mhc_ctx* ctx, const mhc_run_config* cfg) {
   if ((cfg->methods & MHC_GKMA) && !(std::isfinite(cfg->dt) && cfg->dt > 0.0))
     return fail(ctx, MHC_ERR_INVALID_ARG, "dt must be finite and > 0");
   if (cfg->check_finite != 0 && cfg->check_finite != 1) return fail(ctx, MHC_ERR_INVALID_ARG, "check_finite is 0 or 1");
-  if (cfg->reserved[0] || cfg->reserved[1] || cfg->reserved[2])
+  if (cfg->schedule < MHC_SCHED_AUTO || cfg->schedule > MHC_SCHED_STREAMK)
+    return fail(ctx, MHC_ERR_INVALID_ARG, "unknown schedule");
+  if (cfg->reserved[0] || cfg->reserved[1])
     return fail(ctx, MHC_ERR_INVALID_ARG, "reserved fields must be zero");
   ctx->cfg = *cfg;
   ctx->configured = true;
@@ -460,6 +465,16 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     HIP_TRY(hipMemsetAsync(pring, 0, (size_t)ring_len * 3 * 8, ctx->stream), "zero ring");
   }
   if ((st = dev_alloc(ctx, out_doubles * 8, &pout, "read-out"))) return st;
+  if (c.t_block > 1) {
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
+    ctx->n_cu = std::max(1, prop.multiProcessorCount);
+    // per CU: two partial tiles of 256 threads x 256 accumulator floats
+    ctx->ws_floats = (int64_t)ctx->n_cu * 2 * 256 * 256;
+    void* pws = nullptr;
+    if ((st = dev_alloc(ctx, (size_t)ctx->ws_floats * 4, &pws, "stream-K workspace"))) return st;
+    ctx->d_ws = reinterpret_cast<float*>(pws);
+  }
   // masses
   std::vector<float> sm(N), ism(N);
   for (int64_t i = 0; i < N; ++i) {
@@ -545,7 +560,7 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
     n_parts = t_count;
   } else {
     HIP_TRY(launch_gemm(ctx->stream, prec, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
-                        gk ? 1 : 0, &n_parts),
+                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->n_cu, c.schedule),
             "batched contraction");
   }
   if (ctx->timing) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");

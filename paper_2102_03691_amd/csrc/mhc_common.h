@@ -56,9 +56,12 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 //   ntb     t-blocks of 32 steps in the block (t_pad = 32*ntb)
 //   hnema:  out[ntile][M_pad][3]   sum over the tile's steps
 //   gkma :  out[3][M_pad][t_pad]
+//   ws      stream-K workspace (ws_floats floats); n_cu = compute units
+//   sched   0 = automatic, 1 = one tile per work-group, 2 = stream-K
 // Returns the number of column tiles through *n_parts.
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad,
-                       int64_t K_pad, int ntb, float* out, int layout_g, int* n_parts);
+                       int64_t K_pad, int ntb, float* out, int layout_g, int* n_parts, float* ws,
+                       int64_t ws_floats, int n_cu, int sched);
 
 // Bin reduction + float64 accumulation.
 //   HNEMA-only: part sums in[n_parts][M_pad][3] -> hsum/hcomp[nb][3] (Neumaier)

@@ -52,7 +52,7 @@ class Case:
 
 
 def run_library(case: Case, nb, methods, precision, t_block, corr_len=0, dt=1.0, splits=None, bins=None,
-                row_chunk=97, keep=False):
+                row_chunk=97, keep=False, schedule=0):
     from paper_2102_03691_amd import ModalHC, HNEMA, GKMA
     h = ModalHC(0)
     h.load_system(case.m, case.freq)
@@ -60,7 +60,8 @@ def run_library(case: Case, nb, methods, precision, t_block, corr_len=0, dt=1.0,
         h.set_bins_uniform(nb, 0.0, case.lat.f_max)
     else:
         h.set_bins(nb, bins)
-    h.configure(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=dt)
+    h.configure(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=dt,
+                schedule=schedule)
     for r0 in range(0, case.n_modes, row_chunk):
         n = min(row_chunk, case.n_modes - r0)
         h.load_eigvec_rows(r0, case.lat.eig_rows(r0, n))

@@ -45,27 +45,30 @@ def test_sc4_per_step_fp32_hnema():
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16X3])
-@pytest.mark.parametrize("T", [32, 64, 96, 128, 256])
-def test_batched_hnema(small, prec, T):
-    announce(f"batched hnema prec={prec} T={T}")
+@pytest.mark.parametrize("T,sched", [(32, 1), (64, 1), (96, 1), (128, 1), (256, 1), (32, 2), (64, 2), (96, 2),
+                                     (128, 2), (256, 2)])
+def test_batched_hnema(small, prec, T, sched):
+    """sched 1 = one tile per work-group, 2 = stream-K (split tiles + fixup)."""
+    announce(f"batched hnema prec={prec} T={T} sched={sched}")
     ref = small.oracle(23)
-    got = run_library(small, 23, HNEMA, prec, T)
+    got = run_library(small, 23, HNEMA, prec, T, schedule=sched)
     e = rel(got["hnema"], ref["hnema"])
-    log(f"6x6x5_hnema_p{prec}_T{T}", rel_hnema=e, rel_total=rel(got["hnema_total"], ref["hnema_total"]))
+    log(f"6x6x5_hnema_p{prec}_T{T}_s{sched}", rel_hnema=e, rel_total=rel(got["hnema_total"], ref["hnema_total"]))
     assert e <= TOL[prec]
     assert rel(got["hnema_total"], ref["hnema_total"]) <= 1e-12
 
 
-@pytest.mark.parametrize("prec,T", [(FP32, 1), (FP32, 64), (FP32, 128), (BF16X3, 96), (BF16X3, 128)])
-def test_gkma(small, prec, T):
-    announce(f"gkma prec={prec} T={T}")
+@pytest.mark.parametrize("prec,T,sched", [(FP32, 1, 0), (FP32, 64, 1), (FP32, 128, 2), (BF16X3, 96, 2),
+                                          (BF16X3, 128, 1), (BF16X3, 256, 2)])
+def test_gkma(small, prec, T, sched):
+    announce(f"gkma prec={prec} T={T} sched={sched}")
     L, dt = 40, 0.5
     ref = small.oracle(23, corr_len=L, dt=dt)
-    got = run_library(small, 23, GKMA | HNEMA, prec, T, corr_len=L, dt=dt, splits=[77, 1, 150, 72])
+    got = run_library(small, 23, GKMA | HNEMA, prec, T, corr_len=L, dt=dt, splits=[77, 1, 150, 72], schedule=sched)
     ec, ei, eh = rel(got["corr"], ref["corr"]), rel(got["integral"], ref["integral"]), rel(got["hcacf"], ref["hcacf"])
     e0 = rel(got["corr"][0], ref["corr"][0])
     eh2 = rel(got["hnema"], ref["hnema"])
-    log(f"6x6x5_gkma_p{prec}_T{T}", rel_corr=ec, rel_corr_tau0=e0, rel_integral=ei, rel_hcacf=eh, rel_hnema=eh2)
+    log(f"6x6x5_gkma_p{prec}_T{T}_s{sched}", rel_corr=ec, rel_corr_tau0=e0, rel_integral=ei, rel_hcacf=eh, rel_hnema=eh2)
     assert ec <= TOL[prec] and ei <= TOL[prec] and eh2 <= TOL[prec]
     assert eh <= 1e-12
     assert got["n_samples"] == 300
@@ -100,13 +103,14 @@ def test_mode_subset_and_explicit_bins():
     assert e <= TOL[FP32]
 
 
-def test_block_split_invariance_and_determinism(small):
-    announce("split invariance + determinism bf16x3 T=64")
-    a = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16)
-    b = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16)
+@pytest.mark.parametrize("sched", [1, 2])
+def test_block_split_invariance_and_determinism(small, sched):
+    announce(f"split invariance + determinism bf16x3 T=64 sched={sched}")
+    a = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16, schedule=sched)
+    b = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16, schedule=sched)
     for k in ("hnema", "corr", "integral", "hcacf"):
         assert np.array_equal(a[k], b[k]), k
-    c = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16, splits=[1, 7, 64, 228])
+    c = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16, splits=[1, 7, 64, 228], schedule=sched)
     for k in ("hnema", "corr", "hcacf"):
         assert rel(c[k], a[k]) <= 1e-5, k
 
