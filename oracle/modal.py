@@ -173,7 +173,9 @@ def gkma_correlation(Jb: np.ndarray, Jt: np.ndarray, corr_len: int) -> np.ndarra
     for tau in range(min(corr_len, S)):
         late = Jb[tau:]                  # J_b(s),        s = tau .. S-1
         early = Jt[: S - tau]            # J(s - tau)
-        out[tau] = np.einsum("smb,sn->bmn", late, early) / (S - tau)
+        # sum over the origins s of late[s, mu, b] * early[s, nu] -> [mu, b, nu]
+        prod = np.tensordot(late, early, axes=([0], [0]))
+        out[tau] = prod.transpose(1, 0, 2) / (S - tau)
     return out
 
 
