@@ -67,10 +67,18 @@ typedef enum {
  *   FP32    float32 eigenvectors and operands, float32 accumulation
  *   BF16X3  split bfloat16: E = E_hi + E_lo and x = x_hi + x_lo, the product
  *           is hi*hi + hi*lo + lo*hi on bf16 matrix cores with float32
- *           accumulation (the lo*lo term is dropped)                          */
+ *           accumulation (the lo*lo term is dropped)
+ *   FP8     OCP e4m3 eigenvectors with a float32 scale per mode and e4m3
+ *           activations with a float32 scale per (channel, step), one e4m3
+ *           product, float32 accumulation (about 1e-2 relative error)
+ *   FP8X3   the same scales, each operand split into e4m3 hi + lo, products
+ *           hi*hi + hi*lo + lo*hi (about 1e-3 relative error)
+ * FP8 and FP8X3 need t_block > 1.                                          */
 typedef enum {
   MHC_PREC_FP32 = 0,
-  MHC_PREC_BF16X3 = 1
+  MHC_PREC_BF16X3 = 1,
+  MHC_PREC_FP8 = 2,
+  MHC_PREC_FP8X3 = 3
 } mhc_precision;
 
 enum { MHC_HNEMA = 1, MHC_GKMA = 2 };   /* methods bitmask */

@@ -9,7 +9,7 @@ import numpy as np
 from . import _build
 
 HNEMA, GKMA = 1, 2
-PREC_FP32, PREC_BF16X3 = 0, 1
+PREC_FP32, PREC_BF16X3, PREC_FP8, PREC_FP8X3 = 0, 1, 2, 3
 SCHED_AUTO, SCHED_TILES, SCHED_STREAMK = 0, 1, 2
 
 _STATUS = {0: "MHC_OK", 1: "MHC_ERR_INVALID_ARG", 2: "MHC_ERR_STATE", 3: "MHC_ERR_OOM",

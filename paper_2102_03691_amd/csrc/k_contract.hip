@@ -21,6 +21,17 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// Two 16-byte units -> the 32-byte e4m3 operand of one lane.
+__device__ __forceinline__ i32x8 cat8(u32x4 a, u32x4 b) {
+  return __builtin_bit_cast(i32x8, __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+// D += A*B for e4m3 x e4m3 (scale exponents 127 = 2^0: no block scaling).
+__device__ __forceinline__ f32x16 mfma_fp8(i32x8 a, i32x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+}
 
 // Row of the 32x32 accumulator held in register j of lane l (column = l % 32).
 __device__ __forceinline__ int acc_row(int j, int half) { return 8 * (j >> 2) + 4 * half + (j & 3); }
@@ -103,10 +114,15 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 // each) and one t-block of 32 steps, for all four channels: 4*MB accumulators
 // of 32x32 floats.  A tile is WM*MB row blocks x WT t-blocks.
 //
-// Both operands are laid out per row/column block as [stage][SU] u32x4 with
-// a stage of 32 dofs (SU = 256 units of 16 bytes):
-//   BF16: unit (chunk*2 + hi/lo)*64 + lane   (chunk = 16 dofs, 2 per stage)
-//   FP32: unit chunk*64 + lane               (chunk = 8 dofs, 4 per stage)
+// Both operands are laid out per row/column block as [stage][SU] u32x4
+// (SU = 256 units of 16 bytes = 4 KiB per row block per stage):
+//   FP32:  stage of 32 dofs,  unit chunk*64 + lane             (chunk = 8 dofs)
+//   BF16:  stage of 32 dofs,  unit (chunk*2 + hi/lo)*64 + lane  (chunk = 16 dofs)
+//   FP8X3: stage of 64 dofs,  unit (hi/lo*2 + q)*64 + lane      (one 64-dof chunk)
+//   FP8:   stage of 128 dofs, unit (chunk*2 + q)*64 + lane      (chunk = 64 dofs)
+// (q selects the lower or upper 16 bytes of a lane's 32-byte e4m3 operand).
+// e4m3 operands carry a per-slot scale (E) and a per-(channel, step) scale
+// (activations) that the epilogue applies.
 //
 // Pipeline (branch-free, unrolled by two stages so the two A staging sets are
 // static).  At the top of stage s a wave issues its share of the A fragments
@@ -135,15 +151,42 @@ struct GemmGeom {
   int ntb, n_ntiles, n_stages;
   int64_t total_iters, ipw;   // iteration space and iterations per work-group
   int layout_g;
+  const float* row_scale;     // e4m3 only: per-slot scale of E
+  const float* col_scale;     // e4m3 only: [4][ntb*32] activation scales
 };
 
+constexpr bool is_fp8(int prec) { return prec == PREC_FP8 || prec == PREC_FP8X3; }
+
 // Epilogue of one finished tile (accumulators complete).
-template <int WM, int WT, int MB>
+template <int PREC, int WM, int WT, int MB>
 __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __restrict__ out, const GemmGeom& g,
                                               int64_t rb0, int ntile, float* red) {
   constexpr int RBW = WM * MB;
   const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, wave = tid >> 6;
   const int wm = wave / WT, wt = wave % WT;
+  if constexpr (is_fp8(PREC)) {
+    // undo the activation scales of this lane's step (column); the E scale
+    // of each row is applied after the products
+    const int ld = g.ntb * 32;
+    const int t = (ntile * WT + wt) * 32 + (lane & 31);
+    float cs[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cs[c] = g.col_scale[c * ld + t];
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[rb][c][j] *= cs[c];
+  }
+  auto row_factor = [&](int64_t slot) -> float {
+    if constexpr (is_fp8(PREC)) {
+      const float rs = g.row_scale[slot];
+      return rs * rs;                     // J = (s_n Xdot') (s_n A')
+    } else {
+      return 1.f;
+    }
+  };
   if (!g.layout_g) {
     // HNEMA: sum J_n^mu over the tile's steps -> out[ntile][slot][mu]
 #pragma unroll
@@ -161,8 +204,9 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
         }
         if ((lane & 31) == 0) {
           const int row = (wm * MB + rb) * 32 + acc_row(j, half);
+          const float f = row_factor(rb0 * 32 + row);
           float* rp = red + ((int64_t)wt * RBW * 32 + row) * 3;
-          rp[0] = p0; rp[1] = p1; rp[2] = p2;
+          rp[0] = p0 * f; rp[1] = p1 * f; rp[2] = p2 * f;
         }
       }
     }
@@ -183,9 +227,10 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int64_t slot = (rb0 + wm * MB + rb) * 32 + acc_row(j, half);
+        const float f = row_factor(slot);
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu)
-          out[((int64_t)mu * g.M_pad + slot) * ld + t] = acc[rb][0][j] * acc[rb][1 + mu][j];
+          out[((int64_t)mu * g.M_pad + slot) * ld + t] = acc[rb][0][j] * acc[rb][1 + mu][j] * f;
       }
     }
   }
@@ -204,9 +249,11 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
   static_assert(WM * WT == 4, "4 waves");
   constexpr int RBW = WM * MB;                                   // row blocks per work-group
   constexpr bool BF = (PREC == PREC_BF16X3);
-  constexpr int UPC = BF ? 128 : 64;                             // units per chunk
+  constexpr bool F8 = (PREC == PREC_FP8), F8X3 = (PREC == PREC_FP8X3);
+  // units per chunk: FP32 64, BF16 128 (hi, lo), FP8 128 (two q halves), FP8X3 256
+  constexpr int UPC = (PREC == PREC_FP32) ? 64 : (F8X3 ? 256 : 128);
   constexpr int CPS = SU / UPC;                                  // chunks per stage
-  constexpr int NBF = BF ? 8 : 4;                                // B units per chunk per lane
+  constexpr int NBF = 4 * UPC / 64;                              // B units per chunk per lane
   constexpr int NBS = NBF * CPS;                                 // B units per stage per lane
   constexpr int A_PER_THR = RBW * SU / 256;
   constexpr int NREG = MB * 4 * 16;                              // accumulator floats per lane
@@ -217,8 +264,10 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
   const int lane = tid & 63;
   const int wm = wave / WT;
   const int wt = wave % WT;
-  const int64_t per_blk = 8 * g.K_pad;                           // units per row/column block
-  const int n_stages = g.n_stages;                               // even (K_pad % 64 == 0)
+  // 16-byte units per row/column block: 4 B per element for FP32 and BF16 hi+lo,
+  // 2 B for FP8X3, 1 B for FP8
+  const int64_t per_blk = (F8 ? 2 : (F8X3 ? 4 : 8)) * g.K_pad;
+  const int n_stages = g.n_stages;
 
   const int64_t gl = wg_linear(blockIdx.x, gridDim.x);
   const int64_t it_begin = gl * g.ipw;
@@ -226,7 +275,7 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
 
   f32x16 acc[MB][4];
   u32x4 ast0[A_PER_THR], ast1[A_PER_THR];
-  u32x4 bq[NBS];
+  i32x8 bq[NBS / 2];
 
   for (int64_t it = it_begin; it < it_end;) {
     const int64_t tile = it / n_stages;
@@ -255,24 +304,26 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
     const u32x4* Bw[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) Bw[c] = B + ((int64_t)c * g.ntb + tb) * per_blk + lane;
-    auto load_B = [&](int s, int kk, u32x4* dst) {     // chunk kk of stage s
+    // Chunk kk of stage s into NBF/2 eight-dword registers, units paired in
+    // (channel, unit) order: FP32 (c0,c1)(c2,c3); BF16 (hi,lo) per channel;
+    // FP8 (q0,q1) per channel; FP8X3 (hi q0,q1)(lo q0,q1) per channel.
+    auto load_B = [&](int s, int kk, i32x8* dst) {
+      constexpr int UPCH = UPC / 64;                    // units per channel per chunk
+      const int64_t u = (int64_t)s * SU + kk * UPC;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t u = (int64_t)s * SU + kk * UPC;
-        if constexpr (BF) {
-          dst[2 * c + 0] = Bw[c][u];
-          dst[2 * c + 1] = Bw[c][u + 64];
-        } else {
-          dst[c] = Bw[c][u];
-        }
+      for (int p = 0; p < NBF / 2; ++p) {
+        const int i0 = 2 * p, i1 = 2 * p + 1;
+        dst[p] = cat8(Bw[i0 / UPCH][u + (i0 % UPCH) * 64], Bw[i1 / UPCH][u + (i1 % UPCH) * 64]);
       }
     };
     // MFMAs of one stage (A from LDS buffer `buf`, B from `bs`); after chunk
     // kk is consumed its registers are refilled with chunk kk of `s_next`.
-    auto compute = [&](int buf, u32x4* bs, int s_next) {
+    auto lo4 = [](i32x8 v) { return __builtin_shufflevector(v, v, 0, 1, 2, 3); };
+    auto hi4 = [](i32x8 v) { return __builtin_shufflevector(v, v, 4, 5, 6, 7); };
+    auto compute = [&](int buf, i32x8* bs, int s_next) {
 #pragma unroll
       for (int kk = 0; kk < CPS; ++kk) {
-        u32x4* bc = bs + kk * NBF;
+        i32x8* bc = bs + kk * (NBF / 2);
         if constexpr (BF) {
           bf16x8 ah[MB], al[MB];
 #pragma unroll
@@ -286,19 +337,41 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
+                  ah[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
 #pragma unroll
           for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  ah[rb], __builtin_bit_cast(bf16x8, bc[2 * c + 1]), acc[rb][c], 0, 0, 0);
+                  ah[rb], __builtin_bit_cast(bf16x8, hi4(bc[c])), acc[rb][c], 0, 0, 0);
 #pragma unroll
           for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  al[rb], __builtin_bit_cast(bf16x8, bc[2 * c]), acc[rb][c], 0, 0, 0);
+                  al[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
+        } else if constexpr (F8X3) {
+          // bc: per channel c units [hi q0, hi q1, lo q0, lo q1]
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb) {
+            const u32x4* ar = &lds[buf][wm * MB + rb][lane];
+            const i32x8 ah = cat8(ar[0], ar[64]);
+            const i32x8 al = cat8(ar[128], ar[192]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 0], acc[rb][c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 1], acc[rb][c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(al, bc[2 * c + 0], acc[rb][c]);
+          }
+        } else if constexpr (F8) {
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb) {
+            const u32x4* ar = &lds[buf][wm * MB + rb][kk * 128 + lane];
+            const i32x8 a = cat8(ar[0], ar[64]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(a, bc[c], acc[rb][c]);
+          }
         } else {
           f32x4 a[MB];
 #pragma unroll
@@ -311,7 +384,8 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
 #pragma unroll
               for (int c = 0; c < 4; ++c)
                 acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                    a[rb][e], __builtin_bit_cast(f32x4, bc[c])[e], acc[rb][c], 0, 0, 0);
+                    a[rb][e], __builtin_bit_cast(f32x4, (c & 1) ? hi4(bc[c >> 1]) : lo4(bc[c >> 1]))[e],
+                    acc[rb][c], 0, 0, 0);
         }
         // keep the issue order: this chunk's MFMAs, then its refill loads
         __builtin_amdgcn_sched_barrier(0);
@@ -331,7 +405,7 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
     const int last = s1 - 1;
     load_A(s0, ast0);
 #pragma unroll
-    for (int kk = 0; kk < CPS; ++kk) load_B(s0, kk, bq + kk * NBF);
+    for (int kk = 0; kk < CPS; ++kk) load_B(s0, kk, bq + kk * (NBF / 2));
     load_A(min(s0 + 1, last), ast1);
     store_A(0, ast0);
     __syncthreads();
@@ -358,7 +432,7 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
     }
 
     if (s0 == 0 && s1 == n_stages) {
-      gemm_epilogue<WM, WT, MB>(acc, out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+      gemm_epilogue<PREC, WM, WT, MB>(acc, out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
     } else {
       // partial tile: slot 0 = this work-group's first segment, 1 = its last
       float* w = ws + ((gl * 2 + (it == it_begin ? 0 : 1)) * NREG) * 256 + tid;
@@ -376,7 +450,7 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
 
 // Sum the workspace partials of every split tile in work-group order and run
 // the epilogue.  Tiles finished inside k_gemm are skipped.
-template <int WM, int WT, int MB>
+template <int PREC, int WM, int WT, int MB>
 __global__ void __launch_bounds__(256) k_gemm_fixup(float* __restrict__ out, const float* __restrict__ ws,
                                                    GemmGeom g) {
   constexpr int RBW = WM * MB;
@@ -405,7 +479,7 @@ __global__ void __launch_bounds__(256) k_gemm_fixup(float* __restrict__ out, con
         for (int j = 0; j < 16; ++j) acc[rb][c][j] += w[((rb * 4 + c) * 16 + j) * 256];
   }
   const int mtile = (int)(tile / g.n_ntiles), ntile = (int)(tile % g.n_ntiles);
-  gemm_epilogue<WM, WT, MB>(acc, out, g, (int64_t)mtile * RBW, ntile, red);
+  gemm_epilogue<PREC, WM, WT, MB>(acc, out, g, (int64_t)mtile * RBW, ntile, red);
 }
 
 template <int PREC, int WM, int WT, int MB>
@@ -435,20 +509,23 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
                      reinterpret_cast<const u32x4*>(E), reinterpret_cast<const u32x4*>(B), out, ws, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !sk) return e;
-  hipLaunchKernelGGL((k_gemm_fixup<WM, WT, MB>), dim3((unsigned)n_tiles), dim3(256), 0, s, out, ws, g);
+  hipLaunchKernelGGL((k_gemm_fixup<PREC, WM, WT, MB>), dim3((unsigned)n_tiles), dim3(256), 0, s, out, ws, g);
   return hipGetLastError();
 }
 
 template <int PREC>
 static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t K_pad, int ntb,
                                    float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats, int n_cu,
-                                   int sched) {
+                                   int sched, const float* row_scale, const float* col_scale) {
   GemmGeom g{};
   g.K_pad = K_pad;
   g.M_pad = M_pad;
   g.ntb = ntb;
-  g.n_stages = (int)(K_pad / 32);
+  // dofs per stage: 32 (FP32, BF16), 64 (FP8X3), 128 (FP8)
+  g.n_stages = (int)(K_pad / (PREC == PREC_FP8 ? 128 : (PREC == PREC_FP8X3 ? 64 : 32)));
   g.layout_g = layout_g;
+  g.row_scale = row_scale;
+  g.col_scale = col_scale;
   if (ntb % 4 == 0) {
     // 128 slots x 4 t-blocks per tile
     g.n_ntiles = ntb / 4;
@@ -466,11 +543,16 @@ static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, 
 
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
                        int ntb, float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats, int n_cu,
-                       int sched) {
-  if (prec == PREC_BF16X3)
-    return launch_gemm_prec<PREC_BF16X3>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, n_cu,
-                                         sched);
-  return launch_gemm_prec<PREC_FP32>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, n_cu, sched);
+                       int sched, const float* row_scale, const float* col_scale) {
+#define MHC_GEMM(P) \
+  launch_gemm_prec<P>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, n_cu, sched, row_scale, col_scale)
+  switch (prec) {
+    case PREC_BF16X3: return MHC_GEMM(PREC_BF16X3);
+    case PREC_FP8: return MHC_GEMM(PREC_FP8);
+    case PREC_FP8X3: return MHC_GEMM(PREC_FP8X3);
+    default: return MHC_GEMM(PREC_FP32);
+  }
+#undef MHC_GEMM
 }
 
 }  // namespace mhc

@@ -75,6 +75,108 @@ hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64
   return hipGetLastError();
 }
 
+// e4m3 storage: one work-group per row.  s_n = max_j |E[j][n]| / 448 (the
+// per-mode scale), then 16-dof pieces of E/s_n are rounded to e4m3 (and, for
+// the hi/lo form, the residual to a second e4m3).  Piece layout per row block
+// (32 rows), lane l = row%32 + 32*h, dofs k = 64*kc + 32*h + 16*q + [0, 16):
+//   FP8X3  unit kc*256 + (part*2 + q)*64 + lane     (part 0 = hi, 1 = lo)
+//   FP8    unit kc*128 + q*64 + lane
+template <bool X3>
+__global__ void __launch_bounds__(256) k_basis_store_fp8(const double* __restrict__ rows, int64_t K,
+                                                         const int32_t* __restrict__ slot_of_row, void* __restrict__ E,
+                                                         int64_t K_pad, float* __restrict__ row_scale) {
+  __shared__ double sh[256];
+  const int64_t r = blockIdx.x;
+  const int32_t slot = slot_of_row[r];
+  if (slot < 0) return;
+  const double* row = rows + r * K;
+  double mx = 0.0;
+  for (int64_t k = threadIdx.x; k < K; k += 256) mx = fmax(mx, fabs(row[k]));
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double scale = sh[0] > 0.0 ? sh[0] / (double)FP8_MAX : 1.0;
+  if (threadIdx.x == 0) row_scale[slot] = (float)scale;
+  const double inv = 1.0 / scale;
+  const int64_t rb = slot >> 5;
+  const int rr = slot & 31;
+  const int64_t per_blk = (X3 ? 4 : 2) * K_pad;                 // 16-byte units per row block
+  uint4* dst = reinterpret_cast<uint4*>(E) + rb * per_blk;
+  for (int64_t p = threadIdx.x; p < K_pad / 16; p += 256) {
+    const int64_t k0 = p * 16;
+    float x[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = (k0 + e < K) ? (float)(row[k0 + e] * inv) : 0.f;
+    uint32_t hi[4], lo[4];
+    quant16_fp8(x, hi, lo, X3);
+    const int64_t kc = k0 >> 6;
+    const int h = (int)((k0 >> 5) & 1), q = (int)((k0 >> 4) & 1);
+    const int lane = rr + 32 * h;
+    if (X3) {
+      dst[kc * 256 + (0 * 2 + q) * 64 + lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+      dst[kc * 256 + (1 * 2 + q) * 64 + lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    } else {
+      dst[kc * 128 + q * 64 + lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    }
+  }
+}
+
+hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, int64_t n_rows, int64_t K,
+                                  const int32_t* slot_of_row, void* E, int64_t K_pad, float* row_scale) {
+  if (n_rows <= 0) return hipSuccess;
+  if (x3)
+    hipLaunchKernelGGL(k_basis_store_fp8<true>, dim3((unsigned)n_rows), dim3(256), 0, s, rows, K, slot_of_row, E, K_pad,
+                       row_scale);
+  else
+    hipLaunchKernelGGL(k_basis_store_fp8<false>, dim3((unsigned)n_rows), dim3(256), 0, s, rows, K, slot_of_row, E,
+                       K_pad, row_scale);
+  return hipGetLastError();
+}
+
+// Per-column scales of the e4m3 activations: for step t and channel c,
+// s_{c,t} = max_j |B_c[t][j]| / 448 (1 if the column is zero).  One
+// work-group per step, fixed-order max reduction.
+__global__ void __launch_bounds__(256) k_col_scale(const float* __restrict__ v, const float* __restrict__ W,
+                                                   const float* __restrict__ sqrt_m,
+                                                   const float* __restrict__ inv_sqrt_m, int64_t N, int t_count,
+                                                   int t_pad, float* __restrict__ col_scale) {
+  __shared__ float sh[4][256];
+  const int t = blockIdx.x;
+  float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+  if (t < t_count) {
+    for (int64_t i = threadIdx.x; i < N; i += 256) {
+      const float* vp = v + ((int64_t)t * N + i) * 3;
+      const float* Wp = W + ((int64_t)t * N + i) * 9;
+      const float sm = sqrt_m[i], ism = inv_sqrt_m[i];
+      m0 = fmaxf(m0, sm * fmaxf(fmaxf(fabsf(vp[0]), fabsf(vp[1])), fabsf(vp[2])));
+      m1 = fmaxf(m1, ism * fmaxf(fmaxf(fabsf(Wp[0]), fabsf(Wp[1])), fabsf(Wp[2])));
+      m2 = fmaxf(m2, ism * fmaxf(fmaxf(fabsf(Wp[3]), fabsf(Wp[4])), fabsf(Wp[5])));
+      m3 = fmaxf(m3, ism * fmaxf(fmaxf(fabsf(Wp[6]), fabsf(Wp[7])), fabsf(Wp[8])));
+    }
+  }
+  sh[0][threadIdx.x] = m0; sh[1][threadIdx.x] = m1; sh[2][threadIdx.x] = m2; sh[3][threadIdx.x] = m3;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = fmaxf(sh[c][threadIdx.x], sh[c][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) {
+    const float mx = sh[threadIdx.x][0];
+    col_scale[threadIdx.x * t_pad + t] = mx > 0.f ? mx / FP8_MAX : 1.f;
+  }
+}
+
+hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const float* sqrt_m,
+                            const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_scale) {
+  hipLaunchKernelGGL(k_col_scale, dim3((unsigned)t_pad), dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
+                     col_scale);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- input prep
 // Work-group = 32 atoms (96 dofs) x 32 steps, 256 threads.
 // Phase A: thread (tl = tid / 8, sub = tid % 8) handles atoms sub, sub+8, ...
@@ -83,12 +185,13 @@ hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64
 constexpr int PREP_T = 32;
 constexpr int PREP_K = 3 * ATOMS_PER_PREP;   // 96 dofs
 
-template <int MODE>   // 0 = plain, 1 = FP32 fragments, 2 = BF16 fragments
+template <int MODE>   // 0 = plain, 1 = FP32, 2 = BF16 hi/lo, 3 = e4m3, 4 = e4m3 hi/lo fragments
 __global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v, const float* __restrict__ W,
                                                     const float* __restrict__ sqrt_m,
                                                     const float* __restrict__ inv_sqrt_m, int64_t N,
                                                     int t_count, int t_pad, void* __restrict__ B,
-                                                    int64_t K_pad, double* __restrict__ jt_part) {
+                                                    int64_t K_pad, double* __restrict__ jt_part,
+                                                    const float* __restrict__ col_scale) {
   __shared__ float ch[4][PREP_T][PREP_K + 4];
   const int tid = threadIdx.x;
   const int chunk = blockIdx.x;
@@ -173,6 +276,35 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v,
       float4 o = make_float4(ch[c][tt][4 * g], ch[c][tt][4 * g + 1], ch[c][tt][4 * g + 2], ch[c][tt][4 * g + 3]);
       Bp[(cb * KC + kc) * 64 + tt + 32 * h] = o;
     }
+  } else if constexpr (MODE == 3 || MODE == 4) {
+    // e4m3 fragments: piece = (c, 16-dof group g, column tt) of B/s_{c,t}
+    constexpr bool X3 = (MODE == 4);
+    const int ntb = t_pad / 32;
+    const int64_t per_blk = (X3 ? 4 : 2) * K_pad;
+    uint4* Bp = reinterpret_cast<uint4*>(B);
+    for (int idx = tid; idx < 4 * (PREP_K / 16) * PREP_T; idx += 256) {
+      const int tt = idx & 31;
+      const int g = (idx >> 5) % (PREP_K / 16);
+      const int c = (idx >> 5) / (PREP_K / 16);
+      const int64_t k0 = k_base + 16 * g;
+      const int64_t cb = (int64_t)c * ntb + tb;
+      const float inv = 1.f / col_scale[c * t_pad + tb * PREP_T + tt];
+      float x[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) x[e] = ch[c][tt][16 * g + e] * inv;
+      uint32_t hi[4], lo[4];
+      quant16_fp8(x, hi, lo, X3);
+      const int64_t kc = k0 >> 6;
+      const int h = (int)((k0 >> 5) & 1), q = (int)((k0 >> 4) & 1);
+      const int lane = tt + 32 * h;
+      uint4* dst = Bp + cb * per_blk;
+      if (X3) {
+        dst[kc * 256 + (0 * 2 + q) * 64 + lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        dst[kc * 256 + (1 * 2 + q) * 64 + lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+      } else {
+        dst[kc * 128 + q * 64 + lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+      }
+    }
   } else {
     // BF16 fragments: piece = (c, 8-dof group g, column tt), hi and lo
     const int ntb = t_pad / 32;
@@ -203,19 +335,19 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v,
 }
 
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
-                             const float* sqrt_m, const float* inv_sqrt_m, int64_t N, int t_count,
-                             int t_pad, void* B, int64_t K_pad, double* jt_part) {
+                             const float* sqrt_m, const float* inv_sqrt_m, int64_t N, int t_count, int t_pad,
+                             void* B, int64_t K_pad, double* jt_part, const float* col_scale) {
   const int n_chunks = (int)((N + ATOMS_PER_PREP - 1) / ATOMS_PER_PREP);
   dim3 grid((unsigned)n_chunks, (unsigned)((t_pad + PREP_T - 1) / PREP_T));
-  if (plain)
-    hipLaunchKernelGGL(k_input_prep<0>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
-                       B, K_pad, jt_part);
-  else if (prec == PREC_FP32)
-    hipLaunchKernelGGL(k_input_prep<1>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
-                       B, K_pad, jt_part);
-  else
-    hipLaunchKernelGGL(k_input_prep<2>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
-                       B, K_pad, jt_part);
+#define MHC_PREP(M)                                                                                          \
+  hipLaunchKernelGGL(k_input_prep<M>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad, B, \
+                     K_pad, jt_part, col_scale)
+  if (plain) MHC_PREP(0);
+  else if (prec == PREC_FP32) MHC_PREP(1);
+  else if (prec == PREC_BF16X3) MHC_PREP(2);
+  else if (prec == PREC_FP8) MHC_PREP(3);
+  else MHC_PREP(4);
+#undef MHC_PREP
   return hipGetLastError();
 }
 

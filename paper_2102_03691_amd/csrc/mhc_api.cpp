@@ -65,6 +65,8 @@ struct mhc_ctx {
   float* d_sqrtm = nullptr;
   float* d_isqrtm = nullptr;
   int32_t* d_bin_off = nullptr;
+  float* d_rowscale = nullptr;  // e4m3: per-slot scale of E
+  float* d_colscale = nullptr;  // e4m3: per-(channel, step) scale of the activations
 
   // per-block work buffers
   int chunk = 0;       // steps per processed block
@@ -315,7 +317,7 @@ mhc_status mhc_configure(mhc_ctx* ctx, const mhc_run_config* cfg) {
   if (!ctx->has_system || ctx->rows_started) return fail(ctx, MHC_ERR_STATE, "configure needs a system and no rows yet");
   if (!cfg) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL config");
   if (cfg->methods < 1 || cfg->methods > 3) return fail(ctx, MHC_ERR_INVALID_ARG, "methods must be HNEMA, GKMA or both");
-  if (cfg->precision != MHC_PREC_FP32 && cfg->precision != MHC_PREC_BF16X3)
+  if (cfg->precision < MHC_PREC_FP32 || cfg->precision > MHC_PREC_FP8X3)
     return fail(ctx, MHC_ERR_INVALID_ARG, "unknown precision");
   if (cfg->t_block != 1 && (cfg->t_block < 32 || cfg->t_block > 512 || cfg->t_block % 32))
     return fail(ctx, MHC_ERR_INVALID_ARG, "t_block must be 1 or a multiple of 32 in [32, 512]");
@@ -353,11 +355,20 @@ static mhc_status start_rows(mhc_ctx* ctx) {
   // input prep writes whole 32-atom (96-dof) groups, so cover them
   const int64_t K_pad = round_up(3 * round_up(ctx->N, ATOMS_PER_PREP), K_ALIGN);
   const int64_t M_pad = round_up(std::max<int64_t>(M_used, 1), M_ALIGN);
-  const size_t e_bytes = (size_t)M_pad * (size_t)K_pad * 4;   // fp32, or bf16 hi + lo
+  // bytes per element: fp32 or bf16 hi + lo 4, e4m3 hi + lo 2, e4m3 1
+  const int prec = ctx->cfg.precision;
+  const size_t bpe = prec == MHC_PREC_FP8 ? 1 : (prec == MHC_PREC_FP8X3 ? 2 : 4);
+  const size_t e_bytes = (size_t)M_pad * (size_t)K_pad * bpe;
   void* dE = nullptr;
   mhc_status st = dev_alloc(ctx, e_bytes, &dE, "eigenvectors");
   if (st) return st;
   HIP_TRY(hipMemsetAsync(dE, 0, e_bytes, ctx->stream), "zero basis");
+  if (prec == MHC_PREC_FP8 || prec == MHC_PREC_FP8X3) {
+    void* prs = nullptr;
+    if ((st = dev_alloc(ctx, (size_t)M_pad * 4, &prs, "row scales"))) return st;
+    HIP_TRY(hipMemsetAsync(prs, 0, (size_t)M_pad * 4, ctx->stream), "zero row scales");
+    ctx->d_rowscale = reinterpret_cast<float*>(prs);
+  }
   // staging for host rows (about 64 MiB) and slot ids
   const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(M, (int64_t(64) << 20) / (8 * ctx->K)));
   void* drows = nullptr;
@@ -391,7 +402,7 @@ mhc_status mhc_load_eigvec_rows(mhc_ctx* ctx, int64_t mode0, int64_t n_rows, con
   if (!ctx->rows_started) {
     if ((st = start_rows(ctx))) return st;
   }
-  const int prec = ctx->cfg.precision == MHC_PREC_BF16X3 ? PREC_BF16X3 : PREC_FP32;
+  const int prec = ctx->cfg.precision;
   const int64_t step = on_device ? std::min<int64_t>(n_rows, 1 << 16) : ctx->rows_cap;
   std::vector<int32_t> slots;
   for (int64_t r0 = 0; r0 < n_rows; r0 += step) {
@@ -405,8 +416,13 @@ mhc_status mhc_load_eigvec_rows(mhc_ctx* ctx, int64_t mode0, int64_t n_rows, con
               "copy rows");
       src = ctx->d_rows;
     }
-    HIP_TRY(launch_basis_store(ctx->stream, prec, src, nr, ctx->K, ctx->d_slot, ctx->dE, ctx->K_pad),
-            "basis store");
+    if (prec == MHC_PREC_FP8 || prec == MHC_PREC_FP8X3)
+      HIP_TRY(launch_basis_store_fp8(ctx->stream, prec == MHC_PREC_FP8X3, src, nr, ctx->K, ctx->d_slot, ctx->dE,
+                                     ctx->K_pad, ctx->d_rowscale),
+              "basis store");
+    else
+      HIP_TRY(launch_basis_store(ctx->stream, prec, src, nr, ctx->K, ctx->d_slot, ctx->dE, ctx->K_pad),
+              "basis store");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "basis store sync");
   }
   for (int64_t r = 0; r < n_rows; ++r) ctx->row_loaded[mode0 + r] = 1;
@@ -446,6 +462,11 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
   if ((st = dev_alloc(ctx, (size_t)N * 4, &psm, "sqrt m"))) return st;
   if ((st = dev_alloc(ctx, (size_t)N * 4, &pism, "1/sqrt m"))) return st;
   if ((st = dev_alloc(ctx, (size_t)(nb + 1) * 4, &poff, "bin offsets"))) return st;
+  if (c.precision == MHC_PREC_FP8 || c.precision == MHC_PREC_FP8X3) {
+    void* pcs = nullptr;
+    if ((st = dev_alloc(ctx, (size_t)4 * t_pad * 4, &pcs, "column scales"))) return st;
+    ctx->d_colscale = reinterpret_cast<float*>(pcs);
+  }
   const size_t acc_doubles = (size_t)(4 * nb * 3 + 4 * 3);
   if ((st = dev_alloc(ctx, acc_doubles * 8, &pacc, "HNEMA sums"))) return st;
   size_t out_doubles = (size_t)nb * 3 + 3;
@@ -532,9 +553,13 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
   const auto& c = ctx->cfg;
   const bool gk = c.methods & MHC_GKMA;
   const bool per_step = c.t_block == 1;
-  const int prec = c.precision == MHC_PREC_BF16X3 ? PREC_BF16X3 : PREC_FP32;
+  const int prec = c.precision;
+  if (ctx->d_colscale)
+    HIP_TRY(launch_col_scale(ctx->stream, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count, ctx->t_pad,
+                             ctx->d_colscale),
+            "column scales");
   HIP_TRY(launch_input_prep(ctx->stream, prec, per_step ? 1 : 0, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count,
-                            ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt),
+                            ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt, ctx->d_colscale),
           "input prep");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
@@ -560,7 +585,8 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
     n_parts = t_count;
   } else {
     HIP_TRY(launch_gemm(ctx->stream, prec, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
-                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->n_cu, c.schedule),
+                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->n_cu, c.schedule, ctx->d_rowscale,
+                        ctx->d_colscale),
             "batched contraction");
   }
   if (ctx->timing) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");

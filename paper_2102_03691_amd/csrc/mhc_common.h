@@ -20,15 +20,17 @@ namespace mhc {
 //
 //   E  FP32   [M_pad/32][K_pad/8][64][4]            float
 //   E  BF16   [M_pad/32][K_pad/16][2 (hi,lo)][64][8] bf16
+//   E  FP8    [M_pad/32][K_pad/64][2 (q)][64][16] e4m3        (+ per-slot scale)
+//   E  FP8X3  [M_pad/32][K_pad/64][2 (hi,lo)][2 (q)][64][16] e4m3
 //   B  plain  [T][4][K_pad]                           float  (per-step path)
 //   B  FP32   [4*NTB][K_pad/8][64][4]                 float  (cb = c*NTB + tb)
 //   B  BF16   [4*NTB][K_pad/16][2][64][8]             bf16
 // Channels c: 0 = u = sqrt(m) v, 1..3 = w^mu = W^{mu .} / sqrt(m).
-constexpr int K_ALIGN = 64;     // K_pad multiple
+constexpr int K_ALIGN = 128;    // K_pad multiple (one e4m3 stage is 128 dofs)
 constexpr int M_ALIGN = 256;    // M_pad multiple
 constexpr int ATOMS_PER_PREP = 32;  // atoms per input-prep work-group (96 dofs)
 
-enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1 };
+enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1, PREC_FP8 = 2, PREC_FP8X3 = 3 };
 
 // ------------------------------------------------------------- launchers
 // Every launcher queues work on `s` and returns the launch status.
@@ -38,12 +40,23 @@ enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1 };
 hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows,
                               int64_t K, const int32_t* slot_of_row, void* E, int64_t K_pad);
 
+// e4m3 basis store: per-mode scale s_n = max|E[.][n]| / 448 into row_scale[slot],
+// then E/s_n as e4m3 (x3: plus the e4m3 residual).
+hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, int64_t n_rows, int64_t K,
+                                  const int32_t* slot_of_row, void* E, int64_t K_pad, float* row_scale);
+
+// Per-(channel, step) scales of the e4m3 activations: col_scale[c][t_pad].
+hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const float* sqrt_m,
+                            const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_scale);
+
 // Input preparation for one block of t_pad columns (t_count real steps):
 // B operand in the layout of `prec` (or plain when plain != 0) and the
 // per-atom-chunk partial total currents jt_part[t][chunk][3] (float64).
+// e4m3 precisions divide by col_scale (from launch_col_scale).
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
                              const float* sqrt_m, const float* inv_sqrt_m, int64_t N,
-                             int t_count, int t_pad, void* B, int64_t K_pad, double* jt_part);
+                             int t_count, int t_pad, void* B, int64_t K_pad, double* jt_part,
+                             const float* col_scale);
 
 // Per-step matrix-vector path (FP32): for steps t = 0..n_steps-1 of a plain
 // B buffer, J_n^mu = Xdot_n A_n^mu for every slot.  Output either
@@ -61,7 +74,7 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 // Returns the number of column tiles through *n_parts.
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad,
                        int64_t K_pad, int ntb, float* out, int layout_g, int* n_parts, float* ws,
-                       int64_t ws_floats, int n_cu, int sched);
+                       int64_t ws_floats, int n_cu, int sched, const float* row_scale, const float* col_scale);
 
 // Bin reduction + float64 accumulation.
 //   HNEMA-only: part sums in[n_parts][M_pad][3] -> hsum/hcomp[nb][3] (Neumaier)
