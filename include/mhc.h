@@ -249,6 +249,48 @@ mhc_status mhc_kernel_timing(mhc_ctx *ctx, int64_t *launches, double *total_ms);
 /* Bytes of device memory held by the context (basis, buffers, accumulators). */
 mhc_status mhc_device_bytes(mhc_ctx *ctx, int64_t *bytes);
 
+/* ------------------------------------------------------- grouped systems
+ * Many independent systems (uneven sizes, HNEMA and GKMA mixed) advanced
+ * together: per block of t_block steps the input preparation of every
+ * system, ONE persistent contraction launch over the tiles of all systems
+ * (work-groups pull tiles largest-first from a queue), and the binning /
+ * accumulation of every system.  Results equal pushing each system alone
+ * (same arithmetic, same summation order).  The group borrows the contexts:
+ * they must stay alive, and must not be pushed on their own while a group
+ * push is running. */
+typedef struct mhc_group mhc_group;
+
+enum {
+  MHC_GROUP_GRAPH = 1,      /* capture the per-block sequence as a HIP graph on the first full
+                               block and replay it for every later block                 */
+  MHC_GROUP_AUTOTUNE = 2    /* time every valid contraction tile shape on the first block and
+                               keep the fastest (cached per process for the same sizes)  */
+};
+
+/* systems: n finalized contexts with the same device, stream, precision and
+ * t_block > 1.  flags: MHC_GROUP_* bits.
+ * Errors: INVALID_ARG, STATE (a context not finalized or per-step), OOM, HIP. */
+mhc_status mhc_group_create(mhc_ctx *const *systems, int32_t n, int32_t flags, mhc_group **out);
+mhc_status mhc_group_destroy(mhc_group *group);
+const char *mhc_group_last_error(const mhc_group *group);
+
+/* Push n_steps samples to every system: v[i], W[i] are system i's arrays in
+ * the layout of mhc_push (host or device pointers, as on_device says).
+ * Full blocks go through the grouped path; a trailing partial block is
+ * pushed system by system.  Errors: INVALID_ARG, HIP. */
+mhc_status mhc_group_push(mhc_group *group, int32_t n_steps, const float *const *v, const float *const *W,
+                          int on_device);
+
+/* Tile shape in use (0: 128 slots x 4 t-blocks, 1: 256 x 2, 2: 256 x 1), the
+ * autotuner's measured milliseconds per grouped contraction for each shape
+ * ([3], -1 where not timed), and the number of tiles per launch. */
+mhc_status mhc_group_info(mhc_group *group, int32_t *tile_shape, double *tuned_ms, int64_t *n_tiles);
+
+/* HIP-event timing of the grouped contraction (graph replay is switched off
+ * while timing is on); counters as for mhc_kernel_timing. */
+mhc_status mhc_group_set_timing(mhc_group *group, int enable);
+mhc_status mhc_group_kernel_timing(mhc_group *group, int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@ from . import _build
 HNEMA, GKMA = 1, 2
 PREC_FP32, PREC_BF16X3, PREC_FP8, PREC_FP8X3 = 0, 1, 2, 3
 SCHED_AUTO, SCHED_TILES, SCHED_STREAMK = 0, 1, 2
+GROUP_GRAPH, GROUP_AUTOTUNE = 1, 2
 
 _STATUS = {0: "MHC_OK", 1: "MHC_ERR_INVALID_ARG", 2: "MHC_ERR_STATE", 3: "MHC_ERR_OOM",
            4: "MHC_ERR_HIP", 5: "MHC_ERR_UNSUPPORTED", 6: "MHC_ERR_NONFINITE"}
@@ -73,6 +74,13 @@ def library():
         "mhc_set_timing": (i32, [vp, C.c_int]),
         "mhc_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
         "mhc_device_bytes": (i32, [vp, P(i64)]),
+        "mhc_group_create": (i32, [P(vp), i32, i32, P(vp)]),
+        "mhc_group_destroy": (i32, [vp]),
+        "mhc_group_last_error": (C.c_char_p, [vp]),
+        "mhc_group_push": (i32, [vp, i32, P(vp), P(vp), C.c_int]),
+        "mhc_group_info": (i32, [vp, P(i32), P(dbl), P(i64)]),
+        "mhc_group_set_timing": (i32, [vp, C.c_int]),
+        "mhc_group_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -256,3 +264,77 @@ class ModalHC:
         b = C.c_int64()
         self._check(self._lib.mhc_device_bytes(self._h, C.byref(b)), "device_bytes")
         return b.value
+
+
+class ModalGroup:
+    """Several ModalHC systems advanced together (mhc_group_*).
+
+    The systems must share one device, one stream, the precision and t_block.
+    """
+
+    def __init__(self, systems, graph=True, autotune=True):
+        self._lib = library()
+        self.systems = list(systems)
+        arr = (C.c_void_p * len(self.systems))(*[s._h.value for s in self.systems])
+        h = C.c_void_p()
+        flags = (GROUP_GRAPH if graph else 0) | (GROUP_AUTOTUNE if autotune else 0)
+        st = self._lib.mhc_group_create(arr, len(self.systems), flags, C.byref(h))
+        if st:
+            raise MhcError(st, "mhc_group_create")
+        self._h = h
+
+    def _check(self, st, what):
+        if st:
+            raise MhcError(st, f"{what}: {self._lib.mhc_group_last_error(self._h).decode()}")
+
+    def push(self, vs, Ws):
+        """vs[i], Ws[i]: system i's [S, N_i, 3] and [S, N_i, 3, 3] float32 (all torch or all numpy)."""
+        n = len(self.systems)
+        S = vs[0].shape[0]
+        dev = _is_torch(vs[0])
+        keep = []
+        for i, sysm in enumerate(self.systems):
+            v, W = vs[i], Ws[i]
+            assert v.shape[0] == S and W.shape[0] == S
+            if dev:
+                assert v.is_contiguous() and W.is_contiguous()
+                assert v.numel() == S * sysm.n_atoms * 3 and W.numel() == S * sysm.n_atoms * 9
+            else:
+                v = np.ascontiguousarray(v, dtype=np.float32)
+                W = np.ascontiguousarray(W, dtype=np.float32)
+                assert v.size == S * sysm.n_atoms * 3 and W.size == S * sysm.n_atoms * 9
+                keep += [v, W]
+            vs_i, Ws_i = (v, W)
+            if i == 0:
+                pv = (C.c_void_p * n)()
+                pW = (C.c_void_p * n)()
+            pv[i] = _ptr(vs_i)
+            pW[i] = _ptr(Ws_i)
+        self._check(self._lib.mhc_group_push(self._h, S, pv, pW, 1 if dev else 0), "group_push")
+
+    def info(self):
+        shape = C.c_int32()
+        ms = (C.c_double * 3)()
+        nt = C.c_int64()
+        self._check(self._lib.mhc_group_info(self._h, C.byref(shape), ms, C.byref(nt)), "group_info")
+        return {"tile_shape": shape.value, "tuned_ms": list(ms), "n_tiles": nt.value}
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.mhc_group_set_timing(self._h, int(bool(enable))), "group_set_timing")
+
+    def kernel_timing(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(self._lib.mhc_group_kernel_timing(self._h, C.byref(n), C.byref(ms)), "group_kernel_timing")
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mhc_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

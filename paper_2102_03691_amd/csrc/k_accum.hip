@@ -33,6 +33,7 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
   __shared__ double sh[256];
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
+  if (a.t0_dev) a.t0 = *a.t0_dev;
   if (b < a.nb) {
     const int64_t lo = a.bin_off[b], hi = a.bin_off[b + 1];
     const int64_t n = hi - lo;
@@ -147,7 +148,9 @@ constexpr int CL = 64;   // lags per tile
 
 __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
                                               int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
-                                              double* __restrict__ csum, double* __restrict__ ccomp) {
+                                              double* __restrict__ csum, double* __restrict__ ccomp,
+                                              const int64_t* __restrict__ t0_dev) {
+  if (t0_dev) t0 = *t0_dev;
   __shared__ double xs[CT][CR + 2];          // xs[t][r]
   __shared__ double rs[CT + CL][3];          // ring window
   const int tid = threadIdx.x;
@@ -227,10 +230,20 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
 }
 
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
-                       const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp) {
+                       const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
+                       const int64_t* t0_dev) {
   if (t_count <= 0) return hipSuccess;
   dim3 grid((unsigned)((R3 + CR - 1) / CR), (unsigned)((L + CL - 1) / CL));
-  hipLaunchKernelGGL(k_corr, grid, dim3(256), 0, s, X, ldx, t_count, R3, L, ring, ring_len, t0, csum, ccomp);
+  hipLaunchKernelGGL(k_corr, grid, dim3(256), 0, s, X, ldx, t_count, R3, L, ring, ring_len, t0, csum, ccomp, t0_dev);
+  return hipGetLastError();
+}
+
+__global__ void k_advance(int64_t* t0, int64_t by) {
+  if (threadIdx.x == 0) *t0 += by;
+}
+
+hipError_t launch_advance(hipStream_t s, int64_t* t0, int64_t by) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, t0, by);
   return hipGetLastError();
 }
 

@@ -146,15 +146,6 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 // G = n_tiles this is the plain one-tile-per-work-group schedule.
 constexpr int SU = 256;
 
-struct GemmGeom {
-  int64_t K_pad, M_pad;
-  int ntb, n_ntiles, n_stages;
-  int64_t total_iters, ipw;   // iteration space and iterations per work-group
-  int layout_g;
-  const float* row_scale;     // e4m3 only: per-slot scale of E
-  const float* col_scale;     // e4m3 only: [4][ntb*32] activation scales
-};
-
 constexpr bool is_fp8(int prec) { return prec == PREC_FP8 || prec == PREC_FP8X3; }
 
 // Epilogue of one finished tile (accumulators complete).
@@ -242,41 +233,198 @@ __device__ __forceinline__ int64_t wg_linear(int id, int G) {
   return (G % 8 == 0) ? (int64_t)(id % 8) * (G / 8) + id / 8 : id;
 }
 
-template <int PREC, int WM, int WT, int MB>
-__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
-k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restrict__ out,
-       float* __restrict__ ws, GemmGeom g) {
-  static_assert(WM * WT == 4, "4 waves");
-  constexpr int RBW = WM * MB;                                   // row blocks per work-group
-  constexpr bool BF = (PREC == PREC_BF16X3);
-  constexpr bool F8 = (PREC == PREC_FP8), F8X3 = (PREC == PREC_FP8X3);
+template <int PREC>
+struct GemmCfg {
+  static constexpr bool BF = (PREC == PREC_BF16X3);
+  static constexpr bool F8 = (PREC == PREC_FP8), F8X3 = (PREC == PREC_FP8X3);
   // units per chunk: FP32 64, BF16 128 (hi, lo), FP8 128 (two q halves), FP8X3 256
-  constexpr int UPC = (PREC == PREC_FP32) ? 64 : (F8X3 ? 256 : 128);
-  constexpr int CPS = SU / UPC;                                  // chunks per stage
-  constexpr int NBF = 4 * UPC / 64;                              // B units per chunk per lane
-  constexpr int NBS = NBF * CPS;                                 // B units per stage per lane
-  constexpr int A_PER_THR = RBW * SU / 256;
-  constexpr int NREG = MB * 4 * 16;                              // accumulator floats per lane
-  __shared__ u32x4 lds[2][RBW][SU];
+  static constexpr int UPC = (PREC == PREC_FP32) ? 64 : (F8X3 ? 256 : 128);
+  static constexpr int CPS = SU / UPC;                           // chunks per stage
+  static constexpr int NBF = 4 * UPC / 64;                       // B units per chunk per lane
+  static constexpr int NBS = NBF * CPS;                          // B units per stage per lane
+  // 16-byte units per row block per dof: 4 B per element for FP32 and BF16
+  // hi+lo, 2 B for FP8X3, 1 B for FP8 (times 32 rows / 16 bytes)
+  static constexpr int UNITS_PER_DOF2 = F8 ? 2 : (F8X3 ? 4 : 8);
+};
 
+// Accumulate stages [s0, s1) of the tile with row blocks rb0.. and t-block
+// column tb (per wave) into acc.  All 256 threads take part; lds is the
+// double-buffered A stage.  Leaves the work-group synchronized.
+template <int PREC, int WM, int WT, int MB>
+__device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int ntile, int s0, int s1,
+                                             f32x16 (&acc)[MB][4], u32x4 (*lds)[WM * MB][SU]) {
+  using C = GemmCfg<PREC>;
+  constexpr int RBW = WM * MB;
+  constexpr int UPC = C::UPC, CPS = C::CPS, NBF = C::NBF, NBS = C::NBS;
+  constexpr int A_PER_THR = RBW * SU / 256;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave-uniform
   const int lane = tid & 63;
   const int wm = wave / WT;
   const int wt = wave % WT;
-  // 16-byte units per row/column block: 4 B per element for FP32 and BF16 hi+lo,
-  // 2 B for FP8X3, 1 B for FP8
-  const int64_t per_blk = (F8 ? 2 : (F8X3 ? 4 : 8)) * g.K_pad;
-  const int n_stages = g.n_stages;
+  const int tb = ntile * WT + wt;
+  const int64_t per_blk = C::UNITS_PER_DOF2 * g.K_pad;          // 16-byte units per row/column block
 
+  u32x4 ast0[A_PER_THR], ast1[A_PER_THR];
+  i32x8 bq[NBS / 2];
+  const u32x4* Ebase = reinterpret_cast<const u32x4*>(g.E) + rb0 * per_blk;
+  auto load_A = [&](int s, u32x4* dst) {
+#pragma unroll
+    for (int q = 0; q < A_PER_THR; ++q) {
+      const int idx = tid + 256 * q;
+      dst[q] = __builtin_nontemporal_load(Ebase + (idx / SU) * per_blk + (int64_t)s * SU + idx % SU);
+    }
+  };
+  auto store_A = [&](int buf, const u32x4* src) {
+#pragma unroll
+    for (int q = 0; q < A_PER_THR; ++q) {
+      const int idx = tid + 256 * q;
+      lds[buf][idx / SU][idx % SU] = src[q];
+    }
+  };
+  const u32x4* Bw[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Bw[c] = reinterpret_cast<const u32x4*>(g.B) + ((int64_t)c * g.ntb + tb) * per_blk + lane;
+  // Chunk kk of stage s into NBF/2 eight-dword registers, units paired in
+  // (channel, unit) order: FP32 (c0,c1)(c2,c3); BF16 (hi,lo) per channel;
+  // FP8 (q0,q1) per channel; FP8X3 (hi q0,q1)(lo q0,q1) per channel.
+  auto load_B = [&](int s, int kk, i32x8* dst) {
+    constexpr int UPCH = UPC / 64;                      // units per channel per chunk
+    const int64_t u = (int64_t)s * SU + kk * UPC;
+#pragma unroll
+    for (int p = 0; p < NBF / 2; ++p) {
+      const int i0 = 2 * p, i1 = 2 * p + 1;
+      dst[p] = cat8(Bw[i0 / UPCH][u + (i0 % UPCH) * 64], Bw[i1 / UPCH][u + (i1 % UPCH) * 64]);
+    }
+  };
+  auto lo4 = [](i32x8 v) { return __builtin_shufflevector(v, v, 0, 1, 2, 3); };
+  auto hi4 = [](i32x8 v) { return __builtin_shufflevector(v, v, 4, 5, 6, 7); };
+  // MFMAs of one stage (A from LDS buffer `buf`, B from `bs`); after chunk
+  // kk is consumed its registers are refilled with chunk kk of `s_next`.
+  auto compute = [&](int buf, i32x8* bs, int s_next) {
+#pragma unroll
+    for (int kk = 0; kk < CPS; ++kk) {
+      i32x8* bc = bs + kk * (NBF / 2);
+      if constexpr (C::BF) {
+        bf16x8 ah[MB], al[MB];
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb) {
+          ah[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 0) * 64 + lane]);
+          al[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 1) * 64 + lane]);
+        }
+        // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
+        // (lo4 of a channel's register is its hi part, hi4 its lo part)
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                ah[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                ah[rb], __builtin_bit_cast(bf16x8, hi4(bc[c])), acc[rb][c], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                al[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
+      } else if constexpr (C::F8X3) {
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb) {
+          const u32x4* ar = &lds[buf][wm * MB + rb][lane];
+          const i32x8 ah = cat8(ar[0], ar[64]);
+          const i32x8 al = cat8(ar[128], ar[192]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 0], acc[rb][c]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 1], acc[rb][c]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(al, bc[2 * c + 0], acc[rb][c]);
+        }
+      } else if constexpr (C::F8) {
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb) {
+          const u32x4* ar = &lds[buf][wm * MB + rb][kk * 128 + lane];
+          const i32x8 a = cat8(ar[0], ar[64]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(a, bc[c], acc[rb][c]);
+        }
+      } else {
+        f32x4 a[MB];
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+          a[rb] = __builtin_bit_cast(f32x4, lds[buf][wm * MB + rb][kk * 64 + lane]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                  a[rb][e], __builtin_bit_cast(f32x4, (c & 1) ? hi4(bc[c >> 1]) : lo4(bc[c >> 1]))[e],
+                  acc[rb][c], 0, 0, 0);
+      }
+      // keep the issue order: this chunk's MFMAs, then its refill loads
+      __builtin_amdgcn_sched_barrier(0);
+      load_B(s_next, kk, bc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
+
+  // prologue: A(s0) -> LDS buffer 0, A(s0+1) in staging set 1, B(s0) in registers
+  const int last = s1 - 1;
+  load_A(s0, ast0);
+#pragma unroll
+  for (int kk = 0; kk < CPS; ++kk) load_B(s0, kk, bq + kk * (NBF / 2));
+  load_A(min(s0 + 1, last), ast1);
+  store_A(0, ast0);
+  __syncthreads();
+
+  int s = s0;
+  for (; s + 1 < s1; s += 2) {
+    // even stage s: B(s) in bq, A(s+1) in ast1, A(s) in LDS buffer 0
+    load_A(min(s + 2, last), ast0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0, bq, min(s + 1, last));
+    store_A(1, ast1);
+    __syncthreads();
+    // odd stage s+1: B(s+1) in bq, A(s+2) in ast0, A(s+1) in LDS buffer 1
+    load_A(min(s + 3, last), ast1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(1, bq, min(s + 2, last));
+    store_A(0, ast0);
+    __syncthreads();
+  }
+  if (s < s1) {
+    // odd stage count: the last stage sits in LDS buffer 0, its B in bq
+    compute(0, bq, last);
+    __syncthreads();
+  }
+}
+
+template <int PREC, int WM, int WT, int MB>
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+k_gemm(float* __restrict__ ws, GemmGeom g) {
+  constexpr int RBW = WM * MB;
+  constexpr int NREG = MB * 4 * 16;                              // accumulator floats per lane
+  __shared__ u32x4 lds[2][RBW][SU];
+  const int tid = threadIdx.x;
+  const int n_stages = g.n_stages;
   const int64_t gl = wg_linear(blockIdx.x, gridDim.x);
   const int64_t it_begin = gl * g.ipw;
   const int64_t it_end = min(g.total_iters, it_begin + g.ipw);
-
   f32x16 acc[MB][4];
-  u32x4 ast0[A_PER_THR], ast1[A_PER_THR];
-  i32x8 bq[NBS / 2];
-
   for (int64_t it = it_begin; it < it_end;) {
     const int64_t tile = it / n_stages;
     const int s0 = (int)(it - tile * n_stages);
@@ -284,155 +432,9 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
     const int mtile = (int)(tile / g.n_ntiles);
     const int ntile = (int)(tile % g.n_ntiles);
     const int64_t rb0 = (int64_t)mtile * RBW;
-    const int tb = ntile * WT + wt;
-
-    const u32x4* Ebase = E + rb0 * per_blk;
-    auto load_A = [&](int s, u32x4* dst) {
-#pragma unroll
-      for (int q = 0; q < A_PER_THR; ++q) {
-        const int idx = tid + 256 * q;
-        dst[q] = __builtin_nontemporal_load(Ebase + (idx / SU) * per_blk + (int64_t)s * SU + idx % SU);
-      }
-    };
-    auto store_A = [&](int buf, const u32x4* src) {
-#pragma unroll
-      for (int q = 0; q < A_PER_THR; ++q) {
-        const int idx = tid + 256 * q;
-        lds[buf][idx / SU][idx % SU] = src[q];
-      }
-    };
-    const u32x4* Bw[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Bw[c] = B + ((int64_t)c * g.ntb + tb) * per_blk + lane;
-    // Chunk kk of stage s into NBF/2 eight-dword registers, units paired in
-    // (channel, unit) order: FP32 (c0,c1)(c2,c3); BF16 (hi,lo) per channel;
-    // FP8 (q0,q1) per channel; FP8X3 (hi q0,q1)(lo q0,q1) per channel.
-    auto load_B = [&](int s, int kk, i32x8* dst) {
-      constexpr int UPCH = UPC / 64;                    // units per channel per chunk
-      const int64_t u = (int64_t)s * SU + kk * UPC;
-#pragma unroll
-      for (int p = 0; p < NBF / 2; ++p) {
-        const int i0 = 2 * p, i1 = 2 * p + 1;
-        dst[p] = cat8(Bw[i0 / UPCH][u + (i0 % UPCH) * 64], Bw[i1 / UPCH][u + (i1 % UPCH) * 64]);
-      }
-    };
-    // MFMAs of one stage (A from LDS buffer `buf`, B from `bs`); after chunk
-    // kk is consumed its registers are refilled with chunk kk of `s_next`.
-    auto lo4 = [](i32x8 v) { return __builtin_shufflevector(v, v, 0, 1, 2, 3); };
-    auto hi4 = [](i32x8 v) { return __builtin_shufflevector(v, v, 4, 5, 6, 7); };
-    auto compute = [&](int buf, i32x8* bs, int s_next) {
-#pragma unroll
-      for (int kk = 0; kk < CPS; ++kk) {
-        i32x8* bc = bs + kk * (NBF / 2);
-        if constexpr (BF) {
-          bf16x8 ah[MB], al[MB];
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb) {
-            ah[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 0) * 64 + lane]);
-            al[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 1) * 64 + lane]);
-          }
-          // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  ah[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  ah[rb], __builtin_bit_cast(bf16x8, hi4(bc[c])), acc[rb][c], 0, 0, 0);
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  al[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
-        } else if constexpr (F8X3) {
-          // bc: per channel c units [hi q0, hi q1, lo q0, lo q1]
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb) {
-            const u32x4* ar = &lds[buf][wm * MB + rb][lane];
-            const i32x8 ah = cat8(ar[0], ar[64]);
-            const i32x8 al = cat8(ar[128], ar[192]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 0], acc[rb][c]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 1], acc[rb][c]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(al, bc[2 * c + 0], acc[rb][c]);
-          }
-        } else if constexpr (F8) {
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb) {
-            const u32x4* ar = &lds[buf][wm * MB + rb][kk * 128 + lane];
-            const i32x8 a = cat8(ar[0], ar[64]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(a, bc[c], acc[rb][c]);
-          }
-        } else {
-          f32x4 a[MB];
-#pragma unroll
-          for (int rb = 0; rb < MB; ++rb)
-            a[rb] = __builtin_bit_cast(f32x4, lds[buf][wm * MB + rb][kk * 64 + lane]);
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-              for (int c = 0; c < 4; ++c)
-                acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                    a[rb][e], __builtin_bit_cast(f32x4, (c & 1) ? hi4(bc[c >> 1]) : lo4(bc[c >> 1]))[e],
-                    acc[rb][c], 0, 0, 0);
-        }
-        // keep the issue order: this chunk's MFMAs, then its refill loads
-        __builtin_amdgcn_sched_barrier(0);
-        load_B(s_next, kk, bc);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    };
-
-#pragma unroll
-    for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
-
-    // prologue: A(s0) -> LDS buffer 0, A(s0+1) in staging set 1, B(s0) in registers
-    const int last = s1 - 1;
-    load_A(s0, ast0);
-#pragma unroll
-    for (int kk = 0; kk < CPS; ++kk) load_B(s0, kk, bq + kk * (NBF / 2));
-    load_A(min(s0 + 1, last), ast1);
-    store_A(0, ast0);
-    __syncthreads();
-
-    int s = s0;
-    for (; s + 1 < s1; s += 2) {
-      // even stage s: B(s) in bq, A(s+1) in ast1, A(s) in LDS buffer 0
-      load_A(min(s + 2, last), ast0);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(0, bq, min(s + 1, last));
-      store_A(1, ast1);
-      __syncthreads();
-      // odd stage s+1: B(s+1) in bq, A(s+2) in ast0, A(s+1) in LDS buffer 1
-      load_A(min(s + 3, last), ast1);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(1, bq, min(s + 2, last));
-      store_A(0, ast0);
-      __syncthreads();
-    }
-    if (s < s1) {
-      // odd stage count: the last stage sits in LDS buffer 0, its B in bq
-      compute(0, bq, last);
-      __syncthreads();
-    }
-
+    gemm_segment<PREC, WM, WT, MB>(g, rb0, ntile, s0, s1, acc, lds);
     if (s0 == 0 && s1 == n_stages) {
-      gemm_epilogue<PREC, WM, WT, MB>(acc, out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+      gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
     } else {
       // partial tile: slot 0 = this work-group's first segment, 1 = its last
       float* w = ws + ((gl * 2 + (it == it_begin ? 0 : 1)) * NREG) * 256 + tid;
@@ -448,11 +450,41 @@ k_gemm(const u32x4* __restrict__ E, const u32x4* __restrict__ B, float* __restri
   }
 }
 
+// Several systems in one persistent launch: work-groups pull whole tiles
+// (system, m-tile, n-tile) from a queue ordered largest-first; every tile is
+// computed entirely by one work-group, so the results do not depend on which
+// work-group took it.  The queue ends for every wave at the same counter
+// value, so all work-groups exit.
+
+template <int PREC, int WM, int WT, int MB>
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+k_gemm_group(const GemmGeom* __restrict__ sys, const GroupTile* __restrict__ tiles, int n_tiles,
+             int* __restrict__ counter) {
+  constexpr int RBW = WM * MB;
+  __shared__ u32x4 lds[2][RBW][SU];
+  __shared__ int next;
+  f32x16 acc[MB][4];
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = next;
+    __syncthreads();
+    if (idx >= n_tiles) break;
+    const GroupTile gt = tiles[idx];
+    const GemmGeom g = sys[gt.sys];
+    const int mtile = gt.tile / g.n_ntiles;
+    const int ntile = gt.tile % g.n_ntiles;
+    const int64_t rb0 = (int64_t)mtile * RBW;
+    gemm_segment<PREC, WM, WT, MB>(g, rb0, ntile, 0, g.n_stages, acc, lds);
+    gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+    __syncthreads();
+  }
+}
+
 // Sum the workspace partials of every split tile in work-group order and run
 // the epilogue.  Tiles finished inside k_gemm are skipped.
 template <int PREC, int WM, int WT, int MB>
-__global__ void __launch_bounds__(256) k_gemm_fixup(float* __restrict__ out, const float* __restrict__ ws,
-                                                   GemmGeom g) {
+__global__ void __launch_bounds__(256) k_gemm_fixup(const float* __restrict__ ws, GemmGeom g) {
   constexpr int RBW = WM * MB;
   constexpr int NREG = MB * 4 * 16;
   __shared__ float red[4 * RBW * 32 * 3];
@@ -479,7 +511,7 @@ __global__ void __launch_bounds__(256) k_gemm_fixup(float* __restrict__ out, con
         for (int j = 0; j < 16; ++j) acc[rb][c][j] += w[((rb * 4 + c) * 16 + j) * 256];
   }
   const int mtile = (int)(tile / g.n_ntiles), ntile = (int)(tile % g.n_ntiles);
-  gemm_epilogue<PREC, WM, WT, MB>(acc, out, g, (int64_t)mtile * RBW, ntile, red);
+  gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, (int64_t)mtile * RBW, ntile, red);
 }
 
 template <int PREC, int WM, int WT, int MB>
@@ -505,11 +537,13 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
       g.ipw = g.n_stages;
     }
   }
-  hipLaunchKernelGGL((k_gemm<PREC, WM, WT, MB>), dim3((unsigned)G), dim3(256), 0, s,
-                     reinterpret_cast<const u32x4*>(E), reinterpret_cast<const u32x4*>(B), out, ws, g);
+  g.E = E;
+  g.B = B;
+  g.out = out;
+  hipLaunchKernelGGL((k_gemm<PREC, WM, WT, MB>), dim3((unsigned)G), dim3(256), 0, s, ws, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !sk) return e;
-  hipLaunchKernelGGL((k_gemm_fixup<PREC, WM, WT, MB>), dim3((unsigned)n_tiles), dim3(256), 0, s, out, ws, g);
+  hipLaunchKernelGGL((k_gemm_fixup<PREC, WM, WT, MB>), dim3((unsigned)n_tiles), dim3(256), 0, s, ws, g);
   return hipGetLastError();
 }
 
@@ -553,6 +587,66 @@ hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, in
     default: return MHC_GEMM(PREC_FP32);
   }
 #undef MHC_GEMM
+}
+
+// ----------------------------------------------------------- tile shapes
+// shape 0: 128 slots x 4 t-blocks (waves 1 x 4, 4 row blocks each)
+// shape 1: 256 slots x 2 t-blocks (waves 2 x 2, 4 row blocks each)
+// shape 2: 256 slots x 1 t-block  (waves 4 x 1, 2 row blocks each)
+int gemm_shape_rows(int shape) { return shape == 0 ? 128 : 256; }
+int gemm_shape_tbs(int shape) { return shape == 0 ? 4 : (shape == 1 ? 2 : 1); }
+bool gemm_shape_valid(int shape, int ntb) { return shape >= 0 && shape <= 2 && ntb % gemm_shape_tbs(shape) == 0; }
+
+void gemm_geom(int prec, int shape, const void* E, const void* B, float* out, int64_t M_pad, int64_t K_pad, int ntb,
+               int layout_g, const float* row_scale, const float* col_scale, GemmGeom* g, int* n_mtiles) {
+  *g = GemmGeom{};
+  g->E = E;
+  g->B = B;
+  g->out = out;
+  g->K_pad = K_pad;
+  g->M_pad = M_pad;
+  g->ntb = ntb;
+  g->n_ntiles = ntb / gemm_shape_tbs(shape);
+  g->n_stages = (int)(K_pad / (prec == PREC_FP8 ? 128 : (prec == PREC_FP8X3 ? 64 : 32)));
+  g->layout_g = layout_g;
+  g->row_scale = row_scale;
+  g->col_scale = col_scale;
+  *n_mtiles = (int)(M_pad / gemm_shape_rows(shape));
+  g->total_iters = (int64_t)(*n_mtiles) * g->n_ntiles * g->n_stages;
+  g->ipw = g->n_stages;
+}
+
+template <int PREC>
+static hipError_t launch_group_prec(hipStream_t s, int shape, const GemmGeom* d_sys, const GroupTile* d_tiles,
+                                    int n_tiles, int* counter, int n_wg) {
+  dim3 grid((unsigned)n_wg), block(256);
+  if (shape == 0)
+    hipLaunchKernelGGL((k_gemm_group<PREC, 1, 4, 4>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
+  else if (shape == 1)
+    hipLaunchKernelGGL((k_gemm_group<PREC, 2, 2, 4>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
+  else
+    hipLaunchKernelGGL((k_gemm_group<PREC, 4, 1, 2>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_group(hipStream_t s, int prec, int shape, const GemmGeom* d_sys, const GroupTile* d_tiles,
+                             int n_tiles, int* counter, int n_wg) {
+  switch (prec) {
+    case PREC_BF16X3: return launch_group_prec<PREC_BF16X3>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
+    case PREC_FP8: return launch_group_prec<PREC_FP8>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
+    case PREC_FP8X3: return launch_group_prec<PREC_FP8X3>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
+    default: return launch_group_prec<PREC_FP32>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
+  }
+}
+
+__global__ void k_fill_i32(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
 }
 
 }  // namespace mhc

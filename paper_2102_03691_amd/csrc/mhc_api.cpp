@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -86,6 +88,7 @@ struct mhc_ctx {
   double *d_csum = nullptr, *d_ccomp = nullptr;
   double* d_out = nullptr;
   float* d_ws = nullptr;      // stream-K workspace
+  int64_t* d_t0 = nullptr;    // first step of the next block (grouped, graph-replayed pushes)
   int64_t ws_floats = 0;
   int n_cu = 256;
   int64_t n_samples = 0;
@@ -486,6 +489,9 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     HIP_TRY(hipMemsetAsync(pring, 0, (size_t)ring_len * 3 * 8, ctx->stream), "zero ring");
   }
   if ((st = dev_alloc(ctx, out_doubles * 8, &pout, "read-out"))) return st;
+  void* pt0 = nullptr;
+  if ((st = dev_alloc(ctx, 8, &pt0, "step counter"))) return st;
+  ctx->d_t0 = reinterpret_cast<int64_t*>(pt0);
   if (c.t_block > 1) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
@@ -549,47 +555,26 @@ mhc_status mhc_reset(mhc_ctx* ctx) {
   return MHC_OK;
 }
 
-static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_count) {
+// Front of a block: activation scales (e4m3), B operand, per-chunk Eq. 10 partials.
+static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int t_count) {
   const auto& c = ctx->cfg;
-  const bool gk = c.methods & MHC_GKMA;
-  const bool per_step = c.t_block == 1;
-  const int prec = c.precision;
   if (ctx->d_colscale)
     HIP_TRY(launch_col_scale(ctx->stream, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count, ctx->t_pad,
                              ctx->d_colscale),
             "column scales");
-  HIP_TRY(launch_input_prep(ctx->stream, prec, per_step ? 1 : 0, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count,
-                            ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt, ctx->d_colscale),
+  HIP_TRY(launch_input_prep(ctx->stream, c.precision, c.t_block == 1 ? 1 : 0, v, W, ctx->d_sqrtm, ctx->d_isqrtm,
+                            ctx->N, t_count, ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt, ctx->d_colscale),
           "input prep");
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->timing) {
-    if (ctx->ev_used + 2 > ctx->ev.size()) {
-      for (int q = 0; q < 2; ++q) {
-        hipEvent_t e;
-        HIP_TRY(hipEventCreate(&e), "event create");
-        ctx->ev.push_back(e);
-      }
-    }
-    e0 = ctx->ev[ctx->ev_used];
-    e1 = ctx->ev[ctx->ev_used + 1];
-    ctx->ev_used += 2;
-    HIP_TRY(hipEventRecord(e0, ctx->stream), "event record");
-  }
-  int n_parts = 0;
+  return MHC_OK;
+}
+
+// Back of a block: per-step totals, bins + float64 accumulation, GKMA update.
+// With t0_dev the block's first step index is read from device memory (and
+// advanced here), so a captured graph can be replayed block after block.
+static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, int64_t* t0_dev) {
+  const auto& c = ctx->cfg;
+  const bool gk = c.methods & MHC_GKMA;
   const int64_t ld = ctx->t_pad;
-  if (per_step) {
-    HIP_TRY(launch_gemv_f32(ctx->stream, reinterpret_cast<const float*>(ctx->dE),
-                            reinterpret_cast<const float*>(ctx->dB), t_count, ctx->M_pad, ctx->K_pad, ctx->dJ,
-                            gk ? 1 : 0, ld),
-            "per-step contraction");
-    n_parts = t_count;
-  } else {
-    HIP_TRY(launch_gemm(ctx->stream, prec, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
-                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->n_cu, c.schedule, ctx->d_rowscale,
-                        ctx->d_colscale),
-            "batched contraction");
-  }
-  if (ctx->timing) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
   HIP_TRY(launch_total(ctx->stream, ctx->d_jt, ctx->n_atom_chunks, t_count, ctx->d_jtot), "total current");
   ReduceArgs a{};
   a.in = ctx->dJ;
@@ -609,12 +594,56 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
   a.ring = ctx->d_ring;
   a.ring_len = ctx->ring_len;
   a.t0 = ctx->n_samples;
+  a.t0_dev = t0_dev;
   HIP_TRY(launch_reduce(ctx->stream, a), "bin reduce");
   if (gk) {
     HIP_TRY(launch_corr(ctx->stream, ctx->dX, ld, t_count, ctx->R3, c.corr_len, ctx->d_ring, ctx->ring_len,
-                        ctx->n_samples, ctx->d_csum, ctx->d_ccomp),
+                        ctx->n_samples, ctx->d_csum, ctx->d_ccomp, t0_dev),
             "correlation");
   }
+  if (t0_dev) HIP_TRY(launch_advance(ctx->stream, t0_dev, t_count), "advance");
+  return MHC_OK;
+}
+
+static mhc_status timing_begin(mhc_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (!ctx->timing) return MHC_OK;
+  if (ctx->ev_used + 2 > ctx->ev.size()) {
+    for (int q = 0; q < 2; ++q) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e), "event create");
+      ctx->ev.push_back(e);
+    }
+  }
+  *e0 = ctx->ev[ctx->ev_used];
+  *e1 = ctx->ev[ctx->ev_used + 1];
+  ctx->ev_used += 2;
+  HIP_TRY(hipEventRecord(*e0, ctx->stream), "event record");
+  return MHC_OK;
+}
+
+static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_count) {
+  const auto& c = ctx->cfg;
+  const bool gk = c.methods & MHC_GKMA;
+  mhc_status st = block_front(ctx, v, W, t_count);
+  if (st) return st;
+  hipEvent_t e0, e1;
+  if ((st = timing_begin(ctx, &e0, &e1))) return st;
+  int n_parts = 0;
+  if (c.t_block == 1) {
+    HIP_TRY(launch_gemv_f32(ctx->stream, reinterpret_cast<const float*>(ctx->dE),
+                            reinterpret_cast<const float*>(ctx->dB), t_count, ctx->M_pad, ctx->K_pad, ctx->dJ,
+                            gk ? 1 : 0, ctx->t_pad),
+            "per-step contraction");
+    n_parts = t_count;
+  } else {
+    HIP_TRY(launch_gemm(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
+                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->n_cu, c.schedule, ctx->d_rowscale,
+                        ctx->d_colscale),
+            "batched contraction");
+  }
+  if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
+  if ((st = block_back(ctx, t_count, n_parts, nullptr))) return st;
   ctx->n_samples += t_count;
   ctx->last_block = t_count;
   return MHC_OK;
@@ -831,6 +860,352 @@ mhc_status mhc_device_bytes(mhc_ctx* ctx, int64_t* bytes) {
   if (st) return st;
   if (!bytes) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL bytes");
   *bytes = ctx->bytes;
+  return MHC_OK;
+}
+
+}  // extern "C"
+
+// ================================================================= groups
+// Several systems pushed together: per block, the fronts of all systems, one
+// persistent contraction over all their tiles (largest first), and the
+// backs of all systems, optionally captured once as a HIP graph and replayed.
+struct mhc_group {
+  std::vector<mhc_ctx*> sys;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int prec = 0, t_block = 0, ntb = 0, shape = 0;
+  bool use_graph = false, autotune = false, tuned = false;
+  double tuned_ms[3] = {-1.0, -1.0, -1.0};
+  int n_cu = 256;
+  std::vector<DevBuf> allocs;
+  GemmGeom* d_geom = nullptr;
+  GroupTile* d_tiles = nullptr;
+  int* d_counter = nullptr;
+  int n_tiles = 0;
+  std::vector<int> n_parts;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string err;
+  int64_t* h_t0 = nullptr;     // pinned staging for the device step counters
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;   // (precision, T, system sizes) -> tile shape
+
+mhc_status gfail(mhc_group* g, mhc_status st, const std::string& msg) {
+  g->err = msg;
+  return st;
+}
+
+#define GHIP_TRY(call, where)                                                                  \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return gfail(g, MHC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+std::string tune_key(const mhc_group* g) {
+  std::vector<int64_t> n;
+  for (auto* c : g->sys) n.push_back(c->M_pad * 1000003 + c->K_pad);
+  std::sort(n.begin(), n.end());
+  std::string k = std::to_string(g->prec) + "/" + std::to_string(g->t_block);
+  for (auto x : n) k += "/" + std::to_string(x);
+  return k;
+}
+
+// Descriptors and the largest-first tile queue for the current shape.
+mhc_status build_queue(mhc_group* g) {
+  const int n = (int)g->sys.size();
+  std::vector<GemmGeom> geom(n);
+  std::vector<GroupTile> tiles;
+  std::vector<std::pair<int64_t, int>> order;
+  g->n_parts.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    mhc_ctx* c = g->sys[i];
+    int n_m = 0;
+    gemm_geom(g->prec, g->shape, c->dE, c->dB, c->dJ, c->M_pad, c->K_pad, g->ntb,
+              (c->cfg.methods & MHC_GKMA) ? 1 : 0, c->d_rowscale, c->d_colscale, &geom[i], &n_m);
+    g->n_parts[i] = geom[i].n_ntiles;
+    order.push_back({c->K_pad, i});
+  }
+  std::stable_sort(order.begin(), order.end(), [](auto a, auto b) { return a.first > b.first; });
+  for (auto& o : order) {
+    const int i = o.second;
+    const int nt = (int)(g->sys[i]->M_pad / gemm_shape_rows(g->shape)) * geom[i].n_ntiles;
+    for (int t = 0; t < nt; ++t) tiles.push_back({i, t});
+  }
+  g->n_tiles = (int)tiles.size();
+  GHIP_TRY(hipMemcpyAsync(g->d_geom, geom.data(), n * sizeof(GemmGeom), hipMemcpyHostToDevice, g->stream), "geom");
+  GHIP_TRY(hipMemcpyAsync(g->d_tiles, tiles.data(), tiles.size() * sizeof(GroupTile), hipMemcpyHostToDevice,
+                          g->stream),
+           "tiles");
+  GHIP_TRY(hipStreamSynchronize(g->stream), "queue sync");
+  return MHC_OK;
+}
+
+mhc_status group_contract(mhc_group* g) {
+  GHIP_TRY(launch_fill_i32(g->stream, g->d_counter, 1, 0), "queue reset");
+  GHIP_TRY(launch_gemm_group(g->stream, g->prec, g->shape, g->d_geom, g->d_tiles, g->n_tiles, g->d_counter,
+                             std::min(g->n_cu, g->n_tiles)),
+           "grouped contraction");
+  return MHC_OK;
+}
+
+// The whole block (inputs already staged in each context's buffers).
+mhc_status group_block(mhc_group* g, bool timed) {
+  for (auto* c : g->sys) {
+    mhc_status st = block_front(c, c->d_v, c->d_W, g->t_block);
+    if (st) return gfail(g, st, c->err);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    while (g->ev_used + 2 > g->ev.size()) {
+      hipEvent_t e;
+      GHIP_TRY(hipEventCreate(&e), "event create");
+      g->ev.push_back(e);
+    }
+    e0 = g->ev[g->ev_used];
+    e1 = g->ev[g->ev_used + 1];
+    g->ev_used += 2;
+    GHIP_TRY(hipEventRecord(e0, g->stream), "event record");
+  }
+  mhc_status st = group_contract(g);
+  if (st) return st;
+  if (timed) GHIP_TRY(hipEventRecord(e1, g->stream), "event record");
+  for (size_t i = 0; i < g->sys.size(); ++i) {
+    mhc_ctx* c = g->sys[i];
+    if ((st = block_back(c, g->t_block, g->n_parts[i], c->d_t0))) return gfail(g, st, c->err);
+  }
+  return MHC_OK;
+}
+
+// Time every valid tile shape on the staged block and keep the fastest.
+mhc_status autotune(mhc_group* g) {
+  const std::string key = tune_key(g);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      g->shape = it->second;
+      g->tuned = true;
+      return build_queue(g);
+    }
+  }
+  for (auto* c : g->sys) {
+    mhc_status st = block_front(c, c->d_v, c->d_W, g->t_block);
+    if (st) return gfail(g, st, c->err);
+  }
+  hipEvent_t a, b;
+  GHIP_TRY(hipEventCreate(&a), "event");
+  GHIP_TRY(hipEventCreate(&b), "event");
+  int best = -1;
+  double best_ms = 1e300;
+  for (int shape = 0; shape < 3; ++shape) {
+    if (!gemm_shape_valid(shape, g->ntb)) continue;
+    g->shape = shape;
+    mhc_status st = build_queue(g);
+    if (st) return st;
+    if ((st = group_contract(g))) return st;                      // warm-up
+    GHIP_TRY(hipEventRecord(a, g->stream), "event");
+    for (int r = 0; r < 3; ++r)
+      if ((st = group_contract(g))) return st;
+    GHIP_TRY(hipEventRecord(b, g->stream), "event");
+    GHIP_TRY(hipEventSynchronize(b), "event sync");
+    float ms = 0.f;
+    GHIP_TRY(hipEventElapsedTime(&ms, a, b), "elapsed");
+    g->tuned_ms[shape] = ms / 3.0;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = shape;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  g->shape = best;
+  g->tuned = true;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  return build_queue(g);
+}
+
+}  // namespace
+
+extern "C" {
+
+mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, mhc_group** out) {
+  if (!out) return MHC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!systems || n < 1 || n > 4096) return MHC_ERR_INVALID_ARG;
+  if (flags & ~(MHC_GROUP_GRAPH | MHC_GROUP_AUTOTUNE)) return MHC_ERR_INVALID_ARG;
+  mhc_ctx* c0 = systems[0];
+  for (int i = 0; i < n; ++i) {
+    mhc_ctx* c = systems[i];
+    if (!c) return MHC_ERR_INVALID_ARG;
+    if (c->sticky) return c->sticky;
+    if (!c->finalized || c->cfg.t_block == 1) return MHC_ERR_STATE;
+    if (c->device != c0->device || c->stream != c0->stream || c->cfg.precision != c0->cfg.precision ||
+        c->cfg.t_block != c0->cfg.t_block)
+      return MHC_ERR_INVALID_ARG;
+    for (int j = 0; j < i; ++j)
+      if (systems[j] == c) return MHC_ERR_INVALID_ARG;
+  }
+  mhc_group* g = new (std::nothrow) mhc_group();
+  if (!g) return MHC_ERR_OOM;
+  g->sys.assign(systems, systems + n);
+  g->device = c0->device;
+  g->stream = c0->stream;
+  g->prec = c0->cfg.precision;
+  g->t_block = c0->cfg.t_block;
+  g->ntb = g->t_block / 32;
+  g->use_graph = flags & MHC_GROUP_GRAPH;
+  g->autotune = flags & MHC_GROUP_AUTOTUNE;
+  g->n_cu = c0->n_cu;
+  g->shape = (g->ntb % 4 == 0) ? 0 : (g->ntb % 2 == 0 ? 1 : 2);
+  auto cleanup = [&](mhc_status st) {
+    for (auto& a : g->allocs) (void)hipFree(a.p);
+    if (g->h_t0) (void)hipHostFree(g->h_t0);
+    delete g;
+    return st;
+  };
+  if (hipSetDevice(g->device) != hipSuccess) return cleanup(MHC_ERR_HIP);
+  int64_t max_tiles = 0;
+  for (auto* c : g->sys) max_tiles += (c->M_pad / 128) * g->ntb;   // upper bound over shapes
+  void *pg = nullptr, *pt = nullptr, *pc = nullptr;
+  if (hipMalloc(&pg, n * sizeof(GemmGeom)) != hipSuccess) return cleanup(MHC_ERR_OOM);
+  g->allocs.push_back({pg, n * sizeof(GemmGeom)});
+  if (hipMalloc(&pt, max_tiles * sizeof(GroupTile)) != hipSuccess) return cleanup(MHC_ERR_OOM);
+  g->allocs.push_back({pt, (size_t)max_tiles * sizeof(GroupTile)});
+  if (hipMalloc(&pc, 256) != hipSuccess) return cleanup(MHC_ERR_OOM);
+  g->allocs.push_back({pc, 256});
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->h_t0), n * sizeof(int64_t), 0) != hipSuccess)
+    return cleanup(MHC_ERR_OOM);
+  g->d_geom = reinterpret_cast<GemmGeom*>(pg);
+  g->d_tiles = reinterpret_cast<GroupTile*>(pt);
+  g->d_counter = reinterpret_cast<int*>(pc);
+  if (build_queue(g) != MHC_OK) return cleanup(MHC_ERR_HIP);
+  *out = g;
+  return MHC_OK;
+}
+
+mhc_status mhc_group_destroy(mhc_group* g) {
+  if (!g) return MHC_OK;
+  (void)hipSetDevice(g->device);
+  (void)hipStreamSynchronize(g->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (auto e : g->ev) (void)hipEventDestroy(e);
+  for (auto& a : g->allocs) (void)hipFree(a.p);
+  if (g->h_t0) (void)hipHostFree(g->h_t0);
+  delete g;
+  return MHC_OK;
+}
+
+const char* mhc_group_last_error(const mhc_group* g) { return g ? g->err.c_str() : ""; }
+
+mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, const float* const* W,
+                          int on_device) {
+  if (!g) return MHC_ERR_INVALID_ARG;
+  g->err.clear();
+  if (n_steps < 0 || (on_device != 0 && on_device != 1)) return gfail(g, MHC_ERR_INVALID_ARG, "bad arguments");
+  if (n_steps == 0) return MHC_OK;
+  if (!v || !W) return gfail(g, MHC_ERR_INVALID_ARG, "NULL pointer arrays");
+  const int n = (int)g->sys.size();
+  for (int i = 0; i < n; ++i) {
+    if (!v[i] || !W[i]) return gfail(g, MHC_ERR_INVALID_ARG, "NULL input pointer");
+    if (g->sys[i]->sticky) return gfail(g, g->sys[i]->sticky, "system " + std::to_string(i) + " has a HIP error");
+  }
+  GHIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const int T = g->t_block;
+  // device step counters <- host counts (once per call)
+  for (int i = 0; i < n; ++i) g->h_t0[i] = g->sys[i]->n_samples;
+  for (int i = 0; i < n; ++i)
+    GHIP_TRY(hipMemcpyAsync(g->sys[i]->d_t0, &g->h_t0[i], 8, hipMemcpyHostToDevice, g->stream), "step counter");
+  GHIP_TRY(hipStreamSynchronize(g->stream), "step counter sync");
+  int32_t s0 = 0;
+  for (; s0 + T <= n_steps; s0 += T) {
+    for (int i = 0; i < n; ++i) {
+      mhc_ctx* c = g->sys[i];
+      GHIP_TRY(hipMemcpyAsync(c->d_v, v[i] + (int64_t)s0 * c->N * 3, (size_t)T * c->N * 3 * 4, kind, g->stream), "v");
+      GHIP_TRY(hipMemcpyAsync(c->d_W, W[i] + (int64_t)s0 * c->N * 9, (size_t)T * c->N * 9 * 4, kind, g->stream), "W");
+    }
+    if (g->autotune && !g->tuned) {
+      mhc_status st = autotune(g);
+      if (st) return st;
+    }
+    mhc_status st;
+    if (g->use_graph && !g->timing) {
+      if (!g->exec) {
+        GHIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed), "begin capture");
+        st = group_block(g, false);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(g->stream, &graph);
+        if (st) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return st;
+        }
+        GHIP_TRY(e, "end capture");
+        g->graph = graph;
+        GHIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "instantiate");
+      }
+      GHIP_TRY(hipGraphLaunch(g->exec, g->stream), "graph launch");
+    } else {
+      if ((st = group_block(g, g->timing))) return st;
+    }
+    for (auto* c : g->sys) {
+      c->n_samples += T;
+      c->last_block = T;
+    }
+  }
+  // trailing partial block: each system on its own
+  if (s0 < n_steps) {
+    const int tc = n_steps - s0;
+    for (int i = 0; i < n; ++i) {
+      mhc_ctx* c = g->sys[i];
+      GHIP_TRY(hipMemcpyAsync(c->d_v, v[i] + (int64_t)s0 * c->N * 3, (size_t)tc * c->N * 3 * 4, kind, g->stream), "v");
+      GHIP_TRY(hipMemcpyAsync(c->d_W, W[i] + (int64_t)s0 * c->N * 9, (size_t)tc * c->N * 9 * 4, kind, g->stream), "W");
+      mhc_status st = run_block(c, c->d_v, c->d_W, tc);
+      if (st) return gfail(g, st, c->err);
+    }
+  }
+  if (!on_device) GHIP_TRY(hipStreamSynchronize(g->stream), "push sync");
+  return MHC_OK;
+}
+
+mhc_status mhc_group_info(mhc_group* g, int32_t* tile_shape, double* tuned_ms, int64_t* n_tiles) {
+  if (!g) return MHC_ERR_INVALID_ARG;
+  if (tile_shape) *tile_shape = g->shape;
+  if (tuned_ms)
+    for (int i = 0; i < 3; ++i) tuned_ms[i] = g->tuned_ms[i];
+  if (n_tiles) *n_tiles = g->n_tiles;
+  return MHC_OK;
+}
+
+mhc_status mhc_group_set_timing(mhc_group* g, int enable) {
+  if (!g || (enable != 0 && enable != 1)) return MHC_ERR_INVALID_ARG;
+  g->timing = enable == 1;
+  return MHC_OK;
+}
+
+mhc_status mhc_group_kernel_timing(mhc_group* g, int64_t* launches, double* total_ms) {
+  if (!g) return MHC_ERR_INVALID_ARG;
+  GHIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  GHIP_TRY(hipStreamSynchronize(g->stream), "timing sync");
+  double tot = 0.0;
+  for (size_t q = 0; q + 1 < g->ev_used; q += 2) {
+    float ms = 0.f;
+    GHIP_TRY(hipEventElapsedTime(&ms, g->ev[q], g->ev[q + 1]), "elapsed");
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)(g->ev_used / 2);
+  if (total_ms) *total_ms = tot;
+  g->ev_used = 0;
   return MHC_OK;
 }
 

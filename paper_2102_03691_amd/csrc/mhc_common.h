@@ -65,6 +65,39 @@ hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v,
 hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_steps, int64_t M_pad,
                            int64_t K_pad, float* out, int layout_g, int64_t ld);
 
+// Geometry of one system's T-batched contraction (plain data, shared with
+// the grouped launch, which keeps an array of these in device memory).
+struct GemmGeom {
+  const void* E;              // basis (A operand)
+  const void* B;              // activations (B operand)
+  float* out;                 // modal currents
+  int64_t K_pad, M_pad;
+  int ntb, n_ntiles, n_stages;
+  int64_t total_iters, ipw;   // iteration space and iterations per work-group
+  int layout_g;
+  const float* row_scale;     // e4m3 only: per-slot scale of E
+  const float* col_scale;     // e4m3 only: [4][ntb*32] activation scales
+};
+struct GroupTile {
+  int sys;
+  int tile;
+};
+
+// Tile shapes of the matrix-core contraction (slots x t-blocks of 32 steps):
+// 0 = 128 x 4, 1 = 256 x 2, 2 = 256 x 1.
+int gemm_shape_rows(int shape);
+int gemm_shape_tbs(int shape);
+bool gemm_shape_valid(int shape, int ntb);
+void gemm_geom(int prec, int shape, const void* E, const void* B, float* out, int64_t M_pad, int64_t K_pad, int ntb,
+               int layout_g, const float* row_scale, const float* col_scale, GemmGeom* g, int* n_mtiles);
+
+// Persistent launch over the tiles of several systems (same precision and
+// tile shape): n_wg work-groups pull tiles[] in order through *counter, which
+// must be zero at launch (launch_fill_i32).
+hipError_t launch_gemm_group(hipStream_t s, int prec, int shape, const GemmGeom* d_sys, const GroupTile* d_tiles,
+                             int n_tiles, int* counter, int n_wg);
+hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
+
 // T-batched matrix-core contraction with fused modal-current epilogue.
 //   ntb     t-blocks of 32 steps in the block (t_pad = 32*ntb)
 //   hnema:  out[ntile][M_pad][3]   sum over the tile's steps
@@ -89,6 +122,7 @@ struct ReduceArgs {
   double* hsum; double* hcomp; double* tsum; double* tcomp;  // HNEMA (may be null)
   double* X;                                                 // GKMA (may be null)
   double* ring; int64_t ring_len; int64_t t0;                // GKMA history
+  const int64_t* t0_dev;    // if set, the block's first step index is read here instead of t0
 };
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a);
 
@@ -99,7 +133,10 @@ hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int 
 //   C[tau][r][nu] += sum_{t < t_count, t0+t-tau >= 0} X[r][t] * ring[(t0+t-tau) % ring_len][nu]
 // accumulated with Neumaier compensation into csum/ccomp.
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
-                       const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp);
+                       const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
+                       const int64_t* t0_dev);
+// *t0 += by (advances a device-resident step counter after a block).
+hipError_t launch_advance(hipStream_t s, int64_t* t0, int64_t by);
 
 // Read-out of the GKMA accumulators: C = (csum + ccomp) / max(S - tau, 1)
 // (zero when S <= tau) and its trapezoid running integral with step dt.

@@ -1,0 +1,102 @@
+"""Grouped pushes of uneven systems (one persistent contraction launch per
+block, HIP-graph replay, tile-shape autotuning) against the same systems
+pushed one by one, and against the oracle.
+
+Graph replays are checked at several points with eager work and
+synchronizations in between: after every group push, every system's
+outputs are read back and compared with eager single-system pushes of the
+same steps.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests._cases import TOL, Case, announce, log, rel
+
+pytestmark = pytest.mark.gpu
+
+HNEMA, GKMA = 1, 2
+FP32, BF16X3, FP8, FP8X3 = 0, 1, 2, 3
+
+SYSTEMS = [((6, 6, 5), HNEMA), ((4, 4, 4), GKMA | HNEMA), ((5, 4, 3), HNEMA), ((3, 3, 3), GKMA | HNEMA),
+           ((8, 4, 4), GKMA | HNEMA)]
+S_TOTAL = 64 * 5 + 17
+SPLITS = [128, 64, 64 + 17, 64]          # several calls; the third ends with a partial block
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return [Case(d, S_TOTAL, mass_kind="natural", seed=20 + i) for i, (d, _) in enumerate(SYSTEMS)]
+
+
+def _ctx(case, methods, prec, stream):
+    from paper_2102_03691_amd import ModalHC
+    h = ModalHC(0, stream=stream)
+    h.load_system(case.m, case.freq)
+    h.set_bins_uniform(11, 0.0, case.lat.f_max)
+    h.configure(methods=methods, precision=prec, t_block=64, corr_len=20, dt=1.0, schedule=1)
+    h.load_eigvec_rows(0, case.lat.eig_rows(0, case.n_modes))
+    h.finalize()
+    return h
+
+
+def _read(h, methods):
+    out = {}
+    if methods & HNEMA:
+        out["hnema"], out["hnema_total"], out["n"] = h.read_hnema()
+    if methods & GKMA:
+        g = h.read_gkma()
+        out["corr"], out["hcacf"], out["n"] = g["corr"], g["hcacf"], g["n_samples"]
+    return out
+
+
+@pytest.mark.parametrize("prec,graph,autotune", [(BF16X3, True, False), (BF16X3, True, True), (FP32, False, True),
+                                                 (FP8X3, True, True)])
+def test_group_matches_single_pushes(cases, prec, graph, autotune):
+    import torch
+    from paper_2102_03691_amd import ModalGroup
+    announce(f"group prec={prec} graph={graph} autotune={autotune}")
+    stream = torch.cuda.Stream()
+    handle = stream.cuda_stream
+    grouped = [_ctx(c, m, prec, handle) for c, (_, m) in zip(cases, SYSTEMS)]
+    single = [_ctx(c, m, prec, handle) for c, (_, m) in zip(cases, SYSTEMS)]
+    grp = ModalGroup(grouped, graph=graph, autotune=autotune)
+    dev = [(torch.as_tensor(c.v, device="cuda:0"), torch.as_tensor(c.W, device="cuda:0")) for c in cases]
+    torch.cuda.synchronize()
+    s0 = 0
+    for n in SPLITS:
+        grp.push([v[s0:s0 + n] for v, _ in dev], [W[s0:s0 + n] for _, W in dev])
+        for h, (v, W) in zip(single, dev):
+            h.push(v[s0:s0 + n], W[s0:s0 + n])
+        s0 += n
+        for i, (hg, hs) in enumerate(zip(grouped, single)):
+            a, b = _read(hg, SYSTEMS[i][1]), _read(hs, SYSTEMS[i][1])
+            assert a["n"] == b["n"] == s0
+            for k in a:
+                if k == "n":
+                    continue
+                if not autotune:
+                    assert np.array_equal(a[k], b[k]), (i, k, s0)
+                else:
+                    assert rel(a[k], b[k]) <= 1e-5, (i, k, s0)
+    info = grp.info()
+    log(f"group_p{prec}_g{int(graph)}_a{int(autotune)}", **info)
+    # oracle parity of every system after the whole run
+    tol = 1e-2 if prec == FP8X3 else TOL[prec]
+    for i, (case, (_, methods)) in enumerate(zip(cases, SYSTEMS)):
+        ref = case.oracle(11, corr_len=20 if methods & GKMA else 0)
+        got = _read(grouped[i], methods)
+        if methods & HNEMA:
+            assert rel(got["hnema"], ref["hnema"]) <= tol, i
+        if methods & GKMA:
+            assert rel(got["corr"], ref["corr"]) <= tol, i
+    grp.close()
+    for h in grouped + single:
+        h.close()
