@@ -34,9 +34,18 @@ WORKLOADS = {
     "slab48x48x4_hnema_bf16x3_t128": ((48, 48, 4), 128, 1, 1, 1000, 0, 156),
     "slab48x48x4_hnema_fp32_t128": ((48, 48, 4), 128, 0, 1, 1000, 0, 20),
     "sc16_hnema_fp32_t1": ((16, 16, 16), 1, 0, 1, 500, 0, 40),
-    "rod4x4x1500_gkma_bf16x3_t256": ((4, 4, 1500), 256, 1, 3, 1000, 2000, 20),
+    "rod4x4x1500_gkma_bf16x3_t256": ((4, 4, 1500), 256, 1, 3, 1000, 2000, 195),
+    "rod4x4x1500_gkma_fp32_t256": ((4, 4, 1500), 256, 0, 3, 1000, 2000, 20),
 }
 DEFAULT = "slab48x48x4_hnema_bf16x3_t128"
+
+# Uneven serving-style batch: 16 simple-cubic systems, edges and methods drawn by seed
+# from {8,10,12,14,16,20} and {HNEMA, GKMA}; T = 64, 5000 steps each (78 full blocks).
+GROUP_WORKLOADS = {
+    "uneven16_fp8x3_t64": 3, "uneven16_fp8_t64": 2, "uneven16_bf16x3_t64": 1, "uneven16_fp32_t64": 0,
+}
+GROUP_NB, GROUP_L, GROUP_T, GROUP_STEPS = 500, 1000, 64, 78
+PEAK_FP8_FLOPS = 5.0e15
 
 
 def log(msg):
@@ -121,12 +130,92 @@ def cpu_baseline(dims, t_block, nb, budget_s=12.0):
                       f"{spent:.1f} s of CPU work"}
 
 
+def run_group(args, prec):
+    """The uneven batch as one grouped push per block (graph replay, autotuned tiles)."""
+    import torch
+    import synth
+    from paper_2102_03691_amd import GKMA, HNEMA, ModalGroup, ModalHC
+    K = args.steps or GROUP_STEPS
+    batch = synth.uneven_batch(0)
+    stream = torch.cuda.Stream()
+    handle = stream.cuda_stream
+    systems, inputs, units_per_block = [], [], 0.0
+    log(f"uneven batch: edges {[e for e, _ in batch]}, methods {[m for _, m in batch]}")
+    n_blocks = None
+    for i, (edge, meth) in enumerate(batch):
+        lat = synth.BlochLattice((edge, edge, edge))
+        m = synth.masses(lat.n_atoms)
+        h = ModalHC(0, stream=handle)
+        h.load_system(m, lat.frequencies)
+        h.set_bins_uniform(GROUP_NB, 0.0, lat.f_max)
+        methods = HNEMA if meth == 1 else GKMA
+        h.configure(methods=methods, precision=prec, t_block=GROUP_T, corr_len=GROUP_L, dt=1.0)
+        M = lat.n_modes
+        chunk = max(1, min(M, (512 << 20) // (8 * 3 * lat.n_atoms)))
+        for r0 in range(0, M, chunk):
+            n = min(chunk, M - r0)
+            h.load_eigvec_rows(r0, lat.eig_rows_torch(r0, n, device="cuda:0"))
+        torch.cuda.synchronize()
+        h.finalize()
+        systems.append(h)
+        units_per_block += float(lat.n_atoms) * M * GROUP_T
+        if n_blocks is None:
+            n_blocks = max(1, min(K + args.warmup, 8))
+        v, W = synth.gen_steps_torch(100 + i, m, n_blocks * GROUP_T, device="cuda:0")
+        inputs.append((v, W))
+    torch.cuda.synchronize()
+    grp = ModalGroup(systems, graph=True, autotune=True)
+
+    def block(j):
+        b = j % n_blocks
+        grp.push([v[b * GROUP_T:(b + 1) * GROUP_T] for v, _ in inputs],
+                 [W[b * GROUP_T:(b + 1) * GROUP_T] for _, W in inputs])
+
+    for j in range(args.warmup):
+        block(j)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(K):
+        block(args.warmup + j)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = grp.info()
+    # roofline of the grouped contraction: a few eager blocks with HIP events
+    grp.set_timing(True)
+    for j in range(4):
+        block(j)
+    launches, kms = grp.kernel_timing()
+    grp.set_timing(False)
+    avg_ms = kms / max(launches, 1)
+    flop_per_unit = {0: 24.0, 1: 72.0, 2: 24.0, 3: 72.0}[prec]
+    peak = {0: PEAK_FP32_MFMA_FLOPS, 1: PEAK_BF16_FLOPS, 2: PEAK_FP8_FLOPS, 3: PEAK_FP8_FLOPS}[prec]
+    achieved = flop_per_unit * units_per_block / (avg_ms * 1e-3)
+    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "kernel": "k_gemm_group", "avg_launch_ms": avg_ms,
+            "launches": launches, "tile_shape": info["tile_shape"], "autotuned_ms": info["tuned_ms"]}
+    grp.close()
+    for h in systems:
+        h.close()
+    return {"metric": METRIC, "value": units_per_block * K / wall, "unit": "atom*mode*steps/s", "n_gpus": 1,
+            "steps": K, "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": {0: "f32", 1: "bf16x3", 2: "fp8", 3: "fp8x3"}[prec],
+            "data": "synthetic",
+            "config": {"workload": args.workload, "systems": [[e, m] for e, m in batch],
+                       "md_steps_per_step": GROUP_T, "t_block": GROUP_T, "bins": GROUP_NB, "corr_len": GROUP_L,
+                       "precision": {0: "fp32", 1: "split-bf16 three products", 2: "e4m3 one product",
+                                     3: "e4m3 hi/lo three products"}[prec]
+                       + ", per-mode / per-(channel, step) scales for e4m3; fp64 bins and time sums",
+                       "launch": "grouped persistent contraction, HIP graph replay, autotuned tile shape",
+                       "parallelism": "single GPU"},
+            "roofline": roof}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -148,6 +237,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 3 copies of {n * 4} bytes")
         del src, dst
+    if args.workload in GROUP_WORKLOADS:
+        print(json.dumps(run_group(args, GROUP_WORKLOADS[args.workload])), flush=True)
+        return
     dims, t_block, prec, methods, nb, L, default_steps = WORKLOADS[args.workload]
     K = args.steps or default_steps
     lat = synth.BlochLattice(dims)

@@ -56,17 +56,47 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
         if (tid == 0) neumaier_add(a.hsum[b * 3 + mu], a.hcomp[b * 3 + mu], tot);
       }
     } else {
-      // GKMA: per-step binned currents X[(b*3+mu)][t]
+      // GKMA: per-step binned currents X[(b*3+mu)][t].  Threads form G groups
+      // of TT lanes (TT steps side by side); group g sums the bin's modes
+      // q = g, g+G, ... with four independent partial sums, and the groups are
+      // combined in a fixed order through LDS.
+      __shared__ double part[256][3];
+      const int TT = a.t_count <= 64 ? 64 : (a.t_count <= 128 ? 128 : 256);
+      const int G = 256 / TT;
+      const int g = tid / TT;
+      const int tl = tid % TT;
       double h3[3] = {0.0, 0.0, 0.0};
-      for (int t = tid; t < a.t_count; t += 256) {
+      for (int t0 = 0; t0 < a.t_count; t0 += TT) {
+        const int t = t0 + tl;
+        double v3[3] = {0.0, 0.0, 0.0};
+        if (t < a.t_count) {
 #pragma unroll
-        for (int mu = 0; mu < 3; ++mu) {
-          const float* col = a.in + ((int64_t)mu * a.M_pad + lo) * a.ld + t;
-          double s = 0.0;
-          for (int64_t q = 0; q < n; ++q) s += (double)col[q * a.ld];
-          a.X[((int64_t)b * 3 + mu) * a.ld + t] = s;
-          h3[mu] += s;
+          for (int mu = 0; mu < 3; ++mu) {
+            const float* col = a.in + ((int64_t)mu * a.M_pad + lo) * a.ld + t;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int64_t q = g;
+            for (; q + 3 * G < n; q += 4 * G) {
+              s0 += (double)col[q * a.ld];
+              s1 += (double)col[(q + G) * a.ld];
+              s2 += (double)col[(q + 2 * G) * a.ld];
+              s3 += (double)col[(q + 3 * G) * a.ld];
+            }
+            for (; q < n; q += G) s0 += (double)col[q * a.ld];
+            v3[mu] = (s0 + s1) + (s2 + s3);
+          }
         }
+        part[tid][0] = v3[0]; part[tid][1] = v3[1]; part[tid][2] = v3[2];
+        __syncthreads();
+        if (g == 0 && t < a.t_count) {
+#pragma unroll
+          for (int mu = 0; mu < 3; ++mu) {
+            double s = 0.0;
+            for (int gg = 0; gg < G; ++gg) s += part[gg * TT + tl][mu];
+            a.X[((int64_t)b * 3 + mu) * a.ld + t] = s;
+            h3[mu] += s;
+          }
+        }
+        __syncthreads();
       }
       if (a.hsum) {
 #pragma unroll
@@ -138,7 +168,10 @@ hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a) {
 }
 
 // -------------------------------------------------------------- correlation
-// Work-group tile: 64 rows r x 64 lags tau (x 3 nu); thread = 4 rows x 4 lags.
+// Sums are stored lag-contiguous: C[(r*3 + nu)*L + tau].
+// Work-group tile: 64 rows r x 64 lags tau (x 3 nu); thread = 4 rows x 4 lags,
+// with the 16 lag groups on consecutive lanes so that the Neumaier update of
+// a thread's 4 lags is one 32-byte run and a half-wave covers 512 bytes.
 // X and the needed window of the history ring are staged in LDS per chunk of
 // 64 steps; along t the 4 lags of a thread slide over the ring one entry per
 // step, so each step costs 4 X reads + 3 ring reads for 48 FMAs.
@@ -154,8 +187,8 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
   __shared__ double xs[CT][CR + 2];          // xs[t][r]
   __shared__ double rs[CT + CL][3];          // ring window
   const int tid = threadIdx.x;
-  const int tr = tid & 15;
-  const int tt = tid >> 4;
+  const int tt = tid & 15;                   // lag group (consecutive lanes)
+  const int tr = tid >> 4;                   // row group
   const int64_t r0 = (int64_t)blockIdx.x * CR;
   const int tau0 = blockIdx.y * CL;
   double acc[4][4][3];
@@ -188,7 +221,8 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int n = 0; n < 3; ++n) win[k][n] = rs[CL - 1 - 4 * tt - k][n];
-    for (int j = 0; j < CT; ++j) {
+    const int jmax = min(CT, t_count - tc);
+    for (int j = 0; j < jmax; ++j) {
       double x[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) x[i] = xs[j][4 * tr + i];
@@ -198,32 +232,30 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int n = 0; n < 3; ++n) acc[i][k][n] = fma(x[i], win[k][n], acc[i][k][n]);
-      if (j + 1 < CT) {
 #pragma unroll
-        for (int k = 3; k > 0; --k)
+      for (int k = 3; k > 0; --k)
 #pragma unroll
-          for (int n = 0; n < 3; ++n) win[k][n] = win[k - 1][n];
+        for (int n = 0; n < 3; ++n) win[k][n] = win[k - 1][n];
 #pragma unroll
-        for (int n = 0; n < 3; ++n) win[0][n] = rs[j + 1 + CL - 1 - 4 * tt][n];
-      }
+      for (int n = 0; n < 3; ++n) win[0][n] = rs[min(j + CL - 4 * tt, CT + CL - 1)][n];
     }
     __syncthreads();
   }
+  const int taub = tau0 + 4 * tt;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t r = r0 + 4 * tr + i;
     if (r >= R3) continue;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int tau = tau0 + 4 * tt + k;
-      if (tau >= L) continue;
+    for (int n = 0; n < 3; ++n) {
+      const int64_t o = (r * 3 + n) * L + taub;
 #pragma unroll
-      for (int n = 0; n < 3; ++n) {
-        const int64_t o = ((int64_t)tau * R3 + r) * 3 + n;
-        double sm = csum[o], cp = ccomp[o];
+      for (int k = 0; k < 4; ++k) {
+        if (taub + k >= L) continue;
+        double sm = csum[o + k], cp = ccomp[o + k];
         neumaier_add(sm, cp, acc[i][k][n]);
-        csum[o] = sm;
-        ccomp[o] = cp;
+        csum[o + k] = sm;
+        ccomp[o + k] = cp;
       }
     }
   }
@@ -255,9 +287,10 @@ __global__ void __launch_bounds__(256) k_corr_finish(const double* __restrict__ 
   if (q >= R3 * 3) return;
   double G = 0.0, prev = 0.0;
   for (int tau = 0; tau < L; ++tau) {
-    const int64_t o = (int64_t)tau * R3 * 3 + q;
+    const int64_t src = q * L + tau;               // sums are lag-contiguous
+    const int64_t o = (int64_t)tau * R3 * 3 + q;   // output [tau][r][nu]
     const int64_t cnt = S - tau;
-    const double c = (cnt > 0) ? (csum[o] + ccomp[o]) / (double)cnt : 0.0;
+    const double c = (cnt > 0) ? (csum[src] + ccomp[src]) / (double)cnt : 0.0;
     corr[o] = c;
     if (tau > 0) G += dt * 0.5 * (prev + c);
     integral[o] = G;

@@ -130,16 +130,17 @@ hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a);
 hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int t_count, double* jtot);
 
 // GKMA correlation update: for r < R3 = 3(nb+1), tau < L, nu < 3
-//   C[tau][r][nu] += sum_{t < t_count, t0+t-tau >= 0} X[r][t] * ring[(t0+t-tau) % ring_len][nu]
-// accumulated with Neumaier compensation into csum/ccomp.
+//   C[r][nu][tau] += sum_{t < t_count, t0+t-tau >= 0} X[r][t] * ring[(t0+t-tau) % ring_len][nu]
+// accumulated with Neumaier compensation into csum/ccomp (lag-contiguous).
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
                        const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
                        const int64_t* t0_dev);
 // *t0 += by (advances a device-resident step counter after a block).
 hipError_t launch_advance(hipStream_t s, int64_t* t0, int64_t by);
 
-// Read-out of the GKMA accumulators: C = (csum + ccomp) / max(S - tau, 1)
-// (zero when S <= tau) and its trapezoid running integral with step dt.
+// Read-out of the GKMA accumulators: C = (csum + ccomp) / (S - tau) (zero when
+// S <= tau) and its trapezoid running integral with step dt, written as
+// corr/integral[tau][r][nu].
 hipError_t launch_corr_finish(hipStream_t s, const double* csum, const double* ccomp, int64_t R3,
                               int L, int64_t S, double dt, double* corr, double* integral);
 
