@@ -52,7 +52,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_context(lat, t_block, precision, methods, nb, corr_len, device=0):
+def make_context(lat, t_block, precision, methods, nb, corr_len, device=0, schedule=0):
     import torch
     import synth
     from paper_2102_03691_amd import ModalHC
@@ -60,7 +60,8 @@ def make_context(lat, t_block, precision, methods, nb, corr_len, device=0):
     m = synth.masses(lat.n_atoms)
     h.load_system(m, lat.frequencies)
     h.set_bins_uniform(nb, 0.0, lat.f_max)
-    h.configure(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=1.0)
+    h.configure(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=1.0,
+                schedule=schedule)
     M = lat.n_modes
     chunk = max(1, min(M, (512 << 20) // (8 * 3 * lat.n_atoms)))
     for r0 in range(0, M, chunk):
@@ -216,6 +217,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS))
+    ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -245,7 +248,7 @@ def main():
     lat = synth.BlochLattice(dims)
     N, M = lat.n_atoms, lat.n_modes
     log(f"workload {args.workload}: N={N} M={M} T={t_block} prec={prec} steps={K} warmup={args.warmup}")
-    h, m = make_context(lat, t_block, prec, methods, nb, L)
+    h, m = make_context(lat, t_block, prec, methods, nb, L, schedule=args.schedule)
     md_per_step = t_block if t_block > 1 else 256      # per-step path: 256 MD steps per launch
     # inputs resident in HBM before the timed region (distinct block per bench step, cycled if huge)
     bytes_per_block = md_per_step * N * 12 * 4
@@ -284,6 +287,7 @@ def main():
            "vs_baseline": None, "dtype": {0: "f32", 1: "bf16x3"}[prec], "data": "synthetic",
            "config": {"workload": args.workload, "atoms": N, "modes": M, "md_steps_per_step": md_per_step,
                       "t_block": t_block, "bins": nb, "corr_len": L,
+                      "schedule": {0: "auto", 1: "tiles", 2: "stream-K", 3: "split"}[args.schedule],
                       "precision": {0: "fp32 operands, fp32 accumulate",
                                     1: "split-bf16 hi*hi+hi*lo+lo*hi, fp32 accumulate"}[prec]
                       + "; fp64 bins and time sums",

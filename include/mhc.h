@@ -91,16 +91,21 @@ typedef struct {
   int32_t corr_len;      /* GKMA lags L (tau = 0..L-1), 1..65536; ignored for HNEMA  */
   double dt;             /* sample interval for the GKMA integral (> 0)             */
   int32_t check_finite;  /* 1: mhc_push rejects non-finite v or W (host inputs only) */
-  int32_t schedule;      /* T-batched work split: MHC_SCHED_AUTO, _TILES or _STREAMK */
+  int32_t schedule;      /* T-batched work split: one of MHC_SCHED_* (below)         */
   int32_t reserved[2];   /* must be zero                                            */
 } mhc_run_config;
 
-/* Work split of the T-batched contraction (results agree to rounding):
- *   AUTO     the library's choice (currently TILES)
+/* Work split of the T-batched contraction (results agree to rounding; each
+ * choice is deterministic for a given device):
+ *   AUTO     SPLIT where it shortens the launch by 5 % or more, else TILES
  *   TILES    one output tile per work-group
  *   STREAMK  equal contiguous ranges of (tile, k-stage) iterations per CU,
- *            split tiles summed in a fixed order by a second kernel     */
-enum { MHC_SCHED_AUTO = 0, MHC_SCHED_TILES = 1, MHC_SCHED_STREAMK = 2 };
+ *            split tiles summed in a fixed order by a second kernel
+ *   SPLIT    one work-group per CU: whole tiles round by round, then the
+ *            tiles of the last, partial round cut along k so that every CU
+ *            takes part; the pieces of a tile are summed in a fixed order
+ *            by whichever work-group finishes its piece last              */
+enum { MHC_SCHED_AUTO = 0, MHC_SCHED_TILES = 1, MHC_SCHED_STREAMK = 2, MHC_SCHED_SPLIT = 3 };
 
 /* ---------------------------------------------------------------- lifetime */
 

@@ -10,7 +10,7 @@ from . import _build
 
 HNEMA, GKMA = 1, 2
 PREC_FP32, PREC_BF16X3, PREC_FP8, PREC_FP8X3 = 0, 1, 2, 3
-SCHED_AUTO, SCHED_TILES, SCHED_STREAMK = 0, 1, 2
+SCHED_AUTO, SCHED_TILES, SCHED_STREAMK, SCHED_SPLIT = 0, 1, 2, 3
 GROUP_GRAPH, GROUP_AUTOTUNE = 1, 2
 
 _STATUS = {0: "MHC_OK", 1: "MHC_ERR_INVALID_ARG", 2: "MHC_ERR_STATE", 3: "MHC_ERR_OOM",

@@ -13,6 +13,7 @@
 //     through LDS and reused across the 4 channels and all steps of a tile.
 #include <algorithm>
 
+#include "mhc.h"
 #include "mhc_common.h"
 
 namespace mhc {
@@ -146,6 +147,8 @@ hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_
 // G = n_tiles this is the plain one-tile-per-work-group schedule.
 constexpr int SU = 256;
 
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
+
 constexpr bool is_fp8(int prec) { return prec == PREC_FP8 || prec == PREC_FP8X3; }
 
 // Epilogue of one finished tile (accumulators complete).
@@ -267,24 +270,26 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
 
   u32x4 ast0[A_PER_THR], ast1[A_PER_THR];
   i32x8 bq[NBS / 2];
-  const u32x4* Ebase = reinterpret_cast<const u32x4*>(g.E) + rb0 * per_blk;
+  // Global-address-space views: the grouped kernel reads g from memory, and
+  // through generic pointers the loads would become flat loads, which count
+  // against the LDS wait counter too (every LDS wait would drain them).
+  // Bases are wave-uniform (scalar registers); the lane offset is added per
+  // load, so the loads use the scalar-base form and cost no 64-bit vector
+  // address registers.
+  static_assert(SU == 256 && A_PER_THR == RBW, "one A unit per thread per row block and stage");
+  const gu32x4* Ebase = (const gu32x4*)g.E + rb0 * per_blk;
   auto load_A = [&](int s, u32x4* dst) {
 #pragma unroll
-    for (int q = 0; q < A_PER_THR; ++q) {
-      const int idx = tid + 256 * q;
-      dst[q] = __builtin_nontemporal_load(Ebase + (idx / SU) * per_blk + (int64_t)s * SU + idx % SU);
-    }
+    for (int q = 0; q < A_PER_THR; ++q)
+      dst[q] = __builtin_nontemporal_load(Ebase + ((int64_t)q * per_blk + (int64_t)s * SU) + tid);
   };
   auto store_A = [&](int buf, const u32x4* src) {
 #pragma unroll
-    for (int q = 0; q < A_PER_THR; ++q) {
-      const int idx = tid + 256 * q;
-      lds[buf][idx / SU][idx % SU] = src[q];
-    }
+    for (int q = 0; q < A_PER_THR; ++q) lds[buf][q][tid] = src[q];
   };
-  const u32x4* Bw[4];
+  const gu32x4* Bw[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) Bw[c] = reinterpret_cast<const u32x4*>(g.B) + ((int64_t)c * g.ntb + tb) * per_blk + lane;
+  for (int c = 0; c < 4; ++c) Bw[c] = (const gu32x4*)g.B + ((int64_t)c * g.ntb + tb) * per_blk;
   // Chunk kk of stage s into NBF/2 eight-dword registers, units paired in
   // (channel, unit) order: FP32 (c0,c1)(c2,c3); BF16 (hi,lo) per channel;
   // FP8 (q0,q1) per channel; FP8X3 (hi q0,q1)(lo q0,q1) per channel.
@@ -294,7 +299,7 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
 #pragma unroll
     for (int p = 0; p < NBF / 2; ++p) {
       const int i0 = 2 * p, i1 = 2 * p + 1;
-      dst[p] = cat8(Bw[i0 / UPCH][u + (i0 % UPCH) * 64], Bw[i1 / UPCH][u + (i1 % UPCH) * 64]);
+      dst[p] = cat8((Bw[i0 / UPCH] + (u + (i0 % UPCH) * 64))[lane], (Bw[i1 / UPCH] + (u + (i1 % UPCH) * 64))[lane]);
     }
   };
   auto lo4 = [](i32x8 v) { return __builtin_shufflevector(v, v, 0, 1, 2, 3); };
@@ -312,6 +317,7 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
           ah[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 0) * 64 + lane]);
           al[rb] = __builtin_bit_cast(bf16x8, lds[buf][wm * MB + rb][(kk * 2 + 1) * 64 + lane]);
         }
+        __builtin_amdgcn_sched_barrier(0);     // all fragment reads in flight before the first MFMA
         // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
         // (lo4 of a channel's register is its hi part, hi4 its lo part)
 #pragma unroll
@@ -413,6 +419,31 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
   }
 }
 
+// Partial accumulators of one tile in a workspace slot, laid out so that
+// every store and load of the 256 threads is one contiguous 1 KiB row.
+template <int MB>
+__device__ __forceinline__ void acc_store(float* __restrict__ w, const f32x16 (&acc)[MB][4]) {
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) w[((rb * 4 + c) * 16 + j) * 256] = acc[rb][c][j];
+}
+
+template <int MB, bool ADD>
+__device__ __forceinline__ void acc_load(const float* __restrict__ w, f32x16 (&acc)[MB][4]) {
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const float x = w[((rb * 4 + c) * 16 + j) * 256];
+        acc[rb][c][j] = ADD ? acc[rb][c][j] + x : x;
+      }
+}
+
 template <int PREC, int WM, int WT, int MB>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
 k_gemm(float* __restrict__ ws, GemmGeom g) {
@@ -437,15 +468,111 @@ k_gemm(float* __restrict__ ws, GemmGeom g) {
       gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
     } else {
       // partial tile: slot 0 = this work-group's first segment, 1 = its last
-      float* w = ws + ((gl * 2 + (it == it_begin ? 0 : 1)) * NREG) * 256 + tid;
-#pragma unroll
-      for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-          for (int j = 0; j < 16; ++j) w[((rb * 4 + c) * 16 + j) * 256] = acc[rb][c][j];
+      acc_store<MB>(ws + ((gl * 2 + (it == it_begin ? 0 : 1)) * NREG) * 256 + tid, acc);
     }
     it += s1 - s0;
+    __syncthreads();
+  }
+}
+
+// Lockstep split schedule: one persistent work-group per CU.  The first
+// q x G tiles go round by round, one whole tile per work-group.  The R < G
+// remaining tiles are cut along k into m pieces so that the idle CUs of the
+// last round take part, while every group of work-groups that runs
+// concurrently walks the same k-stages (so the activation slices they read
+// stay shared in L2):
+//   Q > 0 (many remainder tiles): piece 0 = stages [0, c) of tile i on
+//     work-group i, piece 1 = [c, S) on work-group R + i % Q, which takes
+//     the tails of tiles i, i + Q, ... one after the other (m = 2);
+//   Q = 0 (few remainder tiles): piece p = [p S / m, (p + 1) S / m) of tile
+//     i on work-group p R + i.
+// Each piece is stored to its workspace slot p R + i, and the work-group
+// whose piece arrives last (a per-tile counter) adds the m pieces in piece
+// order and runs the epilogue, so the result does not depend on the arrival
+// order.  That work-group resets the counter, which is zero between
+// launches.  No work-group waits for another.
+struct SplitPlan {
+  int q;      // rounds of whole tiles
+  int R;      // remainder tiles q G .. q G + R - 1
+  int m;      // pieces per remainder tile (1: whole tiles)
+  int Q;      // tail work-groups (Q > 0: main + tail pieces)
+  int c;      // Q > 0: first stage of the tail piece
+  int* cnt;   // R arrival counters
+};
+
+__device__ __forceinline__ int split_stage(const SplitPlan& sp, int S, int p) {
+  if (sp.Q > 0) return p == 0 ? 0 : (p == 1 ? sp.c : S);
+  return (int)(((int64_t)p * S) / sp.m);
+}
+
+template <int PREC, int WM, int WT, int MB>
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+k_gemm_split(float* __restrict__ ws, GemmGeom g, SplitPlan sp) {
+  constexpr int RBW = WM * MB;
+  constexpr int NREG = MB * 4 * 16;
+  __shared__ u32x4 lds[2][RBW][SU];
+  __shared__ int arrived;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  const int gl = (int)wg_linear(blockIdx.x, G);
+  const int S = g.n_stages;
+  // this work-group's remainder pieces: piece p of tiles i0, i0 + stride, ...
+  int p = 0, i0 = sp.R, stride = 1;
+  if (sp.R > 0) {
+    if (sp.Q > 0) {
+      p = gl < sp.R ? 0 : 1;
+      i0 = p == 0 ? gl : gl - sp.R;
+      stride = p == 0 ? sp.R : sp.Q;
+    } else if (gl / sp.R < sp.m) {
+      p = gl / sp.R;
+      i0 = gl % sp.R;
+      stride = sp.R;
+    }
+  }
+  const int64_t per_slot = (int64_t)NREG * 256;
+  f32x16 acc[MB][4];
+  // jobs 0 .. q-1: whole tiles gl + w G; then the remainder pieces
+  for (int job = 0;; ++job) {
+    int64_t tile;
+    int s0 = 0, s1 = S, i = 0;
+    bool piece = false;
+    if (job < sp.q) {
+      tile = (int64_t)job * G + gl;
+    } else {
+      i = i0 + (job - sp.q) * stride;
+      if (i >= sp.R) break;
+      tile = (int64_t)sp.q * G + i;
+      s0 = split_stage(sp, S, p);
+      s1 = split_stage(sp, S, p + 1);
+      piece = sp.m > 1;
+    }
+    const int64_t rb0 = (tile / g.n_ntiles) * RBW;
+    const int ntile = (int)(tile % g.n_ntiles);
+    gemm_segment<PREC, WM, WT, MB>(g, rb0, ntile, s0, s1, acc, lds);
+    bool finish = true;
+    if (piece) {
+      float* base = ws + tid;
+      acc_store<MB>(base + (int64_t)(p * sp.R + i) * per_slot, acc);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // write this piece back from L2
+      __syncthreads();
+      if (tid == 0) arrived = atomicAdd(&sp.cnt[i], 1);
+      __syncthreads();
+      finish = arrived == sp.m - 1;
+      if (finish) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // drop stale lines before reading the others
+        // pieces 0 + 1 (commutative, so this one may come from registers),
+        // then 2 .. m-1 in order
+        if (p <= 1) {
+          acc_load<MB, true>(base + (int64_t)((1 - p) * sp.R + i) * per_slot, acc);
+        } else {
+          acc_load<MB, false>(base + (int64_t)i * per_slot, acc);
+          acc_load<MB, true>(base + (int64_t)(sp.R + i) * per_slot, acc);
+        }
+        for (int r = 2; r < sp.m; ++r) acc_load<MB, true>(base + (int64_t)(r * sp.R + i) * per_slot, acc);
+        if (tid == 0) sp.cnt[i] = 0;
+      }
+    }
+    if (finish) gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
     __syncthreads();
   }
 }
@@ -514,19 +641,82 @@ __global__ void __launch_bounds__(256) k_gemm_fixup(const float* __restrict__ ws
   gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, (int64_t)mtile * RBW, ntile, red);
 }
 
+// Plan of the lockstep split for n_tiles tiles of S stages on G = n_cu
+// work-groups; false if it would not shorten the launch (estimated in
+// stage-times of one CU) by at least min_gain, or the workspace is short.
+static bool plan_split(int64_t n_tiles, int S, int G, int64_t slot_floats, int64_t ws_floats, double min_gain,
+                       SplitPlan* sp) {
+  constexpr int MIN_PIECE = 8;                                   // stages per piece
+  if (G < 2 || n_tiles < 1) return false;
+  const int64_t q = n_tiles / G;
+  const int R = (int)(n_tiles % G);
+  if (R == 0 || q > (1 << 20)) return false;
+  SplitPlan p{};
+  p.q = (int)q;
+  p.R = R;
+  double span;                                                   // stages on the busiest CU
+  const int Q = G - R;
+  if (R >= Q) {
+    // main pieces [0, c), tails [c, S) k per tail work-group; a tail
+    // work-group runs its stages about 8 % slower (several short pieces,
+    // each with a pipeline start and a partial store)
+    constexpr double TAIL_COST = 1.08;
+    const int k = (R + Q - 1) / Q;
+    int best = -1;
+    double best_span = 1e300;
+    const int r0 = (int)(S / (1.0 + TAIL_COST * k));
+    for (int r = r0; r <= r0 + 1; ++r) {
+      if (r < MIN_PIECE || S - r < MIN_PIECE) continue;
+      const double sp_r = std::max<double>(S - r, TAIL_COST * k * r);
+      if (sp_r < best_span) { best_span = sp_r; best = r; }
+    }
+    if (best < 0) return false;
+    p.m = 2;
+    p.Q = Q;
+    p.c = S - best;
+    span = best_span;
+  } else {
+    const int m = std::min(G / R, S / MIN_PIECE);
+    if (m < 2) return false;
+    p.m = m;
+    p.Q = 0;
+    span = (double)((S + m - 1) / m);
+  }
+  if ((int64_t)p.m * R * slot_floats > ws_floats) return false;
+  const double plain = (double)(q + 1) * S, split = (double)q * S + span;
+  if (split > (1.0 - min_gain) * plain) return false;
+  *sp = p;
+  return true;
+}
+
 template <int PREC, int WM, int WT, int MB>
 static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B, float* out, float* ws,
-                                    int64_t ws_floats, GemmGeom g, int n_mtiles, int n_cu, int sched) {
+                                    int64_t ws_floats, int* tile_cnt, GemmGeom g, int n_mtiles, int n_cu,
+                                    int sched) {
   constexpr int NREG = MB * 4 * 16;
   const int64_t n_tiles = (int64_t)n_mtiles * g.n_ntiles;
   g.total_iters = n_tiles * g.n_stages;
+  g.E = E;
+  g.B = B;
+  g.out = out;
+  // Lockstep split when the last round of tiles would leave CUs idle
+  // (AUTO: only when it saves at least 5 %).
+  if ((sched == MHC_SCHED_SPLIT || sched == MHC_SCHED_AUTO) && tile_cnt) {
+    SplitPlan sp{};
+    if (plan_split(n_tiles, g.n_stages, n_cu, (int64_t)NREG * 256, ws_floats,
+                   sched == MHC_SCHED_AUTO ? 0.05 : 0.0, &sp)) {
+      sp.cnt = tile_cnt;
+      hipLaunchKernelGGL((k_gemm_split<PREC, WM, WT, MB>), dim3((unsigned)n_cu), dim3(256), 0, s, ws, g, sp);
+      return hipGetLastError();
+    }
+  }
   int64_t G = n_tiles;
   g.ipw = g.n_stages;
   // Stream-K only on request: work-groups that start at different k-stages no
   // longer share the activation k-slices in L2 (the tiled schedule marches
   // all work-groups of an XCD through k together), and on the 27648-mode
   // slab that extra MALL traffic costs more than the idle CUs it recovers.
-  bool sk = (sched == 2);
+  bool sk = (sched == MHC_SCHED_STREAMK);
   if (sk) {
     G = std::min<int64_t>(n_cu, std::max<int64_t>(1, g.total_iters / 4));
     g.ipw = (g.total_iters + G - 1) / G;
@@ -537,9 +727,6 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
       g.ipw = g.n_stages;
     }
   }
-  g.E = E;
-  g.B = B;
-  g.out = out;
   hipLaunchKernelGGL((k_gemm<PREC, WM, WT, MB>), dim3((unsigned)G), dim3(256), 0, s, ws, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !sk) return e;
@@ -549,8 +736,9 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
 
 template <int PREC>
 static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t K_pad, int ntb,
-                                   float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats, int n_cu,
-                                   int sched, const float* row_scale, const float* col_scale) {
+                                   float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
+                                   int* tile_cnt, int n_cu, int sched, const float* row_scale,
+                                   const float* col_scale) {
   GemmGeom g{};
   g.K_pad = K_pad;
   g.M_pad = M_pad;
@@ -564,22 +752,23 @@ static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, 
     // 128 slots x 4 t-blocks per tile
     g.n_ntiles = ntb / 4;
     *n_parts = g.n_ntiles;
-    return launch_gemm_shape<PREC, 1, 4, 4>(s, E, B, out, ws, ws_floats, g, (int)(M_pad / 128), n_cu, sched);
+    return launch_gemm_shape<PREC, 1, 4, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 128), n_cu, sched);
   } else if (ntb % 2 == 0) {
     g.n_ntiles = ntb / 2;
     *n_parts = g.n_ntiles;
-    return launch_gemm_shape<PREC, 2, 2, 4>(s, E, B, out, ws, ws_floats, g, (int)(M_pad / 256), n_cu, sched);
+    return launch_gemm_shape<PREC, 2, 2, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched);
   }
   g.n_ntiles = ntb;
   *n_parts = g.n_ntiles;
-  return launch_gemm_shape<PREC, 4, 1, 2>(s, E, B, out, ws, ws_floats, g, (int)(M_pad / 256), n_cu, sched);
+  return launch_gemm_shape<PREC, 4, 1, 2>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched);
 }
 
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
-                       int ntb, float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats, int n_cu,
-                       int sched, const float* row_scale, const float* col_scale) {
+                       int ntb, float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
+                       int* tile_cnt, int n_cu, int sched, const float* row_scale, const float* col_scale) {
 #define MHC_GEMM(P) \
-  launch_gemm_prec<P>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, n_cu, sched, row_scale, col_scale)
+  launch_gemm_prec<P>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, tile_cnt, n_cu, sched, \
+                      row_scale, col_scale)
   switch (prec) {
     case PREC_BF16X3: return MHC_GEMM(PREC_BF16X3);
     case PREC_FP8: return MHC_GEMM(PREC_FP8);

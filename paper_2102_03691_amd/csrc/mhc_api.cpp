@@ -87,7 +87,8 @@ struct mhc_ctx {
   int64_t R3 = 0;
   double *d_csum = nullptr, *d_ccomp = nullptr;
   double* d_out = nullptr;
-  float* d_ws = nullptr;      // stream-K workspace
+  float* d_ws = nullptr;      // partial tiles of the split and stream-K schedules
+  int* d_tile_cnt = nullptr;  // arrival counters of the split schedule (zero between launches)
   int64_t* d_t0 = nullptr;    // first step of the next block (grouped, graph-replayed pushes)
   int64_t ws_floats = 0;
   int n_cu = 256;
@@ -331,7 +332,7 @@ mhc_status mhc_configure(mhc_ctx* ctx, const mhc_run_config* cfg) {
   if ((cfg->methods & MHC_GKMA) && !(std::isfinite(cfg->dt) && cfg->dt > 0.0))
     return fail(ctx, MHC_ERR_INVALID_ARG, "dt must be finite and > 0");
   if (cfg->check_finite != 0 && cfg->check_finite != 1) return fail(ctx, MHC_ERR_INVALID_ARG, "check_finite is 0 or 1");
-  if (cfg->schedule < MHC_SCHED_AUTO || cfg->schedule > MHC_SCHED_STREAMK)
+  if (cfg->schedule < MHC_SCHED_AUTO || cfg->schedule > MHC_SCHED_SPLIT)
     return fail(ctx, MHC_ERR_INVALID_ARG, "unknown schedule");
   if (cfg->reserved[0] || cfg->reserved[1])
     return fail(ctx, MHC_ERR_INVALID_ARG, "reserved fields must be zero");
@@ -499,8 +500,12 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     // per CU: two partial tiles of 256 threads x 256 accumulator floats
     ctx->ws_floats = (int64_t)ctx->n_cu * 2 * 256 * 256;
     void* pws = nullptr;
-    if ((st = dev_alloc(ctx, (size_t)ctx->ws_floats * 4, &pws, "stream-K workspace"))) return st;
+    if ((st = dev_alloc(ctx, (size_t)ctx->ws_floats * 4, &pws, "contraction workspace"))) return st;
     ctx->d_ws = reinterpret_cast<float*>(pws);
+    void* pcnt = nullptr;
+    if ((st = dev_alloc(ctx, (size_t)ctx->n_cu * 4, &pcnt, "split counters"))) return st;
+    HIP_TRY(hipMemsetAsync(pcnt, 0, (size_t)ctx->n_cu * 4, ctx->stream), "zero split counters");
+    ctx->d_tile_cnt = reinterpret_cast<int*>(pcnt);
   }
   // masses
   std::vector<float> sm(N), ism(N);
@@ -638,8 +643,8 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
     n_parts = t_count;
   } else {
     HIP_TRY(launch_gemm(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
-                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->n_cu, c.schedule, ctx->d_rowscale,
-                        ctx->d_colscale),
+                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->d_tile_cnt, ctx->n_cu, c.schedule,
+                        ctx->d_rowscale, ctx->d_colscale),
             "batched contraction");
   }
   if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");

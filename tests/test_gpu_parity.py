@@ -46,9 +46,10 @@ def test_sc4_per_step_fp32_hnema():
 
 @pytest.mark.parametrize("prec", [FP32, BF16X3])
 @pytest.mark.parametrize("T,sched", [(32, 1), (64, 1), (96, 1), (128, 1), (256, 1), (32, 2), (64, 2), (96, 2),
-                                     (128, 2), (256, 2)])
+                                     (128, 2), (256, 2), (32, 3), (64, 3), (256, 3)])
 def test_batched_hnema(small, prec, T, sched):
-    """sched 1 = one tile per work-group, 2 = stream-K (split tiles + fixup)."""
+    """sched 1 = one tile per work-group, 2 = stream-K (split tiles + fixup),
+    3 = lockstep split (tiles of the last round cut along k)."""
     announce(f"batched hnema prec={prec} T={T} sched={sched}")
     ref = small.oracle(23)
     got = run_library(small, 23, HNEMA, prec, T, schedule=sched)
@@ -103,7 +104,7 @@ def test_mode_subset_and_explicit_bins():
     assert e <= TOL[FP32]
 
 
-@pytest.mark.parametrize("sched", [1, 2])
+@pytest.mark.parametrize("sched", [1, 2, 3])
 def test_block_split_invariance_and_determinism(small, sched):
     announce(f"split invariance + determinism bf16x3 T=64 sched={sched}")
     a = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16, schedule=sched)
@@ -200,3 +201,28 @@ def test_fp8(small, prec, T, sched):
     bound = 1e-2 if prec == FP8X3 else 0.15
     assert e["rel_hnema"] <= bound and e["rel_corr"] <= bound and e["rel_integral"] <= bound
     assert e["rel_hcacf"] <= 1e-12
+
+
+@pytest.mark.parametrize("dims,prec,T,n_steps", [((8, 8, 4), BF16X3, 64, 200), ((8, 8, 4), FP32, 32, 200),
+                                                 ((12, 12, 8), FP8X3, 128, 200), ((16, 16, 8), BF16X3, 512, 512)])
+def test_split_schedule(dims, prec, T, n_steps):
+    """Lockstep split with several pieces per tile: 8x8x4 has 24 k-stages and
+    3 tiles (3 pieces each, so the fixed-order sum of pieces 2.. runs); the
+    12x12x8 FP8X3 case cuts 28 tiles into 6 pieces; 16x16x8 at T = 512 has
+    192 tiles, more than half the CUs, so its tiles get a main piece and a
+    tail piece, three tails per spare work-group.  Checked against the oracle,
+    against the one-tile-per-work-group schedule, and for bitwise
+    repeatability."""
+    announce(f"split schedule dims={dims} prec={prec} T={T}")
+    c = Case(dims, n_steps, mass_kind="natural", seed=5)
+    nb = 37
+    ref = c.oracle(nb)
+    a = run_library(c, nb, HNEMA, prec, T, schedule=3, row_chunk=512)
+    b = run_library(c, nb, HNEMA, prec, T, schedule=3, row_chunk=512)
+    t = run_library(c, nb, HNEMA, prec, T, schedule=1, row_chunk=512)
+    e = rel(a["hnema"], ref["hnema"])
+    et = rel(a["hnema"], t["hnema"])
+    log(f"{dims[0]}x{dims[1]}x{dims[2]}_split_p{prec}_T{T}", rel_hnema=e, rel_vs_tiles=et)
+    assert np.array_equal(a["hnema"], b["hnema"])
+    tol = TOL.get(prec, 1e-2)
+    assert e <= tol and et <= tol
