@@ -38,74 +38,103 @@ __device__ __forceinline__ f32x16 mfma_fp8(i32x8 a, i32x8 b, f32x16 c) {
 __device__ __forceinline__ int acc_row(int j, int half) { return 8 * (j >> 2) + 4 * half + (j & 3); }
 
 // ----------------------------------------------------------- per-step FP32
-// Work-group = one row block of 32 slots, 8 waves; wave w owns a contiguous
-// eighth of the dof chunks.  Each lane accumulates 4 channel partial sums of
-// its row over its dofs; the 64 lanes x 8 waves are combined in fixed order.
-constexpr int GEMV_WAVES = 8;
+// One wave = 8 consecutive slots x one step.  E is stored row-major for this
+// path (slot-major, dofs contiguous), so a wave's load of one row is 64 lanes
+// x 4 dofs = 1 KiB contiguous; the lane's 4 dofs of the four activation
+// channels are loaded once and used for all 8 rows.  Both operands are
+// double-buffered in registers (the loads of the next 256 dofs are in flight
+// while the current ones are consumed).  Per (row, channel) each lane keeps
+// one partial sum; the 64 lanes are combined by a fixed butterfly.  Waves are
+// ordered row group fastest, so the chip streams E once per step, step after
+// step.
+typedef __attribute__((address_space(1))) const f32x4 gf32x4;
+constexpr int GEMV_ROWS = 8;
 
-__global__ void __launch_bounds__(64 * GEMV_WAVES)
+__global__ void __launch_bounds__(256)
 k_gemv_f32(const f32x4* __restrict__ E, const float* __restrict__ B, int n_steps, int64_t M_pad,
            int64_t K_pad, float* __restrict__ out, int layout_g, int64_t ld) {
-  __shared__ float red[GEMV_WAVES][32][4];
-  const int rb = blockIdx.x;
-  const int wave = threadIdx.x >> 6;
+  constexpr int R = GEMV_ROWS;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int half = lane >> 5;
-  const int r = lane & 31;
-  const int64_t KC = K_pad >> 3;
-  const int64_t per_wave = KC / GEMV_WAVES;
-  const int64_t kc0 = wave * per_wave;
-  const f32x4* Ew = E + ((int64_t)rb * KC + kc0) * 64 + lane;
-  for (int t = 0; t < n_steps; ++t) {
-    const float* Bt = B + (int64_t)t * 4 * K_pad + kc0 * 8 + 4 * half;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll 8
-    for (int64_t i = 0; i < per_wave; ++i) {
-      const f32x4 e = __builtin_nontemporal_load(Ew + i * 64);
-      const f32x4 b0 = *reinterpret_cast<const f32x4*>(Bt + i * 8);
-      const f32x4 b1 = *reinterpret_cast<const f32x4*>(Bt + K_pad + i * 8);
-      const f32x4 b2 = *reinterpret_cast<const f32x4*>(Bt + 2 * K_pad + i * 8);
-      const f32x4 b3 = *reinterpret_cast<const f32x4*>(Bt + 3 * K_pad + i * 8);
-      a0 = fmaf(e.x, b0.x, a0); a0 = fmaf(e.y, b0.y, a0); a0 = fmaf(e.z, b0.z, a0); a0 = fmaf(e.w, b0.w, a0);
-      a1 = fmaf(e.x, b1.x, a1); a1 = fmaf(e.y, b1.y, a1); a1 = fmaf(e.z, b1.z, a1); a1 = fmaf(e.w, b1.w, a1);
-      a2 = fmaf(e.x, b2.x, a2); a2 = fmaf(e.y, b2.y, a2); a2 = fmaf(e.z, b2.z, a2); a2 = fmaf(e.w, b2.w, a2);
-      a3 = fmaf(e.x, b3.x, a3); a3 = fmaf(e.y, b3.y, a3); a3 = fmaf(e.z, b3.z, a3); a3 = fmaf(e.w, b3.w, a3);
-    }
-    a0 += __shfl_xor(a0, 32);
-    a1 += __shfl_xor(a1, 32);
-    a2 += __shfl_xor(a2, 32);
-    a3 += __shfl_xor(a3, 32);
-    if (half == 0) {
-      red[wave][r][0] = a0; red[wave][r][1] = a1; red[wave][r][2] = a2; red[wave][r][3] = a3;
-    }
-    __syncthreads();
-    if (threadIdx.x < 32) {
-      float x = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+  const int64_t n_rg = M_pad / R;
+  const int64_t unit = (int64_t)blockIdx.x * 4 + wave;
+  if (unit >= n_rg * n_steps) return;
+  const int t = (int)(unit / n_rg);
+  const int64_t rg = unit - (int64_t)t * n_rg;
+  const int64_t KC = K_pad >> 2;                       // 16-byte units per row
+  const gf32x4* Er = (const gf32x4*)E + rg * R * KC;
+  const gf32x4* Bt = (const gf32x4*)B + (int64_t)t * 4 * KC;
+  const int64_t n_it = KC / 64;                         // even: K_pad is a multiple of 512
+  float acc[R][4];
 #pragma unroll
-      for (int w = 0; w < GEMV_WAVES; ++w) {
-        x += red[w][threadIdx.x][0];
-        ax += red[w][threadIdx.x][1];
-        ay += red[w][threadIdx.x][2];
-        az += red[w][threadIdx.x][3];
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.f;
+  f32x4 ea[R], eb[R], ba[4], bb[4];
+  auto load = [&](f32x4 (&e)[R], f32x4 (&bv)[4], int64_t it) {
+    const int64_t u = it * 64 + lane;
+#pragma unroll
+    for (int r = 0; r < R; ++r) e[r] = __builtin_nontemporal_load(Er + r * KC + u);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[c] = Bt[c * KC + u];
+  };
+  auto consume = [&](const f32x4 (&e)[R], const f32x4 (&bv)[4]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float a = acc[r][c];
+        a = fmaf(e[r].x, bv[c].x, a);
+        a = fmaf(e[r].y, bv[c].y, a);
+        a = fmaf(e[r].z, bv[c].z, a);
+        a = fmaf(e[r].w, bv[c].w, a);
+        acc[r][c] = a;
       }
-      const int64_t slot = (int64_t)rb * 32 + threadIdx.x;
-      if (!layout_g) {
-        float* o = out + ((int64_t)t * M_pad + slot) * 3;
-        o[0] = x * ax; o[1] = x * ay; o[2] = x * az;
-      } else {
-        out[(0 * M_pad + slot) * ld + t] = x * ax;
-        out[(1 * M_pad + slot) * ld + t] = x * ay;
-        out[(2 * M_pad + slot) * ld + t] = x * az;
-      }
+  };
+  // iterations in pairs; the prefetch after the last pair re-reads the last
+  // iteration and is not consumed
+  load(ea, ba, 0);
+  for (int64_t it = 0; it < n_it; it += 2) {
+    load(eb, bb, it + 1);
+    __builtin_amdgcn_sched_barrier(0);   // keep each load batch ahead of the other set's FMAs
+    consume(ea, ba);
+    __builtin_amdgcn_sched_barrier(0);
+    load(ea, ba, min(it + 2, n_it - 1));
+    __builtin_amdgcn_sched_barrier(0);
+    consume(eb, bb);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float a = acc[r][c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+      acc[r][c] = a;
     }
-    __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (lane != r) continue;
+    const int64_t slot = rg * R + r;
+    const float x = acc[r][0];
+    if (!layout_g) {
+      float* o = out + ((int64_t)t * M_pad + slot) * 3;
+      o[0] = x * acc[r][1]; o[1] = x * acc[r][2]; o[2] = x * acc[r][3];
+    } else {
+      out[(0 * M_pad + slot) * ld + t] = x * acc[r][1];
+      out[(1 * M_pad + slot) * ld + t] = x * acc[r][2];
+      out[(2 * M_pad + slot) * ld + t] = x * acc[r][3];
+    }
   }
 }
 
 hipError_t launch_gemv_f32(hipStream_t s, const float* E, const float* B, int n_steps, int64_t M_pad,
                            int64_t K_pad, float* out, int layout_g, int64_t ld) {
   if (n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemv_f32, dim3((unsigned)(M_pad / 32)), dim3(64 * GEMV_WAVES), 0, s,
+  if (M_pad % GEMV_ROWS != 0 || K_pad % K_ALIGN_GEMV != 0) return hipErrorInvalidValue;
+  const int64_t units = (M_pad / GEMV_ROWS) * n_steps;
+  hipLaunchKernelGGL(k_gemv_f32, dim3((unsigned)((units + 3) / 4)), dim3(256), 0, s,
                      reinterpret_cast<const f32x4*>(E), B, n_steps, M_pad, K_pad, out, layout_g, ld);
   return hipGetLastError();
 }

@@ -19,7 +19,7 @@ namespace mhc {
 template <int PREC>
 __global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ rows, int64_t n_rows,
                                                      int64_t K, const int32_t* __restrict__ slot_of_row,
-                                                     void* __restrict__ E, int64_t K_pad) {
+                                                     void* __restrict__ E, int64_t K_pad, int gemv) {
   constexpr int PW = (PREC == PREC_FP32) ? 4 : 8;     // dofs per piece
   const int64_t pieces = K_pad / PW;
   const int64_t r = blockIdx.y;
@@ -41,7 +41,10 @@ __global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ 
     o.z = (k0 + 2 < K) ? (float)row[k0 + 2] : 0.f;
     o.w = (k0 + 3 < K) ? (float)row[k0 + 3] : 0.f;
     float4* dst = reinterpret_cast<float4*>(E);
-    dst[(rb * (K_pad >> 3) + kc) * 64 + lane] = o;
+    if (gemv)   // row-major layout of the per-step path
+      dst[(int64_t)slot * (K_pad >> 2) + (k0 >> 2)] = o;
+    else
+      dst[(rb * (K_pad >> 3) + kc) * 64 + lane] = o;
   } else {
     const int64_t kc = k0 >> 4;
     const int h = (int)((k0 >> 3) & 1);
@@ -63,15 +66,17 @@ __global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ 
 }
 
 hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows, int64_t K,
-                              const int32_t* slot_of_row, void* E, int64_t K_pad) {
+                              const int32_t* slot_of_row, void* E, int64_t K_pad, int gemv) {
   if (n_rows <= 0) return hipSuccess;
   const int PW = (prec == PREC_FP32) ? 4 : 8;
   const int64_t pieces = K_pad / PW;
   dim3 grid((unsigned)((pieces + 255) / 256), (unsigned)n_rows);
   if (prec == PREC_FP32)
-    hipLaunchKernelGGL(k_basis_store<PREC_FP32>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad);
+    hipLaunchKernelGGL(k_basis_store<PREC_FP32>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad,
+                       gemv);
   else
-    hipLaunchKernelGGL(k_basis_store<PREC_BF16X3>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad);
+    hipLaunchKernelGGL(k_basis_store<PREC_BF16X3>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad,
+                       0);
   return hipGetLastError();
 }
 

@@ -357,7 +357,8 @@ static mhc_status start_rows(mhc_ctx* ctx) {
   }
   const int64_t M_used = off[nb];
   // input prep writes whole 32-atom (96-dof) groups, so cover them
-  const int64_t K_pad = round_up(3 * round_up(ctx->N, ATOMS_PER_PREP), K_ALIGN);
+  const int64_t K_pad =
+      round_up(3 * round_up(ctx->N, ATOMS_PER_PREP), ctx->cfg.t_block == 1 ? K_ALIGN_GEMV : K_ALIGN);
   const int64_t M_pad = round_up(std::max<int64_t>(M_used, 1), M_ALIGN);
   // bytes per element: fp32 or bf16 hi + lo 4, e4m3 hi + lo 2, e4m3 1
   const int prec = ctx->cfg.precision;
@@ -425,7 +426,8 @@ mhc_status mhc_load_eigvec_rows(mhc_ctx* ctx, int64_t mode0, int64_t n_rows, con
                                      ctx->K_pad, ctx->d_rowscale),
               "basis store");
     else
-      HIP_TRY(launch_basis_store(ctx->stream, prec, src, nr, ctx->K, ctx->d_slot, ctx->dE, ctx->K_pad),
+      HIP_TRY(launch_basis_store(ctx->stream, prec, src, nr, ctx->K, ctx->d_slot, ctx->dE, ctx->K_pad,
+                                 ctx->cfg.t_block == 1 ? 1 : 0),
               "basis store");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "basis store sync");
   }

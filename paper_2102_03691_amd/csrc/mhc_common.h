@@ -27,6 +27,7 @@ namespace mhc {
 //   B  BF16   [4*NTB][K_pad/16][2][64][8]             bf16
 // Channels c: 0 = u = sqrt(m) v, 1..3 = w^mu = W^{mu .} / sqrt(m).
 constexpr int K_ALIGN = 128;    // K_pad multiple (one e4m3 stage is 128 dofs)
+constexpr int K_ALIGN_GEMV = 512;  // per-step path: rows of 128 units, 2 x 64 lanes per iteration pair
 constexpr int M_ALIGN = 256;    // M_pad multiple
 constexpr int ATOMS_PER_PREP = 32;  // atoms per input-prep work-group (96 dofs)
 
@@ -37,8 +38,9 @@ enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1, PREC_FP8 = 2, PREC_FP8X3 = 3 };
 
 // Convert n_rows float64 E^T rows (device, row r = mode r0 + r) into the
 // storage layout.  slot_of_row[r] is the destination slot (-1 = skip).
+// gemv = 1 (FP32 only): the row-major layout of the per-step path.
 hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows,
-                              int64_t K, const int32_t* slot_of_row, void* E, int64_t K_pad);
+                              int64_t K, const int32_t* slot_of_row, void* E, int64_t K_pad, int gemv);
 
 // e4m3 basis store: per-mode scale s_n = max|E[.][n]| / 448 into row_scale[slot],
 // then E/s_n as e4m3 (x3: plus the e4m3 residual).
