@@ -270,15 +270,6 @@ hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count,
   return hipGetLastError();
 }
 
-__global__ void k_advance(int64_t* t0, int64_t by) {
-  if (threadIdx.x == 0) *t0 += by;
-}
-
-hipError_t launch_advance(hipStream_t s, int64_t* t0, int64_t by) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, t0, by);
-  return hipGetLastError();
-}
-
 // ----------------------------------------------------------------- read-out
 __global__ void __launch_bounds__(256) k_corr_finish(const double* __restrict__ csum, const double* __restrict__ ccomp,
                                                      int64_t R3, int L, int64_t S, double dt,

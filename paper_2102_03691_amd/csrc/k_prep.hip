@@ -142,17 +142,27 @@ hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, in
 }
 
 // Per-column scales of the e4m3 activations: for step t and channel c,
-// s_{c,t} = max_j |B_c[t][j]| / 448 (1 if the column is zero).  One
-// work-group per step, fixed-order max reduction.
-__global__ void __launch_bounds__(256) k_col_scale(const float* __restrict__ v, const float* __restrict__ W,
+// s_{c,t} = max_j |B_c[t][j]| / 448 (1 if the column is zero).  Work-group
+// (t, cc) takes the maxima over atoms [cc A, (cc+1) A), A = COLSCALE_ATOMS,
+// into col_part[cc][c][t]; the input prep combines the chunks (max is exact
+// in any order).  With tab != NULL the input pointers are read from tab[0],
+// tab[1] (device memory), so a captured graph can be fed new inputs.
+__global__ void __launch_bounds__(256) k_col_scale(const float* v, const float* W,
                                                    const float* __restrict__ sqrt_m,
                                                    const float* __restrict__ inv_sqrt_m, int64_t N, int t_count,
-                                                   int t_pad, float* __restrict__ col_scale) {
+                                                   int t_pad, float* __restrict__ col_part,
+                                                   const float* const* __restrict__ tab) {
   __shared__ float sh[4][256];
+  if (tab) {
+    v = tab[0];
+    W = tab[1];
+  }
   const int t = blockIdx.x;
+  const int cc = blockIdx.y;
   float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
   if (t < t_count) {
-    for (int64_t i = threadIdx.x; i < N; i += 256) {
+    const int64_t i1 = min(N, (int64_t)(cc + 1) * COLSCALE_ATOMS);
+    for (int64_t i = (int64_t)cc * COLSCALE_ATOMS + threadIdx.x; i < i1; i += 256) {
       const float* vp = v + ((int64_t)t * N + i) * 3;
       const float* Wp = W + ((int64_t)t * N + i) * 9;
       const float sm = sqrt_m[i], ism = inv_sqrt_m[i];
@@ -169,16 +179,15 @@ __global__ void __launch_bounds__(256) k_col_scale(const float* __restrict__ v, 
       for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = fmaxf(sh[c][threadIdx.x], sh[c][threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x < 4) {
-    const float mx = sh[threadIdx.x][0];
-    col_scale[threadIdx.x * t_pad + t] = mx > 0.f ? mx / FP8_MAX : 1.f;
-  }
+  if (threadIdx.x < 4) col_part[((int64_t)cc * 4 + threadIdx.x) * t_pad + t] = sh[threadIdx.x][0];
 }
 
 hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const float* sqrt_m,
-                            const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_scale) {
-  hipLaunchKernelGGL(k_col_scale, dim3((unsigned)t_pad), dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad,
-                     col_scale);
+                            const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_part,
+                            const float* const* tab) {
+  const int n_cc = (int)((N + COLSCALE_ATOMS - 1) / COLSCALE_ATOMS);
+  hipLaunchKernelGGL(k_col_scale, dim3((unsigned)t_pad, (unsigned)n_cc), dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m,
+                     N, t_count, t_pad, col_part, tab);
   return hipGetLastError();
 }
 
@@ -191,13 +200,20 @@ constexpr int PREP_T = 32;
 constexpr int PREP_K = 3 * ATOMS_PER_PREP;   // 96 dofs
 
 template <int MODE>   // 0 = plain, 1 = FP32, 2 = BF16 hi/lo, 3 = e4m3, 4 = e4m3 hi/lo fragments
-__global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v, const float* __restrict__ W,
+__global__ void __launch_bounds__(256) k_input_prep(const float* v, const float* W,
                                                     const float* __restrict__ sqrt_m,
                                                     const float* __restrict__ inv_sqrt_m, int64_t N,
                                                     int t_count, int t_pad, void* __restrict__ B,
                                                     int64_t K_pad, double* __restrict__ jt_part,
-                                                    const float* __restrict__ col_scale) {
+                                                    float* __restrict__ col_scale,
+                                                    const float* __restrict__ col_part,
+                                                    const float* const* __restrict__ tab) {
   __shared__ float ch[4][PREP_T][PREP_K + 4];
+  __shared__ float csc[4][PREP_T];
+  if (tab) {   // inputs named through device memory (graph replay)
+    v = tab[0];
+    W = tab[1];
+  }
   const int tid = threadIdx.x;
   const int chunk = blockIdx.x;
   const int n_chunks = gridDim.x;
@@ -282,7 +298,20 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v,
       Bp[(cb * KC + kc) * 64 + tt + 32 * h] = o;
     }
   } else if constexpr (MODE == 3 || MODE == 4) {
-    // e4m3 fragments: piece = (c, 16-dof group g, column tt) of B/s_{c,t}
+    // e4m3 fragments: piece = (c, 16-dof group g, column tt) of B/s_{c,t}.
+    // The scales of this tile's steps from the atom-chunk maxima (the
+    // work-groups of chunk 0 also publish them for the contraction epilogue).
+    if (tid < 4 * PREP_T) {
+      const int c = tid / PREP_T, tt = tid % PREP_T;
+      const int tg = tb * PREP_T + tt;
+      const int n_cc = (int)((N + COLSCALE_ATOMS - 1) / COLSCALE_ATOMS);
+      float mx = 0.f;
+      for (int cc = 0; cc < n_cc; ++cc) mx = fmaxf(mx, col_part[((int64_t)cc * 4 + c) * t_pad + tg]);
+      const float sc = mx > 0.f ? mx / FP8_MAX : 1.f;
+      csc[c][tt] = sc;
+      if (chunk == 0) col_scale[c * t_pad + tg] = sc;
+    }
+    __syncthreads();
     constexpr bool X3 = (MODE == 4);
     const int ntb = t_pad / 32;
     const int64_t per_blk = (X3 ? 4 : 2) * K_pad;
@@ -293,7 +322,7 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v,
       const int c = (idx >> 5) / (PREP_K / 16);
       const int64_t k0 = k_base + 16 * g;
       const int64_t cb = (int64_t)c * ntb + tb;
-      const float inv = 1.f / col_scale[c * t_pad + tb * PREP_T + tt];
+      const float inv = 1.f / csc[c][tt];
       float x[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) x[e] = ch[c][tt][16 * g + e] * inv;
@@ -341,12 +370,13 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* __restrict__ v,
 
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
                              const float* sqrt_m, const float* inv_sqrt_m, int64_t N, int t_count, int t_pad,
-                             void* B, int64_t K_pad, double* jt_part, const float* col_scale) {
+                             void* B, int64_t K_pad, double* jt_part, float* col_scale,
+                             const float* col_part, const float* const* tab) {
   const int n_chunks = (int)((N + ATOMS_PER_PREP - 1) / ATOMS_PER_PREP);
   dim3 grid((unsigned)n_chunks, (unsigned)((t_pad + PREP_T - 1) / PREP_T));
 #define MHC_PREP(M)                                                                                          \
   hipLaunchKernelGGL(k_input_prep<M>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad, B, \
-                     K_pad, jt_part, col_scale)
+                     K_pad, jt_part, col_scale, col_part, tab)
   if (plain) MHC_PREP(0);
   else if (prec == PREC_FP32) MHC_PREP(1);
   else if (prec == PREC_BF16X3) MHC_PREP(2);

@@ -69,6 +69,7 @@ struct mhc_ctx {
   int32_t* d_bin_off = nullptr;
   float* d_rowscale = nullptr;  // e4m3: per-slot scale of E
   float* d_colscale = nullptr;  // e4m3: per-(channel, step) scale of the activations
+  float* d_colpart = nullptr;   // e4m3: per-atom-chunk maxima behind d_colscale
 
   // per-block work buffers
   int chunk = 0;       // steps per processed block
@@ -89,7 +90,6 @@ struct mhc_ctx {
   double* d_out = nullptr;
   float* d_ws = nullptr;      // partial tiles of the split and stream-K schedules
   int* d_tile_cnt = nullptr;  // arrival counters of the split schedule (zero between launches)
-  int64_t* d_t0 = nullptr;    // first step of the next block (grouped, graph-replayed pushes)
   int64_t ws_floats = 0;
   int n_cu = 256;
   int64_t n_samples = 0;
@@ -472,6 +472,10 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     void* pcs = nullptr;
     if ((st = dev_alloc(ctx, (size_t)4 * t_pad * 4, &pcs, "column scales"))) return st;
     ctx->d_colscale = reinterpret_cast<float*>(pcs);
+    const int64_t n_cc = (N + COLSCALE_ATOMS - 1) / COLSCALE_ATOMS;
+    void* pcp = nullptr;
+    if ((st = dev_alloc(ctx, (size_t)n_cc * 4 * t_pad * 4, &pcp, "column maxima"))) return st;
+    ctx->d_colpart = reinterpret_cast<float*>(pcp);
   }
   const size_t acc_doubles = (size_t)(4 * nb * 3 + 4 * 3);
   if ((st = dev_alloc(ctx, acc_doubles * 8, &pacc, "HNEMA sums"))) return st;
@@ -492,9 +496,6 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     HIP_TRY(hipMemsetAsync(pring, 0, (size_t)ring_len * 3 * 8, ctx->stream), "zero ring");
   }
   if ((st = dev_alloc(ctx, out_doubles * 8, &pout, "read-out"))) return st;
-  void* pt0 = nullptr;
-  if ((st = dev_alloc(ctx, 8, &pt0, "step counter"))) return st;
-  ctx->d_t0 = reinterpret_cast<int64_t*>(pt0);
   if (c.t_block > 1) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
@@ -563,22 +564,27 @@ mhc_status mhc_reset(mhc_ctx* ctx) {
 }
 
 // Front of a block: activation scales (e4m3), B operand, per-chunk Eq. 10 partials.
-static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int t_count) {
+// With tab != NULL the input pointers are read from device memory (tab[0] =
+// v, tab[1] = W) when the kernels run.
+static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int t_count,
+                              const float* const* tab = nullptr) {
   const auto& c = ctx->cfg;
   if (ctx->d_colscale)
     HIP_TRY(launch_col_scale(ctx->stream, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count, ctx->t_pad,
-                             ctx->d_colscale),
+                             ctx->d_colpart, tab),
             "column scales");
   HIP_TRY(launch_input_prep(ctx->stream, c.precision, c.t_block == 1 ? 1 : 0, v, W, ctx->d_sqrtm, ctx->d_isqrtm,
-                            ctx->N, t_count, ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt, ctx->d_colscale),
+                            ctx->N, t_count, ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt, ctx->d_colscale,
+                            ctx->d_colpart, tab),
           "input prep");
   return MHC_OK;
 }
 
 // Back of a block: per-step totals, bins + float64 accumulation, GKMA update.
-// With t0_dev the block's first step index is read from device memory (and
-// advanced here), so a captured graph can be replayed block after block.
-static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, int64_t* t0_dev) {
+// With t0_dev the block's first step index is read from device memory when
+// the kernels run (the group's input table), so a captured graph can be
+// replayed block after block.
+static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64_t* t0_dev) {
   const auto& c = ctx->cfg;
   const bool gk = c.methods & MHC_GKMA;
   const int64_t ld = ctx->t_pad;
@@ -608,7 +614,6 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, int64_t* t0
                         ctx->n_samples, ctx->d_csum, ctx->d_ccomp, t0_dev),
             "correlation");
   }
-  if (t0_dev) HIP_TRY(launch_advance(ctx->stream, t0_dev, t_count), "advance");
   return MHC_OK;
 }
 
@@ -876,6 +881,8 @@ mhc_status mhc_device_bytes(mhc_ctx* ctx, int64_t* bytes) {
 // Several systems pushed together: per block, the fronts of all systems, one
 // persistent contraction over all their tiles (largest first), and the
 // backs of all systems, optionally captured once as a HIP graph and replayed.
+constexpr int TAB_RING = 8;   // pinned input-table slots of a group
+
 struct mhc_group {
   std::vector<mhc_ctx*> sys;
   int device = 0;
@@ -893,7 +900,15 @@ struct mhc_group {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string err;
-  int64_t* h_t0 = nullptr;     // pinned staging for the device step counters
+  // Block table: words 3i, 3i+1, 3i+2 = v, W and first step index of system
+  // i for the block the queued work will process.  Each block's table is
+  // written to its own pinned ring slot, copied to the device in stream
+  // order, and the slot is reused only after that copy has completed (event).
+  uint64_t* d_tab = nullptr;
+  uint64_t* h_tab = nullptr;                // [TAB_RING][3n]
+  hipEvent_t tab_ev[TAB_RING] = {};
+  bool tab_busy[TAB_RING] = {};
+  int tab_pos = 0;
   bool timing = false;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
@@ -964,8 +979,10 @@ mhc_status group_contract(mhc_group* g) {
 
 // The whole block (inputs already staged in each context's buffers).
 mhc_status group_block(mhc_group* g, bool timed) {
-  for (auto* c : g->sys) {
-    mhc_status st = block_front(c, c->d_v, c->d_W, g->t_block);
+  for (size_t i = 0; i < g->sys.size(); ++i) {
+    mhc_ctx* c = g->sys[i];
+    mhc_status st =
+        block_front(c, nullptr, nullptr, g->t_block, reinterpret_cast<const float* const*>(g->d_tab + 3 * i));
     if (st) return gfail(g, st, c->err);
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -985,7 +1002,8 @@ mhc_status group_block(mhc_group* g, bool timed) {
   if (timed) GHIP_TRY(hipEventRecord(e1, g->stream), "event record");
   for (size_t i = 0; i < g->sys.size(); ++i) {
     mhc_ctx* c = g->sys[i];
-    if ((st = block_back(c, g->t_block, g->n_parts[i], c->d_t0))) return gfail(g, st, c->err);
+    if ((st = block_back(c, g->t_block, g->n_parts[i], reinterpret_cast<const int64_t*>(g->d_tab + 3 * i + 2))))
+      return gfail(g, st, c->err);
   }
   return MHC_OK;
 }
@@ -1002,8 +1020,10 @@ mhc_status autotune(mhc_group* g) {
       return build_queue(g);
     }
   }
-  for (auto* c : g->sys) {
-    mhc_status st = block_front(c, c->d_v, c->d_W, g->t_block);
+  for (size_t i = 0; i < g->sys.size(); ++i) {
+    mhc_ctx* c = g->sys[i];
+    mhc_status st =
+        block_front(c, nullptr, nullptr, g->t_block, reinterpret_cast<const float* const*>(g->d_tab + 3 * i));
     if (st) return gfail(g, st, c->err);
   }
   hipEvent_t a, b;
@@ -1076,7 +1096,9 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
   g->shape = (g->ntb % 4 == 0) ? 0 : (g->ntb % 2 == 0 ? 1 : 2);
   auto cleanup = [&](mhc_status st) {
     for (auto& a : g->allocs) (void)hipFree(a.p);
-    if (g->h_t0) (void)hipHostFree(g->h_t0);
+    if (g->h_tab) (void)hipHostFree(g->h_tab);
+    for (auto e : g->tab_ev)
+      if (e) (void)hipEventDestroy(e);
     delete g;
     return st;
   };
@@ -1090,8 +1112,14 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
   g->allocs.push_back({pt, (size_t)max_tiles * sizeof(GroupTile)});
   if (hipMalloc(&pc, 256) != hipSuccess) return cleanup(MHC_ERR_OOM);
   g->allocs.push_back({pc, 256});
-  if (hipHostMalloc(reinterpret_cast<void**>(&g->h_t0), n * sizeof(int64_t), 0) != hipSuccess)
+  void* ptab = nullptr;
+  if (hipMalloc(&ptab, 3 * n * sizeof(uint64_t)) != hipSuccess) return cleanup(MHC_ERR_OOM);
+  g->allocs.push_back({ptab, 3 * n * sizeof(uint64_t)});
+  g->d_tab = reinterpret_cast<uint64_t*>(ptab);
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->h_tab), TAB_RING * 3 * n * sizeof(uint64_t), 0) != hipSuccess)
     return cleanup(MHC_ERR_OOM);
+  for (int k = 0; k < TAB_RING; ++k)
+    if (hipEventCreateWithFlags(&g->tab_ev[k], hipEventDisableTiming) != hipSuccess) return cleanup(MHC_ERR_HIP);
   g->d_geom = reinterpret_cast<GemmGeom*>(pg);
   g->d_tiles = reinterpret_cast<GroupTile*>(pt);
   g->d_counter = reinterpret_cast<int*>(pc);
@@ -1108,7 +1136,9 @@ mhc_status mhc_group_destroy(mhc_group* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   for (auto e : g->ev) (void)hipEventDestroy(e);
   for (auto& a : g->allocs) (void)hipFree(a.p);
-  if (g->h_t0) (void)hipHostFree(g->h_t0);
+  if (g->h_tab) (void)hipHostFree(g->h_tab);
+  for (auto e : g->tab_ev)
+    if (e) (void)hipEventDestroy(e);
   delete g;
   return MHC_OK;
 }
@@ -1130,18 +1160,31 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
   GHIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const int T = g->t_block;
-  // device step counters <- host counts (once per call)
-  for (int i = 0; i < n; ++i) g->h_t0[i] = g->sys[i]->n_samples;
-  for (int i = 0; i < n; ++i)
-    GHIP_TRY(hipMemcpyAsync(g->sys[i]->d_t0, &g->h_t0[i], 8, hipMemcpyHostToDevice, g->stream), "step counter");
-  GHIP_TRY(hipStreamSynchronize(g->stream), "step counter sync");
   int32_t s0 = 0;
   for (; s0 + T <= n_steps; s0 += T) {
+    // device inputs are read in place; host inputs go through the staging buffers
+    const int k = g->tab_pos;
+    g->tab_pos = (g->tab_pos + 1) % TAB_RING;
+    if (g->tab_busy[k]) GHIP_TRY(hipEventSynchronize(g->tab_ev[k]), "input table slot");
+    uint64_t* tab = g->h_tab + (size_t)k * 3 * n;
     for (int i = 0; i < n; ++i) {
       mhc_ctx* c = g->sys[i];
-      GHIP_TRY(hipMemcpyAsync(c->d_v, v[i] + (int64_t)s0 * c->N * 3, (size_t)T * c->N * 3 * 4, kind, g->stream), "v");
-      GHIP_TRY(hipMemcpyAsync(c->d_W, W[i] + (int64_t)s0 * c->N * 9, (size_t)T * c->N * 9 * 4, kind, g->stream), "W");
+      const float* vi = v[i] + (int64_t)s0 * c->N * 3;
+      const float* Wi = W[i] + (int64_t)s0 * c->N * 9;
+      if (!on_device) {
+        GHIP_TRY(hipMemcpyAsync(c->d_v, vi, (size_t)T * c->N * 3 * 4, hipMemcpyHostToDevice, g->stream), "v");
+        GHIP_TRY(hipMemcpyAsync(c->d_W, Wi, (size_t)T * c->N * 9 * 4, hipMemcpyHostToDevice, g->stream), "W");
+        vi = c->d_v;
+        Wi = c->d_W;
+      }
+      tab[3 * i] = reinterpret_cast<uint64_t>(vi);
+      tab[3 * i + 1] = reinterpret_cast<uint64_t>(Wi);
+      tab[3 * i + 2] = (uint64_t)c->n_samples;
     }
+    GHIP_TRY(hipMemcpyAsync(g->d_tab, tab, 3 * n * sizeof(uint64_t), hipMemcpyHostToDevice, g->stream),
+             "block table");
+    GHIP_TRY(hipEventRecord(g->tab_ev[k], g->stream), "input table event");
+    g->tab_busy[k] = true;
     if (g->autotune && !g->tuned) {
       mhc_status st = autotune(g);
       if (st) return st;

@@ -30,6 +30,7 @@ constexpr int K_ALIGN = 128;    // K_pad multiple (one e4m3 stage is 128 dofs)
 constexpr int K_ALIGN_GEMV = 512;  // per-step path: rows of 128 units, 2 x 64 lanes per iteration pair
 constexpr int M_ALIGN = 256;    // M_pad multiple
 constexpr int ATOMS_PER_PREP = 32;  // atoms per input-prep work-group (96 dofs)
+constexpr int COLSCALE_ATOMS = 1024;  // atoms per work-group of the e4m3 column maxima
 
 enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1, PREC_FP8 = 2, PREC_FP8X3 = 3 };
 
@@ -47,18 +48,24 @@ hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64
 hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, int64_t n_rows, int64_t K,
                                   const int32_t* slot_of_row, void* E, int64_t K_pad, float* row_scale);
 
-// Per-(channel, step) scales of the e4m3 activations: col_scale[c][t_pad].
+// Maxima behind the per-(channel, step) scales of the e4m3 activations, per
+// chunk of COLSCALE_ATOMS atoms: col_part[chunk][c][t_pad] (the input prep
+// turns them into col_scale).  With tab != NULL, v and W are ignored and read
+// from tab[0], tab[1] (device).
 hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const float* sqrt_m,
-                            const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_scale);
+                            const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_part,
+                            const float* const* tab);
 
 // Input preparation for one block of t_pad columns (t_count real steps):
 // B operand in the layout of `prec` (or plain when plain != 0) and the
 // per-atom-chunk partial total currents jt_part[t][chunk][3] (float64).
-// e4m3 precisions divide by col_scale (from launch_col_scale).
+// e4m3 precisions divide by col_scale[c][t] = max over chunks of col_part
+// / 448 (1 for a zero column), which the chunk-0 work-groups also store in
+// col_scale for the contraction epilogue.  tab as for launch_col_scale.
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
                              const float* sqrt_m, const float* inv_sqrt_m, int64_t N,
                              int t_count, int t_pad, void* B, int64_t K_pad, double* jt_part,
-                             const float* col_scale);
+                             float* col_scale, const float* col_part, const float* const* tab);
 
 // Per-step matrix-vector path (FP32): for steps t = 0..n_steps-1 of a plain
 // B buffer, J_n^mu = Xdot_n A_n^mu for every slot.  Output either
@@ -138,8 +145,6 @@ hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int 
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
                        const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
                        const int64_t* t0_dev);
-// *t0 += by (advances a device-resident step counter after a block).
-hipError_t launch_advance(hipStream_t s, int64_t* t0, int64_t by);
 
 // Read-out of the GKMA accumulators: C = (csum + ccomp) / (S - tau) (zero when
 // S <= tau) and its trapezoid running integral with step dt, written as

@@ -57,12 +57,14 @@ def _read(h, methods):
     return out
 
 
-@pytest.mark.parametrize("prec,graph,autotune", [(BF16X3, True, False), (BF16X3, True, True), (FP32, False, True),
-                                                 (FP8X3, True, True)])
-def test_group_matches_single_pushes(cases, prec, graph, autotune):
+@pytest.mark.parametrize("prec,graph,autotune,host", [(BF16X3, True, False, False), (BF16X3, True, True, False),
+                                                      (FP32, False, True, False), (FP8X3, True, True, False),
+                                                      (BF16X3, True, False, True)])
+def test_group_matches_single_pushes(cases, prec, graph, autotune, host):
+    """host: the group is fed host arrays (staged copies), the single systems device tensors."""
     import torch
     from paper_2102_03691_amd import ModalGroup
-    announce(f"group prec={prec} graph={graph} autotune={autotune}")
+    announce(f"group prec={prec} graph={graph} autotune={autotune} host={host}")
     stream = torch.cuda.Stream()
     handle = stream.cuda_stream
     grouped = [_ctx(c, m, prec, handle) for c, (_, m) in zip(cases, SYSTEMS)]
@@ -72,7 +74,10 @@ def test_group_matches_single_pushes(cases, prec, graph, autotune):
     torch.cuda.synchronize()
     s0 = 0
     for n in SPLITS:
-        grp.push([v[s0:s0 + n] for v, _ in dev], [W[s0:s0 + n] for _, W in dev])
+        if host:
+            grp.push([c.v[s0:s0 + n] for c in cases], [c.W[s0:s0 + n] for c in cases])
+        else:
+            grp.push([v[s0:s0 + n] for v, _ in dev], [W[s0:s0 + n] for _, W in dev])
         for h, (v, W) in zip(single, dev):
             h.push(v[s0:s0 + n], W[s0:s0 + n])
         s0 += n
@@ -87,7 +92,7 @@ def test_group_matches_single_pushes(cases, prec, graph, autotune):
                 else:
                     assert rel(a[k], b[k]) <= 1e-5, (i, k, s0)
     info = grp.info()
-    log(f"group_p{prec}_g{int(graph)}_a{int(autotune)}", **info)
+    log(f"group_p{prec}_g{int(graph)}_a{int(autotune)}_h{int(host)}", **info)
     # oracle parity of every system after the whole run
     tol = 1e-2 if prec == FP8X3 else TOL[prec]
     for i, (case, (_, methods)) in enumerate(zip(cases, SYSTEMS)):
