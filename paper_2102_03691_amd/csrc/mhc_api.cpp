@@ -882,6 +882,7 @@ mhc_status mhc_device_bytes(mhc_ctx* ctx, int64_t* bytes) {
 // persistent contraction over all their tiles (largest first), and the
 // backs of all systems, optionally captured once as a HIP graph and replayed.
 constexpr int TAB_RING = 8;   // pinned input-table slots of a group
+constexpr int NAUX = 4;       // side streams of a group (the device has 4 hardware queues per process)
 
 struct mhc_group {
   std::vector<mhc_ctx*> sys;
@@ -906,6 +907,11 @@ struct mhc_group {
   // order, and the slot is reused only after that copy has completed (event).
   uint64_t* d_tab = nullptr;
   uint64_t* h_tab = nullptr;                // [TAB_RING][3n]
+  // Per-system front and back kernels fan out over NAUX streams (joined
+  // before and after the shared contraction), so small systems' kernels run
+  // side by side instead of one after another.
+  hipStream_t aux[NAUX] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[NAUX] = {};
   hipEvent_t tab_ev[TAB_RING] = {};
   bool tab_busy[TAB_RING] = {};
   int tab_pos = 0;
@@ -977,14 +983,36 @@ mhc_status group_contract(mhc_group* g) {
   return MHC_OK;
 }
 
-// The whole block (inputs already staged in each context's buffers).
-mhc_status group_block(mhc_group* g, bool timed) {
-  for (size_t i = 0; i < g->sys.size(); ++i) {
+// Run fn(i) for every system with the system's work queued on side stream
+// i % NAUX, forked from and joined back into the group stream.
+template <class F>
+mhc_status fan_out(mhc_group* g, F&& fn) {
+  GHIP_TRY(hipEventRecord(g->fork_ev, g->stream), "fork");
+  for (int k = 0; k < NAUX; ++k) GHIP_TRY(hipStreamWaitEvent(g->aux[k], g->fork_ev, 0), "fork wait");
+  mhc_status st = MHC_OK;
+  for (size_t i = 0; i < g->sys.size() && !st; ++i) {
     mhc_ctx* c = g->sys[i];
-    mhc_status st =
-        block_front(c, nullptr, nullptr, g->t_block, reinterpret_cast<const float* const*>(g->d_tab + 3 * i));
-    if (st) return gfail(g, st, c->err);
+    hipStream_t own = c->stream;
+    c->stream = g->aux[i % NAUX];
+    st = fn(i);
+    c->stream = own;
   }
+  for (int k = 0; k < NAUX; ++k) {
+    GHIP_TRY(hipEventRecord(g->join_ev[k], g->aux[k]), "join");
+    GHIP_TRY(hipStreamWaitEvent(g->stream, g->join_ev[k], 0), "join wait");
+  }
+  return st;
+}
+
+// The whole block (inputs named by the block table).
+mhc_status group_block(mhc_group* g, bool timed) {
+  mhc_status st = fan_out(g, [&](size_t i) {
+    mhc_ctx* c = g->sys[i];
+    mhc_status s2 =
+        block_front(c, nullptr, nullptr, g->t_block, reinterpret_cast<const float* const*>(g->d_tab + 3 * i));
+    return s2 ? gfail(g, s2, c->err) : MHC_OK;
+  });
+  if (st) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     while (g->ev_used + 2 > g->ev.size()) {
@@ -997,15 +1025,13 @@ mhc_status group_block(mhc_group* g, bool timed) {
     g->ev_used += 2;
     GHIP_TRY(hipEventRecord(e0, g->stream), "event record");
   }
-  mhc_status st = group_contract(g);
-  if (st) return st;
+  if ((st = group_contract(g))) return st;
   if (timed) GHIP_TRY(hipEventRecord(e1, g->stream), "event record");
-  for (size_t i = 0; i < g->sys.size(); ++i) {
+  return fan_out(g, [&](size_t i) {
     mhc_ctx* c = g->sys[i];
-    if ((st = block_back(c, g->t_block, g->n_parts[i], reinterpret_cast<const int64_t*>(g->d_tab + 3 * i + 2))))
-      return gfail(g, st, c->err);
-  }
-  return MHC_OK;
+    mhc_status s2 = block_back(c, g->t_block, g->n_parts[i], reinterpret_cast<const int64_t*>(g->d_tab + 3 * i + 2));
+    return s2 ? gfail(g, s2, c->err) : MHC_OK;
+  });
 }
 
 // Time every valid tile shape on the staged block and keep the fastest.
@@ -1099,6 +1125,11 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
     if (g->h_tab) (void)hipHostFree(g->h_tab);
     for (auto e : g->tab_ev)
       if (e) (void)hipEventDestroy(e);
+    if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
+    for (int k = 0; k < NAUX; ++k) {
+      if (g->join_ev[k]) (void)hipEventDestroy(g->join_ev[k]);
+      if (g->aux[k]) (void)hipStreamDestroy(g->aux[k]);
+    }
     delete g;
     return st;
   };
@@ -1120,6 +1151,11 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
     return cleanup(MHC_ERR_OOM);
   for (int k = 0; k < TAB_RING; ++k)
     if (hipEventCreateWithFlags(&g->tab_ev[k], hipEventDisableTiming) != hipSuccess) return cleanup(MHC_ERR_HIP);
+  if (hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming) != hipSuccess) return cleanup(MHC_ERR_HIP);
+  for (int k = 0; k < NAUX; ++k) {
+    if (hipStreamCreateWithFlags(&g->aux[k], hipStreamNonBlocking) != hipSuccess) return cleanup(MHC_ERR_HIP);
+    if (hipEventCreateWithFlags(&g->join_ev[k], hipEventDisableTiming) != hipSuccess) return cleanup(MHC_ERR_HIP);
+  }
   g->d_geom = reinterpret_cast<GemmGeom*>(pg);
   g->d_tiles = reinterpret_cast<GroupTile*>(pt);
   g->d_counter = reinterpret_cast<int*>(pc);
@@ -1139,6 +1175,12 @@ mhc_status mhc_group_destroy(mhc_group* g) {
   if (g->h_tab) (void)hipHostFree(g->h_tab);
   for (auto e : g->tab_ev)
     if (e) (void)hipEventDestroy(e);
+  if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
+  for (int k = 0; k < NAUX; ++k) {
+    if (g->aux[k]) (void)hipStreamSynchronize(g->aux[k]);
+    if (g->join_ev[k]) (void)hipEventDestroy(g->join_ev[k]);
+    if (g->aux[k]) (void)hipStreamDestroy(g->aux[k]);
+  }
   delete g;
   return MHC_OK;
 }
