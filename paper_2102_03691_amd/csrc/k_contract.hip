@@ -307,10 +307,18 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
   // address registers.
   static_assert(SU == 256 && A_PER_THR == RBW, "one A unit per thread per row block and stage");
   const gu32x4* Ebase = (const gu32x4*)g.E + rb0 * per_blk;
+  // E is streamed once (non-temporal) unless sibling t-tiles of the same
+  // rows run alongside and re-read it: then it is kept in L2 for them.
+  const bool e_keep = g.n_ntiles > 1;
   auto load_A = [&](int s, u32x4* dst) {
+    if (e_keep) {
 #pragma unroll
-    for (int q = 0; q < A_PER_THR; ++q)
-      dst[q] = __builtin_nontemporal_load(Ebase + ((int64_t)q * per_blk + (int64_t)s * SU) + tid);
+      for (int q = 0; q < A_PER_THR; ++q) dst[q] = Ebase[((int64_t)q * per_blk + (int64_t)s * SU) + tid];
+    } else {
+#pragma unroll
+      for (int q = 0; q < A_PER_THR; ++q)
+        dst[q] = __builtin_nontemporal_load(Ebase + ((int64_t)q * per_blk + (int64_t)s * SU) + tid);
+    }
   };
   auto store_A = [&](int buf, const u32x4* src) {
 #pragma unroll
