@@ -254,6 +254,11 @@ mhc_status mhc_kernel_timing(mhc_ctx *ctx, int64_t *launches, double *total_ms);
 /* Bytes of device memory held by the context (basis, buffers, accumulators). */
 mhc_status mhc_device_bytes(mhc_ctx *ctx, int64_t *bytes);
 
+/* Work split the last T-batched contraction of this context actually used
+ * (MHC_SCHED_TILES, _STREAMK or _SPLIT; what AUTO resolved to), or 0 when no
+ * batched block has run yet (also for t_block = 1).  Errors: INVALID_ARG. */
+mhc_status mhc_last_schedule(mhc_ctx *ctx, int32_t *schedule);
+
 /* ------------------------------------------------------- grouped systems
  * Many independent systems (uneven sizes, HNEMA and GKMA mixed) advanced
  * together: per block of t_block steps the input preparation of every

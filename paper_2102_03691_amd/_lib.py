@@ -74,6 +74,7 @@ def library():
         "mhc_set_timing": (i32, [vp, C.c_int]),
         "mhc_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
         "mhc_device_bytes": (i32, [vp, P(i64)]),
+        "mhc_last_schedule": (i32, [vp, P(i32)]),
         "mhc_group_create": (i32, [P(vp), i32, i32, P(vp)]),
         "mhc_group_destroy": (i32, [vp]),
         "mhc_group_last_error": (C.c_char_p, [vp]),
@@ -264,6 +265,12 @@ class ModalHC:
         b = C.c_int64()
         self._check(self._lib.mhc_device_bytes(self._h, C.byref(b)), "device_bytes")
         return b.value
+
+    def last_schedule(self):
+        """Work split of the last T-batched contraction (SCHED_TILES/_STREAMK/_SPLIT; 0 before any)."""
+        s = C.c_int32()
+        self._check(self._lib.mhc_last_schedule(self._h, C.byref(s)), "last_schedule")
+        return s.value
 
 
 class ModalGroup:

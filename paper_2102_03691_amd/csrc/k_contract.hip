@@ -729,7 +729,7 @@ static bool plan_split(int64_t n_tiles, int S, int G, int64_t slot_floats, int64
 template <int PREC, int WM, int WT, int MB>
 static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B, float* out, float* ws,
                                     int64_t ws_floats, int* tile_cnt, GemmGeom g, int n_mtiles, int n_cu,
-                                    int sched) {
+                                    int sched, int* used) {
   constexpr int NREG = MB * 4 * 16;
   const int64_t n_tiles = (int64_t)n_mtiles * g.n_ntiles;
   g.total_iters = n_tiles * g.n_stages;
@@ -744,6 +744,7 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
                    sched == MHC_SCHED_AUTO ? 0.05 : 0.0, &sp)) {
       sp.cnt = tile_cnt;
       hipLaunchKernelGGL((k_gemm_split<PREC, WM, WT, MB>), dim3((unsigned)n_cu), dim3(256), 0, s, ws, g, sp);
+      *used = MHC_SCHED_SPLIT;
       return hipGetLastError();
     }
   }
@@ -765,6 +766,7 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
     }
   }
   hipLaunchKernelGGL((k_gemm<PREC, WM, WT, MB>), dim3((unsigned)G), dim3(256), 0, s, ws, g);
+  *used = sk ? MHC_SCHED_STREAMK : MHC_SCHED_TILES;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !sk) return e;
   hipLaunchKernelGGL((k_gemm_fixup<PREC, WM, WT, MB>), dim3((unsigned)n_tiles), dim3(256), 0, s, ws, g);
@@ -775,7 +777,7 @@ template <int PREC>
 static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t K_pad, int ntb,
                                    float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
                                    int* tile_cnt, int n_cu, int sched, const float* row_scale,
-                                   const float* col_scale) {
+                                   const float* col_scale, int* used) {
   GemmGeom g{};
   g.K_pad = K_pad;
   g.M_pad = M_pad;
@@ -789,23 +791,27 @@ static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, 
     // 128 slots x 4 t-blocks per tile
     g.n_ntiles = ntb / 4;
     *n_parts = g.n_ntiles;
-    return launch_gemm_shape<PREC, 1, 4, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 128), n_cu, sched);
+    return launch_gemm_shape<PREC, 1, 4, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 128), n_cu, sched,
+                                                   used);
   } else if (ntb % 2 == 0) {
     g.n_ntiles = ntb / 2;
     *n_parts = g.n_ntiles;
-    return launch_gemm_shape<PREC, 2, 2, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched);
+    return launch_gemm_shape<PREC, 2, 2, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched,
+                                                   used);
   }
   g.n_ntiles = ntb;
   *n_parts = g.n_ntiles;
-  return launch_gemm_shape<PREC, 4, 1, 2>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched);
+  return launch_gemm_shape<PREC, 4, 1, 2>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched,
+                                                   used);
 }
 
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
                        int ntb, float* out, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
-                       int* tile_cnt, int n_cu, int sched, const float* row_scale, const float* col_scale) {
+                       int* tile_cnt, int n_cu, int sched, const float* row_scale, const float* col_scale,
+                       int* used) {
 #define MHC_GEMM(P) \
   launch_gemm_prec<P>(s, E, B, M_pad, K_pad, ntb, out, layout_g, n_parts, ws, ws_floats, tile_cnt, n_cu, sched, \
-                      row_scale, col_scale)
+                      row_scale, col_scale, used)
   switch (prec) {
     case PREC_BF16X3: return MHC_GEMM(PREC_BF16X3);
     case PREC_FP8: return MHC_GEMM(PREC_FP8);

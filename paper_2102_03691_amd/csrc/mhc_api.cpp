@@ -90,6 +90,7 @@ struct mhc_ctx {
   double* d_out = nullptr;
   float* d_ws = nullptr;      // partial tiles of the split and stream-K schedules
   int* d_tile_cnt = nullptr;  // arrival counters of the split schedule (zero between launches)
+  int last_sched = 0;         // schedule the last batched contraction used (MHC_SCHED_*; 0 = none yet)
   int64_t ws_floats = 0;
   int n_cu = 256;
   int64_t n_samples = 0;
@@ -651,7 +652,7 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
   } else {
     HIP_TRY(launch_gemm(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
                         gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->d_tile_cnt, ctx->n_cu, c.schedule,
-                        ctx->d_rowscale, ctx->d_colscale),
+                        ctx->d_rowscale, ctx->d_colscale, &ctx->last_sched),
             "batched contraction");
   }
   if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
@@ -872,6 +873,12 @@ mhc_status mhc_device_bytes(mhc_ctx* ctx, int64_t* bytes) {
   if (st) return st;
   if (!bytes) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL bytes");
   *bytes = ctx->bytes;
+  return MHC_OK;
+}
+
+mhc_status mhc_last_schedule(mhc_ctx* ctx, int32_t* schedule) {
+  if (!ctx || !schedule) return MHC_ERR_INVALID_ARG;
+  *schedule = ctx->last_sched;
   return MHC_OK;
 }
 

@@ -117,7 +117,7 @@ hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad,
                        int64_t K_pad, int ntb, float* out, int layout_g, int* n_parts, float* ws,
                        int64_t ws_floats, int* tile_cnt, int n_cu, int sched, const float* row_scale,
-                       const float* col_scale);
+                       const float* col_scale, int* used);
 
 // Bin reduction + float64 accumulation.
 //   HNEMA-only: part sums in[n_parts][M_pad][3] -> hsum/hcomp[nb][3] (Neumaier)

@@ -226,3 +226,18 @@ def test_split_schedule(dims, prec, T, n_steps):
     assert np.array_equal(a["hnema"], b["hnema"])
     tol = TOL.get(prec, 1e-2)
     assert e <= tol and et <= tol
+
+
+def test_last_schedule_reports_the_split_used(small):
+    """mhc_last_schedule tells which work split ran; on the 6x6x5 case (3 tiles
+    of 20 k-stages on a 256-CU device) AUTO resolves to the lockstep split."""
+    announce("last schedule query")
+    for asked, expect in ((1, 1), (2, 2), (3, 3), (0, 3)):
+        got = run_library(small, 23, HNEMA, BF16X3, 64, schedule=asked, keep=True)
+        h = got.pop("handle")
+        assert h.last_schedule() == expect, (asked, h.last_schedule())
+        h.close()
+    got = run_library(small, 23, HNEMA, FP32, 1, keep=True)
+    h = got.pop("handle")
+    assert h.last_schedule() == 0
+    h.close()
