@@ -1,0 +1,138 @@
+"""Pins of the SHC oracle (Sec. II.C, Eqs. 20-23) against the hand-worked
+fixture, brute force, the Eq. 10 sum rule and closed forms of the transform.
+Mutation tests plant a plausible mistake in a copy of the oracle and show
+that a pin rejects it."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import shc as osh
+from tests import _golden
+
+
+def _fixture():
+    g = _golden.read("shc_two_atoms.txt")
+    S = 3
+    v = np.zeros((S, 2, 3))
+    W = np.zeros((S, 2, 3, 3))
+    W[:, 0, 0, 1] = [float(x) for x in g["W0xy"][0]]
+    v[:, 0, 0] = [float(x) for x in g["v0x"][0]]
+    v[:, 0, 1] = [float(x) for x in g["v0y"][0]]
+    W[:, 1, 2, 0] = [float(x) for x in g["W1zx"][0]]
+    v[:, 1, 0] = [float(x) for x in g["v1x"][0]]
+    K = np.array([[float(x) for x in g[k][0]] for k in ("Kx", "Ky", "Kz")]).T      # [tau, mu]
+    spec = {k: np.array([float(x) for x in g[k][0]]) for k in ("spec_w0", "spec_wpi2", "spec_hann_w0")}
+    return v, W, K, spec
+
+
+def test_golden_correlation_and_transform():
+    v, W, K, spec = _fixture()
+    got = oracle.shc_correlation(v, W, 3)
+    assert np.allclose(got, K, rtol=0, atol=1e-15)
+    assert np.allclose(oracle.shc_spectrum(got, 1.0, [0.0])[0], spec["spec_w0"], atol=1e-15)
+    assert np.allclose(oracle.shc_spectrum(got, 1.0, [math.pi / 2])[0], spec["spec_wpi2"], atol=1e-14)
+    assert np.allclose(oracle.shc_spectrum(got, 1.0, [0.0], window=True)[0], spec["spec_hann_w0"], atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_brute_force_loops(seed):
+    rng = np.random.default_rng(seed)
+    S, N, L = 6, 3, 8            # more lags than samples: the last ones have no origin
+    v = rng.standard_normal((S, N, 3))
+    W = rng.standard_normal((S, N, 3, 3))
+    a = oracle.shc_correlation(v, W, L)
+    b = osh.shc_correlation_loops(v.tolist(), W.tolist(), L)
+    assert np.allclose(a, b, rtol=1e-13, atol=1e-15)
+    assert np.all(a[S:] == 0.0)
+
+
+def test_zero_lag_is_the_eq10_current_time_average():
+    """The paper: Eq. 21 reduces to the heat current of Eq. 10 at t = 0."""
+    rng = np.random.default_rng(3)
+    S, N = 40, 17
+    v = rng.standard_normal((S, N, 3))
+    W = rng.standard_normal((S, N, 3, 3))
+    K = oracle.shc_correlation(v, W, 5)
+    Jt = oracle.total_heat_current(v, W)                 # [S, 3], Eq. 10 per step
+    assert np.allclose(K[0], Jt.mean(axis=0), rtol=1e-13, atol=1e-14)
+
+
+def test_lag_direction_pulse():
+    """A virial at step 2 and a velocity at step 5 correlate at lag 3 only."""
+    S, N = 8, 1
+    v = np.zeros((S, N, 3))
+    W = np.zeros((S, N, 3, 3))
+    W[2, 0, 1, 2] = 1.5          # W^{yz}
+    v[5, 0, 2] = 2.0             # v^z
+    K = oracle.shc_correlation(v, W, 6)
+    expect = np.zeros((6, 3))
+    expect[3, 1] = 1.5 * 2.0 / (S - 3)
+    assert np.array_equal(K, expect)
+
+
+def test_transform_of_a_delta_is_flat():
+    K = np.zeros((9, 3))
+    K[0] = [1.0, -2.0, 0.5]
+    om = np.linspace(0.0, 3.0, 7)
+    out = oracle.shc_spectrum(K, 0.5, om)
+    assert np.allclose(out, 0.5 * K[0][None, :], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [2, 5, 64])
+def test_transform_of_a_constant_closed_form(n):
+    """K = 1 on n lags: trapezoid of the even extension = Dirichlet kernel minus
+    the half-weighted end points, dt [sin((n - 1/2) x) / sin(x / 2) - cos((n - 1) x)],
+    x = omega dt; at omega = 0 it is 2 (n - 1) dt.  With the Hann window the
+    omega = 0 value is (n - 1) dt."""
+    dt = 0.7
+    K = np.ones((n, 3))
+    om = np.array([0.0, 0.3, 1.1, 2.9])
+    got = oracle.shc_spectrum(K, dt, om)[:, 0]
+    x = om * dt
+    with np.errstate(invalid="ignore", divide="ignore"):
+        d = np.where(x == 0, 2 * n - 1, np.sin((n - 0.5) * x) / np.sin(x / 2))
+    expect = dt * (d - np.cos((n - 1) * x))
+    assert np.allclose(got, expect, rtol=1e-12, atol=1e-12)
+    assert math.isclose(got[0], 2 * (n - 1) * dt, rel_tol=1e-14)
+    hann = oracle.shc_spectrum(K, dt, [0.0], window=True)[0, 0]
+    assert math.isclose(hann, (n - 1) * dt, rel_tol=1e-13, abs_tol=1e-13)
+
+
+def test_kappa_prefactor():
+    Kw = np.array([[2.0, 4.0, 6.0]])
+    assert np.allclose(oracle.shc_kappa(Kw, 10.0, 300.0, 0.5), 2 * Kw / (10.0 * 300.0 * 0.5))
+
+
+# ------------------------------------------------------------------ mutations
+def _mut_transposed(v, W, n):
+    return oracle.shc_correlation(v, np.swapaxes(W, 2, 3), n)
+
+
+def _mut_virial_late(v, W, n):
+    S = v.shape[0]
+    K = np.zeros((n, 3))
+    for tau in range(min(n, S)):
+        K[tau] = np.tensordot(W[tau:], v[: S - tau], axes=([0, 1, 3], [0, 1, 2])) / (S - tau)
+    return K
+
+
+def _mut_norm_S(v, W, n):
+    S = v.shape[0]
+    return oracle.shc_correlation(v, W, n) * (S - np.arange(n))[:, None] / S
+
+
+@pytest.mark.parametrize("mut", [_mut_transposed, _mut_virial_late, _mut_norm_S])
+def test_mutations_fail_the_golden(mut):
+    v, W, K, _ = _fixture()
+    assert not np.allclose(mut(v, W, 3), K, atol=1e-12)
+
+
+def test_mutation_rectangle_rule_fails_the_closed_form():
+    n, dt = 5, 1.0
+    K = np.ones((n, 3))
+    c = np.full(n, 2.0)
+    c[0] = 1.0                                       # end point weighted 2, not 1
+    rect = dt * (np.cos(np.outer([0.0], np.arange(n)) * dt) * c) @ K
+    assert not math.isclose(rect[0, 0], 2 * (n - 1) * dt)
