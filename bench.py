@@ -47,6 +47,12 @@ GROUP_WORKLOADS = {
 GROUP_NB, GROUP_L, GROUP_T, GROUP_STEPS = 500, 1000, 64, 78
 PEAK_FP8_FLOPS = 5.0e15
 
+# Spectral heat current (no eigenvectors): 8000 atoms (the paper's Si and CNT
+# sizes), 250 lags (500 fs at a 2 fs sample interval), T = 256 steps per block.
+SHC_WORKLOADS = {"shc8000_l250_t256": (8000, 250, 256, 40)}     # atoms, lags, T, default blocks
+SHC_METRIC = "spectral heat current atom*lag*steps/s (float64 virial-velocity correlation)"
+PEAK_FP64_FLOPS = 78.6e12
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -168,6 +174,66 @@ def cpu_baseline(dims, t_block, nb, budget_s=15.0):
                       f"({lat.n_modes} modes; float64 numpy/BLAS), {spent:.1f} s of CPU work"}
 
 
+def run_shc(args):
+    """SHC virial-velocity correlation (Eq. 21) in float64, inputs resident in HBM."""
+    import torch
+    import oracle
+    import synth
+    from paper_2102_03691_amd import ModalSHC
+    N, L, T, blocks = SHC_WORKLOADS[args.workload]
+    K = args.steps or blocks
+    m = synth.masses(N)
+    n_blocks = max(1, min(K + args.warmup, 16))
+    v, W = synth.gen_steps_torch(3, m, n_blocks * T, device="cuda:0")
+    h = ModalSHC(N, L, T)
+    for j in range(args.warmup):
+        b = j % n_blocks
+        h.push(v[b * T:(b + 1) * T], W[b * T:(b + 1) * T])
+    h.synchronize()
+    h.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(K):
+        b = (args.warmup + j) % n_blocks
+        h.push(v[b * T:(b + 1) * T], W[b * T:(b + 1) * T])
+    h.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, kms = h.kernel_timing()
+    h.close()
+    units_per_block = float(N) * L * T
+    avg_ms = kms / max(launches, 1)
+    flops = 18.0 * units_per_block                    # 9 FMAs per atom, lag and step
+    roof = {"bound": "fp64", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
+            "unit": "TFLOP/s", "traffic": None, "kernel": "k_shc_gram", "avg_launch_ms": avg_ms,
+            "launches": launches}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {"metric": SHC_METRIC, "value": units_per_block * K / wall, "unit": "atom*lag*steps/s", "n_gpus": 1,
+           "steps": K, "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "atoms": N, "lags": L, "md_steps_per_step": T, "t_block": T,
+                      "precision": "float32 inputs, products and sums in float64", "parallelism": "single GPU"},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        vc, Wc = synth.gen_steps(0, m, 0, T)
+        t0 = time.perf_counter()
+        oracle.shc_correlation(vc, Wc, L)
+        spent = time.perf_counter() - t0
+        # the oracle sums each lag over the S - tau origins of the sample
+        work = float(N) * sum(T - tau for tau in range(L))
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count()
+        out["cpu_baseline"] = {"value": work / spent, "unit": "atom*lag*steps/s", "cores": int(cores),
+                               "kind": "oracle",
+                               "sample": f"{T} samples x {L} lags x {N} atoms (float64 numpy tensordot), "
+                                         f"{spent:.1f} s of CPU work"}
+    return out
+
+
 def run_group(args, prec):
     """The uneven batch as one grouped push per block (graph replay, autotuned tiles)."""
     import torch
@@ -255,7 +321,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT,
+                    choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS) + sorted(SHC_WORKLOADS))
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -281,6 +348,9 @@ def main():
         del src, dst
     if args.workload in GROUP_WORKLOADS:
         print(json.dumps(run_group(args, GROUP_WORKLOADS[args.workload])), flush=True)
+        return
+    if args.workload in SHC_WORKLOADS:
+        print(json.dumps(run_shc(args)), flush=True)
         return
     dims, t_block, prec, methods, nb, L, default_steps = WORKLOADS[args.workload]
     K = args.steps or default_steps

@@ -301,6 +301,58 @@ mhc_status mhc_group_info(mhc_group *group, int32_t *tile_shape, double *tuned_m
 mhc_status mhc_group_set_timing(mhc_group *group, int enable);
 mhc_status mhc_group_kernel_timing(mhc_group *group, int64_t *launches, double *total_ms);
 
+/* ---------------------------------------------------- spectral heat current
+ * The SHC method (Sec. II.C), which needs no eigenvectors: the steady-state
+ * virial-velocity correlation of Eq. 21,
+ *   K^mu(tau) = < sum_i sum_nu W_i^{mu nu}(s) v_i^nu(s + tau) >,
+ * with the virial at the time origin s and the velocity tau samples later,
+ * averaged over the S - tau available origins (tau = 0 .. n_lags-1; K(0) is
+ * the time average of the Eq. 10 current), accumulated in float64 on the
+ * device (the float32 inputs' products are exact in float64; fixed summation
+ * order, Neumaier compensation: bitwise reproducible), and its transform
+ * (Eq. 22).  v and W have the layout of mhc_push.  A separate object, so it can
+ * run beside an HNEMA/GKMA context on the same inputs (Sec. III.B). */
+typedef struct mhc_shc mhc_shc;
+
+/* n_atoms in [1, 2^26]; n_lags in [1, 4096]; t_block (steps per device
+ * block) a multiple of 64 in [64, 1024].  hip_stream as for mhc_create.
+ * Device memory: about (n_lags + t_block) * 3N * 12 bytes (virial ring) plus
+ * t_block * 3N * 16 bytes (host-input staging).
+ * Errors: INVALID_ARG, OOM, HIP (mhc_shc_last_error(NULL) tells which). */
+mhc_status mhc_shc_create(int device, void *hip_stream, int64_t n_atoms, int32_t n_lags, int32_t t_block,
+                          mhc_shc **out);
+mhc_status mhc_shc_destroy(mhc_shc *shc);
+const char *mhc_shc_last_error(const mhc_shc *shc);
+
+/* Append n_steps samples: v [n_steps][N][3], W [n_steps][N][3][3] float32
+ * (host pointers copied before return when on_device = 0; device pointers
+ * read by work queued on the stream when on_device = 1, as for mhc_push).
+ * Errors: INVALID_ARG, HIP (sticky). */
+mhc_status mhc_shc_push(mhc_shc *shc, int32_t n_steps, const float *v, const float *W, int on_device);
+
+/* K [n_lags][3] (float64, Eq. 21 as above; lags with no origin are 0) and the
+ * number of samples since the last reset.  Synchronizes.  Errors: INVALID_ARG, HIP. */
+mhc_status mhc_shc_read(mhc_shc *shc, double *K, int64_t *n_samples);
+
+/* Eq. 22 on the sampled lags: K is extended evenly, K(-t) = K(t), and the
+ * integral over [-(n-1) dt, (n-1) dt] taken by the trapezoid rule,
+ *   Kw[w][mu] = dt sum_tau c_tau K[tau][mu] cos(omega[w] tau dt),
+ * c_0 = c_{n-1} = 1, c_tau = 2 otherwise, times the Hann window
+ * (1 + cos(pi tau / (n-1))) / 2 when window = 1.  omega [n_omega] in radians
+ * per unit of dt; n_omega in [1, 2^24].  kappa(omega) = 2 Kw / (V T F_e)
+ * (Eq. 23) is left to the caller.  Synchronizes.  Errors: INVALID_ARG, OOM, HIP. */
+mhc_status mhc_shc_spectrum(mhc_shc *shc, int32_t n_omega, const double *omega, double dt, int32_t window,
+                            double *Kw);
+
+/* Clear the sums and the sample count (the next push starts a new run). */
+mhc_status mhc_shc_reset(mhc_shc *shc);
+mhc_status mhc_shc_synchronize(mhc_shc *shc);
+
+/* HIP-event timing of the product kernels of each pushed block, as for
+ * mhc_set_timing / mhc_kernel_timing. */
+mhc_status mhc_shc_set_timing(mhc_shc *shc, int enable);
+mhc_status mhc_shc_kernel_timing(mhc_shc *shc, int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmodalhc.so")
 
-SOURCES = ["mhc_api.cpp", "k_prep.hip", "k_contract.hip", "k_accum.hip"]
+SOURCES = ["mhc_api.cpp", "mhc_shc.cpp", "k_prep.hip", "k_contract.hip", "k_accum.hip", "k_shc.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -75,6 +75,16 @@ def library():
         "mhc_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
         "mhc_device_bytes": (i32, [vp, P(i64)]),
         "mhc_last_schedule": (i32, [vp, P(i32)]),
+        "mhc_shc_create": (i32, [C.c_int, vp, i64, i32, i32, P(vp)]),
+        "mhc_shc_destroy": (i32, [vp]),
+        "mhc_shc_last_error": (C.c_char_p, [vp]),
+        "mhc_shc_push": (i32, [vp, i32, vp, vp, C.c_int]),
+        "mhc_shc_read": (i32, [vp, vp, P(i64)]),
+        "mhc_shc_spectrum": (i32, [vp, i32, vp, dbl, i32, vp]),
+        "mhc_shc_reset": (i32, [vp]),
+        "mhc_shc_synchronize": (i32, [vp]),
+        "mhc_shc_set_timing": (i32, [vp, C.c_int]),
+        "mhc_shc_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
         "mhc_group_create": (i32, [P(vp), i32, i32, P(vp)]),
         "mhc_group_destroy": (i32, [vp]),
         "mhc_group_last_error": (C.c_char_p, [vp]),
@@ -345,3 +355,89 @@ class ModalGroup:
             self.close()
         except Exception:
             pass
+
+
+class ModalSHC:
+    """Spectral heat current (mhc_shc_*): the virial-velocity correlation of
+    Eq. 21 over n_lags lags and its transform (Eq. 22); no eigenvectors.
+
+    Inputs as for ModalHC.push (torch device tensors or numpy host arrays);
+    work is queued on torch's current stream by default."""
+
+    def __init__(self, n_atoms: int, n_lags: int, t_block: int = 256, device: int = 0, stream=None):
+        self._lib = library()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        st = self._lib.mhc_shc_create(int(device), C.c_void_p(int(stream) if stream else 0), int(n_atoms),
+                                      int(n_lags), int(t_block), C.byref(h))
+        if st:
+            raise MhcError(st, self._lib.mhc_shc_last_error(None).decode())
+        self._h = h
+        self.n_atoms, self.n_lags, self.t_block = int(n_atoms), int(n_lags), int(t_block)
+
+    def _check(self, st, what):
+        if st:
+            raise MhcError(st, f"{what}: {self._lib.mhc_shc_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mhc_shc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def push(self, v, W):
+        """v [S, N, 3] and W [S, N, 3, 3] float32 (numpy host or torch device)."""
+        if _is_torch(v):
+            assert v.is_contiguous() and W.is_contiguous() and v.element_size() == 4 and W.element_size() == 4
+            assert v.shape[0] == W.shape[0] and v.numel() == v.shape[0] * self.n_atoms * 3
+            assert W.numel() == W.shape[0] * self.n_atoms * 9
+            self._check(self._lib.mhc_shc_push(self._h, v.shape[0], _ptr(v), _ptr(W), 1), "shc push")
+        else:
+            vv = np.ascontiguousarray(v, dtype=np.float32)
+            WW = np.ascontiguousarray(W, dtype=np.float32)
+            assert vv.shape[0] == WW.shape[0] and vv.size == vv.shape[0] * self.n_atoms * 3
+            assert WW.size == WW.shape[0] * self.n_atoms * 9
+            self._check(self._lib.mhc_shc_push(self._h, vv.shape[0], _ptr(vv), _ptr(WW), 0), "shc push")
+
+    def read(self):
+        """(K [n_lags, 3] float64, number of samples)."""
+        K = np.empty((self.n_lags, 3), dtype=np.float64)
+        n = C.c_int64()
+        self._check(self._lib.mhc_shc_read(self._h, _ptr(K), C.byref(n)), "shc read")
+        return K, n.value
+
+    def spectrum(self, omega, dt: float, window: bool = False):
+        """Eq. 22 on the sampled lags at the angular frequencies omega: [n_omega, 3]."""
+        om = np.ascontiguousarray(omega, dtype=np.float64).ravel()
+        out = np.empty((om.shape[0], 3), dtype=np.float64)
+        self._check(self._lib.mhc_shc_spectrum(self._h, om.shape[0], _ptr(om), float(dt), int(bool(window)),
+                                               _ptr(out)), "shc spectrum")
+        return out
+
+    def reset(self):
+        self._check(self._lib.mhc_shc_reset(self._h), "shc reset")
+
+    def synchronize(self):
+        self._check(self._lib.mhc_shc_synchronize(self._h), "shc synchronize")
+
+    def set_timing(self, enable: bool):
+        self._check(self._lib.mhc_shc_set_timing(self._h, int(bool(enable))), "shc set_timing")
+
+    def kernel_timing(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(self._lib.mhc_shc_kernel_timing(self._h, C.byref(n), C.byref(ms)), "shc kernel_timing")
+        return n.value, ms.value

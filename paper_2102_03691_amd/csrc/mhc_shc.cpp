@@ -1,0 +1,297 @@
+// Host side of the spectral-heat-current entry points (mhc_shc_*, include/mhc.h).
+//
+// Per pushed block of at most T steps: the block's virials go into the ring
+// of past virials (transposed to [mu][3i + nu]), then the virial-velocity
+// products of the block's steps against the last n_lags origins are formed
+// and added to the float64 sums.  No arithmetic of the method runs here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mhc.h"
+#include "mhc_common.h"
+
+using namespace mhc;
+
+struct mhc_shc {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  mhc_status sticky = MHC_OK;
+  int64_t N = 0, N3 = 0, ld = 0;
+  int n_lags = 0, T = 0;
+  int64_t ring_len = 0;
+  int64_t dk = 0;
+  int n_kc = 0;
+  int64_t S = 0;                       // samples pushed since the last reset
+  std::vector<void*> allocs;
+  float* ring = nullptr;               // [ring_len][3][ld]
+  float* sv = nullptr;                 // host-input staging [T][N][3]
+  float* sW = nullptr;                 // [T][N][9]
+  double* part = nullptr;              // [n_kc][T/64][n_lags_pad][3]
+  double* ksum = nullptr;              // [n_lags][3] x 2 (sum, compensation)
+  double* kout = nullptr;              // [n_lags][3] read-out
+  double* omega = nullptr;             // spectrum frequencies (grown on demand)
+  double* kw = nullptr;                // [n_omega][3]
+  int omega_cap = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_shc_create_error;
+
+mhc_status sfail(mhc_shc* c, mhc_status st, const std::string& msg) {
+  c->err = msg;
+  return st;
+}
+
+mhc_status shc_hip_fail(mhc_shc* c, hipError_t e, const char* where) {
+  (void)hipGetLastError();
+  c->sticky = MHC_ERR_HIP;
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return MHC_ERR_HIP;
+}
+
+#define SHIP_TRY(call, where)                                   \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return shc_hip_fail(c, e_, (where));  \
+  } while (0)
+
+mhc_status senter(mhc_shc* c) {
+  if (!c) return MHC_ERR_INVALID_ARG;
+  if (c->sticky != MHC_OK) return c->sticky;
+  c->err.clear();
+  if (hipSetDevice(c->device) != hipSuccess) return shc_hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+  return MHC_OK;
+}
+
+mhc_status salloc(mhc_shc* c, size_t bytes, void** out, const char* what) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return sfail(c, MHC_ERR_OOM, std::string("device allocation failed: ") + what);
+  }
+  c->allocs.push_back(p);
+  *out = p;
+  return MHC_OK;
+}
+
+void sfree(mhc_shc* c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  c->stream = nullptr;
+}
+
+int lags_pad(int n) { return (n + 63) / 64 * 64; }
+
+// One block of t_count <= T steps whose inputs are device pointers.
+mhc_status shc_block(mhc_shc* c, const float* v, const float* W, int t_count) {
+  SHIP_TRY(launch_shc_ring(c->stream, W, t_count, c->N, c->ring, c->ring_len, c->ld, c->S), "virial ring");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    while (c->ev_used + 2 > c->ev.size()) {
+      hipEvent_t e;
+      SHIP_TRY(hipEventCreate(&e), "event create");
+      c->ev.push_back(e);
+    }
+    e0 = c->ev[c->ev_used];
+    e1 = c->ev[c->ev_used + 1];
+    c->ev_used += 2;
+    SHIP_TRY(hipEventRecord(e0, c->stream), "event record");
+  }
+  SHIP_TRY(launch_shc_block(c->stream, v, c->ring, c->ring_len, c->ld, c->N3, t_count, c->S, c->n_lags, c->T, c->dk,
+                            c->n_kc, c->part, c->ksum, c->ksum + 3 * c->n_lags),
+           "virial-velocity products");
+  if (e1) SHIP_TRY(hipEventRecord(e1, c->stream), "event record");
+  c->S += t_count;
+  return MHC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhc_status mhc_shc_create(int device, void* hip_stream, int64_t n_atoms, int32_t n_lags, int32_t t_block,
+                          mhc_shc** out) {
+  if (!out) return MHC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n_atoms < 1 || n_atoms > (int64_t(1) << 26) || n_lags < 1 || n_lags > 4096 || t_block < 64 ||
+      t_block > 1024 || t_block % 64)
+    return MHC_ERR_INVALID_ARG;
+  mhc_shc* c = new (std::nothrow) mhc_shc();
+  if (!c) return MHC_ERR_OOM;
+  c->device = device;
+  auto bail = [&](mhc_status st, const char* what) {
+    g_shc_create_error = what;
+    sfree(c);
+    delete c;
+    return st;
+  };
+  if (hipSetDevice(device) != hipSuccess) return bail(MHC_ERR_HIP, "hipSetDevice");
+  if (hip_stream) {
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) return bail(MHC_ERR_HIP, "hipStreamCreate");
+    c->own_stream = true;
+  }
+  int n_cu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) n_cu = std::max(1, prop.multiProcessorCount);
+  c->N = n_atoms;
+  c->N3 = 3 * n_atoms;
+  c->ld = (c->N3 + 3) / 4 * 4;
+  c->n_lags = n_lags;
+  c->T = t_block;
+  c->ring_len = (int64_t)n_lags - 1 + t_block;
+  // split the dofs so that a full block has about two work-groups per CU
+  const int64_t tiles = (int64_t)(t_block / 64) * (lags_pad(n_lags) / 64);
+  const int64_t max_kc = (c->N3 + 31) / 32;
+  int64_t kc = std::min<int64_t>(max_kc, std::max<int64_t>(1, (2 * n_cu + tiles - 1) / tiles));
+  c->dk = ((c->N3 + kc - 1) / kc + 31) / 32 * 32;
+  c->n_kc = (int)((c->N3 + c->dk - 1) / c->dk);
+  void *pr, *pv, *pW, *pp, *ps, *po;
+  const size_t ring_bytes = (size_t)c->ring_len * 3 * c->ld * 4;
+  if (salloc(c, ring_bytes, &pr, "virial ring") || salloc(c, (size_t)t_block * c->N3 * 4, &pv, "velocity staging") ||
+      salloc(c, (size_t)t_block * c->N3 * 3 * 4, &pW, "virial staging") ||
+      salloc(c, (size_t)c->n_kc * (t_block / 64) * lags_pad(n_lags) * 3 * 8, &pp, "partials") ||
+      salloc(c, (size_t)n_lags * 3 * 2 * 8, &ps, "sums") || salloc(c, (size_t)n_lags * 3 * 8, &po, "read-out"))
+    return bail(MHC_ERR_OOM, "device allocation failed");
+  c->ring = static_cast<float*>(pr);
+  c->sv = static_cast<float*>(pv);
+  c->sW = static_cast<float*>(pW);
+  c->part = static_cast<double*>(pp);
+  c->ksum = static_cast<double*>(ps);
+  c->kout = static_cast<double*>(po);
+  if (hipMemsetAsync(c->ring, 0, ring_bytes, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ksum, 0, (size_t)n_lags * 3 * 2 * 8, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(MHC_ERR_HIP, "initial clear");
+  *out = c;
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_destroy(mhc_shc* c) {
+  if (!c) return MHC_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  sfree(c);
+  delete c;
+  return MHC_OK;
+}
+
+const char* mhc_shc_last_error(const mhc_shc* c) { return c ? c->err.c_str() : g_shc_create_error.c_str(); }
+
+mhc_status mhc_shc_push(mhc_shc* c, int32_t n_steps, const float* v, const float* W, int on_device) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  if (n_steps < 0 || (on_device != 0 && on_device != 1)) return sfail(c, MHC_ERR_INVALID_ARG, "bad arguments");
+  if (n_steps == 0) return MHC_OK;
+  if (!v || !W) return sfail(c, MHC_ERR_INVALID_ARG, "NULL input");
+  for (int32_t s0 = 0; s0 < n_steps; s0 += c->T) {
+    const int tc = std::min<int32_t>(c->T, n_steps - s0);
+    const float* vb = v + (int64_t)s0 * c->N3;
+    const float* Wb = W + (int64_t)s0 * c->N3 * 3;
+    if (!on_device) {
+      SHIP_TRY(hipMemcpyAsync(c->sv, vb, (size_t)tc * c->N3 * 4, hipMemcpyHostToDevice, c->stream), "copy v");
+      SHIP_TRY(hipMemcpyAsync(c->sW, Wb, (size_t)tc * c->N3 * 12, hipMemcpyHostToDevice, c->stream), "copy W");
+      vb = c->sv;
+      Wb = c->sW;
+    }
+    if ((st = shc_block(c, vb, Wb, tc))) return st;
+  }
+  if (!on_device) SHIP_TRY(hipStreamSynchronize(c->stream), "push sync");
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_read(mhc_shc* c, double* K, int64_t* n_samples) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  if (!K) return sfail(c, MHC_ERR_INVALID_ARG, "NULL output");
+  SHIP_TRY(launch_shc_finish(c->stream, c->ksum, c->ksum + 3 * c->n_lags, c->n_lags, c->S, c->kout), "finish");
+  SHIP_TRY(hipMemcpyAsync(K, c->kout, (size_t)c->n_lags * 3 * 8, hipMemcpyDeviceToHost, c->stream), "copy K");
+  SHIP_TRY(hipStreamSynchronize(c->stream), "read sync");
+  if (n_samples) *n_samples = c->S;
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_spectrum(mhc_shc* c, int32_t n_omega, const double* omega, double dt, int32_t window,
+                            double* Kw) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  if (n_omega < 1 || n_omega > (1 << 24) || !omega || !Kw || !(std::isfinite(dt) && dt > 0.0) ||
+      (window != 0 && window != 1))
+    return sfail(c, MHC_ERR_INVALID_ARG, "bad arguments");
+  for (int32_t w = 0; w < n_omega; ++w)
+    if (!std::isfinite(omega[w])) return sfail(c, MHC_ERR_INVALID_ARG, "non-finite frequency");
+  if (n_omega > c->omega_cap) {
+    void *po, *pk;
+    if ((st = salloc(c, (size_t)n_omega * 8, &po, "frequencies"))) return st;
+    if ((st = salloc(c, (size_t)n_omega * 3 * 8, &pk, "spectrum"))) return st;
+    c->omega = static_cast<double*>(po);
+    c->kw = static_cast<double*>(pk);
+    c->omega_cap = n_omega;
+  }
+  SHIP_TRY(hipMemcpyAsync(c->omega, omega, (size_t)n_omega * 8, hipMemcpyHostToDevice, c->stream), "copy omega");
+  SHIP_TRY(launch_shc_finish(c->stream, c->ksum, c->ksum + 3 * c->n_lags, c->n_lags, c->S, c->kout), "finish");
+  SHIP_TRY(launch_shc_spectrum(c->stream, c->kout, c->n_lags, c->omega, n_omega, dt, window, c->kw), "spectrum");
+  SHIP_TRY(hipMemcpyAsync(Kw, c->kw, (size_t)n_omega * 3 * 8, hipMemcpyDeviceToHost, c->stream), "copy spectrum");
+  SHIP_TRY(hipStreamSynchronize(c->stream), "spectrum sync");
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_reset(mhc_shc* c) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  SHIP_TRY(hipMemsetAsync(c->ksum, 0, (size_t)c->n_lags * 3 * 2 * 8, c->stream), "clear sums");
+  SHIP_TRY(hipStreamSynchronize(c->stream), "reset sync");
+  c->S = 0;
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_synchronize(mhc_shc* c) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  SHIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_set_timing(mhc_shc* c, int enable) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  if (enable != 0 && enable != 1) return sfail(c, MHC_ERR_INVALID_ARG, "enable is 0 or 1");
+  c->timing = enable;
+  c->ev_used = 0;
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_kernel_timing(mhc_shc* c, int64_t* launches, double* total_ms) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  if (!launches || !total_ms) return sfail(c, MHC_ERR_INVALID_ARG, "NULL output");
+  SHIP_TRY(hipStreamSynchronize(c->stream), "timing sync");
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.f;
+    SHIP_TRY(hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]), "elapsed");
+    tot += ms;
+  }
+  *launches = (int64_t)(c->ev_used / 2);
+  *total_ms = tot;
+  c->ev_used = 0;
+  return MHC_OK;
+}
+
+}  // extern "C"

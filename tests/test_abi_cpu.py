@@ -75,3 +75,25 @@ def test_create_without_gpu_reports_hip_error():
     assert lib.mhc_create(0, None, C.byref(h)) == 4
     assert h.value is None
     assert b"HIP" in lib.mhc_last_error(None) or len(lib.mhc_last_error(None)) > 0
+
+
+def test_shc_entry_points_validate_before_touching_a_device():
+    lib = _lib.library()
+    h = C.c_void_p()
+    assert lib.mhc_shc_create(0, None, 10, 0, 64, C.byref(h)) == 1        # no lags
+    assert lib.mhc_shc_create(0, None, 10, 8, 100, C.byref(h)) == 1       # t_block not a multiple of 64
+    assert lib.mhc_shc_create(0, None, 0, 8, 64, C.byref(h)) == 1         # no atoms
+    assert lib.mhc_shc_create(0, None, 10, 8, 64, None) == 1
+    assert lib.mhc_shc_push(None, 1, None, None, 0) == 1
+    assert lib.mhc_shc_read(None, None, None) == 1
+    assert lib.mhc_shc_destroy(None) == 0
+
+
+def test_shc_create_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _lib.library()
+    h = C.c_void_p()
+    assert lib.mhc_shc_create(0, None, 10, 8, 64, C.byref(h)) == 4
+    assert h.value is None

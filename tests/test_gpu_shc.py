@@ -1,0 +1,120 @@
+"""Spectral heat current (Sec. II.C, Eqs. 21-22) on the GPU against the FP64
+oracle, through the C ABI.  The device forms the float32 inputs' products
+exactly in float64 and sums in float64, so the bar is 1e-12 relative (L2 per
+output array); summation order differs from numpy's, nothing else."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._cases import announce, log, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _inputs(n_atoms, S, seed):
+    m = synth.masses(n_atoms, "natural", seed)
+    return synth.gen_steps(seed, m, 0, S)
+
+
+def _run(n_atoms, v, W, n_lags, T, splits, device_inputs):
+    import torch
+    from paper_2102_03691_amd import ModalSHC
+    h = ModalSHC(n_atoms, n_lags, T)
+    if device_inputs:
+        v = torch.as_tensor(v, device="cuda:0")
+        W = torch.as_tensor(W, device="cuda:0")
+    s0 = 0
+    for n in splits:
+        h.push(v[s0:s0 + n], W[s0:s0 + n])
+        s0 += n
+    assert s0 == v.shape[0]
+    K, S = h.read()
+    return h, K, S
+
+
+@pytest.mark.parametrize("n_atoms,S,n_lags,T,splits,dev", [
+    (37, 300, 70, 64, [1, 63, 100, 136], False),           # ragged dofs (111), ragged lag tile, uneven pushes
+    (200, 500, 130, 128, [500], True),                     # lags longer than a block: history across blocks
+    (64, 40, 100, 64, [17, 23], True),                     # more lags than samples: empty lags are zero
+    (1000, 700, 256, 256, [256, 256, 188], True),          # several dof ranges per work-group split
+])
+def test_shc_correlation_parity(n_atoms, S, n_lags, T, splits, dev):
+    announce(f"shc N={n_atoms} S={S} L={n_lags} T={T}")
+    v, W = _inputs(n_atoms, S, seed=n_atoms + S)
+    h, K, n = _run(n_atoms, v, W, n_lags, T, splits, dev)
+    ref = oracle.shc_correlation(v, W, n_lags)
+    e = rel(K, ref)
+    e0 = rel(K[0], oracle.total_heat_current(v, W).mean(axis=0))
+    log(f"shc_N{n_atoms}_S{S}_L{n_lags}_T{T}", rel_K=e, rel_K0_vs_eq10=e0)
+    assert n == S
+    assert e <= TOL and e0 <= TOL
+    if n_lags > S:
+        assert np.all(K[S:] == 0.0)
+    # transform of the device correlation against the oracle's transform of the oracle's correlation
+    om = np.linspace(0.0, np.pi / 2.0, 33)
+    for window in (False, True):
+        Kw = h.spectrum(om, 2.0, window)
+        ref_w = oracle.shc_spectrum(ref, 2.0, om, window)
+        ew = rel(Kw, ref_w)
+        log(f"shc_spectrum_N{n_atoms}_w{int(window)}", rel_Kw=ew)
+        assert ew <= 1e-11
+    h.close()
+
+
+def test_shc_determinism_split_invariance_and_reset():
+    announce("shc determinism / reset")
+    n_atoms, S, L, T = 120, 400, 90, 64
+    v, W = _inputs(n_atoms, S, seed=7)
+    h1, K1, _ = _run(n_atoms, v, W, L, T, [S], True)
+    h2, K2, _ = _run(n_atoms, v, W, L, T, [S], True)
+    assert np.array_equal(K1, K2)
+    h3, K3, _ = _run(n_atoms, v, W, L, T, [5, 100, 1, 294], True)
+    assert rel(K3, K1) <= 1e-13
+    # reset, then a different run: only the new samples count
+    import torch
+    v2, W2 = _inputs(n_atoms, 150, seed=8)
+    h1.reset()
+    h1.push(torch.as_tensor(v2, device="cuda:0"), torch.as_tensor(W2, device="cuda:0"))
+    K4, n4 = h1.read()
+    assert n4 == 150
+    assert rel(K4, oracle.shc_correlation(v2, W2, L)) <= TOL
+    for h in (h1, h2, h3):
+        h.close()
+
+
+def test_shc_invalid_arguments():
+    from paper_2102_03691_amd import MhcError, ModalSHC
+    with pytest.raises(MhcError):
+        ModalSHC(10, 0, 64)
+    with pytest.raises(MhcError):
+        ModalSHC(10, 8, 96)
+    h = ModalSHC(10, 8, 64)
+    with pytest.raises(MhcError):
+        h.spectrum([0.0], -1.0)
+    with pytest.raises(MhcError):
+        h.spectrum([float("nan")], 1.0)
+    h.close()
+
+
+def test_shc_paper_shaped_size():
+    """8000 atoms (the paper's Si and CNT sizes, Sec. III.A), 250 lags (500 fs
+    at a 2 fs sample interval, Sec. III.A.i), T = 256, 600 samples."""
+    announce("shc 8000 atoms L=250 T=256")
+    n_atoms, S, L, T = 8000, 600, 250, 256
+    v, W = _inputs(n_atoms, S, seed=11)
+    h, K, n = _run(n_atoms, v, W, L, T, [256, 256, 88], True)
+    ref = oracle.shc_correlation(v, W, L)
+    e = rel(K, ref)
+    log("shc_N8000_S600_L250_T256", rel_K=e)
+    assert n == S and e <= TOL
+    h.close()
