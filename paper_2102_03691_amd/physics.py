@@ -4,6 +4,8 @@ Eq. 19: kappa_b^{mu nu} F_e^nu = <J_b^mu> / (T V), so for a driving force
 along one axis kappa_b^{mu x} = <J_b^mu> / (T V F_e).
 Eq. 17: kappa_b^{mu nu}(tau) = G_b^{mu nu}(tau) / (k_B T^2 V), G the running
 integral of the modal-current / total-current correlation.
+Eq. 23: kappa(omega) = 2 K~(omega) / (V T F_e), K~ the transform of the SHC
+virial-velocity correlation (eV A/fs integrated over fs: eV A).
 Units: eV, Angstrom, fs, K in; W/(m K) out.
 """
 KB_EV_PER_K = 8.617333262e-5
@@ -18,3 +20,12 @@ def hnema_kappa(avg, temperature, volume_a3, fe_per_a):
 def gkma_kappa(integral, temperature, volume_a3):
     """kappa(tau) from the GKMA running integral ((eV A/fs)^2 fs)."""
     return integral / (KB_EV_PER_K * temperature ** 2 * volume_a3) * _EV_PER_FS_A_K_IN_W_PER_M_K
+
+
+def shc_kappa(Kw, temperature, volume_a3, fe_per_a):
+    """Spectral kappa per unit of frequency (W m^-1 K^-1 THz^-1) from the SHC
+    transform K~(omega) (eV A) for a drive F_e (1/A): Eq. 23 gives kappa per
+    unit of angular frequency, and kappa(f) = 2 pi kappa(omega)."""
+    import math
+    per_omega = 2.0 * Kw / (volume_a3 * temperature * fe_per_a)          # eV / (A K) per (rad / s)
+    return per_omega * (1.602176634e-19 / 1e-10) * 2.0 * math.pi * 1e12

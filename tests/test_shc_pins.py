@@ -136,3 +136,10 @@ def test_mutation_rectangle_rule_fails_the_closed_form():
     c[0] = 1.0                                       # end point weighted 2, not 1
     rect = dt * (np.cos(np.outer([0.0], np.arange(n)) * dt) * c) @ K
     assert not math.isclose(rect[0, 0], 2 * (n - 1) * dt)
+
+
+def test_package_shc_kappa_units():
+    """1 eV A over 1 A^3, 1 K, 1/A: 2 eV/(A K) per rad/s = 3.204e-9 J/(m K s^-1);
+    per THz of f = omega / (2 pi): times 2 pi 1e12."""
+    from paper_2102_03691_amd.physics import shc_kappa
+    assert math.isclose(shc_kappa(1.0, 1.0, 1.0, 1.0), 2 * 1.602176634e-9 * 2 * math.pi * 1e12, rel_tol=1e-15)
