@@ -58,18 +58,22 @@ hipError_t launch_shc_ring(hipStream_t s, const float* W, int t_count, int64_t N
 constexpr int SH_T = 64, SH_L = 64, SH_DC = 32;
 constexpr int SH_ROWS = SH_T + SH_L - 1;                 // 127
 constexpr int SH_VP = SH_T + SH_T / 4;                   // padded step index range of the V tile
-constexpr int SH_WS = 3 * SH_DC + 4;                     // W row stride (floats)
+constexpr int SH_WS = 3 * SH_DC + 28;                    // W row stride (floats): 96 used + room for the shift
+// Row r of the W tile starts at r * SH_WS + 4 * ((r / 4) % 8) floats (the
+// shift stays within the row's 28 spare floats): rows four apart, the rows one
+// LDS pass reads, then fall on different bank groups.
+__device__ __forceinline__ int sh_wrow(int r) { return r * SH_WS + 4 * ((r >> 2) & 7); }
+constexpr int SH_WTILE = SH_ROWS * SH_WS + 28;
 
 __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, const float* __restrict__ ring,
                                                  int64_t ring_len, int64_t ld, int64_t N3, int t_count,
                                                  int64_t s0, int64_t dk, int n_lags_pad,
                                                  double* __restrict__ part) {
   __shared__ f32x4 vs[SH_DC / 4][SH_VP];
-  // the W tile, reused for the final step-group sums once the products are done
-  __shared__ __attribute__((aligned(16))) float ws_raw[SH_ROWS * SH_WS];
-  float (*ws)[SH_WS] = reinterpret_cast<float (*)[SH_WS]>(ws_raw);
-  double (*red)[SH_L][3] = reinterpret_cast<double (*)[SH_L][3]>(ws_raw);     // [16][64][3] doubles: 24 KiB
-  static_assert(16 * SH_L * 3 * sizeof(double) <= SH_ROWS * SH_WS * sizeof(float), "reduction fits in the W tile");
+  // the W tile (rows at sh_wrow), reused for the final step-group sums once the products are done
+  __shared__ __attribute__((aligned(16))) float ws[SH_WTILE];
+  double (*red)[SH_L][3] = reinterpret_cast<double (*)[SH_L][3]>(ws);     // [16][64][3] doubles: 24 KiB
+  static_assert(16 * SH_L * 3 * sizeof(double) <= SH_WTILE * sizeof(float), "reduction fits in the W tile");
   const int tid = threadIdx.x;
   const int kc = blockIdx.x;
   const int a = blockIdx.y;
@@ -89,32 +93,76 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, c
 #pragma unroll
       for (int m = 0; m < 3; ++m) acc[x][y][m] = 0.0;
 
-  for (int64_t jc = j0; jc < j1; jc += SH_DC) {
-    // stage V (64 steps x 32 dofs) and W (127 origins x 3 x 32 dofs)
-    for (int e = tid; e < SH_T * (SH_DC / 4); e += 256) {
-      const int tr = e / (SH_DC / 4), d4 = e % (SH_DC / 4);
+  // Ring offset of each origin row of the tile (-1: before the first sample
+  // or after the block's last step, staged as zeros).
+  __shared__ int64_t roff[SH_ROWS];
+  if (tid < SH_ROWS) {
+    const int64_t sp = row0 + tid;
+    roff[tid] = (sp >= 0 && sp <= s_last) ? (sp % ring_len) * 3 * ld : -1;
+  }
+  __syncthreads();
+  // Staging of one 32-dof chunk through registers: W as float4 (16-byte
+  // aligned: ld and the chunk start are multiples of 4; the ring's pad columns
+  // past 3N are zero), V element-wise (its rows are 3N floats long).  The next
+  // chunk's loads are issued before the current chunk's products.
+  constexpr int WQ = SH_ROWS * 3 * (SH_DC / 4);           // 3048 float4 per chunk
+  constexpr int WPT = (WQ + 255) / 256;                    // 12 per thread
+  constexpr int VPT = SH_T * (SH_DC / 4) / 256;            // 2 per thread
+  f32x4 wst[WPT], vst[VPT];
+  auto load = [&](int64_t jc) {
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      const int e = tid + 256 * k;
+      f32x4 x = {0.f, 0.f, 0.f, 0.f};
+      if (e < WQ) {
+        const int r = e / (3 * SH_DC / 4), rem = e % (3 * SH_DC / 4);
+        const int mu = rem / (SH_DC / 4), q = rem % (SH_DC / 4);
+        const int64_t off = roff[r];
+        const int64_t j = jc + 4 * q;
+        if (off >= 0 && j < j1) x = *reinterpret_cast<const f32x4*>(ring + off + mu * ld + j);
+      }
+      wst[k] = x;
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int e = tid + 256 * k;
+      const int tr = e / (SH_DC / 4), q = e % (SH_DC / 4);
       const int t = SH_T * a + tr;
+      const int64_t j = jc + 4 * q;
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
       if (t < t_count) {
-        const float* src = v + (int64_t)t * N3 + jc + 4 * d4;
-        const int64_t j = jc + 4 * d4;
+        const float* src = v + (int64_t)t * N3 + j;
         x.x = (j + 0 < j1) ? src[0] : 0.f;
         x.y = (j + 1 < j1) ? src[1] : 0.f;
         x.z = (j + 2 < j1) ? src[2] : 0.f;
         x.w = (j + 3 < j1) ? src[3] : 0.f;
       }
-      vs[d4][tr + (tr >> 2)] = x;
+      vst[k] = x;
     }
-    for (int e = tid; e < SH_ROWS * 3 * SH_DC; e += 256) {
-      const int r = e / (3 * SH_DC), rem = e % (3 * SH_DC);
-      const int mu = rem / SH_DC, d = rem % SH_DC;
-      const int64_t sp = row0 + r;
-      const int64_t j = jc + d;
-      float x = 0.f;
-      if (sp >= 0 && sp <= s_last && j < j1) x = ring[((sp % ring_len) * 3 + mu) * ld + j];
-      ws[r][mu * SH_DC + d] = x;
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      const int e = tid + 256 * k;
+      if (e < WQ) {
+        const int r = e / (3 * SH_DC / 4), rem = e % (3 * SH_DC / 4);
+        const int mu = rem / (SH_DC / 4), q = rem % (SH_DC / 4);
+        *reinterpret_cast<f32x4*>(&ws[sh_wrow(r) + mu * SH_DC + 4 * q]) = wst[k];
+      }
     }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int e = tid + 256 * k;
+      const int tr = e / (SH_DC / 4), q = e % (SH_DC / 4);
+      vs[q][tr + (tr >> 2)] = vst[k];
+    }
+  };
+
+  load(j0);
+  for (int64_t jc = j0; jc < j1; jc += SH_DC) {
+    store();
     __syncthreads();
+    if (jc + SH_DC < j1) load(jc + SH_DC);
 #pragma unroll 2
     for (int d4 = 0; d4 < SH_DC / 4; ++d4) {
       f32x4 vv[4];
@@ -125,7 +173,7 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, c
         const int r = 4 * (tt - tl) + (q - 3) + (SH_L - 1);
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-          const f32x4 w4 = *reinterpret_cast<const f32x4*>(&ws[r][m * SH_DC + 4 * d4]);
+          const f32x4 w4 = *reinterpret_cast<const f32x4*>(&ws[sh_wrow(r) + m * SH_DC + 4 * d4]);
           const double w0 = w4.x, w1 = w4.y, w2 = w4.z, w3 = w4.w;
 #pragma unroll
           for (int x = 0; x < 4; ++x) {

@@ -918,6 +918,7 @@ struct mhc_group {
   // before and after the shared contraction), so small systems' kernels run
   // side by side instead of one after another.
   hipStream_t aux[NAUX] = {};
+  std::vector<int> aux_of;      // side stream of each system (balanced by estimated cost)
   hipEvent_t fork_ev = nullptr, join_ev[NAUX] = {};
   hipEvent_t tab_ev[TAB_RING] = {};
   bool tab_busy[TAB_RING] = {};
@@ -1000,7 +1001,7 @@ mhc_status fan_out(mhc_group* g, F&& fn) {
   for (size_t i = 0; i < g->sys.size() && !st; ++i) {
     mhc_ctx* c = g->sys[i];
     hipStream_t own = c->stream;
-    c->stream = g->aux[i % NAUX];
+    c->stream = g->aux[g->aux_of[i]];
     st = fn(i);
     c->stream = own;
   }
@@ -1127,6 +1128,26 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
   g->autotune = flags & MHC_GROUP_AUTOTUNE;
   g->n_cu = c0->n_cu;
   g->shape = (g->ntb % 4 == 0) ? 0 : (g->ntb % 2 == 0 ? 1 : 2);
+  {
+    // longest-processing-time assignment of systems to side streams; a
+    // system's front and back work scales with its modes, GKMA's correlation
+    // update with its bins x lags
+    std::vector<std::pair<double, int>> cost;
+    for (int i = 0; i < n; ++i) {
+      const mhc_ctx* c = systems[i];
+      double w = (double)c->M_pad;
+      if (c->cfg.methods & MHC_GKMA) w += 3.0 * (c->nb + 1) * c->cfg.corr_len * 3.0 / g->t_block;
+      cost.push_back({w, i});
+    }
+    std::stable_sort(cost.begin(), cost.end(), [](auto a, auto b) { return a.first > b.first; });
+    double load[NAUX] = {};
+    g->aux_of.assign(n, 0);
+    for (auto& ci : cost) {
+      int k = (int)(std::min_element(load, load + NAUX) - load);
+      g->aux_of[ci.second] = k;
+      load[k] += ci.first;
+    }
+  }
   auto cleanup = [&](mhc_status st) {
     for (auto& a : g->allocs) (void)hipFree(a.p);
     if (g->h_tab) (void)hipHostFree(g->h_tab);
