@@ -56,47 +56,20 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
         if (tid == 0) neumaier_add(a.hsum[b * 3 + mu], a.hcomp[b * 3 + mu], tot);
       }
     } else {
-      // GKMA: per-step binned currents X[(b*3+mu)][t].  Threads form G groups
-      // of TT lanes (TT steps side by side); group g sums the bin's modes
-      // q = g, g+G, ... with four independent partial sums, and the groups are
-      // combined in a fixed order through LDS.
-      __shared__ double part[256][3];
-      const int TT = a.t_count <= 64 ? 64 : (a.t_count <= 128 ? 128 : 256);
-      const int G = 256 / TT;
-      const int g = tid / TT;
-      const int tl = tid % TT;
+      // GKMA: X[(b*3+mu)][t] = sum over the bin's segment rows in segment order
+      // (from k_reduce_seg); thread t of the work-group, steps strided by 256.
+      const int64_t P = (int64_t)a.n_seg + a.nb;
+      const int64_t sg0 = lo / REDUCE_SEG, sg1 = (hi - 1) / REDUCE_SEG;
       double h3[3] = {0.0, 0.0, 0.0};
-      for (int t0 = 0; t0 < a.t_count; t0 += TT) {
-        const int t = t0 + tl;
-        double v3[3] = {0.0, 0.0, 0.0};
-        if (t < a.t_count) {
+      for (int t = tid; t < a.t_count; t += 256) {
 #pragma unroll
-          for (int mu = 0; mu < 3; ++mu) {
-            const float* col = a.in + ((int64_t)mu * a.M_pad + lo) * a.ld + t;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int64_t q = g;
-            for (; q + 3 * G < n; q += 4 * G) {
-              s0 += (double)col[q * a.ld];
-              s1 += (double)col[(q + G) * a.ld];
-              s2 += (double)col[(q + 2 * G) * a.ld];
-              s3 += (double)col[(q + 3 * G) * a.ld];
-            }
-            for (; q < n; q += G) s0 += (double)col[q * a.ld];
-            v3[mu] = (s0 + s1) + (s2 + s3);
-          }
+        for (int mu = 0; mu < 3; ++mu) {
+          double s = 0.0;
+          if (n > 0)
+            for (int64_t sg = sg0; sg <= sg1; ++sg) s += a.seg_part[((int64_t)mu * P + sg + b) * a.ld + t];
+          a.X[((int64_t)b * 3 + mu) * a.ld + t] = s;
+          h3[mu] += s;
         }
-        part[tid][0] = v3[0]; part[tid][1] = v3[1]; part[tid][2] = v3[2];
-        __syncthreads();
-        if (g == 0 && t < a.t_count) {
-#pragma unroll
-          for (int mu = 0; mu < 3; ++mu) {
-            double s = 0.0;
-            for (int gg = 0; gg < G; ++gg) s += part[gg * TT + tl][mu];
-            a.X[((int64_t)b * 3 + mu) * a.ld + t] = s;
-            h3[mu] += s;
-          }
-        }
-        __syncthreads();
       }
       if (a.hsum) {
 #pragma unroll
@@ -162,7 +135,59 @@ hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int 
   return hipGetLastError();
 }
 
+// GKMA segment pass: TT = 64, 128 or 256 lanes per segment (the smallest that
+// covers t_count; steps strided by TT), 256 / TT segments per work-group.  A
+// segment's REDUCE_SEG slots are summed in slot order, bin by bin, into
+// seg_part[mu][seg + b][t] (every bin the segment touches).
+__global__ void __launch_bounds__(256) k_reduce_seg(ReduceArgs a) {
+  __shared__ int32_t sb[4][REDUCE_SEG];
+  const int tid = threadIdx.x;
+  const int TT = a.t_count <= 64 ? 64 : (a.t_count <= 128 ? 128 : 256);
+  const int G = 256 / TT;
+  const int g = tid / TT, tl = tid % TT;
+  const int64_t seg = (int64_t)blockIdx.x * G + g;
+  const int64_t slot0 = seg * REDUCE_SEG;
+  if (tl < REDUCE_SEG) sb[g][tl] = (seg < a.n_seg && slot0 + tl < a.M_pad) ? a.slot_bin[slot0 + tl] : -1;
+  __syncthreads();
+  if (seg >= a.n_seg) return;
+  const int64_t P = (int64_t)a.n_seg + a.nb;
+  const float* __restrict__ in = a.in;
+  double* __restrict__ out = a.seg_part;
+  for (int t = tl; t < a.t_count; t += TT) {
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      // all of the segment's values first (independent, unconditional loads:
+      // padding rows exist in the contraction output and hold zeros), then
+      // the bin-by-bin sums in slot order
+      const float* col = in + ((int64_t)mu * a.M_pad + slot0) * a.ld + t;
+      float x[REDUCE_SEG];
+#pragma unroll
+      for (int q = 0; q < REDUCE_SEG; ++q) x[q] = col[(int64_t)q * a.ld];
+      double s = 0.0;
+      int cur = sb[g][0];
+#pragma unroll
+      for (int q = 0; q < REDUCE_SEG; ++q) {
+        const int bq = sb[g][q];
+        if (bq != cur) {
+          if (cur >= 0) out[((int64_t)mu * P + seg + cur) * a.ld + t] = s;
+          cur = bq;
+          s = 0.0;
+        }
+        s += (double)(bq >= 0 ? x[q] : 0.f);
+      }
+      if (cur >= 0) out[((int64_t)mu * P + seg + cur) * a.ld + t] = s;
+    }
+  }
+}
+
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a) {
+  if (a.layout_g && a.t_count > 0 && a.n_seg > 0) {
+    const int TT = a.t_count <= 64 ? 64 : (a.t_count <= 128 ? 128 : 256);
+    const int G = 256 / TT;
+    hipLaunchKernelGGL(k_reduce_seg, dim3((unsigned)((a.n_seg + G - 1) / G)), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)(a.nb + 1)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -201,18 +226,22 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
 
   for (int tc = 0; tc < t_count; tc += CT) {
     // stage X rows r0.. (t-major in LDS)
+    // (loads are unconditional, from clamped in-range addresses, and the
+    // value is selected afterwards, so that they all issue back to back)
     for (int idx = tid; idx < CR * CT; idx += 256) {
       const int j = idx % CT, i = idx / CT;
       const int64_t r = r0 + i;
       const int tg = tc + j;
-      xs[j][i] = (r < R3 && tg < t_count) ? X[r * ldx + tg] : 0.0;
+      const double x = X[min(r, R3 - 1) * ldx + min(tg, t_count - 1)];
+      xs[j][i] = (r < R3 && tg < t_count) ? x : 0.0;
     }
     // ring window: q in [0, CT + CL) <-> global time g = t0 + tc - tau0 - (CL - 1) + q
     for (int idx = tid; idx < (CT + CL) * 3; idx += 256) {
       const int q = idx / 3, nu = idx % 3;
       const int64_t g = t0 + tc - tau0 - (CL - 1) + q;
       const bool ok = g >= 0 && g < t0 + t_count;
-      rs[q][nu] = ok ? ring[(g % ring_len) * 3 + nu] : 0.0;
+      const double x = ring[(max(g, (int64_t)0) % ring_len) * 3 + nu];
+      rs[q][nu] = ok ? x : 0.0;
     }
     __syncthreads();
     // lag of slot k: tau = tau0 + 4*tt + k; step j reads q = j + CL - 1 - 4*tt - k
@@ -241,21 +270,30 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
     }
     __syncthreads();
   }
+  // Neumaier update of the thread's 4 rows x 4 lags x 3: every load issues
+  // from a clamped in-range address, only the stores are conditional
   const int taub = tau0 + 4 * tt;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t r = r0 + 4 * tr + i;
-    if (r >= R3) continue;
+    const int64_t rc = min(r, R3 - 1);
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
-      const int64_t o = (r * 3 + n) * L + taub;
+      double sm[4], cp[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (taub + k >= L) continue;
-        double sm = csum[o + k], cp = ccomp[o + k];
-        neumaier_add(sm, cp, acc[i][k][n]);
-        csum[o + k] = sm;
-        ccomp[o + k] = cp;
+        const int64_t o = (rc * 3 + n) * L + min(taub + k, L - 1);
+        sm[k] = csum[o];
+        cp[k] = ccomp[o];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        neumaier_add(sm[k], cp[k], acc[i][k][n]);
+        if (r < R3 && taub + k < L) {
+          const int64_t o = (r * 3 + n) * L + taub + k;
+          csum[o] = sm[k];
+          ccomp[o] = cp[k];
+        }
       }
     }
   }

@@ -67,6 +67,9 @@ struct mhc_ctx {
   float* d_sqrtm = nullptr;
   float* d_isqrtm = nullptr;
   int32_t* d_bin_off = nullptr;
+  int32_t* d_slot_bin = nullptr;  // GKMA: bin of each slot (-1: padding)
+  double* d_seg_part = nullptr;   // GKMA: segment rows of the bin reduction
+  int n_seg = 0;
   float* d_rowscale = nullptr;  // e4m3: per-slot scale of E
   float* d_colscale = nullptr;  // e4m3: per-(channel, step) scale of the activations
   float* d_colpart = nullptr;   // e4m3: per-atom-chunk maxima behind d_colscale
@@ -495,6 +498,19 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     out_doubles = std::max(out_doubles, (size_t)2 * L * R3 * 3);
     HIP_TRY(hipMemsetAsync(pX, 0, (size_t)R3 * t_pad * 8, ctx->stream), "zero series");
     HIP_TRY(hipMemsetAsync(pring, 0, (size_t)ring_len * 3 * 8, ctx->stream), "zero ring");
+    // segment pass of the bin reduction: bin of every slot, float64 segment rows
+    const int64_t n_seg = (M_pad + REDUCE_SEG - 1) / REDUCE_SEG;
+    std::vector<int32_t> sbin(M_pad, -1);
+    for (int64_t b = 0; b < nb; ++b)
+      for (int64_t q = ctx->bin_off[b]; q < ctx->bin_off[b + 1]; ++q) sbin[q] = (int32_t)b;
+    void *psb, *psp;
+    if ((st = dev_alloc(ctx, (size_t)M_pad * 4, &psb, "slot bins"))) return st;
+    if ((st = dev_alloc(ctx, (size_t)3 * (n_seg + nb) * t_pad * 8, &psp, "segment sums"))) return st;
+    HIP_TRY(hipMemcpyAsync(psb, sbin.data(), (size_t)M_pad * 4, hipMemcpyHostToDevice, ctx->stream), "copy slot bins");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "slot bins sync");
+    ctx->d_slot_bin = reinterpret_cast<int32_t*>(psb);
+    ctx->d_seg_part = reinterpret_cast<double*>(psp);
+    ctx->n_seg = (int)n_seg;
   }
   if ((st = dev_alloc(ctx, out_doubles * 8, &pout, "read-out"))) return st;
   if (c.t_block > 1) {
@@ -598,6 +614,9 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64
   a.ld = ld;
   a.t_count = t_count;
   a.bin_off = ctx->d_bin_off;
+  a.slot_bin = ctx->d_slot_bin;
+  a.seg_part = ctx->d_seg_part;
+  a.n_seg = ctx->n_seg;
   a.nb = ctx->nb;
   a.jtot = ctx->d_jtot;
   a.hsum = ctx->d_hsum;

@@ -125,9 +125,15 @@ hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, in
 //               (if hsum) the HNEMA sums of the same steps.
 //   The last work-group distributes the per-step totals jtot[t][3]:
 //   X rows 3*nb..3*nb+2 (GKMA), the history ring (GKMA), tsum/tcomp (HNEMA).
+// GKMA layout: the slots are first summed in segments of REDUCE_SEG (bin by
+// bin inside each segment) into seg_part[mu][seg + b][ld] (float64; row seg + b
+// is unique because bins are slot-ordered), then each bin adds its segments'
+// rows in order.  slot_bin[slot] is the bin of a slot (-1: padding).
+constexpr int REDUCE_SEG = 64;
 struct ReduceArgs {
   const float* in; int layout_g; int n_parts; int64_t M_pad; int64_t ld; int t_count;
   const int32_t* bin_off; int nb;
+  const int32_t* slot_bin; double* seg_part; int n_seg;      // GKMA segment pass
   const double* jtot;
   double* hsum; double* hcomp; double* tsum; double* tcomp;  // HNEMA (may be null)
   double* X;                                                 // GKMA (may be null)
