@@ -123,12 +123,40 @@ def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
 
 
+class _StreamUse:
+    """Stream ordering of device tensors handed to a context whose stream is not
+    torch's current one: the context stream waits for the work queued so far on
+    the current stream (which produced the tensors), and each tensor is recorded
+    on the context stream so that torch's caching allocator does not hand its
+    memory out again before the context has read it."""
+
+    def __init__(self, device: int, handle: int):
+        self.device = int(device)
+        self.handle = int(handle)
+        self._stream = None
+
+    def __call__(self, *tensors):
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream == self.handle:
+            return
+        if self._stream is None:
+            dflt = torch.cuda.default_stream(self.device)
+            self._stream = dflt if dflt.cuda_stream == self.handle else \
+                torch.cuda.ExternalStream(self.handle, device=self.device)
+        self._stream.wait_stream(cur)
+        for t in tensors:
+            t.record_stream(self._stream)
+
+
 class ModalHC:
     """One system (basis, bins, configuration, accumulators) on one GPU.
 
     Device inputs are torch tensors on the context's device (passed by
     pointer); host inputs are numpy arrays.  By default work is queued on
-    torch's current stream of that device, so it orders with torch ops.
+    torch's current stream of that device, so it orders with torch ops.  With
+    another stream, each call that takes device tensors first makes that stream
+    wait for torch's current stream and records the tensors on it.
     """
 
     def __init__(self, device: int = 0, stream=None):
@@ -141,6 +169,7 @@ class ModalHC:
         if st:
             raise MhcError(st, self._lib.mhc_last_error(None).decode())
         self._h = h
+        self._use = _StreamUse(device, int(stream) if stream else 0)
         self.device = device
         self.nb = None
         self.n_atoms = None
@@ -197,6 +226,7 @@ class ModalHC:
         """rows: E^T rows [n, 3N] float64, numpy (host) or torch (device)."""
         if _is_torch(rows):
             assert rows.dtype.is_floating_point and rows.element_size() == 8 and rows.is_contiguous()
+            self._use(rows)
             self._check(self._lib.mhc_load_eigvec_rows(self._h, int(mode0), rows.shape[0], _ptr(rows), 1),
                         "load_eigvec_rows")
         else:
@@ -214,6 +244,7 @@ class ModalHC:
             assert v.is_contiguous() and W.is_contiguous() and v.element_size() == 4 and W.element_size() == 4
             assert v.shape[0] == W.shape[0] and v.numel() == v.shape[0] * self.n_atoms * 3
             assert W.numel() == W.shape[0] * self.n_atoms * 9
+            self._use(v, W)
             self._check(self._lib.mhc_push(self._h, v.shape[0], _ptr(v), _ptr(W), 1), "push")
         else:
             vv = np.ascontiguousarray(v, dtype=np.float32)
@@ -316,6 +347,7 @@ class ModalGroup:
             if dev:
                 assert v.is_contiguous() and W.is_contiguous()
                 assert v.numel() == S * sysm.n_atoms * 3 and W.numel() == S * sysm.n_atoms * 9
+                sysm._use(v, W)
             else:
                 v = np.ascontiguousarray(v, dtype=np.float32)
                 W = np.ascontiguousarray(W, dtype=np.float32)
@@ -375,6 +407,7 @@ class ModalSHC:
         if st:
             raise MhcError(st, self._lib.mhc_shc_last_error(None).decode())
         self._h = h
+        self._use = _StreamUse(device, int(stream) if stream else 0)
         self.n_atoms, self.n_lags, self.t_block = int(n_atoms), int(n_lags), int(t_block)
 
     def _check(self, st, what):
@@ -404,6 +437,7 @@ class ModalSHC:
             assert v.is_contiguous() and W.is_contiguous() and v.element_size() == 4 and W.element_size() == 4
             assert v.shape[0] == W.shape[0] and v.numel() == v.shape[0] * self.n_atoms * 3
             assert W.numel() == W.shape[0] * self.n_atoms * 9
+            self._use(v, W)
             self._check(self._lib.mhc_shc_push(self._h, v.shape[0], _ptr(v), _ptr(W), 1), "shc push")
         else:
             vv = np.ascontiguousarray(v, dtype=np.float32)

@@ -133,3 +133,60 @@ def test_rod1500_gkma_t256(prec, S):
     # lags with no time origin are exactly zero
     if S < L:
         assert np.all(g["corr"][S:] == 0)
+
+
+@pytest.mark.parametrize("prec", [3, 1])
+def test_uneven16_grouped_fullsize(prec):
+    """The 16-system uneven batch at its full sizes (512 to 8000 atoms, nb = 500,
+    L = 1000, T = 64) in the launch configuration the benchmark times: one
+    grouped push per block, graph replay, autotuned tile shape.  Two blocks
+    plus a partial one; every system against the FFT form of the oracle.
+    prec 3 = e4m3 hi/lo (bar 1e-2), 1 = split-BF16 (bar 1e-4)."""
+    import torch
+    from paper_2102_03691_amd import GKMA, HNEMA, ModalGroup, ModalHC
+    announce(f"full size uneven16 grouped prec={prec}")
+    nb, L, T, S = 500, 1000, 64, 2 * 64 + 19
+    stream = torch.cuda.Stream()
+    batch = synth.uneven_batch(0)
+    systems, data = [], []
+    for i, (edge, meth) in enumerate(batch):
+        lat = synth.BlochLattice((edge, edge, edge))
+        m = synth.masses(lat.n_atoms)
+        h = ModalHC(0, stream=stream.cuda_stream)
+        h.load_system(m, lat.frequencies)
+        h.set_bins_uniform(nb, 0.0, lat.f_max)
+        h.configure(methods=HNEMA if meth == 1 else GKMA, precision=prec, t_block=T, corr_len=L, dt=1.0)
+        M = lat.n_modes
+        chunk = max(1, min(M, (512 << 20) // (8 * 3 * lat.n_atoms)))
+        for r0 in range(0, M, chunk):
+            n = min(chunk, M - r0)
+            h.load_eigvec_rows(r0, lat.eig_rows_torch(r0, n, device="cuda:0"))
+        torch.cuda.synchronize()
+        h.finalize()
+        v, W = synth.gen_steps(300 + i, m, 0, S)
+        systems.append(h)
+        data.append((lat, m, meth, v, W))
+    grp = ModalGroup(systems, graph=True, autotune=True)
+    dv = [(torch.as_tensor(v, device="cuda:0"), torch.as_tensor(W, device="cuda:0")) for _, _, _, v, W in data]
+    torch.cuda.synchronize()
+    grp.push([v for v, _ in dv], [W for _, W in dv])
+    torch.cuda.synchronize()
+    tol = 1e-2 if prec == 3 else TOL[1]
+    worst = 0.0
+    for i, (h, (lat, m, meth, v, W)) in enumerate(zip(systems, data)):
+        kb = oracle.bin_of_mode(lat.kpoint_frequencies().ravel(), nb, 0.0, lat.f_max).reshape(lat.dims)
+        Jb = oracle.binned_current_fft(lat.dims, m, v, W, kb, nb)
+        if meth == 1:
+            avg, _, n = h.read_hnema()
+            e = rel(avg, oracle.hnema_average(Jb))
+        else:
+            g = h.read_gkma()
+            n = g["n_samples"]
+            e = rel(g["corr"], oracle.gkma_correlation(Jb, oracle.total_heat_current(v, W), L))
+        assert n == S
+        worst = max(worst, e)
+        assert e <= tol, (i, batch[i], e)
+    log(f"uneven16_fullsize_group_p{prec}", worst_rel=worst, tile_shape=grp.info()["tile_shape"])
+    grp.close()
+    for h in systems:
+        h.close()

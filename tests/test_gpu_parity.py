@@ -75,6 +75,41 @@ def test_gkma(small, prec, T, sched):
     assert got["n_samples"] == 300
 
 
+def test_side_stream_device_inputs(small):
+    """A context on a stream other than torch's current one, fed device tensors
+    that torch makes on its current stream and frees right after each call:
+    the binding orders the context stream after the producer and keeps the
+    memory from being reused until it has been read."""
+    import torch
+    from paper_2102_03691_amd import ModalHC
+    announce("side-stream device inputs bf16x3 T=64")
+    ref = small.oracle(23)
+    side = torch.cuda.Stream()
+    h = ModalHC(0, stream=side.cuda_stream)
+    h.load_system(small.m, small.freq)
+    h.set_bins_uniform(23, 0.0, small.lat.f_max)
+    h.configure(methods=HNEMA, precision=BF16X3, t_block=64)
+    for r0 in range(0, small.n_modes, 97):
+        n = min(97, small.n_modes - r0)
+        rows = small.lat.eig_rows_torch(r0, n, device="cuda:0") * 1.0     # produced on the current stream
+        h.load_eigvec_rows(r0, rows)
+        del rows
+    h.finalize()
+    s0 = 0
+    for n in (64, 64, 100, 72):
+        v = torch.as_tensor(small.v[s0:s0 + n], device="cuda:0") * 1.0
+        W = torch.as_tensor(small.W[s0:s0 + n], device="cuda:0") * 1.0
+        h.push(v, W)
+        del v, W
+        s0 += n
+    got, tot, n = h.read_hnema()
+    h.close()
+    e = rel(got, ref["hnema"])
+    log("6x6x5_side_stream_bf16x3_T64", rel_hnema=e)
+    assert n == 300 and e <= TOL[BF16X3]
+    assert rel(tot, ref["hnema_total"]) <= 1e-12
+
+
 def test_block_currents_elementwise(small):
     from paper_2102_03691_amd import ModalHC  # noqa: F401
     announce("block currents elementwise bf16x3 T=128")
