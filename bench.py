@@ -204,8 +204,10 @@ def run_shc(args):
     units_per_block = float(N) * L * T
     avg_ms = kms / max(launches, 1)
     flops = 18.0 * units_per_block                    # 9 FMAs per atom, lag and step
-    roof = {"bound": "fp64", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
-            "unit": "TFLOP/s", "traffic": None, "kernel": "k_shc_gram", "avg_launch_ms": avg_ms,
+    # plain float64 vector FMAs (no matrix-core form): bound by the FP64 vector ALU rate
+    roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
+            "unit": "TFLOP/s", "traffic": profiled_traffic(args.workload, "k_shc_gram"), "kernel": "k_shc_gram",
+            "avg_launch_ms": avg_ms,
             "launches": launches}
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {"metric": SHC_METRIC, "value": units_per_block * K / wall, "unit": "atom*lag*steps/s", "n_gpus": 1,
