@@ -83,10 +83,20 @@ typedef enum {
   MHC_PREC_FP8X3 = 3
 } mhc_precision;
 
-enum { MHC_HNEMA = 1, MHC_GKMA = 2 };   /* methods bitmask */
+/* methods bitmask.  MHC_DIRECTIONAL adds the split of every modal output by
+ * the Cartesian direction nu of the atoms' motion (Sec. II, remark after
+ * Eq. 10; closing remark of Sec. II.C: e.g. in-plane against out-of-plane
+ * motion of a 2D material):
+ *   J_n^{mu nu}(s) = Xdot_n(s) sum_i m_i^{-1/2} W_i^{mu nu}(s) e_{i,n}^nu,
+ * so that sum_nu J_n^{mu nu} = J_n^mu, and J^{mu nu}(s) = sum_i W_i^{mu nu}(s)
+ * v_i^nu(s) for the Eq. 10 total.  It costs one contraction per direction
+ * (three per block), is read with mhc_read_hnema_dir / mhc_read_gkma_dir
+ * (mhc_read_hnema and mhc_read_gkma then return the sums over nu), and is not
+ * available to grouped pushes or mhc_read_block_currents (UNSUPPORTED). */
+enum { MHC_HNEMA = 1, MHC_GKMA = 2, MHC_DIRECTIONAL = 4 };
 
 typedef struct {
-  int32_t methods;       /* MHC_HNEMA | MHC_GKMA (at least one)                     */
+  int32_t methods;       /* MHC_HNEMA | MHC_GKMA (at least one), | MHC_DIRECTIONAL   */
   int32_t precision;     /* mhc_precision                                           */
   int32_t t_block;       /* steps per contraction: 1 = per-step matrix-vector path,
                             otherwise 32..512 and a multiple of 32 (T-batched GEMM)  */
@@ -223,11 +233,29 @@ mhc_status mhc_read_hnema(mhc_ctx *ctx, double *avg, double *total_avg, int64_t 
 mhc_status mhc_read_gkma(mhc_ctx *ctx, double *corr, double *integral, double *hcacf,
                          int64_t *n_samples);
 
+/* Direction-resolved HNEMA (MHC_DIRECTIONAL):
+ *   avg        [nb][3][3]  <J_b^{mu nu}>, mu the current direction, nu the
+ *                          direction of the atoms' motion          (NULL: skip)
+ *   total_avg  [3][3]      <J^{mu nu}> = <sum_i W_i^{mu nu} v_i^nu>  (NULL: skip)
+ *   n_samples  S                                                   (NULL: skip)
+ * Errors: STATE (HNEMA or the split not enabled). */
+mhc_status mhc_read_hnema_dir(mhc_ctx *ctx, double *avg, double *total_avg, int64_t *n_samples);
+
+/* Direction-resolved GKMA (MHC_DIRECTIONAL), tau = 0 .. L-1:
+ *   corr      [L][nb][3][3][3]  <J_b^{mu nu}(t+tau) J^{mu2}(t)>, indices
+ *                               [tau][b][mu][nu][mu2]; the total current J is
+ *                               whole (not split)                   (NULL: skip)
+ *   integral  [L][nb][3][3][3]  its trapezoid running integral     (NULL: skip)
+ *   n_samples S                                                    (NULL: skip)
+ * Errors: STATE (GKMA or the split not enabled). */
+mhc_status mhc_read_gkma_dir(mhc_ctx *ctx, double *corr, double *integral, int64_t *n_samples);
+
 /* Binned modal currents of the most recent block, per step:
  *   jb  [t_count][nb][3] float64 J_b^mu(s) for the last t_count pushed steps
  *       of the last block (t_count <= the size of that block)
  * Available when GKMA is enabled (the per-step series exists only then).
- * Errors: STATE, INVALID_ARG (t_count larger than the last block). */
+ * Errors: STATE, INVALID_ARG (t_count larger than the last block),
+ * UNSUPPORTED (MHC_DIRECTIONAL: the per-step series is not kept). */
 mhc_status mhc_read_block_currents(mhc_ctx *ctx, int32_t t_count, double *jb);
 
 /* Clear accumulators, sample count and the GKMA history; keep the basis. */
@@ -281,7 +309,8 @@ enum {
 
 /* systems: n finalized contexts with the same device, stream, precision and
  * t_block > 1.  flags: MHC_GROUP_* bits.
- * Errors: INVALID_ARG, STATE (a context not finalized or per-step), OOM, HIP. */
+ * Errors: INVALID_ARG, STATE (a context not finalized or per-step),
+ * UNSUPPORTED (a context with MHC_DIRECTIONAL), OOM, HIP. */
 mhc_status mhc_group_create(mhc_ctx *const *systems, int32_t n, int32_t flags, mhc_group **out);
 mhc_status mhc_group_destroy(mhc_group *group);
 const char *mhc_group_last_error(const mhc_group *group);

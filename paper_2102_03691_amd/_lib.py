@@ -8,7 +8,7 @@ import numpy as np
 
 from . import _build
 
-HNEMA, GKMA = 1, 2
+HNEMA, GKMA, DIRECTIONAL = 1, 2, 4
 PREC_FP32, PREC_BF16X3, PREC_FP8, PREC_FP8X3 = 0, 1, 2, 3
 SCHED_AUTO, SCHED_TILES, SCHED_STREAMK, SCHED_SPLIT = 0, 1, 2, 3
 GROUP_GRAPH, GROUP_AUTOTUNE = 1, 2
@@ -67,6 +67,8 @@ def library():
         "mhc_synchronize": (i32, [vp]),
         "mhc_read_hnema": (i32, [vp, vp, vp, P(i64)]),
         "mhc_read_gkma": (i32, [vp, vp, vp, vp, P(i64)]),
+        "mhc_read_hnema_dir": (i32, [vp, vp, vp, P(i64)]),
+        "mhc_read_gkma_dir": (i32, [vp, vp, vp, P(i64)]),
         "mhc_read_block_currents": (i32, [vp, i32, vp]),
         "mhc_reset": (i32, [vp]),
         "mhc_save_state": (i32, [vp, vp, P(C.c_size_t)]),
@@ -272,6 +274,23 @@ class ModalHC:
         n = C.c_int64()
         self._check(self._lib.mhc_read_gkma(self._h, _ptr(corr), _ptr(integ), _ptr(hc), C.byref(n)), "read_gkma")
         return {"corr": corr, "integral": integ, "hcacf": hc, "n_samples": n.value}
+
+    def read_hnema_dir(self):
+        """Split by the atoms' motion direction: (avg [nb, 3 mu, 3 nu], total [3 mu, 3 nu], S)."""
+        avg = np.empty((self.nb, 3, 3), dtype=np.float64)
+        tot = np.empty((3, 3), dtype=np.float64)
+        n = C.c_int64()
+        self._check(self._lib.mhc_read_hnema_dir(self._h, _ptr(avg), _ptr(tot), C.byref(n)), "read_hnema_dir")
+        return avg, tot, n.value
+
+    def read_gkma_dir(self):
+        """<J_b^{mu nu}(t + tau) J^{mu2}(t)> and its running integral, [L, nb, 3 mu, 3 nu, 3 mu2]."""
+        L = int(self.cfg["corr_len"])
+        corr = np.empty((L, self.nb, 3, 3, 3), dtype=np.float64)
+        integ = np.empty_like(corr)
+        n = C.c_int64()
+        self._check(self._lib.mhc_read_gkma_dir(self._h, _ptr(corr), _ptr(integ), C.byref(n)), "read_gkma_dir")
+        return {"corr": corr, "integral": integ, "n_samples": n.value}
 
     def read_block_currents(self, t_count):
         out = np.empty((t_count, self.nb, 3), dtype=np.float64)

@@ -101,6 +101,17 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
       if (tid == 0) neumaier_add(a.tsum[mu], a.tcomp[mu], tot);
     }
   }
+  if (a.tdsum) {   // motion-direction split of the Eq. 10 total
+    double d3[3] = {0.0, 0.0, 0.0};
+    for (int t = tid; t < a.t_count; t += 256)
+#pragma unroll
+      for (int mu = 0; mu < 3; ++mu) d3[mu] += a.jdtot[t * 3 + mu];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const double tot = block_sum256(d3[mu], sh);
+      if (tid == 0) neumaier_add(a.tdsum[mu], a.tdcomp[mu], tot);
+    }
+  }
 }
 
 // Eq. 10 summed over atoms: one wave per step adds the float64 partials of

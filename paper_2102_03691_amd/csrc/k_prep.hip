@@ -146,12 +146,14 @@ hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, in
 // (t, cc) takes the maxima over atoms [cc A, (cc+1) A), A = COLSCALE_ATOMS,
 // into col_part[cc][c][t]; the input prep combines the chunks (max is exact
 // in any order).  With tab != NULL the input pointers are read from tab[0],
-// tab[1] (device memory), so a captured graph can be fed new inputs.
+// tab[1] (device memory), so a captured graph can be fed new inputs.  With
+// dir in {0, 1, 2} the virial channels hold column dir of W only (the
+// motion-direction split), and their maxima are taken over that column.
 __global__ void __launch_bounds__(256) k_col_scale(const float* v, const float* W,
                                                    const float* __restrict__ sqrt_m,
                                                    const float* __restrict__ inv_sqrt_m, int64_t N, int t_count,
                                                    int t_pad, float* __restrict__ col_part,
-                                                   const float* const* __restrict__ tab) {
+                                                   const float* const* __restrict__ tab, int dir) {
   __shared__ float sh[4][256];
   if (tab) {
     v = tab[0];
@@ -167,9 +169,15 @@ __global__ void __launch_bounds__(256) k_col_scale(const float* v, const float* 
       const float* Wp = W + ((int64_t)t * N + i) * 9;
       const float sm = sqrt_m[i], ism = inv_sqrt_m[i];
       m0 = fmaxf(m0, sm * fmaxf(fmaxf(fabsf(vp[0]), fabsf(vp[1])), fabsf(vp[2])));
-      m1 = fmaxf(m1, ism * fmaxf(fmaxf(fabsf(Wp[0]), fabsf(Wp[1])), fabsf(Wp[2])));
-      m2 = fmaxf(m2, ism * fmaxf(fmaxf(fabsf(Wp[3]), fabsf(Wp[4])), fabsf(Wp[5])));
-      m3 = fmaxf(m3, ism * fmaxf(fmaxf(fabsf(Wp[6]), fabsf(Wp[7])), fabsf(Wp[8])));
+      if (dir < 0) {
+        m1 = fmaxf(m1, ism * fmaxf(fmaxf(fabsf(Wp[0]), fabsf(Wp[1])), fabsf(Wp[2])));
+        m2 = fmaxf(m2, ism * fmaxf(fmaxf(fabsf(Wp[3]), fabsf(Wp[4])), fabsf(Wp[5])));
+        m3 = fmaxf(m3, ism * fmaxf(fmaxf(fabsf(Wp[6]), fabsf(Wp[7])), fabsf(Wp[8])));
+      } else {
+        m1 = fmaxf(m1, ism * fabsf(Wp[dir]));
+        m2 = fmaxf(m2, ism * fabsf(Wp[3 + dir]));
+        m3 = fmaxf(m3, ism * fabsf(Wp[6 + dir]));
+      }
     }
   }
   sh[0][threadIdx.x] = m0; sh[1][threadIdx.x] = m1; sh[2][threadIdx.x] = m2; sh[3][threadIdx.x] = m3;
@@ -184,10 +192,10 @@ __global__ void __launch_bounds__(256) k_col_scale(const float* v, const float* 
 
 hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const float* sqrt_m,
                             const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_part,
-                            const float* const* tab) {
+                            const float* const* tab, int dir) {
   const int n_cc = (int)((N + COLSCALE_ATOMS - 1) / COLSCALE_ATOMS);
   hipLaunchKernelGGL(k_col_scale, dim3((unsigned)t_pad, (unsigned)n_cc), dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m,
-                     N, t_count, t_pad, col_part, tab);
+                     N, t_count, t_pad, col_part, tab, dir);
   return hipGetLastError();
 }
 
@@ -196,6 +204,11 @@ hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const
 // Phase A: thread (tl = tid / 8, sub = tid % 8) handles atoms sub, sub+8, ...
 //          of step tl: channels into LDS and the Eq. 10 partial in float64.
 // Phase B: the LDS tile is written out in the operand layout.
+// Motion-direction split (dir in {0, 1, 2}): the virial channels keep only
+// dof alpha = dir of each atom, W_i^{mu dir} / sqrt(m_i), so the contraction
+// gives the bracket of Eq. 16 restricted to that direction; the velocity
+// channel is whole.  jd_part then receives the split Eq. 10 partials
+// sum_i W_i^{mu dir} v_i^dir beside the whole ones.
 constexpr int PREP_T = 32;
 constexpr int PREP_K = 3 * ATOMS_PER_PREP;   // 96 dofs
 
@@ -207,7 +220,8 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* v, const float*
                                                     int64_t K_pad, double* __restrict__ jt_part,
                                                     float* __restrict__ col_scale,
                                                     const float* __restrict__ col_part,
-                                                    const float* const* __restrict__ tab) {
+                                                    const float* const* __restrict__ tab, int dir,
+                                                    double* __restrict__ jd_part) {
   __shared__ float ch[4][PREP_T][PREP_K + 4];
   __shared__ float csc[4][PREP_T];
   if (tab) {   // inputs named through device memory (graph replay)
@@ -224,6 +238,7 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* v, const float*
   const int64_t i0 = (int64_t)chunk * ATOMS_PER_PREP;
 
   double j0 = 0.0, j1 = 0.0, j2 = 0.0;
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;    // split partials (dir >= 0)
 #pragma unroll
   for (int q = 0; q < ATOMS_PER_PREP / 8; ++q) {
     const int a = sub + 8 * q;
@@ -241,12 +256,18 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* v, const float*
 #pragma unroll
       for (int mu = 0; mu < 3; ++mu)
 #pragma unroll
-        for (int nu = 0; nu < 3; ++nu) w[mu][nu] = Wl[3 * mu + nu] * ism;
+        for (int nu = 0; nu < 3; ++nu) w[mu][nu] = (dir < 0 || nu == dir) ? Wl[3 * mu + nu] * ism : 0.f;
       // Eq. 10 in float64: J^mu += sum_nu W^{mu nu} v^nu
       const double dvx = vx, dvy = vy, dvz = vz;
       j0 += (double)Wl[0] * dvx + (double)Wl[1] * dvy + (double)Wl[2] * dvz;
       j1 += (double)Wl[3] * dvx + (double)Wl[4] * dvy + (double)Wl[5] * dvz;
       j2 += (double)Wl[6] * dvx + (double)Wl[7] * dvy + (double)Wl[8] * dvz;
+      if (dir >= 0) {
+        const double vd = dir == 0 ? dvx : (dir == 1 ? dvy : dvz);
+        d0 += (double)Wl[dir] * vd;
+        d1 += (double)Wl[3 + dir] * vd;
+        d2 += (double)Wl[6 + dir] * vd;
+      }
     }
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
@@ -266,6 +287,18 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* v, const float*
   if (sub == 0 && t < t_pad) {
     double* jp = jt_part + ((int64_t)t * n_chunks + chunk) * 3;
     jp[0] = j0; jp[1] = j1; jp[2] = j2;
+  }
+  if (dir >= 0) {
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      d0 += __shfl_xor(d0, off);
+      d1 += __shfl_xor(d1, off);
+      d2 += __shfl_xor(d2, off);
+    }
+    if (sub == 0 && t < t_pad) {
+      double* jp = jd_part + ((int64_t)t * n_chunks + chunk) * 3;
+      jp[0] = d0; jp[1] = d1; jp[2] = d2;
+    }
   }
   __syncthreads();
 
@@ -371,12 +404,12 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* v, const float*
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
                              const float* sqrt_m, const float* inv_sqrt_m, int64_t N, int t_count, int t_pad,
                              void* B, int64_t K_pad, double* jt_part, float* col_scale,
-                             const float* col_part, const float* const* tab) {
+                             const float* col_part, const float* const* tab, int dir, double* jd_part) {
   const int n_chunks = (int)((N + ATOMS_PER_PREP - 1) / ATOMS_PER_PREP);
   dim3 grid((unsigned)n_chunks, (unsigned)((t_pad + PREP_T - 1) / PREP_T));
 #define MHC_PREP(M)                                                                                          \
   hipLaunchKernelGGL(k_input_prep<M>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad, B, \
-                     K_pad, jt_part, col_scale, col_part, tab)
+                     K_pad, jt_part, col_scale, col_part, tab, dir, jd_part)
   if (plain) MHC_PREP(0);
   else if (prec == PREC_FP32) MHC_PREP(1);
   else if (prec == PREC_BF16X3) MHC_PREP(2);

@@ -85,6 +85,10 @@ struct mhc_ctx {
   float* d_v = nullptr;
   float* d_W = nullptr;
   double *d_hsum = nullptr, *d_hcomp = nullptr, *d_tsum = nullptr, *d_tcomp = nullptr;
+  int n_dir = 1;                 // 3 with the motion-direction split (one pass per direction)
+  double* d_jd = nullptr;        // split Eq. 10 partials of the current pass
+  double* d_jdtot = nullptr;     // split Eq. 10 per-step totals
+  double *d_tdsum = nullptr, *d_tdcomp = nullptr;   // [dir][mu] time sums of the split totals
   double* dX = nullptr;
   double* d_ring = nullptr;
   int64_t ring_len = 0;
@@ -324,7 +328,8 @@ mhc_status mhc_configure(mhc_ctx* ctx, const mhc_run_config* cfg) {
   if (st) return st;
   if (!ctx->has_system || ctx->rows_started) return fail(ctx, MHC_ERR_STATE, "configure needs a system and no rows yet");
   if (!cfg) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL config");
-  if (cfg->methods < 1 || cfg->methods > 3) return fail(ctx, MHC_ERR_INVALID_ARG, "methods must be HNEMA, GKMA or both");
+  if (cfg->methods < 1 || cfg->methods > 7 || !(cfg->methods & (MHC_HNEMA | MHC_GKMA)))
+    return fail(ctx, MHC_ERR_INVALID_ARG, "methods must be HNEMA, GKMA or both, optionally with DIRECTIONAL");
   if (cfg->precision < MHC_PREC_FP32 || cfg->precision > MHC_PREC_FP8X3)
     return fail(ctx, MHC_ERR_INVALID_ARG, "unknown precision");
   if (cfg->t_block != 1 && (cfg->t_block < 32 || cfg->t_block > 512 || cfg->t_block % 32))
@@ -441,6 +446,14 @@ mhc_status mhc_load_eigvec_rows(mhc_ctx* ctx, int64_t mode0, int64_t n_rows, con
 
 static int t_pad_of(const mhc_run_config& c) { return c.t_block == 1 ? 256 : c.t_block; }
 
+// HNEMA accumulator doubles: bin sums and compensations [dir][nb][3], the
+// Eq. 10 total and its compensation [3], and with the split the split totals
+// and compensations [dir][3].
+static size_t hn_doubles(int64_t nb, int nd) { return (size_t)2 * nd * nb * 3 + 6 + (nd > 1 ? 18 : 0); }
+
+// GKMA correlation doubles (sums and compensations of every direction pass).
+static size_t gk_doubles(const mhc_ctx* c) { return (size_t)2 * c->n_dir * c->cfg.corr_len * c->R3 * 3; }
+
 mhc_status mhc_finalize(mhc_ctx* ctx) {
   mhc_status st = enter(ctx);
   if (st) return st;
@@ -481,20 +494,30 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     if ((st = dev_alloc(ctx, (size_t)n_cc * 4 * t_pad * 4, &pcp, "column maxima"))) return st;
     ctx->d_colpart = reinterpret_cast<float*>(pcp);
   }
-  const size_t acc_doubles = (size_t)(4 * nb * 3 + 4 * 3);
+  const int nd = (c.methods & MHC_DIRECTIONAL) ? 3 : 1;
+  ctx->n_dir = nd;
+  const size_t acc_doubles = hn_doubles(nb, nd);
   if ((st = dev_alloc(ctx, acc_doubles * 8, &pacc, "HNEMA sums"))) return st;
-  size_t out_doubles = (size_t)nb * 3 + 3;
+  size_t out_doubles = (size_t)nd * nb * 3 + 12;
+  if (nd > 1) {
+    void *pjd, *pjdt;
+    if ((st = dev_alloc(ctx, (size_t)t_pad * n_ac * 3 * 8, &pjd, "split total partials"))) return st;
+    if ((st = dev_alloc(ctx, (size_t)t_pad * 3 * 8, &pjdt, "split total current"))) return st;
+    HIP_TRY(hipMemsetAsync(pjd, 0, (size_t)t_pad * n_ac * 3 * 8, ctx->stream), "zero split partials");
+    ctx->d_jd = reinterpret_cast<double*>(pjd);
+    ctx->d_jdtot = reinterpret_cast<double*>(pjdt);
+  }
   if (gk) {
     void *pX, *pring, *pc;
     const int64_t ring_len = (int64_t)L - 1 + t_pad;
     if ((st = dev_alloc(ctx, (size_t)R3 * t_pad * 8, &pX, "binned series"))) return st;
     if ((st = dev_alloc(ctx, (size_t)ring_len * 3 * 8, &pring, "history ring"))) return st;
-    if ((st = dev_alloc(ctx, (size_t)2 * L * R3 * 3 * 8, &pc, "correlation sums"))) return st;
+    if ((st = dev_alloc(ctx, (size_t)2 * nd * L * R3 * 3 * 8, &pc, "correlation sums"))) return st;
     ctx->dX = reinterpret_cast<double*>(pX);
     ctx->d_ring = reinterpret_cast<double*>(pring);
     ctx->ring_len = ring_len;
     ctx->d_csum = reinterpret_cast<double*>(pc);
-    ctx->d_ccomp = ctx->d_csum + (size_t)L * R3 * 3;
+    ctx->d_ccomp = ctx->d_csum + (size_t)nd * L * R3 * 3;
     out_doubles = std::max(out_doubles, (size_t)2 * L * R3 * 3);
     HIP_TRY(hipMemsetAsync(pX, 0, (size_t)R3 * t_pad * 8, ctx->stream), "zero series");
     HIP_TRY(hipMemsetAsync(pring, 0, (size_t)ring_len * 3 * 8, ctx->stream), "zero ring");
@@ -556,9 +579,11 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
   ctx->d_bin_off = reinterpret_cast<int32_t*>(poff);
   double* acc = reinterpret_cast<double*>(pacc);
   ctx->d_hsum = hn ? acc : nullptr;
-  ctx->d_hcomp = hn ? acc + nb * 3 : nullptr;
-  ctx->d_tsum = hn ? acc + 2 * nb * 3 : nullptr;
-  ctx->d_tcomp = hn ? acc + 2 * nb * 3 + 3 : nullptr;
+  ctx->d_hcomp = hn ? acc + nd * nb * 3 : nullptr;
+  ctx->d_tsum = hn ? acc + 2 * nd * nb * 3 : nullptr;
+  ctx->d_tcomp = hn ? acc + 2 * nd * nb * 3 + 3 : nullptr;
+  ctx->d_tdsum = (hn && nd > 1) ? acc + 2 * nd * nb * 3 + 6 : nullptr;
+  ctx->d_tdcomp = (hn && nd > 1) ? acc + 2 * nd * nb * 3 + 15 : nullptr;
   ctx->R3 = R3;
   ctx->d_out = reinterpret_cast<double*>(pout);
   ctx->finalized = true;
@@ -571,9 +596,8 @@ mhc_status mhc_reset(mhc_ctx* ctx) {
   if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "reset needs a finalized context");
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   const int64_t nb = ctx->nb;
-  if (ctx->d_hsum) HIP_TRY(hipMemsetAsync(ctx->d_hsum, 0, (size_t)(2 * nb * 3 + 6) * 8, ctx->stream), "zero sums");
-  if (ctx->d_csum)
-    HIP_TRY(hipMemsetAsync(ctx->d_csum, 0, (size_t)2 * ctx->cfg.corr_len * ctx->R3 * 3 * 8, ctx->stream), "zero corr");
+  if (ctx->d_hsum) HIP_TRY(hipMemsetAsync(ctx->d_hsum, 0, hn_doubles(nb, ctx->n_dir) * 8, ctx->stream), "zero sums");
+  if (ctx->d_csum) HIP_TRY(hipMemsetAsync(ctx->d_csum, 0, gk_doubles(ctx) * 8, ctx->stream), "zero corr");
   if (ctx->d_ring) HIP_TRY(hipMemsetAsync(ctx->d_ring, 0, (size_t)ctx->ring_len * 3 * 8, ctx->stream), "zero ring");
   ctx->n_samples = 0;
   ctx->last_block = 0;
@@ -584,15 +608,15 @@ mhc_status mhc_reset(mhc_ctx* ctx) {
 // With tab != NULL the input pointers are read from device memory (tab[0] =
 // v, tab[1] = W) when the kernels run.
 static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int t_count,
-                              const float* const* tab = nullptr) {
+                              const float* const* tab = nullptr, int dir = -1) {
   const auto& c = ctx->cfg;
   if (ctx->d_colscale)
     HIP_TRY(launch_col_scale(ctx->stream, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count, ctx->t_pad,
-                             ctx->d_colpart, tab),
+                             ctx->d_colpart, tab, dir),
             "column scales");
   HIP_TRY(launch_input_prep(ctx->stream, c.precision, c.t_block == 1 ? 1 : 0, v, W, ctx->d_sqrtm, ctx->d_isqrtm,
                             ctx->N, t_count, ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt, ctx->d_colscale,
-                            ctx->d_colpart, tab),
+                            ctx->d_colpart, tab, dir, ctx->d_jd),
           "input prep");
   return MHC_OK;
 }
@@ -601,11 +625,17 @@ static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int 
 // With t0_dev the block's first step index is read from device memory when
 // the kernels run (the group's input table), so a captured graph can be
 // replayed block after block.
-static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64_t* t0_dev) {
+// With the motion-direction split, pass dir in {0, 1, 2} accumulates into its
+// own slice of the bin sums and correlation sums; the whole Eq. 10 total is
+// summed in pass 0 only (every pass rewrites the same GKMA history entries).
+static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64_t* t0_dev, int dir = -1) {
   const auto& c = ctx->cfg;
   const bool gk = c.methods & MHC_GKMA;
   const int64_t ld = ctx->t_pad;
+  const int d = dir < 0 ? 0 : dir;
   HIP_TRY(launch_total(ctx->stream, ctx->d_jt, ctx->n_atom_chunks, t_count, ctx->d_jtot), "total current");
+  if (dir >= 0 && ctx->d_tdsum)
+    HIP_TRY(launch_total(ctx->stream, ctx->d_jd, ctx->n_atom_chunks, t_count, ctx->d_jdtot), "split total current");
   ReduceArgs a{};
   a.in = ctx->dJ;
   a.layout_g = gk ? 1 : 0;
@@ -619,10 +649,15 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64
   a.n_seg = ctx->n_seg;
   a.nb = ctx->nb;
   a.jtot = ctx->d_jtot;
-  a.hsum = ctx->d_hsum;
-  a.hcomp = ctx->d_hcomp;
-  a.tsum = ctx->d_tsum;
-  a.tcomp = ctx->d_tcomp;
+  a.hsum = ctx->d_hsum ? ctx->d_hsum + (int64_t)d * ctx->nb * 3 : nullptr;
+  a.hcomp = ctx->d_hcomp ? ctx->d_hcomp + (int64_t)d * ctx->nb * 3 : nullptr;
+  a.tsum = d == 0 ? ctx->d_tsum : nullptr;
+  a.tcomp = d == 0 ? ctx->d_tcomp : nullptr;
+  if (dir >= 0 && ctx->d_tdsum) {
+    a.jdtot = ctx->d_jdtot;
+    a.tdsum = ctx->d_tdsum + 3 * dir;
+    a.tdcomp = ctx->d_tdcomp + 3 * dir;
+  }
   a.X = gk ? ctx->dX : nullptr;
   a.ring = ctx->d_ring;
   a.ring_len = ctx->ring_len;
@@ -630,8 +665,9 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64
   a.t0_dev = t0_dev;
   HIP_TRY(launch_reduce(ctx->stream, a), "bin reduce");
   if (gk) {
+    const size_t off = (size_t)d * c.corr_len * ctx->R3 * 3;
     HIP_TRY(launch_corr(ctx->stream, ctx->dX, ld, t_count, ctx->R3, c.corr_len, ctx->d_ring, ctx->ring_len,
-                        ctx->n_samples, ctx->d_csum, ctx->d_ccomp, t0_dev),
+                        ctx->n_samples, ctx->d_csum + off, ctx->d_ccomp + off, t0_dev),
             "correlation");
   }
   return MHC_OK;
@@ -654,28 +690,34 @@ static mhc_status timing_begin(mhc_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1) {
   return MHC_OK;
 }
 
+// One block of t_count steps: front, contraction, back; with the
+// motion-direction split, one such pass per direction (the contraction is
+// the same kernel on the masked operand).
 static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_count) {
   const auto& c = ctx->cfg;
   const bool gk = c.methods & MHC_GKMA;
-  mhc_status st = block_front(ctx, v, W, t_count);
-  if (st) return st;
-  hipEvent_t e0, e1;
-  if ((st = timing_begin(ctx, &e0, &e1))) return st;
-  int n_parts = 0;
-  if (c.t_block == 1) {
-    HIP_TRY(launch_gemv_f32(ctx->stream, reinterpret_cast<const float*>(ctx->dE),
-                            reinterpret_cast<const float*>(ctx->dB), t_count, ctx->M_pad, ctx->K_pad, ctx->dJ,
-                            gk ? 1 : 0, ctx->t_pad),
-            "per-step contraction");
-    n_parts = t_count;
-  } else {
-    HIP_TRY(launch_gemm(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32, ctx->dJ,
-                        gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->d_tile_cnt, ctx->n_cu, c.schedule,
-                        ctx->d_rowscale, ctx->d_colscale, &ctx->last_sched),
-            "batched contraction");
+  mhc_status st;
+  for (int d = 0; d < ctx->n_dir; ++d) {
+    const int dir = ctx->n_dir > 1 ? d : -1;
+    if ((st = block_front(ctx, v, W, t_count, nullptr, dir))) return st;
+    hipEvent_t e0, e1;
+    if ((st = timing_begin(ctx, &e0, &e1))) return st;
+    int n_parts = 0;
+    if (c.t_block == 1) {
+      HIP_TRY(launch_gemv_f32(ctx->stream, reinterpret_cast<const float*>(ctx->dE),
+                              reinterpret_cast<const float*>(ctx->dB), t_count, ctx->M_pad, ctx->K_pad, ctx->dJ,
+                              gk ? 1 : 0, ctx->t_pad),
+              "per-step contraction");
+      n_parts = t_count;
+    } else {
+      HIP_TRY(launch_gemm(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32,
+                          ctx->dJ, gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->d_tile_cnt, ctx->n_cu,
+                          c.schedule, ctx->d_rowscale, ctx->d_colscale, &ctx->last_sched),
+              "batched contraction");
+    }
+    if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
+    if ((st = block_back(ctx, t_count, n_parts, nullptr, dir))) return st;
   }
-  if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
-  if ((st = block_back(ctx, t_count, n_parts, nullptr))) return st;
   ctx->n_samples += t_count;
   ctx->last_block = t_count;
   return MHC_OK;
@@ -719,20 +761,75 @@ mhc_status mhc_synchronize(mhc_ctx* ctx) {
   return MHC_OK;
 }
 
+// Finished HNEMA averages on the host: h[0 .. nd*nb*3) = bin averages
+// [dir][b][mu], then the Eq. 10 total [3], then (split) the split totals [dir][mu].
+static mhc_status hnema_finished(mhc_ctx* ctx, std::vector<double>& h) {
+  const int nd = ctx->n_dir;
+  const int64_t n = (int64_t)nd * ctx->nb * 3;
+  HIP_TRY(launch_hnema_finish(ctx->stream, ctx->d_hsum, ctx->d_hcomp, n, ctx->n_samples, ctx->d_out), "finish");
+  HIP_TRY(launch_hnema_finish(ctx->stream, ctx->d_tsum, ctx->d_tcomp, 3, ctx->n_samples, ctx->d_out + n), "finish");
+  if (nd > 1)
+    HIP_TRY(launch_hnema_finish(ctx->stream, ctx->d_tdsum, ctx->d_tdcomp, 9, ctx->n_samples, ctx->d_out + n + 3),
+            "finish");
+  h.resize(n + 3 + (nd > 1 ? 9 : 0));
+  HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
+  return MHC_OK;
+}
+
 mhc_status mhc_read_hnema(mhc_ctx* ctx, double* avg, double* total_avg, int64_t* n_samples) {
   mhc_status st = enter(ctx);
   if (st) return st;
   if (!ctx->finalized || !(ctx->cfg.methods & MHC_HNEMA)) return fail(ctx, MHC_ERR_STATE, "HNEMA not enabled");
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  std::vector<double> h;
+  if ((st = hnema_finished(ctx, h))) return st;
   const int64_t n = ctx->nb * 3;
-  HIP_TRY(launch_hnema_finish(ctx->stream, ctx->d_hsum, ctx->d_hcomp, n, ctx->n_samples, ctx->d_out), "finish");
-  HIP_TRY(launch_hnema_finish(ctx->stream, ctx->d_tsum, ctx->d_tcomp, 3, ctx->n_samples, ctx->d_out + n), "finish");
-  std::vector<double> h(n + 3);
-  HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, (n + 3) * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
-  HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
-  if (avg) std::memcpy(avg, h.data(), n * 8);
-  if (total_avg) std::memcpy(total_avg, h.data() + n, 24);
+  const int nd = ctx->n_dir;
+  if (avg) {
+    // the whole current is the sum of the direction slices, in direction order
+    for (int64_t e = 0; e < n; ++e) {
+      double a = h[e];
+      for (int d = 1; d < nd; ++d) a += h[(size_t)d * n + e];
+      avg[e] = a;
+    }
+  }
+  if (total_avg) std::memcpy(total_avg, h.data() + (size_t)nd * n, 24);
   if (n_samples) *n_samples = ctx->n_samples;
+  return MHC_OK;
+}
+
+mhc_status mhc_read_hnema_dir(mhc_ctx* ctx, double* avg, double* total_avg, int64_t* n_samples) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized || !(ctx->cfg.methods & MHC_HNEMA) || ctx->n_dir == 1)
+    return fail(ctx, MHC_ERR_STATE, "HNEMA with the direction split not enabled");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  std::vector<double> h;
+  if ((st = hnema_finished(ctx, h))) return st;
+  const int64_t nb = ctx->nb, n = nb * 3;
+  if (avg)
+    for (int d = 0; d < 3; ++d)
+      for (int64_t b = 0; b < nb; ++b)
+        for (int mu = 0; mu < 3; ++mu) avg[(b * 3 + mu) * 3 + d] = h[(size_t)d * n + b * 3 + mu];
+  if (total_avg)
+    for (int d = 0; d < 3; ++d)
+      for (int mu = 0; mu < 3; ++mu) total_avg[mu * 3 + d] = h[(size_t)3 * n + 3 + d * 3 + mu];
+  if (n_samples) *n_samples = ctx->n_samples;
+  return MHC_OK;
+}
+
+// Finished correlation and running integral of direction pass d on the host:
+// h[0 .. per) = corr[tau][r][nu], h[per .. 2 per) = integral, r = 3 b + mu.
+static mhc_status gkma_finished(mhc_ctx* ctx, int d, std::vector<double>& h) {
+  const int L = ctx->cfg.corr_len;
+  const size_t per = (size_t)L * ctx->R3 * 3;
+  HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_csum + d * per, ctx->d_ccomp + d * per, ctx->R3, L, ctx->n_samples,
+                             ctx->cfg.dt, ctx->d_out, ctx->d_out + per),
+          "finish");
+  h.resize(2 * per);
+  HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, 2 * per * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
   return MHC_OK;
 }
 
@@ -744,17 +841,50 @@ mhc_status mhc_read_gkma(mhc_ctx* ctx, double* corr, double* integral, double* h
   const int L = ctx->cfg.corr_len;
   const int64_t R3 = ctx->R3, nb = ctx->nb;
   const size_t per = (size_t)L * R3 * 3;
-  HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_csum, ctx->d_ccomp, R3, L, ctx->n_samples, ctx->cfg.dt, ctx->d_out,
-                             ctx->d_out + per),
-          "finish");
-  std::vector<double> h(2 * per);
-  HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, 2 * per * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
-  HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
+  std::vector<double> h, acc;
+  for (int d = 0; d < ctx->n_dir; ++d) {
+    if ((st = gkma_finished(ctx, d, h))) return st;
+    if (d == 0) {
+      acc = h;
+    } else {   // the whole current is the sum of the direction slices, in direction order
+      for (size_t e = 0; e < 2 * per; ++e) acc[e] += h[e];
+    }
+  }
   for (int tau = 0; tau < L; ++tau) {
-    const double* src = h.data() + (size_t)tau * R3 * 3;
+    const double* src = acc.data() + (size_t)tau * R3 * 3;
     if (corr) std::memcpy(corr + (size_t)tau * nb * 9, src, nb * 9 * 8);
-    if (hcacf) std::memcpy(hcacf + (size_t)tau * 9, src + nb * 9, 9 * 8);
-    if (integral) std::memcpy(integral + (size_t)tau * nb * 9, h.data() + per + (size_t)tau * R3 * 3, nb * 9 * 8);
+    if (integral) std::memcpy(integral + (size_t)tau * nb * 9, acc.data() + per + (size_t)tau * R3 * 3, nb * 9 * 8);
+  }
+  if (hcacf) {   // the total current's rows are the same in every pass: take pass 0
+    if (ctx->n_dir > 1 && (st = gkma_finished(ctx, 0, h))) return st;
+    const std::vector<double>& h0 = ctx->n_dir > 1 ? h : acc;
+    for (int tau = 0; tau < L; ++tau) std::memcpy(hcacf + (size_t)tau * 9, h0.data() + (size_t)tau * R3 * 3 + nb * 9, 9 * 8);
+  }
+  if (n_samples) *n_samples = ctx->n_samples;
+  return MHC_OK;
+}
+
+mhc_status mhc_read_gkma_dir(mhc_ctx* ctx, double* corr, double* integral, int64_t* n_samples) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized || !(ctx->cfg.methods & MHC_GKMA) || ctx->n_dir == 1)
+    return fail(ctx, MHC_ERR_STATE, "GKMA with the direction split not enabled");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const int L = ctx->cfg.corr_len;
+  const int64_t R3 = ctx->R3, nb = ctx->nb;
+  const size_t per = (size_t)L * R3 * 3;
+  std::vector<double> h;
+  for (int d = 0; d < 3; ++d) {
+    if ((st = gkma_finished(ctx, d, h))) return st;
+    for (int tau = 0; tau < L; ++tau)
+      for (int64_t b = 0; b < nb; ++b)
+        for (int mu = 0; mu < 3; ++mu)
+          for (int m2 = 0; m2 < 3; ++m2) {
+            const size_t src = ((size_t)tau * R3 + b * 3 + mu) * 3 + m2;
+            const size_t dst = ((((size_t)tau * nb + b) * 3 + mu) * 3 + d) * 3 + m2;
+            if (corr) corr[dst] = h[src];
+            if (integral) integral[dst] = h[per + src];
+          }
   }
   if (n_samples) *n_samples = ctx->n_samples;
   return MHC_OK;
@@ -764,6 +894,7 @@ mhc_status mhc_read_block_currents(mhc_ctx* ctx, int32_t t_count, double* jb) {
   mhc_status st = enter(ctx);
   if (st) return st;
   if (!ctx->finalized || !(ctx->cfg.methods & MHC_GKMA)) return fail(ctx, MHC_ERR_STATE, "GKMA not enabled");
+  if (ctx->n_dir > 1) return fail(ctx, MHC_ERR_UNSUPPORTED, "block currents are not kept with the direction split");
   if (t_count < 0 || t_count > ctx->last_block) return fail(ctx, MHC_ERR_INVALID_ARG, "t_count exceeds the last block");
   if (t_count == 0) return MHC_OK;
   if (!jb) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL output");
@@ -791,8 +922,8 @@ constexpr uint64_t kMagic = 0x4D48435354415431ull;  // "MHCSTAT1"
 
 static size_t state_bytes(const mhc_ctx* c) {
   size_t n = sizeof(StateHeader);
-  if (c->d_hsum) n += (size_t)(2 * c->nb * 3 + 6) * 8;
-  if (c->d_csum) n += (size_t)2 * c->cfg.corr_len * c->R3 * 3 * 8 + (size_t)c->ring_len * 3 * 8;
+  if (c->d_hsum) n += hn_doubles(c->nb, c->n_dir) * 8;
+  if (c->d_csum) n += gk_doubles(c) * 8 + (size_t)c->ring_len * 3 * 8;
   return n;
 }
 
@@ -814,12 +945,12 @@ mhc_status mhc_save_state(mhc_ctx* ctx, void* buf, size_t* len) {
   std::memcpy(p, &hd, sizeof hd);
   p += sizeof hd;
   if (ctx->d_hsum) {
-    const size_t n = (size_t)(2 * ctx->nb * 3 + 6) * 8;
+    const size_t n = hn_doubles(ctx->nb, ctx->n_dir) * 8;
     HIP_TRY(hipMemcpyAsync(p, ctx->d_hsum, n, hipMemcpyDeviceToHost, ctx->stream), "save");
     p += n;
   }
   if (ctx->d_csum) {
-    const size_t n = (size_t)2 * ctx->cfg.corr_len * ctx->R3 * 3 * 8;
+    const size_t n = gk_doubles(ctx) * 8;
     HIP_TRY(hipMemcpyAsync(p, ctx->d_csum, n, hipMemcpyDeviceToHost, ctx->stream), "save");
     p += n;
     const size_t r = (size_t)ctx->ring_len * 3 * 8;
@@ -844,12 +975,12 @@ mhc_status mhc_load_state(mhc_ctx* ctx, const void* buf, size_t len) {
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   const char* p = reinterpret_cast<const char*>(buf) + sizeof hd;
   if (ctx->d_hsum) {
-    const size_t n = (size_t)(2 * ctx->nb * 3 + 6) * 8;
+    const size_t n = hn_doubles(ctx->nb, ctx->n_dir) * 8;
     HIP_TRY(hipMemcpyAsync(ctx->d_hsum, p, n, hipMemcpyHostToDevice, ctx->stream), "load");
     p += n;
   }
   if (ctx->d_csum) {
-    const size_t n = (size_t)2 * ctx->cfg.corr_len * ctx->R3 * 3 * 8;
+    const size_t n = gk_doubles(ctx) * 8;
     HIP_TRY(hipMemcpyAsync(ctx->d_csum, p, n, hipMemcpyHostToDevice, ctx->stream), "load");
     p += n;
     const size_t r = (size_t)ctx->ring_len * 3 * 8;
@@ -1129,6 +1260,7 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
     if (!c) return MHC_ERR_INVALID_ARG;
     if (c->sticky) return c->sticky;
     if (!c->finalized || c->cfg.t_block == 1) return MHC_ERR_STATE;
+    if (c->n_dir > 1) return MHC_ERR_UNSUPPORTED;   // grouped pushes run one pass per block
     if (c->device != c0->device || c->stream != c0->stream || c->cfg.precision != c0->cfg.precision ||
         c->cfg.t_block != c0->cfg.t_block)
       return MHC_ERR_INVALID_ARG;

@@ -51,10 +51,11 @@ hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, in
 // Maxima behind the per-(channel, step) scales of the e4m3 activations, per
 // chunk of COLSCALE_ATOMS atoms: col_part[chunk][c][t_pad] (the input prep
 // turns them into col_scale).  With tab != NULL, v and W are ignored and read
-// from tab[0], tab[1] (device).
+// from tab[0], tab[1] (device).  dir = -1: whole virial rows; dir in {0,1,2}:
+// the virial channels of the motion-direction split (column dir of W only).
 hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const float* sqrt_m,
                             const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_part,
-                            const float* const* tab);
+                            const float* const* tab, int dir);
 
 // Input preparation for one block of t_pad columns (t_count real steps):
 // B operand in the layout of `prec` (or plain when plain != 0) and the
@@ -62,10 +63,15 @@ hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const
 // e4m3 precisions divide by col_scale[c][t] = max over chunks of col_part
 // / 448 (1 for a zero column), which the chunk-0 work-groups also store in
 // col_scale for the contraction epilogue.  tab as for launch_col_scale.
+// dir in {0,1,2} builds the virial channels of the motion-direction split
+// (W_i^{mu dir} / sqrt(m_i) on dof alpha = dir only) and writes the split
+// partial currents sum_i W_i^{mu dir} v_i^dir to jd_part[t][chunk][3];
+// dir = -1 builds the whole operand and leaves jd_part alone.
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
                              const float* sqrt_m, const float* inv_sqrt_m, int64_t N,
                              int t_count, int t_pad, void* B, int64_t K_pad, double* jt_part,
-                             float* col_scale, const float* col_part, const float* const* tab);
+                             float* col_scale, const float* col_part, const float* const* tab, int dir,
+                             double* jd_part);
 
 // Per-step matrix-vector path (FP32): for steps t = 0..n_steps-1 of a plain
 // B buffer, J_n^mu = Xdot_n A_n^mu for every slot.  Output either
@@ -139,6 +145,7 @@ struct ReduceArgs {
   double* X;                                                 // GKMA (may be null)
   double* ring; int64_t ring_len; int64_t t0;                // GKMA history
   const int64_t* t0_dev;    // if set, the block's first step index is read here instead of t0
+  const double* jdtot; double* tdsum; double* tdcomp;        // split Eq. 10 totals (may be null)
 };
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a);
 

@@ -62,6 +62,8 @@ def test_null_context_and_null_pointers_are_invalid_arg():
     assert lib.mhc_load_system(None, 1, None, 1, None) == 1
     assert lib.mhc_push(None, 1, None, None, 0) == 1
     assert lib.mhc_finalize(None) == 1
+    assert lib.mhc_read_hnema_dir(None, None, None, None) == 1
+    assert lib.mhc_read_gkma_dir(None, None, None, None) == 1
     assert lib.mhc_create(0, None, None) == 1
     assert lib.mhc_destroy(None) == 0
 
