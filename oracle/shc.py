@@ -47,6 +47,23 @@ def shc_correlation(v: np.ndarray, W: np.ndarray, n_lags: int) -> np.ndarray:
     return K
 
 
+def shc_correlation_directional(v: np.ndarray, W: np.ndarray, n_lags: int) -> np.ndarray:
+    """Eq. 21 split by the direction nu of the atoms' motion (Sec. II, remark
+    after Eq. 10; closing remark of Sec. II.C):
+    K[tau, mu, nu] = <sum_i W_i^{mu nu}(s) v_i^nu(s + tau)> over the S - tau
+    origins; the sum over nu is Eq. 21.  Shape [n_lags, 3, 3]."""
+    v = np.asarray(v, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    S = v.shape[0]
+    K = np.zeros((n_lags, 3, 3), dtype=np.float64)
+    for tau in range(min(n_lags, S)):
+        early = W[: S - tau]             # W_i^{mu nu}(s)
+        late = v[tau:]                   # v_i^nu(s + tau)
+        # sum over origins s and atoms i; nu is kept, not contracted
+        K[tau] = np.einsum("simn,sin->mn", early, late) / (S - tau)
+    return K
+
+
 def shc_weights(n_lags: int, window: bool = False) -> np.ndarray:
     """Weights c_tau of the even-extension trapezoid rule (times the Hann window
     when ``window``): c_0 = 1, c_tau = 2 inside, c_{n-1} = 1."""

@@ -143,3 +143,44 @@ def test_package_shc_kappa_units():
     per THz of f = omega / (2 pi): times 2 pi 1e12."""
     from paper_2102_03691_amd.physics import shc_kappa
     assert math.isclose(shc_kappa(1.0, 1.0, 1.0, 1.0), 2 * 1.602176634e-9 * 2 * math.pi * 1e12, rel_tol=1e-15)
+
+
+# ------------------------------------------------------- motion-direction split
+def test_golden_directional_split():
+    """The fixture's only virial entries are W_0^{xy} and W_1^{zx}: K^x comes from
+    atom 0 moving along y and K^z from atom 1 moving along x; every other
+    (mu, nu) pair is zero, although v_0^x is nonzero."""
+    v, W, K, _ = _fixture()
+    Kd = oracle.shc_correlation_directional(v, W, 3)
+    expect = np.zeros((3, 3, 3))
+    expect[:, 0, 1] = K[:, 0]
+    expect[:, 2, 0] = K[:, 2]
+    assert np.allclose(Kd, expect, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_directional_sums_to_eq21_and_matches_loops(seed):
+    rng = np.random.default_rng(seed)
+    S, N, L = 7, 4, 9
+    v = rng.standard_normal((S, N, 3))
+    W = rng.standard_normal((S, N, 3, 3))
+    Kd = oracle.shc_correlation_directional(v, W, L)
+    assert np.allclose(Kd.sum(axis=2), oracle.shc_correlation(v, W, L), rtol=1e-13, atol=1e-15)
+    # brute force per direction: only the nu column of W and the nu component of v
+    for nu in range(3):
+        Wn = np.zeros_like(W)
+        Wn[:, :, :, nu] = W[:, :, :, nu]
+        assert np.allclose(Kd[:, :, nu], osh.shc_correlation_loops(v.tolist(), Wn.tolist(), L), rtol=1e-13, atol=1e-15)
+
+
+def test_mutation_directional_wrong_velocity_component_fails_golden():
+    v, W, K, _ = _fixture()
+    S = v.shape[0]
+    bad = np.zeros((3, 3, 3))
+    for tau in range(3):
+        # velocity component mu instead of nu
+        bad[tau] = np.einsum("simn,sim->mn", W[: S - tau], v[tau:]) / (S - tau)
+    expect = np.zeros((3, 3, 3))
+    expect[:, 0, 1] = K[:, 0]
+    expect[:, 2, 0] = K[:, 2]
+    assert not np.allclose(bad, expect, atol=1e-12)
