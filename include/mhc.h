@@ -348,7 +348,7 @@ typedef struct mhc_shc mhc_shc;
 /* n_atoms in [1, 2^26]; n_lags in [1, 4096]; t_block (steps per device
  * block) a multiple of 64 in [64, 1024].  hip_stream as for mhc_create.
  * Device memory: about (n_lags + t_block) * 3N * 12 bytes (virial ring) plus
- * t_block * 3N * 16 bytes (host-input staging).
+ * t_block * 3N * 20 bytes (velocity rows and host-input staging).
  * Errors: INVALID_ARG, OOM, HIP (mhc_shc_last_error(NULL) tells which). */
 mhc_status mhc_shc_create(int device, void *hip_stream, int64_t n_atoms, int32_t n_lags, int32_t t_block,
                           mhc_shc **out);
@@ -374,6 +374,20 @@ mhc_status mhc_shc_read(mhc_shc *shc, double *K, int64_t *n_samples);
  * (Eq. 23) is left to the caller.  Synchronizes.  Errors: INVALID_ARG, OOM, HIP. */
 mhc_status mhc_shc_spectrum(mhc_shc *shc, int32_t n_omega, const double *omega, double dt, int32_t window,
                             double *Kw);
+
+/* Eq. 21 split by the direction nu of the atoms' motion (Sec. II, remark
+ * after Eq. 10; closing remark of Sec. II.C), always accumulated at no extra
+ * cost (K above is its sum over nu):
+ *   K [n_lags][3][3]  K^{mu nu}(tau) = < sum_i W_i^{mu nu}(s) v_i^nu(s + tau) >,
+ *                     indices [tau][mu][nu].
+ * Synchronizes.  Errors: INVALID_ARG, HIP. */
+mhc_status mhc_shc_read_dir(mhc_shc *shc, double *K, int64_t *n_samples);
+
+/* The transform of mhc_shc_spectrum applied to each of the nine split
+ * components: Kw [n_omega][3][3], indices [w][mu][nu].  Arguments and errors
+ * as for mhc_shc_spectrum. */
+mhc_status mhc_shc_spectrum_dir(mhc_shc *shc, int32_t n_omega, const double *omega, double dt, int32_t window,
+                                double *Kw);
 
 /* Clear the sums and the sample count (the next push starts a new run). */
 mhc_status mhc_shc_reset(mhc_shc *shc);

@@ -51,16 +51,20 @@ def shc_correlation_directional(v: np.ndarray, W: np.ndarray, n_lags: int) -> np
     """Eq. 21 split by the direction nu of the atoms' motion (Sec. II, remark
     after Eq. 10; closing remark of Sec. II.C):
     K[tau, mu, nu] = <sum_i W_i^{mu nu}(s) v_i^nu(s + tau)> over the S - tau
-    origins; the sum over nu is Eq. 21.  Shape [n_lags, 3, 3]."""
+    origins; the sum over nu is Eq. 21.  Shape [n_lags, 3, 3].
+
+    For each (mu, nu) the Gram matrix G[s, s'] = sum_i W_i^{mu nu}(s) v_i^nu(s')
+    is one matrix product; the lag-tau sum over origins is its tau-th upper
+    diagonal, sum_s G[s, s + tau]."""
     v = np.asarray(v, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     S = v.shape[0]
     K = np.zeros((n_lags, 3, 3), dtype=np.float64)
-    for tau in range(min(n_lags, S)):
-        early = W[: S - tau]             # W_i^{mu nu}(s)
-        late = v[tau:]                   # v_i^nu(s + tau)
-        # sum over origins s and atoms i; nu is kept, not contracted
-        K[tau] = np.einsum("simn,sin->mn", early, late) / (S - tau)
+    for mu in range(3):
+        for nu in range(3):
+            G = np.ascontiguousarray(W[:, :, mu, nu]) @ np.ascontiguousarray(v[:, :, nu]).T    # [S, S]
+            for tau in range(min(n_lags, S)):
+                K[tau, mu, nu] = np.trace(G, offset=tau) / (S - tau)
     return K
 
 

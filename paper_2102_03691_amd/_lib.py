@@ -83,6 +83,8 @@ def library():
         "mhc_shc_push": (i32, [vp, i32, vp, vp, C.c_int]),
         "mhc_shc_read": (i32, [vp, vp, P(i64)]),
         "mhc_shc_spectrum": (i32, [vp, i32, vp, dbl, i32, vp]),
+        "mhc_shc_read_dir": (i32, [vp, vp, P(i64)]),
+        "mhc_shc_spectrum_dir": (i32, [vp, i32, vp, dbl, i32, vp]),
         "mhc_shc_reset": (i32, [vp]),
         "mhc_shc_synchronize": (i32, [vp]),
         "mhc_shc_set_timing": (i32, [vp, C.c_int]),
@@ -478,6 +480,21 @@ class ModalSHC:
         out = np.empty((om.shape[0], 3), dtype=np.float64)
         self._check(self._lib.mhc_shc_spectrum(self._h, om.shape[0], _ptr(om), float(dt), int(bool(window)),
                                                _ptr(out)), "shc spectrum")
+        return out
+
+    def read_dir(self):
+        """Split by the atoms' motion direction: (K [n_lags, 3 mu, 3 nu], number of samples)."""
+        K = np.empty((self.n_lags, 3, 3), dtype=np.float64)
+        n = C.c_int64()
+        self._check(self._lib.mhc_shc_read_dir(self._h, _ptr(K), C.byref(n)), "shc read_dir")
+        return K, n.value
+
+    def spectrum_dir(self, omega, dt: float, window: bool = False):
+        """Eq. 22 of each split component: [n_omega, 3 mu, 3 nu]."""
+        om = np.ascontiguousarray(omega, dtype=np.float64).ravel()
+        out = np.empty((om.shape[0], 3, 3), dtype=np.float64)
+        self._check(self._lib.mhc_shc_spectrum_dir(self._h, om.shape[0], _ptr(om), float(dt), int(bool(window)),
+                                                   _ptr(out)), "shc spectrum_dir")
         return out
 
     def reset(self):

@@ -1,13 +1,16 @@
 // Spectral heat current (Sec. II.C): the virial-velocity correlation of
 // Eq. 21 accumulated in float64, and its transform (Eq. 22).
 //
-//   K^mu(tau) += sum_{t in block} sum_j Wmu[s0 + t - tau][j] V[t][j]
+//   K^{mu nu}(tau) += sum_{t in block} sum_i Wmu[s0 + t - tau][nu Np + i] V[t][nu Np + i]
 //
-// with j = 3i + nu over atoms and the contracted Cartesian index,
-// Wmu[s][3i + nu] = W_i^{mu nu}(s) (a ring of the last n_lags - 1 + T steps)
-// and V[t][3i + nu] = v_i^nu(s0 + t) (the block's input as pushed).  The
-// products of the float32 inputs are formed exactly in float64 and summed in
-// float64 in a fixed order, so the result is reproducible bit for bit.
+// Dofs are stored direction-major, column j = nu * Np + i (Np = N rounded up
+// to 32, zero padded): Wmu[s][nu Np + i] = W_i^{mu nu}(s) in a ring of the
+// last n_lags - 1 + T steps and V[t][nu Np + i] = v_i^nu(s0 + t).  Every
+// work-group's dof range lies inside one direction segment, so its partial
+// sums belong to one motion direction nu (the split of Sec. II, remark after
+// Eq. 10) and Eq. 21 itself is the sum over nu.  The products of the float32
+// inputs are formed exactly in float64 and summed in float64 in a fixed
+// order, so the result is reproducible bit for bit.
 #include "mhc_common.h"
 #include "mhc_numeric.h"
 
@@ -16,36 +19,46 @@ namespace mhc {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- ring fill
-// ring[(s % ring_len) * 3 + mu][3i + nu] = W[t][i][mu][nu] for the block's
-// steps s = s0 + t, t < t_count.  One thread per (t, i, mu): 3 floats in,
-// 3 floats out.
-__global__ void __launch_bounds__(256) k_shc_ring(const float* __restrict__ W, int t_count, int64_t N,
-                                                 float* __restrict__ ring, int64_t ring_len, int64_t ld,
-                                                 int64_t s0) {
+// ring[(s % ring_len) * 3 + mu][nu Np + i] = W[t][i][mu][nu] and
+// vt[t][nu Np + i] = v[t][i][nu] for the block's steps s = s0 + t, t < t_count
+// (ld = 3 Np).  One thread per (t, i): 12 floats in, 12 out, consecutive
+// atoms to consecutive columns.
+__global__ void __launch_bounds__(256) k_shc_ring(const float* __restrict__ W, const float* __restrict__ v,
+                                                 int t_count, int64_t N, int64_t Np, float* __restrict__ ring,
+                                                 int64_t ring_len, int64_t ld, int64_t s0, float* __restrict__ vt) {
   const int t = blockIdx.y;
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;     // (i, mu)
-  if (t >= t_count || q >= 3 * N) return;
-  const int64_t i = q / 3;
-  const int mu = (int)(q - i * 3);
-  const float* src = W + ((int64_t)t * N + i) * 9 + mu * 3;
-  float* dst = ring + (((s0 + t) % ring_len) * 3 + mu) * ld + 3 * i;
-  dst[0] = src[0];
-  dst[1] = src[1];
-  dst[2] = src[2];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= t_count || i >= N) return;
+  const float* src = W + ((int64_t)t * N + i) * 9;
+  float w[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) w[c] = src[c];
+  const float* vs = v + ((int64_t)t * N + i) * 3;
+  const float v0 = vs[0], v1 = vs[1], v2 = vs[2];
+  float* row = ring + ((s0 + t) % ring_len) * 3 * ld + i;
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu)
+#pragma unroll
+    for (int nu = 0; nu < 3; ++nu) row[mu * ld + nu * Np] = w[3 * mu + nu];
+  float* vr = vt + (int64_t)t * ld + i;
+  vr[0] = v0;
+  vr[Np] = v1;
+  vr[2 * Np] = v2;
 }
 
-hipError_t launch_shc_ring(hipStream_t s, const float* W, int t_count, int64_t N, float* ring, int64_t ring_len,
-                           int64_t ld, int64_t s0) {
+hipError_t launch_shc_ring(hipStream_t s, const float* W, const float* v, int t_count, int64_t N, int64_t Np,
+                           float* ring, int64_t ring_len, int64_t ld, int64_t s0, float* vt) {
   if (t_count <= 0) return hipSuccess;
-  dim3 grid((unsigned)((3 * N + 255) / 256), (unsigned)t_count);
-  hipLaunchKernelGGL(k_shc_ring, grid, dim3(256), 0, s, W, t_count, N, ring, ring_len, ld, s0);
+  dim3 grid((unsigned)((N + 255) / 256), (unsigned)t_count);
+  hipLaunchKernelGGL(k_shc_ring, grid, dim3(256), 0, s, W, v, t_count, N, Np, ring, ring_len, ld, s0, vt);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- products
 // Work-group (kc, a, b): steps t in [64a, 64a + 64) x lags tau in
-// [64b, 64b + 64) x the 3 components mu, over the dof range
-// [kc * dk, kc * dk + dk).  The origins s' = s0 + t - tau of the tile are 127
+// [64b, 64b + 64) x the 3 components mu, over the dof range of direction
+// segment nu = kc / n_kcs: columns nu Np + [c dk, c dk + dk) with c = kc % n_kcs,
+// cut at nu Np + N.  The origins s' = s0 + t - tau of the tile are 127
 // consecutive ring rows r = t_loc - tau_loc + 63.  Dofs are staged 32 at a
 // time through LDS; a thread holds the 4 x 4 x 3 products of steps 4tt + x
 // and lags 4tl + y.  Threads are laid out along diagonals, tt = (tl + k) mod 16
@@ -65,9 +78,9 @@ constexpr int SH_WS = 3 * SH_DC + 28;                    // W row stride (floats
 __device__ __forceinline__ int sh_wrow(int r) { return r * SH_WS + 4 * ((r >> 2) & 7); }
 constexpr int SH_WTILE = SH_ROWS * SH_WS + 28;
 
-__global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, const float* __restrict__ ring,
-                                                 int64_t ring_len, int64_t ld, int64_t N3, int t_count,
-                                                 int64_t s0, int64_t dk, int n_lags_pad,
+__global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring,
+                                                 int64_t ring_len, int64_t ld, int64_t N, int64_t Np, int t_count,
+                                                 int64_t s0, int64_t dk, int n_kcs, int n_lags_pad,
                                                  double* __restrict__ part) {
   __shared__ f32x4 vs[SH_DC / 4][SH_VP];
   // the W tile (rows at sh_wrow), reused for the final step-group sums once the products are done
@@ -80,8 +93,9 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, c
   const int b = blockIdx.z;
   const int tl = tid & 15;
   const int tt = (tl + (tid >> 4)) & 15;
-  const int64_t j0 = (int64_t)kc * dk;
-  const int64_t j1 = min(N3, j0 + dk);
+  const int64_t seg0 = (int64_t)(kc / n_kcs) * Np;
+  const int64_t j0 = seg0 + (int64_t)(kc % n_kcs) * dk;
+  const int64_t j1 = min(seg0 + N, j0 + dk);
   const int64_t row0 = s0 + (int64_t)SH_T * a - (int64_t)SH_L * b - (SH_L - 1);   // origin of row r = 0
   const int64_t s_last = s0 + t_count - 1;
 
@@ -101,10 +115,11 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, c
     roff[tid] = (sp >= 0 && sp <= s_last) ? (sp % ring_len) * 3 * ld : -1;
   }
   __syncthreads();
-  // Staging of one 32-dof chunk through registers: W as float4 (16-byte
-  // aligned: ld and the chunk start are multiples of 4; the ring's pad columns
-  // past 3N are zero), V element-wise (its rows are 3N floats long).  The next
-  // chunk's loads are issued before the current chunk's products.
+  // Staging of one 32-dof chunk through registers, W and V as float4 (16-byte
+  // aligned: ld, Np, dk and the chunk start are multiples of 4).  A chunk never
+  // crosses a multiple of dk or the end of its segment's Np columns, and the
+  // pad columns past N are zero in both arrays.  The next chunk's loads are
+  // issued before the current chunk's products.
   constexpr int WQ = SH_ROWS * 3 * (SH_DC / 4);           // 3048 float4 per chunk
   constexpr int WPT = (WQ + 255) / 256;                    // 12 per thread
   constexpr int VPT = SH_T * (SH_DC / 4) / 256;            // 2 per thread
@@ -130,13 +145,7 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, c
       const int t = SH_T * a + tr;
       const int64_t j = jc + 4 * q;
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
-      if (t < t_count) {
-        const float* src = v + (int64_t)t * N3 + j;
-        x.x = (j + 0 < j1) ? src[0] : 0.f;
-        x.y = (j + 1 < j1) ? src[1] : 0.f;
-        x.z = (j + 2 < j1) ? src[2] : 0.f;
-        x.w = (j + 3 < j1) ? src[3] : 0.f;
-      }
+      if (t < t_count && j < j1) x = *reinterpret_cast<const f32x4*>(vt + (int64_t)t * ld + j);
       vst[k] = x;
     }
   };
@@ -207,76 +216,89 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ v, c
 }
 
 // Fixed-order sum of the partials of one block into the running float64 sums
-// (Neumaier): one thread per (tau, mu).
-__global__ void __launch_bounds__(256) k_shc_accum(const double* __restrict__ part, int n_kc, int n_ttiles,
+// of each motion direction (Neumaier): one thread per (nu, tau, mu), summing
+// the n_kcs dof ranges of segment nu and the step tiles in order;
+// ksum[nu][tau][mu].
+__global__ void __launch_bounds__(256) k_shc_accum(const double* __restrict__ part, int n_kcs, int n_ttiles,
                                                   int n_lags, int n_lags_pad, double* __restrict__ ksum,
                                                   double* __restrict__ kcomp) {
   const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= n_lags * 3) return;
-  const int tau = q / 3, m = q % 3;
+  if (q >= 3 * n_lags * 3) return;
+  const int nu = q / (n_lags * 3);
+  const int r = q - nu * n_lags * 3;
+  const int tau = r / 3, m = r % 3;
   double s = 0.0;
-  for (int kc = 0; kc < n_kc; ++kc)
+  for (int kc = nu * n_kcs; kc < (nu + 1) * n_kcs; ++kc)
     for (int a = 0; a < n_ttiles; ++a) s += part[(((int64_t)kc * n_ttiles + a) * n_lags_pad + tau) * 3 + m];
   neumaier_add(ksum[q], kcomp[q], s);
 }
 
-hipError_t launch_shc_block(hipStream_t s, const float* v, const float* ring, int64_t ring_len, int64_t ld,
-                            int64_t N3, int t_count, int64_t s0, int n_lags, int t_block, int64_t dk, int n_kc,
+hipError_t launch_shc_block(hipStream_t s, const float* vt, const float* ring, int64_t ring_len, int64_t ld,
+                            int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
                             double* part, double* ksum, double* kcomp) {
   if (t_count <= 0) return hipSuccess;
   const int n_ttiles = (t_count + SH_T - 1) / SH_T;
   const int n_lags_pad = (n_lags + SH_L - 1) / SH_L * SH_L;
   const int n_ltiles = n_lags_pad / SH_L;
-  (void)t_block;
-  hipLaunchKernelGGL(k_shc_gram, dim3((unsigned)n_kc, (unsigned)n_ttiles, (unsigned)n_ltiles), dim3(256), 0, s, v,
-                     ring, ring_len, ld, N3, t_count, s0, dk, n_lags_pad, part);
+  hipLaunchKernelGGL(k_shc_gram, dim3((unsigned)(3 * n_kcs), (unsigned)n_ttiles, (unsigned)n_ltiles), dim3(256), 0,
+                     s, vt, ring, ring_len, ld, N, Np, t_count, s0, dk, n_kcs, n_lags_pad, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_shc_accum, dim3((unsigned)((n_lags * 3 + 255) / 256)), dim3(256), 0, s, part, n_kc, n_ttiles,
-                     n_lags, n_lags_pad, ksum, kcomp);
+  hipLaunchKernelGGL(k_shc_accum, dim3((unsigned)((3 * n_lags * 3 + 255) / 256)), dim3(256), 0, s, part, n_kcs,
+                     n_ttiles, n_lags, n_lags_pad, ksum, kcomp);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- read-out
-// K[tau][mu] = (ksum + kcomp) / (S - tau), zero for lags with no origin.
+// Kd[tau][mu][nu] = (ksum + kcomp)[nu][tau][mu] / (S - tau) and
+// K[tau][mu] = (Kd[..][0] + Kd[..][1]) + Kd[..][2]; zero for lags with no origin.
 __global__ void k_shc_finish(const double* __restrict__ ksum, const double* __restrict__ kcomp, int n_lags,
-                             int64_t S, double* __restrict__ K) {
+                             int64_t S, double* __restrict__ K, double* __restrict__ Kd) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= n_lags * 3) return;
   const int tau = q / 3;
-  K[q] = (S > tau) ? (ksum[q] + kcomp[q]) / (double)(S - tau) : 0.0;
+  double k = 0.0;
+#pragma unroll
+  for (int nu = 0; nu < 3; ++nu) {
+    const int e = nu * n_lags * 3 + q;
+    const double d = (S > tau) ? (ksum[e] + kcomp[e]) / (double)(S - tau) : 0.0;
+    Kd[q * 3 + nu] = d;
+    k += d;
+  }
+  K[q] = k;
 }
 
 // Eq. 22 on the sampled lags, even extension, trapezoid rule, optional Hann
-// window: Kw[w][mu] = dt sum_tau c_tau K[tau][mu] cos(omega_w tau dt), the
-// lags summed in order.  One thread per (omega, mu).
-__global__ void k_shc_spectrum(const double* __restrict__ K, int n_lags, const double* __restrict__ omega,
+// window: Kw[w][m] = dt sum_tau c_tau K[tau][m] cos(omega_w tau dt), the lags
+// summed in order, for the nc components m of each lag (3, or 9 for the split).
+// One thread per (omega, m).
+__global__ void k_shc_spectrum(const double* __restrict__ K, int n_lags, int nc, const double* __restrict__ omega,
                                int n_omega, double dt, int window, double* __restrict__ Kw) {
   const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= n_omega * 3) return;
-  const int w = q / 3, m = q % 3;
+  if (q >= n_omega * nc) return;
+  const int w = q / nc, m = q % nc;
   const double om = omega[w];
   double s = 0.0;
   for (int tau = 0; tau < n_lags; ++tau) {
     double c = (tau == 0 || tau == n_lags - 1) ? 1.0 : 2.0;
     if (window && n_lags > 1) c *= 0.5 * (1.0 + cos(M_PI * (double)tau / (double)(n_lags - 1)));
-    s += c * K[tau * 3 + m] * cos(om * (double)tau * dt);
+    s += c * K[tau * nc + m] * cos(om * (double)tau * dt);
   }
   Kw[q] = dt * s;
 }
 
 hipError_t launch_shc_finish(hipStream_t s, const double* ksum, const double* kcomp, int n_lags, int64_t S,
-                             double* K) {
+                             double* K, double* Kd) {
   hipLaunchKernelGGL(k_shc_finish, dim3((unsigned)((n_lags * 3 + 255) / 256)), dim3(256), 0, s, ksum, kcomp, n_lags,
-                     S, K);
+                     S, K, Kd);
   return hipGetLastError();
 }
 
-hipError_t launch_shc_spectrum(hipStream_t s, const double* K, int n_lags, const double* omega, int n_omega, double dt,
-                               int window, double* Kw) {
+hipError_t launch_shc_spectrum(hipStream_t s, const double* K, int n_lags, int nc, const double* omega, int n_omega,
+                               double dt, int window, double* Kw) {
   if (n_omega <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_shc_spectrum, dim3((unsigned)((n_omega * 3 + 255) / 256)), dim3(256), 0, s, K, n_lags, omega,
-                     n_omega, dt, window, Kw);
+  hipLaunchKernelGGL(k_shc_spectrum, dim3((unsigned)((n_omega * nc + 255) / 256)), dim3(256), 0, s, K, n_lags, nc,
+                     omega, n_omega, dt, window, Kw);
   return hipGetLastError();
 }
 

@@ -170,20 +170,26 @@ hipError_t launch_hnema_finish(hipStream_t s, const double* sum, const double* c
                                int64_t S, double* avg);
 
 // ------------------------------------------------------------ spectral heat current
-// ring[(s % ring_len) * 3 + mu][3i + nu] = W[t][i][mu][nu], s = s0 + t, t < t_count.
-hipError_t launch_shc_ring(hipStream_t s, const float* W, int t_count, int64_t N, float* ring, int64_t ring_len,
-                           int64_t ld, int64_t s0);
-// K^mu(tau) sums += sum_{t < t_count} sum_j ring[s0 + t - tau][mu][j] v[t][j] for tau < n_lags,
-// origins s0 + t - tau >= 0 only; the dofs split into n_kc ranges of dk (multiple of 32);
-// part holds [n_kc][ceil(t_count/64)][round_up(n_lags, 64)][3] doubles.  Fixed order, Neumaier.
-hipError_t launch_shc_block(hipStream_t s, const float* v, const float* ring, int64_t ring_len, int64_t ld,
-                            int64_t N3, int t_count, int64_t s0, int n_lags, int t_block, int64_t dk, int n_kc,
+// Direction-major dof columns nu * Np + i (Np = N rounded up to 32, ld = 3 Np):
+// ring[(s % ring_len) * 3 + mu][nu Np + i] = W[t][i][mu][nu] and
+// vt[t][nu Np + i] = v[t][i][nu], s = s0 + t, t < t_count.
+hipError_t launch_shc_ring(hipStream_t s, const float* W, const float* v, int t_count, int64_t N, int64_t Np,
+                           float* ring, int64_t ring_len, int64_t ld, int64_t s0, float* vt);
+// K^{mu nu}(tau) sums += sum_{t < t_count} sum_i ring[s0 + t - tau][mu][nu Np + i] vt[t][nu Np + i]
+// for tau < n_lags, origins s0 + t - tau >= 0 only; each direction segment splits into n_kcs
+// ranges of dk (multiple of 32) dofs; part holds
+// [3 n_kcs][ceil(t_count/64)][round_up(n_lags, 64)][3] doubles; ksum, kcomp [3 nu][n_lags][3 mu].
+// Fixed order, Neumaier.
+hipError_t launch_shc_block(hipStream_t s, const float* vt, const float* ring, int64_t ring_len, int64_t ld,
+                            int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
                             double* part, double* ksum, double* kcomp);
-// K[tau][mu] = (ksum + kcomp) / (S - tau), zero where S <= tau.
+// Kd[tau][mu][nu] = (ksum + kcomp)[nu][tau][mu] / (S - tau) (zero where S <= tau) and
+// K[tau][mu] = sum over nu in order.
 hipError_t launch_shc_finish(hipStream_t s, const double* ksum, const double* kcomp, int n_lags, int64_t S,
-                             double* K);
-// Kw[w][mu] = dt sum_tau c_tau K[tau][mu] cos(omega_w tau dt), c = 1, 2, ..., 2, 1 (times the Hann window).
-hipError_t launch_shc_spectrum(hipStream_t s, const double* K, int n_lags, const double* omega, int n_omega, double dt,
-                               int window, double* Kw);
+                             double* K, double* Kd);
+// Kw[w][m] = dt sum_tau c_tau K[tau][m] cos(omega_w tau dt), c = 1, 2, ..., 2, 1 (times the Hann
+// window), for the nc components of each lag.
+hipError_t launch_shc_spectrum(hipStream_t s, const double* K, int n_lags, int nc, const double* omega, int n_omega,
+                               double dt, int window, double* Kw);
 
 }  // namespace mhc

@@ -1,9 +1,11 @@
 // Host side of the spectral-heat-current entry points (mhc_shc_*, include/mhc.h).
 //
 // Per pushed block of at most T steps: the block's virials go into the ring
-// of past virials (transposed to [mu][3i + nu]), then the virial-velocity
+// of past virials and its velocities into a staging copy, both with
+// direction-major dof columns (nu * Np + i), then the virial-velocity
 // products of the block's steps against the last n_lags origins are formed
-// and added to the float64 sums.  No arithmetic of the method runs here.
+// and added to the float64 sums of each motion direction.  No arithmetic of
+// the method runs here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,19 +25,20 @@ struct mhc_shc {
   bool own_stream = false;
   std::string err;
   mhc_status sticky = MHC_OK;
-  int64_t N = 0, N3 = 0, ld = 0;
+  int64_t N = 0, N3 = 0, Np = 0, ld = 0;
   int n_lags = 0, T = 0;
   int64_t ring_len = 0;
   int64_t dk = 0;
-  int n_kc = 0;
+  int n_kcs = 0;                       // dof ranges per direction segment
   int64_t S = 0;                       // samples pushed since the last reset
   std::vector<void*> allocs;
-  float* ring = nullptr;               // [ring_len][3][ld]
+  float* ring = nullptr;               // [ring_len][3 mu][ld = 3 Np]
+  float* vt = nullptr;                 // [T][ld] velocities, direction-major
   float* sv = nullptr;                 // host-input staging [T][N][3]
   float* sW = nullptr;                 // [T][N][9]
-  double* part = nullptr;              // [n_kc][T/64][n_lags_pad][3]
-  double* ksum = nullptr;              // [n_lags][3] x 2 (sum, compensation)
-  double* kout = nullptr;              // [n_lags][3] read-out
+  double* part = nullptr;              // [3 n_kcs][T/64][n_lags_pad][3]
+  double* ksum = nullptr;              // [3 nu][n_lags][3 mu] x 2 (sum, compensation)
+  double* kout = nullptr;              // [n_lags][3] then [n_lags][3][3] read-out
   double* omega = nullptr;             // spectrum frequencies (grown on demand)
   double* kw = nullptr;                // [n_omega][3]
   int omega_cap = 0;
@@ -99,7 +102,8 @@ int lags_pad(int n) { return (n + 63) / 64 * 64; }
 
 // One block of t_count <= T steps whose inputs are device pointers.
 mhc_status shc_block(mhc_shc* c, const float* v, const float* W, int t_count) {
-  SHIP_TRY(launch_shc_ring(c->stream, W, t_count, c->N, c->ring, c->ring_len, c->ld, c->S), "virial ring");
+  SHIP_TRY(launch_shc_ring(c->stream, W, v, t_count, c->N, c->Np, c->ring, c->ring_len, c->ld, c->S, c->vt),
+           "virial ring");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) {
     while (c->ev_used + 2 > c->ev.size()) {
@@ -112,8 +116,8 @@ mhc_status shc_block(mhc_shc* c, const float* v, const float* W, int t_count) {
     c->ev_used += 2;
     SHIP_TRY(hipEventRecord(e0, c->stream), "event record");
   }
-  SHIP_TRY(launch_shc_block(c->stream, v, c->ring, c->ring_len, c->ld, c->N3, t_count, c->S, c->n_lags, c->T, c->dk,
-                            c->n_kc, c->part, c->ksum, c->ksum + 3 * c->n_lags),
+  SHIP_TRY(launch_shc_block(c->stream, c->vt, c->ring, c->ring_len, c->ld, c->N, c->Np, t_count, c->S, c->n_lags,
+                            c->dk, c->n_kcs, c->part, c->ksum, c->ksum + 9 * c->n_lags),
            "virial-velocity products");
   if (e1) SHIP_TRY(hipEventRecord(e1, c->stream), "event record");
   c->S += t_count;
@@ -152,31 +156,52 @@ mhc_status mhc_shc_create(int device, void* hip_stream, int64_t n_atoms, int32_t
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) n_cu = std::max(1, prop.multiProcessorCount);
   c->N = n_atoms;
   c->N3 = 3 * n_atoms;
-  c->ld = (c->N3 + 3) / 4 * 4;
+  c->Np = (n_atoms + 31) / 32 * 32;
+  c->ld = 3 * c->Np;
   c->n_lags = n_lags;
   c->T = t_block;
   c->ring_len = (int64_t)n_lags - 1 + t_block;
-  // split the dofs so that a full block has about two work-groups per CU
+  // Split each direction's N dofs into n_kcs ranges of dk.  A product
+  // work-group holds one CU (its register file), so a full block takes
+  // ceil(3 n_kcs tiles / n_cu) rounds of dk / 32 chunks each, plus a fixed
+  // cost per work-group (staging, the final sums: about two chunks); pick the
+  // split with the least such time, the fewer work-groups on a tie.
   const int64_t tiles = (int64_t)(t_block / 64) * (lags_pad(n_lags) / 64);
-  const int64_t max_kc = (c->N3 + 31) / 32;
-  int64_t kc = std::min<int64_t>(max_kc, std::max<int64_t>(1, (2 * n_cu + tiles - 1) / tiles));
-  c->dk = ((c->N3 + kc - 1) / kc + 31) / 32 * 32;
-  c->n_kc = (int)((c->N3 + c->dk - 1) / c->dk);
-  void *pr, *pv, *pW, *pp, *ps, *po;
+  const int64_t max_kc = c->Np / 32;
+  int64_t best = -1, best_cost = 0;
+  for (int64_t kc = 1; kc <= max_kc; ++kc) {
+    const int64_t dk = ((c->N + kc - 1) / kc + 31) / 32 * 32;
+    const int64_t n = (c->N + dk - 1) / dk;
+    if (n != kc) continue;
+    const int64_t rounds = (3 * n * tiles + n_cu - 1) / n_cu;
+    const int64_t cost = rounds * (dk / 32 + 2);
+    if (best < 0 || cost < best_cost) {
+      best = kc;
+      best_cost = cost;
+    }
+  }
+  c->dk = ((c->N + best - 1) / best + 31) / 32 * 32;
+  c->n_kcs = (int)((c->N + c->dk - 1) / c->dk);
+  void *pr, *pvt, *pv, *pW, *pp, *ps, *po;
   const size_t ring_bytes = (size_t)c->ring_len * 3 * c->ld * 4;
-  if (salloc(c, ring_bytes, &pr, "virial ring") || salloc(c, (size_t)t_block * c->N3 * 4, &pv, "velocity staging") ||
+  const size_t vt_bytes = (size_t)t_block * c->ld * 4;
+  if (salloc(c, ring_bytes, &pr, "virial ring") || salloc(c, vt_bytes, &pvt, "velocity rows") ||
+      salloc(c, (size_t)t_block * c->N3 * 4, &pv, "velocity staging") ||
       salloc(c, (size_t)t_block * c->N3 * 3 * 4, &pW, "virial staging") ||
-      salloc(c, (size_t)c->n_kc * (t_block / 64) * lags_pad(n_lags) * 3 * 8, &pp, "partials") ||
-      salloc(c, (size_t)n_lags * 3 * 2 * 8, &ps, "sums") || salloc(c, (size_t)n_lags * 3 * 8, &po, "read-out"))
+      salloc(c, (size_t)3 * c->n_kcs * (t_block / 64) * lags_pad(n_lags) * 3 * 8, &pp, "partials") ||
+      salloc(c, (size_t)n_lags * 9 * 2 * 8, &ps, "sums") || salloc(c, (size_t)n_lags * 12 * 8, &po, "read-out"))
     return bail(MHC_ERR_OOM, "device allocation failed");
   c->ring = static_cast<float*>(pr);
+  c->vt = static_cast<float*>(pvt);
   c->sv = static_cast<float*>(pv);
   c->sW = static_cast<float*>(pW);
   c->part = static_cast<double*>(pp);
   c->ksum = static_cast<double*>(ps);
   c->kout = static_cast<double*>(po);
+  // the pad columns of the ring and the velocity rows stay zero for good
   if (hipMemsetAsync(c->ring, 0, ring_bytes, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->ksum, 0, (size_t)n_lags * 3 * 2 * 8, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->vt, 0, vt_bytes, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ksum, 0, (size_t)n_lags * 9 * 2 * 8, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(MHC_ERR_HIP, "initial clear");
   *out = c;
@@ -216,19 +241,26 @@ mhc_status mhc_shc_push(mhc_shc* c, int32_t n_steps, const float* v, const float
   return MHC_OK;
 }
 
-mhc_status mhc_shc_read(mhc_shc* c, double* K, int64_t* n_samples) {
+static mhc_status shc_read(mhc_shc* c, double* K, int64_t* n_samples, int split) {
   mhc_status st = senter(c);
   if (st) return st;
   if (!K) return sfail(c, MHC_ERR_INVALID_ARG, "NULL output");
-  SHIP_TRY(launch_shc_finish(c->stream, c->ksum, c->ksum + 3 * c->n_lags, c->n_lags, c->S, c->kout), "finish");
-  SHIP_TRY(hipMemcpyAsync(K, c->kout, (size_t)c->n_lags * 3 * 8, hipMemcpyDeviceToHost, c->stream), "copy K");
+  const size_t n = (size_t)c->n_lags * 3;
+  SHIP_TRY(launch_shc_finish(c->stream, c->ksum, c->ksum + 9 * c->n_lags, c->n_lags, c->S, c->kout, c->kout + n),
+           "finish");
+  SHIP_TRY(hipMemcpyAsync(K, c->kout + (split ? n : 0), (split ? 3 : 1) * n * 8, hipMemcpyDeviceToHost, c->stream),
+           "copy K");
   SHIP_TRY(hipStreamSynchronize(c->stream), "read sync");
   if (n_samples) *n_samples = c->S;
   return MHC_OK;
 }
 
-mhc_status mhc_shc_spectrum(mhc_shc* c, int32_t n_omega, const double* omega, double dt, int32_t window,
-                            double* Kw) {
+mhc_status mhc_shc_read(mhc_shc* c, double* K, int64_t* n_samples) { return shc_read(c, K, n_samples, 0); }
+
+mhc_status mhc_shc_read_dir(mhc_shc* c, double* K, int64_t* n_samples) { return shc_read(c, K, n_samples, 1); }
+
+static mhc_status shc_spectrum(mhc_shc* c, int32_t n_omega, const double* omega, double dt, int32_t window,
+                               double* Kw, int split) {
   mhc_status st = senter(c);
   if (st) return st;
   if (n_omega < 1 || n_omega > (1 << 24) || !omega || !Kw || !(std::isfinite(dt) && dt > 0.0) ||
@@ -239,23 +271,38 @@ mhc_status mhc_shc_spectrum(mhc_shc* c, int32_t n_omega, const double* omega, do
   if (n_omega > c->omega_cap) {
     void *po, *pk;
     if ((st = salloc(c, (size_t)n_omega * 8, &po, "frequencies"))) return st;
-    if ((st = salloc(c, (size_t)n_omega * 3 * 8, &pk, "spectrum"))) return st;
+    if ((st = salloc(c, (size_t)n_omega * 9 * 8, &pk, "spectrum"))) return st;
     c->omega = static_cast<double*>(po);
     c->kw = static_cast<double*>(pk);
     c->omega_cap = n_omega;
   }
   SHIP_TRY(hipMemcpyAsync(c->omega, omega, (size_t)n_omega * 8, hipMemcpyHostToDevice, c->stream), "copy omega");
-  SHIP_TRY(launch_shc_finish(c->stream, c->ksum, c->ksum + 3 * c->n_lags, c->n_lags, c->S, c->kout), "finish");
-  SHIP_TRY(launch_shc_spectrum(c->stream, c->kout, c->n_lags, c->omega, n_omega, dt, window, c->kw), "spectrum");
-  SHIP_TRY(hipMemcpyAsync(Kw, c->kw, (size_t)n_omega * 3 * 8, hipMemcpyDeviceToHost, c->stream), "copy spectrum");
+  const size_t n = (size_t)c->n_lags * 3;
+  const int nc = split ? 9 : 3;
+  SHIP_TRY(launch_shc_finish(c->stream, c->ksum, c->ksum + 9 * c->n_lags, c->n_lags, c->S, c->kout, c->kout + n),
+           "finish");
+  SHIP_TRY(launch_shc_spectrum(c->stream, c->kout + (split ? n : 0), c->n_lags, nc, c->omega, n_omega, dt, window,
+                               c->kw),
+           "spectrum");
+  SHIP_TRY(hipMemcpyAsync(Kw, c->kw, (size_t)n_omega * nc * 8, hipMemcpyDeviceToHost, c->stream), "copy spectrum");
   SHIP_TRY(hipStreamSynchronize(c->stream), "spectrum sync");
   return MHC_OK;
+}
+
+mhc_status mhc_shc_spectrum(mhc_shc* c, int32_t n_omega, const double* omega, double dt, int32_t window,
+                            double* Kw) {
+  return shc_spectrum(c, n_omega, omega, dt, window, Kw, 0);
+}
+
+mhc_status mhc_shc_spectrum_dir(mhc_shc* c, int32_t n_omega, const double* omega, double dt, int32_t window,
+                                double* Kw) {
+  return shc_spectrum(c, n_omega, omega, dt, window, Kw, 1);
 }
 
 mhc_status mhc_shc_reset(mhc_shc* c) {
   mhc_status st = senter(c);
   if (st) return st;
-  SHIP_TRY(hipMemsetAsync(c->ksum, 0, (size_t)c->n_lags * 3 * 2 * 8, c->stream), "clear sums");
+  SHIP_TRY(hipMemsetAsync(c->ksum, 0, (size_t)c->n_lags * 9 * 2 * 8, c->stream), "clear sums");
   SHIP_TRY(hipStreamSynchronize(c->stream), "reset sync");
   c->S = 0;
   return MHC_OK;

@@ -60,14 +60,25 @@ def test_shc_correlation_parity(n_atoms, S, n_lags, T, splits, dev):
     assert e <= TOL and e0 <= TOL
     if n_lags > S:
         assert np.all(K[S:] == 0.0)
+    # the motion-direction split, accumulated alongside
+    Kd, nd = h.read_dir()
+    ref_d = oracle.shc_correlation_directional(v, W, n_lags)
+    ed = rel(Kd, ref_d)
+    log(f"shc_dir_N{n_atoms}_S{S}_L{n_lags}_T{T}", rel_K_dir=ed)
+    assert nd == S and ed <= TOL
+    assert np.array_equal(Kd.sum(axis=2) * 0 + K, K)
+    assert rel(Kd.sum(axis=2), K) <= 1e-14
     # transform of the device correlation against the oracle's transform of the oracle's correlation
     om = np.linspace(0.0, np.pi / 2.0, 33)
     for window in (False, True):
         Kw = h.spectrum(om, 2.0, window)
         ref_w = oracle.shc_spectrum(ref, 2.0, om, window)
         ew = rel(Kw, ref_w)
-        log(f"shc_spectrum_N{n_atoms}_w{int(window)}", rel_Kw=ew)
-        assert ew <= 1e-11
+        Kwd = h.spectrum_dir(om, 2.0, window)
+        ref_wd = oracle.shc_spectrum(ref_d.reshape(n_lags, 9), 2.0, om, window).reshape(-1, 3, 3)
+        ewd = rel(Kwd, ref_wd)
+        log(f"shc_spectrum_N{n_atoms}_w{int(window)}", rel_Kw=ew, rel_Kw_dir=ewd)
+        assert ew <= 1e-11 and ewd <= 1e-11
     h.close()
 
 
@@ -115,6 +126,8 @@ def test_shc_paper_shaped_size():
     h, K, n = _run(n_atoms, v, W, L, T, [256, 256, 88], True)
     ref = oracle.shc_correlation(v, W, L)
     e = rel(K, ref)
-    log("shc_N8000_S600_L250_T256", rel_K=e)
-    assert n == S and e <= TOL
+    Kd, _ = h.read_dir()
+    ed = rel(Kd, oracle.shc_correlation_directional(v, W, L))
+    log("shc_N8000_S600_L250_T256", rel_K=e, rel_K_dir=ed)
+    assert n == S and e <= TOL and ed <= TOL
     h.close()
