@@ -93,10 +93,18 @@ typedef enum {
  * (three per block), is read with mhc_read_hnema_dir / mhc_read_gkma_dir
  * (mhc_read_hnema and mhc_read_gkma then return the sums over nu), and is not
  * available to grouped pushes or mhc_read_block_currents (UNSUPPORTED). */
-enum { MHC_HNEMA = 1, MHC_GKMA = 2, MHC_DIRECTIONAL = 4 };
+enum { MHC_HNEMA = 1, MHC_GKMA = 2, MHC_DIRECTIONAL = 4, MHC_CROSS = 8 };
+/* MHC_CROSS (with MHC_GKMA, not with MHC_DIRECTIONAL) adds the bin-bin
+ * cross-correlations of the modal currents, <J_b^mu(t+tau) J_b2^nu(t)>
+ * (Sec. II.B.i: mode-mode interactions from cross-correlations of modal heat
+ * currents; Sec. III.C.i: available from the GKMA currents), read with
+ * mhc_read_gkma_cross.  Cost per block about nb times the GKMA correlation
+ * update; device memory 2 nb * 3(nb+1) * 3 * L doubles, so it suits a few
+ * coarse bins.  Grouped pushes carry it like the GKMA correlation. */
 
 typedef struct {
-  int32_t methods;       /* MHC_HNEMA | MHC_GKMA (at least one), | MHC_DIRECTIONAL   */
+  int32_t methods;       /* MHC_HNEMA | MHC_GKMA (at least one), | MHC_DIRECTIONAL
+                            or | MHC_CROSS (see above)                             */
   int32_t precision;     /* mhc_precision                                           */
   int32_t t_block;       /* steps per contraction: 1 = per-step matrix-vector path,
                             otherwise 32..512 and a multiple of 32 (T-batched GEMM)  */
@@ -249,6 +257,17 @@ mhc_status mhc_read_hnema_dir(mhc_ctx *ctx, double *avg, double *total_avg, int6
  *   n_samples S                                                    (NULL: skip)
  * Errors: STATE (GKMA or the split not enabled). */
 mhc_status mhc_read_gkma_dir(mhc_ctx *ctx, double *corr, double *integral, int64_t *n_samples);
+
+/* Bin-bin cross-correlations (MHC_CROSS), tau = 0 .. L-1:
+ *   corr      [L][nb][nb][3][3]  <J_b^mu(t+tau) J_b2^nu(t)>, indices
+ *                                [tau][b][b2][mu][nu], averaged over the S - tau
+ *                                available origins (zero when S <= tau)  (NULL: skip)
+ *   integral  [L][nb][nb][3][3]  trapezoid running integral over tau     (NULL: skip)
+ *   n_samples S                                                          (NULL: skip)
+ * With every mode binned, the sum over b2 equals mhc_read_gkma's corr up to
+ * rounding (the binned currents then sum to the Eq. 10 total).
+ * Errors: STATE (cross-correlations not enabled). */
+mhc_status mhc_read_gkma_cross(mhc_ctx *ctx, double *corr, double *integral, int64_t *n_samples);
 
 /* Binned modal currents of the most recent block, per step:
  *   jb  [t_count][nb][3] float64 J_b^mu(s) for the last t_count pushed steps

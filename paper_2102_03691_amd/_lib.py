@@ -8,7 +8,7 @@ import numpy as np
 
 from . import _build
 
-HNEMA, GKMA, DIRECTIONAL = 1, 2, 4
+HNEMA, GKMA, DIRECTIONAL, CROSS = 1, 2, 4, 8
 PREC_FP32, PREC_BF16X3, PREC_FP8, PREC_FP8X3 = 0, 1, 2, 3
 SCHED_AUTO, SCHED_TILES, SCHED_STREAMK, SCHED_SPLIT = 0, 1, 2, 3
 GROUP_GRAPH, GROUP_AUTOTUNE = 1, 2
@@ -69,6 +69,7 @@ def library():
         "mhc_read_gkma": (i32, [vp, vp, vp, vp, P(i64)]),
         "mhc_read_hnema_dir": (i32, [vp, vp, vp, P(i64)]),
         "mhc_read_gkma_dir": (i32, [vp, vp, vp, P(i64)]),
+        "mhc_read_gkma_cross": (i32, [vp, vp, vp, P(i64)]),
         "mhc_read_block_currents": (i32, [vp, i32, vp]),
         "mhc_reset": (i32, [vp]),
         "mhc_save_state": (i32, [vp, vp, P(C.c_size_t)]),
@@ -292,6 +293,15 @@ class ModalHC:
         integ = np.empty_like(corr)
         n = C.c_int64()
         self._check(self._lib.mhc_read_gkma_dir(self._h, _ptr(corr), _ptr(integ), C.byref(n)), "read_gkma_dir")
+        return {"corr": corr, "integral": integ, "n_samples": n.value}
+
+    def read_gkma_cross(self):
+        """<J_b^mu(t + tau) J_b2^nu(t)> and its running integral, [L, nb, nb, 3 mu, 3 nu]."""
+        L = int(self.cfg["corr_len"])
+        corr = np.empty((L, self.nb, self.nb, 3, 3), dtype=np.float64)
+        integ = np.empty_like(corr)
+        n = C.c_int64()
+        self._check(self._lib.mhc_read_gkma_cross(self._h, _ptr(corr), _ptr(integ), C.byref(n)), "read_gkma_cross")
         return {"corr": corr, "integral": integ, "n_samples": n.value}
 
     def read_block_currents(self, t_count):

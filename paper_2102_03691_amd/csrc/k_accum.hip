@@ -68,6 +68,7 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
           if (n > 0)
             for (int64_t sg = sg0; sg <= sg1; ++sg) s += a.seg_part[((int64_t)mu * P + sg + b) * a.ld + t];
           a.X[((int64_t)b * 3 + mu) * a.ld + t] = s;
+          if (a.bring) a.bring[((int64_t)b * a.ring_len + (a.t0 + t) % a.ring_len) * 3 + mu] = s;
           h3[mu] += s;
         }
       }
@@ -218,8 +219,12 @@ constexpr int CL = 64;   // lags per tile
 __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
                                               int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
                                               double* __restrict__ csum, double* __restrict__ ccomp,
-                                              const int64_t* __restrict__ t0_dev) {
+                                              const int64_t* __restrict__ t0_dev, int64_t ring_zs, int64_t out_zs) {
   if (t0_dev) t0 = *t0_dev;
+  // grid z: one history ring of 3 columns and one slice of sums per z
+  ring += (int64_t)blockIdx.z * ring_zs;
+  csum += (int64_t)blockIdx.z * out_zs;
+  ccomp += (int64_t)blockIdx.z * out_zs;
   __shared__ double xs[CT][CR + 2];          // xs[t][r]
   __shared__ double rs[CT + CL][3];          // ring window
   const int tid = threadIdx.x;
@@ -312,10 +317,11 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
 
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
                        const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
-                       const int64_t* t0_dev) {
-  if (t_count <= 0) return hipSuccess;
-  dim3 grid((unsigned)((R3 + CR - 1) / CR), (unsigned)((L + CL - 1) / CL));
-  hipLaunchKernelGGL(k_corr, grid, dim3(256), 0, s, X, ldx, t_count, R3, L, ring, ring_len, t0, csum, ccomp, t0_dev);
+                       const int64_t* t0_dev, int nz, int64_t ring_zs, int64_t out_zs) {
+  if (t_count <= 0 || nz <= 0) return hipSuccess;
+  dim3 grid((unsigned)((R3 + CR - 1) / CR), (unsigned)((L + CL - 1) / CL), (unsigned)nz);
+  hipLaunchKernelGGL(k_corr, grid, dim3(256), 0, s, X, ldx, t_count, R3, L, ring, ring_len, t0, csum, ccomp, t0_dev,
+                     ring_zs, out_zs);
   return hipGetLastError();
 }
 

@@ -89,6 +89,9 @@ struct mhc_ctx {
   double* d_jd = nullptr;        // split Eq. 10 partials of the current pass
   double* d_jdtot = nullptr;     // split Eq. 10 per-step totals
   double *d_tdsum = nullptr, *d_tdcomp = nullptr;   // [dir][mu] time sums of the split totals
+  bool cross = false;            // bin-bin cross-correlations
+  double* d_bring = nullptr;     // cross: history of the binned currents [nb][ring_len][3]
+  double *d_xsum = nullptr, *d_xcomp = nullptr;     // cross sums [nb (second bin)][R3][3][L]
   double* dX = nullptr;
   double* d_ring = nullptr;
   int64_t ring_len = 0;
@@ -328,8 +331,12 @@ mhc_status mhc_configure(mhc_ctx* ctx, const mhc_run_config* cfg) {
   if (st) return st;
   if (!ctx->has_system || ctx->rows_started) return fail(ctx, MHC_ERR_STATE, "configure needs a system and no rows yet");
   if (!cfg) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL config");
-  if (cfg->methods < 1 || cfg->methods > 7 || !(cfg->methods & (MHC_HNEMA | MHC_GKMA)))
-    return fail(ctx, MHC_ERR_INVALID_ARG, "methods must be HNEMA, GKMA or both, optionally with DIRECTIONAL");
+  if (cfg->methods < 1 || cfg->methods > 15 || !(cfg->methods & (MHC_HNEMA | MHC_GKMA)))
+    return fail(ctx, MHC_ERR_INVALID_ARG, "methods must be HNEMA, GKMA or both, optionally with DIRECTIONAL or CROSS");
+  if ((cfg->methods & MHC_CROSS) && !(cfg->methods & MHC_GKMA))
+    return fail(ctx, MHC_ERR_INVALID_ARG, "CROSS needs GKMA");
+  if ((cfg->methods & MHC_CROSS) && (cfg->methods & MHC_DIRECTIONAL))
+    return fail(ctx, MHC_ERR_UNSUPPORTED, "CROSS together with DIRECTIONAL is not implemented");
   if (cfg->precision < MHC_PREC_FP32 || cfg->precision > MHC_PREC_FP8X3)
     return fail(ctx, MHC_ERR_INVALID_ARG, "unknown precision");
   if (cfg->t_block != 1 && (cfg->t_block < 32 || cfg->t_block > 512 || cfg->t_block % 32))
@@ -454,6 +461,12 @@ static size_t hn_doubles(int64_t nb, int nd) { return (size_t)2 * nd * nb * 3 + 
 // GKMA correlation doubles (sums and compensations of every direction pass).
 static size_t gk_doubles(const mhc_ctx* c) { return (size_t)2 * c->n_dir * c->cfg.corr_len * c->R3 * 3; }
 
+// Cross-correlation doubles (sums and compensations) and bin-history doubles.
+static size_t cross_doubles(const mhc_ctx* c) {
+  return c->cross ? (size_t)2 * c->nb * c->R3 * 3 * c->cfg.corr_len : 0;
+}
+static size_t bring_doubles(const mhc_ctx* c) { return c->cross ? (size_t)c->nb * c->ring_len * 3 : 0; }
+
 mhc_status mhc_finalize(mhc_ctx* ctx) {
   mhc_status st = enter(ctx);
   if (st) return st;
@@ -534,6 +547,18 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     ctx->d_slot_bin = reinterpret_cast<int32_t*>(psb);
     ctx->d_seg_part = reinterpret_cast<double*>(psp);
     ctx->n_seg = (int)n_seg;
+    if (c.methods & MHC_CROSS) {
+      void *pbr, *px;
+      const size_t br = (size_t)nb * ring_len * 3 * 8;
+      const size_t xs = (size_t)2 * nb * R3 * 3 * L * 8;
+      if ((st = dev_alloc(ctx, br, &pbr, "bin history ring"))) return st;
+      if ((st = dev_alloc(ctx, xs, &px, "cross-correlation sums"))) return st;
+      HIP_TRY(hipMemsetAsync(pbr, 0, br, ctx->stream), "zero bin ring");
+      ctx->cross = true;
+      ctx->d_bring = reinterpret_cast<double*>(pbr);
+      ctx->d_xsum = reinterpret_cast<double*>(px);
+      ctx->d_xcomp = ctx->d_xsum + (size_t)nb * R3 * 3 * L;
+    }
   }
   if ((st = dev_alloc(ctx, out_doubles * 8, &pout, "read-out"))) return st;
   if (c.t_block > 1) {
@@ -599,6 +624,10 @@ mhc_status mhc_reset(mhc_ctx* ctx) {
   if (ctx->d_hsum) HIP_TRY(hipMemsetAsync(ctx->d_hsum, 0, hn_doubles(nb, ctx->n_dir) * 8, ctx->stream), "zero sums");
   if (ctx->d_csum) HIP_TRY(hipMemsetAsync(ctx->d_csum, 0, gk_doubles(ctx) * 8, ctx->stream), "zero corr");
   if (ctx->d_ring) HIP_TRY(hipMemsetAsync(ctx->d_ring, 0, (size_t)ctx->ring_len * 3 * 8, ctx->stream), "zero ring");
+  if (ctx->cross) {
+    HIP_TRY(hipMemsetAsync(ctx->d_xsum, 0, cross_doubles(ctx) * 8, ctx->stream), "zero cross");
+    HIP_TRY(hipMemsetAsync(ctx->d_bring, 0, bring_doubles(ctx) * 8, ctx->stream), "zero bin ring");
+  }
   ctx->n_samples = 0;
   ctx->last_block = 0;
   return MHC_OK;
@@ -659,6 +688,7 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64
     a.tdcomp = ctx->d_tdcomp + 3 * dir;
   }
   a.X = gk ? ctx->dX : nullptr;
+  a.bring = ctx->d_bring;
   a.ring = ctx->d_ring;
   a.ring_len = ctx->ring_len;
   a.t0 = ctx->n_samples;
@@ -669,6 +699,11 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64
     HIP_TRY(launch_corr(ctx->stream, ctx->dX, ld, t_count, ctx->R3, c.corr_len, ctx->d_ring, ctx->ring_len,
                         ctx->n_samples, ctx->d_csum + off, ctx->d_ccomp + off, t0_dev),
             "correlation");
+    if (ctx->cross)   // every binned row against the history of every bin b2 (grid z = b2)
+      HIP_TRY(launch_corr(ctx->stream, ctx->dX, ld, t_count, ctx->R3, c.corr_len, ctx->d_bring, ctx->ring_len,
+                          ctx->n_samples, ctx->d_xsum, ctx->d_xcomp, t0_dev, (int)ctx->nb, ctx->ring_len * 3,
+                          ctx->R3 * 3 * c.corr_len),
+              "cross-correlation");
   }
   return MHC_OK;
 }
@@ -890,6 +925,35 @@ mhc_status mhc_read_gkma_dir(mhc_ctx* ctx, double* corr, double* integral, int64
   return MHC_OK;
 }
 
+mhc_status mhc_read_gkma_cross(mhc_ctx* ctx, double* corr, double* integral, int64_t* n_samples) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized || !ctx->cross) return fail(ctx, MHC_ERR_STATE, "cross-correlations not enabled");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  const int L = ctx->cfg.corr_len;
+  const int64_t R3 = ctx->R3, nb = ctx->nb;
+  const size_t per = (size_t)L * R3 * 3;
+  std::vector<double> h(2 * per);
+  for (int64_t b2 = 0; b2 < nb; ++b2) {
+    HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_xsum + b2 * per, ctx->d_xcomp + b2 * per, R3, L, ctx->n_samples,
+                               ctx->cfg.dt, ctx->d_out, ctx->d_out + per),
+            "finish");
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, 2 * per * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
+    for (int tau = 0; tau < L; ++tau)
+      for (int64_t b = 0; b < nb; ++b)
+        for (int mu = 0; mu < 3; ++mu)
+          for (int nu = 0; nu < 3; ++nu) {
+            const size_t src = ((size_t)tau * R3 + b * 3 + mu) * 3 + nu;
+            const size_t dst = ((((size_t)tau * nb + b) * nb + b2) * 3 + mu) * 3 + nu;
+            if (corr) corr[dst] = h[src];
+            if (integral) integral[dst] = h[per + src];
+          }
+  }
+  if (n_samples) *n_samples = ctx->n_samples;
+  return MHC_OK;
+}
+
 mhc_status mhc_read_block_currents(mhc_ctx* ctx, int32_t t_count, double* jb) {
   mhc_status st = enter(ctx);
   if (st) return st;
@@ -924,6 +988,7 @@ static size_t state_bytes(const mhc_ctx* c) {
   size_t n = sizeof(StateHeader);
   if (c->d_hsum) n += hn_doubles(c->nb, c->n_dir) * 8;
   if (c->d_csum) n += gk_doubles(c) * 8 + (size_t)c->ring_len * 3 * 8;
+  n += (cross_doubles(c) + bring_doubles(c)) * 8;
   return n;
 }
 
@@ -957,6 +1022,13 @@ mhc_status mhc_save_state(mhc_ctx* ctx, void* buf, size_t* len) {
     HIP_TRY(hipMemcpyAsync(p, ctx->d_ring, r, hipMemcpyDeviceToHost, ctx->stream), "save");
     p += r;
   }
+  if (ctx->cross) {
+    const size_t x = cross_doubles(ctx) * 8, br = bring_doubles(ctx) * 8;
+    HIP_TRY(hipMemcpyAsync(p, ctx->d_xsum, x, hipMemcpyDeviceToHost, ctx->stream), "save");
+    p += x;
+    HIP_TRY(hipMemcpyAsync(p, ctx->d_bring, br, hipMemcpyDeviceToHost, ctx->stream), "save");
+    p += br;
+  }
   HIP_TRY(hipStreamSynchronize(ctx->stream), "save sync");
   *len = need;
   return MHC_OK;
@@ -985,6 +1057,13 @@ mhc_status mhc_load_state(mhc_ctx* ctx, const void* buf, size_t len) {
     p += n;
     const size_t r = (size_t)ctx->ring_len * 3 * 8;
     HIP_TRY(hipMemcpyAsync(ctx->d_ring, p, r, hipMemcpyHostToDevice, ctx->stream), "load");
+    p += r;
+  }
+  if (ctx->cross) {
+    const size_t x = cross_doubles(ctx) * 8, br = bring_doubles(ctx) * 8;
+    HIP_TRY(hipMemcpyAsync(ctx->d_xsum, p, x, hipMemcpyHostToDevice, ctx->stream), "load");
+    p += x;
+    HIP_TRY(hipMemcpyAsync(ctx->d_bring, p, br, hipMemcpyHostToDevice, ctx->stream), "load");
   }
   HIP_TRY(hipStreamSynchronize(ctx->stream), "load sync");
   ctx->n_samples = hd.n_samples;

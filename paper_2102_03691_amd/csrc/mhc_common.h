@@ -146,6 +146,7 @@ struct ReduceArgs {
   double* ring; int64_t ring_len; int64_t t0;                // GKMA history
   const int64_t* t0_dev;    // if set, the block's first step index is read here instead of t0
   const double* jdtot; double* tdsum; double* tdcomp;        // split Eq. 10 totals (may be null)
+  double* bring;            // cross-correlation: bin history [nb][ring_len][3] (may be null)
 };
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a);
 
@@ -155,9 +156,11 @@ hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int 
 // GKMA correlation update: for r < R3 = 3(nb+1), tau < L, nu < 3
 //   C[r][nu][tau] += sum_{t < t_count, t0+t-tau >= 0} X[r][t] * ring[(t0+t-tau) % ring_len][nu]
 // accumulated with Neumaier compensation into csum/ccomp (lag-contiguous).
+// nz > 1 repeats it for nz rings at ring + z ring_zs into sums at + z out_zs
+// (the cross-correlation: one ring per second bin).
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
                        const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
-                       const int64_t* t0_dev);
+                       const int64_t* t0_dev, int nz = 1, int64_t ring_zs = 0, int64_t out_zs = 0);
 
 // Read-out of the GKMA accumulators: C = (csum + ccomp) / (S - tau) (zero when
 // S <= tau) and its trapezoid running integral with step dt, written as
