@@ -47,6 +47,12 @@ def library():
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2102_03691_amd._build.build() "
                            "(or __graft_entry__.build()); there is no fallback path")
+    try:
+        # torch, when present, loads its HIP runtime first, so that the
+        # library binds to the same runtime instead of a second copy
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P = C.POINTER
