@@ -410,6 +410,16 @@ mhc_status mhc_shc_spectrum_dir(mhc_shc *shc, int32_t n_omega, const double *ome
 
 /* Clear the sums and the sample count (the next push starts a new run). */
 mhc_status mhc_shc_reset(mhc_shc *shc);
+
+/* Accumulator state (float64 sums and compensations, the virial history the
+ * next blocks correlate against, the sample count), as for mhc_save_state:
+ * with buf == NULL *len is set to the size needed (about
+ * (n_lags + t_block) * 3N * 12 bytes); mhc_shc_load_state restores a buffer
+ * saved from an object with the same n_atoms, n_lags and t_block, after which
+ * pushes continue the run exactly.  Errors: INVALID_ARG (size / format
+ * mismatch), HIP. */
+mhc_status mhc_shc_save_state(mhc_shc *shc, void *buf, size_t *len);
+mhc_status mhc_shc_load_state(mhc_shc *shc, const void *buf, size_t len);
 mhc_status mhc_shc_synchronize(mhc_shc *shc);
 
 /* HIP-event timing of the product kernels of each pushed block, as for

@@ -91,6 +91,8 @@ def library():
         "mhc_shc_read": (i32, [vp, vp, P(i64)]),
         "mhc_shc_spectrum": (i32, [vp, i32, vp, dbl, i32, vp]),
         "mhc_shc_read_dir": (i32, [vp, vp, P(i64)]),
+        "mhc_shc_save_state": (i32, [vp, vp, P(C.c_size_t)]),
+        "mhc_shc_load_state": (i32, [vp, vp, C.c_size_t]),
         "mhc_shc_spectrum_dir": (i32, [vp, i32, vp, dbl, i32, vp]),
         "mhc_shc_reset": (i32, [vp]),
         "mhc_shc_synchronize": (i32, [vp]),
@@ -515,6 +517,17 @@ class ModalSHC:
 
     def reset(self):
         self._check(self._lib.mhc_shc_reset(self._h), "shc reset")
+
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        self._check(self._lib.mhc_shc_save_state(self._h, None, C.byref(n)), "shc save_state")
+        buf = C.create_string_buffer(n.value)
+        self._check(self._lib.mhc_shc_save_state(self._h, buf, C.byref(n)), "shc save_state")
+        return buf.raw[: n.value]
+
+    def load_state(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(self._lib.mhc_shc_load_state(self._h, buf, len(data)), "shc load_state")
 
     def synchronize(self):
         self._check(self._lib.mhc_shc_synchronize(self._h), "shc synchronize")

@@ -548,6 +548,7 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     ctx->d_seg_part = reinterpret_cast<double*>(psp);
     ctx->n_seg = (int)n_seg;
     if (c.methods & MHC_CROSS) {
+      if (nb > 65535) return fail(ctx, MHC_ERR_INVALID_ARG, "CROSS allows at most 65535 bins");
       void *pbr, *px;
       const size_t br = (size_t)nb * ring_len * 3 * 8;
       const size_t xs = (size_t)2 * nb * R3 * 3 * L * 8;

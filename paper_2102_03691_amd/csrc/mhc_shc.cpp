@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <string>
 #include <vector>
@@ -305,6 +306,64 @@ mhc_status mhc_shc_reset(mhc_shc* c) {
   SHIP_TRY(hipMemsetAsync(c->ksum, 0, (size_t)c->n_lags * 9 * 2 * 8, c->stream), "clear sums");
   SHIP_TRY(hipStreamSynchronize(c->stream), "reset sync");
   c->S = 0;
+  return MHC_OK;
+}
+
+// Saved state: a header, the float64 sums and compensations, then the virial
+// ring (the history later blocks correlate against).
+namespace {
+struct ShcStateHeader {
+  uint64_t magic;
+  int64_t N, ring_len, ld, S;
+  int32_t n_lags, T;
+};
+constexpr uint64_t kShcMagic = 0x4D48435348435331ull;  // "MHCSHCS1"
+size_t shc_state_bytes(const mhc_shc* c) {
+  return sizeof(ShcStateHeader) + (size_t)c->n_lags * 9 * 2 * 8 + (size_t)c->ring_len * 3 * c->ld * 4;
+}
+}  // namespace
+
+mhc_status mhc_shc_save_state(mhc_shc* c, void* buf, size_t* len) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  if (!len) return sfail(c, MHC_ERR_INVALID_ARG, "NULL len");
+  const size_t need = shc_state_bytes(c);
+  if (!buf) {
+    *len = need;
+    return MHC_OK;
+  }
+  if (*len < need) return sfail(c, MHC_ERR_INVALID_ARG, "buffer too small");
+  ShcStateHeader hd{kShcMagic, c->N, c->ring_len, c->ld, c->S, c->n_lags, c->T};
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  const size_t ks = (size_t)c->n_lags * 9 * 2 * 8;
+  SHIP_TRY(hipMemcpyAsync(p, c->ksum, ks, hipMemcpyDeviceToHost, c->stream), "save sums");
+  p += ks;
+  SHIP_TRY(hipMemcpyAsync(p, c->ring, (size_t)c->ring_len * 3 * c->ld * 4, hipMemcpyDeviceToHost, c->stream),
+           "save ring");
+  SHIP_TRY(hipStreamSynchronize(c->stream), "save sync");
+  *len = need;
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_load_state(mhc_shc* c, const void* buf, size_t len) {
+  mhc_status st = senter(c);
+  if (st) return st;
+  if (!buf || len != shc_state_bytes(c)) return sfail(c, MHC_ERR_INVALID_ARG, "state size mismatch");
+  ShcStateHeader hd;
+  std::memcpy(&hd, buf, sizeof hd);
+  if (hd.magic != kShcMagic || hd.N != c->N || hd.ring_len != c->ring_len || hd.ld != c->ld ||
+      hd.n_lags != c->n_lags || hd.T != c->T || hd.S < 0)
+    return sfail(c, MHC_ERR_INVALID_ARG, "state from a different configuration");
+  const char* p = static_cast<const char*>(buf) + sizeof hd;
+  const size_t ks = (size_t)c->n_lags * 9 * 2 * 8;
+  SHIP_TRY(hipMemcpyAsync(c->ksum, p, ks, hipMemcpyHostToDevice, c->stream), "load sums");
+  p += ks;
+  SHIP_TRY(hipMemcpyAsync(c->ring, p, (size_t)c->ring_len * 3 * c->ld * 4, hipMemcpyHostToDevice, c->stream),
+           "load ring");
+  SHIP_TRY(hipStreamSynchronize(c->stream), "load sync");
+  c->S = hd.S;
   return MHC_OK;
 }
 
