@@ -16,8 +16,10 @@
  * Sec. II.B.ii) or the GKMA correlation <J_b^mu(t+tau) J^nu(t)> and its
  * running time integral (Eq. 17, Sec. II.B.i).  Dividing by T V F_e or by
  * k_B T^2 V to obtain kappa is left to the caller (scalar prefactors).
- * The spectral-heat-current method (Sec. II.C, Eqs. 20-23) has its own object,
- * mhc_shc (end of this header), which needs no eigenvectors.
+ * Options: every modal output split by the direction of the atoms' motion
+ * (MHC_DIRECTIONAL) and bin-bin cross-correlations of the modal currents
+ * (MHC_CROSS).  The spectral-heat-current method (Sec. II.C, Eqs. 20-23) has
+ * its own object, mhc_shc (end of this header), which needs no eigenvectors.
  *
  * Conventions shared by every entry point
  * ---------------------------------------

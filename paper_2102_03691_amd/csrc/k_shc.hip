@@ -55,7 +55,9 @@ hipError_t launch_shc_ring(hipStream_t s, const float* W, const float* v, int t_
 }
 
 // ---------------------------------------------------------------- products
-// Work-group (kc, a, b): steps t in [64a, 64a + 64) x lags tau in
+// Work-group (kc, a, b) (a 1-D grid; consecutive ids go to different XCDs,
+// so ids are remapped to give each XCD a contiguous range, and the tiles of
+// one dof range share that XCD's L2): steps t in [64a, 64a + 64) x lags tau in
 // [64b, 64b + 64) x the 3 components mu, over the dof range of direction
 // segment nu = kc / n_kcs: columns nu Np + [c dk, c dk + dk) with c = kc % n_kcs,
 // cut at nu Np + N.  The origins s' = s0 + t - tau of the tile are 127
@@ -80,17 +82,20 @@ constexpr int SH_WTILE = SH_ROWS * SH_WS + 28;
 
 __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring,
                                                  int64_t ring_len, int64_t ld, int64_t N, int64_t Np, int t_count,
-                                                 int64_t s0, int64_t dk, int n_kcs, int n_lags_pad,
-                                                 double* __restrict__ part) {
+                                                 int64_t s0, int64_t dk, int n_kcs, int n_ttiles,
+                                                 int n_lags_pad, double* __restrict__ part) {
   __shared__ f32x4 vs[SH_DC / 4][SH_VP];
   // the W tile (rows at sh_wrow), reused for the final step-group sums once the products are done
   __shared__ __attribute__((aligned(16))) float ws[SH_WTILE];
   double (*red)[SH_L][3] = reinterpret_cast<double (*)[SH_L][3]>(ws);     // [16][64][3] doubles: 24 KiB
   static_assert(16 * SH_L * 3 * sizeof(double) <= SH_WTILE * sizeof(float), "reduction fits in the W tile");
   const int tid = threadIdx.x;
-  const int kc = blockIdx.x;
-  const int a = blockIdx.y;
-  const int b = blockIdx.z;
+  const int G = gridDim.x;
+  const int v = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int n_tiles = n_ttiles * (n_lags_pad / SH_L);
+  const int kc = v / n_tiles;
+  const int a = (v % n_tiles) % n_ttiles;
+  const int b = (v % n_tiles) / n_ttiles;
   const int tl = tid & 15;
   const int tt = (tl + (tid >> 4)) & 15;
   const int64_t seg0 = (int64_t)(kc / n_kcs) * Np;
@@ -211,7 +216,7 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ vt, 
     const int lt = tid / 3, m = tid % 3;
     double s = 0.0;
     for (int g = 0; g < 16; ++g) s += red[g][lt][m];
-    part[(((int64_t)kc * gridDim.y + a) * n_lags_pad + (int64_t)SH_L * b + lt) * 3 + m] = s;
+    part[(((int64_t)kc * n_ttiles + a) * n_lags_pad + (int64_t)SH_L * b + lt) * 3 + m] = s;
   }
 }
 
@@ -240,8 +245,8 @@ hipError_t launch_shc_block(hipStream_t s, const float* vt, const float* ring, i
   const int n_ttiles = (t_count + SH_T - 1) / SH_T;
   const int n_lags_pad = (n_lags + SH_L - 1) / SH_L * SH_L;
   const int n_ltiles = n_lags_pad / SH_L;
-  hipLaunchKernelGGL(k_shc_gram, dim3((unsigned)(3 * n_kcs), (unsigned)n_ttiles, (unsigned)n_ltiles), dim3(256), 0,
-                     s, vt, ring, ring_len, ld, N, Np, t_count, s0, dk, n_kcs, n_lags_pad, part);
+  hipLaunchKernelGGL(k_shc_gram, dim3((unsigned)(3 * n_kcs * n_ttiles * n_ltiles)), dim3(256), 0, s, vt, ring, ring_len,
+                     ld, N, Np, t_count, s0, dk, n_kcs, n_ttiles, n_lags_pad, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_shc_accum, dim3((unsigned)((3 * n_lags * 3 + 255) / 256)), dim3(256), 0, s, part, n_kcs,
