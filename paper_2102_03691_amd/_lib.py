@@ -45,8 +45,8 @@ def library():
         return _lib
     path = library_path()
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is missing: build it with paper_2102_03691_amd._build.build() "
-                           "(or __graft_entry__.build()); there is no fallback path")
+        raise RuntimeError(f"{path} is missing: build it with paper_2102_03691_amd._build.build(); "
+                           "there is no fallback path")
     try:
         # torch, when present, loads its HIP runtime first, so that the
         # library binds to the same runtime instead of a second copy
