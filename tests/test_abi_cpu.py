@@ -99,3 +99,33 @@ def test_shc_create_without_gpu_reports_hip_error():
     h = C.c_void_p()
     assert lib.mhc_shc_create(0, None, 10, 8, 64, C.byref(h)) == 4
     assert h.value is None
+
+
+def test_header_compiles_as_c_and_links(tmp_path):
+    """include/mhc.h is plain C: a C99 program that uses it builds against the
+    library and runs its host-only helpers (no GPU needed)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib = _lib.library_path()
+    src = tmp_path / "use_mhc.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "mhc.h"
+int main(void) {
+  double f[4] = {0.5, 1.5, 2.5, 3.5};
+  int32_t b[4];
+  mhc_status st = mhc_bins_uniform(4, f, 2, 0.0, 4.0, b);
+  mhc_run_config cfg = {MHC_HNEMA | MHC_GKMA | MHC_DIRECTIONAL, MHC_PREC_BF16X3, 128, 10, 1.0, 0, MHC_SCHED_AUTO, {0, 0}};
+  printf("%d %d %d %d %d %d %s\n", (int)st, b[0], b[1], b[2], b[3], mhc_abi_version(), mhc_status_string(MHC_ERR_STATE));
+  return cfg.t_block == 128 ? 0 : 1;
+}
+''')
+    exe = tmp_path / "use_mhc"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(root, "include"), str(src), lib,
+                    "-Wl,-rpath," + os.path.dirname(lib), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert out[:5] == ["0", "0", "0", "1", "1"] and out[5] == "1" and out[6] == "MHC_ERR_STATE"
