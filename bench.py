@@ -36,7 +36,11 @@ WORKLOADS = {
     "sc16_hnema_fp32_t1": ((16, 16, 16), 1, 0, 1, 500, 0, 40),
     "rod4x4x1500_gkma_bf16x3_t256": ((4, 4, 1500), 256, 1, 3, 1000, 2000, 195),
     "rod4x4x1500_gkma_fp32_t256": ((4, 4, 1500), 256, 0, 3, 1000, 2000, 20),
+    # shaped like the paper's speed test (Sec. III.C.ii): 8000 atoms, the modal current
+    # every step, 3 bins of 8000 modes (equal mode counts in frequency order)
+    "sc20_3bins_fp32_t1": ((20, 20, 20), 1, 0, 1, 3, 0, 8),
 }
+COUNT_BINS = {"sc20_3bins_fp32_t1"}
 DEFAULT = "slab48x48x4_hnema_bf16x3_t128"
 
 # Uneven serving-style batch: 16 simple-cubic systems, edges and methods drawn by seed
@@ -90,14 +94,26 @@ def profiled_traffic(workload, kernel):
     return None
 
 
-def make_context(lat, t_block, precision, methods, nb, corr_len, device=0, schedule=0):
+def count_bins(freq, nb):
+    """Bins of equal mode counts in frequency order (stable for equal frequencies)."""
+    import numpy as np
+    order = np.argsort(np.asarray(freq), kind="stable")
+    bins = np.empty(len(order), dtype=np.int32)
+    bins[order] = (np.arange(len(order)) * nb) // len(order)
+    return bins
+
+
+def make_context(lat, t_block, precision, methods, nb, corr_len, device=0, schedule=0, bins=None):
     import torch
     import synth
     from paper_2102_03691_amd import ModalHC
     h = ModalHC(device)
     m = synth.masses(lat.n_atoms)
     h.load_system(m, lat.frequencies)
-    h.set_bins_uniform(nb, 0.0, lat.f_max)
+    if bins is None:
+        h.set_bins_uniform(nb, 0.0, lat.f_max)
+    else:
+        h.set_bins(nb, bins)
     h.configure(methods=methods, precision=precision, t_block=t_block, corr_len=corr_len, dt=1.0,
                 schedule=schedule)
     M = lat.n_modes
@@ -132,7 +148,7 @@ def time_pushes(h, blocks_v, blocks_W, n_warm, n_steps):
     return t1 - t0, launches, kms
 
 
-def cpu_baseline(dims, t_block, nb, budget_s=15.0):
+def cpu_baseline(dims, t_block, nb, budget_s=15.0, bins=None):
     """The FP64 oracle on a bounded sample of the same workload.
 
     Same lattice and block length; the oracle's Eq. 13/16 projection and the
@@ -147,7 +163,8 @@ def cpu_baseline(dims, t_block, nb, budget_s=15.0):
     lat = synth.BlochLattice(dims)
     m = synth.masses(lat.n_atoms)
     T = max(t_block, 128)
-    bins = oracle.bin_of_mode(lat.frequencies, nb, 0.0, lat.f_max)
+    if bins is None:
+        bins = oracle.bin_of_mode(lat.frequencies, nb, 0.0, lat.f_max)
     rows_per = min(lat.n_modes, 2048)
     done_units, spent, n_rows, n_blocks = 0, 0.0, 0, 0
     while spent < budget_s and n_blocks < 64:
@@ -172,6 +189,19 @@ def cpu_baseline(dims, t_block, nb, budget_s=15.0):
     return {"value": done_units / spent, "unit": "atom*mode*steps/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{n_rows} mode rows x {T} steps over {n_blocks} block(s) of the same lattice "
                       f"({lat.n_modes} modes; float64 numpy/BLAS), {spent:.1f} s of CPU work"}
+
+
+def cpu_baseline_one_core(dims, t_block, nb, budget_s=6.0, bins=None):
+    """The same oracle sample with the BLAS pool limited to one thread (the
+    paper's comparisons are against single CPU cores, Sec. III.C.ii)."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        return None
+    with threadpool_limits(limits=1):
+        r = cpu_baseline(dims, t_block, nb, budget_s=budget_s, bins=bins)
+    r["cores"] = 1
+    return r
 
 
 def run_shc(args):
@@ -359,7 +389,8 @@ def main():
     lat = synth.BlochLattice(dims)
     N, M = lat.n_atoms, lat.n_modes
     log(f"workload {args.workload}: N={N} M={M} T={t_block} prec={prec} steps={K} warmup={args.warmup}")
-    h, m = make_context(lat, t_block, prec, methods, nb, L, schedule=args.schedule)
+    bins = count_bins(lat.frequencies, nb) if args.workload in COUNT_BINS else None
+    h, m = make_context(lat, t_block, prec, methods, nb, L, schedule=args.schedule, bins=bins)
     md_per_step = t_block if t_block > 1 else 256      # per-step path: 256 MD steps per launch
     # inputs resident in HBM before the timed region (distinct block per bench step, cycled if huge)
     bytes_per_block = md_per_step * N * 12 * 4
@@ -400,7 +431,9 @@ def main():
            "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": {0: "f32", 1: "bf16x3"}[prec], "data": "synthetic",
            "config": {"workload": args.workload, "atoms": N, "modes": M, "md_steps_per_step": md_per_step,
-                      "t_block": t_block, "bins": nb, "corr_len": L,
+                      "t_block": t_block,
+                      "bins": nb if bins is None else f"{nb} of equal mode counts in frequency order",
+                      "corr_len": L,
                       "schedule": {0: "auto", 1: "tiles", 2: "stream-K", 3: "split"}[args.schedule]
                       + ("" if t_block == 1 else
                          " -> " + {1: "tiles", 2: "stream-K", 3: "split"}.get(sched_used, "?")),
@@ -412,7 +445,7 @@ def main():
 
     if not args.no_fp32_baseline and not (prec == 0 and t_block == 1):
         log("plain per-step FP32 path on the same lattice")
-        h2, m2 = make_context(lat, 1, 0, 1, nb, 0)
+        h2, m2 = make_context(lat, 1, 0, 1, nb, 0, bins=bins)
         n_md = 256
         v2, W2 = synth.gen_steps_torch(2, m2, n_md, device="cuda:0")
         wall2, l2, k2 = time_pushes(h2, [v2], [W2], 0, 1)
@@ -427,7 +460,12 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(dims, t_block, nb)
+        out["cpu_baseline"] = cpu_baseline(dims, t_block, nb, bins=bins)
+        log("cpu baseline on one core (oracle)")
+        one = cpu_baseline_one_core(dims, t_block, nb, bins=bins)
+        if one is not None:
+            out["cpu_baseline_one_core"] = one
+            out["speedup_vs_one_cpu_core"] = value / one["value"]
     print(json.dumps(out), flush=True)
 
 
