@@ -68,8 +68,11 @@ hipError_t launch_shc_ring(hipStream_t s, const float* W, const float* v, int t_
 // rows (broadcast); velocity rows are stored with one float4 of padding per
 // four steps so that those reads spread over all banks.  Rows before the
 // first sample, rows after the block's last step and steps past t_count are
-// staged as zeros.  The thread's 4 steps are added, then the 16 step groups
-// in order, giving part[kc][a][tau][mu] = sum over the tile's steps.
+// staged as zeros.  With one wave per SIMD the LDS latency is exposed, so the
+// reads of a dof group go out in two batches (diagonals 0..3 and 4..6), each
+// issued while the products of the previous batch run.  The thread's 4 steps
+// are added, then the 16 step groups in order, giving part[kc][a][tau][mu] =
+// sum over the tile's steps.
 constexpr int SH_T = 64, SH_L = 64, SH_DC = 32;
 constexpr int SH_ROWS = SH_T + SH_L - 1;                 // 127
 constexpr int SH_VP = SH_T + SH_T / 4;                   // padded step index range of the V tile
@@ -177,18 +180,28 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ vt, 
     store();
     __syncthreads();
     if (jc + SH_DC < j1) load(jc + SH_DC);
-#pragma unroll 2
-    for (int d4 = 0; d4 < SH_DC / 4; ++d4) {
-      f32x4 vv[4];
+    // LDS reads one batch ahead of the products: the rows of diagonals
+    // q = 0..3 of dof group d4+1 (and its velocities) are read while the
+    // products of q = 4..6 of group d4 run, those of q = 4..6 while q = 0..3 run
+    auto rd_w = [&](int d4, int q0, int nq, f32x4 (*w)[3]) {
 #pragma unroll
-      for (int x = 0; x < 4; ++x) vv[x] = vs[d4][5 * tt + x];           // step 4tt + x, padded index
+      for (int k = 0; k < nq; ++k) {
+        const int r = 4 * (tt - tl) + (q0 + k - 3) + (SH_L - 1);
 #pragma unroll
-      for (int q = 0; q < 7; ++q) {                                       // q = x - y + 3
-        const int r = 4 * (tt - tl) + (q - 3) + (SH_L - 1);
+        for (int m = 0; m < 3; ++m) w[k][m] = *reinterpret_cast<const f32x4*>(&ws[sh_wrow(r) + m * SH_DC + 4 * d4]);
+      }
+    };
+    auto rd_v = [&](int d4, f32x4* vv) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x) vv[x] = vs[d4][5 * tt + x];
+    };
+    auto prod = [&](int q0, int nq, f32x4 (*w)[3], const f32x4* vv) {
+#pragma unroll
+      for (int k = 0; k < nq; ++k) {
+        const int q = q0 + k;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-          const f32x4 w4 = *reinterpret_cast<const f32x4*>(&ws[sh_wrow(r) + m * SH_DC + 4 * d4]);
-          const double w0 = w4.x, w1 = w4.y, w2 = w4.z, w3 = w4.w;
+          const double w0 = w[k][m].x, w1 = w[k][m].y, w2 = w[k][m].z, w3 = w[k][m].w;
 #pragma unroll
           for (int x = 0; x < 4; ++x) {
             const int y = x - (q - 3);
@@ -202,6 +215,25 @@ __global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ vt, 
           }
         }
       }
+    };
+    f32x4 vA[4], vB[4], wa[4][3], wb[3][3];
+    rd_v(0, vA);
+    rd_w(0, 0, 4, wa);
+#pragma unroll
+    for (int d4 = 0; d4 < SH_DC / 4; ++d4) {
+      f32x4* vc = (d4 & 1) ? vB : vA;
+      f32x4* vn = (d4 & 1) ? vA : vB;
+      rd_w(d4, 4, 3, wb);
+      __builtin_amdgcn_sched_barrier(0);
+      prod(0, 4, wa, vc);
+      __builtin_amdgcn_sched_barrier(0);
+      if (d4 + 1 < SH_DC / 4) {
+        rd_v(d4 + 1, vn);
+        rd_w(d4 + 1, 0, 4, wa);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      prod(4, 3, wb, vc);
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   }
