@@ -10,6 +10,7 @@
 // current J^mu = sum_i sum_nu W_i^{mu nu} v_i^nu (Eq. 10) is summed in float64
 // per chunk of atoms.
 #include "mhc_common.h"
+#include "mhc_prep_group.h"
 #include "mhc_numeric.h"
 
 namespace mhc {
@@ -149,18 +150,15 @@ hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, in
 // tab[1] (device memory), so a captured graph can be fed new inputs.  With
 // dir in {0, 1, 2} the virial channels hold column dir of W only (the
 // motion-direction split), and their maxima are taken over that column.
-__global__ void __launch_bounds__(256) k_col_scale(const float* v, const float* W,
-                                                   const float* __restrict__ sqrt_m,
-                                                   const float* __restrict__ inv_sqrt_m, int64_t N, int t_count,
-                                                   int t_pad, float* __restrict__ col_part,
-                                                   const float* const* __restrict__ tab, int dir) {
+__device__ __forceinline__ void col_scale_body(const float* v, const float* W, const float* __restrict__ sqrt_m,
+                                               const float* __restrict__ inv_sqrt_m, int64_t N, int t_count,
+                                               int t_pad, float* __restrict__ col_part,
+                                               const float* const* __restrict__ tab, int dir, int t, int cc) {
   __shared__ float sh[4][256];
   if (tab) {
     v = tab[0];
     W = tab[1];
   }
-  const int t = blockIdx.x;
-  const int cc = blockIdx.y;
   float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
   if (t < t_count) {
     const int64_t i1 = min(N, (int64_t)(cc + 1) * COLSCALE_ATOMS);
@@ -190,6 +188,35 @@ __global__ void __launch_bounds__(256) k_col_scale(const float* v, const float* 
   if (threadIdx.x < 4) col_part[((int64_t)cc * 4 + threadIdx.x) * t_pad + t] = sh[threadIdx.x][0];
 }
 
+__global__ void __launch_bounds__(256) k_col_scale(const float* v, const float* W,
+                                                   const float* __restrict__ sqrt_m,
+                                                   const float* __restrict__ inv_sqrt_m, int64_t N, int t_count,
+                                                   int t_pad, float* __restrict__ col_part,
+                                                   const float* const* __restrict__ tab, int dir) {
+  col_scale_body(v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad, col_part, tab, dir, blockIdx.x, blockIdx.y);
+}
+
+// System of a grouped work-group: the last i with wg0[i] <= wg (wg0 ascending).
+__device__ __forceinline__ int group_system(const PrepDesc* __restrict__ d, int n, int wg, bool prep) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int w0 = prep ? d[mid].wg0_prep : d[mid].wg0_cs;
+    if (w0 <= wg) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The column maxima of every system of a group in one launch: work-group wg
+// is work-group (t, cc) of its system's own grid (t_pad x n_cc).
+__global__ void __launch_bounds__(256) k_col_scale_group(const PrepDesc* __restrict__ d, int n, int t_count) {
+  const int i = group_system(d, n, blockIdx.x, false);
+  const PrepDesc& s = d[i];
+  const int local = blockIdx.x - s.wg0_cs;
+  col_scale_body(nullptr, nullptr, s.sqrt_m, s.inv_sqrt_m, s.N, t_count, s.t_pad, s.col_part, s.tab, -1,
+                 local % s.t_pad, local / s.t_pad);
+}
+
 hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const float* sqrt_m,
                             const float* inv_sqrt_m, int64_t N, int t_count, int t_pad, float* col_part,
                             const float* const* tab, int dir) {
@@ -213,15 +240,13 @@ constexpr int PREP_T = 32;
 constexpr int PREP_K = 3 * ATOMS_PER_PREP;   // 96 dofs
 
 template <int MODE>   // 0 = plain, 1 = FP32, 2 = BF16 hi/lo, 3 = e4m3, 4 = e4m3 hi/lo fragments
-__global__ void __launch_bounds__(256) k_input_prep(const float* v, const float* W,
-                                                    const float* __restrict__ sqrt_m,
-                                                    const float* __restrict__ inv_sqrt_m, int64_t N,
-                                                    int t_count, int t_pad, void* __restrict__ B,
-                                                    int64_t K_pad, double* __restrict__ jt_part,
-                                                    float* __restrict__ col_scale,
-                                                    const float* __restrict__ col_part,
-                                                    const float* const* __restrict__ tab, int dir,
-                                                    double* __restrict__ jd_part) {
+__device__ __forceinline__ void input_prep_body(const float* v, const float* W, const float* __restrict__ sqrt_m,
+                                                const float* __restrict__ inv_sqrt_m, int64_t N, int t_count,
+                                                int t_pad, void* __restrict__ B, int64_t K_pad,
+                                                double* __restrict__ jt_part, float* __restrict__ col_scale,
+                                                const float* __restrict__ col_part,
+                                                const float* const* __restrict__ tab, int dir,
+                                                double* __restrict__ jd_part, int chunk, int n_chunks, int tb) {
   __shared__ float ch[4][PREP_T][PREP_K + 4];
   __shared__ float csc[4][PREP_T];
   if (tab) {   // inputs named through device memory (graph replay)
@@ -229,9 +254,6 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* v, const float*
     W = tab[1];
   }
   const int tid = threadIdx.x;
-  const int chunk = blockIdx.x;
-  const int n_chunks = gridDim.x;
-  const int tb = blockIdx.y;
   const int tl = tid >> 3;
   const int sub = tid & 7;
   const int t = tb * PREP_T + tl;
@@ -399,6 +421,48 @@ __global__ void __launch_bounds__(256) k_input_prep(const float* v, const float*
       Bp[base + 64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
     }
   }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_input_prep(const float* v, const float* W,
+                                                    const float* __restrict__ sqrt_m,
+                                                    const float* __restrict__ inv_sqrt_m, int64_t N,
+                                                    int t_count, int t_pad, void* __restrict__ B,
+                                                    int64_t K_pad, double* __restrict__ jt_part,
+                                                    float* __restrict__ col_scale,
+                                                    const float* __restrict__ col_part,
+                                                    const float* const* __restrict__ tab, int dir,
+                                                    double* __restrict__ jd_part) {
+  input_prep_body<MODE>(v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad, B, K_pad, jt_part, col_scale, col_part, tab,
+                        dir, jd_part, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+// The input prep of every system of a group in one launch: work-group wg is
+// work-group (chunk, tb) of its system's own grid (n_chunks x t_pad / 32).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_input_prep_group(const PrepDesc* __restrict__ d, int n, int t_count) {
+  const int i = group_system(d, n, blockIdx.x, true);
+  const PrepDesc& s = d[i];
+  const int local = blockIdx.x - s.wg0_prep;
+  input_prep_body<MODE>(nullptr, nullptr, s.sqrt_m, s.inv_sqrt_m, s.N, t_count, s.t_pad, s.B, s.K_pad, s.jt_part,
+                        s.col_scale, s.col_part, s.tab, -1, nullptr, local % s.n_chunks, s.n_chunks,
+                        local / s.n_chunks);
+}
+
+hipError_t launch_prep_group(hipStream_t s, int prec, const PrepDesc* d, int n, int t_count, int n_wg_cs,
+                             int n_wg_prep) {
+  if (prec == PREC_FP8 || prec == PREC_FP8X3) {
+    hipLaunchKernelGGL(k_col_scale_group, dim3((unsigned)n_wg_cs), dim3(256), 0, s, d, n, t_count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+#define MHC_PREPG(M) hipLaunchKernelGGL(k_input_prep_group<M>, dim3((unsigned)n_wg_prep), dim3(256), 0, s, d, n, t_count)
+  if (prec == PREC_FP32) MHC_PREPG(1);
+  else if (prec == PREC_BF16X3) MHC_PREPG(2);
+  else if (prec == PREC_FP8) MHC_PREPG(3);
+  else MHC_PREPG(4);
+#undef MHC_PREPG
+  return hipGetLastError();
 }
 
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,

@@ -20,6 +20,7 @@
 
 #include "../../include/mhc.h"
 #include "mhc_common.h"
+#include "mhc_prep_group.h"
 
 using namespace mhc;
 
@@ -1144,6 +1145,11 @@ struct mhc_group {
   // order, and the slot is reused only after that copy has completed (event).
   uint64_t* d_tab = nullptr;
   uint64_t* h_tab = nullptr;                // [TAB_RING][3n]
+  // The input prep of all systems runs as one launch (two for e4m3: the
+  // column maxima first) over per-system descriptors that read v and W
+  // through the block table.
+  PrepDesc* d_prep = nullptr;
+  int n_wg_cs = 0, n_wg_prep = 0;
   // Per-system front and back kernels fan out over NAUX streams (joined
   // before and after the shared contraction), so small systems' kernels run
   // side by side instead of one after another.
@@ -1244,13 +1250,10 @@ mhc_status fan_out(mhc_group* g, F&& fn) {
 
 // The whole block (inputs named by the block table).
 mhc_status group_block(mhc_group* g, bool timed) {
-  mhc_status st = fan_out(g, [&](size_t i) {
-    mhc_ctx* c = g->sys[i];
-    mhc_status s2 =
-        block_front(c, nullptr, nullptr, g->t_block, reinterpret_cast<const float* const*>(g->d_tab + 3 * i));
-    return s2 ? gfail(g, s2, c->err) : MHC_OK;
-  });
-  if (st) return st;
+  mhc_status st;
+  GHIP_TRY(launch_prep_group(g->stream, g->prec, g->d_prep, (int)g->sys.size(), g->t_block, g->n_wg_cs,
+                             g->n_wg_prep),
+           "grouped input prep");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     while (g->ev_used + 2 > g->ev.size()) {
@@ -1428,6 +1431,38 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
   g->d_geom = reinterpret_cast<GemmGeom*>(pg);
   g->d_tiles = reinterpret_cast<GroupTile*>(pt);
   g->d_counter = reinterpret_cast<int*>(pc);
+  {
+    std::vector<PrepDesc> pd(n);
+    int64_t wcs = 0, wpr = 0;
+    for (int i = 0; i < n; ++i) {
+      mhc_ctx* c = g->sys[i];
+      PrepDesc& d = pd[i];
+      d.sqrt_m = c->d_sqrtm;
+      d.inv_sqrt_m = c->d_isqrtm;
+      d.N = c->N;
+      d.t_pad = c->t_pad;
+      d.n_chunks = c->n_atom_chunks;
+      d.B = c->dB;
+      d.K_pad = c->K_pad;
+      d.jt_part = c->d_jt;
+      d.col_scale = c->d_colscale;
+      d.col_part = c->d_colpart;
+      d.tab = reinterpret_cast<const float* const*>(g->d_tab + 3 * i);
+      d.wg0_cs = (int)wcs;
+      d.wg0_prep = (int)wpr;
+      wcs += (int64_t)c->t_pad * ((c->N + COLSCALE_ATOMS - 1) / COLSCALE_ATOMS);
+      wpr += (int64_t)c->n_atom_chunks * ((c->t_pad + 31) / 32);
+    }
+    if (wcs > INT32_MAX || wpr > INT32_MAX) return cleanup(MHC_ERR_INVALID_ARG);
+    g->n_wg_cs = (int)wcs;
+    g->n_wg_prep = (int)wpr;
+    void* pp = nullptr;
+    if (hipMalloc(&pp, n * sizeof(PrepDesc)) != hipSuccess) return cleanup(MHC_ERR_OOM);
+    g->allocs.push_back({pp, n * sizeof(PrepDesc)});
+    g->d_prep = reinterpret_cast<PrepDesc*>(pp);
+    if (hipMemcpy(pp, pd.data(), n * sizeof(PrepDesc), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(MHC_ERR_HIP);
+  }
   if (build_queue(g) != MHC_OK) return cleanup(MHC_ERR_HIP);
   *out = g;
   return MHC_OK;
