@@ -324,8 +324,10 @@ typedef struct mhc_group mhc_group;
 enum {
   MHC_GROUP_GRAPH = 1,      /* capture the per-block sequence as a HIP graph on the first full
                                block and replay it for every later block                 */
-  MHC_GROUP_AUTOTUNE = 2    /* time every valid contraction tile shape on the first block and
-                               keep the fastest (cached per process for the same sizes)  */
+  MHC_GROUP_AUTOTUNE = 2    /* on the first block, time the valid contraction tile shapes
+                               (alternating, one launch at a time, best of four rounds) and
+                               keep the largest tile unless another is more than 3 % faster
+                               (cached per process for the same sizes)                     */
 };
 
 /* systems: n finalized contexts with the same device, stream, precision and
@@ -344,8 +346,8 @@ mhc_status mhc_group_push(mhc_group *group, int32_t n_steps, const float *const 
                           int on_device);
 
 /* Tile shape in use (0: 128 slots x 4 t-blocks, 1: 256 x 2, 2: 256 x 1), the
- * autotuner's measured milliseconds per grouped contraction for each shape
- * ([3], -1 where not timed), and the number of tiles per launch. */
+ * autotuner's best measured milliseconds per grouped contraction for each
+ * shape ([3], -1 where not timed), and the number of tiles per launch. */
 mhc_status mhc_group_info(mhc_group *group, int32_t *tile_shape, double *tuned_ms, int64_t *n_tiles);
 
 /* HIP-event timing of the grouped contraction (graph replay is switched off
