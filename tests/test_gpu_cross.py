@@ -115,3 +115,24 @@ def test_cross_invalid_configurations(case):
         h.read_gkma_cross()
     assert ei.value.status == 2
     h.close()
+
+
+def test_cross_with_excluded_modes():
+    """An explicit bin map that leaves out a third of the modes (-1): the cross
+    correlations of the remaining bins against the oracle (the sum rule to the
+    total no longer holds, parity does)."""
+    from paper_2102_03691_amd import ModalHC
+    announce("cross excluded modes bf16x3 T=64")
+    c = Case((5, 4, 4), 200, mass_kind="natural", seed=13)
+    nb, L = 5, 12
+    bins = oracle.bin_of_mode(c.freq, nb, 0.0, c.lat.f_max)
+    bins[np.arange(c.n_modes) % 3 == 1] = -1
+    ref = c.oracle(nb, corr_len=L, bins=bins)
+    C = ox.gkma_cross_correlation(ref["Jb"], L)
+    got = run_library(c, nb, GKMA | CROSS, BF16X3, 64, corr_len=L, bins=bins, keep=True)
+    h = got["handle"]
+    x = h.read_gkma_cross()
+    h.close()
+    e = rel(x["corr"], C)
+    log("5x4x4_cross_excluded", rel_cross=e)
+    assert x["n_samples"] == 200 and e <= BAR[BF16X3]

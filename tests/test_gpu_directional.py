@@ -152,3 +152,31 @@ def test_split_unsupported_paths(dense):
         p.read_hnema_dir()                         # split not enabled
     assert ei.value.status == 2
     p.close()
+
+
+def test_split_with_mode_subset_and_excluded_modes():
+    """M < 3N modes (the first 400 of a dense 540 x 540 basis) and an explicit
+    bin map that excludes every seventh mode (-1): split outputs against the
+    split oracle on the same subset and map."""
+    from paper_2102_03691_amd import ModalHC
+    announce("directional mode subset + excluded modes fp32 T=64")
+    c = DenseCase(seed=9)
+    M, nb, L = 400, 9, 16
+    E = c.E[:, :M]
+    bins = (np.arange(M) * 7) % nb
+    bins[::7] = -1
+    ref = od.run_dense_directional(E, c.m, c.v, c.W, bins, nb, L, 1.0)
+    h = ModalHC(0)
+    h.load_system(c.m, c.lat.frequencies[:M])
+    h.set_bins(nb, bins)
+    h.configure(methods=HNEMA | GKMA | DIR, precision=FP32, t_block=64, corr_len=L, dt=1.0)
+    for r0 in range(0, M, 100):
+        h.load_eigvec_rows(r0, np.ascontiguousarray(E[:, r0:r0 + 100].T))
+    h.finalize()
+    c.push(h, [200, 100])
+    avg_d, _, n = h.read_hnema_dir()
+    gd = h.read_gkma_dir()
+    h.close()
+    e1, e2 = rel(avg_d, ref["hnema_dir"]), rel(gd["corr"], ref["corr_dir"])
+    log("dense540_dir_subset400_excl", rel_hnema_dir=e1, rel_corr_dir=e2)
+    assert n == 300 and e1 <= BAR[FP32] and e2 <= BAR[FP32]
