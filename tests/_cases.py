@@ -19,6 +19,14 @@ def rel(a, b) -> float:
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
+def rel_max(a, b) -> float:
+    """max |a - b| / max |b|: the max-abs-normalised companion of rel()."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / mb) if mb > 0 else float(np.abs(a).max() if a.size else 0.0)
+
+
 def log(case: str, **vals):
     """Print (and optionally append to $MHC_PARITY_LOG) one measured error record."""
     rec = {"case": case, **vals}

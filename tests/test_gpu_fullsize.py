@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from tests._cases import TOL, announce, log, rel
+from tests._cases import rel_max, TOL, announce, log, rel
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -84,6 +84,8 @@ def test_sc16_per_step_fp32():
     ref = _reference(lat, m, v, W, nb, L)
     e = {k: rel(x, ref[k]) for k, x in (("hnema", avg), ("corr", g["corr"]), ("integral", g["integral"]))}
     e["hcacf"] = rel(g["hcacf"], ref["hcacf"])
+    e["max_hnema"], e["max_corr"] = rel_max(avg, ref["hnema"]), rel_max(g["corr"], ref["corr"])
+    e["corr_tau0"], e["corr_tau_ge1"] = rel(g["corr"][0], ref["corr"][0]), rel(g["corr"][1:], ref["corr"][1:])
     log("sc16_fullsize_fp32_t1", **e)
     assert n == S and e["hnema"] <= TOL[FP32] and e["corr"] <= TOL[FP32] and e["hcacf"] <= 1e-12
 
@@ -103,7 +105,9 @@ def test_slab48_bf16x3_t128():
     ref = _reference(lat, m, v, W, nb, L)
     e = {k: rel(x, ref[k]) for k, x in (("hnema", avg), ("corr", g["corr"]), ("integral", g["integral"]))}
     e["block_currents"] = rel(jb, ref["Jb"][128:].transpose(0, 2, 1))
-    log("slab48_fullsize_bf16x3_t128", **e)
+    e["corr_tau0"], e["corr_tau_ge1"] = rel(g["corr"][0], ref["corr"][0]), rel(g["corr"][1:], ref["corr"][1:])
+    log("slab48_fullsize_bf16x3_t128", max_hnema=rel_max(avg, ref["hnema"]), max_corr=rel_max(g["corr"], ref["corr"]),
+        **e)
     assert n == S
     assert max(e.values()) <= TOL[BF16X3]
 
@@ -125,7 +129,9 @@ def test_rod1500_gkma_t256(prec, S):
     ref = _reference(lat, m, v, W, nb, L)
     e = {k: rel(x, ref[k]) for k, x in (("hnema", avg), ("corr", g["corr"]), ("integral", g["integral"]))}
     e["corr_tau0"] = rel(g["corr"][0], ref["corr"][0])
+    e["corr_tau_ge1"] = rel(g["corr"][1:], ref["corr"][1:])
     e["hcacf"] = rel(g["hcacf"], ref["hcacf"])
+    e["max_hnema"], e["max_corr"] = rel_max(avg, ref["hnema"]), rel_max(g["corr"], ref["corr"])
     log(f"rod1500_fullsize_p{prec}_t256_S{S}", **e)
     assert n == S
     assert e["hnema"] <= TOL[prec] and e["corr"] <= TOL[prec] and e["integral"] <= TOL[prec]
