@@ -8,6 +8,7 @@
 // atomics), so results are reproducible bit for bit; long running sums use
 // Neumaier compensation.
 #include "mhc_common.h"
+#include "mhc_back_group.h"
 #include "mhc_numeric.h"
 
 namespace mhc {
@@ -29,10 +30,9 @@ __device__ __forceinline__ double block_sum256(double x, double* sh) {
 }
 
 // ------------------------------------------------------------------ reduce
-__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
+__device__ __forceinline__ void reduce_body(ReduceArgs a, int b) {
   __shared__ double sh[256];
   const int tid = threadIdx.x;
-  const int b = blockIdx.x;
   if (a.t0_dev) a.t0 = *a.t0_dev;
   if (b < a.nb) {
     const int64_t lo = a.bin_off[b], hi = a.bin_off[b + 1];
@@ -115,11 +115,12 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x); }
+
 // Eq. 10 summed over atoms: one wave per step adds the float64 partials of
 // the atom chunks in a fixed order.
-__global__ void __launch_bounds__(64) k_total(const double* __restrict__ jt_part, int n_chunks,
-                                              double* __restrict__ jtot) {
-  const int t = blockIdx.x;
+__device__ __forceinline__ void total_body(const double* __restrict__ jt_part, int n_chunks,
+                                           double* __restrict__ jtot, int t) {
   const int lane = threadIdx.x;
   double j0 = 0.0, j1 = 0.0, j2 = 0.0;
   const double* p = jt_part + (int64_t)t * n_chunks * 3;
@@ -141,6 +142,11 @@ __global__ void __launch_bounds__(64) k_total(const double* __restrict__ jt_part
   }
 }
 
+__global__ void __launch_bounds__(64) k_total(const double* __restrict__ jt_part, int n_chunks,
+                                              double* __restrict__ jtot) {
+  total_body(jt_part, n_chunks, jtot, blockIdx.x);
+}
+
 hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int t_count, double* jtot) {
   if (t_count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_total, dim3((unsigned)t_count), dim3(64), 0, s, jt_part, n_chunks, jtot);
@@ -151,13 +157,13 @@ hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int 
 // covers t_count; steps strided by TT), 256 / TT segments per work-group.  A
 // segment's REDUCE_SEG slots are summed in slot order, bin by bin, into
 // seg_part[mu][seg + b][t] (every bin the segment touches).
-__global__ void __launch_bounds__(256) k_reduce_seg(ReduceArgs a) {
+__device__ __forceinline__ void reduce_seg_body(const ReduceArgs& a, int blk) {
   __shared__ int32_t sb[4][REDUCE_SEG];
   const int tid = threadIdx.x;
   const int TT = a.t_count <= 64 ? 64 : (a.t_count <= 128 ? 128 : 256);
   const int G = 256 / TT;
   const int g = tid / TT, tl = tid % TT;
-  const int64_t seg = (int64_t)blockIdx.x * G + g;
+  const int64_t seg = (int64_t)blk * G + g;
   const int64_t slot0 = seg * REDUCE_SEG;
   if (tl < REDUCE_SEG) sb[g][tl] = (seg < a.n_seg && slot0 + tl < a.M_pad) ? a.slot_bin[slot0 + tl] : -1;
   __syncthreads();
@@ -192,6 +198,8 @@ __global__ void __launch_bounds__(256) k_reduce_seg(ReduceArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_reduce_seg(ReduceArgs a) { reduce_seg_body(a, blockIdx.x); }
+
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a) {
   if (a.layout_g && a.t_count > 0 && a.n_seg > 0) {
     const int TT = a.t_count <= 64 ? 64 : (a.t_count <= 128 ? 128 : 256);
@@ -216,22 +224,18 @@ constexpr int CT = 64;   // steps per chunk
 constexpr int CR = 64;   // rows per tile
 constexpr int CL = 64;   // lags per tile
 
-__global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
-                                              int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
-                                              double* __restrict__ csum, double* __restrict__ ccomp,
-                                              const int64_t* __restrict__ t0_dev, int64_t ring_zs, int64_t out_zs) {
+__device__ __forceinline__ void corr_body(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
+                                          int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
+                                          double* __restrict__ csum, double* __restrict__ ccomp,
+                                          const int64_t* __restrict__ t0_dev, int bx, int by) {
   if (t0_dev) t0 = *t0_dev;
-  // grid z: one history ring of 3 columns and one slice of sums per z
-  ring += (int64_t)blockIdx.z * ring_zs;
-  csum += (int64_t)blockIdx.z * out_zs;
-  ccomp += (int64_t)blockIdx.z * out_zs;
   __shared__ double xs[CT][CR + 2];          // xs[t][r]
   __shared__ double rs[CT + CL][3];          // ring window
   const int tid = threadIdx.x;
   const int tt = tid & 15;                   // lag group (consecutive lanes)
   const int tr = tid >> 4;                   // row group
-  const int64_t r0 = (int64_t)blockIdx.x * CR;
-  const int tau0 = blockIdx.y * CL;
+  const int64_t r0 = (int64_t)bx * CR;
+  const int tau0 = by * CL;
   double acc[4][4][3];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -315,6 +319,16 @@ __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int6
   }
 }
 
+__global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
+                                              int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
+                                              double* __restrict__ csum, double* __restrict__ ccomp,
+                                              const int64_t* __restrict__ t0_dev, int64_t ring_zs, int64_t out_zs) {
+  // grid z: one history ring of 3 columns and one slice of sums per z
+  corr_body(X, ldx, t_count, R3, L, ring + (int64_t)blockIdx.z * ring_zs, ring_len, t0,
+            csum + (int64_t)blockIdx.z * out_zs, ccomp + (int64_t)blockIdx.z * out_zs, t0_dev, blockIdx.x,
+            blockIdx.y);
+}
+
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
                        const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
                        const int64_t* t0_dev, int nz, int64_t ring_zs, int64_t out_zs) {
@@ -362,6 +376,62 @@ hipError_t launch_hnema_finish(hipStream_t s, const double* sum, const double* c
                                double* avg) {
   hipLaunchKernelGGL(k_hnema_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sum, comp, n, S, avg);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------- grouped back end
+// The back end of every system of a group in four launches (totals, segment
+// sums, bin sums, correlations); work-group w belongs to the last system i
+// with wg0[i] <= w (systems with no work-groups in a launch are skipped).
+__device__ __forceinline__ int back_system(const int* __restrict__ wg0, int n, int w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wg0[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(64) k_total_group(const BackDesc* __restrict__ d, int t_count) {
+  const BackDesc& s = d[blockIdx.x / t_count];
+  total_body(s.jt_part, s.n_chunks, s.jtot, blockIdx.x % t_count);
+}
+
+__global__ void __launch_bounds__(256) k_reduce_seg_group(const ReduceArgs* __restrict__ a,
+                                                          const int* __restrict__ wg0, int n) {
+  const int i = back_system(wg0, n, blockIdx.x);
+  reduce_seg_body(a[i], blockIdx.x - wg0[i]);
+}
+
+__global__ void __launch_bounds__(256) k_reduce_group(const ReduceArgs* __restrict__ a, const int* __restrict__ wg0,
+                                                      int n) {
+  const int i = back_system(wg0, n, blockIdx.x);
+  reduce_body(a[i], blockIdx.x - wg0[i]);
+}
+
+__global__ void __launch_bounds__(256) k_corr_group(const BackDesc* __restrict__ d, const int* __restrict__ wg0, int n,
+                                                    int t_count) {
+  const int i = back_system(wg0, n, blockIdx.x);
+  const BackDesc& s = d[i];
+  const int local = blockIdx.x - wg0[i];
+  corr_body(s.X, s.ldx, t_count, s.R3, s.L, s.ring, s.ring_len, 0, s.csum, s.ccomp, s.t0_dev, local % s.n_rt,
+            local / s.n_rt);
+}
+
+hipError_t launch_back_group(hipStream_t s, const BackGroup& b, int n, int t_count) {
+  hipLaunchKernelGGL(k_total_group, dim3((unsigned)(n * t_count)), dim3(64), 0, s, b.d, t_count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (b.n_wg_seg > 0) {
+    hipLaunchKernelGGL(k_reduce_seg_group, dim3((unsigned)b.n_wg_seg), dim3(256), 0, s, b.red, b.wg0_seg, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_reduce_group, dim3((unsigned)b.n_wg_red), dim3(256), 0, s, b.red, b.wg0_red, n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (b.n_wg_corr > 0) {
+    hipLaunchKernelGGL(k_corr_group, dim3((unsigned)b.n_wg_corr), dim3(256), 0, s, b.d, b.wg0_corr, n, t_count);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace mhc

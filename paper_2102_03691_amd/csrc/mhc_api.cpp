@@ -21,6 +21,7 @@
 #include "../../include/mhc.h"
 #include "mhc_common.h"
 #include "mhc_prep_group.h"
+#include "mhc_back_group.h"
 
 using namespace mhc;
 
@@ -1150,6 +1151,11 @@ struct mhc_group {
   // through the block table.
   PrepDesc* d_prep = nullptr;
   int n_wg_cs = 0, n_wg_prep = 0;
+  // The back end of all systems likewise (four launches) unless a system
+  // keeps cross-correlations, which fan out per system as before.
+  bool back_grouped = false;
+  BackGroup back{};
+  void* d_back = nullptr;           // BackDesc[n], ReduceArgs[n], int wg0[3][n]
   // Per-system front and back kernels fan out over NAUX streams (joined
   // before and after the shared contraction), so small systems' kernels run
   // side by side instead of one after another.
@@ -1190,6 +1196,84 @@ std::string tune_key(const mhc_group* g) {
 }
 
 // Descriptors and the largest-first tile queue for the current shape.
+// Descriptors of the grouped back end (the reduction's part count depends on
+// the tile shape, so they are rebuilt with the queue).
+mhc_status build_back(mhc_group* g) {
+  if (!g->back_grouped) return MHC_OK;
+  const int n = (int)g->sys.size();
+  const int T = g->t_block;
+  const int TT = T <= 64 ? 64 : (T <= 128 ? 128 : 256);
+  const int G = 256 / TT;
+  std::vector<BackDesc> bd(n);
+  std::vector<ReduceArgs> ra(n);
+  std::vector<int> w(3 * n);
+  int64_t ws = 0, wr = 0, wc = 0;
+  for (int i = 0; i < n; ++i) {
+    mhc_ctx* c = g->sys[i];
+    const bool gk = c->cfg.methods & MHC_GKMA;
+    const int64_t* t0_dev = reinterpret_cast<const int64_t*>(g->d_tab + 3 * i + 2);
+    ReduceArgs& a = ra[i];
+    a = ReduceArgs{};
+    a.in = c->dJ;
+    a.layout_g = gk ? 1 : 0;
+    a.n_parts = g->n_parts[i];
+    a.M_pad = c->M_pad;
+    a.ld = c->t_pad;
+    a.t_count = T;
+    a.bin_off = c->d_bin_off;
+    a.slot_bin = c->d_slot_bin;
+    a.seg_part = c->d_seg_part;
+    a.n_seg = c->n_seg;
+    a.nb = c->nb;
+    a.jtot = c->d_jtot;
+    a.hsum = c->d_hsum;
+    a.hcomp = c->d_hcomp;
+    a.tsum = c->d_tsum;
+    a.tcomp = c->d_tcomp;
+    a.X = gk ? c->dX : nullptr;
+    a.ring = c->d_ring;
+    a.ring_len = c->ring_len;
+    a.t0_dev = t0_dev;
+    BackDesc& d = bd[i];
+    d.jt_part = c->d_jt;
+    d.n_chunks = c->n_atom_chunks;
+    d.jtot = c->d_jtot;
+    d.X = c->dX;
+    d.ldx = c->t_pad;
+    d.R3 = c->R3;
+    d.L = gk ? c->cfg.corr_len : 0;
+    d.ring = c->d_ring;
+    d.ring_len = c->ring_len;
+    d.csum = c->d_csum;
+    d.ccomp = c->d_ccomp;
+    d.t0_dev = t0_dev;
+    d.n_rt = gk ? (int)((c->R3 + 63) / 64) : 0;
+    w[i] = (int)ws;
+    w[n + i] = (int)wr;
+    w[2 * n + i] = (int)wc;
+    if (gk && c->n_seg > 0) ws += (c->n_seg + G - 1) / G;
+    wr += c->nb + 1;
+    if (gk) wc += (int64_t)d.n_rt * ((d.L + 63) / 64);
+  }
+  if (ws > INT32_MAX || wr > INT32_MAX || wc > INT32_MAX) return gfail(g, MHC_ERR_INVALID_ARG, "group too large");
+  char* base = static_cast<char*>(g->d_back);
+  const size_t o_red = (size_t)n * sizeof(BackDesc), o_w = o_red + (size_t)n * sizeof(ReduceArgs);
+  GHIP_TRY(hipMemcpy(base, bd.data(), o_red, hipMemcpyHostToDevice), "back descriptors");
+  GHIP_TRY(hipMemcpy(base + o_red, ra.data(), (size_t)n * sizeof(ReduceArgs), hipMemcpyHostToDevice),
+           "reduce descriptors");
+  GHIP_TRY(hipMemcpy(base + o_w, w.data(), w.size() * sizeof(int), hipMemcpyHostToDevice), "back offsets");
+  const int* wd = reinterpret_cast<const int*>(base + o_w);
+  g->back.d = reinterpret_cast<const BackDesc*>(base);
+  g->back.red = reinterpret_cast<const ReduceArgs*>(base + o_red);
+  g->back.wg0_seg = wd;
+  g->back.wg0_red = wd + n;
+  g->back.wg0_corr = wd + 2 * n;
+  g->back.n_wg_seg = (int)ws;
+  g->back.n_wg_red = (int)wr;
+  g->back.n_wg_corr = (int)wc;
+  return MHC_OK;
+}
+
 mhc_status build_queue(mhc_group* g) {
   const int n = (int)g->sys.size();
   std::vector<GemmGeom> geom(n);
@@ -1216,7 +1300,7 @@ mhc_status build_queue(mhc_group* g) {
                           g->stream),
            "tiles");
   GHIP_TRY(hipStreamSynchronize(g->stream), "queue sync");
-  return MHC_OK;
+  return build_back(g);
 }
 
 mhc_status group_contract(mhc_group* g) {
@@ -1268,6 +1352,10 @@ mhc_status group_block(mhc_group* g, bool timed) {
   }
   if ((st = group_contract(g))) return st;
   if (timed) GHIP_TRY(hipEventRecord(e1, g->stream), "event record");
+  if (g->back_grouped) {
+    GHIP_TRY(launch_back_group(g->stream, g->back, (int)g->sys.size(), g->t_block), "grouped back end");
+    return MHC_OK;
+  }
   return fan_out(g, [&](size_t i) {
     mhc_ctx* c = g->sys[i];
     mhc_status s2 = block_back(c, g->t_block, g->n_parts[i], reinterpret_cast<const int64_t*>(g->d_tab + 3 * i + 2));
@@ -1462,6 +1550,16 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
     g->d_prep = reinterpret_cast<PrepDesc*>(pp);
     if (hipMemcpy(pp, pd.data(), n * sizeof(PrepDesc), hipMemcpyHostToDevice) != hipSuccess)
       return cleanup(MHC_ERR_HIP);
+  }
+  g->back_grouped = true;
+  for (auto* c : g->sys)
+    if (c->cross) g->back_grouped = false;
+  if (g->back_grouped) {
+    const size_t bytes = (size_t)n * (sizeof(BackDesc) + sizeof(ReduceArgs) + 3 * sizeof(int));
+    void* pb = nullptr;
+    if (hipMalloc(&pb, bytes) != hipSuccess) return cleanup(MHC_ERR_OOM);
+    g->allocs.push_back({pb, bytes});
+    g->d_back = pb;
   }
   if (build_queue(g) != MHC_OK) return cleanup(MHC_ERR_HIP);
   *out = g;
