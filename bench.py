@@ -300,7 +300,7 @@ def run_group(args, prec):
         v, W = synth.gen_steps_torch(100 + i, m, n_blocks * GROUP_T, device="cuda:0")
         inputs.append((v, W))
     torch.cuda.synchronize()
-    grp = ModalGroup(systems, graph=True, autotune=True)
+    grp = ModalGroup(systems, graph=not args.no_graph, autotune=True)
 
     def block(j):
         b = j % n_blocks
@@ -343,7 +343,8 @@ def run_group(args, prec):
                        "precision": {0: "fp32", 1: "split-bf16 three products", 2: "e4m3 one product",
                                      3: "e4m3 hi/lo three products"}[prec]
                        + ", per-mode / per-(channel, step) scales for e4m3; fp64 bins and time sums",
-                       "launch": "grouped persistent contraction, HIP graph replay, autotuned tile shape",
+                       "launch": "grouped persistent contraction, "
+                                 + ("eager launches" if args.no_graph else "HIP graph replay") + ", autotuned tile shape",
                        "parallelism": "single GPU"},
             "roofline": roof}
 
@@ -359,6 +360,7 @@ def main():
                     help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="grouped workloads: launch each block eagerly")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GiB copied by a plain device copy before the workload (to calibrate HBM counters)")
     args = ap.parse_args()

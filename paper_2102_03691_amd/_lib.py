@@ -386,7 +386,7 @@ class ModalGroup:
             if dev:
                 assert v.is_contiguous() and W.is_contiguous()
                 assert v.numel() == S * sysm.n_atoms * 3 and W.numel() == S * sysm.n_atoms * 9
-                sysm._use(v, W)
+                keep += [v, W]
             else:
                 v = np.ascontiguousarray(v, dtype=np.float32)
                 W = np.ascontiguousarray(W, dtype=np.float32)
@@ -398,6 +398,9 @@ class ModalGroup:
                 pW = (C.c_void_p * n)()
             pv[i] = _ptr(vs_i)
             pW[i] = _ptr(Ws_i)
+        if dev:
+            # the systems share one stream: one wait on torch's stream for all inputs
+            self.systems[0]._use(*keep)
         self._check(self._lib.mhc_group_push(self._h, S, pv, pW, 1 if dev else 0), "group_push")
 
     def info(self):
