@@ -367,7 +367,11 @@ class ModalGroup:
         flags = (GROUP_GRAPH if graph else 0) | (GROUP_AUTOTUNE if autotune else 0)
         st = self._lib.mhc_group_create(arr, len(self.systems), flags, C.byref(h))
         if st:
-            raise MhcError(st, "mhc_group_create")
+            why = {1: "the systems must be distinct and share one device, one stream (contexts created with a "
+                      "null stream each own a stream of their own), the precision and t_block",
+                   2: "every system must be finalized, with t_block > 1",
+                   5: "systems with the motion-direction split cannot be grouped"}.get(st, "")
+            raise MhcError(st, f"mhc_group_create: {why}" if why else "mhc_group_create")
         self._h = h
 
     def _check(self, st, what):
