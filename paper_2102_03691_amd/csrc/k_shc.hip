@@ -55,200 +55,159 @@ hipError_t launch_shc_ring(hipStream_t s, const float* W, const float* v, int t_
 }
 
 // ---------------------------------------------------------------- products
-// Work-group (kc, a, b) (a 1-D grid; consecutive ids go to different XCDs,
-// so ids are remapped to give each XCD a contiguous range, and the tiles of
-// one dof range share that XCD's L2): steps t in [64a, 64a + 64) x lags tau in
-// [64b, 64b + 64) x the 3 components mu, over the dof range of direction
-// segment nu = kc / n_kcs: columns nu Np + [c dk, c dk + dk) with c = kc % n_kcs,
-// cut at nu Np + N.  The origins s' = s0 + t - tau of the tile are 127
-// consecutive ring rows r = t_loc - tau_loc + 63.  Dofs are staged 32 at a
-// time through LDS; a thread holds the 4 x 4 x 3 products of steps 4tt + x
-// and lags 4tl + y.  Threads are laid out along diagonals, tt = (tl + k) mod 16
-// with k = tid / 16, so the 16 lanes of an LDS pass read one or two virial
-// rows (broadcast); velocity rows are stored with one float4 of padding per
-// four steps so that those reads spread over all banks.  Rows before the
-// first sample, rows after the block's last step and steps past t_count are
-// staged as zeros.  With one wave per SIMD the LDS latency is exposed, so the
-// reads of a dof group go out in two batches (diagonals 0..3 and 4..6), each
-// issued while the products of the previous batch run.  The thread's 4 steps
-// are added, then the 16 step groups in order, giving part[kc][a][tau][mu] =
-// sum over the tile's steps.
-constexpr int SH_T = 64, SH_L = 64, SH_DC = 32;
-constexpr int SH_ROWS = SH_T + SH_L - 1;                 // 127
-constexpr int SH_VP = SH_T + SH_T / 4;                   // padded step index range of the V tile
-constexpr int SH_WS = 3 * SH_DC + 28;                    // W row stride (floats): 96 used + room for the shift
-// Row r of the W tile starts at r * SH_WS + 4 * ((r / 4) % 8) floats (the
-// shift stays within the row's 28 spare floats): rows four apart, the rows one
-// LDS pass reads, then fall on different bank groups.
-__device__ __forceinline__ int sh_wrow(int r) { return r * SH_WS + 4 * ((r >> 2) & 7); }
-constexpr int SH_WTILE = SH_ROWS * SH_WS + 28;
+// The partial sums on the FP64 matrix cores, in Gram form.  Work-group
+// (kc, mu, a, b) covers steps t in [64a, 64a + 64), lags tau in
+// [128b, 128b + 128) and one component mu over the dof range of kc (a 1-D
+// grid; consecutive ids go to different XCDs, so ids are remapped to give
+// each XCD a contiguous range, and the tiles of one dof range are adjacent,
+// sharing that XCD's L2).  Its origins s' = s0 + t - tau are 192 consecutive
+// ring rows R (origin row0 + R); wave w takes steps 64a + 16w + c (c < 16)
+// and rows R = 16w + rho, rho < 144 (9 blocks of 16), and accumulates
+//   G[rho][c] = sum_j Wmu[row0 + 16w + rho][j] V[64a + 16w + c][j]
+// with v_mfma_f64_16x16x4f64: A = a block of virial rows, B = velocity rows,
+// 4 dofs per product (lane l supplies row or step l % 16 at dof l / 16 of the
+// product's 4), and lane l's register i of the result is entry
+// [4i + l / 16][l % 16].  The entry with lag tau = 128b + lambda lies at
+// rho = 127 + c - lambda, so a work-group's partial for lambda is the sum of
+// G along that diagonal over the 4 waves and 16 steps, taken in a fixed order
+// after the dof loop.  Of the 9 x 256 products per wave and dof, the 16 x 128
+// on those diagonals are used.  Dofs are staged 32 at a time in LDS (float32,
+// double-buffered; rows padded to 36 floats) and converted to float64 as the
+// operands are read; the products of float32 inputs are exact in float64.  G
+// is summed in the LDS of the staging buffers, so a work-group takes 73 KiB
+// and two fit on a CU, whose waves hide each other's load and LDS latency.
+constexpr int SM_T = 64, SM_L = 128, SM_DC = 32;
+constexpr int SM_RB = (SM_L + 16) / 16;                 // 9 row blocks per wave
+constexpr int SM_ROWS = SM_T - 16 + 16 * SM_RB;         // 192 staged rows
+constexpr int SM_WS = SM_DC + 4;                        // LDS row stride (floats)
 
-__global__ void __launch_bounds__(256) k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring,
-                                                 int64_t ring_len, int64_t ld, int64_t N, int64_t Np, int t_count,
-                                                 int64_t s0, int64_t dk, int n_kcs, int n_ttiles,
-                                                 int n_lags_pad, double* __restrict__ part) {
-  __shared__ f32x4 vs[SH_DC / 4][SH_VP];
-  // the W tile (rows at sh_wrow), reused for the final step-group sums once the products are done
-  __shared__ __attribute__((aligned(16))) float ws[SH_WTILE];
-  double (*red)[SH_L][3] = reinterpret_cast<double (*)[SH_L][3]>(ws);     // [16][64][3] doubles: 24 KiB
-  static_assert(16 * SH_L * 3 * sizeof(double) <= SH_WTILE * sizeof(float), "reduction fits in the W tile");
-  const int tid = threadIdx.x;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t ring_len, int64_t ld, int64_t N,
+               int64_t Np, int t_count, int64_t s0, int64_t dk, int n_kcs, int n_ttiles, int n_lags_pad,
+               double* __restrict__ part) {
+  // staging buffers, and after the products the G of the 4 waves
+  constexpr int WSH = 2 * SM_ROWS * SM_WS, VSH = 2 * SM_T * SM_WS;          // floats
+  constexpr int RED = 4 * 16 * SM_RB * 16;                                  // doubles
+  constexpr int SMEM = (WSH + VSH) * 4 > RED * 8 ? (WSH + VSH) * 4 : RED * 8;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+  float (*wsh)[SM_ROWS][SM_WS] = reinterpret_cast<float (*)[SM_ROWS][SM_WS]>(smem);
+  float (*vsh)[SM_T][SM_WS] = reinterpret_cast<float (*)[SM_T][SM_WS]>(smem + WSH * 4);
+  double (*red)[16 * SM_RB][16] = reinterpret_cast<double (*)[16 * SM_RB][16]>(smem);
+  __shared__ int64_t roff[SM_ROWS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
   const int G = gridDim.x;
   const int v = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
-  const int n_tiles = n_ttiles * (n_lags_pad / SH_L);
-  const int kc = v / n_tiles;
-  const int a = (v % n_tiles) % n_ttiles;
-  const int b = (v % n_tiles) / n_ttiles;
-  const int tl = tid & 15;
-  const int tt = (tl + (tid >> 4)) & 15;
+  const int n_ab = n_ttiles * (n_lags_pad / SM_L);
+  const int kc = v / (3 * n_ab);
+  const int mu = (v / n_ab) % 3;
+  const int a = (v % n_ab) % n_ttiles;
+  const int b = (v % n_ab) / n_ttiles;
   const int64_t seg0 = (int64_t)(kc / n_kcs) * Np;
   const int64_t j0 = seg0 + (int64_t)(kc % n_kcs) * dk;
   const int64_t j1 = min(seg0 + N, j0 + dk);
-  const int64_t row0 = s0 + (int64_t)SH_T * a - (int64_t)SH_L * b - (SH_L - 1);   // origin of row r = 0
+  const int64_t row0 = s0 + (int64_t)SM_T * a - (int64_t)SM_L * b - (SM_L - 1);
   const int64_t s_last = s0 + t_count - 1;
-
-  double acc[4][4][3];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int m = 0; m < 3; ++m) acc[x][y][m] = 0.0;
-
-  // Ring offset of each origin row of the tile (-1: before the first sample
-  // or after the block's last step, staged as zeros).
-  __shared__ int64_t roff[SH_ROWS];
-  if (tid < SH_ROWS) {
+  if (tid < SM_ROWS) {
     const int64_t sp = row0 + tid;
-    roff[tid] = (sp >= 0 && sp <= s_last) ? (sp % ring_len) * 3 * ld : -1;
+    roff[tid] = (sp >= 0 && sp <= s_last) ? (sp % ring_len) * 3 * ld + mu * ld : -1;
   }
   __syncthreads();
-  // Staging of one 32-dof chunk through registers, W and V as float4 (16-byte
-  // aligned: ld, Np, dk and the chunk start are multiples of 4).  A chunk never
-  // crosses a multiple of dk or the end of its segment's Np columns, and the
-  // pad columns past N are zero in both arrays.  The next chunk's loads are
-  // issued before the current chunk's products.
-  constexpr int WQ = SH_ROWS * 3 * (SH_DC / 4);           // 3048 float4 per chunk
-  constexpr int WPT = (WQ + 255) / 256;                    // 12 per thread
-  constexpr int VPT = SH_T * (SH_DC / 4) / 256;            // 2 per thread
+
+  // staging of one 32-dof chunk: W as 192 rows x 8 float4 (6 per thread), V
+  // as 64 steps x 8 float4 (2 per thread); zeros outside the sampled rows,
+  // the block's steps and the dof range
+  constexpr int WPT = SM_ROWS * (SM_DC / 4) / 256, VPT = SM_T * (SM_DC / 4) / 256;
+  static_assert(WPT * 256 == SM_ROWS * (SM_DC / 4) && VPT * 256 == SM_T * (SM_DC / 4), "staging shape");
   f32x4 wst[WPT], vst[VPT];
   auto load = [&](int64_t jc) {
 #pragma unroll
     for (int k = 0; k < WPT; ++k) {
       const int e = tid + 256 * k;
+      const int r = e / (SM_DC / 4), q = e % (SM_DC / 4);
+      const int64_t off = roff[r];
+      const int64_t j = jc + 4 * q;
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
-      if (e < WQ) {
-        const int r = e / (3 * SH_DC / 4), rem = e % (3 * SH_DC / 4);
-        const int mu = rem / (SH_DC / 4), q = rem % (SH_DC / 4);
-        const int64_t off = roff[r];
-        const int64_t j = jc + 4 * q;
-        if (off >= 0 && j < j1) x = *reinterpret_cast<const f32x4*>(ring + off + mu * ld + j);
-      }
+      if (off >= 0 && j < j1) x = *reinterpret_cast<const f32x4*>(ring + off + j);
       wst[k] = x;
     }
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const int e = tid + 256 * k;
-      const int tr = e / (SH_DC / 4), q = e % (SH_DC / 4);
-      const int t = SH_T * a + tr;
+      const int tr = e / (SM_DC / 4), q = e % (SM_DC / 4);
+      const int t = SM_T * a + tr;
       const int64_t j = jc + 4 * q;
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
       if (t < t_count && j < j1) x = *reinterpret_cast<const f32x4*>(vt + (int64_t)t * ld + j);
       vst[k] = x;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int k = 0; k < WPT; ++k) {
       const int e = tid + 256 * k;
-      if (e < WQ) {
-        const int r = e / (3 * SH_DC / 4), rem = e % (3 * SH_DC / 4);
-        const int mu = rem / (SH_DC / 4), q = rem % (SH_DC / 4);
-        *reinterpret_cast<f32x4*>(&ws[sh_wrow(r) + mu * SH_DC + 4 * q]) = wst[k];
-      }
+      const int r = e / (SM_DC / 4), q = e % (SM_DC / 4);
+      *reinterpret_cast<f32x4*>(&wsh[buf][r][4 * q]) = wst[k];
     }
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const int e = tid + 256 * k;
-      const int tr = e / (SH_DC / 4), q = e % (SH_DC / 4);
-      vs[q][tr + (tr >> 2)] = vst[k];
+      const int tr = e / (SM_DC / 4), q = e % (SM_DC / 4);
+      *reinterpret_cast<f32x4*>(&vsh[buf][tr][4 * q]) = vst[k];
     }
   };
 
+  f64x4 acc[SM_RB];
+#pragma unroll
+  for (int rb = 0; rb < SM_RB; ++rb) acc[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+
   load(j0);
-  for (int64_t jc = j0; jc < j1; jc += SH_DC) {
-    store();
-    __syncthreads();
-    if (jc + SH_DC < j1) load(jc + SH_DC);
-    // LDS reads one batch ahead of the products: the rows of diagonals
-    // q = 0..3 of dof group d4+1 (and its velocities) are read while the
-    // products of q = 4..6 of group d4 run, those of q = 4..6 while q = 0..3 run
-    auto rd_w = [&](int d4, int q0, int nq, f32x4 (*w)[3]) {
-#pragma unroll
-      for (int k = 0; k < nq; ++k) {
-        const int r = 4 * (tt - tl) + (q0 + k - 3) + (SH_L - 1);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) w[k][m] = *reinterpret_cast<const f32x4*>(&ws[sh_wrow(r) + m * SH_DC + 4 * d4]);
-      }
-    };
-    auto rd_v = [&](int d4, f32x4* vv) {
-#pragma unroll
-      for (int x = 0; x < 4; ++x) vv[x] = vs[d4][5 * tt + x];
-    };
-    auto prod = [&](int q0, int nq, f32x4 (*w)[3], const f32x4* vv) {
-#pragma unroll
-      for (int k = 0; k < nq; ++k) {
-        const int q = q0 + k;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const double w0 = w[k][m].x, w1 = w[k][m].y, w2 = w[k][m].z, w3 = w[k][m].w;
-#pragma unroll
-          for (int x = 0; x < 4; ++x) {
-            const int y = x - (q - 3);
-            if (y < 0 || y > 3) continue;
-            double s = acc[x][y][m];
-            s = fma(w0, (double)vv[x].x, s);
-            s = fma(w1, (double)vv[x].y, s);
-            s = fma(w2, (double)vv[x].z, s);
-            s = fma(w3, (double)vv[x].w, s);
-            acc[x][y][m] = s;
-          }
-        }
-      }
-    };
-    f32x4 vA[4], vB[4], wa[4][3], wb[3][3];
-    rd_v(0, vA);
-    rd_w(0, 0, 4, wa);
-#pragma unroll
-    for (int d4 = 0; d4 < SH_DC / 4; ++d4) {
-      f32x4* vc = (d4 & 1) ? vB : vA;
-      f32x4* vn = (d4 & 1) ? vA : vB;
-      rd_w(d4, 4, 3, wb);
-      __builtin_amdgcn_sched_barrier(0);
-      prod(0, 4, wa, vc);
-      __builtin_amdgcn_sched_barrier(0);
-      if (d4 + 1 < SH_DC / 4) {
-        rd_v(d4 + 1, vn);
-        rd_w(d4 + 1, 0, 4, wa);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      prod(4, 3, wb, vc);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    __syncthreads();
-  }
-  // sum the thread's 4 steps, then the 16 step groups in order
-#pragma unroll
-  for (int y = 0; y < 4; ++y)
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-      red[tt][4 * tl + y][m] = ((acc[0][y][m] + acc[1][y][m]) + acc[2][y][m]) + acc[3][y][m];
+  store(0);
   __syncthreads();
-  if (tid < SH_L * 3) {
-    const int lt = tid / 3, m = tid % 3;
+  int buf = 0;
+  for (int64_t jc = j0; jc < j1; jc += SM_DC) {
+    const bool more = jc + SM_DC < j1;
+    if (more) load(jc + SM_DC);
+    // two 16-dof halves; lane (c, g) supplies dofs 16 h + 4 g .. + 3
+#pragma unroll
+    for (int h = 0; h < SM_DC / 16; ++h) {
+      const f32x4 vb = *reinterpret_cast<const f32x4*>(&vsh[buf][16 * wave + c][16 * h + 4 * g]);
+      f32x4 wa[SM_RB];
+#pragma unroll
+      for (int rb = 0; rb < SM_RB; ++rb)
+        wa[rb] = *reinterpret_cast<const f32x4*>(&wsh[buf][16 * wave + 16 * rb + c][16 * h + 4 * g]);
+      // the 9 independent accumulators between two products on the same one
+#pragma unroll
+      for (int rb = 0; rb < SM_RB; ++rb)
+        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wa[rb].x, (double)vb.x, acc[rb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < SM_RB; ++rb)
+        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wa[rb].y, (double)vb.y, acc[rb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < SM_RB; ++rb)
+        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wa[rb].z, (double)vb.z, acc[rb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < SM_RB; ++rb)
+        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wa[rb].w, (double)vb.w, acc[rb], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // lane (c, g) holds G[16 rb + 4 i + g][c] in acc[rb][i]
+#pragma unroll
+  for (int rb = 0; rb < SM_RB; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wave][16 * rb + 4 * i + g][c] = acc[rb][i];
+  __syncthreads();
+  if (tid < SM_L) {
+    const int lam = tid;
     double s = 0.0;
-    for (int g = 0; g < 16; ++g) s += red[g][lt][m];
-    part[(((int64_t)kc * n_ttiles + a) * n_lags_pad + (int64_t)SH_L * b + lt) * 3 + m] = s;
+    for (int w = 0; w < 4; ++w)
+      for (int cc = 0; cc < 16; ++cc) s += red[w][(SM_L - 1) + cc - lam][cc];
+    part[(((int64_t)kc * n_ttiles + a) * n_lags_pad + (int64_t)SM_L * b + lam) * 3 + mu] = s;
   }
 }
 
@@ -274,11 +233,11 @@ hipError_t launch_shc_block(hipStream_t s, const float* vt, const float* ring, i
                             int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
                             double* part, double* ksum, double* kcomp) {
   if (t_count <= 0) return hipSuccess;
-  const int n_ttiles = (t_count + SH_T - 1) / SH_T;
-  const int n_lags_pad = (n_lags + SH_L - 1) / SH_L * SH_L;
-  const int n_ltiles = n_lags_pad / SH_L;
-  hipLaunchKernelGGL(k_shc_gram, dim3((unsigned)(3 * n_kcs * n_ttiles * n_ltiles)), dim3(256), 0, s, vt, ring, ring_len,
-                     ld, N, Np, t_count, s0, dk, n_kcs, n_ttiles, n_lags_pad, part);
+  const int n_ttiles = (t_count + SM_T - 1) / SM_T;
+  const int n_lags_pad = (n_lags + SM_L - 1) / SM_L * SM_L;
+  const int n_ltiles = n_lags_pad / SM_L;
+  hipLaunchKernelGGL(k_shc_gram, dim3((unsigned)(9 * n_kcs * n_ttiles * n_ltiles)), dim3(256), 0, s, vt, ring,
+                     ring_len, ld, N, Np, t_count, s0, dk, n_kcs, n_ttiles, n_lags_pad, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_shc_accum, dim3((unsigned)((3 * n_lags * 3 + 255) / 256)), dim3(256), 0, s, part, n_kcs,

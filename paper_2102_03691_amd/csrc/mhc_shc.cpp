@@ -99,7 +99,8 @@ void sfree(mhc_shc* c) {
   c->stream = nullptr;
 }
 
-int lags_pad(int n) { return (n + 63) / 64 * 64; }
+// lags of the product work-groups are padded to 128
+int lags_pad(int n) { return (n + 127) / 128 * 128; }
 
 // One block of t_count <= T steps whose inputs are device pointers.
 mhc_status shc_block(mhc_shc* c, const float* v, const float* W, int t_count) {
@@ -163,18 +164,19 @@ mhc_status mhc_shc_create(int device, void* hip_stream, int64_t n_atoms, int32_t
   c->T = t_block;
   c->ring_len = (int64_t)n_lags - 1 + t_block;
   // Split each direction's N dofs into n_kcs ranges of dk.  A product
-  // work-group holds one CU (its register file), so a full block takes
-  // ceil(3 n_kcs tiles / n_cu) rounds of dk / 32 chunks each, plus a fixed
-  // cost per work-group (staging, the final sums: about two chunks); pick the
-  // split with the least such time, the fewer work-groups on a tie.
-  const int64_t tiles = (int64_t)(t_block / 64) * (lags_pad(n_lags) / 64);
+  // work-group (64 steps x 128 lags x one virial component) takes half a CU
+  // (half its registers and LDS), so a full block takes
+  // ceil(3 n_kcs tiles / (2 n_cu)) rounds of dk / 32 chunks each, plus a
+  // fixed cost per work-group (staging, the diagonal sums: about two chunks);
+  // pick the split with the least such time, the fewer work-groups on a tie.
+  const int64_t tiles = (int64_t)3 * (t_block / 64) * (lags_pad(n_lags) / 128);
   const int64_t max_kc = c->Np / 32;
   int64_t best = -1, best_cost = 0;
   for (int64_t kc = 1; kc <= max_kc; ++kc) {
     const int64_t dk = ((c->N + kc - 1) / kc + 31) / 32 * 32;
     const int64_t n = (c->N + dk - 1) / dk;
     if (n != kc) continue;
-    const int64_t rounds = (3 * n * tiles + n_cu - 1) / n_cu;
+    const int64_t rounds = (3 * n * tiles + 2 * n_cu - 1) / (2 * n_cu);
     const int64_t cost = rounds * (dk / 32 + 2);
     if (best < 0 || cost < best_cost) {
       best = kc;
