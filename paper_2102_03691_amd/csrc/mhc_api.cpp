@@ -86,6 +86,12 @@ struct mhc_ctx {
   double* d_jtot = nullptr;
   float* d_v = nullptr;
   float* d_W = nullptr;
+  // host-pointer pushes: a second staging set and a copy stream, so that the
+  // PCIe copy of one block overlaps the kernels of the previous one
+  float* d_v2 = nullptr;
+  float* d_W2 = nullptr;
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_copied[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
   double *d_hsum = nullptr, *d_hcomp = nullptr, *d_tsum = nullptr, *d_tcomp = nullptr;
   int n_dir = 1;                 // 3 with the motion-direction split (one pass per direction)
   double* d_jd = nullptr;        // split Eq. 10 partials of the current pass
@@ -272,8 +278,12 @@ mhc_status mhc_destroy(mhc_ctx* ctx) {
   if (!ctx) return MHC_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
   free_all(ctx);
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {ctx->ev_start, ctx->ev_copied[0], ctx->ev_copied[1], ctx->ev_free[0], ctx->ev_free[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return MHC_OK;
@@ -761,6 +771,24 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
   return MHC_OK;
 }
 
+// Second input staging set, copy stream and events of host-pointer pushes,
+// created on the first such push.
+static mhc_status host_staging(mhc_ctx* ctx) {
+  if (ctx->copy_stream) return MHC_OK;
+  void *pv = nullptr, *pW = nullptr;
+  mhc_status st = dev_alloc(ctx, (size_t)ctx->chunk * ctx->N * 3 * 4, &pv, "velocity staging 2");
+  if (st) return st;
+  if ((st = dev_alloc(ctx, (size_t)ctx->chunk * ctx->N * 9 * 4, &pW, "virial staging 2"))) return st;
+  for (hipEvent_t* e : {&ctx->ev_start, &ctx->ev_copied[0], &ctx->ev_copied[1], &ctx->ev_free[0], &ctx->ev_free[1]})
+    HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
+  hipStream_t cs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "copy stream");
+  ctx->d_v2 = reinterpret_cast<float*>(pv);
+  ctx->d_W2 = reinterpret_cast<float*>(pW);
+  ctx->copy_stream = cs;
+  return MHC_OK;
+}
+
 mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* W, int on_device) {
   mhc_status st = enter(ctx);
   if (st) return st;
@@ -775,19 +803,49 @@ mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* 
       return fail(ctx, MHC_ERR_NONFINITE, "non-finite velocity or virial");
   }
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-  for (int32_t s0 = 0; s0 < n_steps; s0 += ctx->chunk) {
-    const int tc = std::min(ctx->chunk, n_steps - s0);
-    const float* vp = v + (int64_t)s0 * N * 3;
-    const float* Wp = W + (int64_t)s0 * N * 9;
-    if (!on_device) {
-      HIP_TRY(hipMemcpyAsync(ctx->d_v, vp, (size_t)tc * N * 3 * 4, hipMemcpyHostToDevice, ctx->stream), "copy v");
-      HIP_TRY(hipMemcpyAsync(ctx->d_W, Wp, (size_t)tc * N * 9 * 4, hipMemcpyHostToDevice, ctx->stream), "copy W");
-      vp = ctx->d_v;
-      Wp = ctx->d_W;
+  if (on_device) {
+    for (int32_t s0 = 0; s0 < n_steps; s0 += ctx->chunk) {
+      const int tc = std::min(ctx->chunk, n_steps - s0);
+      if ((st = run_block(ctx, v + (int64_t)s0 * N * 3, W + (int64_t)s0 * N * 9, tc))) return st;
     }
-    if ((st = run_block(ctx, vp, Wp, tc))) return st;
+    return MHC_OK;
   }
-  if (!on_device) HIP_TRY(hipStreamSynchronize(ctx->stream), "push sync");
+  if (n_steps <= ctx->chunk) {
+    // one block: copy and kernels in order on the context stream
+    HIP_TRY(hipMemcpyAsync(ctx->d_v, v, (size_t)n_steps * N * 3 * 4, hipMemcpyHostToDevice, ctx->stream), "copy v");
+    HIP_TRY(hipMemcpyAsync(ctx->d_W, W, (size_t)n_steps * N * 9 * 4, hipMemcpyHostToDevice, ctx->stream), "copy W");
+    if ((st = run_block(ctx, ctx->d_v, ctx->d_W, n_steps))) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "push sync");
+    return MHC_OK;
+  }
+  // Several blocks of host inputs: block k is copied into staging set k % 2
+  // on the copy stream while block k - 1 runs.  The copy stream first waits for all work queued
+  // on the context stream (which may still read the staging sets, e.g. a
+  // grouped push), then each copy waits for the block that last used its set.
+  if ((st = host_staging(ctx))) return st;
+  HIP_TRY(hipEventRecord(ctx->ev_start, ctx->stream), "event record");
+  HIP_TRY(hipStreamWaitEvent(ctx->copy_stream, ctx->ev_start, 0), "stream wait");
+  float* const sv[2] = {ctx->d_v, ctx->d_v2};
+  float* const sW[2] = {ctx->d_W, ctx->d_W2};
+  int k = 0;
+  for (int32_t s0 = 0; s0 < n_steps; s0 += ctx->chunk, ++k) {
+    const int tc = std::min(ctx->chunk, n_steps - s0);
+    const int b = k & 1;
+    if (k >= 2) HIP_TRY(hipStreamWaitEvent(ctx->copy_stream, ctx->ev_free[b], 0), "stream wait");
+    HIP_TRY(hipMemcpyAsync(sv[b], v + (int64_t)s0 * N * 3, (size_t)tc * N * 3 * 4, hipMemcpyHostToDevice,
+                           ctx->copy_stream), "copy v");
+    HIP_TRY(hipMemcpyAsync(sW[b], W + (int64_t)s0 * N * 9, (size_t)tc * N * 9 * 4, hipMemcpyHostToDevice,
+                           ctx->copy_stream), "copy W");
+    HIP_TRY(hipEventRecord(ctx->ev_copied[b], ctx->copy_stream), "event record");
+    HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->ev_copied[b], 0), "stream wait");
+    if ((st = run_block(ctx, sv[b], sW[b], tc))) {
+      (void)hipStreamSynchronize(ctx->copy_stream);     // the caller may reuse v and W on return
+      return st;
+    }
+    HIP_TRY(hipEventRecord(ctx->ev_free[b], ctx->stream), "event record");
+  }
+  // every copy precedes a kernel the context stream waited for
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "push sync");
   return MHC_OK;
 }
 
