@@ -129,3 +129,34 @@ int main(void) {
                     "-Wl,-rpath," + os.path.dirname(lib), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     assert out[:5] == ["0", "0", "0", "1", "1"] and out[5] == "1" and out[6] == "MHC_ERR_STATE"
+
+
+def test_header_compiles_as_cpp_and_links(tmp_path):
+    """The same program as C++17: the header's extern "C" guards give the
+    library's unmangled symbols."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib = _lib.library_path()
+    src = tmp_path / "use_mhc.cpp"
+    src.write_text(r'''
+#include <cstdio>
+#include "mhc.h"
+int main() {
+  const double f[4] = {0.5, 1.5, 2.5, 3.5};
+  int32_t b[4];
+  const mhc_status st = mhc_bins_uniform(4, f, 2, 0.0, 4.0, b);
+  mhc_ctx* ctx = nullptr;
+  const mhc_status bad = mhc_push(ctx, 1, nullptr, nullptr, 0);
+  std::printf("%d %d %d %d %d %d\n", (int)st, b[0], b[1], b[2], b[3], (int)bad);
+  return 0;
+}
+''')
+    exe = tmp_path / "use_mhc_cpp"
+    subprocess.run([gxx, "-std=c++17", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.join(root, "include"),
+                    str(src), lib, "-Wl,-rpath," + os.path.dirname(lib), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert out == ["0", "0", "0", "1", "1", "1"]
