@@ -772,19 +772,24 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
 }
 
 // Second input staging set, copy stream and events of host-pointer pushes,
-// created on the first such push.
+// created on the first such push; each piece once, so that a push after a
+// failed one completes the set without leaking what was already made.
 static mhc_status host_staging(mhc_ctx* ctx) {
   if (ctx->copy_stream) return MHC_OK;
-  void *pv = nullptr, *pW = nullptr;
-  mhc_status st = dev_alloc(ctx, (size_t)ctx->chunk * ctx->N * 3 * 4, &pv, "velocity staging 2");
-  if (st) return st;
-  if ((st = dev_alloc(ctx, (size_t)ctx->chunk * ctx->N * 9 * 4, &pW, "virial staging 2"))) return st;
+  mhc_status st;
+  void* p = nullptr;
+  if (!ctx->d_v2) {
+    if ((st = dev_alloc(ctx, (size_t)ctx->chunk * ctx->N * 3 * 4, &p, "velocity staging 2"))) return st;
+    ctx->d_v2 = reinterpret_cast<float*>(p);
+  }
+  if (!ctx->d_W2) {
+    if ((st = dev_alloc(ctx, (size_t)ctx->chunk * ctx->N * 9 * 4, &p, "virial staging 2"))) return st;
+    ctx->d_W2 = reinterpret_cast<float*>(p);
+  }
   for (hipEvent_t* e : {&ctx->ev_start, &ctx->ev_copied[0], &ctx->ev_copied[1], &ctx->ev_free[0], &ctx->ev_free[1]})
-    HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
+    if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
   hipStream_t cs = nullptr;
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "copy stream");
-  ctx->d_v2 = reinterpret_cast<float*>(pv);
-  ctx->d_W2 = reinterpret_cast<float*>(pW);
   ctx->copy_stream = cs;
   return MHC_OK;
 }
