@@ -229,17 +229,23 @@ __global__ void __launch_bounds__(256) k_shc_accum(const double* __restrict__ pa
   neumaier_add(ksum[q], kcomp[q], s);
 }
 
-hipError_t launch_shc_block(hipStream_t s, const float* vt, const float* ring, int64_t ring_len, int64_t ld,
-                            int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
-                            double* part, double* ksum, double* kcomp) {
+hipError_t launch_shc_products(hipStream_t s, const float* vt, const float* ring, int64_t ring_len, int64_t ld,
+                               int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
+                               double* part) {
   if (t_count <= 0) return hipSuccess;
   const int n_ttiles = (t_count + SM_T - 1) / SM_T;
   const int n_lags_pad = (n_lags + SM_L - 1) / SM_L * SM_L;
   const int n_ltiles = n_lags_pad / SM_L;
   hipLaunchKernelGGL(k_shc_gram, dim3((unsigned)(9 * n_kcs * n_ttiles * n_ltiles)), dim3(256), 0, s, vt, ring,
                      ring_len, ld, N, Np, t_count, s0, dk, n_kcs, n_ttiles, n_lags_pad, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_shc_accum(hipStream_t s, const double* part, int t_count, int n_lags, int n_kcs, double* ksum,
+                            double* kcomp) {
+  if (t_count <= 0) return hipSuccess;
+  const int n_ttiles = (t_count + SM_T - 1) / SM_T;
+  const int n_lags_pad = (n_lags + SM_L - 1) / SM_L * SM_L;
   hipLaunchKernelGGL(k_shc_accum, dim3((unsigned)((3 * n_lags * 3 + 255) / 256)), dim3(256), 0, s, part, n_kcs,
                      n_ttiles, n_lags, n_lags_pad, ksum, kcomp);
   return hipGetLastError();

@@ -178,14 +178,17 @@ hipError_t launch_hnema_finish(hipStream_t s, const double* sum, const double* c
 // vt[t][nu Np + i] = v[t][i][nu], s = s0 + t, t < t_count.
 hipError_t launch_shc_ring(hipStream_t s, const float* W, const float* v, int t_count, int64_t N, int64_t Np,
                            float* ring, int64_t ring_len, int64_t ld, int64_t s0, float* vt);
-// K^{mu nu}(tau) sums += sum_{t < t_count} sum_i ring[s0 + t - tau][mu][nu Np + i] vt[t][nu Np + i]
-// for tau < n_lags, origins s0 + t - tau >= 0 only; each direction segment splits into n_kcs
-// ranges of dk (multiple of 32) dofs; part holds
-// [3 n_kcs][ceil(t_count/64)][round_up(n_lags, 64)][3] doubles; ksum, kcomp [3 nu][n_lags][3 mu].
-// Fixed order, Neumaier.
-hipError_t launch_shc_block(hipStream_t s, const float* vt, const float* ring, int64_t ring_len, int64_t ld,
-                            int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
-                            double* part, double* ksum, double* kcomp);
+// Partial K^{mu nu}(tau) of one block: sum_{t < t_count} sum_i ring[s0 + t - tau][mu][nu Np + i]
+// vt[t][nu Np + i] for tau < n_lags, origins s0 + t - tau >= 0 only, per dof range and 64-step
+// tile; each direction segment splits into n_kcs ranges of dk (multiple of 32) dofs; part holds
+// [3 n_kcs][ceil(t_count/64)][round_up(n_lags, 128)][3] doubles.
+hipError_t launch_shc_products(hipStream_t s, const float* vt, const float* ring, int64_t ring_len, int64_t ld,
+                               int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
+                               double* part);
+// The block's partials added to the running sums ksum, kcomp [3 nu][n_lags][3 mu] in a fixed
+// order (dof ranges, then step tiles), Neumaier.
+hipError_t launch_shc_accum(hipStream_t s, const double* part, int t_count, int n_lags, int n_kcs, double* ksum,
+                            double* kcomp);
 // Kd[tau][mu][nu] = (ksum + kcomp)[nu][tau][mu] / (S - tau) (zero where S <= tau) and
 // K[tau][mu] = sum over nu in order.
 hipError_t launch_shc_finish(hipStream_t s, const double* ksum, const double* kcomp, int n_lags, int64_t S,

@@ -118,10 +118,12 @@ mhc_status shc_block(mhc_shc* c, const float* v, const float* W, int t_count) {
     c->ev_used += 2;
     SHIP_TRY(hipEventRecord(e0, c->stream), "event record");
   }
-  SHIP_TRY(launch_shc_block(c->stream, c->vt, c->ring, c->ring_len, c->ld, c->N, c->Np, t_count, c->S, c->n_lags,
-                            c->dk, c->n_kcs, c->part, c->ksum, c->ksum + 9 * c->n_lags),
+  SHIP_TRY(launch_shc_products(c->stream, c->vt, c->ring, c->ring_len, c->ld, c->N, c->Np, t_count, c->S,
+                               c->n_lags, c->dk, c->n_kcs, c->part),
            "virial-velocity products");
   if (e1) SHIP_TRY(hipEventRecord(e1, c->stream), "event record");
+  SHIP_TRY(launch_shc_accum(c->stream, c->part, t_count, c->n_lags, c->n_kcs, c->ksum, c->ksum + 9 * c->n_lags),
+           "partial sums");
   c->S += t_count;
   return MHC_OK;
 }
