@@ -37,6 +37,12 @@ struct mhc_shc {
   float* vt = nullptr;                 // [T][ld] velocities, direction-major
   float* sv = nullptr;                 // host-input staging [T][N][3]
   float* sW = nullptr;                 // [T][N][9]
+  // host pushes of several blocks: a second staging set and a copy stream,
+  // so that one block's PCIe copy overlaps the previous block's kernels
+  float* sv2 = nullptr;
+  float* sW2 = nullptr;
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_copied[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
   double* part = nullptr;              // [3 n_kcs][T/64][n_lags_pad][3]
   double* ksum = nullptr;              // [3 nu][n_lags][3 mu] x 2 (sum, compensation)
   double* kout = nullptr;              // [n_lags][3] then [n_lags][3][3] read-out
@@ -91,10 +97,20 @@ mhc_status salloc(mhc_shc* c, size_t bytes, void** out, const char* what) {
 }
 
 void sfree(mhc_shc* c) {
+  if (c->copy_stream) {
+    (void)hipStreamSynchronize(c->copy_stream);
+    (void)hipStreamDestroy(c->copy_stream);
+    c->copy_stream = nullptr;
+  }
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   for (auto e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
+  for (hipEvent_t* e : {&c->ev_start, &c->ev_copied[0], &c->ev_copied[1], &c->ev_free[0], &c->ev_free[1]})
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   c->stream = nullptr;
 }
@@ -224,25 +240,77 @@ mhc_status mhc_shc_destroy(mhc_shc* c) {
 
 const char* mhc_shc_last_error(const mhc_shc* c) { return c ? c->err.c_str() : g_shc_create_error.c_str(); }
 
+// Second staging set, copy stream and events of host pushes, created on the
+// first push of several blocks; each piece once.
+static mhc_status shc_host_staging(mhc_shc* c) {
+  if (c->copy_stream) return MHC_OK;
+  mhc_status st;
+  void* p = nullptr;
+  if (!c->sv2) {
+    if ((st = salloc(c, (size_t)c->T * c->N3 * 4, &p, "velocity staging 2"))) return st;
+    c->sv2 = static_cast<float*>(p);
+  }
+  if (!c->sW2) {
+    if ((st = salloc(c, (size_t)c->T * c->N3 * 12, &p, "virial staging 2"))) return st;
+    c->sW2 = static_cast<float*>(p);
+  }
+  for (hipEvent_t* e : {&c->ev_start, &c->ev_copied[0], &c->ev_copied[1], &c->ev_free[0], &c->ev_free[1]})
+    if (!*e) SHIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
+  hipStream_t cs = nullptr;
+  SHIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "copy stream");
+  c->copy_stream = cs;
+  return MHC_OK;
+}
+
 mhc_status mhc_shc_push(mhc_shc* c, int32_t n_steps, const float* v, const float* W, int on_device) {
   mhc_status st = senter(c);
   if (st) return st;
   if (n_steps < 0 || (on_device != 0 && on_device != 1)) return sfail(c, MHC_ERR_INVALID_ARG, "bad arguments");
   if (n_steps == 0) return MHC_OK;
   if (!v || !W) return sfail(c, MHC_ERR_INVALID_ARG, "NULL input");
-  for (int32_t s0 = 0; s0 < n_steps; s0 += c->T) {
-    const int tc = std::min<int32_t>(c->T, n_steps - s0);
-    const float* vb = v + (int64_t)s0 * c->N3;
-    const float* Wb = W + (int64_t)s0 * c->N3 * 3;
-    if (!on_device) {
-      SHIP_TRY(hipMemcpyAsync(c->sv, vb, (size_t)tc * c->N3 * 4, hipMemcpyHostToDevice, c->stream), "copy v");
-      SHIP_TRY(hipMemcpyAsync(c->sW, Wb, (size_t)tc * c->N3 * 12, hipMemcpyHostToDevice, c->stream), "copy W");
-      vb = c->sv;
-      Wb = c->sW;
+  if (on_device) {
+    for (int32_t s0 = 0; s0 < n_steps; s0 += c->T) {
+      const int tc = std::min<int32_t>(c->T, n_steps - s0);
+      if ((st = shc_block(c, v + (int64_t)s0 * c->N3, W + (int64_t)s0 * c->N3 * 3, tc))) return st;
     }
-    if ((st = shc_block(c, vb, Wb, tc))) return st;
+    return MHC_OK;
   }
-  if (!on_device) SHIP_TRY(hipStreamSynchronize(c->stream), "push sync");
+  if (n_steps <= c->T) {
+    // one block: copy and kernels in order on the stream
+    SHIP_TRY(hipMemcpyAsync(c->sv, v, (size_t)n_steps * c->N3 * 4, hipMemcpyHostToDevice, c->stream), "copy v");
+    SHIP_TRY(hipMemcpyAsync(c->sW, W, (size_t)n_steps * c->N3 * 12, hipMemcpyHostToDevice, c->stream), "copy W");
+    if ((st = shc_block(c, c->sv, c->sW, n_steps))) return st;
+    SHIP_TRY(hipStreamSynchronize(c->stream), "push sync");
+    return MHC_OK;
+  }
+  // Several blocks: block k is copied into staging set k % 2 on the copy
+  // stream while block k - 1 runs; the copy stream first waits for the work
+  // already queued on the stream, then each copy for the block that last
+  // read its set.
+  if ((st = shc_host_staging(c))) return st;
+  SHIP_TRY(hipEventRecord(c->ev_start, c->stream), "event record");
+  SHIP_TRY(hipStreamWaitEvent(c->copy_stream, c->ev_start, 0), "stream wait");
+  float* const sv[2] = {c->sv, c->sv2};
+  float* const sW[2] = {c->sW, c->sW2};
+  int k = 0;
+  for (int32_t s0 = 0; s0 < n_steps; s0 += c->T, ++k) {
+    const int tc = std::min<int32_t>(c->T, n_steps - s0);
+    const int b = k & 1;
+    if (k >= 2) SHIP_TRY(hipStreamWaitEvent(c->copy_stream, c->ev_free[b], 0), "stream wait");
+    SHIP_TRY(hipMemcpyAsync(sv[b], v + (int64_t)s0 * c->N3, (size_t)tc * c->N3 * 4, hipMemcpyHostToDevice,
+                            c->copy_stream), "copy v");
+    SHIP_TRY(hipMemcpyAsync(sW[b], W + (int64_t)s0 * c->N3 * 3, (size_t)tc * c->N3 * 12, hipMemcpyHostToDevice,
+                            c->copy_stream), "copy W");
+    SHIP_TRY(hipEventRecord(c->ev_copied[b], c->copy_stream), "event record");
+    SHIP_TRY(hipStreamWaitEvent(c->stream, c->ev_copied[b], 0), "stream wait");
+    if ((st = shc_block(c, sv[b], sW[b], tc))) {
+      (void)hipStreamSynchronize(c->copy_stream);     // the caller may reuse v and W on return
+      return st;
+    }
+    SHIP_TRY(hipEventRecord(c->ev_free[b], c->stream), "event record");
+  }
+  // every copy precedes a kernel the stream waited for
+  SHIP_TRY(hipStreamSynchronize(c->stream), "push sync");
   return MHC_OK;
 }
 

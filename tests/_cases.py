@@ -60,7 +60,7 @@ class Case:
 
 
 def run_library(case: Case, nb, methods, precision, t_block, corr_len=0, dt=1.0, splits=None, bins=None,
-                row_chunk=97, keep=False, schedule=0):
+                row_chunk=97, keep=False, schedule=0, device_inputs=False):
     from paper_2102_03691_amd import ModalHC, HNEMA, GKMA
     h = ModalHC(0)
     h.load_system(case.m, case.freq)
@@ -76,9 +76,14 @@ def run_library(case: Case, nb, methods, precision, t_block, corr_len=0, dt=1.0,
     h.finalize()
     S = case.v.shape[0]
     splits = splits or [S]
+    v, W = case.v, case.W
+    if device_inputs:
+        import torch
+        v = torch.as_tensor(v, device="cuda:0")
+        W = torch.as_tensor(W, device="cuda:0")
     s0 = 0
     for n in splits:
-        h.push(case.v[s0:s0 + n], case.W[s0:s0 + n])
+        h.push(v[s0:s0 + n], W[s0:s0 + n])
         s0 += n
     assert s0 == S
     out = {}

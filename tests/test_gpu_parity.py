@@ -149,6 +149,11 @@ def test_block_split_invariance_and_determinism(small, sched):
     c = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16, splits=[1, 7, 64, 228], schedule=sched)
     for k in ("hnema", "corr", "hcacf"):
         assert rel(c[k], a[k]) <= 1e-5, k
+    # host pushes of several blocks overlap each copy with the previous block's kernels; device inputs
+    # of the same blocks give the same bits
+    d = run_library(small, 23, HNEMA | GKMA, BF16X3, 64, corr_len=16, schedule=sched, device_inputs=True)
+    for k in ("hnema", "corr", "integral", "hcacf"):
+        assert np.array_equal(d[k], a[k]), k
 
 
 def test_save_and_restore_is_bitwise(small):

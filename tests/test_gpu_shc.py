@@ -91,6 +91,10 @@ def test_shc_determinism_split_invariance_and_reset():
     assert np.array_equal(K1, K2)
     h3, K3, _ = _run(n_atoms, v, W, L, T, [5, 100, 1, 294], True)
     assert rel(K3, K1) <= 1e-13
+    # the same blocks pushed from host memory (copies overlapped with the kernels): bitwise equal
+    h5, K5, _ = _run(n_atoms, v, W, L, T, [S], False)
+    assert np.array_equal(K5, K1)
+    h5.close()
     # reset, then a different run: only the new samples count
     import torch
     v2, W2 = _inputs(n_atoms, 150, seed=8)
