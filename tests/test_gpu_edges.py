@@ -136,3 +136,52 @@ def test_group_with_a_one_atom_system():
     grp.close()
     for h in hs:
         h.close()
+
+
+def test_maximum_lags():
+    """corr_len = 65536, the largest the API takes, on a small system: the
+    first 300 lags against the oracle, every later lag exactly zero."""
+    announce("edge maximum lags (65536) fp32 T=64")
+    L, S = 65536, 300
+    c = Tiny((2, 2, 2), None, 2, S, seed=51)
+    ref = c.oracle(L)
+    h = c.context(HNEMA | GKMA, FP32, 64, L)
+    h.push(c.v[:100], c.W[:100])
+    h.push(c.v[100:], c.W[100:])
+    g = h.read_gkma()
+    h.close()
+    e = {"rel_corr": rel(g["corr"][:S], ref["corr"][:S]), "rel_integral": rel(g["integral"], ref["integral"]),
+         "rel_hcacf": rel(g["hcacf"], ref["hcacf"])}
+    log("edge_max_lags", **e)
+    assert g["corr"].shape[0] == L and g["n_samples"] == S
+    assert e["rel_corr"] <= TOL[0] and e["rel_integral"] <= TOL[0] and e["rel_hcacf"] <= 1e-12
+    assert not g["corr"][S:].any() and not g["hcacf"][S:].any()
+
+
+def test_maximum_bins():
+    """n_bins = 2^20, the largest the API takes, with the 108 modes of a
+    4x3x3 lattice spread over it (the last bin included): the bins that hold
+    modes against the oracle on the same map compacted to those bins (a
+    bin's current does not depend on its label), every other bin exactly
+    zero, for HNEMA and a two-lag GKMA."""
+    announce("edge maximum bins (2^20) bf16x3 T=32")
+    nb, L, S = 1 << 20, 2, 96
+    c = Tiny((4, 3, 3), None, 1, S, seed=52)
+    bins = ((np.arange(c.M) * 9973) % nb).astype(np.int32)
+    bins[0] = nb - 1
+    used, compact = np.unique(bins, return_inverse=True)
+    ref = oracle.run_dense(c.E, c.m, c.v, c.W, compact.astype(np.int32), len(used), corr_len=L, dt=1.0)
+    c.nb, c.bins = nb, bins
+    h = c.context(HNEMA | GKMA, BF16X3, 32, L)
+    h.push(c.v, c.W)
+    avg, tot, n = h.read_hnema()
+    g = h.read_gkma()
+    h.close()
+    empty = np.ones(nb, bool)
+    empty[used] = False
+    e = {"rel_hnema": rel(avg[used], ref["hnema"]), "rel_corr": rel(g["corr"][:, used], ref["corr"]),
+         "rel_total": rel(tot, ref["hnema_total"])}
+    log("edge_max_bins", **e)
+    assert n == S and avg.shape == (nb, 3) and g["corr"].shape == (L, nb, 3, 3)
+    assert e["rel_hnema"] <= TOL[1] and e["rel_corr"] <= TOL[1] and e["rel_total"] <= 1e-12
+    assert not avg[empty].any() and not g["corr"][:, empty].any()
