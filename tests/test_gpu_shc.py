@@ -175,3 +175,21 @@ def test_shc_paper_shaped_size():
     log("shc_N8000_S600_L250_T256", rel_K=e, rel_K_dir=ed)
     assert n == S and e <= TOL and ed <= TOL
     h.close()
+
+
+def test_shc_maximum_lags_and_block():
+    """n_lags = 4096 and t_block = 1024, the largest the API takes, on 10
+    atoms: 2100 samples pushed from host memory in one call (two full blocks
+    and a partial one, copies overlapped), K and the direction split against
+    the oracle, every lag past the run exactly zero."""
+    announce("shc 10 atoms L=4096 T=1024")
+    n_atoms, S, L, T = 10, 2100, 4096, 1024
+    v, W = _inputs(n_atoms, S, seed=13)
+    h, K, n = _run(n_atoms, v, W, L, T, [S], False)
+    Kd, _ = h.read_dir()
+    h.close()
+    e = rel(K, oracle.shc_correlation(v, W, L))
+    ed = rel(Kd, oracle.shc_correlation_directional(v, W, L))
+    log("shc_N10_S2100_L4096_T1024", rel_K=e, rel_K_dir=ed)
+    assert n == S and K.shape == (L, 3) and e <= TOL and ed <= TOL
+    assert not K[S:].any() and not Kd[S:].any()
