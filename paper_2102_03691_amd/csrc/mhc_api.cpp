@@ -774,8 +774,7 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
 // Second input staging set, copy stream and events of host-pointer pushes,
 // created on the first such push; each piece once, so that a push after a
 // failed one completes the set without leaking what was already made.
-static mhc_status host_staging(mhc_ctx* ctx) {
-  if (ctx->copy_stream) return MHC_OK;
+static mhc_status staging_set2(mhc_ctx* ctx) {
   mhc_status st;
   void* p = nullptr;
   if (!ctx->d_v2) {
@@ -786,6 +785,13 @@ static mhc_status host_staging(mhc_ctx* ctx) {
     if ((st = dev_alloc(ctx, (size_t)ctx->chunk * ctx->N * 9 * 4, &p, "virial staging 2"))) return st;
     ctx->d_W2 = reinterpret_cast<float*>(p);
   }
+  return MHC_OK;
+}
+
+static mhc_status host_staging(mhc_ctx* ctx) {
+  if (ctx->copy_stream) return MHC_OK;
+  mhc_status st;
+  if ((st = staging_set2(ctx))) return st;
   for (hipEvent_t* e : {&ctx->ev_start, &ctx->ev_copied[0], &ctx->ev_copied[1], &ctx->ev_free[0], &ctx->ev_free[1]})
     if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
   hipStream_t cs = nullptr;
@@ -1227,6 +1233,10 @@ struct mhc_group {
   hipEvent_t fork_ev = nullptr, join_ev[NAUX] = {};
   hipEvent_t tab_ev[TAB_RING] = {};
   bool tab_busy[TAB_RING] = {};
+  // host-input pushes of several blocks: copies of block k go to staging set
+  // k % 2 of every system on this stream while block k - 1 runs
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t cp_start = nullptr, cp_done[2] = {nullptr, nullptr}, cp_free[2] = {nullptr, nullptr};
   int tab_pos = 0;
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -1646,6 +1656,12 @@ mhc_status mhc_group_destroy(mhc_group* g) {
     if (g->join_ev[k]) (void)hipEventDestroy(g->join_ev[k]);
     if (g->aux[k]) (void)hipStreamDestroy(g->aux[k]);
   }
+  if (g->copy_stream) {
+    (void)hipStreamSynchronize(g->copy_stream);
+    (void)hipStreamDestroy(g->copy_stream);
+  }
+  for (hipEvent_t e : {g->cp_start, g->cp_done[0], g->cp_done[1], g->cp_free[0], g->cp_free[1]})
+    if (e) (void)hipEventDestroy(e);
   delete g;
   return MHC_OK;
 }
@@ -1667,9 +1683,31 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
   GHIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const int T = g->t_block;
+  // host inputs of two or more full blocks: copies on the copy stream into
+  // alternating staging sets, overlapped with the previous block's kernels
+  // (the copy stream first waits for everything queued on the group stream,
+  // then each copy for the block that last read its set)
+  const bool overlap = !on_device && n_steps >= 2 * T;
+  if (overlap) {
+    for (auto* c : g->sys) {
+      mhc_status st = staging_set2(c);
+      if (st) return gfail(g, st, c->err);
+    }
+    for (hipEvent_t* e : {&g->cp_start, &g->cp_done[0], &g->cp_done[1], &g->cp_free[0], &g->cp_free[1]})
+      if (!*e) GHIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
+    if (!g->copy_stream) {
+      hipStream_t cs = nullptr;
+      GHIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "copy stream");
+      g->copy_stream = cs;
+    }
+    GHIP_TRY(hipEventRecord(g->cp_start, g->stream), "event record");
+    GHIP_TRY(hipStreamWaitEvent(g->copy_stream, g->cp_start, 0), "stream wait");
+  }
   int32_t s0 = 0;
-  for (; s0 + T <= n_steps; s0 += T) {
+  for (int blk = 0; s0 + T <= n_steps; s0 += T, ++blk) {
     // device inputs are read in place; host inputs go through the staging buffers
+    const int b = blk & 1;
+    if (overlap && blk >= 2) GHIP_TRY(hipStreamWaitEvent(g->copy_stream, g->cp_free[b], 0), "stream wait");
     const int k = g->tab_pos;
     g->tab_pos = (g->tab_pos + 1) % TAB_RING;
     if (g->tab_busy[k]) GHIP_TRY(hipEventSynchronize(g->tab_ev[k]), "input table slot");
@@ -1679,14 +1717,21 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
       const float* vi = v[i] + (int64_t)s0 * c->N * 3;
       const float* Wi = W[i] + (int64_t)s0 * c->N * 9;
       if (!on_device) {
-        GHIP_TRY(hipMemcpyAsync(c->d_v, vi, (size_t)T * c->N * 3 * 4, hipMemcpyHostToDevice, g->stream), "v");
-        GHIP_TRY(hipMemcpyAsync(c->d_W, Wi, (size_t)T * c->N * 9 * 4, hipMemcpyHostToDevice, g->stream), "W");
-        vi = c->d_v;
-        Wi = c->d_W;
+        float* sv = (overlap && b) ? c->d_v2 : c->d_v;
+        float* sW = (overlap && b) ? c->d_W2 : c->d_W;
+        hipStream_t cs = overlap ? g->copy_stream : g->stream;
+        GHIP_TRY(hipMemcpyAsync(sv, vi, (size_t)T * c->N * 3 * 4, hipMemcpyHostToDevice, cs), "v");
+        GHIP_TRY(hipMemcpyAsync(sW, Wi, (size_t)T * c->N * 9 * 4, hipMemcpyHostToDevice, cs), "W");
+        vi = sv;
+        Wi = sW;
       }
       tab[3 * i] = reinterpret_cast<uint64_t>(vi);
       tab[3 * i + 1] = reinterpret_cast<uint64_t>(Wi);
       tab[3 * i + 2] = (uint64_t)c->n_samples;
+    }
+    if (overlap) {
+      GHIP_TRY(hipEventRecord(g->cp_done[b], g->copy_stream), "event record");
+      GHIP_TRY(hipStreamWaitEvent(g->stream, g->cp_done[b], 0), "stream wait");
     }
     GHIP_TRY(hipMemcpyAsync(g->d_tab, tab, 3 * n * sizeof(uint64_t), hipMemcpyHostToDevice, g->stream),
              "block table");
@@ -1694,7 +1739,10 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
     g->tab_busy[k] = true;
     if (g->autotune && !g->tuned) {
       mhc_status st = autotune(g);
-      if (st) return st;
+      if (st) {
+        if (overlap) (void)hipStreamSynchronize(g->copy_stream);   // the caller may reuse v and W on return
+        return st;
+      }
     }
     mhc_status st;
     if (g->use_graph && !g->timing) {
@@ -1705,6 +1753,7 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
         hipError_t e = hipStreamEndCapture(g->stream, &graph);
         if (st) {
           if (graph) (void)hipGraphDestroy(graph);
+          if (overlap) (void)hipStreamSynchronize(g->copy_stream);
           return st;
         }
         GHIP_TRY(e, "end capture");
@@ -1713,8 +1762,12 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
       }
       GHIP_TRY(hipGraphLaunch(g->exec, g->stream), "graph launch");
     } else {
-      if ((st = group_block(g, g->timing))) return st;
+      if ((st = group_block(g, g->timing))) {
+        if (overlap) (void)hipStreamSynchronize(g->copy_stream);
+        return st;
+      }
     }
+    if (overlap) GHIP_TRY(hipEventRecord(g->cp_free[b], g->stream), "event record");
     for (auto* c : g->sys) {
       c->n_samples += T;
       c->last_block = T;
