@@ -223,9 +223,19 @@ __global__ void __launch_bounds__(256) k_shc_accum(const double* __restrict__ pa
   const int nu = q / (n_lags * 3);
   const int r = q - nu * n_lags * 3;
   const int tau = r / 3, m = r % 3;
+  // partials (kc, a) of segment nu, kc-major: loads eight at a time, added in that order
+  const int n_p = n_kcs * n_ttiles;
+  const double* base = part + ((int64_t)nu * n_p * n_lags_pad + tau) * 3 + m;
+  const int64_t stride = (int64_t)n_lags_pad * 3;
   double s = 0.0;
-  for (int kc = nu * n_kcs; kc < (nu + 1) * n_kcs; ++kc)
-    for (int a = 0; a < n_ttiles; ++a) s += part[(((int64_t)kc * n_ttiles + a) * n_lags_pad + tau) * 3 + m];
+  for (int p0 = 0; p0 < n_p; p0 += 8) {
+    double x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = base[(int64_t)min(p0 + k, n_p - 1) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (p0 + k < n_p) s += x[k];
+  }
   neumaier_add(ksum[q], kcomp[q], s);
 }
 
