@@ -85,8 +85,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
 k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t ring_len, int64_t ld, int64_t N,
-               int64_t Np, int t_count, int64_t s0, int64_t dk, int n_kcs, int n_ttiles, int n_lags_pad,
-               double* __restrict__ part) {
+           int64_t Np, int t_count, int64_t s0, int64_t dk, int n_kcs, int n_ttiles, int n_lags_pad,
+           double* __restrict__ part) {
   // staging buffers, and after the products the G of the 4 waves
   constexpr int WSH = 2 * SM_ROWS * SM_WS, VSH = 2 * SM_T * SM_WS;          // floats
   constexpr int RED = 4 * 16 * SM_RB * 16;                                  // doubles
