@@ -214,15 +214,23 @@ hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a) {
 
 // -------------------------------------------------------------- correlation
 // Sums are stored lag-contiguous: C[(r*3 + nu)*L + tau].
-// Work-group tile: 64 rows r x 64 lags tau (x 3 nu); thread = 4 rows x 4 lags,
-// with the 16 lag groups on consecutive lanes so that the Neumaier update of
-// a thread's 4 lags is one 32-byte run and a half-wave covers 512 bytes.
-// X and the needed window of the history ring are staged in LDS per chunk of
-// 64 steps; along t the 4 lags of a thread slide over the ring one entry per
-// step, so each step costs 4 X reads + 3 ring reads for 48 FMAs.
+// Work-group tile: 64 rows r x 64 lags tau (x 3 nu); X and the needed window
+// of the history ring are staged in LDS per chunk of 64 steps.  The update of
+// one chunk is a float64 matrix product on the matrix cores: with the window
+// entry q = j + 63 - lambda holding the total at step j of the chunk minus lag
+// tau0 + lambda,
+//   C[r][lambda][nu] += sum_j X[r][j] * window[nu][j + 63 - lambda],
+// done by v_mfma_f64_16x16x4f64 over 4 steps at a time (A = 16 rows x 4
+// steps of X, B = 4 steps x 16 lags of the window, its lane (k, c) reading
+// entry j + k + 63 - lambda_c).  Wave w owns rows 16w .. 16w + 15 and all 64
+// lags (4 blocks of 16) for the 3 nu: 12 accumulators; lane l's register i of
+// an accumulator is row 4i + l / 16, lag l % 16 of its block.  Steps past the
+// block's end are staged as zeros, so every 4-step product is complete.
 constexpr int CT = 64;   // steps per chunk
 constexpr int CR = 64;   // rows per tile
 constexpr int CL = 64;   // lags per tile
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void corr_body(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
                                           int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
@@ -230,19 +238,17 @@ __device__ __forceinline__ void corr_body(const double* __restrict__ X, int64_t 
                                           const int64_t* __restrict__ t0_dev, int bx, int by) {
   if (t0_dev) t0 = *t0_dev;
   __shared__ double xs[CT][CR + 2];          // xs[t][r]
-  __shared__ double rs[CT + CL][3];          // ring window
+  __shared__ double rs[3][CT + CL + 2];      // ring window, rs[nu][q]
   const int tid = threadIdx.x;
-  const int tt = tid & 15;                   // lag group (consecutive lanes)
-  const int tr = tid >> 4;                   // row group
+  const int lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
   const int64_t r0 = (int64_t)bx * CR;
   const int tau0 = by * CL;
-  double acc[4][4][3];
+  f64x4 acc[4][3];                           // [lag block][nu]
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int lb = 0; lb < 4; ++lb)
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int n = 0; n < 3; ++n) acc[i][k][n] = 0.0;
+    for (int n = 0; n < 3; ++n) acc[lb][n] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   for (int tc = 0; tc < t_count; tc += CT) {
     // stage X rows r0.. (t-major in LDS)
@@ -258,61 +264,48 @@ __device__ __forceinline__ void corr_body(const double* __restrict__ X, int64_t 
     // ring window: q in [0, CT + CL) <-> global time g = t0 + tc - tau0 - (CL - 1) + q
     for (int idx = tid; idx < (CT + CL) * 3; idx += 256) {
       const int q = idx / 3, nu = idx % 3;
-      const int64_t g = t0 + tc - tau0 - (CL - 1) + q;
-      const bool ok = g >= 0 && g < t0 + t_count;
-      const double x = ring[(max(g, (int64_t)0) % ring_len) * 3 + nu];
-      rs[q][nu] = ok ? x : 0.0;
+      const int64_t gt = t0 + tc - tau0 - (CL - 1) + q;
+      const bool ok = gt >= 0 && gt < t0 + t_count;
+      const double x = ring[(max(gt, (int64_t)0) % ring_len) * 3 + nu];
+      rs[nu][q] = ok ? x : 0.0;
     }
     __syncthreads();
-    // lag of slot k: tau = tau0 + 4*tt + k; step j reads q = j + CL - 1 - 4*tt - k
-    double win[4][3];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int n = 0; n < 3; ++n) win[k][n] = rs[CL - 1 - 4 * tt - k][n];
     const int jmax = min(CT, t_count - tc);
-    for (int j = 0; j < jmax; ++j) {
-      double x[4];
+    for (int j0 = 0; j0 < jmax; j0 += 4) {
+      const int j = j0 + g;
+      const double a = xs[j][16 * wave + c];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = xs[j][4 * tr + i];
+      for (int lb = 0; lb < 4; ++lb) {
+        const int q = j + (CL - 1) - (16 * lb + c);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int n = 0; n < 3; ++n) acc[i][k][n] = fma(x[i], win[k][n], acc[i][k][n]);
-#pragma unroll
-      for (int k = 3; k > 0; --k)
-#pragma unroll
-        for (int n = 0; n < 3; ++n) win[k][n] = win[k - 1][n];
-#pragma unroll
-      for (int n = 0; n < 3; ++n) win[0][n] = rs[min(j + CL - 4 * tt, CT + CL - 1)][n];
+        for (int n = 0; n < 3; ++n) acc[lb][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rs[n][q], acc[lb][n], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  // Neumaier update of the thread's 4 rows x 4 lags x 3: every load issues
+  // Neumaier update of the lane's 4 rows x 4 lags x 3: every load issues
   // from a clamped in-range address, only the stores are conditional
-  const int taub = tau0 + 4 * tt;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t r = r0 + 4 * tr + i;
+    const int64_t r = r0 + 16 * wave + 4 * i + g;
     const int64_t rc = min(r, R3 - 1);
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
       double sm[4], cp[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int64_t o = (rc * 3 + n) * L + min(taub + k, L - 1);
-        sm[k] = csum[o];
-        cp[k] = ccomp[o];
+      for (int lb = 0; lb < 4; ++lb) {
+        const int64_t o = (rc * 3 + n) * L + min(tau0 + 16 * lb + c, L - 1);
+        sm[lb] = csum[o];
+        cp[lb] = ccomp[o];
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        neumaier_add(sm[k], cp[k], acc[i][k][n]);
-        if (r < R3 && taub + k < L) {
-          const int64_t o = (r * 3 + n) * L + taub + k;
-          csum[o] = sm[k];
-          ccomp[o] = cp[k];
+      for (int lb = 0; lb < 4; ++lb) {
+        const int tau = tau0 + 16 * lb + c;
+        neumaier_add(sm[lb], cp[lb], acc[lb][n][i]);
+        if (r < R3 && tau < L) {
+          const int64_t o = (r * 3 + n) * L + tau;
+          csum[o] = sm[lb];
+          ccomp[o] = cp[lb];
         }
       }
     }
