@@ -8,7 +8,11 @@ before the timed region.
 
 Metric: atom*mode*steps/s = N_atoms * N_modes * (MD steps processed) / time.
 
-Prints one JSON line (see the design notes for the field definitions).
+Prints one JSON line: the metric, its value and unit, steps and warm-up, the
+workload's configuration, the roofline of the dominant kernel (achieved
+algorithmic FLOP/s or bytes/s against the MI355X peak, and the HBM bytes per
+launch from the rocprofv3 summary while its kernel sources are unchanged) and
+the FP64 oracle timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -366,8 +370,8 @@ def main():
                     help="GiB copied by a plain device copy before the workload (to calibrate HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design "
-              "note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
+              "implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -62,7 +62,7 @@ typedef enum {
   MHC_ERR_STATE = 2,        /* call not allowed in the context's state      */
   MHC_ERR_OOM = 3,          /* device or host allocation failed             */
   MHC_ERR_HIP = 4,          /* HIP runtime error (sticky)                   */
-  MHC_ERR_UNSUPPORTED = 5,  /* valid request this build does not implement  */
+  MHC_ERR_UNSUPPORTED = 5,  /* valid request the library does not implement */
   MHC_ERR_NONFINITE = 6     /* non-finite input found (check_finite = 1)    */
 } mhc_status;
 

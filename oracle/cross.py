@@ -15,7 +15,7 @@ modal current where Eq. 17 has the total current:
     C[tau, b, b2, mu, nu] = <J_b^mu(t + tau) J_b2^nu(t)>,
 
 with the time-origin average, lag direction and origin count of
-``oracle.modal.gkma_correlation`` (readings listed in the design notes).
+``oracle.modal.gkma_correlation`` (the readings stated there).
 With every mode binned and a complete basis, the sum over b2 is the Eq. 17
 integrand, since the binned currents then sum to the Eq. 10 total.
 """

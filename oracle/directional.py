@@ -19,7 +19,7 @@ virial bracket to the nu column of W_i and the nu component of e_{i,n}:
 so that sum_nu J_n^{mu nu} = J_n^mu.  The total of Eq. 10 splits alike:
 J^{mu nu}(s) = sum_i W_i^{mu nu}(s) v_i^nu(s).
 
-Readings (listed in the design notes):
+Readings:
   * nu is the second virial index, the one contracted with the motion
     (Eq. 10 convention of ``oracle.modal``).
   * The GKMA correlation of a split current keeps the total current whole:

@@ -20,7 +20,7 @@ Array conventions (the paper uses none; these are this project's):
   bins   [M]          bin index of each mode, -1 = mode excluded
 Outputs carry the Cartesian index mu of the heat current.
 
-Readings where the paper is silent (each is listed in the design notes):
+Readings where the paper is silent:
   * e* = e: only real bases are used (Eq. 13).
   * (W . v)^mu = sum_nu W^{mu nu} v^nu, i.e. the virial's first index is the
     heat-current direction (Eq. 8 defines W_i as r_ij (outer) dU_j/dr_ji and

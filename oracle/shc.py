@@ -8,7 +8,7 @@ does, and it imports nothing from the library.
 Array conventions as in ``oracle.modal``: v [S, N, 3], W [S, N, 3, 3] with
 W[s, i, mu, nu] = W_i^{mu nu}.
 
-Readings where the paper is silent (each is listed in the design notes):
+Readings where the paper is silent:
   * Eq. 21 uses the virial convention of Eq. 10, (W . v)^mu = sum_nu W^{mu nu}
     v^nu, so that K(0) is the Eq. 10 current, as the paper states.
   * The virial is taken at the time origin and the velocity at the later time,

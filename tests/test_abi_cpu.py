@@ -160,3 +160,14 @@ int main() {
                     str(src), lib, "-Wl,-rpath," + os.path.dirname(lib), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     assert out == ["0", "0", "0", "1", "1", "1"]
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus above 1 exits with status 2 and a message, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in (r.stdout + r.stderr)
