@@ -171,3 +171,19 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in (r.stdout + r.stderr)
+
+
+def test_c_abi_driver_builds(tmp_path):
+    """tests/c/abi_run.c (the C99 program the GPU test runs through the ABI)
+    compiles with -Wall -Werror and links against the library."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib = _lib.library_path()
+    subprocess.run([gcc, "-std=c99", "-O2", "-Wall", "-Werror", "-I", os.path.join(root, "include"),
+                    os.path.join(root, "tests", "c", "abi_run.c"), lib, "-Wl,-rpath," + os.path.dirname(lib),
+                    "-o", str(tmp_path / "abi_run")], check=True)
+    assert (tmp_path / "abi_run").exists()
