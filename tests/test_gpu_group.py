@@ -59,7 +59,7 @@ def _read(h, methods):
 
 @pytest.mark.parametrize("prec,graph,autotune,host", [(BF16X3, True, False, False), (BF16X3, True, True, False),
                                                       (FP32, False, True, False), (FP8X3, True, True, False),
-                                                      (BF16X3, True, False, True)])
+                                                      (BF16X3, True, False, True), (FP8, True, False, False)])
 def test_group_matches_single_pushes(cases, prec, graph, autotune, host):
     """host: the group is fed host arrays (staged copies), the single systems device tensors."""
     import torch
@@ -94,7 +94,8 @@ def test_group_matches_single_pushes(cases, prec, graph, autotune, host):
     info = grp.info()
     log(f"group_p{prec}_g{int(graph)}_a{int(autotune)}_h{int(host)}", **info)
     # oracle parity of every system after the whole run
-    tol = 1e-2 if prec == FP8X3 else TOL[prec]
+    # single-term e4m3 is bounded loosely, as in the single-context tests (it is not expected to meet 1e-2)
+    tol = {FP8X3: 1e-2, FP8: 0.15}.get(prec) or TOL[prec]
     for i, (case, (_, methods)) in enumerate(zip(cases, SYSTEMS)):
         ref = case.oracle(11, corr_len=20 if methods & GKMA else 0)
         got = _read(grouped[i], methods)
