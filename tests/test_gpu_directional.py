@@ -91,7 +91,8 @@ def test_hnema_split(dense, prec, T, sched):
     assert e["rel_total_dir"] <= 1e-12 and e["rel_total"] <= 1e-12
 
 
-@pytest.mark.parametrize("prec,T,sched", [(FP32, 1, 0), (BF16X3, 64, 1), (BF16X3, 128, 3), (FP8X3, 64, 2)])
+@pytest.mark.parametrize("prec,T,sched", [(FP32, 1, 0), (BF16X3, 64, 1), (BF16X3, 128, 3), (FP8X3, 64, 2),
+                                          (FP8, 128, 0)])
 def test_gkma_split(dense, prec, T, sched):
     announce(f"directional gkma prec={prec} T={T} sched={sched}")
     L, dt = 30, 0.5
