@@ -158,6 +158,17 @@ def test_shc_invalid_arguments():
         h.spectrum([0.0], -1.0)
     with pytest.raises(MhcError):
         h.spectrum([float("nan")], 1.0)
+    # before any sample, and after an empty push: S = 0 and every lag zero
+    K, n = h.read()
+    assert n == 0 and not K.any()
+    v, W = _inputs(10, 3, seed=3)
+    h.push(v[:0], W[:0])
+    K, n = h.read()
+    assert n == 0 and not K.any()
+    h.push(v, W)
+    K, n = h.read()
+    assert n == 3 and rel(K, oracle.shc_correlation(v, W, 8)) <= TOL
+    assert not K[3:].any()
     h.close()
 
 
