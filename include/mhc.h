@@ -218,6 +218,28 @@ mhc_status mhc_finalize(mhc_ctx *ctx);
  * host input holds NaN/Inf; nothing is pushed), OOM, HIP. */
 mhc_status mhc_push(mhc_ctx *ctx, int32_t n_steps, const float *v, const float *W, int on_device);
 
+/* Allocation-free push, for callers that cannot allocate memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same inputs, work and results as mhc_push with on_device = 1 (device
+ * pointers only; they must stay valid until the queued work completes), and
+ * the same work split, so the same bits.  It calls no allocating routine
+ * (no hipMalloc / hipFree, no event or stream creation): everything the
+ * context needs was allocated by mhc_finalize, and the T-batched
+ * contraction's workspace (the partial tiles of the split and stream-K
+ * schedules and the split's arrival counters) is a static device array of
+ * the library instead of the context's own, 128 MiB + 1 KiB (two 256 KiB
+ * partial tiles per compute unit, for at most 256 compute units).  Each
+ * device the library is loaded on holds its own copy until the process ends.
+ * Every call on one device shares that copy, and each call clears the
+ * counters (with a kernel) before its first contraction: calls queued on one
+ * stream are ordered and safe, but two calls whose work overlaps on the same
+ * device (other streams, other contexts in flight) race and give wrong
+ * results.  Kernel timing (mhc_set_timing) is not recorded for these calls.
+ * Errors: as mhc_push; UNSUPPORTED when the device has more than 256 compute
+ * units (its workspace would not fit the array); HIP if the array's device
+ * address cannot be obtained. */
+mhc_status mhc_push_noalloc(mhc_ctx *ctx, int32_t n_steps, const float *v, const float *W);
+
 /* Wait for all queued work of the context. Errors: HIP. */
 mhc_status mhc_synchronize(mhc_ctx *ctx);
 

@@ -70,6 +70,7 @@ def library():
         "mhc_load_eigvec_rows": (i32, [vp, i64, i64, vp, C.c_int]),
         "mhc_finalize": (i32, [vp]),
         "mhc_push": (i32, [vp, i32, vp, vp, C.c_int]),
+        "mhc_push_noalloc": (i32, [vp, i32, vp, vp]),
         "mhc_synchronize": (i32, [vp]),
         "mhc_read_hnema": (i32, [vp, vp, vp, P(i64)]),
         "mhc_read_gkma": (i32, [vp, vp, vp, vp, P(i64)]),
@@ -265,6 +266,15 @@ class ModalHC:
             assert vv.shape[0] == WW.shape[0] and vv.size == vv.shape[0] * self.n_atoms * 3
             assert WW.size == WW.shape[0] * self.n_atoms * 9
             self._check(self._lib.mhc_push(self._h, vv.shape[0], _ptr(vv), _ptr(WW), 0), "push")
+
+    def push_noalloc(self, v, W):
+        """mhc_push_noalloc: v [S, N, 3] and W [S, N, 3, 3] float32 torch tensors on the context's device."""
+        assert _is_torch(v) and _is_torch(W) and v.is_cuda and W.is_cuda
+        assert v.is_contiguous() and W.is_contiguous() and v.element_size() == 4 and W.element_size() == 4
+        assert v.shape[0] == W.shape[0] and v.numel() == v.shape[0] * self.n_atoms * 3
+        assert W.numel() == W.shape[0] * self.n_atoms * 9
+        self._use(v, W)
+        self._check(self._lib.mhc_push_noalloc(self._h, v.shape[0], _ptr(v), _ptr(W)), "push_noalloc")
 
     def synchronize(self):
         self._check(self._lib.mhc_synchronize(self._h), "synchronize")

@@ -25,9 +25,48 @@
 
 using namespace mhc;
 
+// Scratch of mhc_push_noalloc: the T-batched contraction's partial tiles (two
+// 256-thread x 256-float tiles per compute unit, for up to 256 CUs) followed
+// by the split schedule's arrival counters (one int per CU).  One copy per
+// device, held until the process ends.  Host code never passes this name to a
+// kernel (on the host it is only a stand-in for the symbol); it uses the
+// device address from hipGetSymbolAddress instead.
+#define MHC_NOALLOC_MAX_CU 256
+#define MHC_NOALLOC_WS_FLOATS ((size_t)MHC_NOALLOC_MAX_CU * 2 * 256 * 256)
+#define MHC_NOALLOC_SCRATCH_BYTES (MHC_NOALLOC_WS_FLOATS * 4 + (size_t)MHC_NOALLOC_MAX_CU * 4)
+static __device__ __align__(256) unsigned char scratch[MHC_NOALLOC_SCRATCH_BYTES];
+
+// Clears the arrival counters in the scratch before a push: a kernel rather
+// than a memset, so that the call can be captured in a HIP graph.
+__global__ void k_zero_ints(int* __restrict__ p, int n) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = 0;
+}
+
 namespace {
 
 thread_local std::string g_create_error;
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current.
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;
+
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_addr[device] = p;
+  *out = p;
+  return hipSuccess;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -738,18 +777,30 @@ static mhc_status timing_begin(mhc_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1) {
   return MHC_OK;
 }
 
+// Workspace of the T-batched contraction: partial tiles of the split and
+// stream-K schedules and the split's arrival counters (zero between launches).
+struct Workspace {
+  float* ws = nullptr;
+  int64_t ws_floats = 0;
+  int* cnt = nullptr;
+};
+
+static Workspace ctx_workspace(const mhc_ctx* ctx) { return {ctx->d_ws, ctx->ws_floats, ctx->d_tile_cnt}; }
+
 // One block of t_count steps: front, contraction, back; with the
 // motion-direction split, one such pass per direction (the contraction is
-// the same kernel on the masked operand).
-static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_count) {
+// the same kernel on the masked operand).  timed = false skips the event
+// timing (which creates events on first use).
+static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_count, const Workspace& wk,
+                            bool timed = true) {
   const auto& c = ctx->cfg;
   const bool gk = c.methods & MHC_GKMA;
   mhc_status st;
   for (int d = 0; d < ctx->n_dir; ++d) {
     const int dir = ctx->n_dir > 1 ? d : -1;
     if ((st = block_front(ctx, v, W, t_count, nullptr, dir))) return st;
-    hipEvent_t e0, e1;
-    if ((st = timing_begin(ctx, &e0, &e1))) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed && (st = timing_begin(ctx, &e0, &e1))) return st;
     int n_parts = 0;
     if (c.t_block == 1) {
       HIP_TRY(launch_gemv_f32(ctx->stream, reinterpret_cast<const float*>(ctx->dE),
@@ -759,8 +810,8 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
       n_parts = t_count;
     } else {
       HIP_TRY(launch_gemm(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->K_pad, ctx->t_pad / 32,
-                          ctx->dJ, gk ? 1 : 0, &n_parts, ctx->d_ws, ctx->ws_floats, ctx->d_tile_cnt, ctx->n_cu,
-                          c.schedule, ctx->d_rowscale, ctx->d_colscale, &ctx->last_sched),
+                          ctx->dJ, gk ? 1 : 0, &n_parts, wk.ws, wk.ws_floats, wk.cnt, ctx->n_cu, c.schedule,
+                          ctx->d_rowscale, ctx->d_colscale, &ctx->last_sched),
               "batched contraction");
     }
     if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
@@ -817,7 +868,8 @@ mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* 
   if (on_device) {
     for (int32_t s0 = 0; s0 < n_steps; s0 += ctx->chunk) {
       const int tc = std::min(ctx->chunk, n_steps - s0);
-      if ((st = run_block(ctx, v + (int64_t)s0 * N * 3, W + (int64_t)s0 * N * 9, tc))) return st;
+      if ((st = run_block(ctx, v + (int64_t)s0 * N * 3, W + (int64_t)s0 * N * 9, tc, ctx_workspace(ctx))))
+        return st;
     }
     return MHC_OK;
   }
@@ -825,7 +877,7 @@ mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* 
     // one block: copy and kernels in order on the context stream
     HIP_TRY(hipMemcpyAsync(ctx->d_v, v, (size_t)n_steps * N * 3 * 4, hipMemcpyHostToDevice, ctx->stream), "copy v");
     HIP_TRY(hipMemcpyAsync(ctx->d_W, W, (size_t)n_steps * N * 9 * 4, hipMemcpyHostToDevice, ctx->stream), "copy W");
-    if ((st = run_block(ctx, ctx->d_v, ctx->d_W, n_steps))) return st;
+    if ((st = run_block(ctx, ctx->d_v, ctx->d_W, n_steps, ctx_workspace(ctx)))) return st;
     HIP_TRY(hipStreamSynchronize(ctx->stream), "push sync");
     return MHC_OK;
   }
@@ -849,7 +901,7 @@ mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* 
                            ctx->copy_stream), "copy W");
     HIP_TRY(hipEventRecord(ctx->ev_copied[b], ctx->copy_stream), "event record");
     HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->ev_copied[b], 0), "stream wait");
-    if ((st = run_block(ctx, sv[b], sW[b], tc))) {
+    if ((st = run_block(ctx, sv[b], sW[b], tc, ctx_workspace(ctx)))) {
       (void)hipStreamSynchronize(ctx->copy_stream);     // the caller may reuse v and W on return
       return st;
     }
@@ -857,6 +909,41 @@ mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* 
   }
   // every copy precedes a kernel the context stream waited for
   HIP_TRY(hipStreamSynchronize(ctx->stream), "push sync");
+  return MHC_OK;
+}
+
+mhc_status mhc_push_noalloc(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* W) {
+  mhc_status st = enter(ctx);
+  if (st) return st;
+  if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "push needs a finalized context");
+  if (n_steps < 0) return fail(ctx, MHC_ERR_INVALID_ARG, "n_steps < 0");
+  if (n_steps == 0) return MHC_OK;
+  if (!v || !W) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL v or W");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  Workspace wk{};
+  if (ctx->cfg.t_block > 1) {
+    // the same workspace size the context's own push uses, so that both take
+    // the same work split and give the same bits
+    if (ctx->n_cu > MHC_NOALLOC_MAX_CU)
+      return fail(ctx, MHC_ERR_UNSUPPORTED,
+                  "mhc_push_noalloc: the device has " + std::to_string(ctx->n_cu) +
+                      " compute units; its scratch holds the contraction workspace of at most " +
+                      std::to_string(MHC_NOALLOC_MAX_CU) + " (" + std::to_string(MHC_NOALLOC_SCRATCH_BYTES) +
+                      " bytes)");
+    void* base = nullptr;
+    HIP_TRY(scratch_address(ctx->device, &base), "hipGetSymbolAddress(scratch)");
+    wk.ws = reinterpret_cast<float*>(base);
+    wk.ws_floats = (int64_t)ctx->n_cu * 2 * 256 * 256;
+    wk.cnt = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(base) + MHC_NOALLOC_WS_FLOATS * 4);
+    // the scratch keeps whatever the last call on this device left in it
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(MHC_NOALLOC_MAX_CU), 0, ctx->stream, wk.cnt, MHC_NOALLOC_MAX_CU);
+    HIP_TRY(hipGetLastError(), "clear scratch counters");
+  }
+  const int64_t N = ctx->N;
+  for (int32_t s0 = 0; s0 < n_steps; s0 += ctx->chunk) {
+    const int tc = std::min(ctx->chunk, n_steps - s0);
+    if ((st = run_block(ctx, v + (int64_t)s0 * N * 3, W + (int64_t)s0 * N * 9, tc, wk, false))) return st;
+  }
   return MHC_OK;
 }
 
@@ -1780,7 +1867,7 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
       mhc_ctx* c = g->sys[i];
       GHIP_TRY(hipMemcpyAsync(c->d_v, v[i] + (int64_t)s0 * c->N * 3, (size_t)tc * c->N * 3 * 4, kind, g->stream), "v");
       GHIP_TRY(hipMemcpyAsync(c->d_W, W[i] + (int64_t)s0 * c->N * 9, (size_t)tc * c->N * 9 * 4, kind, g->stream), "W");
-      mhc_status st = run_block(c, c->d_v, c->d_W, tc);
+      mhc_status st = run_block(c, c->d_v, c->d_W, tc, ctx_workspace(c));
       if (st) return gfail(g, st, c->err);
     }
   }
