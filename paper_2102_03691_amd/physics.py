@@ -5,7 +5,8 @@ along one axis kappa_b^{mu x} = <J_b^mu> / (T V F_e).
 Eq. 17: kappa_b^{mu nu}(tau) = G_b^{mu nu}(tau) / (k_B T^2 V), G the running
 integral of the modal-current / total-current correlation.
 Eq. 23: kappa(omega) = 2 K~(omega) / (V T F_e), K~ the transform of the SHC
-virial-velocity correlation (eV A/fs integrated over fs: eV A).
+virial-velocity correlation (eV A/fs integrated over fs: eV A), a density per
+unit of frequency f = omega / (2 pi).
 Units: eV, Angstrom, fs, K in; W/(m K) out.
 """
 KB_EV_PER_K = 8.617333262e-5
@@ -24,8 +25,13 @@ def gkma_kappa(integral, temperature, volume_a3):
 
 def shc_kappa(Kw, temperature, volume_a3, fe_per_a):
     """Spectral kappa per unit of frequency (W m^-1 K^-1 THz^-1) from the SHC
-    transform K~(omega) (eV A) for a drive F_e (1/A): Eq. 23 gives kappa per
-    unit of angular frequency, and kappa(f) = 2 pi kappa(omega)."""
-    import math
-    per_omega = 2.0 * Kw / (volume_a3 * temperature * fe_per_a)          # eV / (A K) per (rad / s)
-    return per_omega * (1.602176634e-19 / 1e-10) * 2.0 * math.pi * 1e12
+    transform K~(omega) (eV A) for a drive F_e (1/A).
+
+    Eq. 23's kappa(omega) = 2 K~(omega) / (V T F_e) is a density in
+    d omega / (2 pi) = d f: K~ is even in omega and integrates over
+    d omega / (2 pi) to K(0), the time average of the Eq. 10 current, so
+    int_0^inf kappa(omega) d f = K(0) / (V T F_e), the HNEMD total.  In
+    eV / (A K) it is already per hertz of f (1 eV / (A K) = 1.602e-9 J / (m K)
+    = 1.602e-9 W m^-1 K^-1 Hz^-1); times 1e12 per THz."""
+    per_hz = 2.0 * Kw / (volume_a3 * temperature * fe_per_a)             # eV / (A K)
+    return per_hz * (1.602176634e-19 / 1e-10) * 1e12

@@ -139,10 +139,29 @@ def test_mutation_rectangle_rule_fails_the_closed_form():
 
 
 def test_package_shc_kappa_units():
-    """1 eV A over 1 A^3, 1 K, 1/A: 2 eV/(A K) per rad/s = 3.204e-9 J/(m K s^-1);
-    per THz of f = omega / (2 pi): times 2 pi 1e12."""
+    """1 eV A over 1 A^3, 1 K, 1/A: 2 eV/(A K) = 3.204e-9 J/(m K) per hertz of
+    f; times 1e12 per THz."""
     from paper_2102_03691_amd.physics import shc_kappa
-    assert math.isclose(shc_kappa(1.0, 1.0, 1.0, 1.0), 2 * 1.602176634e-9 * 2 * math.pi * 1e12, rel_tol=1e-15)
+    assert math.isclose(shc_kappa(1.0, 1.0, 1.0, 1.0), 2 * 1.602176634e-9 * 1e12, rel_tol=1e-15)
+
+
+def test_package_shc_kappa_sum_rule():
+    """The spectral kappa integrates over f to the HNEMD total: Eq. 21 at lag 0
+    is the time average of the Eq. 10 current, so int_0^{f_Nyquist} kappa(f) df
+    equals hnema_kappa(K(0)) (Eq. 19 with the same T, V, F_e).  K is an
+    exponential sampled every fs; the transform of the sampled lags has
+    int_0^{pi/dt} K~ d omega / pi = c_0 K(0) exactly, and a trapezoid over
+    omega with N panels integrates cos(omega tau dt) exactly for tau < 2N."""
+    from paper_2102_03691_amd.physics import hnema_kappa, shc_kappa
+    dt, n, T, V, Fe = 1.0, 400, 300.0, 1.7e4, 2e-4
+    K = np.exp(-np.arange(n) / 37.0)[:, None] * np.array([[0.8, -0.1, 0.05]])
+    n_panels = 4000
+    omega = np.linspace(0.0, np.pi / dt, n_panels + 1)          # rad per fs, up to Nyquist
+    Kw = oracle.shc_spectrum(K, dt, omega)
+    f_thz = omega / (2 * np.pi) * 1e3                           # 1/fs -> THz
+    dens = shc_kappa(Kw, T, V, Fe)
+    total = ((dens[1:] + dens[:-1]) * 0.5 * np.diff(f_thz)[:, None]).sum(axis=0)
+    assert np.allclose(total, hnema_kappa(K[0], T, V, Fe), rtol=1e-11, atol=0)
 
 
 # ------------------------------------------------------- motion-direction split
