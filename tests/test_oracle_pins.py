@@ -80,6 +80,29 @@ def test_gkma_lags_golden():
     np.testing.assert_array_equal(oracle.correlation_counts(S, L), [4, 3, 2, 1, 0])
 
 
+def test_hnema_average_golden():
+    """Eq. 19 numerator on the hand-worked series: the mean over all S samples
+    (an S - 1 denominator or a dropped sample gives another fraction)."""
+    g = _golden.read("gkma_lags.txt")
+    Jb = np.array([_f(x) for x in g["Jb"][0]])
+    Jt = np.array([_f(x) for x in g["Jt"][0]])
+    S = Jb.size
+    Jb3 = np.zeros((S, 3, 2))
+    Jb3[:, 1, 0] = Jb
+    Jb3[:, 2, 1] = Jt
+    avg = oracle.hnema_average(Jb3)
+    want = np.zeros((2, 3))
+    want[0, 1] = _f(g["mean_Jb"][0][0])
+    want[1, 2] = _f(g["mean_Jt"][0][0])
+    np.testing.assert_array_equal(avg, want)
+
+
+def test_mutation_hnema_sample_count_fails_golden():
+    g = _golden.read("gkma_lags.txt")
+    Jb = np.array([_f(x) for x in g["Jb"][0]])
+    assert Jb.sum() / (Jb.size - 1) != _f(g["mean_Jb"][0][0])
+
+
 def test_single_atom_identity_basis_brute_force():
     """N = 1: the basis is the identity, masses cancel, J_alpha^mu = W^{mu alpha} v^alpha."""
     E = synth.BlochLattice((1, 1, 1)).eig_matrix()
