@@ -10,9 +10,12 @@ Metric: atom*mode*steps/s = N_atoms * N_modes * (MD steps processed) / time.
 
 Prints one JSON line: the metric, its value and unit, steps and warm-up, the
 workload's configuration, the roofline of the dominant kernel (achieved
-algorithmic FLOP/s or bytes/s against the MI355X peak, and the HBM bytes per
-launch from the rocprofv3 summary while its kernel sources are unchanged) and
-the FP64 oracle timed on the host's cores.
+algorithmic FLOP/s or bytes/s against the MI355X peak -- 24 FLOP per
+atom*mode*step, the method's own work; the split precisions issue three
+products, reported beside it as frac_issued -- and the HBM bytes per launch
+from the rocprofv3 summary while its kernel sources are unchanged), the
+relative error of one seeded block of the same workload against the FP64
+oracle, and the FP64 oracle timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -60,6 +63,13 @@ PEAK_FP8_FLOPS = 5.0e15
 SHC_WORKLOADS = {"shc8000_l250_t256": (8000, 250, 256, 40)}     # atoms, lags, T, default blocks
 SHC_METRIC = "spectral heat current atom*lag*steps/s (float64 virial-velocity correlation)"
 PEAK_FP64_FLOPS = 78.6e12
+
+
+# Algorithmic work of the modal current per atom*mode*step: 3 FMAs of the
+# projection (Eq. 13) and 9 of the virial bracket (Eq. 16).  The split
+# precisions (split-BF16, e4m3 hi/lo) issue three products of that size.
+FLOP_PER_UNIT = 24.0
+ISSUED_PER_UNIT = {0: 24.0, 1: 72.0, 2: 24.0, 3: 72.0}
 
 
 def log(msg):
@@ -208,6 +218,54 @@ def cpu_baseline_one_core(dims, t_block, nb, budget_s=6.0, bins=None):
     return r
 
 
+def _rel(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def lattice_reference(lat, m, v, W, nb, methods, L):
+    """The FP64 oracle's binned currents (FFT form, exact for the plane-wave
+    basis) of seeded inputs, and its HNEMA average / GKMA correlation."""
+    import oracle
+    kb = oracle.bin_of_mode(lat.kpoint_frequencies().ravel(), nb, 0.0, lat.f_max).reshape(lat.dims)
+    Jb = oracle.binned_current_fft(lat.dims, m, v, W, kb, nb)
+    ref = {}
+    if methods & 1:
+        ref["hnema"] = oracle.hnema_average(Jb)
+    if methods & 2:
+        ref["corr"] = oracle.gkma_correlation(Jb, oracle.total_heat_current(v, W), L)
+    return ref
+
+
+def library_errors(h, ref):
+    out = {}
+    if "hnema" in ref:
+        out["hnema"] = _rel(h.read_hnema()[0], ref["hnema"])
+    if "corr" in ref:
+        out["corr"] = _rel(h.read_gkma()["corr"], ref["corr"])
+    return out
+
+
+def accuracy_vs_oracle(h, lat, m, methods, nb, L, steps):
+    """Relative L2 error of the timed context on one seeded block: the context
+    is reset, fed ``steps`` seeded MD steps (device inputs) and read; the
+    reference is the FP64 oracle on the same float32 inputs."""
+    import torch
+    import synth
+    h.reset()
+    v, W = synth.gen_steps(7, m, 0, steps)
+    h.push(torch.as_tensor(v, device="cuda:0"), torch.as_tensor(W, device="cuda:0"))
+    h.synchronize()
+    out = library_errors(h, lattice_reference(lat, m, v, W, nb, methods, L))
+    out.update(oracle="binned_current_fft (FFT form of the FP64 oracle, exact for the plane-wave basis)",
+               sample=f"{steps} seeded MD steps (float32 inputs) through the timed context after a reset",
+               norm="relative L2 per output array")
+    return out
+
+
 def run_shc(args):
     """SHC virial-velocity correlation (Eq. 21) in float64, inputs resident in HBM."""
     import torch
@@ -234,6 +292,15 @@ def run_shc(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launches, kms = h.kernel_timing()
+    acc = None
+    if not args.no_cpu_baseline:
+        log("accuracy: one seeded block against the FP64 oracle")
+        h.reset()
+        vc, Wc = synth.gen_steps(7, m, 0, T)
+        h.push(torch.as_tensor(vc, device="cuda:0"), torch.as_tensor(Wc, device="cuda:0"))
+        acc = {"K": _rel(h.read()[0], oracle.shc_correlation(vc, Wc, L)),
+               "oracle": "shc_correlation (FP64)", "sample": f"{T} seeded samples after a reset",
+               "norm": "relative L2 per output array"}
     h.close()
     units_per_block = float(N) * L * T
     avg_ms = kms / max(launches, 1)
@@ -251,6 +318,8 @@ def run_shc(args):
            "config": {"workload": args.workload, "atoms": N, "lags": L, "md_steps_per_step": T, "t_block": T,
                       "precision": "float32 inputs, products and sums in float64", "parallelism": "single GPU"},
            "roofline": roof}
+    if acc is not None:
+        out["rel_err_vs_oracle"] = acc
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         vc, Wc = synth.gen_steps(0, m, 0, T)
@@ -280,7 +349,7 @@ def run_group(args, prec):
     batch = synth.uneven_batch(0)
     stream = torch.cuda.Stream()
     handle = stream.cuda_stream
-    systems, inputs, units_per_block = [], [], 0.0
+    systems, inputs, units_per_block, lats = [], [], 0.0, []
     log(f"uneven batch: edges {[e for e, _ in batch]}, methods {[m for _, m in batch]}")
     n_blocks = None
     for i, (edge, meth) in enumerate(batch):
@@ -299,6 +368,7 @@ def run_group(args, prec):
         torch.cuda.synchronize()
         h.finalize()
         systems.append(h)
+        lats.append((lat, m, methods))
         units_per_block += float(lat.n_atoms) * M * GROUP_T
         if n_blocks is None:
             n_blocks = max(1, min(K + args.warmup, 8))
@@ -328,14 +398,34 @@ def run_group(args, prec):
     launches, kms = grp.kernel_timing()
     grp.set_timing(False)
     avg_ms = kms / max(launches, 1)
-    flop_per_unit = {0: 24.0, 1: 72.0, 2: 24.0, 3: 72.0}[prec]
     peak = {0: PEAK_FP32_MFMA_FLOPS, 1: PEAK_BF16_FLOPS, 2: PEAK_FP8_FLOPS, 3: PEAK_FP8_FLOPS}[prec]
-    achieved = flop_per_unit * units_per_block / (avg_ms * 1e-3)
+    achieved = FLOP_PER_UNIT * units_per_block / (avg_ms * 1e-3)
+    issued = ISSUED_PER_UNIT[prec] * units_per_block / (avg_ms * 1e-3)
     roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": profiled_traffic(args.workload, "k_gemm_group"),
+            "frac": achieved / peak, "work": "24 FLOP per atom*mode*step (Eq. 13: 3 FMAs; Eq. 16 bracket: 9 FMAs)",
+            "achieved_issued": issued / 1e12, "frac_issued": issued / peak,
+            "traffic": profiled_traffic(args.workload, "k_gemm_group"),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "kernel": "k_gemm_group", "avg_launch_ms": avg_ms,
             "launches": launches, "tile_shape": info["tile_shape"], "autotuned_ms": info["tuned_ms"]}
+    acc = None
+    if not args.no_cpu_baseline:
+        # one grouped block of seeded inputs against the oracle, per system
+        log("accuracy: one seeded grouped block against the FP64 oracle")
+        for h in systems:
+            h.reset()
+        host = [synth.gen_steps(200 + i, m, 0, GROUP_T) for i, (_, m, _) in enumerate(lats)]
+        grp.push([torch.as_tensor(v, device="cuda:0") for v, _ in host],
+                 [torch.as_tensor(W, device="cuda:0") for _, W in host])
+        torch.cuda.synchronize()
+        worst = {}
+        for h, (lat, m, meth), (v, W) in zip(systems, lats, host):
+            for k, e in library_errors(h, lattice_reference(lat, m, v, W, GROUP_NB, meth, GROUP_L)).items():
+                worst[k] = max(worst.get(k, 0.0), e)
+        acc = {**{f"{k}_worst_system": e for k, e in worst.items()},
+               "oracle": "binned_current_fft (FFT form of the FP64 oracle, exact for the plane-wave basis)",
+               "sample": f"one grouped block of {GROUP_T} seeded MD steps per system after a reset",
+               "norm": "relative L2 per output array"}
     grp.close()
     for h in systems:
         h.close()
@@ -351,7 +441,7 @@ def run_group(args, prec):
                        "launch": "grouped persistent contraction, "
                                  + ("eager launches" if args.no_graph else "HIP graph replay") + ", autotuned tile shape",
                        "parallelism": "single GPU"},
-            "roofline": roof}
+            "roofline": roof, **({"rel_err_vs_oracle": acc} if acc is not None else {})}
 
 
 def main():
@@ -363,7 +453,8 @@ def main():
                     choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS) + sorted(SHC_WORKLOADS))
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline timing and the accuracy check of one seeded block)")
     ap.add_argument("--no-fp32-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="grouped workloads: launch each block eagerly")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -412,14 +503,13 @@ def main():
     value = units / wall
     avg_ms = kms / max(launches, 1)
     units_per_launch = float(N) * M * md_per_step
-    if prec == 1:
-        flops = 72.0 * units_per_launch          # three bf16 products, 24 FLOP each
-        roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_BF16_FLOPS / 1e12,
-                "unit": "TFLOP/s"}
-    elif t_block > 1:
-        flops = 24.0 * units_per_launch
-        roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_FP32_MFMA_FLOPS / 1e12,
-                "unit": "TFLOP/s"}
+    if t_block > 1:
+        peak = PEAK_BF16_FLOPS if prec == 1 else PEAK_FP32_MFMA_FLOPS
+        flops = FLOP_PER_UNIT * units_per_launch
+        issued = ISSUED_PER_UNIT[prec] * units_per_launch
+        roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "work": "24 FLOP per atom*mode*step (Eq. 13: 3 FMAs; Eq. 16 bracket: 9 FMAs)",
+                "achieved_issued": issued / (avg_ms * 1e-3) / 1e12, "frac_issued": issued / (avg_ms * 1e-3) / peak}
     else:
         byts = 12.0 * units_per_launch               # E streamed once per MD step: 3 dofs x 4 B per atom*mode
         roof = {"bound": "hbm", "achieved": byts / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_BPS / 1e9, "unit": "GB/s"}
@@ -431,6 +521,14 @@ def main():
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = launches
     del bv, bW, v, W
+    acc = None
+    if not args.no_cpu_baseline:
+        if bins is None:
+            log("accuracy: one seeded block against the FP64 oracle")
+            acc = accuracy_vs_oracle(h, lat, m, methods, nb, L, md_per_step if t_block > 1 else 128)
+        else:
+            acc = {"skipped": "bins of equal mode counts split k-points, which the FFT form of the oracle cannot "
+                              "represent; the dense oracle does not fit this basis"}
     h.close()
     torch.cuda.empty_cache()
 
@@ -449,6 +547,8 @@ def main():
                       + "; fp64 bins and time sums",
                       "parallelism": "single GPU"},
            "roofline": roof}
+    if acc is not None:
+        out["rel_err_vs_oracle"] = acc
 
     if not args.no_fp32_baseline and not (prec == 0 and t_block == 1):
         log("plain per-step FP32 path on the same lattice")
