@@ -74,7 +74,9 @@ typedef enum {
  *           accumulation (the lo*lo term is dropped)
  *   FP8     OCP e4m3 eigenvectors with a float32 scale per mode and e4m3
  *           activations with a float32 scale per (channel, step), one e4m3
- *           product, float32 accumulation (about 1e-2 relative error)
+ *           product, float32 accumulation (about 4-6e-2 relative error on
+ *           random-phase inputs: it misses a 1e-2 accuracy bar; only FP8X3
+ *           meets it)
  *   FP8X3   the same scales, each operand split into e4m3 hi + lo, products
  *           hi*hi + hi*lo + lo*hi (about 1e-3 relative error)
  * FP8 and FP8X3 need t_block > 1.                                          */
@@ -112,7 +114,8 @@ typedef struct {
                             otherwise 32..512 and a multiple of 32 (T-batched GEMM)  */
   int32_t corr_len;      /* GKMA lags L (tau = 0..L-1), 1..65536; ignored for HNEMA  */
   double dt;             /* sample interval for the GKMA integral (> 0)             */
-  int32_t check_finite;  /* 1: mhc_push rejects non-finite v or W (host inputs only) */
+  int32_t check_finite;  /* 1: mhc_push / mhc_group_push reject non-finite v or W
+                            (device inputs: a scan kernel, and the push synchronizes) */
   int32_t schedule;      /* T-batched work split: one of MHC_SCHED_* (below)         */
   int32_t reserved[2];   /* must be zero                                            */
 } mhc_run_config;
@@ -214,8 +217,10 @@ mhc_status mhc_finalize(mhc_ctx *ctx);
  * Steps are processed in blocks of t_block; a trailing partial block is
  * processed as a shorter block, so results do not depend on how a
  * trajectory is split into calls.
- * Errors: INVALID_ARG, STATE (not finalized), NONFINITE (check_finite and a
- * host input holds NaN/Inf; nothing is pushed), OOM, HIP. */
+ * Errors: INVALID_ARG, STATE (not finalized), NONFINITE (check_finite and an
+ * input holds NaN/Inf; nothing is pushed -- for device inputs the check is a
+ * scan kernel whose result is read back, so the call synchronizes the
+ * stream), OOM, HIP. */
 mhc_status mhc_push(mhc_ctx *ctx, int32_t n_steps, const float *v, const float *W, int on_device);
 
 /* Allocation-free push, for callers that cannot allocate memory: code under
@@ -234,7 +239,9 @@ mhc_status mhc_push(mhc_ctx *ctx, int32_t n_steps, const float *v, const float *
  * counters (with a kernel) before its first contraction: calls queued on one
  * stream are ordered and safe, but two calls whose work overlaps on the same
  * device (other streams, other contexts in flight) race and give wrong
- * results.  Kernel timing (mhc_set_timing) is not recorded for these calls.
+ * results.  Kernel timing (mhc_set_timing) is not recorded for these calls,
+ * and check_finite is not applied (its device check reads a flag back, which
+ * a graph capture does not allow).
  * Errors: as mhc_push; UNSUPPORTED when the device has more than 256 compute
  * units (its workspace would not fit the array); HIP if the array's device
  * address cannot be obtained. */
@@ -337,8 +344,12 @@ mhc_status mhc_last_schedule(mhc_ctx *ctx, int32_t *schedule);
  * together: per block of t_block steps the input preparation of every
  * system, ONE persistent contraction launch over the tiles of all systems
  * (work-groups pull tiles largest-first from a queue), and the binning /
- * accumulation of every system.  Results equal pushing each system alone
- * (same arithmetic, same summation order).  The group borrows the contexts:
+ * accumulation of every system.  Results equal pushing each system alone bit
+ * for bit when those single pushes use schedule MHC_SCHED_TILES and the
+ * group keeps its untuned tile shape (no MHC_GROUP_AUTOTUNE); otherwise they
+ * agree to float32 rounding (a single push with AUTO may take the split
+ * schedule, which adds k-pieces in float32, and another tile shape changes
+ * the float32 per-tile step sums of HNEMA).  The group borrows the contexts:
  * they must stay alive, and must not be pushed on their own while a group
  * push is running. */
 typedef struct mhc_group mhc_group;
@@ -363,7 +374,9 @@ const char *mhc_group_last_error(const mhc_group *group);
 /* Push n_steps samples to every system: v[i], W[i] are system i's arrays in
  * the layout of mhc_push (host or device pointers, as on_device says).
  * Full blocks go through the grouped path; a trailing partial block is
- * pushed system by system.  Errors: INVALID_ARG, HIP. */
+ * pushed system by system.  Systems configured with check_finite have their
+ * inputs checked first, as for mhc_push.
+ * Errors: INVALID_ARG, NONFINITE (nothing pushed to any system), HIP. */
 mhc_status mhc_group_push(mhc_group *group, int32_t n_steps, const float *const *v, const float *const *W,
                           int on_device);
 

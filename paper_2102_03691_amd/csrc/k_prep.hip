@@ -465,6 +465,35 @@ hipError_t launch_prep_group(hipStream_t s, int prec, const PrepDesc* d, int n, 
   return hipGetLastError();
 }
 
+// Non-finite scan of n floats: any NaN or Inf stores 1 to *flag (every
+// writer stores the same value, so the unordered stores need no atomic).
+// 16-byte loads where the pointer allows, the ragged ends one float at a time.
+__global__ void __launch_bounds__(256) k_nonfinite(const float* __restrict__ p, int64_t n, int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t head = (int64_t)((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 4;
+  const int64_t h = head < n ? head : n;
+  const int64_t n4 = (n - h) / 4;
+  const float4* q = reinterpret_cast<const float4*>(p + h);
+  bool bad = false;
+  for (int64_t i = tid; i < n4; i += stride) {
+    const float4 x = q[i];
+    bad |= !isfinite(x.x) | !isfinite(x.y) | !isfinite(x.z) | !isfinite(x.w);
+  }
+  if (tid < h) bad |= !isfinite(p[tid]);
+  const int64_t tail = h + 4 * n4;
+  if (tail + tid < n) bad |= !isfinite(p[tail + tid]);
+  if (bad) *flag = 1;
+}
+
+hipError_t launch_nonfinite(hipStream_t s, const float* p, int64_t n, int* flag) {
+  if (n <= 0) return hipSuccess;
+  const int64_t want = (n / 4 + 255) / 256;
+  const unsigned grid = (unsigned)(want < 2048 ? (want < 1 ? 1 : want) : 2048);
+  hipLaunchKernelGGL(k_nonfinite, dim3(grid), dim3(256), 0, s, p, n, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
                              const float* sqrt_m, const float* inv_sqrt_m, int64_t N, int t_count, int t_pad,
                              void* B, int64_t K_pad, double* jt_part, float* col_scale,

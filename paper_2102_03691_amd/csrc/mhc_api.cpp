@@ -147,6 +147,7 @@ struct mhc_ctx {
   double* d_out = nullptr;
   float* d_ws = nullptr;      // partial tiles of the split and stream-K schedules
   int* d_tile_cnt = nullptr;  // arrival counters of the split schedule (zero between launches)
+  int* d_flag = nullptr;      // non-finite flag of the device-input check
   int last_sched = 0;         // schedule the last batched contraction used (MHC_SCHED_*; 0 = none yet)
   int64_t ws_floats = 0;
   int n_cu = 256;
@@ -201,6 +202,16 @@ mhc_status dev_alloc(mhc_ctx* ctx, size_t bytes, void** out, const char* what) {
   ctx->bytes += (int64_t)bytes;
   *out = p;
   return MHC_OK;
+}
+
+// Free the allocations made since allocs.size() was `mark` (a load step that
+// failed part-way leaves the context as it was).
+void rollback_allocs(mhc_ctx* c, size_t mark) {
+  while (c->allocs.size() > mark) {
+    (void)hipFree(c->allocs.back().p);
+    c->bytes -= (int64_t)c->allocs.back().bytes;
+    c->allocs.pop_back();
+  }
 }
 
 void free_all(mhc_ctx* c) {
@@ -409,7 +420,15 @@ mhc_status mhc_configure(mhc_ctx* ctx, const mhc_run_config* cfg) {
 }
 
 // Build the bin-sorted slot order and allocate the basis on the first row load.
+static mhc_status start_rows_impl(mhc_ctx* ctx);
 static mhc_status start_rows(mhc_ctx* ctx) {
+  const size_t mark = ctx->allocs.size();
+  const mhc_status st = start_rows_impl(ctx);
+  if (st) rollback_allocs(ctx, mark);
+  return st;
+}
+
+static mhc_status start_rows_impl(mhc_ctx* ctx) {
   const int64_t M = ctx->M, nb = ctx->nb;
   std::vector<int64_t> count(nb + 1, 0);
   for (int64_t n = 0; n < M; ++n)
@@ -518,10 +537,23 @@ static size_t cross_doubles(const mhc_ctx* c) {
 }
 static size_t bring_doubles(const mhc_ctx* c) { return c->cross ? (size_t)c->nb * c->ring_len * 3 : 0; }
 
+static mhc_status finalize_impl(mhc_ctx* ctx);
+
 mhc_status mhc_finalize(mhc_ctx* ctx) {
   mhc_status st = enter(ctx);
   if (st) return st;
   if (!ctx->rows_started || ctx->finalized) return fail(ctx, MHC_ERR_STATE, "finalize needs loaded rows, once");
+  const size_t mark = ctx->allocs.size();
+  st = finalize_impl(ctx);
+  if (st) {                             // a failed finalize keeps nothing (it may be retried)
+    rollback_allocs(ctx, mark);
+    ctx->finalized = false;
+  }
+  return st;
+}
+
+static mhc_status finalize_impl(mhc_ctx* ctx) {
+  mhc_status st;
   for (int64_t n = 0; n < ctx->M; ++n)
     if (ctx->slot_of_mode[n] >= 0 && !ctx->row_loaded[n])
       return fail(ctx, MHC_ERR_STATE, "eigenvector row " + std::to_string(n) + " was not loaded");
@@ -613,6 +645,9 @@ mhc_status mhc_finalize(mhc_ctx* ctx) {
     }
   }
   if ((st = dev_alloc(ctx, out_doubles * 8, &pout, "read-out"))) return st;
+  void* pflag = nullptr;
+  if ((st = dev_alloc(ctx, 16, &pflag, "non-finite flag"))) return st;
+  ctx->d_flag = reinterpret_cast<int*>(pflag);
   if (c.t_block > 1) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
@@ -851,6 +886,19 @@ static mhc_status host_staging(mhc_ctx* ctx) {
   return MHC_OK;
 }
 
+// check_finite on device inputs: a scan kernel sets the context's flag, which
+// is read back before anything of the push is queued (this synchronizes).
+static mhc_status device_inputs_finite(mhc_ctx* ctx, const float* v, const float* W, int64_t n_steps, bool* ok) {
+  HIP_TRY(launch_fill_i32(ctx->stream, ctx->d_flag, 1, 0), "clear flag");
+  HIP_TRY(launch_nonfinite(ctx->stream, v, n_steps * ctx->N * 3, ctx->d_flag), "non-finite scan");
+  HIP_TRY(launch_nonfinite(ctx->stream, W, n_steps * ctx->N * 9, ctx->d_flag), "non-finite scan");
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "read flag");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "non-finite check sync");
+  *ok = flag == 0;
+  return MHC_OK;
+}
+
 mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* W, int on_device) {
   mhc_status st = enter(ctx);
   if (st) return st;
@@ -865,6 +913,11 @@ mhc_status mhc_push(mhc_ctx* ctx, int32_t n_steps, const float* v, const float* 
       return fail(ctx, MHC_ERR_NONFINITE, "non-finite velocity or virial");
   }
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  if (on_device && ctx->cfg.check_finite) {
+    bool ok = false;
+    if ((st = device_inputs_finite(ctx, v, W, n_steps, &ok))) return st;
+    if (!ok) return fail(ctx, MHC_ERR_NONFINITE, "non-finite velocity or virial (device input)");
+  }
   if (on_device) {
     for (int32_t s0 = 0; s0 < n_steps; s0 += ctx->chunk) {
       const int tc = std::min(ctx->chunk, n_steps - s0);
@@ -1768,6 +1821,20 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
     if (g->sys[i]->sticky) return gfail(g, g->sys[i]->sticky, "system " + std::to_string(i) + " has a HIP error");
   }
   GHIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  // check_finite of the member contexts, before anything is queued
+  for (int i = 0; i < n; ++i) {
+    mhc_ctx* c = g->sys[i];
+    if (!c->cfg.check_finite) continue;
+    bool ok = true;
+    if (!on_device) {
+      ok = all_finite_f(v[i], (int64_t)n_steps * c->N * 3) && all_finite_f(W[i], (int64_t)n_steps * c->N * 9);
+    } else {
+      mhc_status st = device_inputs_finite(c, v[i], W[i], n_steps, &ok);
+      if (st) return gfail(g, st, c->err);
+    }
+    if (!ok)
+      return gfail(g, MHC_ERR_NONFINITE, "non-finite velocity or virial of system " + std::to_string(i));
+  }
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const int T = g->t_block;
   // host inputs of two or more full blocks: copies on the copy stream into

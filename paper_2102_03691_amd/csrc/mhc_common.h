@@ -73,6 +73,10 @@ hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v,
                              float* col_scale, const float* col_part, const float* const* tab, int dir,
                              double* jd_part);
 
+// Non-finite scan: stores 1 to *flag when any of the n floats at p (device)
+// is NaN or Inf; the caller clears *flag first (launch_fill_i32).
+hipError_t launch_nonfinite(hipStream_t s, const float* p, int64_t n, int* flag);
+
 // Per-step matrix-vector path (FP32): for steps t = 0..n_steps-1 of a plain
 // B buffer, J_n^mu = Xdot_n A_n^mu for every slot.  Output either
 //   hnema: out[t][M_pad][3]   (layout_g == 0)
