@@ -112,9 +112,11 @@ def test_slab48_bf16x3_t128():
     assert max(e.values()) <= TOL[BF16X3]
 
 
-@pytest.mark.parametrize("prec,S", [(BF16X3, 1024), (FP32, 512)])
+@pytest.mark.parametrize("prec,S", [(BF16X3, 2560), (FP32, 512)])
 def test_rod1500_gkma_t256(prec, S):
-    """4x4x1500 rod, 24000 atoms / 72000 modes, GKMA with L = 2000, T = 256, 1000 bins."""
+    """4x4x1500 rod, 24000 atoms / 72000 modes, GKMA with L = 2000, T = 256, 1000 bins.
+    With S = 2560 >= L + 2T the 2255-entry history ring wraps several times and
+    every lag has time origins (the last lag 561 of them)."""
     announce(f"full size rod1500 gkma prec={prec} S={S}")
     lat = synth.BlochLattice((4, 4, 1500))
     nb, L = 1000, 2000
@@ -136,18 +138,22 @@ def test_rod1500_gkma_t256(prec, S):
     assert n == S
     assert e["hnema"] <= TOL[prec] and e["corr"] <= TOL[prec] and e["integral"] <= TOL[prec]
     assert e["hcacf"] <= 1e-12
-    # lags with no time origin are exactly zero
+    # lags with no time origin are exactly zero; with S > L every lag is compared
     if S < L:
         assert np.all(g["corr"][S:] == 0)
+    else:
+        e_last = rel(g["corr"][L - 256:], ref["corr"][L - 256:])
+        log(f"rod1500_fullsize_p{prec}_t256_S{S}_last_lags", rel_corr_last256=e_last)
+        assert e_last <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [3, 1])
+@pytest.mark.parametrize("prec", [3, 1, 0])
 def test_uneven16_grouped_fullsize(prec):
     """The 16-system uneven batch at its full sizes (512 to 8000 atoms, nb = 500,
     L = 1000, T = 64) in the launch configuration the benchmark times: one
     grouped push per block, graph replay, autotuned tile shape.  Two blocks
     plus a partial one; every system against the FFT form of the oracle.
-    prec 3 = e4m3 hi/lo (bar 1e-2), 1 = split-BF16 (bar 1e-4)."""
+    prec 3 = e4m3 hi/lo (bar 1e-2), 1 = split-BF16 (bar 1e-4), 0 = FP32 (bar 1e-5)."""
     import torch
     from paper_2102_03691_amd import GKMA, HNEMA, ModalGroup, ModalHC
     announce(f"full size uneven16 grouped prec={prec}")
@@ -177,7 +183,7 @@ def test_uneven16_grouped_fullsize(prec):
     torch.cuda.synchronize()
     grp.push([v for v, _ in dv], [W for _, W in dv])
     torch.cuda.synchronize()
-    tol = 1e-2 if prec == 3 else TOL[1]
+    tol = 1e-2 if prec == 3 else TOL[prec]
     worst = 0.0
     for i, (h, (lat, m, meth, v, W)) in enumerate(zip(systems, data)):
         kb = oracle.bin_of_mode(lat.kpoint_frequencies().ravel(), nb, 0.0, lat.f_max).reshape(lat.dims)

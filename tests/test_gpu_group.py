@@ -95,7 +95,7 @@ def test_group_matches_single_pushes(cases, prec, graph, autotune, host):
     log(f"group_p{prec}_g{int(graph)}_a{int(autotune)}_h{int(host)}", **info)
     # oracle parity of every system after the whole run
     # single-term e4m3 is bounded loosely, as in the single-context tests (it is not expected to meet 1e-2)
-    tol = {FP8X3: 1e-2, FP8: 0.15}.get(prec) or TOL[prec]
+    tol = {FP8X3: 1e-2, FP8: 6e-2}.get(prec) or TOL[prec]
     for i, (case, (_, methods)) in enumerate(zip(cases, SYSTEMS)):
         ref = case.oracle(11, corr_len=20 if methods & GKMA else 0)
         got = _read(grouped[i], methods)

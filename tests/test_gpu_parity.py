@@ -230,7 +230,8 @@ FP8, FP8X3 = 2, 3
 def test_fp8(small, prec, T, sched):
     """e4m3 with per-mode and per-(channel, step) scales.  FP8X3 (hi/lo, three
     products) must meet the 1e-2 gate; single-term FP8 is reported with its
-    measured error and bounded loosely (it is not expected to meet 1e-2)."""
+    measured error (4.1-4.6e-2 here), bounded at 6e-2 so that a regression of
+    its accuracy fails; it is not expected to meet 1e-2."""
     announce(f"fp8 prec={prec} T={T} sched={sched}")
     L = 24
     ref = small.oracle(23, corr_len=L)
@@ -238,7 +239,7 @@ def test_fp8(small, prec, T, sched):
     e = {"rel_hnema": rel(got["hnema"], ref["hnema"]), "rel_corr": rel(got["corr"], ref["corr"]),
          "rel_integral": rel(got["integral"], ref["integral"]), "rel_hcacf": rel(got["hcacf"], ref["hcacf"])}
     log(f"6x6x5_fp8_p{prec}_T{T}_s{sched}", **e)
-    bound = 1e-2 if prec == FP8X3 else 0.15
+    bound = 1e-2 if prec == FP8X3 else 6e-2
     assert e["rel_hnema"] <= bound and e["rel_corr"] <= bound and e["rel_integral"] <= bound
     assert e["rel_hcacf"] <= 1e-12
 

@@ -66,7 +66,8 @@ def test_shc_correlation_parity(n_atoms, S, n_lags, T, splits, dev):
     ed = rel(Kd, ref_d)
     log(f"shc_dir_N{n_atoms}_S{S}_L{n_lags}_T{T}", rel_K_dir=ed)
     assert nd == S and ed <= TOL
-    assert np.array_equal(Kd.sum(axis=2) * 0 + K, K)
+    # K is the device's in-order float64 sum of the three split components
+    assert np.array_equal(K, (Kd[:, :, 0] + Kd[:, :, 1]) + Kd[:, :, 2])
     assert rel(Kd.sum(axis=2), K) <= 1e-14
     # transform of the device correlation against the oracle's transform of the oracle's correlation
     om = np.linspace(0.0, np.pi / 2.0, 33)
