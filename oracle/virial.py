@@ -1,0 +1,290 @@
+"""Per-atom virial, heat current and HNEMD driving force of a many-body
+potential (Sec. II.A, Eqs. 1-12): the plain FP64 oracle.
+
+TEST INFRASTRUCTURE ONLY (see oracle.modal): imported by the tests, the
+package smoke check and the benchmark's oracle leg, never by the library.
+
+What the paper fixes (Sec. II.A):
+  * the potential is a sum of site energies, U = sum_i U_i, and U_i depends on
+    the relative positions r_ij = r_j - r_i (Eq. 3) of atom i's neighbours;
+  * the force on i is sum_j F_ij with F_ij = dU_i/dr_ij - dU_j/dr_ji (Eq. 4);
+  * the per-atom virial is W_i = sum_{j != i} r_ij (x) dU_j/dr_ji (Eq. 8), i.e.
+    W_i^{mu nu} = sum_j r_ij^mu (dU_j/dr_ji)^nu, and it sums to the total
+    virial of Eq. 5 (written with the pair forces of Eq. 4);
+  * the potential part of the per-atom heat current is
+    J_i = sum_j r_ij (dU_j/dr_ji . v_i) (Eq. 9) = W_i v_i (Eq. 10);
+  * the HNEMD driving force is
+    F_i^ext = E_i F_e + sum_j (dU_j/dr_ji (x) r_ij) . F_e (Eq. 11)
+            = E_i F_e + F_e . W_i (Eq. 12), E_i the total energy of atom i.
+
+The site energies are those of Tersoff's bond-order potential (Phys. Rev. B
+38, 9902 (1988); the paper's "original Tersoff" for Si, Sec. III.A):
+  U_i  = 1/2 sum_{j != i} f_C(r_ij) [A exp(-l1 r_ij) - b_ij B exp(-l2 r_ij)]
+  b_ij = (1 + beta^n zeta_ij^n)^(-1/(2n))
+  zeta_ij = sum_{k != i, j} f_C(r_ik) g(cos theta_ijk) exp(l3^m (r_ij - r_ik)^m)
+  g(c) = gamma (1 + c0^2/d^2 - c0^2 / (d^2 + (c - h)^2))          (c0: the "c" parameter)
+  f_C(r) = 1 below R - D, 1/2 - 1/2 sin(pi/2 (r - R)/D) inside, 0 above R + D,
+where cos theta_ijk is the angle between r_ij and r_ik.  U_i depends only on
+the vectors r_ij of atom i's neighbours, which is what Eq. 8 needs; its
+partials dU_i/dr_ij are written out below by the chain rule, with every
+r_ij treated as an independent variable.
+
+Periodic orthorhombic box, minimum image (the box must exceed twice the
+cutoff R + D).  Units: A, eV, amu, fs (1 amu A^2/fs^2 = KE_UNIT eV).
+Everything is float64; loops are plain Python over atoms and neighbours.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# 1 amu * (A/fs)^2 in eV, from CODATA: 1.66053906660e-27 kg * 1e10 m^2/s^2 / 1.602176634e-19 J
+KE_UNIT = 1.66053906660e-27 * 1e10 / 1.602176634e-19
+
+
+def tersoff_si() -> dict:
+    """Tersoff's published parameters for silicon (Si(C) of the 1988 paper)."""
+    return dict(A=1830.8, B=471.18, lambda1=2.4799, lambda2=1.7322, lambda3=0.0, m=3, beta=1.1e-6, n=0.78734,
+                c=1.0039e5, d=16.217, h=-0.59825, gamma=1.0, R=2.85, D=0.15)
+
+
+def min_image(d: np.ndarray, box) -> np.ndarray:
+    box = np.asarray(box, dtype=np.float64)
+    return d - box * np.round(d / box)
+
+
+def neighbor_lists(pos, box, cutoff: float):
+    """For each atom i the ascending list of j != i with |r_ij| < cutoff (brute force)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    out = []
+    for i in range(pos.shape[0]):
+        r = np.linalg.norm(min_image(pos - pos[i], box), axis=1)
+        out.append([int(j) for j in np.nonzero(r < cutoff)[0] if j != i])
+    return out
+
+
+def cutoff_fn(r: float, R: float, D: float):
+    """f_C and its derivative d f_C / d r."""
+    if r < R - D:
+        return 1.0, 0.0
+    if r > R + D:
+        return 0.0, 0.0
+    x = 0.5 * math.pi * (r - R) / D
+    return 0.5 - 0.5 * math.sin(x), -0.25 * math.pi / D * math.cos(x)
+
+
+def angle_fn(c: float, p):
+    """g(cos theta) and dg / d cos theta."""
+    c0sq, dsq = p["c"] ** 2, p["d"] ** 2
+    t = c - p["h"]
+    den = dsq + t * t
+    return p["gamma"] * (1.0 + c0sq / dsq - c0sq / den), p["gamma"] * c0sq * 2.0 * t / (den * den)
+
+
+def exp_fn(x: float, p):
+    """exp(l3^m x^m) and its derivative in x."""
+    m, l3 = p["m"], p["lambda3"]
+    e = math.exp((l3 ** m) * (x ** m))
+    return e, e * m * (l3 ** m) * (x ** (m - 1))
+
+
+def _vec(pos, box, i, j):
+    return min_image(np.asarray(pos[j], dtype=np.float64) - np.asarray(pos[i], dtype=np.float64), box)
+
+
+def bond_terms(pos, box, p, nl):
+    """zeta_ij, b_ij and db_ij/dzeta_ij for every neighbour j of every atom i:
+    lists indexed [i][s] for j = nl[i][s]."""
+    zeta, b, db = [], [], []
+    for i in range(len(nl)):
+        rv = [_vec(pos, box, i, j) for j in nl[i]]
+        rn = [float(np.linalg.norm(x)) for x in rv]
+        zi, bi, dbi = [], [], []
+        for s in range(len(nl[i])):
+            z = 0.0
+            for q in range(len(nl[i])):
+                if q == s:
+                    continue
+                fc, _ = cutoff_fn(rn[q], p["R"], p["D"])
+                cos = float(rv[s] @ rv[q]) / (rn[s] * rn[q])
+                g, _ = angle_fn(cos, p)
+                e, _ = exp_fn(rn[s] - rn[q], p)
+                z += fc * g * e
+            n, beta = p["n"], p["beta"]
+            bz = (beta * z) ** n
+            bb = (1.0 + bz) ** (-0.5 / n)
+            # d b / d zeta = -1/2 beta^n zeta^(n-1) (1 + (beta zeta)^n)^(-1/(2n) - 1), zero at zeta = 0
+            dbb = 0.0 if z == 0.0 else -0.5 * bz / z * (1.0 + bz) ** (-0.5 / n - 1.0)
+            zi.append(z)
+            bi.append(bb)
+            dbi.append(dbb)
+        zeta.append(zi)
+        b.append(bi)
+        db.append(dbi)
+    return zeta, b, db
+
+
+def site_energies(pos, box, p, nl) -> np.ndarray:
+    """U_i of the Tersoff form above, [N]."""
+    _, b, _ = bond_terms(pos, box, p, nl)
+    U = np.zeros(len(nl))
+    for i in range(len(nl)):
+        acc = []
+        for s, j in enumerate(nl[i]):
+            r = float(np.linalg.norm(_vec(pos, box, i, j)))
+            fc, _ = cutoff_fn(r, p["R"], p["D"])
+            acc.append(fc * (p["A"] * math.exp(-p["lambda1"] * r) - b[i][s] * p["B"] * math.exp(-p["lambda2"] * r)))
+        U[i] = 0.5 * math.fsum(acc)
+    return U
+
+
+def site_energy_partials(pos, box, p, nl):
+    """dU_i/dr_ij for every neighbour j = nl[i][s]: list [i] of arrays [len(nl[i]), 3].
+
+    With a_ik = f_C(r_ik) B exp(-l2 r_ik) and V_ij the pair bracket,
+      dU_i/dr_ij = 1/2 dV_ij/dr_ij (b_ij held fixed)
+                   - 1/2 sum_k a_ik (db_ik/dzeta_ik) dzeta_ik/dr_ij,
+    where k runs over all neighbours of i: zeta_ij depends on r_ij through every
+    term of its sum, zeta_ik (k != j) through its term l = j.
+    """
+    _, b, db = bond_terms(pos, box, p, nl)
+    out = []
+    for i in range(len(nl)):
+        nj = len(nl[i])
+        rv = [_vec(pos, box, i, j) for j in nl[i]]
+        rn = [float(np.linalg.norm(x)) for x in rv]
+        fc = [cutoff_fn(r, p["R"], p["D"]) for r in rn]
+        a = [fc[q][0] * p["B"] * math.exp(-p["lambda2"] * rn[q]) for q in range(nj)]
+
+        def dcos_drij(s, q):
+            # derivative of cos theta between r_s and r_q with respect to r_s
+            c = float(rv[s] @ rv[q]) / (rn[s] * rn[q])
+            return rv[q] / (rn[s] * rn[q]) - c * rv[s] / (rn[s] ** 2), c
+
+        D = np.zeros((nj, 3))
+        for s in range(nj):
+            r, u = rn[s], rv[s] / rn[s]
+            fcs, dfcs = fc[s]
+            fr, dfr = p["A"] * math.exp(-p["lambda1"] * r), -p["lambda1"] * p["A"] * math.exp(-p["lambda1"] * r)
+            fa, dfa = p["B"] * math.exp(-p["lambda2"] * r), -p["lambda2"] * p["B"] * math.exp(-p["lambda2"] * r)
+            grad = 0.5 * (dfcs * (fr - b[i][s] * fa) + fcs * (dfr - b[i][s] * dfa)) * u
+            # k = j: every term l != j of zeta_ij depends on r_ij
+            dz = np.zeros(3)
+            for q in range(nj):
+                if q == s:
+                    continue
+                dc, c = dcos_drij(s, q)
+                g, dg = angle_fn(c, p)
+                e, de = exp_fn(rn[s] - rn[q], p)
+                dz += fc[q][0] * (dg * dc * e + g * de * u)
+            grad -= 0.5 * a[s] * db[i][s] * dz
+            # k != j: the term l = j of zeta_ik
+            for q in range(nj):
+                if q == s:
+                    continue
+                dc, c = dcos_drij(s, q)      # cos theta_ikj, differentiated in r_ij
+                g, dg = angle_fn(c, p)
+                e, de = exp_fn(rn[q] - rn[s], p)
+                dzq = dfcs * g * e * u + fcs * dg * dc * e - fcs * g * de * u
+                grad -= 0.5 * a[q] * db[i][q] * dzq
+            D[s] = grad
+        out.append(D)
+    return out
+
+
+def _partial(Dp, nl, j, i):
+    """dU_j/dr_ji from the partials of atom j."""
+    return Dp[j][nl[j].index(i)]
+
+
+def per_atom_virial(pos, box, p, nl) -> np.ndarray:
+    """Eq. 8: W_i^{mu nu} = sum_{j != i} r_ij^mu (dU_j/dr_ji)^nu, [N, 3, 3]."""
+    Dp = site_energy_partials(pos, box, p, nl)
+    W = np.zeros((len(nl), 3, 3))
+    for i in range(len(nl)):
+        for j in nl[i]:
+            W[i] += np.outer(_vec(pos, box, i, j), _partial(Dp, nl, j, i))
+    return W
+
+
+def forces(pos, box, p, nl) -> np.ndarray:
+    """Eq. 4 summed over the neighbours: F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji), [N, 3]."""
+    Dp = site_energy_partials(pos, box, p, nl)
+    F = np.zeros((len(nl), 3))
+    for i in range(len(nl)):
+        for s, j in enumerate(nl[i]):
+            F[i] += Dp[i][s] - _partial(Dp, nl, j, i)
+    return F
+
+
+def total_virial_eq5(pos, box, p, nl) -> np.ndarray:
+    """Eq. 5: W = -1/2 sum_i sum_j r_ij (x) F_ij, with the F_ij of Eq. 4."""
+    Dp = site_energy_partials(pos, box, p, nl)
+    W = np.zeros((3, 3))
+    for i in range(len(nl)):
+        for s, j in enumerate(nl[i]):
+            W -= 0.5 * np.outer(_vec(pos, box, i, j), Dp[i][s] - _partial(Dp, nl, j, i))
+    return W
+
+
+def per_atom_virial_eq2(pos, box, p, nl) -> np.ndarray:
+    """Eq. 2, the earlier per-atom virial: -1/2 sum_j r_ij (x) F_ij, [N, 3, 3]."""
+    Dp = site_energy_partials(pos, box, p, nl)
+    W = np.zeros((len(nl), 3, 3))
+    for i in range(len(nl)):
+        for s, j in enumerate(nl[i]):
+            W[i] -= 0.5 * np.outer(_vec(pos, box, i, j), Dp[i][s] - _partial(Dp, nl, j, i))
+    return W
+
+
+def heat_current_eq9(pos, box, vel, p, nl) -> np.ndarray:
+    """Eq. 9: J_i = sum_j r_ij (dU_j/dr_ji . v_i), [N, 3] (loops)."""
+    Dp = site_energy_partials(pos, box, p, nl)
+    vel = np.asarray(vel, dtype=np.float64)
+    J = np.zeros((len(nl), 3))
+    for i in range(len(nl)):
+        for j in nl[i]:
+            J[i] += _vec(pos, box, i, j) * float(_partial(Dp, nl, j, i) @ vel[i])
+    return J
+
+
+def heat_current_eq10(W, vel) -> np.ndarray:
+    """Eq. 10: J_i^mu = sum_nu W_i^{mu nu} v_i^nu, [N, 3]."""
+    return np.einsum("imn,in->im", np.asarray(W, dtype=np.float64), np.asarray(vel, dtype=np.float64))
+
+
+def atom_energies(U, mass, vel) -> np.ndarray:
+    """E_i = U_i + m_i |v_i|^2 / 2 (kinetic part converted to eV)."""
+    vel = np.asarray(vel, dtype=np.float64)
+    return np.asarray(U, dtype=np.float64) + 0.5 * np.asarray(mass, dtype=np.float64) * (vel * vel).sum(axis=1) * KE_UNIT
+
+
+def hnemd_force_eq11(pos, box, E, fe, p, nl) -> np.ndarray:
+    """Eq. 11: F_i^ext = E_i F_e + sum_j (dU_j/dr_ji (x) r_ij) . F_e, [N, 3] (loops)."""
+    Dp = site_energy_partials(pos, box, p, nl)
+    fe = np.asarray(fe, dtype=np.float64)
+    F = np.zeros((len(nl), 3))
+    for i in range(len(nl)):
+        F[i] = E[i] * fe
+        for j in nl[i]:
+            F[i] += np.outer(_partial(Dp, nl, j, i), _vec(pos, box, i, j)) @ fe
+    return F
+
+
+def hnemd_force_eq12(E, W, fe) -> np.ndarray:
+    """Eq. 12: F_i^ext = E_i F_e + F_e . W_i, (F_e . W_i)^nu = sum_mu F_e^mu W_i^{mu nu}."""
+    fe = np.asarray(fe, dtype=np.float64)
+    return np.asarray(E, dtype=np.float64)[:, None] * fe[None, :] + np.einsum("m,imn->in", fe, W)
+
+
+def evaluate(pos, box, vel, mass, fe, p, nl=None) -> dict:
+    """Everything the device computes for one configuration: U, F, W (Eq. 8),
+    per-atom heat current (Eq. 10) and F^ext (Eq. 12)."""
+    if nl is None:
+        nl = neighbor_lists(pos, box, p["R"] + p["D"])
+    U = site_energies(pos, box, p, nl)
+    W = per_atom_virial(pos, box, p, nl)
+    E = atom_energies(U, mass, vel)
+    return {"U": U, "F": forces(pos, box, p, nl), "W": W, "J": heat_current_eq10(W, vel),
+            "Fext": hnemd_force_eq12(E, W, fe), "E": E, "nl": nl}

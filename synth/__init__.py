@@ -292,6 +292,36 @@ def random_orthonormal(n: int, seed: int) -> np.ndarray:
     return q * np.sign(np.diag(r))[None, :]
 
 
+# ------------------------------------------------------------ atomic structures
+SI_LATTICE_A = 5.432                    # diamond-cubic Si lattice constant, A
+
+
+def diamond(cells, a: float = SI_LATTICE_A, sigma: float = 0.0, seed: int = 0):
+    """Diamond-cubic crystal of cells = (n1, n2, n3) conventional cells (8 atoms
+    each) in a periodic orthorhombic box, every atom displaced by an iid
+    Gaussian of standard deviation sigma (A) per component.
+
+    Returns (pos [N, 3] float64 in [0, box), box [3] float64).  Atom order:
+    cell (c1, c2, c3) row-major, then the 8 basis sites."""
+    n1, n2, n3 = cells
+    basis = np.array([[0, 0, 0], [0, 2, 2], [2, 0, 2], [2, 2, 0],
+                      [1, 1, 1], [1, 3, 3], [3, 1, 3], [3, 3, 1]], dtype=np.float64) * (a / 4.0)
+    c = np.stack(np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij"), axis=-1).reshape(-1, 3)
+    pos = (c[:, None, :] * a + basis[None, :, :]).reshape(-1, 3)
+    box = np.array([n1, n2, n3], dtype=np.float64) * a
+    if sigma > 0:
+        rng = np.random.Generator(np.random.PCG64([seed, 0xD1A3]))
+        pos = pos + rng.standard_normal(pos.shape) * sigma
+    return np.mod(pos, box), box
+
+
+def thermal_velocities(mass_amu: np.ndarray, temperature: float, seed: int) -> np.ndarray:
+    """Maxwell-Boltzmann velocities [N, 3] float64 (A/fs), one PCG64 stream per seed."""
+    rng = np.random.Generator(np.random.PCG64([seed, 0x7E10]))
+    m = np.asarray(mass_amu, dtype=np.float64)
+    return rng.standard_normal((m.shape[0], 3)) * velocity_sigma(m, temperature)[:, None]
+
+
 # --------------------------------------------------------------- workloads
 @dataclass(frozen=True)
 class Workload:
