@@ -466,6 +466,87 @@ mhc_status mhc_shc_synchronize(mhc_shc *shc);
 mhc_status mhc_shc_set_timing(mhc_shc *shc, int enable);
 mhc_status mhc_shc_kernel_timing(mhc_shc *shc, int64_t *launches, double *total_ms);
 
+/* ------------------------------------------------------ per-atom virial
+ * The inputs of the modal current, from positions (Sec. II.A): for a
+ * many-body potential written as site energies U = sum_i U_i, with U_i a
+ * function of the vectors r_ij = r_j - r_i (Eq. 3) to atom i's neighbours,
+ *   F_i        = sum_j (dU_i/dr_ij - dU_j/dr_ji)                 (Eq. 4)
+ *   W_i^{mu nu} = sum_{j != i} r_ij^mu (dU_j/dr_ji)^nu            (Eq. 8)
+ *   J_i        = W_i v_i                                          (Eq. 10)
+ *   F_i^ext    = E_i F_e + F_e . W_i, (F_e . W_i)^nu = sum_mu F_e^mu W_i^{mu nu}
+ *                                                                 (Eq. 12)
+ * with E_i = U_i + m_i |v_i|^2 / 2 the total energy of atom i.  W_i is not
+ * symmetric for a many-body potential; its sum over atoms is the total virial
+ * of Eq. 5.  The potential is Tersoff's bond-order form (Phys. Rev. B 38, 9902
+ * (1988); the paper's Si potential, Sec. III.A):
+ *   U_i     = 1/2 sum_j f_C(r_ij) [A exp(-lambda1 r_ij) - b_ij B exp(-lambda2 r_ij)]
+ *   b_ij    = (1 + beta^n zeta_ij^n)^(-1/(2n))
+ *   zeta_ij = sum_{k != i,j} f_C(r_ik) g(cos theta_ijk) exp(lambda3^m (r_ij - r_ik)^m)
+ *   g(x)    = gamma (1 + c^2/d^2 - c^2 / (d^2 + (x - h)^2))
+ *   f_C(r)  = 1 (r < R - D), 1/2 - 1/2 sin(pi/2 (r - R)/D) (|r - R| <= D), 0 beyond.
+ * Everything is float64 on the device, in a fixed summation order (bitwise
+ * repeatable).  Units: A, eV, amu, fs (kinetic energy converted with
+ * 1 amu A^2/fs^2 = 103.6427 eV); F_e in 1/A.  Periodic orthorhombic box,
+ * minimum image. */
+typedef struct mhc_virial mhc_virial;
+
+typedef struct {
+  double A, B;            /* eV                                    */
+  double lambda1, lambda2;/* 1/A                                   */
+  double lambda3;         /* 1/A (0 switches the exponential off)  */
+  int32_t m;              /* exponent of the lambda3 term: 1 or 3  */
+  int32_t reserved;       /* must be zero                          */
+  double beta, n, c, d, h, gamma;
+  double R, D;            /* cutoff centre and half-width, A       */
+} mhc_tersoff_params;
+
+/* n_atoms in [1, 2^26]; mass_amu [N] host array (> 0); box [3] host array of
+ * the orthorhombic box edges, each larger than 2 (R + D + skin); max_neighbors
+ * in [1, 64] (atoms within R + D + skin); skin >= 0 widens the neighbour lists
+ * so that they stay valid while atoms move less than skin / 2 (pairs beyond
+ * R + D contribute exactly zero).  hip_stream as for mhc_create.
+ * Device memory: about N (12 max_neighbors + 1) doubles and N (2 max_neighbors
+ * + 4) ints.  Errors: INVALID_ARG, OOM, HIP (mhc_virial_last_error(NULL)). */
+mhc_status mhc_virial_create(int device, void *hip_stream, int64_t n_atoms, const double *mass_amu,
+                             const double *box, const mhc_tersoff_params *params, int32_t max_neighbors,
+                             double skin, mhc_virial **out);
+mhc_status mhc_virial_destroy(mhc_virial *v);
+const char *mhc_virial_last_error(const mhc_virial *v);
+
+/* Build the neighbour lists from pos [N][3] (device, A; any periodic image):
+ * every j != i with |r_ij| < R + D + skin, in ascending j.  Synchronizes.
+ * *max_found (if not NULL) receives the largest neighbour count.
+ * Errors: INVALID_ARG (an atom has more than max_neighbors neighbours, or the
+ * lists are not symmetric, which non-finite positions cause; the lists are
+ * then invalid until the next successful call), HIP. */
+mhc_status mhc_virial_neighbors(mhc_virial *v, const double *pos, int32_t *max_found);
+
+/* Copy the lists to the host: counts [N] and lists [N][max_neighbors]
+ * (entries past an atom's count are -1); either may be NULL.
+ * Errors: STATE (no valid lists), HIP. */
+mhc_status mhc_virial_read_neighbors(mhc_virial *v, int32_t *counts, int32_t *lists);
+
+/* One evaluation at positions pos [N][3] (device), with the current lists:
+ * outputs are device arrays, each optional (NULL skips it):
+ *   U    [N]        site energies U_i (eV)
+ *   F    [N][3]     forces (Eq. 4 summed, eV/A)
+ *   W    [N][3][3]  per-atom virial W_i^{mu nu} (Eq. 8, eV), float64
+ *   W32  [N][3][3]  the same rounded to float32: one step of the W input of
+ *                   mhc_push / mhc_shc_push
+ *   Fext [N][3]     HNEMD driving force (Eq. 12, eV/A) for fe [3] (host, 1/A;
+ *                   NULL: zero); vel [N][3] (device, A/fs) gives the kinetic
+ *                   part of E_i (NULL: E_i = U_i).
+ * Queued on the stream (returns before the GPU finishes).
+ * Errors: INVALID_ARG, STATE (no valid lists), HIP. */
+mhc_status mhc_virial_compute(mhc_virial *v, const double *pos, const double *vel, const double *fe, double *U,
+                              double *F, double *W, float *W32, double *Fext);
+mhc_status mhc_virial_synchronize(mhc_virial *v);
+
+/* HIP-event timing of each evaluation (both kernels), as mhc_set_timing /
+ * mhc_kernel_timing. */
+mhc_status mhc_virial_set_timing(mhc_virial *v, int enable);
+mhc_status mhc_virial_kernel_timing(mhc_virial *v, int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmodalhc.so")
 OBJ_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["mhc_api.cpp", "mhc_shc.cpp", "k_prep.hip", "k_contract.hip", "k_accum.hip", "k_shc.hip"]
+SOURCES = ["mhc_api.cpp", "mhc_shc.cpp", "mhc_virial.cpp", "k_prep.hip", "k_contract.hip", "k_accum.hip", "k_shc.hip",
+           "k_tersoff.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

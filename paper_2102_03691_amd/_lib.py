@@ -31,6 +31,13 @@ class RunConfig(C.Structure):
                 ("schedule", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
+class TersoffParams(C.Structure):
+    _fields_ = [("A", C.c_double), ("B", C.c_double), ("lambda1", C.c_double), ("lambda2", C.c_double),
+                ("lambda3", C.c_double), ("m", C.c_int32), ("reserved", C.c_int32), ("beta", C.c_double),
+                ("n", C.c_double), ("c", C.c_double), ("d", C.c_double), ("h", C.c_double), ("gamma", C.c_double),
+                ("R", C.c_double), ("D", C.c_double)]
+
+
 _lib = None
 
 
@@ -99,6 +106,15 @@ def library():
         "mhc_shc_synchronize": (i32, [vp]),
         "mhc_shc_set_timing": (i32, [vp, C.c_int]),
         "mhc_shc_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
+        "mhc_virial_create": (i32, [C.c_int, vp, i64, vp, vp, P(TersoffParams), i32, dbl, P(vp)]),
+        "mhc_virial_destroy": (i32, [vp]),
+        "mhc_virial_last_error": (C.c_char_p, [vp]),
+        "mhc_virial_neighbors": (i32, [vp, vp, P(i32)]),
+        "mhc_virial_read_neighbors": (i32, [vp, vp, vp]),
+        "mhc_virial_compute": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "mhc_virial_synchronize": (i32, [vp]),
+        "mhc_virial_set_timing": (i32, [vp, C.c_int]),
+        "mhc_virial_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
         "mhc_group_create": (i32, [P(vp), i32, i32, P(vp)]),
         "mhc_group_destroy": (i32, [vp]),
         "mhc_group_last_error": (C.c_char_p, [vp]),
@@ -556,4 +572,111 @@ class ModalSHC:
         n = C.c_int64()
         ms = C.c_double()
         self._check(self._lib.mhc_shc_kernel_timing(self._h, C.byref(n), C.byref(ms)), "shc kernel_timing")
+        return n.value, ms.value
+
+
+class ModalVirial:
+    """Per-atom virial, forces and HNEMD driving force of a Tersoff potential
+    (mhc_virial_*): positions in, the W input of the modal-current push out.
+
+    params: dict with the keys of mhc_tersoff_params (A, B, lambda1, lambda2,
+    lambda3, m, beta, n, c, d, h, gamma, R, D).  Positions, velocities and
+    outputs are float64 torch tensors on the device (W32 float32)."""
+
+    def __init__(self, mass, box, params: dict, max_neighbors: int = 16, skin: float = 0.0, device: int = 0,
+                 stream=None):
+        self._lib = library()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        m = np.ascontiguousarray(mass, dtype=np.float64)
+        b = np.ascontiguousarray(box, dtype=np.float64)
+        assert b.shape == (3,)
+        tp = TersoffParams(**{k: params[k] for k in ("A", "B", "lambda1", "lambda2", "lambda3", "beta", "n", "c", "d",
+                                                      "h", "gamma", "R", "D")}, m=int(params["m"]), reserved=0)
+        h = C.c_void_p()
+        st = self._lib.mhc_virial_create(int(device), C.c_void_p(int(stream) if stream else 0), m.shape[0], _ptr(m),
+                                         _ptr(b), C.byref(tp), int(max_neighbors), float(skin), C.byref(h))
+        if st:
+            raise MhcError(st, self._lib.mhc_virial_last_error(None).decode())
+        self._h = h
+        self._use = _StreamUse(device, int(stream) if stream else 0)
+        self.n_atoms, self.max_neighbors, self.device = m.shape[0], int(max_neighbors), device
+
+    def _check(self, st, what):
+        if st:
+            raise MhcError(st, f"{what}: {self._lib.mhc_virial_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mhc_virial_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _dev(self, t, dtype_size, shape_tail):
+        assert _is_torch(t) and t.is_cuda and t.is_contiguous() and t.element_size() == dtype_size
+        assert t.numel() == self.n_atoms * shape_tail
+        return _ptr(t)
+
+    def neighbors(self, pos) -> int:
+        """Build the lists from pos [N, 3] (float64 device tensor); returns the largest count."""
+        p = self._dev(pos, 8, 3)
+        self._use(pos)
+        mx = C.c_int32()
+        self._check(self._lib.mhc_virial_neighbors(self._h, p, C.byref(mx)), "virial neighbors")
+        return mx.value
+
+    def read_neighbors(self):
+        counts = np.empty(self.n_atoms, dtype=np.int32)
+        lists = np.empty((self.n_atoms, self.max_neighbors), dtype=np.int32)
+        self._check(self._lib.mhc_virial_read_neighbors(self._h, _ptr(counts), _ptr(lists)), "virial read_neighbors")
+        return counts, lists
+
+    def compute(self, pos, vel=None, fe=None, want=("U", "F", "W", "W32", "Fext"), out=None):
+        """One evaluation; returns {name: tensor} for the names in want (or the
+        preallocated tensors given in out, e.g. a step slice of a W32 block)."""
+        import torch
+        N = self.n_atoms
+        out = dict(out or {})
+        shapes = {"U": (N,), "F": (N, 3), "W": (N, 3, 3), "W32": (N, 3, 3), "Fext": (N, 3)}
+        for k in want:
+            if k not in out:
+                out[k] = torch.empty(shapes[k], dtype=torch.float32 if k == "W32" else torch.float64,
+                                     device=pos.device)
+        ptrs = {}
+        for k, t in out.items():
+            ptrs[k] = self._dev(t, 4 if k == "W32" else 8, {"U": 1, "F": 3, "W": 9, "W32": 9, "Fext": 3}[k])
+        p = self._dev(pos, 8, 3)
+        vp = self._dev(vel, 8, 3) if vel is not None else None
+        f = None
+        if fe is not None:
+            fa = np.ascontiguousarray(fe, dtype=np.float64)
+            assert fa.shape == (3,)
+            f = _ptr(fa)
+        self._use(*[t for t in (pos, vel) if t is not None], *out.values())
+        self._check(self._lib.mhc_virial_compute(self._h, p, vp, f, ptrs.get("U"), ptrs.get("F"), ptrs.get("W"),
+                                                 ptrs.get("W32"), ptrs.get("Fext")), "virial compute")
+        return out
+
+    def synchronize(self):
+        self._check(self._lib.mhc_virial_synchronize(self._h), "virial synchronize")
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.mhc_virial_set_timing(self._h, int(bool(enable))), "virial set_timing")
+
+    def kernel_timing(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(self._lib.mhc_virial_kernel_timing(self._h, C.byref(n), C.byref(ms)), "virial kernel_timing")
         return n.value, ms.value

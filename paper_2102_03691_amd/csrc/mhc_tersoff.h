@@ -1,0 +1,77 @@
+// Internal declarations of the per-atom virial kernels (k_tersoff.hip) used
+// by the host side in mhc_virial.cpp.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mhc {
+
+// Cell grid of the neighbour search: nc cells per axis (1, or at least 3, so
+// that the 27 surrounding cells never repeat), each at least the cutoff wide.
+struct CellGrid {
+  double box[3];
+  int nc[3];
+};
+
+// Device buffers of the neighbour lists: nbr, rev [max_nb][N] (slot-major),
+// n_nb [N]; cell_of [N], atoms [N]; count, fill [n_cells], start [n_cells + 1];
+// flags[0] = largest neighbour count found, flags[1] = 1 if a reverse slot
+// was missing.
+struct NeighborBufs {
+  int* nbr;
+  int* rev;
+  int* n_nb;
+  int* cell_of;
+  int* atoms;
+  int* count;
+  int* fill;
+  int* start;
+  int* flags;
+};
+
+// Tersoff parameters as the kernels use them: l3m = lambda3^m, c2 = c^2, d2 = d^2.
+struct TersoffParams {
+  double A, B, l1, l2, l3m, beta, n, c2, d2, h, gamma, R, D;
+  int m;
+};
+
+// Per-evaluation buffers: positions (device, [N][3]); neighbour lists; pair
+// arrays rv [4][max_nb][N] (x, y, z, |r|), bb and adb [max_nb][N], dd
+// [3][max_nb][N] (dU_i/dr_ij); site energies U [N].
+struct TersoffArgs {
+  const double* pos;
+  int64_t N;
+  double box[3];
+  const int* nbr;
+  const int* n_nb;
+  const int* rev;
+  int max_nb;
+  double* rv;
+  double* bb;
+  double* adb;
+  double* dd;
+  double* U;
+};
+
+// Outputs of the gather kernel (any may be null): F [N][3], W [N][3][3] float64
+// and W32 float32 (W[i][mu][nu]), Fext [N][3]; vel [N][3] and mass [N] give the
+// kinetic part of E_i (vel null: E_i = U_i).
+struct GatherArgs {
+  const double* vel;
+  const double* mass;
+  double fe[3];
+  double ke_unit;
+  double* F;
+  double* W;
+  float* W32;
+  double* Fext;
+};
+
+hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, int max_nb,
+                            NeighborBufs b);
+// Queues the site and gather kernels; e0 / e1 (optional) are recorded around them.
+hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o,
+                          hipEvent_t e0, hipEvent_t e1);
+
+}  // namespace mhc

@@ -1,0 +1,349 @@
+// Host side of the per-atom virial object (mhc_virial_*, include/mhc.h):
+// argument checks, device buffers, the cell grid of the neighbour search and
+// the launch sequence.  Every step of the computation is a HIP kernel
+// (k_tersoff.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mhc.h"
+#include "mhc_tersoff.h"
+
+using namespace mhc;
+
+namespace {
+
+thread_local std::string g_virial_create_error;
+
+// 1 amu (A/fs)^2 in eV: 1.66053906660e-27 kg * 1e10 m^2/s^2 / 1.602176634e-19 J
+constexpr double KE_UNIT_EV = 1.66053906660e-27 * 1e10 / 1.602176634e-19;
+
+}  // namespace
+
+struct mhc_virial {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  mhc_status sticky = MHC_OK;
+
+  int64_t N = 0;
+  double box[3] = {0, 0, 0};
+  TersoffParams tp{};
+  double rc = 0.0;        // neighbour cutoff: R + D + skin
+  int max_nb = 0;
+  CellGrid cg{};
+  bool lists_ok = false;
+
+  std::vector<void*> allocs;
+  double* d_mass = nullptr;
+  NeighborBufs nb{};
+  double *d_rv = nullptr, *d_bb = nullptr, *d_adb = nullptr, *d_dd = nullptr, *d_U = nullptr;
+
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+mhc_status vfail(mhc_virial* v, mhc_status st, const std::string& msg) {
+  if (v) {
+    v->err = msg;
+    if (st == MHC_ERR_HIP) v->sticky = MHC_ERR_HIP;
+  }
+  return st;
+}
+
+#define VHIP_TRY(call, where)                                                               \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return vfail(v, MHC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+mhc_status venter(mhc_virial* v) {
+  if (!v) return MHC_ERR_INVALID_ARG;
+  if (v->sticky != MHC_OK) return v->sticky;
+  v->err.clear();
+  return MHC_OK;
+}
+
+void vfree(mhc_virial* v) {
+  for (void* p : v->allocs) (void)hipFree(p);
+  v->allocs.clear();
+}
+
+template <class T>
+bool valloc(mhc_virial* v, size_t count, T** out) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16)) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  v->allocs.push_back(p);
+  *out = reinterpret_cast<T*>(p);
+  return true;
+}
+
+bool finite_params(const mhc_tersoff_params* p) {
+  const double x[] = {p->A, p->B, p->lambda1, p->lambda2, p->lambda3, p->beta, p->n, p->c, p->d, p->h, p->gamma,
+                      p->R, p->D};
+  for (double a : x)
+    if (!std::isfinite(a)) return false;
+  return true;
+}
+
+// Cells per axis: floor(box / cutoff) (so a cell is at least the cutoff wide),
+// 1 where that is below 3; the total kept below 8N + 64 by halving the
+// largest count (cells only get wider).
+CellGrid make_grid(const double box[3], double rc, int64_t N) {
+  CellGrid g{};
+  for (int a = 0; a < 3; ++a) {
+    g.box[a] = box[a];
+    const double c = std::floor(box[a] / rc);
+    int n = c > 1024.0 ? 1024 : (int)c;
+    g.nc[a] = n < 3 ? 1 : n;
+  }
+  const int64_t cap = 8 * N + 64;
+  while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > cap) {
+    int a = 0;
+    for (int b = 1; b < 3; ++b)
+      if (g.nc[b] > g.nc[a]) a = b;
+    const int n = g.nc[a] / 2;
+    g.nc[a] = n < 3 ? 1 : n;
+  }
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, const double* mass_amu,
+                             const double* box, const mhc_tersoff_params* params, int32_t max_neighbors, double skin,
+                             mhc_virial** out) {
+  g_virial_create_error.clear();
+  auto bad = [](const char* msg) {
+    g_virial_create_error = msg;
+    return MHC_ERR_INVALID_ARG;
+  };
+  if (!out) return bad("out is NULL");
+  *out = nullptr;
+  if (n_atoms < 1 || n_atoms > (int64_t(1) << 26)) return bad("n_atoms must be in [1, 2^26]");
+  if (!mass_amu || !box || !params) return bad("NULL mass, box or parameters");
+  if (max_neighbors < 1 || max_neighbors > 64) return bad("max_neighbors must be in [1, 64]");
+  if (!std::isfinite(skin) || skin < 0.0) return bad("skin must be finite and >= 0");
+  if (!finite_params(params) || params->reserved != 0) return bad("parameters must be finite, reserved zero");
+  if (params->m != 1 && params->m != 3) return bad("m must be 1 or 3");
+  if (!(params->D > 0.0) || !(params->R > params->D)) return bad("need R > D > 0");
+  if (!(params->n > 0.0) || params->beta < 0.0 || !(params->d != 0.0)) return bad("need n > 0, beta >= 0, d != 0");
+  const double rc = params->R + params->D + skin;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(box[a]) || !(box[a] > 2.0 * rc)) return bad("every box edge must exceed twice R + D + skin");
+  for (int64_t i = 0; i < n_atoms; ++i)
+    if (!std::isfinite(mass_amu[i]) || !(mass_amu[i] > 0.0)) return bad("masses must be finite and positive");
+  int nd = 0;
+  hipError_t e = hipGetDeviceCount(&nd);
+  if (e != hipSuccess || nd == 0) {
+    (void)hipGetLastError();
+    g_virial_create_error = "no HIP device";
+    return MHC_ERR_HIP;
+  }
+  if (device < 0 || device >= nd) return bad("device index out of range");
+  if ((e = hipSetDevice(device)) != hipSuccess) {
+    g_virial_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return MHC_ERR_HIP;
+  }
+  mhc_virial* v = new (std::nothrow) mhc_virial();
+  if (!v) {
+    g_virial_create_error = "host allocation failed";
+    return MHC_ERR_OOM;
+  }
+  v->device = device;
+  v->N = n_atoms;
+  for (int a = 0; a < 3; ++a) v->box[a] = box[a];
+  v->rc = rc;
+  v->max_nb = max_neighbors;
+  v->cg = make_grid(box, rc, n_atoms);
+  const mhc_tersoff_params& p = *params;
+  v->tp = TersoffParams{p.A, p.B, p.lambda1, p.lambda2, std::pow(p.lambda3, (double)p.m), p.beta, p.n, p.c * p.c,
+                        p.d * p.d, p.h, p.gamma, p.R, p.D, p.m};
+  auto cleanup = [&](mhc_status st, const char* msg) {
+    vfree(v);
+    if (v->own_stream) (void)hipStreamDestroy(v->stream);
+    delete v;
+    g_virial_create_error = msg;
+    return st;
+  };
+  if (hip_stream) {
+    v->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&v->stream) != hipSuccess) return cleanup(MHC_ERR_HIP, "hipStreamCreate failed");
+    v->own_stream = true;
+  }
+  const int64_t N = n_atoms, MN = (int64_t)max_neighbors * N;
+  const int64_t n_cells = (int64_t)v->cg.nc[0] * v->cg.nc[1] * v->cg.nc[2];
+  NeighborBufs& b = v->nb;
+  bool ok = valloc(v, N, &v->d_mass) && valloc(v, MN, &b.nbr) && valloc(v, MN, &b.rev) && valloc(v, N, &b.n_nb) &&
+            valloc(v, N, &b.cell_of) && valloc(v, N, &b.atoms) && valloc(v, n_cells, &b.count) &&
+            valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) && valloc(v, 2, &b.flags) &&
+            valloc(v, 4 * MN, &v->d_rv) && valloc(v, MN, &v->d_bb) && valloc(v, MN, &v->d_adb) &&
+            valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U);
+  if (!ok) return cleanup(MHC_ERR_OOM, "device allocation failed");
+  if (hipMemcpyAsync(v->d_mass, mass_amu, N * sizeof(double), hipMemcpyHostToDevice, v->stream) != hipSuccess ||
+      hipStreamSynchronize(v->stream) != hipSuccess)
+    return cleanup(MHC_ERR_HIP, "copy of the masses failed");
+  *out = v;
+  return MHC_OK;
+}
+
+mhc_status mhc_virial_destroy(mhc_virial* v) {
+  if (!v) return MHC_OK;
+  (void)hipSetDevice(v->device);
+  (void)hipStreamSynchronize(v->stream);
+  vfree(v);
+  for (auto e : v->ev) (void)hipEventDestroy(e);
+  if (v->own_stream) (void)hipStreamDestroy(v->stream);
+  delete v;
+  return MHC_OK;
+}
+
+const char* mhc_virial_last_error(const mhc_virial* v) {
+  if (!v) return g_virial_create_error.c_str();
+  return v->err.c_str();
+}
+
+mhc_status mhc_virial_neighbors(mhc_virial* v, const double* pos, int32_t* max_found) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  if (!pos) return vfail(v, MHC_ERR_INVALID_ARG, "NULL positions");
+  VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
+  v->lists_ok = false;
+  VHIP_TRY(launch_neighbors(v->stream, pos, v->N, v->cg, v->rc, v->max_nb, v->nb), "neighbour search");
+  int flags[2] = {0, 0};
+  VHIP_TRY(hipMemcpyAsync(flags, v->nb.flags, sizeof(flags), hipMemcpyDeviceToHost, v->stream), "read flags");
+  VHIP_TRY(hipStreamSynchronize(v->stream), "neighbour search sync");
+  if (max_found) *max_found = flags[0];
+  if (flags[0] > v->max_nb)
+    return vfail(v, MHC_ERR_INVALID_ARG,
+                 "an atom has " + std::to_string(flags[0]) + " neighbours within the cutoff, more than max_neighbors = " +
+                     std::to_string(v->max_nb));
+  if (flags[1]) return vfail(v, MHC_ERR_INVALID_ARG, "neighbour lists are not symmetric (non-finite positions?)");
+  v->lists_ok = true;
+  return MHC_OK;
+}
+
+mhc_status mhc_virial_read_neighbors(mhc_virial* v, int32_t* counts, int32_t* lists) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  if (!v->lists_ok) return vfail(v, MHC_ERR_STATE, "no valid neighbour lists (call mhc_virial_neighbors)");
+  VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
+  const int64_t N = v->N;
+  if (counts)
+    VHIP_TRY(hipMemcpyAsync(counts, v->nb.n_nb, N * 4, hipMemcpyDeviceToHost, v->stream), "read counts");
+  std::vector<int32_t> slot_major;
+  if (lists) {
+    slot_major.resize((size_t)v->max_nb * N);
+    VHIP_TRY(hipMemcpyAsync(slot_major.data(), v->nb.nbr, slot_major.size() * 4, hipMemcpyDeviceToHost, v->stream),
+             "read lists");
+  }
+  std::vector<int32_t> cnt(N);
+  VHIP_TRY(hipMemcpyAsync(cnt.data(), v->nb.n_nb, N * 4, hipMemcpyDeviceToHost, v->stream), "read counts");
+  VHIP_TRY(hipStreamSynchronize(v->stream), "read sync");
+  if (lists) {
+    for (int64_t i = 0; i < N; ++i)
+      for (int s = 0; s < v->max_nb; ++s)
+        lists[i * v->max_nb + s] = s < cnt[i] ? slot_major[(size_t)s * N + i] : -1;
+  }
+  return MHC_OK;
+}
+
+mhc_status mhc_virial_compute(mhc_virial* v, const double* pos, const double* vel, const double* fe, double* U,
+                              double* F, double* W, float* W32, double* Fext) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  if (!pos) return vfail(v, MHC_ERR_INVALID_ARG, "NULL positions");
+  if (!v->lists_ok) return vfail(v, MHC_ERR_STATE, "no valid neighbour lists (call mhc_virial_neighbors)");
+  double f[3] = {0.0, 0.0, 0.0};
+  if (fe)
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(fe[a])) return vfail(v, MHC_ERR_INVALID_ARG, "non-finite F_e");
+      f[a] = fe[a];
+    }
+  VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
+  TersoffArgs a{};
+  a.pos = pos;
+  a.N = v->N;
+  for (int q = 0; q < 3; ++q) a.box[q] = v->box[q];
+  a.nbr = v->nb.nbr;
+  a.n_nb = v->nb.n_nb;
+  a.rev = v->nb.rev;
+  a.max_nb = v->max_nb;
+  a.rv = v->d_rv;
+  a.bb = v->d_bb;
+  a.adb = v->d_adb;
+  a.dd = v->d_dd;
+  a.U = U ? U : v->d_U;
+  GatherArgs o{};
+  o.vel = vel;
+  o.mass = v->d_mass;
+  for (int q = 0; q < 3; ++q) o.fe[q] = f[q];
+  o.ke_unit = KE_UNIT_EV;
+  o.F = F;
+  o.W = W;
+  o.W32 = W32;
+  o.Fext = Fext;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (v->timing) {
+    if (v->ev_used + 2 > v->ev.size())
+      for (int q = 0; q < 2; ++q) {
+        hipEvent_t e;
+        VHIP_TRY(hipEventCreate(&e), "event create");
+        v->ev.push_back(e);
+      }
+    e0 = v->ev[v->ev_used];
+    e1 = v->ev[v->ev_used + 1];
+    v->ev_used += 2;
+  }
+  VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, e0, e1), "virial kernels");
+  return MHC_OK;
+}
+
+mhc_status mhc_virial_synchronize(mhc_virial* v) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
+  VHIP_TRY(hipStreamSynchronize(v->stream), "synchronize");
+  return MHC_OK;
+}
+
+mhc_status mhc_virial_set_timing(mhc_virial* v, int enable) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  if (enable != 0 && enable != 1) return vfail(v, MHC_ERR_INVALID_ARG, "enable is 0 or 1");
+  v->timing = enable == 1;
+  return MHC_OK;
+}
+
+mhc_status mhc_virial_kernel_timing(mhc_virial* v, int64_t* launches, double* total_ms) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
+  VHIP_TRY(hipStreamSynchronize(v->stream), "timing sync");
+  double tot = 0.0;
+  for (size_t q = 0; q + 1 < v->ev_used; q += 2) {
+    float ms = 0.0f;
+    VHIP_TRY(hipEventElapsedTime(&ms, v->ev[q], v->ev[q + 1]), "event elapsed");
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)(v->ev_used / 2);
+  if (total_ms) *total_ms = tot;
+  v->ev_used = 0;
+  return MHC_OK;
+}
+
+}  // extern "C"

@@ -187,3 +187,34 @@ def test_c_abi_driver_builds(tmp_path):
                     os.path.join(root, "tests", "c", "abi_run.c"), lib, "-Wl,-rpath," + os.path.dirname(lib),
                     "-o", str(tmp_path / "abi_run")], check=True)
     assert (tmp_path / "abi_run").exists()
+
+
+def test_virial_create_validates_arguments_without_a_gpu():
+    """mhc_virial_create checks its arguments before any HIP call."""
+    import ctypes as C
+    from oracle import virial as ov
+    lib = _lib.library()
+    p = ov.tersoff_si()
+    good = dict(A=p["A"], B=p["B"], lambda1=p["lambda1"], lambda2=p["lambda2"], lambda3=0.0, m=3, reserved=0,
+                beta=p["beta"], n=p["n"], c=p["c"], d=p["d"], h=p["h"], gamma=1.0, R=p["R"], D=p["D"])
+    m = np.full(8, 28.0855)
+    box = np.full(3, 10.0)
+    out = C.c_void_p()
+
+    def create(mass=m, bx=box, max_nb=16, skin=0.0, **kw):
+        tp = _lib.TersoffParams(**{**good, **kw})
+        return lib.mhc_virial_create(0, None, len(mass), mass.ctypes.data, bx.ctypes.data, C.byref(tp), max_nb,
+                                     skin, C.byref(out))
+
+    assert create(bx=np.full(3, 5.9)) == 1                      # box edge below 2 (R + D)
+    assert b"twice" in lib.mhc_virial_last_error(None)
+    assert create(skin=2.0) == 1                                # 2 (R + D + skin) = 10 is not below the box
+    assert create(m=2) == 1
+    assert create(reserved=1) == 1
+    assert create(D=0.0) == 1
+    assert create(max_nb=0) == 1 and create(max_nb=65) == 1
+    assert create(mass=np.array([28.0, -1.0])) == 1
+    assert create(n=float("nan")) == 1
+    assert lib.mhc_virial_create(0, None, 8, None, box.ctypes.data, None, 16, 0.0, C.byref(out)) == 1
+    assert lib.mhc_virial_destroy(None) == 0
+    assert lib.mhc_virial_compute(None, None, None, None, None, None, None, None, None) == 1
