@@ -64,6 +64,14 @@ SHC_WORKLOADS = {"shc8000_l250_t256": (8000, 250, 256, 40)}     # atoms, lags, T
 SHC_METRIC = "spectral heat current atom*lag*steps/s (float64 virial-velocity correlation)"
 PEAK_FP64_FLOPS = 78.6e12
 
+# Per-atom virial, forces and HNEMD force of Tersoff Si from positions (the
+# inputs of the modal current, Sec. II.A): diamond crystals of n^3 conventional
+# cells with thermal displacements; one bench step = one evaluation of every
+# atom (neighbour lists built before the timed region, as an MD code rebuilds
+# them every few steps).  8000 atoms is the paper's speed-test size.
+VIRIAL_WORKLOADS = {"si8000_virial": ((10, 10, 10), 200), "si512k_virial": ((40, 40, 40), 100)}
+VIRIAL_METRIC = "per-atom virial (Eq. 8) + forces + HNEMD force (Eq. 12) atom*steps/s, float64 Tersoff Si"
+
 
 # Algorithmic work of the modal current per atom*mode*step: 3 FMAs of the
 # projection (Eq. 13) and 9 of the virial bracket (Eq. 16).  The split
@@ -340,6 +348,98 @@ def run_shc(args):
     return out
 
 
+def run_virial(args):
+    """Tersoff Si: per-atom virial, forces, site energies, float32 W and HNEMD
+    force for every atom per step, inputs resident in HBM."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2102_03691_amd import ModalVirial
+    cells, default_steps = VIRIAL_WORKLOADS[args.workload]
+    K = args.steps or default_steps
+    pos, box = synth.diamond(cells, sigma=0.06, seed=1)
+    N = len(pos)
+    m = synth.masses(N, "natural", 1)
+    vel = synth.thermal_velocities(m, 300.0, 1)
+    fe = np.array([1e-4, 0.0, 0.0])
+    params = dict(A=1830.8, B=471.18, lambda1=2.4799, lambda2=1.7322, lambda3=0.0, m=3, beta=1.1e-6, n=0.78734,
+                  c=1.0039e5, d=16.217, h=-0.59825, gamma=1.0, R=2.85, D=0.15)     # Tersoff Si
+    vir = ModalVirial(m, box, params, max_neighbors=8, skin=0.0)
+    pt = torch.as_tensor(pos, device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0")
+    out = {k: torch.empty(sh, dtype=torch.float32 if k == "W32" else torch.float64, device="cuda:0")
+           for k, sh in (("U", (N,)), ("F", (N, 3)), ("W", (N, 3, 3)), ("W32", (N, 3, 3)), ("Fext", (N, 3)))}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    max_found = vir.neighbors(pt)
+    nb_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(args.warmup):
+        vir.compute(pt, vt, fe, out=out)
+    vir.synchronize()
+    vir.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        vir.compute(pt, vt, fe, out=out)
+    vir.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, site_ms, gather_ms = vir.kernel_timing()
+    vir.set_timing(False)
+    counts, _ = vir.read_neighbors()
+    site_avg, gather_avg = site_ms / max(launches, 1), gather_ms / max(launches, 1)
+    # Dominant kernel: the site kernel, bound by float64 vector arithmetic.  Its
+    # algorithmic operations, from the formulas (exp, pow, sqrt and a division
+    # count one each): 65 per neighbour pair (pair vector and minimum image,
+    # |r| and 1/|r|, f_C, f_R, f_A, b_ij and db/dzeta, the pair energy, the
+    # radial part and the assembly of dU_i/dr_ij) and 79 per ordered pair of
+    # neighbours (the zeta term: cos theta, g, product; the derivative: cos theta,
+    # its gradient, g and g', the dzeta_ij and dzeta_ik terms), plus the U_i sum.
+    n_i = counts.astype(np.float64)
+    flops = float((65.0 * n_i + 79.0 * n_i * (n_i - 1.0) + n_i).sum())
+    roof = {"bound": "alu", "achieved": flops / (site_avg * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
+            "unit": "TFLOP/s", "work": "65 float64 ops per neighbour pair + 79 per ordered pair of neighbours",
+            "flop_per_launch": flops, "traffic": profiled_traffic(args.workload, "k_tersoff_site"),
+            "kernel": "k_tersoff_site", "avg_launch_ms": site_avg, "launches": launches,
+            "gather_kernel_avg_ms": gather_avg}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    # the gather kernel is bound by HBM: the pair partials written by the site
+    # kernel (read twice, 24 B per pair each), the lists (8 B per pair + 4 B),
+    # positions, velocities, masses and U (64 B) and the outputs (156 B)
+    gb = float((48.0 * n_i + 8.0 * n_i + 4.0 + 64.0 + 156.0).sum())
+    roof["gather_hbm_GBps"] = gb / (gather_avg * 1e-3) / 1e9
+    res = {"metric": VIRIAL_METRIC, "value": N * K / wall, "unit": "atom*steps/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "atoms": N, "cells": list(cells), "potential": "Tersoff Si",
+                      "neighbors_per_atom": 4, "max_found": max_found, "neighbor_build_ms": nb_ms,
+                      "outputs": "U, F, W (f64 and f32), F_ext", "parallelism": "single GPU"},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        import oracle.virial as ov
+        log("accuracy: sampled atoms against the FP64 oracle")
+        got = {k: t.cpu().numpy() for k, t in out.items()}
+        rng = np.random.default_rng(3)
+        idx = np.sort(rng.choice(N, size=48, replace=False))
+        ref = ov.evaluate_atoms(pos, box, vel, m, fe, ov.tersoff_si(), idx)
+        res["rel_err_vs_oracle"] = {
+            **{k: float(np.abs(got[k][idx] - ref[k]).max() / np.abs(ref[k]).max()) for k in ("U", "F", "W", "Fext")},
+            "oracle": "oracle.virial.evaluate_atoms (FP64, each sampled atom on its own)",
+            "sample": "48 random atoms of the timed configuration", "norm": "max |diff| / max |ref| per array"}
+        log("cpu baseline (oracle)")
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < 12.0:
+            ov.evaluate_atoms(pos, box, vel, m, fe, ov.tersoff_si(), rng.choice(N, size=16, replace=False))
+            done += 16
+        spent = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": done / spent, "unit": "atom*steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{done} random atoms evaluated one by one (pure Python float64, brute-force "
+                                         f"neighbour search included), {spent:.1f} s"}
+    vir.close()
+    return res
+
+
 def run_group(args, prec):
     """The uneven batch as one grouped push per block (graph replay, autotuned tiles)."""
     import torch
@@ -450,7 +550,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
-                    choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS) + sorted(SHC_WORKLOADS))
+                    choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS) + sorted(SHC_WORKLOADS)
+                    + sorted(VIRIAL_WORKLOADS))
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -481,6 +582,9 @@ def main():
         return
     if args.workload in SHC_WORKLOADS:
         print(json.dumps(run_shc(args)), flush=True)
+        return
+    if args.workload in VIRIAL_WORKLOADS:
+        print(json.dumps(run_virial(args)), flush=True)
         return
     dims, t_block, prec, methods, nb, L, default_steps = WORKLOADS[args.workload]
     K = args.steps or default_steps

@@ -505,8 +505,9 @@ typedef struct {
  * in [1, 64] (atoms within R + D + skin); skin >= 0 widens the neighbour lists
  * so that they stay valid while atoms move less than skin / 2 (pairs beyond
  * R + D contribute exactly zero).  hip_stream as for mhc_create.
- * Device memory: about N (12 max_neighbors + 1) doubles and N (2 max_neighbors
- * + 4) ints.  Errors: INVALID_ARG, OOM, HIP (mhc_virial_last_error(NULL)). */
+ * Device memory: about N (3 max_neighbors + 2) doubles and N (2 max_neighbors
+ * + 3) ints, plus at most 3 (8N + 64) ints of cells.
+ * Errors: INVALID_ARG, OOM, HIP (mhc_virial_last_error(NULL)). */
 mhc_status mhc_virial_create(int device, void *hip_stream, int64_t n_atoms, const double *mass_amu,
                              const double *box, const mhc_tersoff_params *params, int32_t max_neighbors,
                              double skin, mhc_virial **out);
@@ -542,10 +543,11 @@ mhc_status mhc_virial_compute(mhc_virial *v, const double *pos, const double *ve
                               double *F, double *W, float *W32, double *Fext);
 mhc_status mhc_virial_synchronize(mhc_virial *v);
 
-/* HIP-event timing of each evaluation (both kernels), as mhc_set_timing /
- * mhc_kernel_timing. */
+/* HIP-event timing of each evaluation, as mhc_set_timing / mhc_kernel_timing:
+ * the summed milliseconds of the per-atom site kernel (bond orders, site
+ * energies, partials) and of the gather kernel (forces, W, F_ext) apart. */
 mhc_status mhc_virial_set_timing(mhc_virial *v, int enable);
-mhc_status mhc_virial_kernel_timing(mhc_virial *v, int64_t *launches, double *total_ms);
+mhc_status mhc_virial_kernel_timing(mhc_virial *v, int64_t *launches, double *site_ms, double *gather_ms);
 
 #ifdef __cplusplus
 }

@@ -93,50 +93,96 @@ def _vec(pos, box, i, j):
     return min_image(np.asarray(pos[j], dtype=np.float64) - np.asarray(pos[i], dtype=np.float64), box)
 
 
+def _bond_terms_one(pos, box, p, i, js):
+    """zeta_ij, b_ij and db_ij/dzeta_ij for the neighbours js of atom i."""
+    rv = [_vec(pos, box, i, j) for j in js]
+    rn = [float(np.linalg.norm(x)) for x in rv]
+    zi, bi, dbi = [], [], []
+    for s in range(len(js)):
+        z = 0.0
+        for q in range(len(js)):
+            if q == s:
+                continue
+            fc, _ = cutoff_fn(rn[q], p["R"], p["D"])
+            cos = float(rv[s] @ rv[q]) / (rn[s] * rn[q])
+            g, _ = angle_fn(cos, p)
+            e, _ = exp_fn(rn[s] - rn[q], p)
+            z += fc * g * e
+        n, beta = p["n"], p["beta"]
+        bz = (beta * z) ** n
+        bb = (1.0 + bz) ** (-0.5 / n)
+        # d b / d zeta = -1/2 beta^n zeta^(n-1) (1 + (beta zeta)^n)^(-1/(2n) - 1), zero at zeta = 0
+        dbb = 0.0 if z == 0.0 else -0.5 * bz / z * (1.0 + bz) ** (-0.5 / n - 1.0)
+        zi.append(z)
+        bi.append(bb)
+        dbi.append(dbb)
+    return zi, bi, dbi
+
+
 def bond_terms(pos, box, p, nl):
     """zeta_ij, b_ij and db_ij/dzeta_ij for every neighbour j of every atom i:
     lists indexed [i][s] for j = nl[i][s]."""
-    zeta, b, db = [], [], []
-    for i in range(len(nl)):
-        rv = [_vec(pos, box, i, j) for j in nl[i]]
-        rn = [float(np.linalg.norm(x)) for x in rv]
-        zi, bi, dbi = [], [], []
-        for s in range(len(nl[i])):
-            z = 0.0
-            for q in range(len(nl[i])):
-                if q == s:
-                    continue
-                fc, _ = cutoff_fn(rn[q], p["R"], p["D"])
-                cos = float(rv[s] @ rv[q]) / (rn[s] * rn[q])
-                g, _ = angle_fn(cos, p)
-                e, _ = exp_fn(rn[s] - rn[q], p)
-                z += fc * g * e
-            n, beta = p["n"], p["beta"]
-            bz = (beta * z) ** n
-            bb = (1.0 + bz) ** (-0.5 / n)
-            # d b / d zeta = -1/2 beta^n zeta^(n-1) (1 + (beta zeta)^n)^(-1/(2n) - 1), zero at zeta = 0
-            dbb = 0.0 if z == 0.0 else -0.5 * bz / z * (1.0 + bz) ** (-0.5 / n - 1.0)
-            zi.append(z)
-            bi.append(bb)
-            dbi.append(dbb)
-        zeta.append(zi)
-        b.append(bi)
-        db.append(dbi)
-    return zeta, b, db
+    out = [_bond_terms_one(pos, box, p, i, nl[i]) for i in range(len(nl))]
+    return [o[0] for o in out], [o[1] for o in out], [o[2] for o in out]
+
+
+def _site_energy_one(pos, box, p, i, js):
+    _, b, _ = _bond_terms_one(pos, box, p, i, js)
+    acc = []
+    for s, j in enumerate(js):
+        r = float(np.linalg.norm(_vec(pos, box, i, j)))
+        fc, _ = cutoff_fn(r, p["R"], p["D"])
+        acc.append(fc * (p["A"] * math.exp(-p["lambda1"] * r) - b[s] * p["B"] * math.exp(-p["lambda2"] * r)))
+    return 0.5 * math.fsum(acc)
 
 
 def site_energies(pos, box, p, nl) -> np.ndarray:
     """U_i of the Tersoff form above, [N]."""
-    _, b, _ = bond_terms(pos, box, p, nl)
-    U = np.zeros(len(nl))
-    for i in range(len(nl)):
-        acc = []
-        for s, j in enumerate(nl[i]):
-            r = float(np.linalg.norm(_vec(pos, box, i, j)))
-            fc, _ = cutoff_fn(r, p["R"], p["D"])
-            acc.append(fc * (p["A"] * math.exp(-p["lambda1"] * r) - b[i][s] * p["B"] * math.exp(-p["lambda2"] * r)))
-        U[i] = 0.5 * math.fsum(acc)
-    return U
+    return np.array([_site_energy_one(pos, box, p, i, nl[i]) for i in range(len(nl))], dtype=np.float64)
+
+
+def _site_partials_one(pos, box, p, i, js) -> np.ndarray:
+    """dU_i/dr_ij for the neighbours js of atom i, [len(js), 3] (see site_energy_partials)."""
+    _, b, db = _bond_terms_one(pos, box, p, i, js)
+    nj = len(js)
+    rv = [_vec(pos, box, i, j) for j in js]
+    rn = [float(np.linalg.norm(x)) for x in rv]
+    fc = [cutoff_fn(r, p["R"], p["D"]) for r in rn]
+    a = [fc[q][0] * p["B"] * math.exp(-p["lambda2"] * rn[q]) for q in range(nj)]
+
+    def dcos_drij(s, q):
+        # derivative of cos theta between r_s and r_q with respect to r_s
+        c = float(rv[s] @ rv[q]) / (rn[s] * rn[q])
+        return rv[q] / (rn[s] * rn[q]) - c * rv[s] / (rn[s] ** 2), c
+
+    D = np.zeros((nj, 3))
+    for s in range(nj):
+        r, u = rn[s], rv[s] / rn[s]
+        fcs, dfcs = fc[s]
+        fr, dfr = p["A"] * math.exp(-p["lambda1"] * r), -p["lambda1"] * p["A"] * math.exp(-p["lambda1"] * r)
+        fa, dfa = p["B"] * math.exp(-p["lambda2"] * r), -p["lambda2"] * p["B"] * math.exp(-p["lambda2"] * r)
+        grad = 0.5 * (dfcs * (fr - b[s] * fa) + fcs * (dfr - b[s] * dfa)) * u
+        # k = j: every term l != j of zeta_ij depends on r_ij
+        dz = np.zeros(3)
+        for q in range(nj):
+            if q == s:
+                continue
+            dc, c = dcos_drij(s, q)
+            g, dg = angle_fn(c, p)
+            e, de = exp_fn(rn[s] - rn[q], p)
+            dz += fc[q][0] * (dg * dc * e + g * de * u)
+        grad -= 0.5 * a[s] * db[s] * dz
+        # k != j: the term l = j of zeta_ik
+        for q in range(nj):
+            if q == s:
+                continue
+            dc, c = dcos_drij(s, q)      # cos theta_ikj, differentiated in r_ij
+            g, dg = angle_fn(c, p)
+            e, de = exp_fn(rn[q] - rn[s], p)
+            dzq = dfcs * g * e * u + fcs * dg * dc * e - fcs * g * de * u
+            grad -= 0.5 * a[q] * db[q] * dzq
+        D[s] = grad
+    return D
 
 
 def site_energy_partials(pos, box, p, nl):
@@ -148,49 +194,7 @@ def site_energy_partials(pos, box, p, nl):
     where k runs over all neighbours of i: zeta_ij depends on r_ij through every
     term of its sum, zeta_ik (k != j) through its term l = j.
     """
-    _, b, db = bond_terms(pos, box, p, nl)
-    out = []
-    for i in range(len(nl)):
-        nj = len(nl[i])
-        rv = [_vec(pos, box, i, j) for j in nl[i]]
-        rn = [float(np.linalg.norm(x)) for x in rv]
-        fc = [cutoff_fn(r, p["R"], p["D"]) for r in rn]
-        a = [fc[q][0] * p["B"] * math.exp(-p["lambda2"] * rn[q]) for q in range(nj)]
-
-        def dcos_drij(s, q):
-            # derivative of cos theta between r_s and r_q with respect to r_s
-            c = float(rv[s] @ rv[q]) / (rn[s] * rn[q])
-            return rv[q] / (rn[s] * rn[q]) - c * rv[s] / (rn[s] ** 2), c
-
-        D = np.zeros((nj, 3))
-        for s in range(nj):
-            r, u = rn[s], rv[s] / rn[s]
-            fcs, dfcs = fc[s]
-            fr, dfr = p["A"] * math.exp(-p["lambda1"] * r), -p["lambda1"] * p["A"] * math.exp(-p["lambda1"] * r)
-            fa, dfa = p["B"] * math.exp(-p["lambda2"] * r), -p["lambda2"] * p["B"] * math.exp(-p["lambda2"] * r)
-            grad = 0.5 * (dfcs * (fr - b[i][s] * fa) + fcs * (dfr - b[i][s] * dfa)) * u
-            # k = j: every term l != j of zeta_ij depends on r_ij
-            dz = np.zeros(3)
-            for q in range(nj):
-                if q == s:
-                    continue
-                dc, c = dcos_drij(s, q)
-                g, dg = angle_fn(c, p)
-                e, de = exp_fn(rn[s] - rn[q], p)
-                dz += fc[q][0] * (dg * dc * e + g * de * u)
-            grad -= 0.5 * a[s] * db[i][s] * dz
-            # k != j: the term l = j of zeta_ik
-            for q in range(nj):
-                if q == s:
-                    continue
-                dc, c = dcos_drij(s, q)      # cos theta_ikj, differentiated in r_ij
-                g, dg = angle_fn(c, p)
-                e, de = exp_fn(rn[q] - rn[s], p)
-                dzq = dfcs * g * e * u + fcs * dg * dc * e - fcs * g * de * u
-                grad -= 0.5 * a[q] * db[i][q] * dzq
-            D[s] = grad
-        out.append(D)
-    return out
+    return [_site_partials_one(pos, box, p, i, nl[i]) for i in range(len(nl))]
 
 
 def _partial(Dp, nl, j, i):
@@ -276,6 +280,43 @@ def hnemd_force_eq12(E, W, fe) -> np.ndarray:
     """Eq. 12: F_i^ext = E_i F_e + F_e . W_i, (F_e . W_i)^nu = sum_mu F_e^mu W_i^{mu nu}."""
     fe = np.asarray(fe, dtype=np.float64)
     return np.asarray(E, dtype=np.float64)[:, None] * fe[None, :] + np.einsum("m,imn->in", fe, W)
+
+
+def evaluate_atoms(pos, box, vel, mass, fe, p, atoms) -> dict:
+    """The quantities of evaluate() for the listed atoms only, each computed on
+    its own: the neighbour lists of the atom and of its neighbours by brute
+    force, then U_i, F_i (Eq. 4), W_i (Eq. 8) and F_i^ext (Eq. 12).  For
+    sampling systems too large for the whole-system functions."""
+    pos = np.asarray(pos, dtype=np.float64)
+    rc = p["R"] + p["D"]
+    lists = {}
+
+    def nl_of(i):
+        if i not in lists:
+            r = np.linalg.norm(min_image(pos - pos[i], box), axis=1)
+            lists[i] = [int(j) for j in np.nonzero(r < rc)[0] if j != i]
+        return lists[i]
+
+    fe = np.asarray(fe, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    out = {k: [] for k in ("U", "F", "W", "Fext")}
+    for i in atoms:
+        js = nl_of(int(i))
+        Di = _site_partials_one(pos, box, p, int(i), js)
+        U = _site_energy_one(pos, box, p, int(i), js)
+        F = np.zeros(3)
+        W = np.zeros((3, 3))
+        for s, j in enumerate(js):
+            jl = nl_of(j)
+            dji = _site_partials_one(pos, box, p, j, jl)[jl.index(int(i))]
+            F += Di[s] - dji
+            W += np.outer(_vec(pos, box, int(i), j), dji)
+        E = U + 0.5 * float(mass[i]) * float(vel[i] @ vel[i]) * KE_UNIT
+        out["U"].append(U)
+        out["F"].append(F)
+        out["W"].append(W)
+        out["Fext"].append(E * fe + fe @ W)
+    return {k: np.array(v) for k, v in out.items()}
 
 
 def evaluate(pos, box, vel, mass, fe, p, nl=None) -> dict:

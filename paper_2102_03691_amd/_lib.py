@@ -114,7 +114,7 @@ def library():
         "mhc_virial_compute": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "mhc_virial_synchronize": (i32, [vp]),
         "mhc_virial_set_timing": (i32, [vp, C.c_int]),
-        "mhc_virial_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
+        "mhc_virial_kernel_timing": (i32, [vp, P(i64), P(dbl), P(dbl)]),
         "mhc_group_create": (i32, [P(vp), i32, i32, P(vp)]),
         "mhc_group_destroy": (i32, [vp]),
         "mhc_group_last_error": (C.c_char_p, [vp]),
@@ -676,7 +676,10 @@ class ModalVirial:
         self._check(self._lib.mhc_virial_set_timing(self._h, int(bool(enable))), "virial set_timing")
 
     def kernel_timing(self):
+        """(evaluations, summed site-kernel ms, summed gather-kernel ms) since the last call."""
         n = C.c_int64()
-        ms = C.c_double()
-        self._check(self._lib.mhc_virial_kernel_timing(self._h, C.byref(n), C.byref(ms)), "virial kernel_timing")
-        return n.value, ms.value
+        ms_site = C.c_double()
+        ms_gather = C.c_double()
+        self._check(self._lib.mhc_virial_kernel_timing(self._h, C.byref(n), C.byref(ms_site), C.byref(ms_gather)),
+                    "virial kernel_timing")
+        return n.value, ms_site.value, ms_gather.value

@@ -9,19 +9,26 @@
 //   zeta_ij = sum_{k != j} f_C(r_ik) g(cos theta_ijk) exp(l3^m (r_ij - r_ik)^m)
 //   g(c)    = gamma (1 + c0^2/d^2 - c0^2/(d^2 + (c - h)^2)).
 //
-// Pipeline (one thread per atom everywhere, deterministic):
+// Pipeline (deterministic: fixed summation orders, sorted lists):
 //   neighbours (every few MD steps): cell of each atom (counting sort with
-//     atomics), exclusive scan of the cell counts, cell fill, per-atom scan
-//     of the 27 surrounding cells (minimum image, r < R + D), list sorted by
-//     atom index (so the result does not depend on the order the atomics
-//     filled the cells), reverse slots (where i sits in j's list);
-//   per evaluation: k_tersoff_site -- pair vectors, bond orders, U_i and the
-//     partials dU_i/dr_ij of atom i's own neighbours; k_tersoff_gather --
-//     forces, the Eq. 8 virial (the partial dU_j/dr_ji read from j's list
-//     through the reverse slot), Eq. 12 and the float32 copy of W_i in the
-//     layout the modal-current push takes.
-// Pair arrays are slot-major, [slot][N], so that the threads of a wave read
-// consecutive addresses.
+//     atomics), exclusive scan of the cell counts (per-block sums, their
+//     scan, per-block scans), cell fill, per-atom scan of the 27 surrounding
+//     cells (minimum image, r < R + D + skin), list sorted by atom index (so
+//     the result does not depend on the order the atomics filled the cells),
+//     reverse slots (where i sits in j's list);
+//   per evaluation, LPA lanes per atom (one per neighbour slot, LPA the
+//     next power of two >= the largest neighbour count, at least 4), the
+//     pair values of an atom shared through LDS:
+//     k_tersoff_site -- pair vector, f_C, the two exponentials, zeta_ij,
+//       b_ij, db_ij/dzeta_ij; U_i (summed in slot order by the first lane);
+//       the partial dU_i/dr_ij of the lane's pair;
+//     k_tersoff_gather -- per pair dU_i/dr_ij - dU_j/dr_ji and
+//       r_ij (x) dU_j/dr_ji (the second partial read from j's list through the
+//       reverse slot), summed in slot order into F_i and W_i (Eq. 8), then
+//       E_i, F_ext (Eq. 12) and the float32 copy of W_i in the layout the
+//       modal-current push takes.
+// Pair arrays are slot-major, [slot][N]: the lanes of a wave read 64/LPA
+// consecutive atoms of each slot.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,28 +62,59 @@ __global__ void __launch_bounds__(256) k_cell_count(const double* __restrict__ p
   atomicAdd(&count[c], 1);
 }
 
-// Exclusive scan of n counts into start[0..n] (start[n] = total), one work-group.
-__global__ void __launch_bounds__(1024) k_cell_scan(const int* __restrict__ count, int n, int* __restrict__ start) {
-  __shared__ int part[1024];
+// Exclusive scan of n counts into start[0..n] (start[n] = total) in three
+// passes over tiles of SCAN_TILE counts: per-tile sums, an exclusive scan of
+// the tile sums (one work-group), then every tile's own scan plus its offset.
+constexpr int SCAN_TILE = 1024;
+
+// Inclusive scan of one value per thread over a 1024-thread work-group.
+__device__ __forceinline__ int block_scan_incl(int v, int* sh) {
   const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int b0 = t * per, b1 = min(n, b0 + per);
-  int s = 0;
-  for (int c = b0; c < b1; ++c) s += count[c];
-  part[t] = s;
+  sh[t] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan of the partial sums
-    const int v = t >= off ? part[t - off] : 0;
+  for (int off = 1; off < SCAN_TILE; off <<= 1) {
+    const int w = t >= off ? sh[t - off] : 0;
     __syncthreads();
-    part[t] += v;
+    sh[t] += w;
     __syncthreads();
   }
-  int run = t == 0 ? 0 : part[t - 1];
-  for (int c = b0; c < b1; ++c) {
-    start[c] = run;
-    run += count[c];
+  const int r = sh[t];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_tile_sums(const int* __restrict__ count, int n, int* __restrict__ sums) {
+  __shared__ int sh[SCAN_TILE];
+  const int c = blockIdx.x * SCAN_TILE + threadIdx.x;
+  const int v = block_scan_incl(c < n ? count[c] : 0, sh);
+  if (threadIdx.x == SCAN_TILE - 1) sums[blockIdx.x] = v;
+}
+
+// Exclusive scan of the tile sums in place (n_tiles values, any count).
+__global__ void __launch_bounds__(1024) k_scan_tile_offsets(int* __restrict__ sums, int n_tiles) {
+  __shared__ int sh[SCAN_TILE];
+  __shared__ int total;
+  int run = 0;
+  for (int base = 0; base < n_tiles; base += SCAN_TILE) {
+    const int c = base + threadIdx.x;
+    const int v = c < n_tiles ? sums[c] : 0;
+    const int incl = block_scan_incl(v, sh);
+    if (c < n_tiles) sums[c] = run + incl - v;
+    if (threadIdx.x == SCAN_TILE - 1) total = incl;
+    __syncthreads();
+    run += total;
+    __syncthreads();
   }
-  if (t == 1023) start[n] = part[1023];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(const int* __restrict__ count, int n,
+                                                     const int* __restrict__ offsets, int* __restrict__ start) {
+  __shared__ int sh[SCAN_TILE];
+  const int c = blockIdx.x * SCAN_TILE + threadIdx.x;
+  const int v = c < n ? count[c] : 0;
+  const int incl = block_scan_incl(v, sh) + offsets[blockIdx.x];
+  if (c < n) start[c] = incl - v;
+  if (c == n - 1) start[n] = incl;
 }
 
 __global__ void __launch_bounds__(256) k_cell_fill(int64_t N, const int* __restrict__ cell_of,
@@ -173,9 +211,9 @@ __device__ __forceinline__ void cutoff_fn(const TersoffParams& p, double r, doub
 
 __device__ __forceinline__ void angle_fn(const TersoffParams& p, double cs, double* g, double* dg) {
   const double t = cs - p.h;
-  const double den = p.d2 + t * t;
-  *g = p.gamma * (1.0 + p.c2 / p.d2 - p.c2 / den);
-  *dg = p.gamma * p.c2 * 2.0 * t / (den * den);
+  const double inv = 1.0 / (p.d2 + t * t);
+  *g = p.gamma * (1.0 + p.c2d2 - p.c2 * inv);
+  *dg = p.gamma * p.c2 * 2.0 * t * inv * inv;
 }
 
 // exp(l3^m x^m) and its derivative in x (m = 1 or 3)
@@ -190,130 +228,144 @@ __device__ __forceinline__ void exp_fn(const TersoffParams& p, double x, double*
   *de = *e * p.m * p.l3m * xm1;
 }
 
-// Per atom i: pair vectors of its neighbours, the bond orders b_ij and
-// db_ij/dzeta_ij, the site energy U_i and the partials dU_i/dr_ij.
+// LPA lanes per atom: lane s of the group handles the pair (i, j = nbr[s][i]).
+// Each lane publishes its pair values in LDS (field-major, sh[field][lane]);
+// the others read them after a barrier.
+template <int LPA>
 __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffParams p) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sh[8][256];
+  const int tid = threadIdx.x;
+  const int s = tid & (LPA - 1);
+  const int g0 = tid - s;
   const int64_t N = a.N;
-  if (i >= N) return;
-  const int n = a.n_nb[i];
-  const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
-  double* rx = a.rv;
-  double* ry = a.rv + (int64_t)a.max_nb * N;
-  double* rz = a.rv + 2 * (int64_t)a.max_nb * N;
-  double* rr = a.rv + 3 * (int64_t)a.max_nb * N;
-  for (int s = 0; s < n; ++s) {
+  const int64_t i = ((int64_t)blockIdx.x * 256 + tid) / LPA;
+  const int n = i < N ? a.n_nb[i] : 0;
+  const bool act = s < n;
+  double x = 0.0, y = 0.0, z = 0.0, r = 1.0, ir = 1.0, fc = 0.0, dfc = 0.0, er = 0.0, ea = 0.0;
+  if (act) {
     const int64_t j = a.nbr[(int64_t)s * N + i];
-    const double dx = min_image(a.pos[3 * j] - xi, a.box[0]);
-    const double dy = min_image(a.pos[3 * j + 1] - yi, a.box[1]);
-    const double dz = min_image(a.pos[3 * j + 2] - zi, a.box[2]);
-    const int64_t e = (int64_t)s * N + i;
-    rx[e] = dx;
-    ry[e] = dy;
-    rz[e] = dz;
-    rr[e] = sqrt(dx * dx + dy * dy + dz * dz);
+    x = min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0]);
+    y = min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1]);
+    z = min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2]);
+    r = sqrt(x * x + y * y + z * z);
+    ir = 1.0 / r;
+    cutoff_fn(p, r, &fc, &dfc);
+    er = p.A * exp(-p.l1 * r);         // f_R
+    ea = p.B * exp(-p.l2 * r);         // f_A (the attractive term enters as -b f_A)
   }
-  // bond orders and the site energy
-  double u = 0.0;
-  for (int s = 0; s < n; ++s) {
-    const int64_t es = (int64_t)s * N + i;
-    const double sx = rx[es], sy = ry[es], sz = rz[es], rs = rr[es];
-    double z = 0.0;
+  sh[0][tid] = x;
+  sh[1][tid] = y;
+  sh[2][tid] = z;
+  sh[3][tid] = r;
+  sh[4][tid] = ir;
+  sh[5][tid] = fc;
+  __syncthreads();
+  double b = 1.0, adb = 0.0, u = 0.0;
+  if (act) {
+    double zeta = 0.0;
     for (int q = 0; q < n; ++q) {
       if (q == s) continue;
-      const int64_t eq = (int64_t)q * N + i;
-      const double rq = rr[eq];
-      double fc, dfc, g, dg, e, de;
-      cutoff_fn(p, rq, &fc, &dfc);
-      const double cs = (sx * rx[eq] + sy * ry[eq] + sz * rz[eq]) / (rs * rq);
+      const int l = g0 + q;
+      const double cs = (x * sh[0][l] + y * sh[1][l] + z * sh[2][l]) * ir * sh[4][l];
+      double g, dg, e, de;
       angle_fn(p, cs, &g, &dg);
-      exp_fn(p, rs - rq, &e, &de);
-      z += fc * g * e;
+      exp_fn(p, r - sh[3][l], &e, &de);
+      zeta += sh[5][l] * g * e;
     }
-    const double bz = pow(p.beta * z, p.n);
-    const double b = pow(1.0 + bz, -0.5 / p.n);
-    const double db = z == 0.0 ? 0.0 : -0.5 * bz / z * pow(1.0 + bz, -0.5 / p.n - 1.0);
-    double fc, dfc;
-    cutoff_fn(p, rs, &fc, &dfc);
-    const double fa = p.B * exp(-p.l2 * rs);
-    u += fc * (p.A * exp(-p.l1 * rs) - b * fa);
-    a.bb[es] = b;
-    a.adb[es] = fc * fa * db;           // a_ij db_ij/dzeta_ij, a_ij = f_C(r_ij) B exp(-l2 r_ij)
+    // (beta zeta)^n and (1 + bz)^(-1/(2n)) through exp and log (zeta = 0 gives bz = 0)
+    const double bz = exp(p.n * log(p.beta * zeta));
+    b = exp(-0.5 / p.n * log1p(bz));
+    // db/dzeta = -1/2 beta^n zeta^(n-1) (1 + (beta zeta)^n)^(-1/(2n) - 1) = -b bz / (2 zeta (1 + bz))
+    const double db = zeta == 0.0 ? 0.0 : -0.5 * b * bz / (zeta * (1.0 + bz));
+    adb = fc * ea * db;
+    u = fc * (er - b * ea);
   }
-  a.U[i] = 0.5 * u;
-  // partials dU_i/dr_ij
-  double* d0 = a.dd;
-  double* d1 = a.dd + (int64_t)a.max_nb * N;
-  double* d2 = a.dd + 2 * (int64_t)a.max_nb * N;
-  for (int s = 0; s < n; ++s) {
-    const int64_t es = (int64_t)s * N + i;
-    const double sx = rx[es], sy = ry[es], sz = rz[es], rs = rr[es];
-    const double ux = sx / rs, uy = sy / rs, uz = sz / rs;
-    double fcs, dfcs;
-    cutoff_fn(p, rs, &fcs, &dfcs);
-    const double fr = p.A * exp(-p.l1 * rs), fa = p.B * exp(-p.l2 * rs);
-    const double b = a.bb[es];
-    const double radial = 0.5 * (dfcs * (fr - b * fa) + fcs * (-p.l1 * fr + p.l2 * b * fa));
-    double gx = radial * ux, gy = radial * uy, gz = radial * uz;
-    double zx = 0.0, zy = 0.0, zz = 0.0;          // d zeta_ij / d r_ij
-    double kx = 0.0, ky = 0.0, kz = 0.0;          // sum_k a_ik db_ik d zeta_ik / d r_ij, k != j
-    for (int q = 0; q < n; ++q) {
-      if (q == s) continue;
-      const int64_t eq = (int64_t)q * N + i;
-      const double qx = rx[eq], qy = ry[eq], qz = rz[eq], rq = rr[eq];
-      const double cs = (sx * qx + sy * qy + sz * qz) / (rs * rq);
-      // d cos theta / d r_ij
-      const double cx = qx / (rs * rq) - cs * sx / (rs * rs);
-      const double cy = qy / (rs * rq) - cs * sy / (rs * rs);
-      const double cz = qz / (rs * rq) - cs * sz / (rs * rs);
-      double fcq, dfcq, g, dg, e1, de1, e2, de2;
-      cutoff_fn(p, rq, &fcq, &dfcq);
-      angle_fn(p, cs, &g, &dg);
-      exp_fn(p, rs - rq, &e1, &de1);
-      exp_fn(p, rq - rs, &e2, &de2);
-      zx += fcq * (dg * cx * e1 + g * de1 * ux);
-      zy += fcq * (dg * cy * e1 + g * de1 * uy);
-      zz += fcq * (dg * cz * e1 + g * de1 * uz);
-      const double w = a.adb[eq];
-      kx += w * (dfcs * g * e2 * ux + fcs * dg * cx * e2 - fcs * g * de2 * ux);
-      ky += w * (dfcs * g * e2 * uy + fcs * dg * cy * e2 - fcs * g * de2 * uy);
-      kz += w * (dfcs * g * e2 * uz + fcs * dg * cz * e2 - fcs * g * de2 * uz);
-    }
-    const double w = a.adb[es];
-    gx -= 0.5 * (w * zx + kx);
-    gy -= 0.5 * (w * zy + ky);
-    gz -= 0.5 * (w * zz + kz);
-    d0[es] = gx;
-    d1[es] = gy;
-    d2[es] = gz;
+  sh[6][tid] = adb;
+  sh[7][tid] = u;
+  __syncthreads();
+  if (i < N && s == 0) {
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += sh[7][g0 + q];
+    a.U[i] = 0.5 * acc;
   }
+  if (!act) return;
+  // dU_i/dr_ij for this lane's pair j
+  const double ux = x * ir, uy = y * ir, uz = z * ir;
+  const double radial = 0.5 * (dfc * (er - b * ea) + fc * (-p.l1 * er + p.l2 * b * ea));
+  double zx = 0.0, zy = 0.0, zz = 0.0;   // d zeta_ij / d r_ij
+  double kx = 0.0, ky = 0.0, kz = 0.0;   // sum_{k != j} a_ik db_ik d zeta_ik / d r_ij
+  for (int q = 0; q < n; ++q) {
+    if (q == s) continue;
+    const int l = g0 + q;
+    const double qx = sh[0][l], qy = sh[1][l], qz = sh[2][l], rq = sh[3][l], irq = sh[4][l];
+    const double cs = (x * qx + y * qy + z * qz) * ir * irq;
+    // d cos theta / d r_ij
+    const double cx = qx * ir * irq - cs * x * ir * ir;
+    const double cy = qy * ir * irq - cs * y * ir * ir;
+    const double cz = qz * ir * irq - cs * z * ir * ir;
+    double g, dg, e1, de1, e2, de2;
+    angle_fn(p, cs, &g, &dg);
+    exp_fn(p, r - rq, &e1, &de1);
+    exp_fn(p, rq - r, &e2, &de2);
+    const double fcq = sh[5][l];
+    zx += fcq * (dg * cx * e1 + g * de1 * ux);
+    zy += fcq * (dg * cy * e1 + g * de1 * uy);
+    zz += fcq * (dg * cz * e1 + g * de1 * uz);
+    const double w = sh[6][l];
+    kx += w * (dfc * g * e2 * ux + fc * dg * cx * e2 - fc * g * de2 * ux);
+    ky += w * (dfc * g * e2 * uy + fc * dg * cy * e2 - fc * g * de2 * uy);
+    kz += w * (dfc * g * e2 * uz + fc * dg * cz * e2 - fc * g * de2 * uz);
+  }
+  const int64_t mn = (int64_t)a.max_nb * N, es = (int64_t)s * N + i;
+  a.dd[es] = radial * ux - 0.5 * (adb * zx + kx);
+  a.dd[mn + es] = radial * uy - 0.5 * (adb * zy + ky);
+  a.dd[2 * mn + es] = radial * uz - 0.5 * (adb * zz + kz);
 }
 
-// Per atom i: F_i (Eq. 4 summed), W_i (Eq. 8), E_i and F_ext (Eq. 12).
+// Per pair: dU_i/dr_ij - dU_j/dr_ji (Eq. 4) and r_ij (x) dU_j/dr_ji (Eq. 8);
+// the first lane of each atom sums its pairs in slot order and writes F_i,
+// W_i, E_i and F_ext (Eq. 12).
+template <int LPA>
 __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArgs o) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sh[12][256];
+  const int tid = threadIdx.x;
+  const int s = tid & (LPA - 1);
+  const int g0 = tid - s;
   const int64_t N = a.N;
-  if (i >= N) return;
-  const int n = a.n_nb[i];
-  const int64_t mn = (int64_t)a.max_nb * N;
-  double f[3] = {0.0, 0.0, 0.0};
-  double w[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < n; ++s) {
-    const int64_t es = (int64_t)s * N + i;
+  const int64_t i = ((int64_t)blockIdx.x * 256 + tid) / LPA;
+  const int n = i < N ? a.n_nb[i] : 0;
+  double c[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) c[q] = 0.0;
+  if (s < n) {
+    const int64_t mn = (int64_t)a.max_nb * N, es = (int64_t)s * N + i;
     const int64_t j = a.nbr[es];
     const int64_t ej = (int64_t)a.rev[es] * N + j;
-    const double r[3] = {a.rv[es], a.rv[mn + es], a.rv[2 * mn + es]};
+    const double r[3] = {min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0]),
+                         min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1]),
+                         min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2])};
     const double dij[3] = {a.dd[es], a.dd[mn + es], a.dd[2 * mn + es]};
     const double dji[3] = {a.dd[ej], a.dd[mn + ej], a.dd[2 * mn + ej]};
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
-      f[mu] += dij[mu] - dji[mu];
+      c[mu] = dij[mu] - dji[mu];
 #pragma unroll
-      for (int nu = 0; nu < 3; ++nu) w[3 * mu + nu] += r[mu] * dji[nu];
+      for (int nu = 0; nu < 3; ++nu) c[3 + 3 * mu + nu] = r[mu] * dji[nu];
     }
   }
+#pragma unroll
+  for (int q = 0; q < 12; ++q) sh[q][tid] = c[q];
+  __syncthreads();
+  if (i >= N || s != 0) return;
+  double t[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) t[q] = 0.0;
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int q = 0; q < 12; ++q) t[q] += sh[q][g0 + k];
+  const double* w = t + 3;
   if (o.F)
-    for (int mu = 0; mu < 3; ++mu) o.F[3 * i + mu] = f[mu];
+    for (int mu = 0; mu < 3; ++mu) o.F[3 * i + mu] = t[mu];
   if (o.W)
     for (int q = 0; q < 9; ++q) o.W[9 * i + q] = w[q];
   if (o.W32)
@@ -336,13 +388,17 @@ static inline unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 
 hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, int max_nb,
                             NeighborBufs b) {
   const int n_cells = cg.nc[0] * cg.nc[1] * cg.nc[2];
+  const int n_tiles = (n_cells + SCAN_TILE - 1) / SCAN_TILE;
   hipError_t e;
   hipLaunchKernelGGL(k_fill_zero_i32, dim3(blocks_of(n_cells, 256)), dim3(256), 0, s, b.count, n_cells);
   hipLaunchKernelGGL(k_fill_zero_i32, dim3(blocks_of(n_cells, 256)), dim3(256), 0, s, b.fill, n_cells);
   hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b.flags, 2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cell_count, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, cg, b.cell_of, b.count);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, b.count, n_cells, b.start);
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)n_tiles), dim3(SCAN_TILE), 0, s, b.count, n_cells, b.tile_sums);
+  hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(SCAN_TILE), 0, s, b.tile_sums, n_tiles);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)n_tiles), dim3(SCAN_TILE), 0, s, b.count, n_cells, b.tile_sums,
+                     b.start);
   hipLaunchKernelGGL(k_cell_fill, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, b.cell_of, b.start, b.fill, b.atoms);
   hipLaunchKernelGGL(k_neighbors, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, cg, rc * rc, b.cell_of, b.start,
                      b.atoms, max_nb, b.nbr, b.n_nb, b.flags);
@@ -350,16 +406,40 @@ hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const C
   return hipGetLastError();
 }
 
-hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o,
-                          hipEvent_t e0, hipEvent_t e1) {
-  if (e0) {
-    hipError_t e = hipEventRecord(e0, s);
+template <int LPA>
+static hipError_t launch_pair_kernels(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o,
+                                      hipEvent_t e1) {
+  const unsigned grid = blocks_of(a.N * LPA, 256);
+  hipLaunchKernelGGL(k_tersoff_site<LPA>, dim3(grid), dim3(256), 0, s, a, p);
+  if (e1) {
+    hipError_t e = hipEventRecord(e1, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_tersoff_site, dim3(blocks_of(a.N, 256)), dim3(256), 0, s, a, p);
-  hipLaunchKernelGGL(k_tersoff_gather, dim3(blocks_of(a.N, 256)), dim3(256), 0, s, a, o);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
+  hipLaunchKernelGGL(k_tersoff_gather<LPA>, dim3(grid), dim3(256), 0, s, a, o);
+  return hipSuccess;
+}
+
+int tersoff_lanes(int max_count) {
+  int l = 4;
+  while (l < max_count) l *= 2;
+  return l;
+}
+
+hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o, int lpa,
+                          hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+  hipError_t e = hipSuccess;
+  if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
+  switch (lpa) {
+    case 4: e = launch_pair_kernels<4>(s, a, p, o, e1); break;
+    case 8: e = launch_pair_kernels<8>(s, a, p, o, e1); break;
+    case 16: e = launch_pair_kernels<16>(s, a, p, o, e1); break;
+    case 32: e = launch_pair_kernels<32>(s, a, p, o, e1); break;
+    case 64: e = launch_pair_kernels<64>(s, a, p, o, e1); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (e2) e = hipEventRecord(e2, s);
   return e;
 }
 

@@ -16,8 +16,8 @@ struct CellGrid {
 
 // Device buffers of the neighbour lists: nbr, rev [max_nb][N] (slot-major),
 // n_nb [N]; cell_of [N], atoms [N]; count, fill [n_cells], start [n_cells + 1];
-// flags[0] = largest neighbour count found, flags[1] = 1 if a reverse slot
-// was missing.
+// tile_sums [ceil(n_cells / 1024)] (scan workspace); flags[0] = largest
+// neighbour count found, flags[1] = 1 if a reverse slot was missing.
 struct NeighborBufs {
   int* nbr;
   int* rev;
@@ -27,18 +27,19 @@ struct NeighborBufs {
   int* count;
   int* fill;
   int* start;
+  int* tile_sums;
   int* flags;
 };
 
-// Tersoff parameters as the kernels use them: l3m = lambda3^m, c2 = c^2, d2 = d^2.
+// Tersoff parameters as the kernels use them: l3m = lambda3^m, c2 = c^2, d2 = d^2,
+// c2d2 = c^2 / d^2.
 struct TersoffParams {
-  double A, B, l1, l2, l3m, beta, n, c2, d2, h, gamma, R, D;
+  double A, B, l1, l2, l3m, beta, n, c2, d2, c2d2, h, gamma, R, D;
   int m;
 };
 
-// Per-evaluation buffers: positions (device, [N][3]); neighbour lists; pair
-// arrays rv [4][max_nb][N] (x, y, z, |r|), bb and adb [max_nb][N], dd
-// [3][max_nb][N] (dU_i/dr_ij); site energies U [N].
+// Per-evaluation buffers: positions (device, [N][3]); neighbour lists; the
+// partials dd [3][max_nb][N] (dU_i/dr_ij); site energies U [N].
 struct TersoffArgs {
   const double* pos;
   int64_t N;
@@ -47,9 +48,6 @@ struct TersoffArgs {
   const int* n_nb;
   const int* rev;
   int max_nb;
-  double* rv;
-  double* bb;
-  double* adb;
   double* dd;
   double* U;
 };
@@ -70,8 +68,13 @@ struct GatherArgs {
 
 hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, int max_nb,
                             NeighborBufs b);
-// Queues the site and gather kernels; e0 / e1 (optional) are recorded around them.
-hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o,
-                          hipEvent_t e0, hipEvent_t e1);
+// Lanes per atom of the evaluation kernels for a largest neighbour count:
+// the next power of two, at least 4 (64 at most: max_nb <= 64).
+int tersoff_lanes(int max_count);
+// Queues the site and gather kernels with lpa lanes per atom; the optional
+// events are recorded before the site kernel (e0), between the two (e1) and
+// after the gather kernel (e2).
+hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o, int lpa,
+                          hipEvent_t e0, hipEvent_t e1, hipEvent_t e2);
 
 }  // namespace mhc

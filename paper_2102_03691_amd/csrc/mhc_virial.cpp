@@ -42,7 +42,8 @@ struct mhc_virial {
   std::vector<void*> allocs;
   double* d_mass = nullptr;
   NeighborBufs nb{};
-  double *d_rv = nullptr, *d_bb = nullptr, *d_adb = nullptr, *d_dd = nullptr, *d_U = nullptr;
+  double *d_dd = nullptr, *d_U = nullptr;
+  int lpa = 4;            // lanes per atom of the evaluation kernels (from the largest neighbour count)
 
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -171,7 +172,7 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
   v->cg = make_grid(box, rc, n_atoms);
   const mhc_tersoff_params& p = *params;
   v->tp = TersoffParams{p.A, p.B, p.lambda1, p.lambda2, std::pow(p.lambda3, (double)p.m), p.beta, p.n, p.c * p.c,
-                        p.d * p.d, p.h, p.gamma, p.R, p.D, p.m};
+                        p.d * p.d, (p.c * p.c) / (p.d * p.d), p.h, p.gamma, p.R, p.D, p.m};
   auto cleanup = [&](mhc_status st, const char* msg) {
     vfree(v);
     if (v->own_stream) (void)hipStreamDestroy(v->stream);
@@ -190,8 +191,8 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
   NeighborBufs& b = v->nb;
   bool ok = valloc(v, N, &v->d_mass) && valloc(v, MN, &b.nbr) && valloc(v, MN, &b.rev) && valloc(v, N, &b.n_nb) &&
             valloc(v, N, &b.cell_of) && valloc(v, N, &b.atoms) && valloc(v, n_cells, &b.count) &&
-            valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) && valloc(v, 2, &b.flags) &&
-            valloc(v, 4 * MN, &v->d_rv) && valloc(v, MN, &v->d_bb) && valloc(v, MN, &v->d_adb) &&
+            valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) &&
+            valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 2, &b.flags) &&
             valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U);
   if (!ok) return cleanup(MHC_ERR_OOM, "device allocation failed");
   if (hipMemcpyAsync(v->d_mass, mass_amu, N * sizeof(double), hipMemcpyHostToDevice, v->stream) != hipSuccess ||
@@ -233,6 +234,7 @@ mhc_status mhc_virial_neighbors(mhc_virial* v, const double* pos, int32_t* max_f
                  "an atom has " + std::to_string(flags[0]) + " neighbours within the cutoff, more than max_neighbors = " +
                      std::to_string(v->max_nb));
   if (flags[1]) return vfail(v, MHC_ERR_INVALID_ARG, "neighbour lists are not symmetric (non-finite positions?)");
+  v->lpa = tersoff_lanes(flags[0]);
   v->lists_ok = true;
   return MHC_OK;
 }
@@ -283,9 +285,6 @@ mhc_status mhc_virial_compute(mhc_virial* v, const double* pos, const double* ve
   a.n_nb = v->nb.n_nb;
   a.rev = v->nb.rev;
   a.max_nb = v->max_nb;
-  a.rv = v->d_rv;
-  a.bb = v->d_bb;
-  a.adb = v->d_adb;
   a.dd = v->d_dd;
   a.U = U ? U : v->d_U;
   GatherArgs o{};
@@ -297,19 +296,20 @@ mhc_status mhc_virial_compute(mhc_virial* v, const double* pos, const double* ve
   o.W = W;
   o.W32 = W32;
   o.Fext = Fext;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (v->timing) {
-    if (v->ev_used + 2 > v->ev.size())
-      for (int q = 0; q < 2; ++q) {
+    if (v->ev_used + 3 > v->ev.size())
+      for (int q = 0; q < 3; ++q) {
         hipEvent_t e;
         VHIP_TRY(hipEventCreate(&e), "event create");
         v->ev.push_back(e);
       }
     e0 = v->ev[v->ev_used];
     e1 = v->ev[v->ev_used + 1];
-    v->ev_used += 2;
+    e2 = v->ev[v->ev_used + 2];
+    v->ev_used += 3;
   }
-  VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, e0, e1), "virial kernels");
+  VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, e0, e1, e2), "virial kernels");
   return MHC_OK;
 }
 
@@ -329,19 +329,22 @@ mhc_status mhc_virial_set_timing(mhc_virial* v, int enable) {
   return MHC_OK;
 }
 
-mhc_status mhc_virial_kernel_timing(mhc_virial* v, int64_t* launches, double* total_ms) {
+mhc_status mhc_virial_kernel_timing(mhc_virial* v, int64_t* launches, double* site_ms, double* gather_ms) {
   mhc_status st = venter(v);
   if (st) return st;
   VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
   VHIP_TRY(hipStreamSynchronize(v->stream), "timing sync");
-  double tot = 0.0;
-  for (size_t q = 0; q + 1 < v->ev_used; q += 2) {
-    float ms = 0.0f;
-    VHIP_TRY(hipEventElapsedTime(&ms, v->ev[q], v->ev[q + 1]), "event elapsed");
-    tot += ms;
+  double ts = 0.0, tg = 0.0;
+  for (size_t q = 0; q + 3 <= v->ev_used; q += 3) {
+    float a = 0.0f, b = 0.0f;
+    VHIP_TRY(hipEventElapsedTime(&a, v->ev[q], v->ev[q + 1]), "event elapsed");
+    VHIP_TRY(hipEventElapsedTime(&b, v->ev[q + 1], v->ev[q + 2]), "event elapsed");
+    ts += a;
+    tg += b;
   }
-  if (launches) *launches = (int64_t)(v->ev_used / 2);
-  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)(v->ev_used / 3);
+  if (site_ms) *site_ms = ts;
+  if (gather_ms) *gather_ms = tg;
   v->ev_used = 0;
   return MHC_OK;
 }

@@ -178,6 +178,7 @@ def test_device_virials_feed_the_modal_push(prec, T):
     wblk = torch.empty((S, N, 3, 3), dtype=torch.float32, device="cuda:0")
     v_host = np.empty((S, N, 3), dtype=np.float32)
     W_ref = np.empty((S, N, 3, 3))
+    configs = []
     for s in range(S):
         pos = np.mod(pos0 + rng.standard_normal(pos0.shape) * 0.05, box)
         vel = synth.thermal_velocities(m, 300.0, 100 + s)
@@ -187,7 +188,9 @@ def test_device_virials_feed_the_modal_push(prec, T):
         vir.compute(pt, want=(), out={"W32": wblk[s]})
         v_host[s] = vel.astype(np.float32)
         vblk[s] = torch.as_tensor(v_host[s], device="cuda:0")
-        W_ref[s] = ov.per_atom_virial(pos, box, p, ov.neighbor_lists(pos, box, p["R"] + p["D"]))
+        nl = ov.neighbor_lists(pos, box, p["R"] + p["D"])
+        W_ref[s] = ov.per_atom_virial(pos, box, p, nl)
+        configs.append((pos, nl))
     torch.cuda.synchronize()
     vir.close()
     W32 = W_ref.astype(np.float32)
@@ -206,8 +209,13 @@ def test_device_virials_feed_the_modal_push(prec, T):
     ref = oracle.run_dense(E, m, v_host, W32, bins, nb, corr_len=L)
     e = {"hnema": rel(avg, ref["hnema"]), "corr": rel(g["corr"], ref["corr"]), "total": rel(tot, ref["hnema_total"])}
     log(f"virial_to_push_p{prec}_T{T}", **e)
-    assert n == S and e["hnema"] <= TOL[prec] and e["corr"] <= TOL[prec] and e["total"] <= 1e-12
-    # the Eq. 10 total of the push equals the oracle's Eq. 9 current summed over atoms (float32 W, v)
-    J9 = np.mean([ov.heat_current_eq10(W32[s].astype(np.float64), v_host[s].astype(np.float64)).sum(axis=0)
-                  for s in range(S)], axis=0)
-    assert rel(tot, J9) <= 1e-12
+    assert n == S and e["hnema"] <= TOL[prec] and e["corr"] <= TOL[prec]
+    # the Eq. 10 total of the push against the oracle's Eq. 9 current (float32 W and v): the two
+    # float32 virials may differ by one rounding (2^-24 relative) per element, so the totals agree
+    # to 2^-24 sum |W||v| (plus float64 rounding)
+    Wv = np.abs(W32.astype(np.float64)) * np.abs(v_host.astype(np.float64))[:, :, None, :]
+    bound = 2.0 ** -24 * Wv.sum(axis=(1, 3)).mean(axis=0) + 1e-12 * np.abs(ref["hnema_total"]).max()
+    J9 = np.mean([ov.heat_current_eq9(pos_s, box, v_host[s].astype(np.float64), p, nl_s).sum(axis=0)
+                  for s, (pos_s, nl_s) in enumerate(configs)], axis=0)
+    assert np.all(np.abs(tot - ref["hnema_total"]) <= bound)
+    assert np.all(np.abs(tot - J9) <= bound + 2.0 ** -24 * np.abs(J9))

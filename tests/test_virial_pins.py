@@ -214,6 +214,21 @@ def test_evaluate_bundles_the_same_quantities():
     np.testing.assert_array_equal(out["Fext"], ov.hnemd_force_eq12(out["E"], out["W"], fe))
 
 
+def test_sampled_atoms_equal_the_whole_system():
+    """evaluate_atoms (each atom on its own, for sampling large systems) gives the
+    same bits as the whole-system functions."""
+    p = _exp_on()
+    pos, box = synth.diamond((3, 3, 3), sigma=0.08, seed=2)
+    m = synth.masses(len(pos), "natural", 1)
+    v = synth.thermal_velocities(m, 300.0, 1)
+    fe = np.array([1e-4, 2e-5, -3e-5])
+    full = ov.evaluate(pos, box, v, m, fe, p)
+    idx = [0, 7, 100, 215]
+    sub = ov.evaluate_atoms(pos, box, v, m, fe, p, idx)
+    for k in ("U", "F", "W", "Fext"):
+        np.testing.assert_array_equal(sub[k], full[k][idx])
+
+
 # ------------------------------------------------------------------ mutations
 def test_mutation_partials_of_the_wrong_atom_fail_the_strain_pin():
     """Using dU_i/dr_ij in place of dU_j/dr_ji flips the sign of the total (Eq. 6)."""
