@@ -70,5 +70,59 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host sanitizer build of the test drivers: the host translation units of the C
+# ABI compiled with AddressSanitizer and UndefinedBehaviorSanitizer (host code
+# only; the device code and the kernel objects are the normal build's), linked
+# with the normal build's kernel objects into a separate library that two C99
+# drivers (tests/c) load.  The drivers link the sanitizer runtimes themselves,
+# so no preloading is needed.
+HOST_TUS = ["mhc_api.cpp", "mhc_shc.cpp", "mhc_virial.cpp"]
+ASAN_DIR = os.path.join(ROOT, "tests", "c", "build")
+SAN_HOST = ["-g", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-fsanitize=address",
+            "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined"]
+DRIVERS = ["abi_run.c", "abi_errors.c"]
+
+
+def clang() -> str:
+    for cand in ("/opt/rocm/llvm/bin/clang", "clang"):
+        if os.path.sep not in cand or os.path.exists(cand):
+            return cand
+    return "clang"
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """Build tests/c/build/libmodalhc_asan.so and the sanitized C drivers; needs build() first."""
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    dev_objs = [os.path.join(OBJ_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES if s not in HOST_TUS]
+    missing = [o for o in dev_objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"kernel objects missing ({missing[0]}): run build() first")
+    host_objs = [os.path.join(ASAN_DIR, os.path.splitext(s)[0] + ".o") for s in HOST_TUS]
+    cmds = [[hipcc(), *FLAGS, *SAN_HOST, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(HOST_TUS, host_objs)]
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        results = list(ex.map(_run, cmds))
+    for (rc, err), s in zip(results, HOST_TUS):
+        if rc != 0:
+            raise RuntimeError(f"sanitized hipcc failed on {s} ({rc}):\n{err}")
+    lib = os.path.join(ASAN_DIR, "libmodalhc_asan.so")
+    rc, err = _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *host_objs, *dev_objs, "-o", lib])
+    if rc != 0:
+        raise RuntimeError(f"sanitized link failed ({rc}):\n{err}")
+    for d in DRIVERS:
+        exe = os.path.join(ASAN_DIR, os.path.splitext(d)[0] + "_asan")
+        cmd = [clang(), "-std=c99", "-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined", "-I", os.path.join(ROOT, "include"),
+               os.path.join(ROOT, "tests", "c", d), lib, "-Wl,-rpath," + ASAN_DIR, "-o", exe]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        rc, err = _run(cmd)
+        if rc != 0:
+            raise RuntimeError(f"driver build failed ({d}, {rc}):\n{err}")
+    return lib
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_sanitized(verbose=True))

@@ -258,7 +258,11 @@ extern "C" {
 int mhc_abi_version(void) { return MHC_ABI_VERSION; }
 
 const char* mhc_status_string(mhc_status s) {
-  switch (s) {
+  // a C caller may pass any int: read the bits as an int (loading an
+  // out-of-range value as the enum type is undefined in C++)
+  int v = 0;
+  std::memcpy(&v, &s, sizeof v < sizeof s ? sizeof v : sizeof s);
+  switch (v) {
     case MHC_OK: return "MHC_OK";
     case MHC_ERR_INVALID_ARG: return "MHC_ERR_INVALID_ARG";
     case MHC_ERR_STATE: return "MHC_ERR_STATE";
