@@ -60,6 +60,7 @@ __device__ __forceinline__ void reduce_body(ReduceArgs a, int b) {
       // (from k_reduce_seg); thread t of the work-group, steps strided by 256.
       const int64_t P = (int64_t)a.n_seg + a.nb;
       const int64_t sg0 = lo / REDUCE_SEG, sg1 = (hi - 1) / REDUCE_SEG;
+      const int64_t xo = a.xoff_dev ? *a.xoff_dev : a.xoff;
       double h3[3] = {0.0, 0.0, 0.0};
       for (int t = tid; t < a.t_count; t += 256) {
 #pragma unroll
@@ -67,7 +68,7 @@ __device__ __forceinline__ void reduce_body(ReduceArgs a, int b) {
           double s = 0.0;
           if (n > 0)
             for (int64_t sg = sg0; sg <= sg1; ++sg) s += a.seg_part[((int64_t)mu * P + sg + b) * a.ld + t];
-          a.X[((int64_t)b * 3 + mu) * a.ld + t] = s;
+          a.X[((int64_t)b * 3 + mu) * a.ldx + xo + t] = s;
           if (a.bring) a.bring[((int64_t)b * a.ring_len + (a.t0 + t) % a.ring_len) * 3 + mu] = s;
           h3[mu] += s;
         }
@@ -84,13 +85,14 @@ __device__ __forceinline__ void reduce_body(ReduceArgs a, int b) {
   }
   // last work-group: per-step total current of Eq. 10 (already summed over atoms)
   double h3[3] = {0.0, 0.0, 0.0};
+  const int64_t xo = a.X ? (a.xoff_dev ? *a.xoff_dev : a.xoff) : 0;
   for (int t = tid; t < a.t_count; t += 256) {
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
       const double j = a.jtot[t * 3 + mu];
       h3[mu] += j;
       if (a.X) {
-        a.X[((int64_t)a.nb * 3 + mu) * a.ld + t] = j;
+        a.X[((int64_t)a.nb * 3 + mu) * a.ldx + xo + t] = j;
         a.ring[((a.t0 + t) % a.ring_len) * 3 + mu] = j;
       }
     }
@@ -235,8 +237,17 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void corr_body(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
                                           int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
                                           double* __restrict__ csum, double* __restrict__ ccomp,
-                                          const int64_t* __restrict__ t0_dev, int bx, int by) {
-  if (t0_dev) t0 = *t0_dev;
+                                          const int64_t* __restrict__ t0_dev, const int64_t* __restrict__ tbuf_dev,
+                                          int bx, int by) {
+  if (tbuf_dev) {
+    // buffered steps ending with this block (the same value in every thread)
+    const int64_t tb = *tbuf_dev;
+    if (tb <= 0) return;
+    t0 = *t0_dev + t_count - tb;
+    t_count = (int)tb;
+  } else if (t0_dev) {
+    t0 = *t0_dev;
+  }
   __shared__ double xs[CT][CR + 2];          // xs[t][r]
   __shared__ double rs[3][CT + CL + 2];      // ring window, rs[nu][q]
   const int tid = threadIdx.x;
@@ -250,26 +261,52 @@ __device__ __forceinline__ void corr_body(const double* __restrict__ X, int64_t 
 #pragma unroll
     for (int n = 0; n < 3; ++n) acc[lb][n] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  for (int tc = 0; tc < t_count; tc += CT) {
-    // stage X rows r0.. (t-major in LDS)
-    // (loads are unconditional, from clamped in-range addresses, and the
-    // value is selected afterwards, so that they all issue back to back)
-    for (int idx = tid; idx < CR * CT; idx += 256) {
+  // Staging of a chunk: X rows r0.. (t-major in LDS) and the ring window
+  // (q in [0, CT + CL) <-> global time t0 + tc - tau0 - (CL - 1) + q).  The
+  // next chunk's values are loaded into registers while the current chunk's
+  // products run, and written to LDS after them.  Loads are unconditional,
+  // from clamped in-range addresses, with the value selected afterwards, so
+  // that they all issue back to back.
+  constexpr int XPT = CR * CT / 256;                    // X values per thread
+  constexpr int RPT = ((CT + CL) * 3 + 255) / 256;      // ring values per thread
+  double xr[XPT], rr[RPT];
+  auto fetch = [&](int tc) {
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int idx = tid + 256 * k;
       const int j = idx % CT, i = idx / CT;
       const int64_t r = r0 + i;
       const int tg = tc + j;
       const double x = X[min(r, R3 - 1) * ldx + min(tg, t_count - 1)];
-      xs[j][i] = (r < R3 && tg < t_count) ? x : 0.0;
+      xr[k] = (r < R3 && tg < t_count) ? x : 0.0;
     }
-    // ring window: q in [0, CT + CL) <-> global time g = t0 + tc - tau0 - (CL - 1) + q
-    for (int idx = tid; idx < (CT + CL) * 3; idx += 256) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int idx = min(tid + 256 * k, (CT + CL) * 3 - 1);
       const int q = idx / 3, nu = idx % 3;
       const int64_t gt = t0 + tc - tau0 - (CL - 1) + q;
       const bool ok = gt >= 0 && gt < t0 + t_count;
       const double x = ring[(max(gt, (int64_t)0) % ring_len) * 3 + nu];
-      rs[nu][q] = ok ? x : 0.0;
+      rr[k] = ok ? x : 0.0;
     }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int idx = tid + 256 * k;
+      xs[idx % CT][idx / CT] = xr[k];
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int idx = tid + 256 * k;
+      if (idx < (CT + CL) * 3) rs[idx % 3][idx / 3] = rr[k];
+    }
+  };
+  fetch(0);
+  for (int tc = 0; tc < t_count; tc += CT) {
+    stage();
     __syncthreads();
+    if (tc + CT < t_count) fetch(tc + CT);
     const int jmax = min(CT, t_count - tc);
     for (int j0 = 0; j0 < jmax; j0 += 4) {
       const int j = j0 + g;
@@ -315,25 +352,27 @@ __device__ __forceinline__ void corr_body(const double* __restrict__ X, int64_t 
 __global__ void __launch_bounds__(256) k_corr(const double* __restrict__ X, int64_t ldx, int t_count, int64_t R3,
                                               int L, const double* __restrict__ ring, int64_t ring_len, int64_t t0,
                                               double* __restrict__ csum, double* __restrict__ ccomp,
-                                              const int64_t* __restrict__ t0_dev, int64_t ring_zs, int64_t out_zs) {
+                                              const int64_t* __restrict__ t0_dev, const int64_t* __restrict__ tbuf_dev,
+                                              int64_t ring_zs, int64_t out_zs) {
   // grid z: one history ring of 3 columns and one slice of sums per z
   corr_body(X, ldx, t_count, R3, L, ring + (int64_t)blockIdx.z * ring_zs, ring_len, t0,
-            csum + (int64_t)blockIdx.z * out_zs, ccomp + (int64_t)blockIdx.z * out_zs, t0_dev, blockIdx.x,
+            csum + (int64_t)blockIdx.z * out_zs, ccomp + (int64_t)blockIdx.z * out_zs, t0_dev, tbuf_dev, blockIdx.x,
             blockIdx.y);
 }
 
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
                        const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
-                       const int64_t* t0_dev, int nz, int64_t ring_zs, int64_t out_zs) {
+                       const int64_t* t0_dev, const int64_t* tbuf_dev, int nz, int64_t ring_zs, int64_t out_zs) {
   if (t_count <= 0 || nz <= 0) return hipSuccess;
   dim3 grid((unsigned)((R3 + CR - 1) / CR), (unsigned)((L + CL - 1) / CL), (unsigned)nz);
   hipLaunchKernelGGL(k_corr, grid, dim3(256), 0, s, X, ldx, t_count, R3, L, ring, ring_len, t0, csum, ccomp, t0_dev,
-                     ring_zs, out_zs);
+                     tbuf_dev, ring_zs, out_zs);
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- read-out
 __global__ void __launch_bounds__(256) k_corr_finish(const double* __restrict__ csum, const double* __restrict__ ccomp,
+                                                     const double* __restrict__ psum, const double* __restrict__ pcomp,
                                                      int64_t R3, int L, int64_t S, double dt,
                                                      double* __restrict__ corr, double* __restrict__ integral) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // series (r, nu)
@@ -343,7 +382,9 @@ __global__ void __launch_bounds__(256) k_corr_finish(const double* __restrict__ 
     const int64_t src = q * L + tau;               // sums are lag-contiguous
     const int64_t o = (int64_t)tau * R3 * 3 + q;   // output [tau][r][nu]
     const int64_t cnt = S - tau;
-    const double c = (cnt > 0) ? (csum[src] + ccomp[src]) / (double)cnt : 0.0;
+    double sum = csum[src] + ccomp[src];
+    if (psum) sum += psum[src] + pcomp[src];       // steps not yet in the running sums
+    const double c = (cnt > 0) ? sum / (double)cnt : 0.0;
     corr[o] = c;
     if (tau > 0) G += dt * 0.5 * (prev + c);
     integral[o] = G;
@@ -351,11 +392,12 @@ __global__ void __launch_bounds__(256) k_corr_finish(const double* __restrict__ 
   }
 }
 
-hipError_t launch_corr_finish(hipStream_t s, const double* csum, const double* ccomp, int64_t R3, int L, int64_t S,
-                              double dt, double* corr, double* integral) {
+hipError_t launch_corr_finish(hipStream_t s, const double* csum, const double* ccomp, const double* psum,
+                              const double* pcomp, int64_t R3, int L, int64_t S, double dt, double* corr,
+                              double* integral) {
   const int64_t n = R3 * 3;
-  hipLaunchKernelGGL(k_corr_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, csum, ccomp, R3, L, S, dt,
-                     corr, integral);
+  hipLaunchKernelGGL(k_corr_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, csum, ccomp, psum, pcomp, R3,
+                     L, S, dt, corr, integral);
   return hipGetLastError();
 }
 
@@ -406,8 +448,8 @@ __global__ void __launch_bounds__(256) k_corr_group(const BackDesc* __restrict__
   const int i = back_system(wg0, n, blockIdx.x);
   const BackDesc& s = d[i];
   const int local = blockIdx.x - wg0[i];
-  corr_body(s.X, s.ldx, t_count, s.R3, s.L, s.ring, s.ring_len, 0, s.csum, s.ccomp, s.t0_dev, local % s.n_rt,
-            local / s.n_rt);
+  corr_body(s.X, s.ldx, t_count, s.R3, s.L, s.ring, s.ring_len, 0, s.csum, s.ccomp, s.t0_dev, s.tbuf_dev,
+            local % s.n_rt, local / s.n_rt);
 }
 
 hipError_t launch_back_group(hipStream_t s, const BackGroup& b, int n, int t_count) {

@@ -153,6 +153,11 @@ struct mhc_ctx {
   int n_cu = 256;
   int64_t n_samples = 0;
   int last_block = 0;
+  // GKMA: the binned series of several blocks is kept in X (x_cap columns)
+  // and correlated in one update; X holds steps [x_base, x_base + x_fill),
+  // the last block starting at column x_last
+  int64_t x_cap = 0, x_base = 0, x_fill = 0, x_last = 0;
+  double* d_psum = nullptr;      // reads: correlation of the buffered steps (sum + compensation)
 
   // timing
   bool timing = false;
@@ -609,17 +614,31 @@ static mhc_status finalize_impl(mhc_ctx* ctx) {
   }
   if (gk) {
     void *pX, *pring, *pc;
-    const int64_t ring_len = (int64_t)L - 1 + t_pad;
-    if ((st = dev_alloc(ctx, (size_t)R3 * t_pad * 8, &pX, "binned series"))) return st;
+    // Blocks of binned currents folded into one correlation update, so that
+    // the float64 read-modify-write of the correlation sums happens once per
+    // fold; the matrix-core accumulators sum the fold's steps uncompensated
+    // (at most 1024 steps).  One block per update with the direction split
+    // (its passes share the series buffer) and with cross-correlations (their
+    // bin history would grow with the fold).
+    const int fold = (nd == 1 && !(c.methods & MHC_CROSS)) ? std::max(1, std::min(16, 1024 / t_pad)) : 1;
+    const int64_t x_cap = (int64_t)fold * t_pad;
+    const int64_t ring_len = (int64_t)L - 1 + x_cap;
+    if ((st = dev_alloc(ctx, (size_t)R3 * x_cap * 8, &pX, "binned series"))) return st;
     if ((st = dev_alloc(ctx, (size_t)ring_len * 3 * 8, &pring, "history ring"))) return st;
     if ((st = dev_alloc(ctx, (size_t)2 * nd * L * R3 * 3 * 8, &pc, "correlation sums"))) return st;
     ctx->dX = reinterpret_cast<double*>(pX);
     ctx->d_ring = reinterpret_cast<double*>(pring);
     ctx->ring_len = ring_len;
+    ctx->x_cap = x_cap;
+    if (fold > 1) {   // reads add the buffered steps' correlation from scratch sums
+      void* pp = nullptr;
+      if ((st = dev_alloc(ctx, (size_t)2 * L * R3 * 3 * 8, &pp, "pending correlation sums"))) return st;
+      ctx->d_psum = reinterpret_cast<double*>(pp);
+    }
     ctx->d_csum = reinterpret_cast<double*>(pc);
     ctx->d_ccomp = ctx->d_csum + (size_t)nd * L * R3 * 3;
     out_doubles = std::max(out_doubles, (size_t)2 * L * R3 * 3);
-    HIP_TRY(hipMemsetAsync(pX, 0, (size_t)R3 * t_pad * 8, ctx->stream), "zero series");
+    HIP_TRY(hipMemsetAsync(pX, 0, (size_t)R3 * x_cap * 8, ctx->stream), "zero series");
     HIP_TRY(hipMemsetAsync(pring, 0, (size_t)ring_len * 3 * 8, ctx->stream), "zero ring");
     // segment pass of the bin reduction: bin of every slot, float64 segment rows
     const int64_t n_seg = (M_pad + REDUCE_SEG - 1) / REDUCE_SEG;
@@ -721,6 +740,7 @@ mhc_status mhc_reset(mhc_ctx* ctx) {
   }
   ctx->n_samples = 0;
   ctx->last_block = 0;
+  ctx->x_base = ctx->x_fill = ctx->x_last = 0;
   return MHC_OK;
 }
 
@@ -741,14 +761,50 @@ static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int 
   return MHC_OK;
 }
 
+// Correlation update of the count buffered GKMA steps starting at global step
+// t0 (X columns 0 .. count - 1) into the sums (sum, comp), by default the
+// context's own.
+static mhc_status corr_update(mhc_ctx* ctx, int64_t t0, int64_t count, double* sum = nullptr,
+                              double* comp = nullptr) {
+  const int L = ctx->cfg.corr_len;
+  HIP_TRY(launch_corr(ctx->stream, ctx->dX, ctx->x_cap, (int)count, ctx->R3, L, ctx->d_ring, ctx->ring_len, t0,
+                      sum ? sum : ctx->d_csum, comp ? comp : ctx->d_ccomp, nullptr),
+          "correlation");
+  if (sum) return MHC_OK;
+  if (ctx->cross)   // every binned row against the history of every bin b2 (grid z = b2)
+    HIP_TRY(launch_corr(ctx->stream, ctx->dX, ctx->x_cap, (int)count, ctx->R3, L, ctx->d_bring, ctx->ring_len, t0,
+                        ctx->d_xsum, ctx->d_xcomp, nullptr, nullptr, (int)ctx->nb, ctx->ring_len * 3,
+                        ctx->R3 * 3 * L),
+            "cross-correlation");
+  return MHC_OK;
+}
+
+
+// Where a block's binned series goes in X, and whether the correlation update
+// runs after it (the number of buffered steps to correlate, 0 for none); the
+// host keeps this account for the single pushes and for the group's table.
+static void fold_step(mhc_ctx* ctx, int t_count, int64_t* xoff, int64_t* tbuf) {
+  *xoff = ctx->x_fill;
+  ctx->x_last = ctx->x_fill;
+  ctx->x_fill += t_count;
+  *tbuf = 0;
+  if (ctx->x_fill + ctx->t_pad > ctx->x_cap) {   // no room for another full block
+    *tbuf = ctx->x_fill;
+    ctx->x_base += ctx->x_fill;
+    ctx->x_fill = 0;
+  }
+}
+
 // Back of a block: per-step totals, bins + float64 accumulation, GKMA update.
 // With t0_dev the block's first step index is read from device memory when
 // the kernels run (the group's input table), so a captured graph can be
-// replayed block after block.
+// replayed block after block; so are the block's column in X (xoff_dev) and
+// the correlation update's step count (tbuf_dev).
 // With the motion-direction split, pass dir in {0, 1, 2} accumulates into its
 // own slice of the bin sums and correlation sums; the whole Eq. 10 total is
 // summed in pass 0 only (every pass rewrites the same GKMA history entries).
-static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64_t* t0_dev, int dir = -1) {
+static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64_t* t0_dev, int dir = -1,
+                             const int64_t* xoff_dev = nullptr, const int64_t* tbuf_dev = nullptr) {
   const auto& c = ctx->cfg;
   const bool gk = c.methods & MHC_GKMA;
   const int64_t ld = ctx->t_pad;
@@ -784,17 +840,33 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64
   a.ring_len = ctx->ring_len;
   a.t0 = ctx->n_samples;
   a.t0_dev = t0_dev;
+  a.ldx = gk ? ctx->x_cap : ld;
+  int64_t xoff = 0, tbuf = 0;
+  if (gk && dir < 0 && !t0_dev) fold_step(ctx, t_count, &xoff, &tbuf);
+  a.xoff = xoff;
+  a.xoff_dev = t0_dev ? xoff_dev : nullptr;
   HIP_TRY(launch_reduce(ctx->stream, a), "bin reduce");
-  if (gk) {
+  if (!gk) return MHC_OK;
+  if (dir >= 0) {
+    // direction passes: one update per pass over this block (X holds one block)
     const size_t off = (size_t)d * c.corr_len * ctx->R3 * 3;
-    HIP_TRY(launch_corr(ctx->stream, ctx->dX, ld, t_count, ctx->R3, c.corr_len, ctx->d_ring, ctx->ring_len,
+    HIP_TRY(launch_corr(ctx->stream, ctx->dX, ctx->x_cap, t_count, ctx->R3, c.corr_len, ctx->d_ring, ctx->ring_len,
                         ctx->n_samples, ctx->d_csum + off, ctx->d_ccomp + off, t0_dev),
             "correlation");
-    if (ctx->cross)   // every binned row against the history of every bin b2 (grid z = b2)
-      HIP_TRY(launch_corr(ctx->stream, ctx->dX, ld, t_count, ctx->R3, c.corr_len, ctx->d_bring, ctx->ring_len,
-                          ctx->n_samples, ctx->d_xsum, ctx->d_xcomp, t0_dev, (int)ctx->nb, ctx->ring_len * 3,
-                          ctx->R3 * 3 * c.corr_len),
+  } else if (t0_dev) {
+    // grouped: the block table says how many buffered steps to correlate now
+    HIP_TRY(launch_corr(ctx->stream, ctx->dX, ctx->x_cap, t_count, ctx->R3, c.corr_len, ctx->d_ring, ctx->ring_len,
+                        0, ctx->d_csum, ctx->d_ccomp, t0_dev, tbuf_dev),
+            "correlation");
+    if (ctx->cross)
+      HIP_TRY(launch_corr(ctx->stream, ctx->dX, ctx->x_cap, t_count, ctx->R3, c.corr_len, ctx->d_bring,
+                          ctx->ring_len, 0, ctx->d_xsum, ctx->d_xcomp, t0_dev, tbuf_dev, (int)ctx->nb,
+                          ctx->ring_len * 3, ctx->R3 * 3 * c.corr_len),
               "cross-correlation");
+  } else if (tbuf > 0) {
+    // the tbuf buffered steps ending with this block (fold_step has moved
+    // x_base past them)
+    return corr_update(ctx, ctx->x_base - tbuf, tbuf);
   }
   return MHC_OK;
 }
@@ -1075,8 +1147,19 @@ mhc_status mhc_read_hnema_dir(mhc_ctx* ctx, double* avg, double* total_avg, int6
 static mhc_status gkma_finished(mhc_ctx* ctx, int d, std::vector<double>& h) {
   const int L = ctx->cfg.corr_len;
   const size_t per = (size_t)L * ctx->R3 * 3;
-  HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_csum + d * per, ctx->d_ccomp + d * per, ctx->R3, L, ctx->n_samples,
-                             ctx->cfg.dt, ctx->d_out, ctx->d_out + per),
+  const double *psum = nullptr, *pcomp = nullptr;
+  if (ctx->x_fill > 0) {
+    // steps still buffered for a later update: their contribution goes into
+    // scratch sums that the read adds, so a read leaves the running sums (and
+    // the order of later updates) as they were
+    HIP_TRY(hipMemsetAsync(ctx->d_psum, 0, 2 * per * 8, ctx->stream), "zero pending sums");
+    mhc_status st = corr_update(ctx, ctx->x_base, ctx->x_fill, ctx->d_psum, ctx->d_psum + per);
+    if (st) return st;
+    psum = ctx->d_psum;
+    pcomp = ctx->d_psum + per;
+  }
+  HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_csum + d * per, ctx->d_ccomp + d * per, psum, pcomp, ctx->R3, L,
+                             ctx->n_samples, ctx->cfg.dt, ctx->d_out, ctx->d_out + per),
           "finish");
   h.resize(2 * per);
   HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, 2 * per * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
@@ -1151,8 +1234,8 @@ mhc_status mhc_read_gkma_cross(mhc_ctx* ctx, double* corr, double* integral, int
   const size_t per = (size_t)L * R3 * 3;
   std::vector<double> h(2 * per);
   for (int64_t b2 = 0; b2 < nb; ++b2) {
-    HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_xsum + b2 * per, ctx->d_xcomp + b2 * per, R3, L, ctx->n_samples,
-                               ctx->cfg.dt, ctx->d_out, ctx->d_out + per),
+    HIP_TRY(launch_corr_finish(ctx->stream, ctx->d_xsum + b2 * per, ctx->d_xcomp + b2 * per, nullptr, nullptr, R3, L,
+                               ctx->n_samples, ctx->cfg.dt, ctx->d_out, ctx->d_out + per),
             "finish");
     HIP_TRY(hipMemcpyAsync(h.data(), ctx->d_out, 2 * per * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
@@ -1179,11 +1262,11 @@ mhc_status mhc_read_block_currents(mhc_ctx* ctx, int32_t t_count, double* jb) {
   if (t_count == 0) return MHC_OK;
   if (!jb) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL output");
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-  const int64_t nb = ctx->nb, ld = ctx->t_pad;
+  const int64_t nb = ctx->nb, ld = ctx->x_cap;
   std::vector<double> h((size_t)3 * nb * ld);
   HIP_TRY(hipMemcpyAsync(h.data(), ctx->dX, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream), "read");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "read sync");
-  const int first = ctx->last_block - t_count;
+  const int64_t first = ctx->x_last + ctx->last_block - t_count;   // the last block starts at column x_last
   for (int t = 0; t < t_count; ++t)
     for (int64_t b = 0; b < nb; ++b)
       for (int mu = 0; mu < 3; ++mu) jb[((size_t)t * nb + b) * 3 + mu] = h[(size_t)(b * 3 + mu) * ld + first + t];
@@ -1196,14 +1279,17 @@ struct StateHeader {
   uint64_t magic;
   int64_t N, M, nb, L, ring_len, R3, n_samples;
   int32_t methods, precision, t_block, last_block;
+  int64_t x_cap, x_fill;   // GKMA: steps buffered for a later correlation update
 };
-constexpr uint64_t kMagic = 0x4D48435354415431ull;  // "MHCSTAT1"
+constexpr uint64_t kMagic = 0x4D48435354415432ull;  // "MHCSTAT2"
 }  // namespace
 
-static size_t state_bytes(const mhc_ctx* c) {
+// Bytes of a saved state with x_fill buffered GKMA steps (their binned series
+// rows, R3 x x_fill doubles, follow the other sections).
+static size_t state_bytes(const mhc_ctx* c, int64_t x_fill) {
   size_t n = sizeof(StateHeader);
   if (c->d_hsum) n += hn_doubles(c->nb, c->n_dir) * 8;
-  if (c->d_csum) n += gk_doubles(c) * 8 + (size_t)c->ring_len * 3 * 8;
+  if (c->d_csum) n += gk_doubles(c) * 8 + (size_t)c->ring_len * 3 * 8 + (size_t)c->R3 * x_fill * 8;
   n += (cross_doubles(c) + bring_doubles(c)) * 8;
   return n;
 }
@@ -1213,7 +1299,7 @@ mhc_status mhc_save_state(mhc_ctx* ctx, void* buf, size_t* len) {
   if (st) return st;
   if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "save needs a finalized context");
   if (!len) return fail(ctx, MHC_ERR_INVALID_ARG, "NULL len");
-  const size_t need = state_bytes(ctx);
+  const size_t need = state_bytes(ctx, ctx->x_fill);
   if (!buf) {
     *len = need;
     return MHC_OK;
@@ -1221,7 +1307,7 @@ mhc_status mhc_save_state(mhc_ctx* ctx, void* buf, size_t* len) {
   if (*len < need) return fail(ctx, MHC_ERR_INVALID_ARG, "buffer too small");
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   StateHeader hd{kMagic, ctx->N, ctx->M, ctx->nb, ctx->cfg.corr_len, ctx->ring_len, ctx->R3, ctx->n_samples,
-                 ctx->cfg.methods, ctx->cfg.precision, ctx->cfg.t_block, ctx->last_block};
+                 ctx->cfg.methods, ctx->cfg.precision, ctx->cfg.t_block, ctx->last_block, ctx->x_cap, ctx->x_fill};
   char* p = reinterpret_cast<char*>(buf);
   std::memcpy(p, &hd, sizeof hd);
   p += sizeof hd;
@@ -1245,6 +1331,12 @@ mhc_status mhc_save_state(mhc_ctx* ctx, void* buf, size_t* len) {
     HIP_TRY(hipMemcpyAsync(p, ctx->d_bring, br, hipMemcpyDeviceToHost, ctx->stream), "save");
     p += br;
   }
+  if (ctx->d_csum && ctx->x_fill > 0) {   // the buffered steps' binned series, rows of x_fill
+    HIP_TRY(hipMemcpy2DAsync(p, (size_t)ctx->x_fill * 8, ctx->dX, (size_t)ctx->x_cap * 8, (size_t)ctx->x_fill * 8,
+                             (size_t)ctx->R3, hipMemcpyDeviceToHost, ctx->stream),
+            "save");
+    p += (size_t)ctx->R3 * ctx->x_fill * 8;
+  }
   HIP_TRY(hipStreamSynchronize(ctx->stream), "save sync");
   *len = need;
   return MHC_OK;
@@ -1254,12 +1346,15 @@ mhc_status mhc_load_state(mhc_ctx* ctx, const void* buf, size_t len) {
   mhc_status st = enter(ctx);
   if (st) return st;
   if (!ctx->finalized) return fail(ctx, MHC_ERR_STATE, "load needs a finalized context");
-  if (!buf || len != state_bytes(ctx)) return fail(ctx, MHC_ERR_INVALID_ARG, "state size mismatch");
+  if (!buf || len < sizeof(StateHeader)) return fail(ctx, MHC_ERR_INVALID_ARG, "state size mismatch");
   StateHeader hd;
   std::memcpy(&hd, buf, sizeof hd);
   if (hd.magic != kMagic || hd.N != ctx->N || hd.M != ctx->M || hd.nb != ctx->nb || hd.L != ctx->cfg.corr_len ||
-      hd.ring_len != ctx->ring_len || hd.R3 != ctx->R3 || hd.methods != ctx->cfg.methods || hd.n_samples < 0)
+      hd.ring_len != ctx->ring_len || hd.R3 != ctx->R3 || hd.methods != ctx->cfg.methods || hd.n_samples < 0 ||
+      hd.x_cap != ctx->x_cap || hd.x_fill < 0 || hd.x_fill > ctx->x_cap || hd.x_fill > hd.n_samples ||
+      (!ctx->d_csum && hd.x_fill != 0))
     return fail(ctx, MHC_ERR_INVALID_ARG, "state from a different system or configuration");
+  if (len != state_bytes(ctx, hd.x_fill)) return fail(ctx, MHC_ERR_INVALID_ARG, "state size mismatch");
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   const char* p = reinterpret_cast<const char*>(buf) + sizeof hd;
   if (ctx->d_hsum) {
@@ -1280,10 +1375,18 @@ mhc_status mhc_load_state(mhc_ctx* ctx, const void* buf, size_t len) {
     HIP_TRY(hipMemcpyAsync(ctx->d_xsum, p, x, hipMemcpyHostToDevice, ctx->stream), "load");
     p += x;
     HIP_TRY(hipMemcpyAsync(ctx->d_bring, p, br, hipMemcpyHostToDevice, ctx->stream), "load");
+    p += br;
   }
+  if (hd.x_fill > 0)
+    HIP_TRY(hipMemcpy2DAsync(ctx->dX, (size_t)ctx->x_cap * 8, p, (size_t)hd.x_fill * 8, (size_t)hd.x_fill * 8,
+                             (size_t)ctx->R3, hipMemcpyHostToDevice, ctx->stream),
+            "load");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "load sync");
   ctx->n_samples = hd.n_samples;
   ctx->last_block = 0;
+  ctx->x_fill = hd.x_fill;
+  ctx->x_base = hd.n_samples - hd.x_fill;
+  ctx->x_last = 0;
   return MHC_OK;
 }
 
@@ -1334,6 +1437,7 @@ mhc_status mhc_last_schedule(mhc_ctx* ctx, int32_t* schedule) {
 // persistent contraction over all their tiles (largest first), and the
 // backs of all systems, optionally captured once as a HIP graph and replayed.
 constexpr int TAB_RING = 8;   // pinned input-table slots of a group
+constexpr int TAB_W = 5;      // table words per system
 constexpr int NAUX = 4;       // side streams of a group (the device has 4 hardware queues per process)
 
 struct mhc_group {
@@ -1353,12 +1457,15 @@ struct mhc_group {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string err;
-  // Block table: words 3i, 3i+1, 3i+2 = v, W and first step index of system
-  // i for the block the queued work will process.  Each block's table is
-  // written to its own pinned ring slot, copied to the device in stream
-  // order, and the slot is reused only after that copy has completed (event).
+  // Block table: words TAB_W i + 0 .. 4 = v, W, the first step index of
+  // system i for the block the queued work will process, the block's column
+  // in the system's GKMA series buffer and the number of buffered steps the
+  // correlation update correlates after the block (0: none).  Each block's
+  // table is written to its own pinned ring slot, copied to the device in
+  // stream order, and the slot is reused only after that copy has completed
+  // (event).
   uint64_t* d_tab = nullptr;
-  uint64_t* h_tab = nullptr;                // [TAB_RING][3n]
+  uint64_t* h_tab = nullptr;                // [TAB_RING][TAB_W n]
   // The input prep of all systems runs as one launch (two for e4m3: the
   // column maxima first) over per-system descriptors that read v and W
   // through the block table.
@@ -1428,7 +1535,9 @@ mhc_status build_back(mhc_group* g) {
   for (int i = 0; i < n; ++i) {
     mhc_ctx* c = g->sys[i];
     const bool gk = c->cfg.methods & MHC_GKMA;
-    const int64_t* t0_dev = reinterpret_cast<const int64_t*>(g->d_tab + 3 * i + 2);
+    const int64_t* t0_dev = reinterpret_cast<const int64_t*>(g->d_tab + TAB_W * i + 2);
+    const int64_t* xoff_dev = reinterpret_cast<const int64_t*>(g->d_tab + TAB_W * i + 3);
+    const int64_t* tbuf_dev = reinterpret_cast<const int64_t*>(g->d_tab + TAB_W * i + 4);
     ReduceArgs& a = ra[i];
     a = ReduceArgs{};
     a.in = c->dJ;
@@ -1451,12 +1560,14 @@ mhc_status build_back(mhc_group* g) {
     a.ring = c->d_ring;
     a.ring_len = c->ring_len;
     a.t0_dev = t0_dev;
+    a.ldx = gk ? c->x_cap : c->t_pad;
+    a.xoff_dev = gk ? xoff_dev : nullptr;
     BackDesc& d = bd[i];
     d.jt_part = c->d_jt;
     d.n_chunks = c->n_atom_chunks;
     d.jtot = c->d_jtot;
     d.X = c->dX;
-    d.ldx = c->t_pad;
+    d.ldx = c->x_cap;
     d.R3 = c->R3;
     d.L = gk ? c->cfg.corr_len : 0;
     d.ring = c->d_ring;
@@ -1464,6 +1575,7 @@ mhc_status build_back(mhc_group* g) {
     d.csum = c->d_csum;
     d.ccomp = c->d_ccomp;
     d.t0_dev = t0_dev;
+    d.tbuf_dev = tbuf_dev;
     d.n_rt = gk ? (int)((c->R3 + 63) / 64) : 0;
     w[i] = (int)ws;
     w[n + i] = (int)wr;
@@ -1575,7 +1687,8 @@ mhc_status group_block(mhc_group* g, bool timed) {
   }
   return fan_out(g, [&](size_t i) {
     mhc_ctx* c = g->sys[i];
-    mhc_status s2 = block_back(c, g->t_block, g->n_parts[i], reinterpret_cast<const int64_t*>(g->d_tab + 3 * i + 2));
+    const int64_t* w = reinterpret_cast<const int64_t*>(g->d_tab + TAB_W * i);
+    mhc_status s2 = block_back(c, g->t_block, g->n_parts[i], w + 2, -1, w + 3, w + 4);
     return s2 ? gfail(g, s2, c->err) : MHC_OK;
   });
 }
@@ -1602,7 +1715,7 @@ mhc_status autotune(mhc_group* g) {
   for (size_t i = 0; i < g->sys.size(); ++i) {
     mhc_ctx* c = g->sys[i];
     mhc_status st =
-        block_front(c, nullptr, nullptr, g->t_block, reinterpret_cast<const float* const*>(g->d_tab + 3 * i));
+        block_front(c, nullptr, nullptr, g->t_block, reinterpret_cast<const float* const*>(g->d_tab + TAB_W * i));
     if (st) return gfail(g, st, c->err);
   }
   std::vector<int> shapes;
@@ -1721,10 +1834,10 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
   if (hipMalloc(&pc, 256) != hipSuccess) return cleanup(MHC_ERR_OOM);
   g->allocs.push_back({pc, 256});
   void* ptab = nullptr;
-  if (hipMalloc(&ptab, 3 * n * sizeof(uint64_t)) != hipSuccess) return cleanup(MHC_ERR_OOM);
-  g->allocs.push_back({ptab, 3 * n * sizeof(uint64_t)});
+  if (hipMalloc(&ptab, TAB_W * n * sizeof(uint64_t)) != hipSuccess) return cleanup(MHC_ERR_OOM);
+  g->allocs.push_back({ptab, TAB_W * n * sizeof(uint64_t)});
   g->d_tab = reinterpret_cast<uint64_t*>(ptab);
-  if (hipHostMalloc(reinterpret_cast<void**>(&g->h_tab), TAB_RING * 3 * n * sizeof(uint64_t), 0) != hipSuccess)
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->h_tab), TAB_RING * TAB_W * n * sizeof(uint64_t), 0) != hipSuccess)
     return cleanup(MHC_ERR_OOM);
   for (int k = 0; k < TAB_RING; ++k)
     if (hipEventCreateWithFlags(&g->tab_ev[k], hipEventDisableTiming) != hipSuccess) return cleanup(MHC_ERR_HIP);
@@ -1752,7 +1865,7 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
       d.jt_part = c->d_jt;
       d.col_scale = c->d_colscale;
       d.col_part = c->d_colpart;
-      d.tab = reinterpret_cast<const float* const*>(g->d_tab + 3 * i);
+      d.tab = reinterpret_cast<const float* const*>(g->d_tab + TAB_W * i);
       d.wg0_cs = (int)wcs;
       d.wg0_prep = (int)wpr;
       wcs += (int64_t)c->t_pad * ((c->N + COLSCALE_ATOMS - 1) / COLSCALE_ATOMS);
@@ -1869,7 +1982,7 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
     const int k = g->tab_pos;
     g->tab_pos = (g->tab_pos + 1) % TAB_RING;
     if (g->tab_busy[k]) GHIP_TRY(hipEventSynchronize(g->tab_ev[k]), "input table slot");
-    uint64_t* tab = g->h_tab + (size_t)k * 3 * n;
+    uint64_t* tab = g->h_tab + (size_t)k * TAB_W * n;
     for (int i = 0; i < n; ++i) {
       mhc_ctx* c = g->sys[i];
       const float* vi = v[i] + (int64_t)s0 * c->N * 3;
@@ -1883,15 +1996,19 @@ mhc_status mhc_group_push(mhc_group* g, int32_t n_steps, const float* const* v, 
         vi = sv;
         Wi = sW;
       }
-      tab[3 * i] = reinterpret_cast<uint64_t>(vi);
-      tab[3 * i + 1] = reinterpret_cast<uint64_t>(Wi);
-      tab[3 * i + 2] = (uint64_t)c->n_samples;
+      tab[TAB_W * i] = reinterpret_cast<uint64_t>(vi);
+      tab[TAB_W * i + 1] = reinterpret_cast<uint64_t>(Wi);
+      tab[TAB_W * i + 2] = (uint64_t)c->n_samples;
+      int64_t xoff = 0, tbuf = 0;
+      if (c->cfg.methods & MHC_GKMA) fold_step(c, T, &xoff, &tbuf);
+      tab[TAB_W * i + 3] = (uint64_t)xoff;
+      tab[TAB_W * i + 4] = (uint64_t)tbuf;
     }
     if (overlap) {
       GHIP_TRY(hipEventRecord(g->cp_done[b], g->copy_stream), "event record");
       GHIP_TRY(hipStreamWaitEvent(g->stream, g->cp_done[b], 0), "stream wait");
     }
-    GHIP_TRY(hipMemcpyAsync(g->d_tab, tab, 3 * n * sizeof(uint64_t), hipMemcpyHostToDevice, g->stream),
+    GHIP_TRY(hipMemcpyAsync(g->d_tab, tab, TAB_W * n * sizeof(uint64_t), hipMemcpyHostToDevice, g->stream),
              "block table");
     GHIP_TRY(hipEventRecord(g->tab_ev[k], g->stream), "input table event");
     g->tab_busy[k] = true;

@@ -8,11 +8,13 @@ namespace mhc {
 
 // Per-system arguments of the totals and the correlation update (device-
 // resident).  n_rt: row tiles of the correlation grid (0 for a system
-// without GKMA); the correlation reads the block's first step index at t0_dev.
+// without GKMA); the correlation reads the block's first step index at t0_dev
+// and the number of buffered steps to correlate (0: none this block) at
+// tbuf_dev.
 struct BackDesc {
   const double* jt_part; int n_chunks; double* jtot;
   const double* X; int64_t ldx; int64_t R3; int L; const double* ring; int64_t ring_len;
-  double* csum; double* ccomp; const int64_t* t0_dev; int n_rt;
+  double* csum; double* ccomp; const int64_t* t0_dev; const int64_t* tbuf_dev; int n_rt;
 };
 
 // Device arrays of one group's back end: descriptors, the reduction

@@ -151,6 +151,9 @@ struct ReduceArgs {
   const int64_t* t0_dev;    // if set, the block's first step index is read here instead of t0
   const double* jdtot; double* tdsum; double* tdcomp;        // split Eq. 10 totals (may be null)
   double* bring;            // cross-correlation: bin history [nb][ring_len][3] (may be null)
+  int64_t ldx;              // leading dimension of X (>= ld: X keeps several blocks)
+  int64_t xoff;             // column of X where this block's first step goes
+  const int64_t* xoff_dev;  // if set, xoff is read here (the group's block table)
 };
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs& a);
 
@@ -159,18 +162,25 @@ hipError_t launch_total(hipStream_t s, const double* jt_part, int n_chunks, int 
 
 // GKMA correlation update: for r < R3 = 3(nb+1), tau < L, nu < 3
 //   C[r][nu][tau] += sum_{t < t_count, t0+t-tau >= 0} X[r][t] * ring[(t0+t-tau) % ring_len][nu]
-// accumulated with Neumaier compensation into csum/ccomp (lag-contiguous).
+// accumulated with Neumaier compensation into csum/ccomp (lag-contiguous);
+// X column t holds global step t0 + t.  With tbuf_dev (the group's block
+// table) the kernels read t0 from t0_dev and the number of buffered steps tb
+// from tbuf_dev: tb = 0 means no update this block, otherwise the update
+// covers the tb steps ending with the block of t_count steps at *t0_dev.
 // nz > 1 repeats it for nz rings at ring + z ring_zs into sums at + z out_zs
 // (the cross-correlation: one ring per second bin).
 hipError_t launch_corr(hipStream_t s, const double* X, int64_t ldx, int t_count, int64_t R3, int L,
                        const double* ring, int64_t ring_len, int64_t t0, double* csum, double* ccomp,
-                       const int64_t* t0_dev, int nz = 1, int64_t ring_zs = 0, int64_t out_zs = 0);
+                       const int64_t* t0_dev, const int64_t* tbuf_dev = nullptr, int nz = 1, int64_t ring_zs = 0,
+                       int64_t out_zs = 0);
 
-// Read-out of the GKMA accumulators: C = (csum + ccomp) / (S - tau) (zero when
-// S <= tau) and its trapezoid running integral with step dt, written as
-// corr/integral[tau][r][nu].
-hipError_t launch_corr_finish(hipStream_t s, const double* csum, const double* ccomp, int64_t R3,
-                              int L, int64_t S, double dt, double* corr, double* integral);
+// Read-out of the GKMA accumulators: C = (csum + ccomp [+ psum + pcomp]) /
+// (S - tau) (zero when S <= tau; psum, pcomp optional: the correlation of
+// steps not yet added to the running sums) and its trapezoid running integral
+// with step dt, written as corr/integral[tau][r][nu].
+hipError_t launch_corr_finish(hipStream_t s, const double* csum, const double* ccomp, const double* psum,
+                              const double* pcomp, int64_t R3, int L, int64_t S, double dt, double* corr,
+                              double* integral);
 
 // Read-out of the HNEMA accumulators: avg = (sum + comp) / S (zero when S = 0).
 hipError_t launch_hnema_finish(hipStream_t s, const double* sum, const double* comp, int64_t n,
