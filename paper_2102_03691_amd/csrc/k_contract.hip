@@ -35,6 +35,12 @@ __device__ __forceinline__ f32x16 mfma_fp8(i32x8 a, i32x8 b, f32x16 c) {
 }
 
 // Row of the 32x32 accumulator held in register j of lane l (column = l % 32).
+// The contraction passes the activations as the MFMA's A operand and the E
+// fragment as its B operand (the two operand layouts are the same, so this
+// is only the order of the arguments): accumulator rows are steps, columns
+// are slots.  Lane l then holds 16 steps of slot l % 32, and the sum over
+// steps of the modal-current epilogue is a sum over the lane's own registers
+// plus one exchange between the two half-waves.
 __device__ __forceinline__ int acc_row(int j, int half) { return 8 * (j >> 2) + 4 * half + (j & 3); }
 
 // ----------------------------------------------------------- per-step FP32
@@ -180,27 +186,30 @@ typedef __attribute__((address_space(1))) const u32x4 gu32x4;
 
 constexpr bool is_fp8(int prec) { return prec == PREC_FP8 || prec == PREC_FP8X3; }
 
-// Epilogue of one finished tile (accumulators complete).
+// Epilogue of one finished tile (accumulators complete).  Lane l holds slot
+// (row block, l % 32) and, in register j, step acc_row(j, l / 32) of the
+// wave's t-block, for the four channels.
 template <int PREC, int WM, int WT, int MB>
 __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __restrict__ out, const GemmGeom& g,
                                               int64_t rb0, int ntile, float* red) {
   constexpr int RBW = WM * MB;
   const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, wave = tid >> 6;
   const int wm = wave / WT, wt = wave % WT;
+  const int64_t t0 = (int64_t)(ntile * WT + wt) * 32;          // first step of the wave's t-block
   if constexpr (is_fp8(PREC)) {
-    // undo the activation scales of this lane's step (column); the E scale
-    // of each row is applied after the products
-    const int ld = g.ntb * 32;
-    const int t = (ntile * WT + wt) * 32 + (lane & 31);
-    float cs[4];
+    // undo the activation scales of each register's step; the E scale of
+    // each slot is applied after the products
+    const int64_t ld = (int64_t)g.ntb * 32;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) cs[c] = g.col_scale[c * ld + t];
+    for (int j = 0; j < 16; ++j) {
+      const int64_t t = t0 + acc_row(j, half);
 #pragma unroll
-    for (int rb = 0; rb < MB; ++rb)
+      for (int c = 0; c < 4; ++c) {
+        const float cs = g.col_scale[c * ld + t];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) acc[rb][c][j] *= cs[c];
+        for (int rb = 0; rb < MB; ++rb) acc[rb][c][j] *= cs;
+      }
+    }
   }
   auto row_factor = [&](int64_t slot) -> float {
     if constexpr (is_fp8(PREC)) {
@@ -211,26 +220,26 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
     }
   };
   if (!g.layout_g) {
-    // HNEMA: sum J_n^mu over the tile's steps -> out[ntile][slot][mu]
+    // HNEMA: sum J_n^mu over the tile's steps -> out[ntile][slot][mu]: the
+    // lane's 16 steps in register order, plus the other half-wave's 16, then
+    // the WT t-blocks in wave order through LDS
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
+      float p0 = 0.f, p1 = 0.f, p2 = 0.f;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        float p0 = acc[rb][0][j] * acc[rb][1][j];
-        float p1 = acc[rb][0][j] * acc[rb][2][j];
-        float p2 = acc[rb][0][j] * acc[rb][3][j];
-#pragma unroll
-        for (int off = 1; off < 32; off <<= 1) {
-          p0 += __shfl_xor(p0, off);
-          p1 += __shfl_xor(p1, off);
-          p2 += __shfl_xor(p2, off);
-        }
-        if ((lane & 31) == 0) {
-          const int row = (wm * MB + rb) * 32 + acc_row(j, half);
-          const float f = row_factor(rb0 * 32 + row);
-          float* rp = red + ((int64_t)wt * RBW * 32 + row) * 3;
-          rp[0] = p0 * f; rp[1] = p1 * f; rp[2] = p2 * f;
-        }
+        p0 += acc[rb][0][j] * acc[rb][1][j];
+        p1 += acc[rb][0][j] * acc[rb][2][j];
+        p2 += acc[rb][0][j] * acc[rb][3][j];
+      }
+      p0 += __shfl_xor(p0, 32);
+      p1 += __shfl_xor(p1, 32);
+      p2 += __shfl_xor(p2, 32);
+      if (half == 0) {
+        const int row = (wm * MB + rb) * 32 + lane;
+        const float f = row_factor(rb0 * 32 + row);
+        float* rp = red + ((int64_t)wt * RBW * 32 + row) * 3;
+        rp[0] = p0 * f; rp[1] = p1 * f; rp[2] = p2 * f;
       }
     }
     __syncthreads();
@@ -242,18 +251,23 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
     }
     __syncthreads();
   } else {
-    // GKMA: per-step J_n^mu(t) -> out[mu][slot][t]
+    // GKMA: per-step J_n^mu(t) -> out[mu][slot][t]; registers 4q .. 4q+3 are
+    // the 4 consecutive steps 8q + 4*half .. +3, stored as one 16-byte unit
     const int64_t ld = (int64_t)g.ntb * 32;
-    const int64_t t = (int64_t)(ntile * WT + wt) * 32 + (lane & 31);
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
+      const int64_t slot = (rb0 + wm * MB + rb) * 32 + (lane & 31);
+      const float f = row_factor(slot);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int64_t slot = (rb0 + wm * MB + rb) * 32 + acc_row(j, half);
-        const float f = row_factor(slot);
+      for (int mu = 0; mu < 3; ++mu) {
+        float* o = out + ((int64_t)mu * g.M_pad + slot) * ld + t0 + 4 * half;
 #pragma unroll
-        for (int mu = 0; mu < 3; ++mu)
-          out[((int64_t)mu * g.M_pad + slot) * ld + t] = acc[rb][0][j] * acc[rb][1 + mu][j] * f;
+        for (int q = 0; q < 4; ++q) {
+          f32x4 v;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = acc[rb][0][4 * q + e] * acc[rb][1 + mu][4 * q + e] * f;
+          *reinterpret_cast<f32x4*>(o + 8 * q) = v;
+        }
       }
     }
   }
@@ -356,25 +370,26 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
         }
         __builtin_amdgcn_sched_barrier(0);     // all fragment reads in flight before the first MFMA
         // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
-        // (lo4 of a channel's register is its hi part, hi4 its lo part)
+        // (lo4 of a channel's register is its hi part, hi4 its lo part);
+        // activations as operand A, E as operand B
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                ah[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
+                __builtin_bit_cast(bf16x8, lo4(bc[c])), ah[rb], acc[rb][c], 0, 0, 0);
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                ah[rb], __builtin_bit_cast(bf16x8, hi4(bc[c])), acc[rb][c], 0, 0, 0);
+                __builtin_bit_cast(bf16x8, hi4(bc[c])), ah[rb], acc[rb][c], 0, 0, 0);
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                al[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c], 0, 0, 0);
+                __builtin_bit_cast(bf16x8, lo4(bc[c])), al[rb], acc[rb][c], 0, 0, 0);
       } else if constexpr (C::F8X3) {
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb) {
@@ -382,11 +397,11 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
           const i32x8 ah = cat8(ar[0], ar[64]);
           const i32x8 al = cat8(ar[128], ar[192]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 0], acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[2 * c + 0], ah, acc[rb][c]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(ah, bc[2 * c + 1], acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[2 * c + 1], ah, acc[rb][c]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(al, bc[2 * c + 0], acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[2 * c + 0], al, acc[rb][c]);
         }
       } else if constexpr (C::F8) {
 #pragma unroll
@@ -394,7 +409,7 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
           const u32x4* ar = &lds[buf][wm * MB + rb][kk * 128 + lane];
           const i32x8 a = cat8(ar[0], ar[64]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(a, bc[c], acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[c], a, acc[rb][c]);
         }
       } else {
         f32x4 a[MB];
@@ -408,7 +423,7 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
 #pragma unroll
             for (int c = 0; c < 4; ++c)
               acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                  a[rb][e], __builtin_bit_cast(f32x4, (c & 1) ? hi4(bc[c >> 1]) : lo4(bc[c >> 1]))[e],
+                  __builtin_bit_cast(f32x4, (c & 1) ? hi4(bc[c >> 1]) : lo4(bc[c >> 1]))[e], a[rb][e],
                   acc[rb][c], 0, 0, 0);
       }
       // keep the issue order: this chunk's MFMAs, then its refill loads
