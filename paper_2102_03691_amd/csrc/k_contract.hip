@@ -34,13 +34,32 @@ __device__ __forceinline__ f32x16 mfma_fp8(i32x8 a, i32x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
 }
 
+// acc += E x activations in the orientation TR (see acc_row below); e is the
+// E fragment, b the activation fragment.
+template <bool TR>
+__device__ __forceinline__ f32x16 mm_bf16(bf16x8 e, bf16x8 b, f32x16 c) {
+  return TR ? __builtin_amdgcn_mfma_f32_32x32x16_bf16(b, e, c, 0, 0, 0)
+            : __builtin_amdgcn_mfma_f32_32x32x16_bf16(e, b, c, 0, 0, 0);
+}
+template <bool TR>
+__device__ __forceinline__ f32x16 mm_fp8(i32x8 e, i32x8 b, f32x16 c) {
+  return TR ? mfma_fp8(b, e, c) : mfma_fp8(e, b, c);
+}
+template <bool TR>
+__device__ __forceinline__ f32x16 mm_f32(float e, float b, f32x16 c) {
+  return TR ? __builtin_amdgcn_mfma_f32_32x32x2f32(b, e, c, 0, 0, 0)
+            : __builtin_amdgcn_mfma_f32_32x32x2f32(e, b, c, 0, 0, 0);
+}
+
 // Row of the 32x32 accumulator held in register j of lane l (column = l % 32).
-// The contraction passes the activations as the MFMA's A operand and the E
-// fragment as its B operand (the two operand layouts are the same, so this
-// is only the order of the arguments): accumulator rows are steps, columns
-// are slots.  Lane l then holds 16 steps of slot l % 32, and the sum over
-// steps of the modal-current epilogue is a sum over the lane's own registers
-// plus one exchange between the two half-waves.
+// The A and B operand layouts of the MFMAs are the same, so the order of the
+// arguments chooses the orientation of the accumulators:
+//   TR = false (GKMA): E fragment as A, activations as B: rows are slots,
+//     columns are steps, so a half-wave's store of one register is 32
+//     consecutive steps of one slot;
+//   TR = true (HNEMA): activations as A, E as B: rows are steps, columns are
+//     slots, so the sum over steps is a sum over the lane's own registers
+//     plus one exchange between the two half-waves.
 __device__ __forceinline__ int acc_row(int j, int half) { return 8 * (j >> 2) + 4 * half + (j & 3); }
 
 // ----------------------------------------------------------- per-step FP32
@@ -186,28 +205,40 @@ typedef __attribute__((address_space(1))) const u32x4 gu32x4;
 
 constexpr bool is_fp8(int prec) { return prec == PREC_FP8 || prec == PREC_FP8X3; }
 
-// Epilogue of one finished tile (accumulators complete).  Lane l holds slot
-// (row block, l % 32) and, in register j, step acc_row(j, l / 32) of the
-// wave's t-block, for the four channels.
-template <int PREC, int WM, int WT, int MB>
+// Epilogue of one finished tile (accumulators complete); TR = !layout_g.
+// TR: lane l holds slot (row block, l % 32) and, in register j, step
+// acc_row(j, l / 32) of the wave's t-block; otherwise the reverse.
+template <int PREC, int WM, int WT, int MB, bool TR>
 __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __restrict__ out, const GemmGeom& g,
                                               int64_t rb0, int ntile, float* red) {
   constexpr int RBW = WM * MB;
   const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, wave = tid >> 6;
   const int wm = wave / WT, wt = wave % WT;
   const int64_t t0 = (int64_t)(ntile * WT + wt) * 32;          // first step of the wave's t-block
+  const int64_t ld = (int64_t)g.ntb * 32;
   if constexpr (is_fp8(PREC)) {
-    // undo the activation scales of each register's step; the E scale of
-    // each slot is applied after the products
-    const int64_t ld = (int64_t)g.ntb * 32;
+    // undo the activation scales of each step; the E scale of each slot is
+    // applied after the products
+    if constexpr (TR) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int64_t t = t0 + acc_row(j, half);
+      for (int j = 0; j < 16; ++j) {
+        const int64_t t = t0 + acc_row(j, half);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float cs = g.col_scale[c * ld + t];
+#pragma unroll
+          for (int rb = 0; rb < MB; ++rb) acc[rb][c][j] *= cs;
+        }
+      }
+    } else {
+      const int64_t t = t0 + (lane & 31);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const float cs = g.col_scale[c * ld + t];
 #pragma unroll
-        for (int rb = 0; rb < MB; ++rb) acc[rb][c][j] *= cs;
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[rb][c][j] *= cs;
       }
     }
   }
@@ -219,7 +250,7 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
       return 1.f;
     }
   };
-  if (!g.layout_g) {
+  if constexpr (TR) {
     // HNEMA: sum J_n^mu over the tile's steps -> out[ntile][slot][mu]: the
     // lane's 16 steps in register order, plus the other half-wave's 16, then
     // the WT t-blocks in wave order through LDS
@@ -251,23 +282,17 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
     }
     __syncthreads();
   } else {
-    // GKMA: per-step J_n^mu(t) -> out[mu][slot][t]; registers 4q .. 4q+3 are
-    // the 4 consecutive steps 8q + 4*half .. +3, stored as one 16-byte unit
-    const int64_t ld = (int64_t)g.ntb * 32;
+    // GKMA: per-step J_n^mu(t) -> out[mu][slot][t]
+    const int64_t t = t0 + (lane & 31);
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb) {
-      const int64_t slot = (rb0 + wm * MB + rb) * 32 + (lane & 31);
-      const float f = row_factor(slot);
 #pragma unroll
-      for (int mu = 0; mu < 3; ++mu) {
-        float* o = out + ((int64_t)mu * g.M_pad + slot) * ld + t0 + 4 * half;
+      for (int j = 0; j < 16; ++j) {
+        const int64_t slot = (rb0 + wm * MB + rb) * 32 + acc_row(j, half);
+        const float f = row_factor(slot);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          f32x4 v;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc[rb][0][4 * q + e] * acc[rb][1 + mu][4 * q + e] * f;
-          *reinterpret_cast<f32x4*>(o + 8 * q) = v;
-        }
+        for (int mu = 0; mu < 3; ++mu)
+          out[((int64_t)mu * g.M_pad + slot) * ld + t] = acc[rb][0][j] * acc[rb][1 + mu][j] * f;
       }
     }
   }
@@ -294,9 +319,9 @@ struct GemmCfg {
 };
 
 // Accumulate stages [s0, s1) of the tile with row blocks rb0.. and t-block
-// column tb (per wave) into acc.  All 256 threads take part; lds is the
+// column tb (per wave) into acc, in the orientation TR.  All 256 threads take part; lds is the
 // double-buffered A stage.  Leaves the work-group synchronized.
-template <int PREC, int WM, int WT, int MB>
+template <int PREC, int WM, int WT, int MB, bool TR>
 __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int ntile, int s0, int s1,
                                              f32x16 (&acc)[MB][4], u32x4 (*lds)[WM * MB][SU]) {
   using C = GemmCfg<PREC>;
@@ -370,26 +395,22 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
         }
         __builtin_amdgcn_sched_barrier(0);     // all fragment reads in flight before the first MFMA
         // hi*hi, hi*lo, lo*hi, interleaved over the 4*MB independent accumulators
-        // (lo4 of a channel's register is its hi part, hi4 its lo part);
-        // activations as operand A, E as operand B
+        // (lo4 of a channel's register is its hi part, hi4 its lo part)
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, lo4(bc[c])), ah[rb], acc[rb][c], 0, 0, 0);
+            acc[rb][c] = mm_bf16<TR>(ah[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c]);
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, hi4(bc[c])), ah[rb], acc[rb][c], 0, 0, 0);
+            acc[rb][c] = mm_bf16<TR>(ah[rb], __builtin_bit_cast(bf16x8, hi4(bc[c])), acc[rb][c]);
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, lo4(bc[c])), al[rb], acc[rb][c], 0, 0, 0);
+            acc[rb][c] = mm_bf16<TR>(al[rb], __builtin_bit_cast(bf16x8, lo4(bc[c])), acc[rb][c]);
       } else if constexpr (C::F8X3) {
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb) {
@@ -397,11 +418,11 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
           const i32x8 ah = cat8(ar[0], ar[64]);
           const i32x8 al = cat8(ar[128], ar[192]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[2 * c + 0], ah, acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mm_fp8<TR>(ah, bc[2 * c + 0], acc[rb][c]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[2 * c + 1], ah, acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mm_fp8<TR>(ah, bc[2 * c + 1], acc[rb][c]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[2 * c + 0], al, acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mm_fp8<TR>(al, bc[2 * c + 0], acc[rb][c]);
         }
       } else if constexpr (C::F8) {
 #pragma unroll
@@ -409,7 +430,7 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
           const u32x4* ar = &lds[buf][wm * MB + rb][kk * 128 + lane];
           const i32x8 a = cat8(ar[0], ar[64]);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[rb][c] = mfma_fp8(bc[c], a, acc[rb][c]);
+          for (int c = 0; c < 4; ++c) acc[rb][c] = mm_fp8<TR>(a, bc[c], acc[rb][c]);
         }
       } else {
         f32x4 a[MB];
@@ -422,9 +443,8 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
           for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-              acc[rb][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                  __builtin_bit_cast(f32x4, (c & 1) ? hi4(bc[c >> 1]) : lo4(bc[c >> 1]))[e], a[rb][e],
-                  acc[rb][c], 0, 0, 0);
+              acc[rb][c] = mm_f32<TR>(
+                  a[rb][e], __builtin_bit_cast(f32x4, (c & 1) ? hi4(bc[c >> 1]) : lo4(bc[c >> 1]))[e], acc[rb][c]);
       }
       // keep the issue order: this chunk's MFMAs, then its refill loads
       __builtin_amdgcn_sched_barrier(0);
@@ -496,7 +516,7 @@ __device__ __forceinline__ void acc_load(const float* __restrict__ w, f32x16 (&a
       }
 }
 
-template <int PREC, int WM, int WT, int MB>
+template <int PREC, int WM, int WT, int MB, bool TR>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
 k_gemm(float* __restrict__ ws, GemmGeom g) {
   constexpr int RBW = WM * MB;
@@ -515,9 +535,9 @@ k_gemm(float* __restrict__ ws, GemmGeom g) {
     const int mtile = (int)(tile / g.n_ntiles);
     const int ntile = (int)(tile % g.n_ntiles);
     const int64_t rb0 = (int64_t)mtile * RBW;
-    gemm_segment<PREC, WM, WT, MB>(g, rb0, ntile, s0, s1, acc, lds);
+    gemm_segment<PREC, WM, WT, MB, TR>(g, rb0, ntile, s0, s1, acc, lds);
     if (s0 == 0 && s1 == n_stages) {
-      gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+      gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
     } else {
       // partial tile: slot 0 = this work-group's first segment, 1 = its last
       acc_store<MB>(ws + ((gl * 2 + (it == it_begin ? 0 : 1)) * NREG) * 256 + tid, acc);
@@ -557,7 +577,7 @@ __device__ __forceinline__ int split_stage(const SplitPlan& sp, int S, int p) {
   return (int)(((int64_t)p * S) / sp.m);
 }
 
-template <int PREC, int WM, int WT, int MB>
+template <int PREC, int WM, int WT, int MB, bool TR>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
 k_gemm_split(float* __restrict__ ws, GemmGeom g, SplitPlan sp) {
   constexpr int RBW = WM * MB;
@@ -600,7 +620,7 @@ k_gemm_split(float* __restrict__ ws, GemmGeom g, SplitPlan sp) {
     }
     const int64_t rb0 = (tile / g.n_ntiles) * RBW;
     const int ntile = (int)(tile % g.n_ntiles);
-    gemm_segment<PREC, WM, WT, MB>(g, rb0, ntile, s0, s1, acc, lds);
+    gemm_segment<PREC, WM, WT, MB, TR>(g, rb0, ntile, s0, s1, acc, lds);
     bool finish = true;
     if (piece) {
       float* base = ws + tid;
@@ -624,7 +644,7 @@ k_gemm_split(float* __restrict__ ws, GemmGeom g, SplitPlan sp) {
         if (tid == 0) sp.cnt[i] = 0;
       }
     }
-    if (finish) gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+    if (finish) gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
     __syncthreads();
   }
 }
@@ -654,15 +674,21 @@ k_gemm_group(const GemmGeom* __restrict__ sys, const GroupTile* __restrict__ til
     const int mtile = gt.tile / g.n_ntiles;
     const int ntile = gt.tile % g.n_ntiles;
     const int64_t rb0 = (int64_t)mtile * RBW;
-    gemm_segment<PREC, WM, WT, MB>(g, rb0, ntile, 0, g.n_stages, acc, lds);
-    gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+    // the orientation follows the system's method (uniform per work-group)
+    if (g.layout_g) {
+      gemm_segment<PREC, WM, WT, MB, false>(g, rb0, ntile, 0, g.n_stages, acc, lds);
+      gemm_epilogue<PREC, WM, WT, MB, false>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+    } else {
+      gemm_segment<PREC, WM, WT, MB, true>(g, rb0, ntile, 0, g.n_stages, acc, lds);
+      gemm_epilogue<PREC, WM, WT, MB, true>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+    }
     __syncthreads();
   }
 }
 
 // Sum the workspace partials of every split tile in work-group order and run
 // the epilogue.  Tiles finished inside k_gemm are skipped.
-template <int PREC, int WM, int WT, int MB>
+template <int PREC, int WM, int WT, int MB, bool TR>
 __global__ void __launch_bounds__(256) k_gemm_fixup(const float* __restrict__ ws, GemmGeom g) {
   constexpr int RBW = WM * MB;
   constexpr int NREG = MB * 4 * 16;
@@ -690,7 +716,7 @@ __global__ void __launch_bounds__(256) k_gemm_fixup(const float* __restrict__ ws
         for (int j = 0; j < 16; ++j) acc[rb][c][j] += w[((rb * 4 + c) * 16 + j) * 256];
   }
   const int mtile = (int)(tile / g.n_ntiles), ntile = (int)(tile % g.n_ntiles);
-  gemm_epilogue<PREC, WM, WT, MB>(acc, g.out, g, (int64_t)mtile * RBW, ntile, red);
+  gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out, g, (int64_t)mtile * RBW, ntile, red);
 }
 
 // Plan of the lockstep split for n_tiles tiles of S stages on G = n_cu
@@ -741,7 +767,7 @@ static bool plan_split(int64_t n_tiles, int S, int G, int64_t slot_floats, int64
   return true;
 }
 
-template <int PREC, int WM, int WT, int MB>
+template <int PREC, int WM, int WT, int MB, bool TR>
 static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B, float* out, float* ws,
                                     int64_t ws_floats, int* tile_cnt, GemmGeom g, int n_mtiles, int n_cu,
                                     int sched, int* used) {
@@ -758,7 +784,7 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
     if (plan_split(n_tiles, g.n_stages, n_cu, (int64_t)NREG * 256, ws_floats,
                    sched == MHC_SCHED_AUTO ? 0.05 : 0.0, &sp)) {
       sp.cnt = tile_cnt;
-      hipLaunchKernelGGL((k_gemm_split<PREC, WM, WT, MB>), dim3((unsigned)n_cu), dim3(256), 0, s, ws, g, sp);
+      hipLaunchKernelGGL((k_gemm_split<PREC, WM, WT, MB, TR>), dim3((unsigned)n_cu), dim3(256), 0, s, ws, g, sp);
       *used = MHC_SCHED_SPLIT;
       return hipGetLastError();
     }
@@ -780,11 +806,11 @@ static hipError_t launch_gemm_shape(hipStream_t s, const void* E, const void* B,
       g.ipw = g.n_stages;
     }
   }
-  hipLaunchKernelGGL((k_gemm<PREC, WM, WT, MB>), dim3((unsigned)G), dim3(256), 0, s, ws, g);
+  hipLaunchKernelGGL((k_gemm<PREC, WM, WT, MB, TR>), dim3((unsigned)G), dim3(256), 0, s, ws, g);
   *used = sk ? MHC_SCHED_STREAMK : MHC_SCHED_TILES;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !sk) return e;
-  hipLaunchKernelGGL((k_gemm_fixup<PREC, WM, WT, MB>), dim3((unsigned)n_tiles), dim3(256), 0, s, ws, g);
+  hipLaunchKernelGGL((k_gemm_fixup<PREC, WM, WT, MB, TR>), dim3((unsigned)n_tiles), dim3(256), 0, s, ws, g);
   return hipGetLastError();
 }
 
@@ -802,22 +828,27 @@ static hipError_t launch_gemm_prec(hipStream_t s, const void* E, const void* B, 
   g.layout_g = layout_g;
   g.row_scale = row_scale;
   g.col_scale = col_scale;
+  // HNEMA (layout 0) in the step-major accumulator orientation, GKMA in the
+  // slot-major one
+#define MHC_SHAPE(WM, WT, MB, ROWS)                                                                              \
+  (layout_g ? launch_gemm_shape<PREC, WM, WT, MB, false>(s, E, B, out, ws, ws_floats, tile_cnt, g,               \
+                                                         (int)(M_pad / (ROWS)), n_cu, sched, used)              \
+            : launch_gemm_shape<PREC, WM, WT, MB, true>(s, E, B, out, ws, ws_floats, tile_cnt, g,                \
+                                                        (int)(M_pad / (ROWS)), n_cu, sched, used))
   if (ntb % 4 == 0) {
     // 128 slots x 4 t-blocks per tile
     g.n_ntiles = ntb / 4;
     *n_parts = g.n_ntiles;
-    return launch_gemm_shape<PREC, 1, 4, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 128), n_cu, sched,
-                                                   used);
+    return MHC_SHAPE(1, 4, 4, 128);
   } else if (ntb % 2 == 0) {
     g.n_ntiles = ntb / 2;
     *n_parts = g.n_ntiles;
-    return launch_gemm_shape<PREC, 2, 2, 4>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched,
-                                                   used);
+    return MHC_SHAPE(2, 2, 4, 256);
   }
   g.n_ntiles = ntb;
   *n_parts = g.n_ntiles;
-  return launch_gemm_shape<PREC, 4, 1, 2>(s, E, B, out, ws, ws_floats, tile_cnt, g, (int)(M_pad / 256), n_cu, sched,
-                                                   used);
+  return MHC_SHAPE(4, 1, 2, 256);
+#undef MHC_SHAPE
 }
 
 hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t K_pad,
