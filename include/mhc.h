@@ -93,8 +93,12 @@ typedef enum {
  * motion of a 2D material):
  *   J_n^{mu nu}(s) = Xdot_n(s) sum_i m_i^{-1/2} W_i^{mu nu}(s) e_{i,n}^nu,
  * so that sum_nu J_n^{mu nu} = J_n^mu, and J^{mu nu}(s) = sum_i W_i^{mu nu}(s)
- * v_i^nu(s) for the Eq. 10 total.  It costs one contraction per direction
- * (three per block), is read with mhc_read_hnema_dir / mhc_read_gkma_dir
+ * v_i^nu(s) for the Eq. 10 total.  T-batched FP32 and split-BF16 contexts
+ * run it as one contraction per block (K ordered by direction, so the three
+ * brackets are the contraction over its three thirds while Xdot runs over
+ * all of K: the MFMA work of the unsplit contraction); e4m3 precisions and
+ * t_block = 1 run one contraction per direction.  It is read with
+ * mhc_read_hnema_dir / mhc_read_gkma_dir
  * (mhc_read_hnema and mhc_read_gkma then return the sums over nu), and is not
  * available to grouped pushes or mhc_read_block_currents (UNSUPPORTED). */
 enum { MHC_HNEMA = 1, MHC_GKMA = 2, MHC_DIRECTIONAL = 4, MHC_CROSS = 8 };

@@ -319,11 +319,12 @@ struct GemmCfg {
 };
 
 // Accumulate stages [s0, s1) of the tile with row blocks rb0.. and t-block
-// column tb (per wave) into acc, in the orientation TR.  All 256 threads take part; lds is the
+// column tb (per wave) into acc, in the orientation TR; channels below c0
+// keep their values and add to them.  All 256 threads take part; lds is the
 // double-buffered A stage.  Leaves the work-group synchronized.
 template <int PREC, int WM, int WT, int MB, bool TR>
 __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int ntile, int s0, int s1,
-                                             f32x16 (&acc)[MB][4], u32x4 (*lds)[WM * MB][SU]) {
+                                             f32x16 (&acc)[MB][4], u32x4 (*lds)[WM * MB][SU], int c0 = 0) {
   using C = GemmCfg<PREC>;
   constexpr int RBW = WM * MB;
   constexpr int UPC = C::UPC, CPS = C::CPS, NBF = C::NBF, NBS = C::NBS;
@@ -453,12 +454,15 @@ __device__ __forceinline__ void gemm_segment(const GemmGeom& g, int64_t rb0, int
     }
   };
 
+  // channels c0 .. 3 start from zero (c0 = 1 keeps the running Xdot)
 #pragma unroll
   for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
+      if (c >= c0) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
+        for (int j = 0; j < 16; ++j) acc[rb][c][j] = 0.f;
+      }
 
   // prologue: A(s0) -> LDS buffer 0, A(s0+1) in staging set 1, B(s0) in registers
   const int last = s1 - 1;
@@ -645,6 +649,66 @@ k_gemm_split(float* __restrict__ ws, GemmGeom g, SplitPlan sp) {
       }
     }
     if (finish) gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
+    __syncthreads();
+  }
+}
+
+// The bracket channels (1 .. 3) of the accumulators in a workspace slot,
+// one contiguous 1 KiB row per store or load of the 256 threads.
+template <int MB>
+__device__ __forceinline__ void bracket_store(float* __restrict__ w, const f32x16 (&acc)[MB][4]) {
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) w[((rb * 3 + c - 1) * 16 + j) * 256] = acc[rb][c][j];
+}
+
+template <int MB>
+__device__ __forceinline__ void bracket_load(const float* __restrict__ w, f32x16 (&acc)[MB][4]) {
+#pragma unroll
+  for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[rb][c][j] = w[((rb * 3 + c - 1) * 16 + j) * 256];
+}
+
+// Motion-direction split in one contraction (Sec. II, remark after Eq. 10).
+// K is ordered direction-major (dof (i, nu) at k = nu n3 + i, each third a
+// whole number s3 of stages), so the bracket of Eq. 16 restricted to
+// direction nu, A_n^{mu nu} = sum_i W_i^{mu nu} e_{i,n}^nu / sqrt(m_i), is
+// the contraction over third nu alone, while Xdot_n needs all of K.  Channel
+// 0 therefore runs on across the thirds and channels 1 .. 3 restart at each;
+// the brackets of thirds 0 and 1 wait in the work-group's two workspace slots
+// until Xdot is complete, then the epilogue runs once per direction into
+// out + nu * region.  The MFMA work is that of one plain contraction.
+// Persistent: work-group b takes tiles b, b + G, ...
+template <int PREC, int WM, int WT, int MB, bool TR>
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+k_gemm_dir(float* __restrict__ ws, GemmGeom g, int s3, int64_t region) {
+  static_assert(!is_fp8(PREC), "the e4m3 activation scales are per whole column");
+  constexpr int RBW = WM * MB;
+  constexpr int NBR = MB * 3 * 16;                               // bracket floats per lane
+  __shared__ u32x4 lds[2][RBW][SU];
+  static_assert(2 * RBW * SU * 4 >= WT * RBW * 32 * 3, "the epilogue reuses the A stages' LDS");
+  const int64_t n_tiles = (g.M_pad / (RBW * 32)) * g.n_ntiles;
+  float* slot = ws + (int64_t)blockIdx.x * 2 * NBR * 256 + threadIdx.x;
+  float* red = reinterpret_cast<float*>(&lds[0][0][0]);
+  f32x16 acc[MB][4];
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t rb0 = (tile / g.n_ntiles) * RBW;
+    const int ntile = (int)(tile % g.n_ntiles);
+    for (int nu = 0; nu < 3; ++nu) {
+      gemm_segment<PREC, WM, WT, MB, TR>(g, rb0, ntile, nu * s3, (nu + 1) * s3, acc, lds, nu == 0 ? 0 : 1);
+      if (nu < 2) bracket_store<MB>(slot + (int64_t)nu * NBR * 256, acc);
+    }
+    gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + 2 * region, g, rb0, ntile, red);
+    for (int nu = 0; nu < 2; ++nu) {
+      bracket_load<MB>(slot + (int64_t)nu * NBR * 256, acc);
+      gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + nu * region, g, rb0, ntile, red);
+    }
     __syncthreads();
   }
 }
@@ -865,6 +929,65 @@ hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, in
     default: return MHC_GEMM(PREC_FP32);
   }
 #undef MHC_GEMM
+}
+
+template <int PREC, int WM, int WT, int MB, bool TR>
+static hipError_t launch_dir_shape(hipStream_t s, GemmGeom g, int s3, int64_t region, float* ws, int64_t ws_floats,
+                                   int n_cu) {
+  constexpr int NBR = MB * 3 * 16;
+  const int64_t n_tiles = (g.M_pad / (WM * MB * 32)) * g.n_ntiles;
+  const int64_t G = std::min<int64_t>({n_tiles, (int64_t)n_cu, ws_floats / ((int64_t)2 * NBR * 256)});
+  if (G < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm_dir<PREC, WM, WT, MB, TR>), dim3((unsigned)G), dim3(256), 0, s, ws, g, s3, region);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_gemm_dir_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t n3, int ntb,
+                                       float* out, int64_t region, int layout_g, int* n_parts, float* ws,
+                                       int64_t ws_floats, int n_cu) {
+  GemmGeom g{};
+  g.K_pad = 3 * n3;
+  g.M_pad = M_pad;
+  g.ntb = ntb;
+  g.n_stages = (int)(g.K_pad / 32);
+  g.layout_g = layout_g;
+  g.E = E;
+  g.B = B;
+  g.out = out;
+  const int s3 = (int)(n3 / 32);
+#define MHC_DSHAPE(WM, WT, MB)                                                                           \
+  (layout_g ? launch_dir_shape<PREC, WM, WT, MB, false>(s, g, s3, region, ws, ws_floats, n_cu)            \
+            : launch_dir_shape<PREC, WM, WT, MB, true>(s, g, s3, region, ws, ws_floats, n_cu))
+  if (ntb % 4 == 0) {
+    g.n_ntiles = ntb / 4;
+    *n_parts = g.n_ntiles;
+    return MHC_DSHAPE(1, 4, 4);
+  } else if (ntb % 2 == 0) {
+    g.n_ntiles = ntb / 2;
+    *n_parts = g.n_ntiles;
+    return MHC_DSHAPE(2, 2, 4);
+  }
+  g.n_ntiles = ntb;
+  *n_parts = g.n_ntiles;
+  return MHC_DSHAPE(4, 1, 2);
+#undef MHC_DSHAPE
+}
+
+hipError_t launch_gemm_dir(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t n3, int ntb,
+                           float* out, int64_t region, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
+                           int n_cu) {
+  if (n3 <= 0 || n3 % 32 != 0) return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_BF16X3:
+      return launch_gemm_dir_prec<PREC_BF16X3>(s, E, B, M_pad, n3, ntb, out, region, layout_g, n_parts, ws, ws_floats,
+                                               n_cu);
+    case PREC_FP32:
+      return launch_gemm_dir_prec<PREC_FP32>(s, E, B, M_pad, n3, ntb, out, region, layout_g, n_parts, ws, ws_floats,
+                                             n_cu);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 // ----------------------------------------------------------- tile shapes

@@ -17,10 +17,12 @@ namespace mhc {
 
 // ------------------------------------------------------------ basis store
 // One thread per output piece: FP32 piece = 4 floats, BF16 piece = 8 hi + 8 lo.
+// With n3 > 0 the dofs are stored direction-major: dof 3 i + nu at
+// k = nu * n3 + i (the direction split's operand order), zero for i >= K / 3.
 template <int PREC>
 __global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ rows, int64_t n_rows,
                                                      int64_t K, const int32_t* __restrict__ slot_of_row,
-                                                     void* __restrict__ E, int64_t K_pad, int gemv) {
+                                                     void* __restrict__ E, int64_t K_pad, int gemv, int64_t n3) {
   constexpr int PW = (PREC == PREC_FP32) ? 4 : 8;     // dofs per piece
   const int64_t pieces = K_pad / PW;
   const int64_t r = blockIdx.y;
@@ -32,15 +34,22 @@ __global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ 
   const double* row = rows + r * K;
   const int64_t rb = slot >> 5;
   const int rr = slot & 31;
+  auto val = [&](int64_t k) -> double {
+    if (n3 > 0) {
+      const int64_t i = k % n3, nu = k / n3;
+      return (3 * i < K && nu < 3) ? row[3 * i + nu] : 0.0;
+    }
+    return k < K ? row[k] : 0.0;
+  };
   if constexpr (PREC == PREC_FP32) {
     const int64_t kc = k0 >> 3;
     const int h = (int)((k0 >> 2) & 1);
     const int lane = rr + 32 * h;
     float4 o;
-    o.x = (k0 + 0 < K) ? (float)row[k0 + 0] : 0.f;
-    o.y = (k0 + 1 < K) ? (float)row[k0 + 1] : 0.f;
-    o.z = (k0 + 2 < K) ? (float)row[k0 + 2] : 0.f;
-    o.w = (k0 + 3 < K) ? (float)row[k0 + 3] : 0.f;
+    o.x = (float)val(k0 + 0);
+    o.y = (float)val(k0 + 1);
+    o.z = (float)val(k0 + 2);
+    o.w = (float)val(k0 + 3);
     float4* dst = reinterpret_cast<float4*>(E);
     if (gemv)   // row-major layout of the per-step path
       dst[(int64_t)slot * (K_pad >> 2) + (k0 >> 2)] = o;
@@ -54,8 +63,8 @@ __global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ 
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
       uint16_t h0, l0, h1, l1;
-      split_bf16_from_f64((k0 + e < K) ? row[k0 + e] : 0.0, h0, l0);
-      split_bf16_from_f64((k0 + e + 1 < K) ? row[k0 + e + 1] : 0.0, h1, l1);
+      split_bf16_from_f64(val(k0 + e), h0, l0);
+      split_bf16_from_f64(val(k0 + e + 1), h1, l1);
       hi[e / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
       lo[e / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
     }
@@ -67,17 +76,18 @@ __global__ void __launch_bounds__(256) k_basis_store(const double* __restrict__ 
 }
 
 hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows, int64_t K,
-                              const int32_t* slot_of_row, void* E, int64_t K_pad, int gemv) {
+                              const int32_t* slot_of_row, void* E, int64_t K_pad, int gemv, int64_t n3) {
   if (n_rows <= 0) return hipSuccess;
+  if (n3 > 0 && (gemv || 3 * n3 != K_pad || 3 * n3 < K)) return hipErrorInvalidValue;
   const int PW = (prec == PREC_FP32) ? 4 : 8;
   const int64_t pieces = K_pad / PW;
   dim3 grid((unsigned)((pieces + 255) / 256), (unsigned)n_rows);
   if (prec == PREC_FP32)
     hipLaunchKernelGGL(k_basis_store<PREC_FP32>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad,
-                       gemv);
+                       gemv, n3);
   else
     hipLaunchKernelGGL(k_basis_store<PREC_BF16X3>, grid, dim3(256), 0, s, rows, n_rows, K, slot_of_row, E, K_pad,
-                       0);
+                       0, n3);
   return hipGetLastError();
 }
 
@@ -259,8 +269,12 @@ __device__ __forceinline__ void input_prep_body(const float* v, const float* W, 
   const int t = tb * PREP_T + tl;
   const int64_t i0 = (int64_t)chunk * ATOMS_PER_PREP;
 
+  // dir == DIR_ALL: all three directions in one operand, K direction-major
+  // (dof (i, nu) at k = nu * K_pad / 3 + i), and the split partials of every
+  // direction; otherwise atom-major (k = 3 i + alpha)
+  const bool dm = (dir == DIR_ALL);
   double j0 = 0.0, j1 = 0.0, j2 = 0.0;
-  double d0 = 0.0, d1 = 0.0, d2 = 0.0;    // split partials (dir >= 0)
+  double dd[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};   // split partials [nu][mu] (dir >= 0)
 #pragma unroll
   for (int q = 0; q < ATOMS_PER_PREP / 8; ++q) {
     const int a = sub + 8 * q;
@@ -278,25 +292,32 @@ __device__ __forceinline__ void input_prep_body(const float* v, const float* W, 
 #pragma unroll
       for (int mu = 0; mu < 3; ++mu)
 #pragma unroll
-        for (int nu = 0; nu < 3; ++nu) w[mu][nu] = (dir < 0 || nu == dir) ? Wl[3 * mu + nu] * ism : 0.f;
+        for (int nu = 0; nu < 3; ++nu) w[mu][nu] = (dir < 0 || dm || nu == dir) ? Wl[3 * mu + nu] * ism : 0.f;
       // Eq. 10 in float64: J^mu += sum_nu W^{mu nu} v^nu
       const double dvx = vx, dvy = vy, dvz = vz;
       j0 += (double)Wl[0] * dvx + (double)Wl[1] * dvy + (double)Wl[2] * dvz;
       j1 += (double)Wl[3] * dvx + (double)Wl[4] * dvy + (double)Wl[5] * dvz;
       j2 += (double)Wl[6] * dvx + (double)Wl[7] * dvy + (double)Wl[8] * dvz;
-      if (dir >= 0) {
+      if (dm) {
+        const double vv[3] = {dvx, dvy, dvz};
+#pragma unroll
+        for (int nu = 0; nu < 3; ++nu)
+#pragma unroll
+          for (int mu = 0; mu < 3; ++mu) dd[nu][mu] += (double)Wl[3 * mu + nu] * vv[nu];
+      } else if (dir >= 0) {
         const double vd = dir == 0 ? dvx : (dir == 1 ? dvy : dvz);
-        d0 += (double)Wl[dir] * vd;
-        d1 += (double)Wl[3 + dir] * vd;
-        d2 += (double)Wl[6 + dir] * vd;
+        dd[0][0] += (double)Wl[dir] * vd;
+        dd[0][1] += (double)Wl[3 + dir] * vd;
+        dd[0][2] += (double)Wl[6 + dir] * vd;
       }
     }
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
-      ch[0][tl][3 * a + al] = u[al];
-      ch[1][tl][3 * a + al] = w[0][al];
-      ch[2][tl][3 * a + al] = w[1][al];
-      ch[3][tl][3 * a + al] = w[2][al];
+      const int pos = dm ? al * ATOMS_PER_PREP + a : 3 * a + al;
+      ch[0][tl][pos] = u[al];
+      ch[1][tl][pos] = w[0][al];
+      ch[2][tl][pos] = w[1][al];
+      ch[3][tl][pos] = w[2][al];
     }
   }
   // fixed-order reduction over the 8 threads of a step
@@ -311,20 +332,31 @@ __device__ __forceinline__ void input_prep_body(const float* v, const float* W, 
     jp[0] = j0; jp[1] = j1; jp[2] = j2;
   }
   if (dir >= 0) {
+    // jd_part[nu][t][chunk][mu] (one direction: nu = 0 only)
+    const int n_nu = dm ? 3 : 1;
 #pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-      d0 += __shfl_xor(d0, off);
-      d1 += __shfl_xor(d1, off);
-      d2 += __shfl_xor(d2, off);
-    }
-    if (sub == 0 && t < t_pad) {
-      double* jp = jd_part + ((int64_t)t * n_chunks + chunk) * 3;
-      jp[0] = d0; jp[1] = d1; jp[2] = d2;
+    for (int nu = 0; nu < 3; ++nu) {
+      if (nu >= n_nu) break;
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1)
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) dd[nu][mu] += __shfl_xor(dd[nu][mu], off);
+      if (sub == 0 && t < t_pad) {
+        double* jp = jd_part + ((int64_t)nu * t_pad + t) * n_chunks * 3 + (int64_t)chunk * 3;
+        jp[0] = dd[nu][0]; jp[1] = dd[nu][1]; jp[2] = dd[nu][2];
+      }
     }
   }
   __syncthreads();
 
   const int64_t k_base = (int64_t)chunk * PREP_K;
+  // global k of local position l (the first of a piece; pieces never cross a
+  // direction's 32 positions)
+  const int64_t n3 = K_pad / 3;
+  auto k_of = [&](int l) -> int64_t {
+    return dm ? (int64_t)(l / ATOMS_PER_PREP) * n3 + (int64_t)chunk * ATOMS_PER_PREP + l % ATOMS_PER_PREP
+              : k_base + l;
+  };
   if constexpr (MODE == 0) {
     // plain [t][4][K_pad]: 4 * 32 * 96 floats, coalesced along k
     for (int idx = tid; idx < 4 * PREP_T * PREP_K; idx += 256) {
@@ -345,7 +377,7 @@ __device__ __forceinline__ void input_prep_body(const float* v, const float* W, 
       const int tt = idx & 31;
       const int g = (idx >> 5) % (PREP_K / 4);
       const int c = (idx >> 5) / (PREP_K / 4);
-      const int64_t k = k_base + 4 * g;
+      const int64_t k = k_of(4 * g);
       const int64_t kc = k >> 3;
       const int h = (int)((k >> 2) & 1);
       const int64_t cb = (int64_t)c * ntb + tb;
@@ -403,7 +435,7 @@ __device__ __forceinline__ void input_prep_body(const float* v, const float* W, 
       const int tt = idx & 31;
       const int g = (idx >> 5) % (PREP_K / 8);
       const int c = (idx >> 5) / (PREP_K / 8);
-      const int64_t k = k_base + 8 * g;
+      const int64_t k = k_of(8 * g);
       const int64_t kc = k >> 4;
       const int h = (int)((k >> 3) & 1);
       const int64_t cb = (int64_t)c * ntb + tb;
@@ -499,6 +531,9 @@ hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v,
                              void* B, int64_t K_pad, double* jt_part, float* col_scale,
                              const float* col_part, const float* const* tab, int dir, double* jd_part) {
   const int n_chunks = (int)((N + ATOMS_PER_PREP - 1) / ATOMS_PER_PREP);
+  if (dir == DIR_ALL && (plain || (prec != PREC_FP32 && prec != PREC_BF16X3) || K_pad % 96 != 0 ||
+                         K_pad / 3 < (int64_t)n_chunks * ATOMS_PER_PREP))
+    return hipErrorInvalidValue;
   dim3 grid((unsigned)n_chunks, (unsigned)((t_pad + PREP_T - 1) / PREP_T));
 #define MHC_PREP(M)                                                                                          \
   hipLaunchKernelGGL(k_input_prep<M>, grid, dim3(256), 0, s, v, W, sqrt_m, inv_sqrt_m, N, t_count, t_pad, B, \

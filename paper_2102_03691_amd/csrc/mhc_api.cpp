@@ -96,6 +96,9 @@ struct mhc_ctx {
   // loading
   bool rows_started = false, finalized = false;
   int64_t K_pad = 0, M_used = 0, M_pad = 0;
+  // > 0: the direction split as one contraction, K direction-major with
+  // thirds of n3 dofs (T-batched FP32 and split-BF16 contexts)
+  int64_t n3 = 0;
   std::vector<int32_t> slot_of_mode, bin_off;
   std::vector<uint8_t> row_loaded;
 
@@ -132,7 +135,8 @@ struct mhc_ctx {
   hipStream_t copy_stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_copied[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
   double *d_hsum = nullptr, *d_hcomp = nullptr, *d_tsum = nullptr, *d_tcomp = nullptr;
-  int n_dir = 1;                 // 3 with the motion-direction split (one pass per direction)
+  int n_dir = 1;                 // 3 with the motion-direction split
+  int64_t j_region = 0;          // one contraction split: floats of each direction's modal currents in dJ
   double* d_jd = nullptr;        // split Eq. 10 partials of the current pass
   double* d_jdtot = nullptr;     // split Eq. 10 per-step totals
   double *d_tdsum = nullptr, *d_tdcomp = nullptr;   // [dir][mu] time sums of the split totals
@@ -451,9 +455,16 @@ static mhc_status start_rows_impl(mhc_ctx* ctx) {
     if (b >= 0) slot[n] = fill[b]++;
   }
   const int64_t M_used = off[nb];
-  // input prep writes whole 32-atom (96-dof) groups, so cover them
-  const int64_t K_pad =
-      round_up(3 * round_up(ctx->N, ATOMS_PER_PREP), ctx->cfg.t_block == 1 ? K_ALIGN_GEMV : K_ALIGN);
+  // input prep writes whole 32-atom (96-dof) groups, so cover them; the
+  // one-contraction direction split orders K direction-major, each third a
+  // whole number of 32-dof stages
+  const auto& cf = ctx->cfg;
+  const bool dir1 = (cf.methods & MHC_DIRECTIONAL) && cf.t_block > 1 &&
+                    (cf.precision == MHC_PREC_FP32 || cf.precision == MHC_PREC_BF16X3);
+  const int64_t n3 = dir1 ? round_up(ctx->N, K_ALIGN) : 0;
+  const int64_t K_pad = dir1 ? 3 * n3
+                             : round_up(3 * round_up(ctx->N, ATOMS_PER_PREP),
+                                        ctx->cfg.t_block == 1 ? K_ALIGN_GEMV : K_ALIGN);
   const int64_t M_pad = round_up(std::max<int64_t>(M_used, 1), M_ALIGN);
   // bytes per element: fp32 or bf16 hi + lo 4, e4m3 hi + lo 2, e4m3 1
   const int prec = ctx->cfg.precision;
@@ -483,6 +494,7 @@ static mhc_status start_rows_impl(mhc_ctx* ctx) {
   ctx->bin_off = std::move(off);
   ctx->M_used = M_used;
   ctx->K_pad = K_pad;
+  ctx->n3 = n3;
   ctx->M_pad = M_pad;
   ctx->row_loaded.assign(M, 0);
   ctx->rows_started = true;
@@ -522,7 +534,7 @@ mhc_status mhc_load_eigvec_rows(mhc_ctx* ctx, int64_t mode0, int64_t n_rows, con
               "basis store");
     else
       HIP_TRY(launch_basis_store(ctx->stream, prec, src, nr, ctx->K, ctx->d_slot, ctx->dE, ctx->K_pad,
-                                 ctx->cfg.t_block == 1 ? 1 : 0),
+                                 ctx->cfg.t_block == 1 ? 1 : 0, ctx->n3),
               "basis store");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "basis store sync");
   }
@@ -577,6 +589,8 @@ static mhc_status finalize_impl(mhc_ctx* ctx) {
   const int64_t n_parts = (c.t_block == 1) ? chunk : std::max(1, t_pad / 32);
   size_t j_bytes = (size_t)n_parts * M_pad * 3 * 4;
   if (gk) j_bytes = std::max(j_bytes, (size_t)3 * M_pad * t_pad * 4);
+  ctx->j_region = ctx->n3 ? (int64_t)(j_bytes / 4) : 0;
+  if (ctx->n3) j_bytes *= 3;          // one region per direction
   const int64_t R3 = 3 * (nb + 1);
   const int L = gk ? c.corr_len : 0;
   void *pB, *pJ, *pjt, *pv, *pW, *psm, *pism, *poff, *pacc, *pout;
@@ -606,9 +620,10 @@ static mhc_status finalize_impl(mhc_ctx* ctx) {
   size_t out_doubles = (size_t)nd * nb * 3 + 12;
   if (nd > 1) {
     void *pjd, *pjdt;
-    if ((st = dev_alloc(ctx, (size_t)t_pad * n_ac * 3 * 8, &pjd, "split total partials"))) return st;
+    const size_t jd_bytes = (size_t)(ctx->n3 ? 3 : 1) * t_pad * n_ac * 3 * 8;   // [nu][t][chunk][mu]
+    if ((st = dev_alloc(ctx, jd_bytes, &pjd, "split total partials"))) return st;
     if ((st = dev_alloc(ctx, (size_t)t_pad * 3 * 8, &pjdt, "split total current"))) return st;
-    HIP_TRY(hipMemsetAsync(pjd, 0, (size_t)t_pad * n_ac * 3 * 8, ctx->stream), "zero split partials");
+    HIP_TRY(hipMemsetAsync(pjd, 0, jd_bytes, ctx->stream), "zero split partials");
     ctx->d_jd = reinterpret_cast<double*>(pjd);
     ctx->d_jdtot = reinterpret_cast<double*>(pjdt);
   }
@@ -809,11 +824,16 @@ static mhc_status block_back(mhc_ctx* ctx, int t_count, int n_parts, const int64
   const bool gk = c.methods & MHC_GKMA;
   const int64_t ld = ctx->t_pad;
   const int d = dir < 0 ? 0 : dir;
+  // the one-contraction split leaves every direction's currents and split
+  // partials in their own regions; the pass-per-direction form reuses one
+  const bool one = ctx->n3 > 0 && dir >= 0;
   HIP_TRY(launch_total(ctx->stream, ctx->d_jt, ctx->n_atom_chunks, t_count, ctx->d_jtot), "total current");
   if (dir >= 0 && ctx->d_tdsum)
-    HIP_TRY(launch_total(ctx->stream, ctx->d_jd, ctx->n_atom_chunks, t_count, ctx->d_jdtot), "split total current");
+    HIP_TRY(launch_total(ctx->stream, ctx->d_jd + (one ? (int64_t)d * ctx->t_pad * ctx->n_atom_chunks * 3 : 0),
+                         ctx->n_atom_chunks, t_count, ctx->d_jdtot),
+            "split total current");
   ReduceArgs a{};
-  a.in = ctx->dJ;
+  a.in = ctx->dJ + (one ? d * ctx->j_region : 0);
   a.layout_g = gk ? 1 : 0;
   a.n_parts = n_parts;
   a.M_pad = ctx->M_pad;
@@ -907,6 +927,24 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
   const auto& c = ctx->cfg;
   const bool gk = c.methods & MHC_GKMA;
   mhc_status st;
+  if (ctx->n3) {
+    // direction split in one contraction: one operand with every direction,
+    // one launch, then the back end once per direction on its own region
+    if ((st = block_front(ctx, v, W, t_count, nullptr, DIR_ALL))) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed && (st = timing_begin(ctx, &e0, &e1))) return st;
+    int n_parts = 0;
+    HIP_TRY(launch_gemm_dir(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->n3, ctx->t_pad / 32, ctx->dJ,
+                            ctx->j_region, gk ? 1 : 0, &n_parts, wk.ws, wk.ws_floats, ctx->n_cu),
+            "direction-split contraction");
+    ctx->last_sched = MHC_SCHED_TILES;
+    if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
+    for (int d = 0; d < 3; ++d)
+      if ((st = block_back(ctx, t_count, n_parts, nullptr, d))) return st;
+    ctx->n_samples += t_count;
+    ctx->last_block = t_count;
+    return MHC_OK;
+  }
   for (int d = 0; d < ctx->n_dir; ++d) {
     const int dir = ctx->n_dir > 1 ? d : -1;
     if ((st = block_front(ctx, v, W, t_count, nullptr, dir))) return st;

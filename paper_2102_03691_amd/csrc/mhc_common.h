@@ -26,6 +26,7 @@ namespace mhc {
 //   B  FP32   [4*NTB][K_pad/8][64][4]                 float  (cb = c*NTB + tb)
 //   B  BF16   [4*NTB][K_pad/16][2][64][8]             bf16
 // Channels c: 0 = u = sqrt(m) v, 1..3 = w^mu = W^{mu .} / sqrt(m).
+constexpr int DIR_ALL = 3;     // input prep: every direction, K direction-major
 constexpr int K_ALIGN = 128;    // K_pad multiple (one e4m3 stage is 128 dofs)
 constexpr int K_ALIGN_GEMV = 512;  // per-step path: rows of 128 units, 2 x 64 lanes per iteration pair
 constexpr int M_ALIGN = 256;    // M_pad multiple
@@ -39,9 +40,11 @@ enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1, PREC_FP8 = 2, PREC_FP8X3 = 3 };
 
 // Convert n_rows float64 E^T rows (device, row r = mode r0 + r) into the
 // storage layout.  slot_of_row[r] is the destination slot (-1 = skip).
-// gemv = 1 (FP32 only): the row-major layout of the per-step path.
+// gemv = 1 (FP32 only): the row-major layout of the per-step path.  n3 > 0
+// (T-batched FP32 / BF16, K_pad = 3 n3): dofs direction-major, dof 3 i + nu
+// at k = nu n3 + i (the one-contraction direction split).
 hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows,
-                              int64_t K, const int32_t* slot_of_row, void* E, int64_t K_pad, int gemv);
+                              int64_t K, const int32_t* slot_of_row, void* E, int64_t K_pad, int gemv, int64_t n3);
 
 // e4m3 basis store: per-mode scale s_n = max|E[.][n]| / 448 into row_scale[slot],
 // then E/s_n as e4m3 (x3: plus the e4m3 residual).
@@ -66,7 +69,11 @@ hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const
 // dir in {0,1,2} builds the virial channels of the motion-direction split
 // (W_i^{mu dir} / sqrt(m_i) on dof alpha = dir only) and writes the split
 // partial currents sum_i W_i^{mu dir} v_i^dir to jd_part[t][chunk][3];
-// dir = -1 builds the whole operand and leaves jd_part alone.
+// dir = DIR_ALL (FP32 / BF16 fragments only) builds the whole operand with K
+// direction-major (dof 3 i + nu at k = nu K_pad / 3 + i; K_pad / 3 covers
+// every atom chunk) and writes the split partials of all three directions to
+// jd_part[nu][t][chunk][3]; dir = -1 builds the whole operand atom-major and
+// leaves jd_part alone.
 hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v, const float* W,
                              const float* sqrt_m, const float* inv_sqrt_m, int64_t N,
                              int t_count, int t_pad, void* B, int64_t K_pad, double* jt_part,
@@ -128,6 +135,15 @@ hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, in
                        int64_t K_pad, int ntb, float* out, int layout_g, int* n_parts, float* ws,
                        int64_t ws_floats, int* tile_cnt, int n_cu, int sched, const float* row_scale,
                        const float* col_scale, int* used);
+
+// Motion-direction split as one contraction (FP32 or split-BF16): K ordered
+// direction-major (third nu = dofs (i, nu) at k = nu*n3 + i, n3 a multiple of
+// 32), out = three regions of `region` floats (direction nu at out + nu *
+// region), each laid out as launch_gemm's out.  ws holds two bracket slots
+// per work-group (ws_floats floats); n_cu = compute units.
+hipError_t launch_gemm_dir(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t n3, int ntb,
+                           float* out, int64_t region, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
+                           int n_cu);
 
 // Bin reduction + float64 accumulation.
 //   HNEMA-only: part sums in[n_parts][M_pad][3] -> hsum/hcomp[nb][3] (Neumaier)

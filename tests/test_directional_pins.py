@@ -129,3 +129,21 @@ def test_mutation_transposed_total_fails_golden():
     g, m, v, W = _two_atom()
     want = np.array([[float(x) for x in r[1:]] for r in g["total_dir"]])
     assert not np.array_equal(od.total_heat_current_directional(v, np.swapaxes(W, 2, 3))[0], want)
+
+
+def test_bench_plane_wave_split_reference_equals_dense_split():
+    """The benchmark's direction-split reference (FFT form per polarisation: a
+    plane-wave mode of polarisation nu moves atoms along nu only) equals the
+    dense split oracle on the same lattice basis and bins."""
+    import bench
+    lat = synth.BlochLattice((3, 3, 2))
+    m = synth.masses(lat.n_atoms)
+    v, W = synth.gen_steps(3, m, 0, 16)
+    nb = 7
+    ref = bench.lattice_reference(lat, m, v, W, nb, 5, 0)
+    bins = oracle.bin_of_mode(lat.frequencies, nb, 0.0, lat.f_max)
+    d = od.run_dense_directional(lat.eig_matrix(), m, v, W, bins, nb, 0, 1.0)
+    scale = np.abs(d["hnema_dir"]).max()
+    assert scale > 0
+    assert np.abs(ref["hnema_dir"] - d["hnema_dir"]).max() <= 1e-13 * scale
+    assert np.abs(ref["hnema_dir"].sum(axis=2) - ref["hnema"]).max() <= 1e-13 * scale

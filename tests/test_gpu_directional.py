@@ -1,5 +1,9 @@
 """Motion-direction split (Sec. II, remark after Eq. 10; closing remark of
-Sec. II.C) on the GPU against the FP64 oracle, through the C ABI.
+Sec. II.C) on the GPU against the FP64 oracle, through the C ABI.  T-batched
+FP32 and split-BF16 contexts run it as one contraction per block over a
+direction-major operand (the three per-direction brackets are the
+contraction's thirds of K); e4m3 and the per-step path run one contraction
+per direction.
 
 The basis is a dense random orthonormal matrix (540 x 540 for 180 atoms), so
 every mode moves every atom in every direction and the split is not the
@@ -79,7 +83,14 @@ def test_hnema_split(dense, prec, T, sched):
     announce(f"directional hnema prec={prec} T={T} sched={sched}")
     ref = dense.oracle()
     h = dense.context(HNEMA | DIR, prec, T, schedule=sched)
+    h.set_timing(True)
     dense.push(h, [1, 150, 149])
+    launches, _ = h.kernel_timing()
+    # FP32 / split-BF16 T-batched: one contraction per block over the
+    # direction-major operand; otherwise one per direction
+    blocks = sum(-(-n // T) for n in (1, 150, 149)) if T > 1 else None
+    if blocks is not None:
+        assert launches == (blocks if prec in (FP32, BF16X3) else 3 * blocks), launches
     avg_d, tot_d, n = h.read_hnema_dir()
     avg, tot, n2 = h.read_hnema()
     h.close()
