@@ -99,8 +99,9 @@ typedef enum {
  * all of K: the MFMA work of the unsplit contraction); e4m3 precisions and
  * t_block = 1 run one contraction per direction.  It is read with
  * mhc_read_hnema_dir / mhc_read_gkma_dir
- * (mhc_read_hnema and mhc_read_gkma then return the sums over nu), and is not
- * available to grouped pushes or mhc_read_block_currents (UNSUPPORTED). */
+ * (mhc_read_hnema and mhc_read_gkma then return the sums over nu).  Grouped
+ * pushes take it in its one-contraction form only; mhc_read_block_currents
+ * does not keep it (both UNSUPPORTED otherwise). */
 enum { MHC_HNEMA = 1, MHC_GKMA = 2, MHC_DIRECTIONAL = 4, MHC_CROSS = 8 };
 /* MHC_CROSS (with MHC_GKMA, not with MHC_DIRECTIONAL) adds the bin-bin
  * cross-correlations of the modal currents, <J_b^mu(t+tau) J_b2^nu(t)>
@@ -370,7 +371,8 @@ enum {
 /* systems: n finalized contexts with the same device, stream, precision and
  * t_block > 1.  flags: MHC_GROUP_* bits.
  * Errors: INVALID_ARG, STATE (a context not finalized or per-step),
- * UNSUPPORTED (a context with MHC_DIRECTIONAL), OOM, HIP. */
+ * UNSUPPORTED (a context with MHC_DIRECTIONAL in an e4m3 precision, whose
+ * split takes one contraction per direction), OOM, HIP. */
 mhc_status mhc_group_create(mhc_ctx *const *systems, int32_t n, int32_t flags, mhc_group **out);
 mhc_status mhc_group_destroy(mhc_group *group);
 const char *mhc_group_last_error(const mhc_group *group);

@@ -685,32 +685,41 @@ __device__ __forceinline__ void bracket_load(const float* __restrict__ w, f32x16
 // until Xdot is complete, then the epilogue runs once per direction into
 // out + nu * region.  The MFMA work is that of one plain contraction.
 // Persistent: work-group b takes tiles b, b + G, ...
+// One tile of the one-contraction direction split: the three thirds, the
+// brackets of thirds 0 and 1 through the work-group's slots (slot = this
+// thread's position in them), then the three epilogues.  Leaves the
+// work-group synchronized.
+template <int PREC, int WM, int WT, int MB, bool TR>
+__device__ __forceinline__ void dir_tile(const GemmGeom& g, int64_t rb0, int ntile, float* slot, f32x16 (&acc)[MB][4],
+                                         u32x4 (*lds)[WM * MB][SU]) {
+  static_assert(!is_fp8(PREC), "the e4m3 activation scales are per whole column");
+  constexpr int NBR = MB * 3 * 16;                               // bracket floats per lane
+  float* red = reinterpret_cast<float*>(&lds[0][0][0]);
+  for (int nu = 0; nu < 3; ++nu) {
+    gemm_segment<PREC, WM, WT, MB, TR>(g, rb0, ntile, nu * g.s3, (nu + 1) * g.s3, acc, lds, nu == 0 ? 0 : 1);
+    if (nu < 2) bracket_store<MB>(slot + (int64_t)nu * NBR * 256, acc);
+  }
+  gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + 2 * g.region, g, rb0, ntile, red);
+  for (int nu = 0; nu < 2; ++nu) {
+    bracket_load<MB>(slot + (int64_t)nu * NBR * 256, acc);
+    gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + nu * g.region, g, rb0, ntile, red);
+  }
+  __syncthreads();
+}
+
+// Persistent: work-group b takes tiles b, b + G, ... of one system.
 template <int PREC, int WM, int WT, int MB, bool TR>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
-k_gemm_dir(float* __restrict__ ws, GemmGeom g, int s3, int64_t region) {
-  static_assert(!is_fp8(PREC), "the e4m3 activation scales are per whole column");
+k_gemm_dir(GemmGeom g) {
   constexpr int RBW = WM * MB;
-  constexpr int NBR = MB * 3 * 16;                               // bracket floats per lane
+  constexpr int NBR = MB * 3 * 16;
   __shared__ u32x4 lds[2][RBW][SU];
   static_assert(2 * RBW * SU * 4 >= WT * RBW * 32 * 3, "the epilogue reuses the A stages' LDS");
   const int64_t n_tiles = (g.M_pad / (RBW * 32)) * g.n_ntiles;
-  float* slot = ws + (int64_t)blockIdx.x * 2 * NBR * 256 + threadIdx.x;
-  float* red = reinterpret_cast<float*>(&lds[0][0][0]);
+  float* slot = g.ws + (int64_t)blockIdx.x * 2 * NBR * 256 + threadIdx.x;
   f32x16 acc[MB][4];
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t rb0 = (tile / g.n_ntiles) * RBW;
-    const int ntile = (int)(tile % g.n_ntiles);
-    for (int nu = 0; nu < 3; ++nu) {
-      gemm_segment<PREC, WM, WT, MB, TR>(g, rb0, ntile, nu * s3, (nu + 1) * s3, acc, lds, nu == 0 ? 0 : 1);
-      if (nu < 2) bracket_store<MB>(slot + (int64_t)nu * NBR * 256, acc);
-    }
-    gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + 2 * region, g, rb0, ntile, red);
-    for (int nu = 0; nu < 2; ++nu) {
-      bracket_load<MB>(slot + (int64_t)nu * NBR * 256, acc);
-      gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + nu * region, g, rb0, ntile, red);
-    }
-    __syncthreads();
-  }
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+    dir_tile<PREC, WM, WT, MB, TR>(g, (tile / g.n_ntiles) * RBW, (int)(tile % g.n_ntiles), slot, acc, lds);
 }
 
 // Several systems in one persistent launch: work-groups pull whole tiles
@@ -739,6 +748,16 @@ k_gemm_group(const GemmGeom* __restrict__ sys, const GroupTile* __restrict__ til
     const int ntile = gt.tile % g.n_ntiles;
     const int64_t rb0 = (int64_t)mtile * RBW;
     // the orientation follows the system's method (uniform per work-group)
+    if constexpr (!is_fp8(PREC)) {
+      if (g.s3 > 0) {
+        float* slot = g.ws + (int64_t)blockIdx.x * 2 * (MB * 3 * 16) * 256 + threadIdx.x;
+        if (g.layout_g)
+          dir_tile<PREC, WM, WT, MB, false>(g, rb0, ntile, slot, acc, lds);
+        else
+          dir_tile<PREC, WM, WT, MB, true>(g, rb0, ntile, slot, acc, lds);
+        continue;
+      }
+    }
     if (g.layout_g) {
       gemm_segment<PREC, WM, WT, MB, false>(g, rb0, ntile, 0, g.n_stages, acc, lds);
       gemm_epilogue<PREC, WM, WT, MB, false>(acc, g.out, g, rb0, ntile, reinterpret_cast<float*>(&lds[0][0][0]));
@@ -938,7 +957,10 @@ static hipError_t launch_dir_shape(hipStream_t s, GemmGeom g, int s3, int64_t re
   const int64_t n_tiles = (g.M_pad / (WM * MB * 32)) * g.n_ntiles;
   const int64_t G = std::min<int64_t>({n_tiles, (int64_t)n_cu, ws_floats / ((int64_t)2 * NBR * 256)});
   if (G < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm_dir<PREC, WM, WT, MB, TR>), dim3((unsigned)G), dim3(256), 0, s, ws, g, s3, region);
+  g.s3 = s3;
+  g.region = region;
+  g.ws = ws;
+  hipLaunchKernelGGL((k_gemm_dir<PREC, WM, WT, MB, TR>), dim3((unsigned)G), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(256) k_input_prep_group(const PrepDesc* __rest
   const PrepDesc& s = d[i];
   const int local = blockIdx.x - s.wg0_prep;
   input_prep_body<MODE>(nullptr, nullptr, s.sqrt_m, s.inv_sqrt_m, s.N, t_count, s.t_pad, s.B, s.K_pad, s.jt_part,
-                        s.col_scale, s.col_part, s.tab, -1, nullptr, local % s.n_chunks, s.n_chunks,
+                        s.col_scale, s.col_part, s.tab, s.dir, s.jd_part, local % s.n_chunks, s.n_chunks,
                         local / s.n_chunks);
 }
 

@@ -765,6 +765,7 @@ mhc_status mhc_reset(mhc_ctx* ctx) {
 static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int t_count,
                               const float* const* tab = nullptr, int dir = -1) {
   const auto& c = ctx->cfg;
+  if (ctx->n3 && dir < 0) dir = DIR_ALL;   // one-contraction split: every direction in one operand
   if (ctx->d_colscale)
     HIP_TRY(launch_col_scale(ctx->stream, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count, ctx->t_pad,
                              ctx->d_colpart, tab, dir),
@@ -930,7 +931,7 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
   if (ctx->n3) {
     // direction split in one contraction: one operand with every direction,
     // one launch, then the back end once per direction on its own region
-    if ((st = block_front(ctx, v, W, t_count, nullptr, DIR_ALL))) return st;
+    if ((st = block_front(ctx, v, W, t_count))) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed && (st = timing_begin(ctx, &e0, &e1))) return st;
     int n_parts = 0;
@@ -1653,6 +1654,11 @@ mhc_status build_queue(mhc_group* g) {
     gemm_geom(g->prec, g->shape, c->dE, c->dB, c->dJ, c->M_pad, c->K_pad, g->ntb,
               (c->cfg.methods & MHC_GKMA) ? 1 : 0, c->d_rowscale, c->d_colscale, &geom[i], &n_m);
     g->n_parts[i] = geom[i].n_ntiles;
+    if (c->n3) {   // direction split as one contraction
+      geom[i].s3 = (int)(c->n3 / 32);
+      geom[i].region = c->j_region;
+      geom[i].ws = c->d_ws;
+    }
     order.push_back({c->K_pad, i});
   }
   std::stable_sort(order.begin(), order.end(), [](auto a, auto b) { return a.first > b.first; });
@@ -1726,7 +1732,12 @@ mhc_status group_block(mhc_group* g, bool timed) {
   return fan_out(g, [&](size_t i) {
     mhc_ctx* c = g->sys[i];
     const int64_t* w = reinterpret_cast<const int64_t*>(g->d_tab + TAB_W * i);
-    mhc_status s2 = block_back(c, g->t_block, g->n_parts[i], w + 2, -1, w + 3, w + 4);
+    mhc_status s2 = MHC_OK;
+    if (c->n_dir > 1) {   // the three directions' regions, one after the other
+      for (int d = 0; d < 3 && !s2; ++d) s2 = block_back(c, g->t_block, g->n_parts[i], w + 2, d, w + 3, w + 4);
+    } else {
+      s2 = block_back(c, g->t_block, g->n_parts[i], w + 2, -1, w + 3, w + 4);
+    }
     return s2 ? gfail(g, s2, c->err) : MHC_OK;
   });
 }
@@ -1809,7 +1820,9 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
     if (!c) return MHC_ERR_INVALID_ARG;
     if (c->sticky) return c->sticky;
     if (!c->finalized || c->cfg.t_block == 1) return MHC_ERR_STATE;
-    if (c->n_dir > 1) return MHC_ERR_UNSUPPORTED;   // grouped pushes run one pass per block
+    // grouped pushes run one contraction per block: the direction split only
+    // in its one-contraction form (T-batched FP32 and split-BF16)
+    if (c->n_dir > 1 && !c->n3) return MHC_ERR_UNSUPPORTED;
     if (c->device != c0->device || c->stream != c0->stream || c->cfg.precision != c0->cfg.precision ||
         c->cfg.t_block != c0->cfg.t_block)
       return MHC_ERR_INVALID_ARG;
@@ -1904,6 +1917,8 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
       d.col_scale = c->d_colscale;
       d.col_part = c->d_colpart;
       d.tab = reinterpret_cast<const float* const*>(g->d_tab + TAB_W * i);
+      d.dir = c->n3 ? DIR_ALL : -1;
+      d.jd_part = c->n3 ? c->d_jd : nullptr;
       d.wg0_cs = (int)wcs;
       d.wg0_prep = (int)wpr;
       wcs += (int64_t)c->t_pad * ((c->N + COLSCALE_ATOMS - 1) / COLSCALE_ATOMS);
@@ -1921,7 +1936,7 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
   }
   g->back_grouped = true;
   for (auto* c : g->sys)
-    if (c->cross) g->back_grouped = false;
+    if (c->cross || c->n_dir > 1) g->back_grouped = false;
   if (g->back_grouped) {
     const size_t bytes = (size_t)n * (sizeof(BackDesc) + sizeof(ReduceArgs) + 3 * sizeof(int));
     void* pb = nullptr;

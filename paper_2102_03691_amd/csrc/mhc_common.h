@@ -103,6 +103,12 @@ struct GemmGeom {
   int layout_g;
   const float* row_scale;     // e4m3 only: per-slot scale of E
   const float* col_scale;     // e4m3 only: [4][ntb*32] activation scales
+  // direction split as one contraction (grouped systems): s3 > 0 stages per
+  // third of K, out regions of `region` floats per direction, and two bracket
+  // slots per work-group in ws (0 / nullptr: an unsplit system)
+  int s3;
+  int64_t region;
+  float* ws;
 };
 struct GroupTile {
   int sys;

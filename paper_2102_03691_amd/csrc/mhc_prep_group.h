@@ -14,6 +14,8 @@ struct PrepDesc {
   const float* sqrt_m; const float* inv_sqrt_m; int64_t N; int t_pad; int n_chunks;
   void* B; int64_t K_pad; double* jt_part; float* col_scale; float* col_part;
   const float* const* tab;
+  int dir;            // -1, or DIR_ALL for a system with the one-contraction direction split
+  double* jd_part;    // its split Eq. 10 partials (dir = DIR_ALL)
   int wg0_cs, wg0_prep;
 };
 

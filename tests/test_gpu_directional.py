@@ -153,12 +153,15 @@ def test_split_unsupported_paths(dense):
     with pytest.raises(MhcError) as ei:
         h.read_block_currents(8)
     assert ei.value.status == 5
-    with pytest.raises(MhcError):
-        ModalGroup([h])
     with pytest.raises(MhcError) as ei:
         h.read_hnema_dir()                         # HNEMA not enabled
     assert ei.value.status == 2
     h.close()
+    h8 = dense.context(HNEMA | DIR, FP8X3, 64)     # e4m3 split: one contraction per direction,
+    with pytest.raises(MhcError) as ei:              # so not in grouped pushes
+        ModalGroup([h8])
+    assert ei.value.status == 5
+    h8.close()
     p = dense.context(HNEMA, BF16X3, 64)
     with pytest.raises(MhcError) as ei:
         p.read_hnema_dir()                         # split not enabled

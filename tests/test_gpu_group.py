@@ -111,3 +111,66 @@ def test_group_matches_single_pushes(cases, prec, graph, autotune, host):
     grp.close()
     for h in grouped + single:
         h.close()
+
+
+DIR = 4
+DIR_SYSTEMS = [HNEMA | DIR, GKMA | HNEMA | DIR, HNEMA, GKMA | HNEMA | DIR, HNEMA | DIR]
+
+
+def _read_dir(h, methods):
+    out = _read(h, methods)
+    if methods & DIR:
+        if methods & HNEMA:
+            out["hnema_dir"], out["hnema_total_dir"], _ = h.read_hnema_dir()
+        if methods & GKMA:
+            gd = h.read_gkma_dir()
+            out["corr_dir"], out["integral_dir"] = gd["corr"], gd["integral"]
+    return out
+
+
+@pytest.mark.parametrize("prec,graph", [(BF16X3, True), (FP32, False)])
+def test_group_with_direction_split(cases, prec, graph):
+    """Systems with the motion-direction split (one contraction per block,
+    direction-major operand) mixed with unsplit ones in one grouped push: every
+    output, split and summed, bit for bit equal to the same systems pushed one
+    by one, and the split HNEMA of the split systems against the plane-wave
+    oracle per polarisation.  An e4m3 split context is refused."""
+    import torch
+    from paper_2102_03691_amd import MhcError, ModalGroup
+    announce(f"group with direction split prec={prec} graph={graph}")
+    stream = torch.cuda.Stream()
+    handle = stream.cuda_stream
+    grouped = [_ctx(c, m, prec, handle) for c, m in zip(cases, DIR_SYSTEMS)]
+    single = [_ctx(c, m, prec, handle) for c, m in zip(cases, DIR_SYSTEMS)]
+    grp = ModalGroup(grouped, graph=graph, autotune=False)
+    dev = [(torch.as_tensor(c.v, device="cuda:0"), torch.as_tensor(c.W, device="cuda:0")) for c in cases]
+    torch.cuda.synchronize()
+    s0 = 0
+    for n in SPLITS:
+        grp.push([v[s0:s0 + n] for v, _ in dev], [W[s0:s0 + n] for _, W in dev])
+        for h, (v, W) in zip(single, dev):
+            h.push(v[s0:s0 + n], W[s0:s0 + n])
+        s0 += n
+        for i, (hg, hs) in enumerate(zip(grouped, single)):
+            a, b = _read_dir(hg, DIR_SYSTEMS[i]), _read_dir(hs, DIR_SYSTEMS[i])
+            assert a["n"] == b["n"] == s0
+            for k in a:
+                if k != "n":
+                    assert np.array_equal(a[k], b[k]), (i, k, s0)
+    import bench
+    errs = {}
+    for i, (case, methods) in enumerate(zip(cases, DIR_SYSTEMS)):
+        if methods & DIR:
+            ref = bench.lattice_reference(case.lat, case.m, case.v, case.W, 11, HNEMA | DIR, 0)
+            errs[f"hnema_dir_{i}"] = rel(grouped[i].read_hnema_dir()[0], ref["hnema_dir"])
+    log(f"group_dir_p{prec}_g{int(graph)}", **errs)
+    for k, e in errs.items():
+        assert e <= TOL[prec], (k, e)
+    grp.close()
+    for h in grouped + single:
+        h.close()
+    h8 = _ctx(cases[0], HNEMA | DIR, FP8X3, handle)
+    with pytest.raises(MhcError) as ei:
+        ModalGroup([h8])
+    assert ei.value.status == 5
+    h8.close()
