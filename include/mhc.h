@@ -93,15 +93,15 @@ typedef enum {
  * motion of a 2D material):
  *   J_n^{mu nu}(s) = Xdot_n(s) sum_i m_i^{-1/2} W_i^{mu nu}(s) e_{i,n}^nu,
  * so that sum_nu J_n^{mu nu} = J_n^mu, and J^{mu nu}(s) = sum_i W_i^{mu nu}(s)
- * v_i^nu(s) for the Eq. 10 total.  T-batched FP32 and split-BF16 contexts
- * run it as one contraction per block (K ordered by direction, so the three
- * brackets are the contraction over its three thirds while Xdot runs over
- * all of K: the MFMA work of the unsplit contraction); e4m3 precisions and
- * t_block = 1 run one contraction per direction.  It is read with
+ * v_i^nu(s) for the Eq. 10 total.  T-batched contexts run it as one
+ * contraction per block (K ordered by direction, so the three brackets are
+ * the contraction over its three thirds while Xdot runs over all of K: the
+ * MFMA work of the unsplit contraction; e4m3 activations keep one scale per
+ * whole column); t_block = 1 runs one contraction per direction.  It is read with
  * mhc_read_hnema_dir / mhc_read_gkma_dir
- * (mhc_read_hnema and mhc_read_gkma then return the sums over nu).  Grouped
- * pushes take it in its one-contraction form only; mhc_read_block_currents
- * does not keep it (both UNSUPPORTED otherwise). */
+ * (mhc_read_hnema and mhc_read_gkma then return the sums over nu), grouped
+ * pushes take it, and mhc_read_block_currents does not keep it
+ * (UNSUPPORTED). */
 enum { MHC_HNEMA = 1, MHC_GKMA = 2, MHC_DIRECTIONAL = 4, MHC_CROSS = 8 };
 /* MHC_CROSS (with MHC_GKMA, not with MHC_DIRECTIONAL) adds the bin-bin
  * cross-correlations of the modal currents, <J_b^mu(t+tau) J_b2^nu(t)>
@@ -370,9 +370,7 @@ enum {
 
 /* systems: n finalized contexts with the same device, stream, precision and
  * t_block > 1.  flags: MHC_GROUP_* bits.
- * Errors: INVALID_ARG, STATE (a context not finalized or per-step),
- * UNSUPPORTED (a context with MHC_DIRECTIONAL in an e4m3 precision, whose
- * split takes one contraction per direction), OOM, HIP. */
+ * Errors: INVALID_ARG, STATE (a context not finalized or per-step), OOM, HIP. */
 mhc_status mhc_group_create(mhc_ctx *const *systems, int32_t n, int32_t flags, mhc_group **out);
 mhc_status mhc_group_destroy(mhc_group *group);
 const char *mhc_group_last_error(const mhc_group *group);

@@ -204,13 +204,18 @@ constexpr int SU = 256;
 typedef __attribute__((address_space(1))) const u32x4 gu32x4;
 
 constexpr bool is_fp8(int prec) { return prec == PREC_FP8 || prec == PREC_FP8X3; }
+// dofs per k-stage: 32 (FP32, BF16), 64 (FP8X3), 128 (FP8)
+constexpr int stage_dofs(int prec) { return prec == PREC_FP8 ? 128 : (prec == PREC_FP8X3 ? 64 : 32); }
 
 // Epilogue of one finished tile (accumulators complete); TR = !layout_g.
 // TR: lane l holds slot (row block, l % 32) and, in register j, step
 // acc_row(j, l / 32) of the wave's t-block; otherwise the reverse.
+// c0: the first channel whose activation scales are still to be undone (e4m3;
+// 1 when channel 0 already carries them, as in the later directions of the
+// one-contraction split).
 template <int PREC, int WM, int WT, int MB, bool TR>
 __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __restrict__ out, const GemmGeom& g,
-                                              int64_t rb0, int ntile, float* red) {
+                                              int64_t rb0, int ntile, float* red, int c0 = 0) {
   constexpr int RBW = WM * MB;
   const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, wave = tid >> 6;
   const int wm = wave / WT, wt = wave % WT;
@@ -225,6 +230,7 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
         const int64_t t = t0 + acc_row(j, half);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
+          if (c < c0) continue;
           const float cs = g.col_scale[c * ld + t];
 #pragma unroll
           for (int rb = 0; rb < MB; ++rb) acc[rb][c][j] *= cs;
@@ -234,6 +240,7 @@ __device__ __forceinline__ void gemm_epilogue(f32x16 (&acc)[MB][4], float* __res
       const int64_t t = t0 + (lane & 31);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
+        if (c < c0) continue;
         const float cs = g.col_scale[c * ld + t];
 #pragma unroll
         for (int rb = 0; rb < MB; ++rb)
@@ -692,17 +699,18 @@ __device__ __forceinline__ void bracket_load(const float* __restrict__ w, f32x16
 template <int PREC, int WM, int WT, int MB, bool TR>
 __device__ __forceinline__ void dir_tile(const GemmGeom& g, int64_t rb0, int ntile, float* slot, f32x16 (&acc)[MB][4],
                                          u32x4 (*lds)[WM * MB][SU]) {
-  static_assert(!is_fp8(PREC), "the e4m3 activation scales are per whole column");
   constexpr int NBR = MB * 3 * 16;                               // bracket floats per lane
   float* red = reinterpret_cast<float*>(&lds[0][0][0]);
   for (int nu = 0; nu < 3; ++nu) {
     gemm_segment<PREC, WM, WT, MB, TR>(g, rb0, ntile, nu * g.s3, (nu + 1) * g.s3, acc, lds, nu == 0 ? 0 : 1);
     if (nu < 2) bracket_store<MB>(slot + (int64_t)nu * NBR * 256, acc);
   }
+  // e4m3: every third of a channel was quantised with the whole column's
+  // scale, so the scales are undone once on Xdot and once per bracket
   gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + 2 * g.region, g, rb0, ntile, red);
   for (int nu = 0; nu < 2; ++nu) {
     bracket_load<MB>(slot + (int64_t)nu * NBR * 256, acc);
-    gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + nu * g.region, g, rb0, ntile, red);
+    gemm_epilogue<PREC, WM, WT, MB, TR>(acc, g.out + nu * g.region, g, rb0, ntile, red, 1);
   }
   __syncthreads();
 }
@@ -748,15 +756,13 @@ k_gemm_group(const GemmGeom* __restrict__ sys, const GroupTile* __restrict__ til
     const int ntile = gt.tile % g.n_ntiles;
     const int64_t rb0 = (int64_t)mtile * RBW;
     // the orientation follows the system's method (uniform per work-group)
-    if constexpr (!is_fp8(PREC)) {
-      if (g.s3 > 0) {
-        float* slot = g.ws + (int64_t)blockIdx.x * 2 * (MB * 3 * 16) * 256 + threadIdx.x;
-        if (g.layout_g)
-          dir_tile<PREC, WM, WT, MB, false>(g, rb0, ntile, slot, acc, lds);
-        else
-          dir_tile<PREC, WM, WT, MB, true>(g, rb0, ntile, slot, acc, lds);
-        continue;
-      }
+    if (g.s3 > 0) {
+      float* slot = g.ws + (int64_t)blockIdx.x * 2 * (MB * 3 * 16) * 256 + threadIdx.x;
+      if (g.layout_g)
+        dir_tile<PREC, WM, WT, MB, false>(g, rb0, ntile, slot, acc, lds);
+      else
+        dir_tile<PREC, WM, WT, MB, true>(g, rb0, ntile, slot, acc, lds);
+      continue;
     }
     if (g.layout_g) {
       gemm_segment<PREC, WM, WT, MB, false>(g, rb0, ntile, 0, g.n_stages, acc, lds);
@@ -967,17 +973,21 @@ static hipError_t launch_dir_shape(hipStream_t s, GemmGeom g, int s3, int64_t re
 template <int PREC>
 static hipError_t launch_gemm_dir_prec(hipStream_t s, const void* E, const void* B, int64_t M_pad, int64_t n3, int ntb,
                                        float* out, int64_t region, int layout_g, int* n_parts, float* ws,
-                                       int64_t ws_floats, int n_cu) {
+                                       int64_t ws_floats, int n_cu, const float* row_scale, const float* col_scale) {
+  constexpr int SD = stage_dofs(PREC);
+  if (n3 % SD != 0) return hipErrorInvalidValue;
   GemmGeom g{};
   g.K_pad = 3 * n3;
   g.M_pad = M_pad;
   g.ntb = ntb;
-  g.n_stages = (int)(g.K_pad / 32);
+  g.n_stages = (int)(g.K_pad / SD);
   g.layout_g = layout_g;
   g.E = E;
   g.B = B;
   g.out = out;
-  const int s3 = (int)(n3 / 32);
+  g.row_scale = row_scale;
+  g.col_scale = col_scale;
+  const int s3 = (int)(n3 / SD);
 #define MHC_DSHAPE(WM, WT, MB)                                                                           \
   (layout_g ? launch_dir_shape<PREC, WM, WT, MB, false>(s, g, s3, region, ws, ws_floats, n_cu)            \
             : launch_dir_shape<PREC, WM, WT, MB, true>(s, g, s3, region, ws, ws_floats, n_cu))
@@ -998,18 +1008,23 @@ static hipError_t launch_gemm_dir_prec(hipStream_t s, const void* E, const void*
 
 hipError_t launch_gemm_dir(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t n3, int ntb,
                            float* out, int64_t region, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
-                           int n_cu) {
-  if (n3 <= 0 || n3 % 32 != 0) return hipErrorInvalidValue;
+                           int n_cu, const float* row_scale, const float* col_scale) {
+  if (n3 <= 0) return hipErrorInvalidValue;
+#define MHC_DIRP(P) \
+  launch_gemm_dir_prec<P>(s, E, B, M_pad, n3, ntb, out, region, layout_g, n_parts, ws, ws_floats, n_cu, row_scale, \
+                          col_scale)
   switch (prec) {
-    case PREC_BF16X3:
-      return launch_gemm_dir_prec<PREC_BF16X3>(s, E, B, M_pad, n3, ntb, out, region, layout_g, n_parts, ws, ws_floats,
-                                               n_cu);
-    case PREC_FP32:
-      return launch_gemm_dir_prec<PREC_FP32>(s, E, B, M_pad, n3, ntb, out, region, layout_g, n_parts, ws, ws_floats,
-                                             n_cu);
-    default:
-      return hipErrorInvalidValue;
+    case PREC_BF16X3: return MHC_DIRP(PREC_BF16X3);
+    case PREC_FP8: return MHC_DIRP(PREC_FP8);
+    case PREC_FP8X3: return MHC_DIRP(PREC_FP8X3);
+    case PREC_FP32: return MHC_DIRP(PREC_FP32);
+    default: return hipErrorInvalidValue;
   }
+#undef MHC_DIRP
+}
+
+int stage_dofs_of(int prec) {
+  return prec == PREC_FP8 ? stage_dofs(PREC_FP8) : (prec == PREC_FP8X3 ? stage_dofs(PREC_FP8X3) : stage_dofs(PREC_FP32));
 }
 
 // ----------------------------------------------------------- tile shapes

@@ -100,7 +100,7 @@ hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64
 template <bool X3>
 __global__ void __launch_bounds__(256) k_basis_store_fp8(const double* __restrict__ rows, int64_t K,
                                                          const int32_t* __restrict__ slot_of_row, void* __restrict__ E,
-                                                         int64_t K_pad, float* __restrict__ row_scale) {
+                                                         int64_t K_pad, float* __restrict__ row_scale, int64_t n3) {
   __shared__ double sh[256];
   const int64_t r = blockIdx.x;
   const int32_t slot = slot_of_row[r];
@@ -125,7 +125,17 @@ __global__ void __launch_bounds__(256) k_basis_store_fp8(const double* __restric
     const int64_t k0 = p * 16;
     float x[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = (k0 + e < K) ? (float)(row[k0 + e] * inv) : 0.f;
+    for (int e = 0; e < 16; ++e) {
+      const int64_t k = k0 + e;
+      double v = 0.0;
+      if (n3 > 0) {   // direction-major: dof 3 i + nu at k = nu n3 + i
+        const int64_t i = k % n3, nu = k / n3;
+        if (3 * i < K && nu < 3) v = row[3 * i + nu];
+      } else if (k < K) {
+        v = row[k];
+      }
+      x[e] = (float)(v * inv);
+    }
     uint32_t hi[4], lo[4];
     quant16_fp8(x, hi, lo, X3);
     const int64_t kc = k0 >> 6;
@@ -141,14 +151,15 @@ __global__ void __launch_bounds__(256) k_basis_store_fp8(const double* __restric
 }
 
 hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, int64_t n_rows, int64_t K,
-                                  const int32_t* slot_of_row, void* E, int64_t K_pad, float* row_scale) {
+                                  const int32_t* slot_of_row, void* E, int64_t K_pad, float* row_scale, int64_t n3) {
   if (n_rows <= 0) return hipSuccess;
+  if (n3 > 0 && (3 * n3 != K_pad || 3 * n3 < K)) return hipErrorInvalidValue;
   if (x3)
     hipLaunchKernelGGL(k_basis_store_fp8<true>, dim3((unsigned)n_rows), dim3(256), 0, s, rows, K, slot_of_row, E, K_pad,
-                       row_scale);
+                       row_scale, n3);
   else
     hipLaunchKernelGGL(k_basis_store_fp8<false>, dim3((unsigned)n_rows), dim3(256), 0, s, rows, K, slot_of_row, E,
-                       K_pad, row_scale);
+                       K_pad, row_scale, n3);
   return hipGetLastError();
 }
 
@@ -407,7 +418,7 @@ __device__ __forceinline__ void input_prep_body(const float* v, const float* W, 
       const int tt = idx & 31;
       const int g = (idx >> 5) % (PREP_K / 16);
       const int c = (idx >> 5) / (PREP_K / 16);
-      const int64_t k0 = k_base + 16 * g;
+      const int64_t k0 = k_of(16 * g);
       const int64_t cb = (int64_t)c * ntb + tb;
       const float inv = 1.f / csc[c][tt];
       float x[16];
@@ -531,8 +542,7 @@ hipError_t launch_input_prep(hipStream_t s, int prec, int plain, const float* v,
                              void* B, int64_t K_pad, double* jt_part, float* col_scale,
                              const float* col_part, const float* const* tab, int dir, double* jd_part) {
   const int n_chunks = (int)((N + ATOMS_PER_PREP - 1) / ATOMS_PER_PREP);
-  if (dir == DIR_ALL && (plain || (prec != PREC_FP32 && prec != PREC_BF16X3) || K_pad % 96 != 0 ||
-                         K_pad / 3 < (int64_t)n_chunks * ATOMS_PER_PREP))
+  if (dir == DIR_ALL && (plain || K_pad % 96 != 0 || K_pad / 3 < (int64_t)n_chunks * ATOMS_PER_PREP))
     return hipErrorInvalidValue;
   dim3 grid((unsigned)n_chunks, (unsigned)((t_pad + PREP_T - 1) / PREP_T));
 #define MHC_PREP(M)                                                                                          \

@@ -97,7 +97,7 @@ struct mhc_ctx {
   bool rows_started = false, finalized = false;
   int64_t K_pad = 0, M_used = 0, M_pad = 0;
   // > 0: the direction split as one contraction, K direction-major with
-  // thirds of n3 dofs (T-batched FP32 and split-BF16 contexts)
+  // thirds of n3 dofs (T-batched contexts)
   int64_t n3 = 0;
   std::vector<int32_t> slot_of_mode, bin_off;
   std::vector<uint8_t> row_loaded;
@@ -459,8 +459,7 @@ static mhc_status start_rows_impl(mhc_ctx* ctx) {
   // one-contraction direction split orders K direction-major, each third a
   // whole number of 32-dof stages
   const auto& cf = ctx->cfg;
-  const bool dir1 = (cf.methods & MHC_DIRECTIONAL) && cf.t_block > 1 &&
-                    (cf.precision == MHC_PREC_FP32 || cf.precision == MHC_PREC_BF16X3);
+  const bool dir1 = (cf.methods & MHC_DIRECTIONAL) && cf.t_block > 1;
   const int64_t n3 = dir1 ? round_up(ctx->N, K_ALIGN) : 0;
   const int64_t K_pad = dir1 ? 3 * n3
                              : round_up(3 * round_up(ctx->N, ATOMS_PER_PREP),
@@ -530,7 +529,7 @@ mhc_status mhc_load_eigvec_rows(mhc_ctx* ctx, int64_t mode0, int64_t n_rows, con
     }
     if (prec == MHC_PREC_FP8 || prec == MHC_PREC_FP8X3)
       HIP_TRY(launch_basis_store_fp8(ctx->stream, prec == MHC_PREC_FP8X3, src, nr, ctx->K, ctx->d_slot, ctx->dE,
-                                     ctx->K_pad, ctx->d_rowscale),
+                                     ctx->K_pad, ctx->d_rowscale, ctx->n3),
               "basis store");
     else
       HIP_TRY(launch_basis_store(ctx->stream, prec, src, nr, ctx->K, ctx->d_slot, ctx->dE, ctx->K_pad,
@@ -768,7 +767,7 @@ static mhc_status block_front(mhc_ctx* ctx, const float* v, const float* W, int 
   if (ctx->n3 && dir < 0) dir = DIR_ALL;   // one-contraction split: every direction in one operand
   if (ctx->d_colscale)
     HIP_TRY(launch_col_scale(ctx->stream, v, W, ctx->d_sqrtm, ctx->d_isqrtm, ctx->N, t_count, ctx->t_pad,
-                             ctx->d_colpart, tab, dir),
+                             ctx->d_colpart, tab, dir == DIR_ALL ? -1 : dir),   // whole columns serve every third
             "column scales");
   HIP_TRY(launch_input_prep(ctx->stream, c.precision, c.t_block == 1 ? 1 : 0, v, W, ctx->d_sqrtm, ctx->d_isqrtm,
                             ctx->N, t_count, ctx->t_pad, ctx->dB, ctx->K_pad, ctx->d_jt, ctx->d_colscale,
@@ -936,7 +935,8 @@ static mhc_status run_block(mhc_ctx* ctx, const float* v, const float* W, int t_
     if (timed && (st = timing_begin(ctx, &e0, &e1))) return st;
     int n_parts = 0;
     HIP_TRY(launch_gemm_dir(ctx->stream, c.precision, ctx->dE, ctx->dB, ctx->M_pad, ctx->n3, ctx->t_pad / 32, ctx->dJ,
-                            ctx->j_region, gk ? 1 : 0, &n_parts, wk.ws, wk.ws_floats, ctx->n_cu),
+                            ctx->j_region, gk ? 1 : 0, &n_parts, wk.ws, wk.ws_floats, ctx->n_cu, ctx->d_rowscale,
+                            ctx->d_colscale),
             "direction-split contraction");
     ctx->last_sched = MHC_SCHED_TILES;
     if (e1) HIP_TRY(hipEventRecord(e1, ctx->stream), "event record");
@@ -1655,7 +1655,7 @@ mhc_status build_queue(mhc_group* g) {
               (c->cfg.methods & MHC_GKMA) ? 1 : 0, c->d_rowscale, c->d_colscale, &geom[i], &n_m);
     g->n_parts[i] = geom[i].n_ntiles;
     if (c->n3) {   // direction split as one contraction
-      geom[i].s3 = (int)(c->n3 / 32);
+      geom[i].s3 = (int)(c->n3 / stage_dofs_of(g->prec));
       geom[i].region = c->j_region;
       geom[i].ws = c->d_ws;
     }
@@ -1820,8 +1820,8 @@ mhc_status mhc_group_create(mhc_ctx* const* systems, int32_t n, int32_t flags, m
     if (!c) return MHC_ERR_INVALID_ARG;
     if (c->sticky) return c->sticky;
     if (!c->finalized || c->cfg.t_block == 1) return MHC_ERR_STATE;
-    // grouped pushes run one contraction per block: the direction split only
-    // in its one-contraction form (T-batched FP32 and split-BF16)
+    // grouped pushes run one contraction per block: the direction split in
+    // its one-contraction form (every T-batched context has it)
     if (c->n_dir > 1 && !c->n3) return MHC_ERR_UNSUPPORTED;
     if (c->device != c0->device || c->stream != c0->stream || c->cfg.precision != c0->cfg.precision ||
         c->cfg.t_block != c0->cfg.t_block)

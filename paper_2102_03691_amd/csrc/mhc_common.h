@@ -41,15 +41,15 @@ enum Prec { PREC_FP32 = 0, PREC_BF16X3 = 1, PREC_FP8 = 2, PREC_FP8X3 = 3 };
 // Convert n_rows float64 E^T rows (device, row r = mode r0 + r) into the
 // storage layout.  slot_of_row[r] is the destination slot (-1 = skip).
 // gemv = 1 (FP32 only): the row-major layout of the per-step path.  n3 > 0
-// (T-batched FP32 / BF16, K_pad = 3 n3): dofs direction-major, dof 3 i + nu
+// (T-batched layouts, K_pad = 3 n3): dofs direction-major, dof 3 i + nu
 // at k = nu n3 + i (the one-contraction direction split).
 hipError_t launch_basis_store(hipStream_t s, int prec, const double* rows, int64_t n_rows,
                               int64_t K, const int32_t* slot_of_row, void* E, int64_t K_pad, int gemv, int64_t n3);
 
 // e4m3 basis store: per-mode scale s_n = max|E[.][n]| / 448 into row_scale[slot],
-// then E/s_n as e4m3 (x3: plus the e4m3 residual).
+// then E/s_n as e4m3 (x3: plus the e4m3 residual); n3 as for launch_basis_store.
 hipError_t launch_basis_store_fp8(hipStream_t s, bool x3, const double* rows, int64_t n_rows, int64_t K,
-                                  const int32_t* slot_of_row, void* E, int64_t K_pad, float* row_scale);
+                                  const int32_t* slot_of_row, void* E, int64_t K_pad, float* row_scale, int64_t n3);
 
 // Maxima behind the per-(channel, step) scales of the e4m3 activations, per
 // chunk of COLSCALE_ATOMS atoms: col_part[chunk][c][t_pad] (the input prep
@@ -69,7 +69,7 @@ hipError_t launch_col_scale(hipStream_t s, const float* v, const float* W, const
 // dir in {0,1,2} builds the virial channels of the motion-direction split
 // (W_i^{mu dir} / sqrt(m_i) on dof alpha = dir only) and writes the split
 // partial currents sum_i W_i^{mu dir} v_i^dir to jd_part[t][chunk][3];
-// dir = DIR_ALL (FP32 / BF16 fragments only) builds the whole operand with K
+// dir = DIR_ALL (T-batched layouts) builds the whole operand with K
 // direction-major (dof 3 i + nu at k = nu K_pad / 3 + i; K_pad / 3 covers
 // every atom chunk) and writes the split partials of all three directions to
 // jd_part[nu][t][chunk][3]; dir = -1 builds the whole operand atom-major and
@@ -142,14 +142,19 @@ hipError_t launch_gemm(hipStream_t s, int prec, const void* E, const void* B, in
                        int64_t ws_floats, int* tile_cnt, int n_cu, int sched, const float* row_scale,
                        const float* col_scale, int* used);
 
-// Motion-direction split as one contraction (FP32 or split-BF16): K ordered
-// direction-major (third nu = dofs (i, nu) at k = nu*n3 + i, n3 a multiple of
-// 32), out = three regions of `region` floats (direction nu at out + nu *
-// region), each laid out as launch_gemm's out.  ws holds two bracket slots
-// per work-group (ws_floats floats); n_cu = compute units.
+// Motion-direction split as one contraction: K ordered direction-major
+// (third nu = dofs (i, nu) at k = nu*n3 + i, n3 a multiple of the precision's
+// k-stage, stage_dofs_of), out = three regions of `region` floats (direction
+// nu at out + nu * region), each laid out as launch_gemm's out.  ws holds two
+// bracket slots per work-group (ws_floats floats); n_cu = compute units;
+// row_scale / col_scale as for launch_gemm (e4m3; whole-column activation
+// scales, the same for every third).
 hipError_t launch_gemm_dir(hipStream_t s, int prec, const void* E, const void* B, int64_t M_pad, int64_t n3, int ntb,
                            float* out, int64_t region, int layout_g, int* n_parts, float* ws, int64_t ws_floats,
-                           int n_cu);
+                           int n_cu, const float* row_scale, const float* col_scale);
+
+// dofs per k-stage of a precision's T-batched contraction.
+int stage_dofs_of(int prec);
 
 // Bin reduction + float64 accumulation.
 //   HNEMA-only: part sums in[n_parts][M_pad][3] -> hsum/hcomp[nb][3] (Neumaier)

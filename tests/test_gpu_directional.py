@@ -1,9 +1,9 @@
 """Motion-direction split (Sec. II, remark after Eq. 10; closing remark of
 Sec. II.C) on the GPU against the FP64 oracle, through the C ABI.  T-batched
-FP32 and split-BF16 contexts run it as one contraction per block over a
+contexts run it as one contraction per block over a
 direction-major operand (the three per-direction brackets are the
-contraction's thirds of K); e4m3 and the per-step path run one contraction
-per direction.
+contraction's thirds of K), in every precision; the per-step path runs one
+contraction per direction.
 
 The basis is a dense random orthonormal matrix (540 x 540 for 180 atoms), so
 every mode moves every atom in every direction and the split is not the
@@ -86,11 +86,10 @@ def test_hnema_split(dense, prec, T, sched):
     h.set_timing(True)
     dense.push(h, [1, 150, 149])
     launches, _ = h.kernel_timing()
-    # FP32 / split-BF16 T-batched: one contraction per block over the
-    # direction-major operand; otherwise one per direction
-    blocks = sum(-(-n // T) for n in (1, 150, 149)) if T > 1 else None
-    if blocks is not None:
-        assert launches == (blocks if prec in (FP32, BF16X3) else 3 * blocks), launches
+    # T-batched: one contraction per block over the direction-major operand
+    # (the per-step path runs one per direction)
+    if T > 1:
+        assert launches == sum(-(-n // T) for n in (1, 150, 149)), launches
     avg_d, tot_d, n = h.read_hnema_dir()
     avg, tot, n2 = h.read_hnema()
     h.close()
@@ -157,11 +156,6 @@ def test_split_unsupported_paths(dense):
         h.read_hnema_dir()                         # HNEMA not enabled
     assert ei.value.status == 2
     h.close()
-    h8 = dense.context(HNEMA | DIR, FP8X3, 64)     # e4m3 split: one contraction per direction,
-    with pytest.raises(MhcError) as ei:              # so not in grouped pushes
-        ModalGroup([h8])
-    assert ei.value.status == 5
-    h8.close()
     p = dense.context(HNEMA, BF16X3, 64)
     with pytest.raises(MhcError) as ei:
         p.read_hnema_dir()                         # split not enabled

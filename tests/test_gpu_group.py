@@ -128,15 +128,15 @@ def _read_dir(h, methods):
     return out
 
 
-@pytest.mark.parametrize("prec,graph", [(BF16X3, True), (FP32, False)])
+@pytest.mark.parametrize("prec,graph", [(BF16X3, True), (FP32, False), (FP8X3, True)])
 def test_group_with_direction_split(cases, prec, graph):
     """Systems with the motion-direction split (one contraction per block,
     direction-major operand) mixed with unsplit ones in one grouped push: every
     output, split and summed, bit for bit equal to the same systems pushed one
     by one, and the split HNEMA of the split systems against the plane-wave
-    oracle per polarisation.  An e4m3 split context is refused."""
+    oracle per polarisation."""
     import torch
-    from paper_2102_03691_amd import MhcError, ModalGroup
+    from paper_2102_03691_amd import ModalGroup
     announce(f"group with direction split prec={prec} graph={graph}")
     stream = torch.cuda.Stream()
     handle = stream.cuda_stream
@@ -164,13 +164,9 @@ def test_group_with_direction_split(cases, prec, graph):
             ref = bench.lattice_reference(case.lat, case.m, case.v, case.W, 11, HNEMA | DIR, 0)
             errs[f"hnema_dir_{i}"] = rel(grouped[i].read_hnema_dir()[0], ref["hnema_dir"])
     log(f"group_dir_p{prec}_g{int(graph)}", **errs)
+    tol = 1e-2 if prec == FP8X3 else TOL[prec]
     for k, e in errs.items():
-        assert e <= TOL[prec], (k, e)
+        assert e <= tol, (k, e)
     grp.close()
     for h in grouped + single:
         h.close()
-    h8 = _ctx(cases[0], HNEMA | DIR, FP8X3, handle)
-    with pytest.raises(MhcError) as ei:
-        ModalGroup([h8])
-    assert ei.value.status == 5
-    h8.close()

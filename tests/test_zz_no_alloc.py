@@ -36,6 +36,9 @@ def _ctx(case, nb, methods, prec, T, L, sched):
     return h
 
 
+DIR = 4
+
+
 def _reads(h, methods):
     out = {}
     if methods & HNEMA:
@@ -43,15 +46,22 @@ def _reads(h, methods):
     if methods & GKMA:
         g = h.read_gkma()
         out.update(corr=g["corr"], integral=g["integral"], hcacf=g["hcacf"], n=g["n_samples"])
+    if methods & DIR:
+        out["hnema_dir"], out["hnema_total_dir"], _ = h.read_hnema_dir()
+        gd = h.read_gkma_dir()
+        out["corr_dir"], out["integral_dir"] = gd["corr"], gd["integral"]
     return out
 
 
-@pytest.mark.parametrize("prec,T,sched", [(BF16X3, 64, 3), (BF16X3, 96, 2), (FP32, 128, 3), (BF16X3, 128, 1),
-                                          (FP32, 1, 0)])
-def test_noalloc_push_matches_push(prec, T, sched):
+@pytest.mark.parametrize("prec,T,sched,split", [(BF16X3, 64, 3, False), (BF16X3, 96, 2, False),
+                                                (FP32, 128, 3, False), (BF16X3, 128, 1, False),
+                                                (FP32, 1, 0, False), (BF16X3, 64, 0, True)])
+def test_noalloc_push_matches_push(prec, T, sched, split):
+    """split: the motion-direction split in its one-contraction form, whose
+    bracket slots also live in the scratch."""
     import torch
-    announce(f"noalloc push prec={prec} T={T} sched={sched}")
-    methods = HNEMA | GKMA
+    announce(f"noalloc push prec={prec} T={T} sched={sched} split={split}")
+    methods = HNEMA | GKMA | (DIR if split else 0)
     L, nb = 40, 23
     for dims, splits, seed in [((6, 6, 5), [230, 70], 1), ((4, 4, 3), [150, 37], 2)]:
         case = Case(dims, sum(splits), mass_kind="natural", seed=seed)
@@ -72,7 +82,7 @@ def test_noalloc_push_matches_push(prec, T, sched):
         b.close()
         assert ra["n"] == rb["n"] == s0
         assert bytes_a == bytes_b
-        for k in ("hnema", "hnema_total", "corr", "integral", "hcacf"):
+        for k in ra:
             np.testing.assert_array_equal(rb[k], ra[k], err_msg=k)
         e_h, e_c = rel(rb["hnema"], ref["hnema"]), rel(rb["corr"], ref["corr"])
         e_i = rel(rb["integral"], ref["integral"])
