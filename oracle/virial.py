@@ -329,3 +329,39 @@ def evaluate(pos, box, vel, mass, fe, p, nl=None) -> dict:
     E = atom_energies(U, mass, vel)
     return {"U": U, "F": forces(pos, box, p, nl), "W": W, "J": heat_current_eq10(W, vel),
             "Fext": hnemd_force_eq12(E, W, fe), "E": E, "nl": nl}
+
+
+def md_nve(pos, vel, mass, box, p, dt: float, n_steps: int) -> dict:
+    """NVE molecular dynamics with the forces above, by velocity Verlet (the
+    paper's production runs are NVE with a 1 fs time step, Sec. III.A; it names
+    no integrator).  One step, with a = F / (m KE_UNIT) in A/fs^2:
+        v <- v + dt/2 a(x);   x <- x + dt v (wrapped into the box);   v <- v + dt/2 a(x).
+    The neighbour lists are rebuilt from scratch at every step.  Returns, for
+    every step s = 1 .. n_steps, the positions, velocities and per-atom virials
+    (Eq. 8) after the step, and the total energy sum_i U_i + m_i |v_i|^2 / 2
+    before the first step (index 0) and after each step."""
+    box = np.asarray(box, dtype=np.float64)
+    x = np.mod(np.array(pos, dtype=np.float64), box)
+    v = np.array(vel, dtype=np.float64)
+    m = np.asarray(mass, dtype=np.float64)
+    inv_mk = 1.0 / (m * KE_UNIT)
+
+    def state(x):
+        nl = neighbor_lists(x, box, p["R"] + p["D"])
+        return forces(x, box, p, nl), nl
+
+    def energy(x, v, nl):
+        return float(site_energies(x, box, p, nl).sum() + 0.5 * (m * (v * v).sum(axis=1)).sum() * KE_UNIT)
+
+    F, nl = state(x)
+    out = {"pos": [], "vel": [], "W": [], "E": [energy(x, v, nl)]}
+    for _ in range(n_steps):
+        v = v + 0.5 * dt * F * inv_mk[:, None]
+        x = np.mod(x + dt * v, box)
+        F, nl = state(x)
+        v = v + 0.5 * dt * F * inv_mk[:, None]
+        out["pos"].append(x.copy())
+        out["vel"].append(v.copy())
+        out["W"].append(per_atom_virial(x, box, p, nl))
+        out["E"].append(energy(x, v, nl))
+    return {k: np.array(val) for k, val in out.items()}
