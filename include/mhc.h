@@ -547,6 +547,31 @@ mhc_status mhc_virial_compute(mhc_virial *v, const double *pos, const double *ve
                               double *F, double *W, float *W32, double *Fext);
 mhc_status mhc_virial_synchronize(mhc_virial *v);
 
+/* NVE molecular dynamics with these forces, fused with the per-step inputs of
+ * the modal push (the paper's NVE production runs use a 1 fs time step,
+ * Sec. III.A; it names no integrator, and velocity Verlet is used): n_steps
+ * steps of dt fs on pos [N][3] (A) and vel [N][3] (A/fs), device float64
+ * arrays updated in place (positions wrapped into the box).  One step, with
+ * a = F / (m KE) in A/fs^2 (KE = 103.6427 eV per amu A^2/fs^2):
+ *   v += dt/2 a(x);  x += dt v;  v += dt/2 a(x).
+ * The force at the entry positions is evaluated first.  The neighbour lists
+ * are rebuilt before the force of every step whose number (1-based) is a
+ * multiple of rebuild (0: never; the lists in use must then stay valid, i.e.
+ * no atom moves more than skin / 2 from where they were built); the first
+ * call needs lists (mhc_virial_neighbors).  After step s (0-based) the
+ * step's velocities and per-atom virials rounded to float32 go to
+ * v32 + 3 N s and W32 + 9 N s (device; either may be NULL): the v and W
+ * inputs of mhc_push / mhc_shc_push for that step, so n_steps MD steps fill
+ * a block of n_steps steps.  The last forces go to F (device [N][3], NULL:
+ * skip).  No thermostat and no driving force act (the HNEMD force of Eq. 12
+ * is an output of mhc_virial_compute).  Queued on the stream, except that
+ * every rebuild synchronizes.
+ * Errors: INVALID_ARG (NULL pos or vel, n_steps or rebuild < 0, dt not finite
+ * and positive, a rebuild finding too many neighbours), STATE (no valid
+ * lists), HIP. */
+mhc_status mhc_virial_md(mhc_virial *v, double *pos, double *vel, double dt, int32_t n_steps, int32_t rebuild,
+                         float *v32, float *W32, double *F);
+
 /* HIP-event timing of each evaluation, as mhc_set_timing / mhc_kernel_timing:
  * the summed milliseconds of the per-atom site kernel (bond orders, site
  * energies, partials) and of the gather kernel (forces, W, F_ext) apart. */

@@ -115,6 +115,7 @@ def library():
         "mhc_virial_synchronize": (i32, [vp]),
         "mhc_virial_set_timing": (i32, [vp, C.c_int]),
         "mhc_virial_kernel_timing": (i32, [vp, P(i64), P(dbl), P(dbl)]),
+        "mhc_virial_md": (i32, [vp, vp, vp, dbl, i32, i32, vp, vp, vp]),
         "mhc_group_create": (i32, [P(vp), i32, i32, P(vp)]),
         "mhc_group_destroy": (i32, [vp]),
         "mhc_group_last_error": (C.c_char_p, [vp]),
@@ -668,6 +669,27 @@ class ModalVirial:
         self._check(self._lib.mhc_virial_compute(self._h, p, vp, f, ptrs.get("U"), ptrs.get("F"), ptrs.get("W"),
                                                  ptrs.get("W32"), ptrs.get("Fext")), "virial compute")
         return out
+
+    def md(self, pos, vel, dt, n_steps, rebuild=0, v32=None, W32=None, F=None):
+        """n_steps velocity-Verlet steps of dt fs on the device tensors pos and vel
+        (float64 [N][3], updated in place); per step the float32 velocities and
+        virials go to v32 [n_steps][N][3] and W32 [n_steps][N][3][3] (device
+        tensors or None), the push's inputs for those steps; the lists are
+        rebuilt every `rebuild` steps (0: never)."""
+        N = self.n_atoms
+        p = self._dev(pos, 8, 3)
+        vp = self._dev(vel, 8, 3)
+        ptr = {}
+        for name, t, es, per in (("v32", v32, 4, 3 * n_steps), ("W32", W32, 4, 9 * n_steps), ("F", F, 8, 3)):
+            if t is not None:
+                if not (_is_torch(t) and t.is_cuda and t.is_contiguous() and t.element_size() == es
+                        and t.numel() == N * per):
+                    raise ValueError(f"{name} must be a contiguous device tensor of {N * per} "
+                                     f"{'float32' if es == 4 else 'float64'} values")
+                ptr[name] = _ptr(t)
+        self._use(pos, vel, *[t for t in (v32, W32, F) if t is not None])
+        self._check(self._lib.mhc_virial_md(self._h, p, vp, float(dt), int(n_steps), int(rebuild), ptr.get("v32"),
+                                            ptr.get("W32"), ptr.get("F")), "virial md")
 
     def synchronize(self):
         self._check(self._lib.mhc_virial_synchronize(self._h), "virial synchronize")

@@ -419,6 +419,49 @@ static hipError_t launch_pair_kernels(hipStream_t s, const TersoffArgs& a, const
   return hipSuccess;
 }
 
+// ------------------------------------------------ velocity Verlet (NVE)
+// One thread per atom component.  Half kick: v += c F / m with c = dt / (2 KE)
+// (a = F / (m KE) in A/fs^2); with v32 the kicked velocity is also stored in
+// float32 (the push's velocity input of the step).
+__global__ void __launch_bounds__(256) k_md_kick(double* __restrict__ vel, const double* __restrict__ F,
+                                                 const double* __restrict__ mass, double c, int64_t n3,
+                                                 float* __restrict__ v32) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n3) return;
+  const double v = vel[q] + c * F[q] / mass[q / 3];
+  vel[q] = v;
+  if (v32) v32[q] = (float)v;
+}
+
+// Drift: x += dt v, wrapped into [0, L) per axis (x - floor(x / L) L, then
+// one correction step against rounding at the edges).
+__global__ void __launch_bounds__(256) k_md_drift(double* __restrict__ pos, const double* __restrict__ vel, double dt,
+                                                  double Lx, double Ly, double Lz, int64_t n3) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n3) return;
+  const int a = (int)(q % 3);
+  const double L = a == 0 ? Lx : (a == 1 ? Ly : Lz);
+  double x = pos[q] + dt * vel[q];
+  x -= floor(x / L) * L;
+  if (x >= L) x -= L;
+  if (x < 0.0) x += L;
+  pos[q] = x;
+}
+
+hipError_t launch_md_kick(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
+                          float* v32) {
+  const int64_t n3 = 3 * N;
+  hipLaunchKernelGGL(k_md_kick, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, vel, F, mass, c, n3, v32);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_drift(hipStream_t s, double* pos, const double* vel, double dt, const double box[3], int64_t N) {
+  const int64_t n3 = 3 * N;
+  hipLaunchKernelGGL(k_md_drift, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, pos, vel, dt, box[0], box[1],
+                     box[2], n3);
+  return hipGetLastError();
+}
+
 int tersoff_lanes(int max_count) {
   int l = 4;
   while (l < max_count) l *= 2;

@@ -77,4 +77,11 @@ int tersoff_lanes(int max_count);
 hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o, int lpa,
                           hipEvent_t e0, hipEvent_t e1, hipEvent_t e2);
 
+// Velocity Verlet pieces on [N][3] float64 arrays: a half kick
+// vel += c F / mass (v32: the result also in float32, NULL to skip) and a
+// drift pos += dt vel wrapped into the box.
+hipError_t launch_md_kick(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
+                          float* v32);
+hipError_t launch_md_drift(hipStream_t s, double* pos, const double* vel, double dt, const double box[3], int64_t N);
+
 }  // namespace mhc

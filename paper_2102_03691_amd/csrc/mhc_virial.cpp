@@ -43,6 +43,7 @@ struct mhc_virial {
   double* d_mass = nullptr;
   NeighborBufs nb{};
   double *d_dd = nullptr, *d_U = nullptr;
+  double* d_F = nullptr;  // forces of the molecular dynamics (mhc_virial_md)
   int lpa = 4;            // lanes per atom of the evaluation kernels (from the largest neighbour count)
 
   bool timing = false;
@@ -193,7 +194,7 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
             valloc(v, N, &b.cell_of) && valloc(v, N, &b.atoms) && valloc(v, n_cells, &b.count) &&
             valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) &&
             valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 2, &b.flags) &&
-            valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U);
+            valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U) && valloc(v, 3 * N, &v->d_F);
   if (!ok) return cleanup(MHC_ERR_OOM, "device allocation failed");
   if (hipMemcpyAsync(v->d_mass, mass_amu, N * sizeof(double), hipMemcpyHostToDevice, v->stream) != hipSuccess ||
       hipStreamSynchronize(v->stream) != hipSuccess)
@@ -310,6 +311,50 @@ mhc_status mhc_virial_compute(mhc_virial* v, const double* pos, const double* ve
     v->ev_used += 3;
   }
   VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, e0, e1, e2), "virial kernels");
+  return MHC_OK;
+}
+
+mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_steps, int32_t rebuild,
+                         float* v32, float* W32, double* F) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  if (!pos || !vel) return vfail(v, MHC_ERR_INVALID_ARG, "NULL positions or velocities");
+  if (n_steps < 0 || rebuild < 0) return vfail(v, MHC_ERR_INVALID_ARG, "n_steps and rebuild must be >= 0");
+  if (!std::isfinite(dt) || !(dt > 0.0)) return vfail(v, MHC_ERR_INVALID_ARG, "dt must be finite and > 0");
+  if (!v->lists_ok) return vfail(v, MHC_ERR_STATE, "no valid neighbour lists (call mhc_virial_neighbors)");
+  if (n_steps == 0) return MHC_OK;
+  VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
+  const int64_t N = v->N;
+  auto force = [&](float* w32) -> mhc_status {
+    TersoffArgs a{};
+    a.pos = pos;
+    a.N = N;
+    for (int q = 0; q < 3; ++q) a.box[q] = v->box[q];
+    a.nbr = v->nb.nbr;
+    a.n_nb = v->nb.n_nb;
+    a.rev = v->nb.rev;
+    a.max_nb = v->max_nb;
+    a.dd = v->d_dd;
+    a.U = v->d_U;
+    GatherArgs o{};
+    o.mass = v->d_mass;
+    o.ke_unit = KE_UNIT_EV;
+    o.F = v->d_F;
+    o.W32 = w32;
+    VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, nullptr, nullptr, nullptr), "force kernels");
+    return MHC_OK;
+  };
+  const double c = 0.5 * dt / KE_UNIT_EV;   // half kick: dv = dt/2 F / (m KE)
+  if ((st = force(nullptr))) return st;     // forces at the entry positions
+  for (int32_t s = 0; s < n_steps; ++s) {
+    VHIP_TRY(launch_md_kick(v->stream, vel, v->d_F, v->d_mass, c, N, nullptr), "half kick");
+    VHIP_TRY(launch_md_drift(v->stream, pos, vel, dt, v->box, N), "drift");
+    if (rebuild > 0 && (s + 1) % rebuild == 0 && (st = mhc_virial_neighbors(v, pos, nullptr))) return st;
+    if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr))) return st;
+    VHIP_TRY(launch_md_kick(v->stream, vel, v->d_F, v->d_mass, c, N, v32 ? v32 + (int64_t)s * N * 3 : nullptr),
+             "half kick");
+  }
+  if (F) VHIP_TRY(hipMemcpyAsync(F, v->d_F, (size_t)N * 3 * 8, hipMemcpyDeviceToDevice, v->stream), "copy forces");
   return MHC_OK;
 }
 

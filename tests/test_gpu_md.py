@@ -1,0 +1,152 @@
+"""NVE molecular dynamics on the device (mhc_virial_md: velocity Verlet with
+the Tersoff forces, the paper's 1 fs time step, Sec. III.A) against the
+oracle's integrator (oracle.virial.md_nve), through the C ABI:
+  * positions and velocities after 20 steps (float64 on both sides; they
+    differ only by the summation order of the forces) and every step's
+    float32 velocities and per-atom virials (the push inputs) within one
+    float32 rounding of the oracle's, with the lists rebuilt every step, every
+    5 steps, or never (a skin covers the moves);
+  * total energy conserved over 400 steps of 512 atoms;
+  * the device trajectory's float32 v and W pushed as one block into HNEMA +
+    GKMA against the oracle's modal path on the oracle's trajectory;
+  * argument and state errors."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import virial as ov
+from tests._cases import TOL, announce, log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_03691_amd import library
+    library()
+
+
+def _start(cells, sigma, seed):
+    pos, box = synth.diamond(cells, sigma=sigma, seed=seed)
+    m = synth.masses(len(pos), "natural", seed)
+    return pos, box, m, synth.thermal_velocities(m, 300.0, seed + 1)
+
+
+def _device_md(pos, box, m, vel, dt, n, rebuild, skin, max_nb=24):
+    import torch
+    from paper_2102_03691_amd import ModalVirial
+    N = len(pos)
+    v = ModalVirial(m, box, ov.tersoff_si(), max_neighbors=max_nb, skin=skin)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    v.neighbors(pt)
+    v32 = torch.empty((n, N, 3), dtype=torch.float32, device="cuda:0")
+    W32 = torch.empty((n, N, 3, 3), dtype=torch.float32, device="cuda:0")
+    v.md(pt, vt, dt, n, rebuild=rebuild, v32=v32, W32=W32)
+    torch.cuda.synchronize()
+    out = {"pos": pt.cpu().numpy(), "vel": vt.cpu().numpy(), "v32": v32.cpu().numpy(), "W32": W32.cpu().numpy()}
+    return v, out
+
+
+def _ulps(got32, ref64):
+    ref32 = ref64.astype(np.float32)
+    ulp = np.spacing(np.abs(ref32)).astype(np.float64)
+    return float((np.abs(got32.astype(np.float64) - ref32.astype(np.float64)) / ulp).max())
+
+
+@pytest.mark.parametrize("rebuild,skin", [(1, 0.0), (5, 1.0), (0, 1.0)])
+def test_md_matches_oracle(rebuild, skin):
+    announce(f"md vs oracle rebuild={rebuild} skin={skin}")
+    pos, box, m, vel = _start((2, 2, 2), 0.05, 7)
+    n, dt = 20, 1.0
+    ref = ov.md_nve(pos, vel, m, box, ov.tersoff_si(), dt, n)
+    v, got = _device_md(pos, box, m, vel, dt, n, rebuild, skin)
+    v.close()
+    dx = float(np.abs(ov.min_image(got["pos"] - ref["pos"][-1], box)).max())
+    dv = float(np.abs(got["vel"] - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max())
+    e = {"dx_A": dx, "dv_rel": dv, "v32_ulps": _ulps(got["v32"], ref["vel"]), "W32_ulps": _ulps(got["W32"], ref["W"])}
+    log(f"md64_rebuild{rebuild}_skin{skin}", **e)
+    assert dx <= 1e-11 and dv <= 1e-11
+    assert e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0
+
+
+@pytest.mark.timeout(300)
+def test_md_conserves_energy():
+    import torch
+    announce("md energy conservation 512 atoms 400 steps")
+    pos, box, m, vel = _start((4, 4, 4), 0.05, 11)
+    N = len(pos)
+    v, got = _device_md(pos, box, m, vel, 1.0, 1, 1, 1.0)
+
+    def energy(p_np, v_np):
+        pt = torch.as_tensor(p_np, device="cuda:0")
+        v.neighbors(pt)
+        U = v.compute(pt, want=("U",))["U"].cpu().numpy()
+        return float(U.sum() + 0.5 * (m * (v_np * v_np).sum(axis=1)).sum() * ov.KE_UNIT)
+
+    E0 = energy(np.mod(pos, box), vel)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    v.neighbors(pt)
+    drift = []
+    for _ in range(8):
+        v.md(pt, vt, 1.0, 50, rebuild=10)
+        torch.cuda.synchronize()
+        drift.append(abs(energy(pt.cpu().numpy(), vt.cpu().numpy()) - E0) / N)
+    v.close()
+    log("md512_energy", max_drift_eV_per_atom=max(drift))
+    assert max(drift) < 2e-4
+
+
+def test_md_trajectory_feeds_the_push():
+    import torch
+    from paper_2102_03691_amd import GKMA, HNEMA, ModalHC
+    announce("md trajectory -> modal push")
+    pos, box, m, vel = _start((2, 2, 2), 0.05, 13)
+    N, S, nb, L = len(pos), 64, 6, 10
+    ref = ov.md_nve(pos, vel, m, box, ov.tersoff_si(), 1.0, S)
+    v, got = _device_md(pos, box, m, vel, 1.0, S, 4, 1.0)
+    vblk = torch.as_tensor(got["v32"], device="cuda:0")
+    wblk = torch.as_tensor(got["W32"], device="cuda:0")
+    v.close()
+    E = synth.random_orthonormal(3 * N, 23)
+    freq = np.linspace(0.0, 15.0, 3 * N)
+    h = ModalHC(0)
+    h.load_system(m, freq)
+    h.set_bins_uniform(nb, 0.0, 15.0)
+    h.configure(methods=HNEMA | GKMA, precision=1, t_block=S, corr_len=L, dt=1.0)
+    h.load_eigvec_rows(0, np.ascontiguousarray(E.T))
+    h.finalize()
+    h.push(vblk, wblk)
+    avg, tot, n = h.read_hnema()
+    g = h.read_gkma()
+    h.close()
+    bins = oracle.bin_of_mode(freq, nb, 0.0, 15.0)
+    r = oracle.run_dense(E, m, ref["vel"].astype(np.float32), ref["W"].astype(np.float32), bins, nb, corr_len=L)
+    e = {"hnema": rel(avg, r["hnema"]), "corr": rel(g["corr"], r["corr"]), "total": rel(tot, r["hnema_total"])}
+    log("md_to_push_bf16_T64", **e)
+    assert n == S and e["hnema"] <= TOL[1] and e["corr"] <= TOL[1] and e["total"] <= 1e-6
+
+
+def test_md_errors():
+    import torch
+    from paper_2102_03691_amd import MhcError, ModalVirial
+    announce("md errors")
+    pos, box, m, vel = _start((2, 2, 2), 0.05, 17)
+    v = ModalVirial(m, box, ov.tersoff_si(), max_neighbors=24, skin=0.5)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    with pytest.raises(MhcError) as ei:
+        v.md(pt, vt, 1.0, 3)                  # no lists yet
+    assert ei.value.status == 2
+    v.neighbors(pt)
+    for dt, n, rb in ((0.0, 3, 0), (float("nan"), 3, 0), (1.0, -1, 0), (1.0, 3, -2)):
+        with pytest.raises(MhcError) as ei:
+            v.md(pt, vt, dt, n, rebuild=rb)
+        assert ei.value.status == 1
+    v.md(pt, vt, 1.0, 0)                      # nothing to do
+    v.close()
