@@ -72,6 +72,10 @@ PEAK_FP64_FLOPS = 78.6e12
 # atom (neighbour lists built before the timed region, as an MD code rebuilds
 # them every few steps).  8000 atoms is the paper's speed-test size.
 VIRIAL_WORKLOADS = {"si8000_virial": ((10, 10, 10), 200), "si512k_virial": ((40, 40, 40), 100)}
+# NVE velocity-Verlet steps on the device with the same forces, each step writing its
+# float32 v and W (the push inputs); lists with a 1 A skin rebuilt every 50 steps
+MD_WORKLOADS = {"si8000_md": ((10, 10, 10), 400), "si512k_md": ((40, 40, 40), 200)}
+MD_METRIC = "NVE molecular dynamics (velocity Verlet, Tersoff Si, float64) atom*steps/s incl. push inputs"
 VIRIAL_METRIC = "per-atom virial (Eq. 8) + forces + HNEMD force (Eq. 12) atom*steps/s, float64 Tersoff Si"
 
 
@@ -456,6 +460,104 @@ def run_virial(args):
     return res
 
 
+def run_md(args):
+    """NVE molecular dynamics on the device: K velocity-Verlet steps of 1 fs
+    (the paper's time step), every step's float32 v and W written as push
+    inputs; inputs resident in HBM."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2102_03691_amd import ModalVirial
+    cells, default_steps = MD_WORKLOADS[args.workload]
+    K = args.steps or default_steps
+    pos, box = synth.diamond(cells, sigma=0.06, seed=1)
+    N = len(pos)
+    m = synth.masses(N, "natural", 1)
+    vel = synth.thermal_velocities(m, 300.0, 1)
+    params = dict(A=1830.8, B=471.18, lambda1=2.4799, lambda2=1.7322, lambda3=0.0, m=3, beta=1.1e-6, n=0.78734,
+                  c=1.0039e5, d=16.217, h=-0.59825, gamma=1.0, R=2.85, D=0.15)     # Tersoff Si
+    REBUILD = 50
+    vir = ModalVirial(m, box, params, max_neighbors=24, skin=1.0)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    v32 = torch.empty((K, N, 3), dtype=torch.float32, device="cuda:0")
+    W32 = torch.empty((K, N, 3, 3), dtype=torch.float32, device="cuda:0")
+    vir.neighbors(pt)
+
+    def energy():
+        vir.neighbors(pt)
+        U = vir.compute(pt, want=("U",))["U"]
+        return float(U.sum()) + 0.5 * float((torch.as_tensor(m, device="cuda:0") * (vt * vt).sum(dim=1)).sum()) * 103.64269652680505
+
+    E0 = energy()
+    if args.warmup:
+        vir.md(pt, vt, 1.0, args.warmup, rebuild=REBUILD)
+    vir.synchronize()
+    vir.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vir.md(pt, vt, 1.0, K, rebuild=REBUILD, v32=v32, W32=W32)
+    vir.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, site_ms, gather_ms = vir.kernel_timing()
+    vir.set_timing(False)
+    E1 = energy()
+    counts, _ = vir.read_neighbors()
+    n_i = counts.astype(np.float64)
+    site_avg = site_ms / max(launches, 1)
+    # the site kernel's algorithmic operations (as for the per-atom virial workloads),
+    # counted for the pairs within R + D only (the skin's extra pairs are skipped work)
+    n_b = np.full(N, 4.0)
+    flops = float((65.0 * n_b + 79.0 * n_b * (n_b - 1.0) + n_b).sum())
+    roof = {"bound": "alu", "achieved": flops / (site_avg * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
+            "unit": "TFLOP/s", "work": "65 float64 ops per bond + 79 per ordered pair of bonds (4 bonds per Si atom)",
+            "flop_per_launch": flops, "traffic": profiled_traffic(args.workload, "k_tersoff_site"),
+            "kernel": "k_tersoff_site", "avg_launch_ms": site_avg, "launches": launches,
+            "gather_kernel_avg_ms": gather_ms / max(launches, 1), "listed_neighbors_mean": float(n_i.mean())}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    res = {"metric": MD_METRIC, "value": N * K / wall, "unit": "atom*steps/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "atoms": N, "cells": list(cells), "potential": "Tersoff Si",
+                      "dt_fs": 1.0, "skin_A": 1.0, "rebuild_every": REBUILD,
+                      "outputs": "positions, velocities (f64); per step v and W in f32 (push inputs)",
+                      "parallelism": "single GPU"},
+           "roofline": roof,
+           "energy_drift_eV_per_atom": abs(E1 - E0) / N}
+    if not args.no_cpu_baseline:
+        import oracle.virial as ov
+        log("accuracy: the first steps against the FP64 oracle integrator on a 64-atom cut of the workload")
+        spos, sbox = synth.diamond((2, 2, 2), sigma=0.06, seed=1)
+        sm = synth.masses(len(spos), "natural", 1)
+        svel = synth.thermal_velocities(sm, 300.0, 1)
+        ref = ov.md_nve(spos, svel, sm, sbox, ov.tersoff_si(), 1.0, 10)
+        sv = ModalVirial(sm, sbox, params, max_neighbors=24, skin=1.0)
+        sp = torch.as_tensor(np.mod(spos, sbox), device="cuda:0")
+        svt = torch.as_tensor(svel, device="cuda:0").clone()
+        sv.neighbors(sp)
+        sv.md(sp, svt, 1.0, 10)
+        torch.cuda.synchronize()
+        res["rel_err_vs_oracle"] = {
+            "pos_A": float(np.abs(ov.min_image(sp.cpu().numpy() - ref["pos"][-1], sbox)).max()),
+            "vel": float(np.abs(svt.cpu().numpy() - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max()),
+            "oracle": "oracle.virial.md_nve (FP64 velocity Verlet)", "sample": "64 atoms (2x2x2 cells), 10 steps",
+            "norm": "max |diff| (A) / max |diff| / max |ref|"}
+        sv.close()
+        log("cpu baseline (oracle)")
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < 12.0:
+            ov.md_nve(spos, svel, sm, sbox, ov.tersoff_si(), 1.0, 20)
+            done += 20
+        spent = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(spos) * done / spent, "unit": "atom*steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{done} steps of the 64-atom cut (pure Python float64 forces, lists rebuilt "
+                                         f"every step), {spent:.1f} s"}
+    vir.close()
+    return res
+
+
 def run_group(args, prec):
     """The uneven batch as one grouped push per block (graph replay, autotuned tiles)."""
     import torch
@@ -567,7 +669,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS) + sorted(SHC_WORKLOADS)
-                    + sorted(VIRIAL_WORKLOADS))
+                    + sorted(VIRIAL_WORKLOADS) + sorted(MD_WORKLOADS))
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -601,6 +703,9 @@ def main():
         return
     if args.workload in VIRIAL_WORKLOADS:
         print(json.dumps(run_virial(args)), flush=True)
+        return
+    if args.workload in MD_WORKLOADS:
+        print(json.dumps(run_md(args)), flush=True)
         return
     dims, t_block, prec, methods, nb, L, default_steps = WORKLOADS[args.workload]
     K = args.steps or default_steps

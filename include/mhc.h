@@ -572,8 +572,9 @@ mhc_status mhc_virial_synchronize(mhc_virial *v);
 mhc_status mhc_virial_md(mhc_virial *v, double *pos, double *vel, double dt, int32_t n_steps, int32_t rebuild,
                          float *v32, float *W32, double *F);
 
-/* HIP-event timing of each evaluation, as mhc_set_timing / mhc_kernel_timing:
- * the summed milliseconds of the per-atom site kernel (bond orders, site
+/* HIP-event timing of each evaluation (mhc_virial_compute, and every force
+ * evaluation of mhc_virial_md), as mhc_set_timing / mhc_kernel_timing: the
+ * summed milliseconds of the per-atom site kernel (bond orders, site
  * energies, partials) and of the gather kernel (forces, W, F_ext) apart. */
 mhc_status mhc_virial_set_timing(mhc_virial *v, int enable);
 mhc_status mhc_virial_kernel_timing(mhc_virial *v, int64_t *launches, double *site_ms, double *gather_ms);

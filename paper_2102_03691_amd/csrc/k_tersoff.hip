@@ -250,8 +250,10 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
     r = sqrt(x * x + y * y + z * z);
     ir = 1.0 / r;
     cutoff_fn(p, r, &fc, &dfc);
-    er = p.A * exp(-p.l1 * r);         // f_R
-    ea = p.B * exp(-p.l2 * r);         // f_A (the attractive term enters as -b f_A)
+    if (fc != 0.0) {                   // a pair beyond R + D (listed with a skin) needs neither
+      er = p.A * exp(-p.l1 * r);       // f_R
+      ea = p.B * exp(-p.l2 * r);       // f_A (the attractive term enters as -b f_A)
+    }
   }
   sh[0][tid] = x;
   sh[1][tid] = y;
@@ -260,11 +262,16 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
   sh[4][tid] = ir;
   sh[5][tid] = fc;
   __syncthreads();
+  // Listed pairs beyond R + D (f_C = 0: lists built with a skin) add exact
+  // zeros to every sum below, so they are skipped, and such a pair's own
+  // lane has nothing to compute (its energy, bracket weight and partials are
+  // zero).
+  const bool bond = act && fc != 0.0;
   double b = 1.0, adb = 0.0, u = 0.0;
-  if (act) {
+  if (bond) {
     double zeta = 0.0;
     for (int q = 0; q < n; ++q) {
-      if (q == s) continue;
+      if (q == s || sh[5][g0 + q] == 0.0) continue;
       const int l = g0 + q;
       const double cs = (x * sh[0][l] + y * sh[1][l] + z * sh[2][l]) * ir * sh[4][l];
       double g, dg, e, de;
@@ -289,13 +296,20 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
     a.U[i] = 0.5 * acc;
   }
   if (!act) return;
+  const int64_t mn = (int64_t)a.max_nb * N, es = (int64_t)s * N + i;
+  if (!bond) {
+    a.dd[es] = 0.0;
+    a.dd[mn + es] = 0.0;
+    a.dd[2 * mn + es] = 0.0;
+    return;
+  }
   // dU_i/dr_ij for this lane's pair j
   const double ux = x * ir, uy = y * ir, uz = z * ir;
   const double radial = 0.5 * (dfc * (er - b * ea) + fc * (-p.l1 * er + p.l2 * b * ea));
   double zx = 0.0, zy = 0.0, zz = 0.0;   // d zeta_ij / d r_ij
   double kx = 0.0, ky = 0.0, kz = 0.0;   // sum_{k != j} a_ik db_ik d zeta_ik / d r_ij
   for (int q = 0; q < n; ++q) {
-    if (q == s) continue;
+    if (q == s || sh[5][g0 + q] == 0.0) continue;
     const int l = g0 + q;
     const double qx = sh[0][l], qy = sh[1][l], qz = sh[2][l], rq = sh[3][l], irq = sh[4][l];
     const double cs = (x * qx + y * qy + z * qz) * ir * irq;
@@ -316,7 +330,6 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
     ky += w * (dfc * g * e2 * uy + fc * dg * cy * e2 - fc * g * de2 * uy);
     kz += w * (dfc * g * e2 * uz + fc * dg * cz * e2 - fc * g * de2 * uz);
   }
-  const int64_t mn = (int64_t)a.max_nb * N, es = (int64_t)s * N + i;
   a.dd[es] = radial * ux - 0.5 * (adb * zx + kx);
   a.dd[mn + es] = radial * uy - 0.5 * (adb * zy + ky);
   a.dd[2 * mn + es] = radial * uz - 0.5 * (adb * zz + kz);
@@ -344,13 +357,17 @@ __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArg
     const double r[3] = {min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0]),
                          min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1]),
                          min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2])};
-    const double dij[3] = {a.dd[es], a.dd[mn + es], a.dd[2 * mn + es]};
-    const double dji[3] = {a.dd[ej], a.dd[mn + ej], a.dd[2 * mn + ej]};
+    // a pair beyond R + D has zero partials both ways (written so by the site
+    // kernel): nothing to load or add
+    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] < o.rcut2) {
+      const double dij[3] = {a.dd[es], a.dd[mn + es], a.dd[2 * mn + es]};
+      const double dji[3] = {a.dd[ej], a.dd[mn + ej], a.dd[2 * mn + ej]};
 #pragma unroll
-    for (int mu = 0; mu < 3; ++mu) {
-      c[mu] = dij[mu] - dji[mu];
+      for (int mu = 0; mu < 3; ++mu) {
+        c[mu] = dij[mu] - dji[mu];
 #pragma unroll
-      for (int nu = 0; nu < 3; ++nu) c[3 + 3 * mu + nu] = r[mu] * dji[nu];
+        for (int nu = 0; nu < 3; ++nu) c[3 + 3 * mu + nu] = r[mu] * dji[nu];
+      }
     }
   }
 #pragma unroll

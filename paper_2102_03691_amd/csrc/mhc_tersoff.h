@@ -60,6 +60,7 @@ struct GatherArgs {
   const double* mass;
   double fe[3];
   double ke_unit;
+  double rcut2;               // (R + D)^2 slightly widened: pairs beyond have zero partials
   double* F;
   double* W;
   float* W32;

@@ -67,6 +67,29 @@ mhc_status vfail(mhc_virial* v, mhc_status st, const std::string& msg) {
     if (e_ != hipSuccess) return vfail(v, MHC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Three events around the site and gather kernels of one evaluation when
+// timing is on (none otherwise).
+mhc_status timing_events(mhc_virial* v, hipEvent_t e[3]) {
+  if (!v->timing) return MHC_OK;
+  if (v->ev_used + 3 > v->ev.size())
+    for (int q = 0; q < 3; ++q) {
+      hipEvent_t ev;
+      VHIP_TRY(hipEventCreate(&ev), "event create");
+      v->ev.push_back(ev);
+    }
+  for (int q = 0; q < 3; ++q) e[q] = v->ev[v->ev_used + q];
+  v->ev_used += 3;
+  return MHC_OK;
+}
+
+// Squared pair distance beyond which the site kernel writes zero partials
+// (R + D), widened by one part in 10^12 so that rounding in the gather
+// kernel's own distance never drops a pair the site kernel kept.
+double rcut2_of(const mhc_virial* v) {
+  const double rc = (v->tp.R + v->tp.D) * (1.0 + 1e-12);
+  return rc * rc;
+}
+
 mhc_status venter(mhc_virial* v) {
   if (!v) return MHC_ERR_INVALID_ARG;
   if (v->sticky != MHC_OK) return v->sticky;
@@ -293,24 +316,14 @@ mhc_status mhc_virial_compute(mhc_virial* v, const double* pos, const double* ve
   o.mass = v->d_mass;
   for (int q = 0; q < 3; ++q) o.fe[q] = f[q];
   o.ke_unit = KE_UNIT_EV;
+  o.rcut2 = rcut2_of(v);
   o.F = F;
   o.W = W;
   o.W32 = W32;
   o.Fext = Fext;
-  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-  if (v->timing) {
-    if (v->ev_used + 3 > v->ev.size())
-      for (int q = 0; q < 3; ++q) {
-        hipEvent_t e;
-        VHIP_TRY(hipEventCreate(&e), "event create");
-        v->ev.push_back(e);
-      }
-    e0 = v->ev[v->ev_used];
-    e1 = v->ev[v->ev_used + 1];
-    e2 = v->ev[v->ev_used + 2];
-    v->ev_used += 3;
-  }
-  VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, e0, e1, e2), "virial kernels");
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  if ((st = timing_events(v, e))) return st;
+  VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, e[0], e[1], e[2]), "virial kernels");
   return MHC_OK;
 }
 
@@ -339,9 +352,13 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
     GatherArgs o{};
     o.mass = v->d_mass;
     o.ke_unit = KE_UNIT_EV;
+  o.rcut2 = rcut2_of(v);
     o.F = v->d_F;
     o.W32 = w32;
-    VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, nullptr, nullptr, nullptr), "force kernels");
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    mhc_status s2 = timing_events(v, e);
+    if (s2) return s2;
+    VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, e[0], e[1], e[2]), "force kernels");
     return MHC_OK;
   };
   const double c = 0.5 * dt / KE_UNIT_EV;   // half kick: dv = dt/2 F / (m KE)
