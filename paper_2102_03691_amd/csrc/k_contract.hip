@@ -736,7 +736,11 @@ k_gemm_dir(GemmGeom g) {
 // work-group took it.  The queue ends for every wave at the same counter
 // value, so all work-groups exit.
 
-template <int PREC, int WM, int WT, int MB>
+// DIRG: the group holds systems with the one-contraction direction split
+// (their tiles take the three-third procedure).  A separate instantiation,
+// because the extra path raises the register pressure of the e4m3 kernels
+// into spills inside their product loops.
+template <int PREC, int WM, int WT, int MB, bool DIRG>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
 k_gemm_group(const GemmGeom* __restrict__ sys, const GroupTile* __restrict__ tiles, int n_tiles,
              int* __restrict__ counter) {
@@ -756,13 +760,15 @@ k_gemm_group(const GemmGeom* __restrict__ sys, const GroupTile* __restrict__ til
     const int ntile = gt.tile % g.n_ntiles;
     const int64_t rb0 = (int64_t)mtile * RBW;
     // the orientation follows the system's method (uniform per work-group)
-    if (g.s3 > 0) {
-      float* slot = g.ws + (int64_t)blockIdx.x * 2 * (MB * 3 * 16) * 256 + threadIdx.x;
-      if (g.layout_g)
-        dir_tile<PREC, WM, WT, MB, false>(g, rb0, ntile, slot, acc, lds);
-      else
-        dir_tile<PREC, WM, WT, MB, true>(g, rb0, ntile, slot, acc, lds);
-      continue;
+    if constexpr (DIRG) {
+      if (g.s3 > 0) {
+        float* slot = g.ws + (int64_t)blockIdx.x * 2 * (MB * 3 * 16) * 256 + threadIdx.x;
+        if (g.layout_g)
+          dir_tile<PREC, WM, WT, MB, false>(g, rb0, ntile, slot, acc, lds);
+        else
+          dir_tile<PREC, WM, WT, MB, true>(g, rb0, ntile, slot, acc, lds);
+        continue;
+      }
     }
     if (g.layout_g) {
       gemm_segment<PREC, WM, WT, MB, false>(g, rb0, ntile, 0, g.n_stages, acc, lds);
@@ -1054,27 +1060,31 @@ void gemm_geom(int prec, int shape, const void* E, const void* B, float* out, in
   g->ipw = g->n_stages;
 }
 
-template <int PREC>
+template <int PREC, bool DIRG>
 static hipError_t launch_group_prec(hipStream_t s, int shape, const GemmGeom* d_sys, const GroupTile* d_tiles,
                                     int n_tiles, int* counter, int n_wg) {
   dim3 grid((unsigned)n_wg), block(256);
   if (shape == 0)
-    hipLaunchKernelGGL((k_gemm_group<PREC, 1, 4, 4>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
+    hipLaunchKernelGGL((k_gemm_group<PREC, 1, 4, 4, DIRG>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
   else if (shape == 1)
-    hipLaunchKernelGGL((k_gemm_group<PREC, 2, 2, 4>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
+    hipLaunchKernelGGL((k_gemm_group<PREC, 2, 2, 4, DIRG>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
   else
-    hipLaunchKernelGGL((k_gemm_group<PREC, 4, 1, 2>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
+    hipLaunchKernelGGL((k_gemm_group<PREC, 4, 1, 2, DIRG>), grid, block, 0, s, d_sys, d_tiles, n_tiles, counter);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_group(hipStream_t s, int prec, int shape, const GemmGeom* d_sys, const GroupTile* d_tiles,
-                             int n_tiles, int* counter, int n_wg) {
+                             int n_tiles, int* counter, int n_wg, bool with_dir) {
+#define MHC_GRP(P)                                                                                   \
+  (with_dir ? launch_group_prec<P, true>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg)          \
+            : launch_group_prec<P, false>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg))
   switch (prec) {
-    case PREC_BF16X3: return launch_group_prec<PREC_BF16X3>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
-    case PREC_FP8: return launch_group_prec<PREC_FP8>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
-    case PREC_FP8X3: return launch_group_prec<PREC_FP8X3>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
-    default: return launch_group_prec<PREC_FP32>(s, shape, d_sys, d_tiles, n_tiles, counter, n_wg);
+    case PREC_BF16X3: return MHC_GRP(PREC_BF16X3);
+    case PREC_FP8: return MHC_GRP(PREC_FP8);
+    case PREC_FP8X3: return MHC_GRP(PREC_FP8X3);
+    default: return MHC_GRP(PREC_FP32);
   }
+#undef MHC_GRP
 }
 
 __global__ void k_fill_i32(int* p, int n, int v) {

@@ -1678,8 +1678,10 @@ mhc_status build_queue(mhc_group* g) {
 
 mhc_status group_contract(mhc_group* g) {
   GHIP_TRY(launch_fill_i32(g->stream, g->d_counter, 1, 0), "queue reset");
+  bool with_dir = false;
+  for (auto* c : g->sys) with_dir |= c->n3 > 0;
   GHIP_TRY(launch_gemm_group(g->stream, g->prec, g->shape, g->d_geom, g->d_tiles, g->n_tiles, g->d_counter,
-                             std::min(g->n_cu, g->n_tiles)),
+                             std::min(g->n_cu, g->n_tiles), with_dir),
            "grouped contraction");
   return MHC_OK;
 }

@@ -125,9 +125,10 @@ void gemm_geom(int prec, int shape, const void* E, const void* B, float* out, in
 
 // Persistent launch over the tiles of several systems (same precision and
 // tile shape): n_wg work-groups pull tiles[] in order through *counter, which
-// must be zero at launch (launch_fill_i32).
+// must be zero at launch (launch_fill_i32).  with_dir: some system has the
+// one-contraction direction split (GemmGeom::s3 > 0).
 hipError_t launch_gemm_group(hipStream_t s, int prec, int shape, const GemmGeom* d_sys, const GroupTile* d_tiles,
-                             int n_tiles, int* counter, int n_wg);
+                             int n_tiles, int* counter, int n_wg, bool with_dir);
 hipError_t launch_fill_i32(hipStream_t s, int* p, int n, int v);
 
 // T-batched matrix-core contraction with fused modal-current epilogue.
