@@ -35,3 +35,11 @@ def shc_kappa(Kw, temperature, volume_a3, fe_per_a):
     = 1.602e-9 W m^-1 K^-1 Hz^-1); times 1e12 per THz."""
     per_hz = 2.0 * Kw / (volume_a3 * temperature * fe_per_a)             # eV / (A K)
     return per_hz * (1.602176634e-19 / 1e-10) * 1e12
+
+
+def tersoff_si() -> dict:
+    """Tersoff's published silicon parameters (Phys. Rev. B 38, 9902 (1988);
+    the paper's Si potential, Sec. III.A), in the form ModalVirial takes:
+    eV, 1/A and A."""
+    return dict(A=1830.8, B=471.18, lambda1=2.4799, lambda2=1.7322, lambda3=0.0, m=3, beta=1.1e-6, n=0.78734,
+                c=1.0039e5, d=16.217, h=-0.59825, gamma=1.0, R=2.85, D=0.15)

@@ -276,3 +276,10 @@ def test_mutation_transposed_virial_fails_eq9_and_eq11():
     F11 = ov.hnemd_force_eq11(pos, box, E, fe, p, nl)
     Fbad = E[:, None] * fe[None, :] + np.einsum("imn,n->im", W, fe)
     assert np.abs(Fbad - F11).max() > 1e-3 * np.abs(F11 - E[:, None] * fe[None, :]).max()
+
+
+def test_package_parameters_are_the_published_ones():
+    """The package's tersoff_si() (what users pass to ModalVirial) holds the same
+    published numbers as the oracle's, each written from Tersoff's paper."""
+    from paper_2102_03691_amd.physics import tersoff_si
+    assert tersoff_si() == ov.tersoff_si()
