@@ -112,6 +112,43 @@ def test_slab48_bf16x3_t128():
     assert max(e.values()) <= TOL[BF16X3]
 
 
+def test_slab48_direction_split_bf16x3_t128():
+    """48x48x4 slab with the motion-direction split as one contraction
+    (split-BF16, T = 128, 1000 bins, HNEMA + GKMA): per direction against the
+    plane-wave reference (a mode of polarisation nu moves atoms along nu only,
+    so J_b^{mu nu} is the FFT-form current of v^nu and W^{. nu}); the GKMA split
+    correlates each direction's binned current with the whole total current."""
+    announce("full size slab48 direction split bf16x3 T=128")
+    lat = synth.BlochLattice((48, 48, 4))
+    nb, L, S = 1000, 32, 256
+    h, m = _context(lat, nb, HNEMA | GKMA | 4, BF16X3, 128, L)
+    v, W = synth.gen_steps(14, m, 0, S)
+    _push(h, v, W, 128)
+    avg_d, tot_d, n = h.read_hnema_dir()
+    gd = h.read_gkma_dir()
+    avg, _, _ = h.read_hnema()
+    h.close()
+    kb = oracle.bin_of_mode(lat.kpoint_frequencies().ravel(), nb, 0.0, lat.f_max).reshape(lat.dims)
+    Jt = oracle.total_heat_current(v, W)
+    e = {}
+    for nu in range(3):
+        vm = np.zeros_like(v)
+        vm[..., nu] = v[..., nu]
+        Wm = np.zeros_like(W)
+        Wm[..., :, nu] = W[..., :, nu]
+        Jb = oracle.binned_current_fft(lat.dims, m, vm, Wm, kb, nb)
+        e[f"hnema_nu{nu}"] = rel(avg_d[:, :, nu], oracle.hnema_average(Jb))
+        e[f"corr_nu{nu}"] = rel(gd["corr"][:, :, :, nu, :], oracle.gkma_correlation(Jb, Jt, L))
+        # the split Eq. 10 total: sum_i W_i^{mu nu} v_i^nu
+        Wd, vd = W.astype(np.float64), v.astype(np.float64)
+        e[f"total_nu{nu}"] = rel(tot_d[:, nu], (Wd[..., :, nu] * vd[..., None, nu]).sum(axis=1).mean(axis=0))
+    e["hnema_sum"] = rel(avg, avg_d.sum(axis=2))
+    log("slab48_fullsize_dir_bf16x3_t128", **e)
+    assert n == S
+    for k, x in e.items():
+        assert x <= (1e-12 if k.startswith("total") or k == "hnema_sum" else TOL[BF16X3]), (k, x)
+
+
 @pytest.mark.parametrize("prec,S", [(BF16X3, 2560), (FP32, 512)])
 def test_rod1500_gkma_t256(prec, S):
     """4x4x1500 rod, 24000 atoms / 72000 modes, GKMA with L = 2000, T = 256, 1000 bins.

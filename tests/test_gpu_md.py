@@ -74,6 +74,22 @@ def test_md_matches_oracle(rebuild, skin):
     assert e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0
 
 
+@pytest.mark.timeout(600)
+def test_md_si8000_full_size():
+    """The paper's 8000-atom Si (10 x 10 x 10 cells): 3 steps of 1 fs against the
+    oracle's integrator over every atom, lists with a 1 A skin rebuilt every step."""
+    announce("md si8000 full size 3 steps")
+    pos, box, m, vel = _start((10, 10, 10), 0.06, 19)
+    ref = ov.md_nve(pos, vel, m, box, ov.tersoff_si(), 1.0, 3)
+    v, got = _device_md(pos, box, m, vel, 1.0, 3, 1, 1.0)
+    v.close()
+    dx = float(np.abs(ov.min_image(got["pos"] - ref["pos"][-1], box)).max())
+    dv = float(np.abs(got["vel"] - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max())
+    e = {"dx_A": dx, "dv_rel": dv, "v32_ulps": _ulps(got["v32"], ref["vel"]), "W32_ulps": _ulps(got["W32"], ref["W"])}
+    log("md8000", **e)
+    assert dx <= 1e-11 and dv <= 1e-11 and e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0
+
+
 @pytest.mark.timeout(300)
 def test_md_conserves_energy():
     import torch
