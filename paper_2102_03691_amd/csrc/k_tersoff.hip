@@ -45,6 +45,16 @@ __device__ __forceinline__ int cell_coord(double x, double L, int nc) {
 }
 
 // ------------------------------------------------------------- neighbour lists
+// atomicMax of v over the whole wave with one atomic per wave instead of one
+// per lane (the lanes of an atom-per-lane kernel all target one counter, and
+// 64 times fewer atomics on one address matter at 10^5..10^6 atoms).  Every
+// lane of the wave must call it.
+__device__ __forceinline__ void wave_atomic_max(int* addr, int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(addr, v);
+}
+
 __global__ void k_fill_zero_i32(int* __restrict__ p, int n) {
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i < n) p[i] = 0;
@@ -127,13 +137,12 @@ __global__ void __launch_bounds__(256) k_cell_fill(int64_t N, const int* __restr
   atoms[start[c] + k] = (int)i;
 }
 
-__global__ void __launch_bounds__(256) k_neighbors(const double* __restrict__ pos, int64_t N, CellGrid cg,
-                                                   double rc2, const int* __restrict__ cell_of,
-                                                   const int* __restrict__ start, const int* __restrict__ atoms,
-                                                   int max_nb, int* __restrict__ nbr, int* __restrict__ n_nb,
-                                                   int* __restrict__ max_found) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// The list of atom i; returns the number of atoms found inside rc (which may
+// exceed max_nb: only max_nb are kept).
+__device__ int neighbors_of(int64_t i, const double* __restrict__ pos, int64_t N, const CellGrid& cg, double rc2,
+                            const int* __restrict__ cell_of, const int* __restrict__ start,
+                            const int* __restrict__ atoms, int max_nb, int* __restrict__ nbr,
+                            int* __restrict__ n_nb) {
   const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
   const int c = cell_of[i];
   const int cz0 = c % cg.nc[2], cy0 = (c / cg.nc[2]) % cg.nc[1], cx0 = c / (cg.nc[2] * cg.nc[1]);
@@ -172,7 +181,17 @@ __global__ void __launch_bounds__(256) k_neighbors(const double* __restrict__ po
     nbr[(int64_t)(b + 1) * N + i] = key;
   }
   n_nb[i] = n;
-  atomicMax(max_found, cnt);
+  return cnt;
+}
+
+__global__ void __launch_bounds__(256) k_neighbors(const double* __restrict__ pos, int64_t N, CellGrid cg,
+                                                   double rc2, const int* __restrict__ cell_of,
+                                                   const int* __restrict__ start, const int* __restrict__ atoms,
+                                                   int max_nb, int* __restrict__ nbr, int* __restrict__ n_nb,
+                                                   int* __restrict__ max_found) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int cnt = i < N ? neighbors_of(i, pos, N, cg, rc2, cell_of, start, atoms, max_nb, nbr, n_nb) : 0;
+  wave_atomic_max(max_found, cnt);
 }
 
 // rev[s][i] = slot of i in the list of j = nbr[s][i] (-1 if absent, which a
@@ -190,6 +209,85 @@ __global__ void __launch_bounds__(256) k_reverse(int64_t N, const int* __restric
       if (nbr[(int64_t)t * N + j] == (int)i) r = t;
     rev[(int64_t)s * N + i] = r;
     if (r < 0) *missing = 1;
+  }
+}
+
+// Bonds of one configuration out of lists built with a skin: the listed pairs
+// closer than R + D (rb2: its square, slightly widened so that no pair with a
+// nonzero cutoff function is dropped; a kept pair at the edge contributes
+// zero), in list order (so still ascending j), at most max_b per atom.
+// mask[i] bit s = list slot s of i is a bond; count[i] = bonds kept;
+// flags[0] = largest bond count found (atomic max); flags[1] = 1 if an atom
+// had more than max_b.
+__global__ void __launch_bounds__(256) k_bonds(const double* __restrict__ pos, int64_t N, double Lx, double Ly,
+                                               double Lz, const int* __restrict__ nbr, const int* __restrict__ n_nb,
+                                               double rb2, int max_b, int* __restrict__ bnbr,
+                                               int* __restrict__ bcount, unsigned long long* __restrict__ mask,
+                                               int* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < N;
+  const int n = act ? n_nb[i] : 0;
+  const double xi = act ? pos[3 * i] : 0.0, yi = act ? pos[3 * i + 1] : 0.0, zi = act ? pos[3 * i + 2] : 0.0;
+  int c = 0, found = 0;
+  unsigned long long m = 0;
+  // 16 list slots at a time, every load issued before the first distance
+  // (slots past the list read atom i itself and are masked out)
+  constexpr int U = 16;
+  for (int s0 = 0; s0 < n; s0 += U) {
+    int jj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) jj[u] = s0 + u < n ? nbr[(int64_t)(s0 + u) * N + i] : (int)i;
+    double px[U], py[U], pz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      px[u] = pos[3 * (int64_t)jj[u]];
+      py[u] = pos[3 * (int64_t)jj[u] + 1];
+      pz[u] = pos[3 * (int64_t)jj[u] + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double x = min_image(px[u] - xi, Lx);
+      const double y = min_image(py[u] - yi, Ly);
+      const double z = min_image(pz[u] - zi, Lz);
+      if (s0 + u < n && x * x + y * y + z * z < rb2) {
+        ++found;
+        m |= 1ull << (s0 + u);
+        if (c < max_b) bnbr[(int64_t)(c++) * N + i] = jj[u];
+      }
+    }
+  }
+  if (act) {
+    bcount[i] = c;
+    mask[i] = m;
+  }
+  wave_atomic_max(&flags[0], found);
+  if (found > max_b) flags[1] = 1;
+}
+
+// Reverse slots of the bond lists from those of the full lists: bond c of i
+// sits at list slot s, which is slot t = rev[s][i] in the list of j; its bond
+// slot in j's bond list is the number of j's bonds at list slots below t.
+// flags[2] = 1 if the pair is not a bond of j (asymmetric test) or has no
+// reverse slot.
+__global__ void __launch_bounds__(256) k_bond_reverse(int64_t N, const int* __restrict__ nbr,
+                                                      const int* __restrict__ rev,
+                                                      const unsigned long long* __restrict__ mask, int max_b,
+                                                      int* __restrict__ brev, int* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  unsigned long long m = mask[i];
+  for (int c = 0; m != 0 && c < max_b; ++c) {
+    const int s = __builtin_ctzll(m);
+    m &= m - 1;
+    const int j = nbr[(int64_t)s * N + i];
+    const int t = rev[(int64_t)s * N + i];
+    int r = -1;
+    if (t >= 0) {
+      const unsigned long long mj = mask[j];
+      if ((mj >> t) & 1ull) r = __builtin_popcountll(mj & ((1ull << t) - 1ull));
+    }
+    brev[(int64_t)c * N + i] = r;
+    if (r < 0) flags[2] = 1;
   }
 }
 
@@ -401,6 +499,21 @@ __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArg
 
 // ------------------------------------------------------------- launchers
 static inline unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_zero_i32(hipStream_t s, int* p, int n) {
+  hipLaunchKernelGGL(k_fill_zero_i32, dim3(blocks_of(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bonds(hipStream_t s, const double* pos, int64_t N, const double box[3], const int* nbr,
+                        const int* n_nb, const int* rev, double rb2, int max_b, BondBufs b, bool reset_flags) {
+  if (reset_flags) hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b.flags, 3);
+  hipLaunchKernelGGL(k_bonds, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, box[0], box[1], box[2], nbr, n_nb, rb2,
+                     max_b, b.nbr, b.n_nb, b.mask, b.flags);
+  hipLaunchKernelGGL(k_bond_reverse, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, nbr, rev, b.mask, max_b, b.rev,
+                     b.flags);
+  return hipGetLastError();
+}
 
 hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, int max_nb,
                             NeighborBufs b) {

@@ -31,6 +31,18 @@ struct NeighborBufs {
   int* flags;
 };
 
+// Bond lists of one configuration (the listed pairs inside R + D): nbr, rev
+// [max_b][N] (slot-major), n_nb [N], mask [N] (bit s: list slot s is a bond);
+// flags[0] = largest bond count found, flags[1] = 1 if an atom had more than
+// max_b, flags[2] = 1 if a reverse slot was missing.
+struct BondBufs {
+  int* nbr;
+  int* rev;
+  int* n_nb;
+  unsigned long long* mask;
+  int* flags;
+};
+
 // Tersoff parameters as the kernels use them: l3m = lambda3^m, c2 = c^2, d2 = d^2,
 // c2d2 = c^2 / d^2.
 struct TersoffParams {
@@ -69,6 +81,14 @@ struct GatherArgs {
 
 hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, int max_nb,
                             NeighborBufs b);
+// Zero n ints (n > 0).
+hipError_t launch_zero_i32(hipStream_t s, int* p, int n);
+// Bonds out of the lists (nbr, n_nb, with reverse slots rev): pairs with
+// squared distance below rb2, at most max_b per atom (max_nb <= 64), and
+// their reverse slots.  The flags accumulate over launches unless
+// reset_flags clears them first.
+hipError_t launch_bonds(hipStream_t s, const double* pos, int64_t N, const double box[3], const int* nbr,
+                        const int* n_nb, const int* rev, double rb2, int max_b, BondBufs b, bool reset_flags);
 // Lanes per atom of the evaluation kernels for a largest neighbour count:
 // the next power of two, at least 4 (64 at most: max_nb <= 64).
 int tersoff_lanes(int max_count);

@@ -44,6 +44,14 @@ struct mhc_virial {
   NeighborBufs nb{};
   double *d_dd = nullptr, *d_U = nullptr;
   double* d_F = nullptr;  // forces of the molecular dynamics (mhc_virial_md)
+  // Bond lists of the molecular dynamics when the lists carry a skin: each
+  // step's pairs inside R + D, with max_b slots (the largest count at the
+  // last list build plus 2) and lpa_b lanes per atom (compact: fewer lanes
+  // than the lists need).  bb.flags[0..2] accumulate over one mhc_virial_md
+  // call; [4..6] serve the count at list builds.
+  BondBufs bb{};
+  int max_b = 0, lpa_b = 4;
+  bool compact = false;
   int lpa = 4;            // lanes per atom of the evaluation kernels (from the largest neighbour count)
 
   bool timing = false;
@@ -88,6 +96,24 @@ mhc_status timing_events(mhc_virial* v, hipEvent_t e[3]) {
 double rcut2_of(const mhc_virial* v) {
   const double rc = (v->tp.R + v->tp.D) * (1.0 + 1e-12);
   return rc * rc;
+}
+
+// Largest bond count now (pairs inside R + D, from the current lists), read
+// back; sets the bond slots and lanes of the molecular dynamics.
+mhc_status plan_bonds(mhc_virial* v, const double* pos) {
+  v->compact = false;
+  if (!(v->rc > (v->tp.R + v->tp.D) * (1.0 + 1e-9))) return MHC_OK;   // no skin: the lists are the bonds
+  BondBufs pb = v->bb;
+  pb.flags = v->bb.flags + 4;
+  VHIP_TRY(launch_bonds(v->stream, pos, v->N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev, rcut2_of(v), v->max_nb, pb, true),
+           "bonds");
+  int f[3] = {0, 0, 0};
+  VHIP_TRY(hipMemcpyAsync(f, pb.flags, sizeof(f), hipMemcpyDeviceToHost, v->stream), "read bond flags");
+  VHIP_TRY(hipStreamSynchronize(v->stream), "bonds sync");
+  v->max_b = std::min(v->max_nb, f[0] + 2);
+  v->lpa_b = tersoff_lanes(v->max_b);
+  v->compact = v->lpa_b < v->lpa;
+  return MHC_OK;
 }
 
 mhc_status venter(mhc_virial* v) {
@@ -217,7 +243,10 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
             valloc(v, N, &b.cell_of) && valloc(v, N, &b.atoms) && valloc(v, n_cells, &b.count) &&
             valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) &&
             valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 2, &b.flags) &&
-            valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U) && valloc(v, 3 * N, &v->d_F);
+            valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U) && valloc(v, 3 * N, &v->d_F) &&
+            valloc(v, MN, &v->bb.nbr) && valloc(v, MN, &v->bb.rev) && valloc(v, N, &v->bb.n_nb) &&
+            valloc(v, N, &v->bb.mask) &&
+            valloc(v, 8, &v->bb.flags);
   if (!ok) return cleanup(MHC_ERR_OOM, "device allocation failed");
   if (hipMemcpyAsync(v->d_mass, mass_amu, N * sizeof(double), hipMemcpyHostToDevice, v->stream) != hipSuccess ||
       hipStreamSynchronize(v->stream) != hipSuccess)
@@ -260,7 +289,7 @@ mhc_status mhc_virial_neighbors(mhc_virial* v, const double* pos, int32_t* max_f
   if (flags[1]) return vfail(v, MHC_ERR_INVALID_ARG, "neighbour lists are not symmetric (non-finite positions?)");
   v->lpa = tersoff_lanes(flags[0]);
   v->lists_ok = true;
-  return MHC_OK;
+  return plan_bonds(v, pos);
 }
 
 mhc_status mhc_virial_read_neighbors(mhc_virial* v, int32_t* counts, int32_t* lists) {
@@ -338,6 +367,7 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
   if (n_steps == 0) return MHC_OK;
   VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
   const int64_t N = v->N;
+  bool any_compact = false;
   auto force = [&](float* w32) -> mhc_status {
     TersoffArgs a{};
     a.pos = pos;
@@ -347,21 +377,34 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
     a.n_nb = v->nb.n_nb;
     a.rev = v->nb.rev;
     a.max_nb = v->max_nb;
+    int lpa = v->lpa;
+    if (v->compact) {   // this configuration's bonds out of the skin lists
+      any_compact = true;
+      VHIP_TRY(launch_bonds(v->stream, pos, N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev, rcut2_of(v), v->max_b, v->bb, false),
+               "bonds");
+      a.nbr = v->bb.nbr;
+      a.n_nb = v->bb.n_nb;
+      a.rev = v->bb.rev;
+      a.max_nb = v->max_b;
+      lpa = v->lpa_b;
+    }
     a.dd = v->d_dd;
     a.U = v->d_U;
     GatherArgs o{};
     o.mass = v->d_mass;
     o.ke_unit = KE_UNIT_EV;
-  o.rcut2 = rcut2_of(v);
+    o.rcut2 = rcut2_of(v);
     o.F = v->d_F;
     o.W32 = w32;
     hipEvent_t e[3] = {nullptr, nullptr, nullptr};
     mhc_status s2 = timing_events(v, e);
     if (s2) return s2;
-    VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, v->lpa, e[0], e[1], e[2]), "force kernels");
+    VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, lpa, e[0], e[1], e[2]), "force kernels");
     return MHC_OK;
   };
   const double c = 0.5 * dt / KE_UNIT_EV;   // half kick: dv = dt/2 F / (m KE)
+  // overflow and reverse-slot flags of the bond passes accumulate over this call's steps
+  VHIP_TRY(launch_zero_i32(v->stream, v->bb.flags, 3), "clear bond flags");
   if ((st = force(nullptr))) return st;     // forces at the entry positions
   for (int32_t s = 0; s < n_steps; ++s) {
     VHIP_TRY(launch_md_kick(v->stream, vel, v->d_F, v->d_mass, c, N, nullptr), "half kick");
@@ -372,6 +415,17 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
              "half kick");
   }
   if (F) VHIP_TRY(hipMemcpyAsync(F, v->d_F, (size_t)N * 3 * 8, hipMemcpyDeviceToDevice, v->stream), "copy forces");
+  if (any_compact) {
+    int f[3] = {0, 0, 0};
+    VHIP_TRY(hipMemcpyAsync(f, v->bb.flags, sizeof(f), hipMemcpyDeviceToHost, v->stream), "read bond flags");
+    VHIP_TRY(hipStreamSynchronize(v->stream), "md sync");
+    if (f[1])
+      return vfail(v, MHC_ERR_INVALID_ARG,
+                   "an atom's bond count rose to " + std::to_string(f[0]) + ", above the " + std::to_string(v->max_b) +
+                       " bond slots set at the last list build (rebuild the lists more often); the steps' results are "
+                       "not valid");
+    if (f[2]) return vfail(v, MHC_ERR_INVALID_ARG, "bond lists are not symmetric (non-finite positions?)");
+  }
   return MHC_OK;
 }
 

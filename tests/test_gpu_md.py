@@ -166,3 +166,37 @@ def test_md_errors():
         assert ei.value.status == 1
     v.md(pt, vt, 1.0, 0)                      # nothing to do
     v.close()
+
+
+def test_md_bond_overflow_is_reported():
+    """With a skin the steps evaluate each configuration's bonds (pairs inside
+    R + D) with as many slots as the largest bond count at the last list build
+    plus two.  A centre atom whose seven list neighbours sit outside R + D at
+    the build and inside it at the step has more bonds than slots: the call
+    reports it instead of returning forces with bonds left out."""
+    import torch
+    from paper_2102_03691_amd import MhcError, ModalVirial
+    announce("md bond-slot overflow")
+    dirs = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1]], float)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    box = np.array([20.0, 20.0, 20.0])
+    c = box / 2
+    p = ov.tersoff_si()
+    far = np.vstack([c, c + (p["R"] + p["D"] + 0.3) * dirs])     # no bonds at the list build
+    near = np.vstack([c, c + (p["R"] + p["D"] - 0.1) * dirs])    # 0.4 A later: seven bonds at the centre
+    m = np.full(len(far), 28.0855)
+    v = ModalVirial(m, box, p, max_neighbors=24, skin=1.0)
+    v.neighbors(torch.as_tensor(far, device="cuda:0"))
+    pt = torch.as_tensor(near, device="cuda:0")
+    vt = torch.zeros_like(pt)
+    with pytest.raises(MhcError) as ei:
+        v.md(pt, vt, 1.0, 1)
+    assert ei.value.status == 1 and "bond" in str(ei.value)
+    pt = torch.as_tensor(near, device="cuda:0")               # lists built where the bonds are: runs
+    vt = torch.zeros_like(pt)
+    v.neighbors(pt)
+    v.md(pt, vt, 1.0, 1)
+    torch.cuda.synchronize()
+    ref = ov.md_nve(near, np.zeros_like(near), m, box, p, 1.0, 1)
+    assert np.abs(pt.cpu().numpy() - ref["pos"][-1]).max() < 1e-12
+    v.close()
