@@ -32,11 +32,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "mhc_tersoff.h"
 
 namespace mhc {
 
-__device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
+// Minimum-image difference; iL = 1 / L.  For every pair closer than L / 2 by
+// more than rounding (all listed pairs: each box edge exceeds twice the list
+// cutoff) the shift is the same integer as with d / L, so the result is too.
+__device__ __forceinline__ double min_image(double d, double L, double iL) { return d - L * rint(d * iL); }
 
 __device__ __forceinline__ int cell_coord(double x, double L, int nc) {
   const double w = x - L * floor(x / L);
@@ -53,6 +59,10 @@ __device__ __forceinline__ void wave_atomic_max(int* addr, int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(addr, v);
+}
+
+__global__ void k_set_i32(int* __restrict__ p, int value) {
+  if (threadIdx.x == 0) *p = value;
 }
 
 __global__ void k_fill_zero_i32(int* __restrict__ p, int n) {
@@ -158,9 +168,9 @@ __device__ int neighbors_of(int64_t i, const double* __restrict__ pos, int64_t N
         for (int q = start[cc]; q < start[cc + 1]; ++q) {
           const int j = atoms[q];
           if (j == (int)i) continue;
-          const double ddx = min_image(pos[3 * (int64_t)j] - xi, cg.box[0]);
-          const double ddy = min_image(pos[3 * (int64_t)j + 1] - yi, cg.box[1]);
-          const double ddz = min_image(pos[3 * (int64_t)j + 2] - zi, cg.box[2]);
+          const double ddx = min_image(pos[3 * (int64_t)j] - xi, cg.box[0], cg.ibox[0]);
+          const double ddy = min_image(pos[3 * (int64_t)j + 1] - yi, cg.box[1], cg.ibox[1]);
+          const double ddz = min_image(pos[3 * (int64_t)j + 2] - zi, cg.box[2], cg.ibox[2]);
           if (ddx * ddx + ddy * ddy + ddz * ddz < rc2) {
             if (cnt < max_nb) nbr[(int64_t)cnt * N + i] = j;
             ++cnt;
@@ -212,19 +222,25 @@ __global__ void __launch_bounds__(256) k_reverse(int64_t N, const int* __restric
   }
 }
 
-// Bonds of one configuration out of lists built with a skin: the listed pairs
-// closer than R + D (rb2: its square, slightly widened so that no pair with a
-// nonzero cutoff function is dropped; a kept pair at the edge contributes
-// zero), in list order (so still ascending j), at most max_b per atom.
-// mask[i] bit s = list slot s of i is a bond; count[i] = bonds kept;
-// flags[0] = largest bond count found (atomic max); flags[1] = 1 if an atom
-// had more than max_b.
+// Bond lists out of lists built with a skin: the listed pairs closer than rb
+// (rb2 = rb^2, rb = R + D + delta with delta the bond lists' own skin), in
+// list order (so still ascending j), at most max_b per atom.  mask[i] bit s =
+// list slot s of i is kept; count[i] = pairs kept; ref[i] = pos[i] (the
+// positions of the build, for the displacement test); flags[0] = largest
+// count found (atomic max); flags[1] = 1 if an atom had more than max_b.
+// need (null: always build) = the rebuild flag of this evaluation, one value
+// read by every thread, so the whole grid builds or none of it does; clear
+// (null: none) is the other evaluation's flag, zeroed here.
 __global__ void __launch_bounds__(256) k_bonds(const double* __restrict__ pos, int64_t N, double Lx, double Ly,
-                                               double Lz, const int* __restrict__ nbr, const int* __restrict__ n_nb,
-                                               double rb2, int max_b, int* __restrict__ bnbr,
-                                               int* __restrict__ bcount, unsigned long long* __restrict__ mask,
-                                               int* __restrict__ flags) {
+                                               double Lz, double iLx, double iLy, double iLz,
+                                               const int* __restrict__ nbr, const int* __restrict__ n_nb, double rb2,
+                                               int max_b, int* __restrict__ bnbr, int* __restrict__ bcount,
+                                               unsigned long long* __restrict__ mask, double* __restrict__ ref,
+                                               int* __restrict__ flags, const int* __restrict__ need,
+                                               int* __restrict__ clear) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (clear && i == 0) *clear = 0;
+  if (need && *need == 0) return;
   const bool act = i < N;
   const int n = act ? n_nb[i] : 0;
   const double xi = act ? pos[3 * i] : 0.0, yi = act ? pos[3 * i + 1] : 0.0, zi = act ? pos[3 * i + 2] : 0.0;
@@ -246,9 +262,9 @@ __global__ void __launch_bounds__(256) k_bonds(const double* __restrict__ pos, i
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const double x = min_image(px[u] - xi, Lx);
-      const double y = min_image(py[u] - yi, Ly);
-      const double z = min_image(pz[u] - zi, Lz);
+      const double x = min_image(px[u] - xi, Lx, iLx);
+      const double y = min_image(py[u] - yi, Ly, iLy);
+      const double z = min_image(pz[u] - zi, Lz, iLz);
       if (s0 + u < n && x * x + y * y + z * z < rb2) {
         ++found;
         m |= 1ull << (s0 + u);
@@ -259,6 +275,9 @@ __global__ void __launch_bounds__(256) k_bonds(const double* __restrict__ pos, i
   if (act) {
     bcount[i] = c;
     mask[i] = m;
+    ref[3 * i] = xi;
+    ref[3 * i + 1] = yi;
+    ref[3 * i + 2] = zi;
   }
   wave_atomic_max(&flags[0], found);
   if (found > max_b) flags[1] = 1;
@@ -272,9 +291,10 @@ __global__ void __launch_bounds__(256) k_bonds(const double* __restrict__ pos, i
 __global__ void __launch_bounds__(256) k_bond_reverse(int64_t N, const int* __restrict__ nbr,
                                                       const int* __restrict__ rev,
                                                       const unsigned long long* __restrict__ mask, int max_b,
-                                                      int* __restrict__ brev, int* __restrict__ flags) {
+                                                      int* __restrict__ brev, int* __restrict__ flags,
+                                                      const int* __restrict__ need) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  if (i >= N || (need && *need == 0)) return;
   unsigned long long m = mask[i];
   for (int c = 0; m != 0 && c < max_b; ++c) {
     const int s = __builtin_ctzll(m);
@@ -342,9 +362,9 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
   double x = 0.0, y = 0.0, z = 0.0, r = 1.0, ir = 1.0, fc = 0.0, dfc = 0.0, er = 0.0, ea = 0.0;
   if (act) {
     const int64_t j = a.nbr[(int64_t)s * N + i];
-    x = min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0]);
-    y = min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1]);
-    z = min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2]);
+    x = min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0], a.ibox[0]);
+    y = min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1], a.ibox[1]);
+    z = min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2], a.ibox[2]);
     r = sqrt(x * x + y * y + z * z);
     ir = 1.0 / r;
     cutoff_fn(p, r, &fc, &dfc);
@@ -452,9 +472,9 @@ __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArg
     const int64_t mn = (int64_t)a.max_nb * N, es = (int64_t)s * N + i;
     const int64_t j = a.nbr[es];
     const int64_t ej = (int64_t)a.rev[es] * N + j;
-    const double r[3] = {min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0]),
-                         min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1]),
-                         min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2])};
+    const double r[3] = {min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0], a.ibox[0]),
+                         min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1], a.ibox[1]),
+                         min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2], a.ibox[2])};
     // a pair beyond R + D has zero partials both ways (written so by the site
     // kernel): nothing to load or add
     if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] < o.rcut2) {
@@ -506,12 +526,20 @@ hipError_t launch_zero_i32(hipStream_t s, int* p, int n) {
 }
 
 hipError_t launch_bonds(hipStream_t s, const double* pos, int64_t N, const double box[3], const int* nbr,
-                        const int* n_nb, const int* rev, double rb2, int max_b, BondBufs b, bool reset_flags) {
+                        const int* n_nb, const int* rev, double rb, int max_b, BondBufs b, bool reset_flags,
+                        const int* need, int* clear) {
   if (reset_flags) hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b.flags, 3);
-  hipLaunchKernelGGL(k_bonds, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, box[0], box[1], box[2], nbr, n_nb, rb2,
-                     max_b, b.nbr, b.n_nb, b.mask, b.flags);
+  const double rb2 = rb * rb * (1.0 + 1e-12);
+  hipLaunchKernelGGL(k_bonds, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, box[0], box[1], box[2], 1.0 / box[0],
+                     1.0 / box[1], 1.0 / box[2], nbr, n_nb, rb2, max_b, b.nbr, b.n_nb, b.mask, b.ref, b.flags, need,
+                     clear);
   hipLaunchKernelGGL(k_bond_reverse, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, nbr, rev, b.mask, max_b, b.rev,
-                     b.flags);
+                     b.flags, need);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_i32(hipStream_t s, int* p, int value) {
+  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, s, p, value);
   return hipGetLastError();
 }
 
@@ -576,6 +604,38 @@ __global__ void __launch_bounds__(256) k_md_drift(double* __restrict__ pos, cons
   if (x >= L) x -= L;
   if (x < 0.0) x += L;
   pos[q] = x;
+}
+
+// The drift per atom, with the displacement test of the bond lists: need = 1
+// if any atom moved farther than sqrt(thr2) from ref (its position at the
+// last bond build).  Same arithmetic as k_md_drift.
+__global__ void __launch_bounds__(256) k_md_drift_track(double* __restrict__ pos, const double* __restrict__ vel,
+                                                        double dt, double Lx, double Ly, double Lz, int64_t N,
+                                                        const double* __restrict__ ref, double thr2,
+                                                        int* __restrict__ need) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double d2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double L = a == 0 ? Lx : (a == 1 ? Ly : Lz);
+    double x = pos[3 * i + a] + dt * vel[3 * i + a];
+    x -= floor(x / L) * L;
+    if (x >= L) x -= L;
+    if (x < 0.0) x += L;
+    pos[3 * i + a] = x;
+    double d = x - ref[3 * i + a];
+    d -= L * rint(d / L);
+    d2 += d * d;
+  }
+  if (d2 > thr2) *need = 1;
+}
+
+hipError_t launch_md_drift_track(hipStream_t s, double* pos, const double* vel, double dt, const double box[3],
+                                 int64_t N, const double* ref, double thr2, int* need) {
+  hipLaunchKernelGGL(k_md_drift_track, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, vel, dt, box[0], box[1], box[2],
+                     N, ref, thr2, need);
+  return hipGetLastError();
 }
 
 hipError_t launch_md_kick(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,

@@ -11,6 +11,7 @@ namespace mhc {
 // that the 27 surrounding cells never repeat), each at least the cutoff wide.
 struct CellGrid {
   double box[3];
+  double ibox[3];   // 1 / box: the minimum-image shift multiplies instead of dividing
   int nc[3];
 };
 
@@ -31,16 +32,20 @@ struct NeighborBufs {
   int* flags;
 };
 
-// Bond lists of one configuration (the listed pairs inside R + D): nbr, rev
-// [max_b][N] (slot-major), n_nb [N], mask [N] (bit s: list slot s is a bond);
-// flags[0] = largest bond count found, flags[1] = 1 if an atom had more than
-// max_b, flags[2] = 1 if a reverse slot was missing.
+// Bond lists (the listed pairs inside R + D + delta, delta the bond lists'
+// own skin): nbr, rev [max_b][N] (slot-major), n_nb [N], mask [N] (bit s:
+// list slot s is kept), ref [N][3] (positions at their build); flags[0] =
+// largest count found, flags[1] = 1 if an atom had more than max_b, flags[2] =
+// 1 if a reverse slot was missing; need [2]: the rebuild flags of alternate
+// evaluations.
 struct BondBufs {
   int* nbr;
   int* rev;
   int* n_nb;
   unsigned long long* mask;
   int* flags;
+  double* ref;
+  int* need;
 };
 
 // Tersoff parameters as the kernels use them: l3m = lambda3^m, c2 = c^2, d2 = d^2,
@@ -56,6 +61,7 @@ struct TersoffArgs {
   const double* pos;
   int64_t N;
   double box[3];
+  double ibox[3];   // 1 / box
   const int* nbr;
   const int* n_nb;
   const int* rev;
@@ -83,12 +89,19 @@ hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const C
                             NeighborBufs b);
 // Zero n ints (n > 0).
 hipError_t launch_zero_i32(hipStream_t s, int* p, int n);
-// Bonds out of the lists (nbr, n_nb, with reverse slots rev): pairs with
-// squared distance below rb2, at most max_b per atom (max_nb <= 64), and
-// their reverse slots.  The flags accumulate over launches unless
-// reset_flags clears them first.
+// Bond lists out of the lists (nbr, n_nb, with reverse slots rev): every
+// pair closer than rb, at most max_b per atom (max_nb <= 64), and their
+// reverse slots.  The flags accumulate over launches unless reset_flags
+// clears them first.  need (null: always) makes the build conditional on
+// *need != 0, decided on the device; clear (null: none) is zeroed.
 hipError_t launch_bonds(hipStream_t s, const double* pos, int64_t N, const double box[3], const int* nbr,
-                        const int* n_nb, const int* rev, double rb2, int max_b, BondBufs b, bool reset_flags);
+                        const int* n_nb, const int* rev, double rb, int max_b, BondBufs b, bool reset_flags,
+                        const int* need, int* clear);
+hipError_t launch_set_i32(hipStream_t s, int* p, int value);
+// Drift that also sets *need = 1 when an atom is farther than sqrt(thr2) from
+// its position in ref.
+hipError_t launch_md_drift_track(hipStream_t s, double* pos, const double* vel, double dt, const double box[3],
+                                 int64_t N, const double* ref, double thr2, int* need);
 // Lanes per atom of the evaluation kernels for a largest neighbour count:
 // the next power of two, at least 4 (64 at most: max_nb <= 64).
 int tersoff_lanes(int max_count);

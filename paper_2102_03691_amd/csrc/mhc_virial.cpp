@@ -44,12 +44,16 @@ struct mhc_virial {
   NeighborBufs nb{};
   double *d_dd = nullptr, *d_U = nullptr;
   double* d_F = nullptr;  // forces of the molecular dynamics (mhc_virial_md)
-  // Bond lists of the molecular dynamics when the lists carry a skin: each
-  // step's pairs inside R + D, with max_b slots (the largest count at the
-  // last list build plus 2) and lpa_b lanes per atom (compact: fewer lanes
-  // than the lists need).  bb.flags[0..2] accumulate over one mhc_virial_md
-  // call; [4..6] serve the count at list builds.
+  // Bond lists of the molecular dynamics when the lists carry a skin: the
+  // pairs inside R + D + delta (delta = bond_skin, the smaller of the skin and
+  // 0.5 A), rebuilt on the device whenever an atom has moved more than
+  // delta / 2 since their last build (so they hold every pair inside R + D),
+  // with max_b slots (the largest count at the last list build plus 2) and
+  // lpa_b lanes per atom (compact: fewer lanes than the lists need).
+  // bb.flags[0..2] accumulate over one mhc_virial_md call; [4..6] serve the
+  // count at list builds; bb.need = flags + 8.
   BondBufs bb{};
+  double bond_skin = 0.0;
   int max_b = 0, lpa_b = 4;
   bool compact = false;
   int lpa = 4;            // lanes per atom of the evaluation kernels (from the largest neighbour count)
@@ -105,7 +109,8 @@ mhc_status plan_bonds(mhc_virial* v, const double* pos) {
   if (!(v->rc > (v->tp.R + v->tp.D) * (1.0 + 1e-9))) return MHC_OK;   // no skin: the lists are the bonds
   BondBufs pb = v->bb;
   pb.flags = v->bb.flags + 4;
-  VHIP_TRY(launch_bonds(v->stream, pos, v->N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev, rcut2_of(v), v->max_nb, pb, true),
+  VHIP_TRY(launch_bonds(v->stream, pos, v->N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev,
+                        v->tp.R + v->tp.D + v->bond_skin, v->max_nb, pb, true, nullptr, nullptr),
            "bonds");
   int f[3] = {0, 0, 0};
   VHIP_TRY(hipMemcpyAsync(f, pb.flags, sizeof(f), hipMemcpyDeviceToHost, v->stream), "read bond flags");
@@ -155,6 +160,7 @@ CellGrid make_grid(const double box[3], double rc, int64_t N) {
   CellGrid g{};
   for (int a = 0; a < 3; ++a) {
     g.box[a] = box[a];
+    g.ibox[a] = 1.0 / box[a];
     const double c = std::floor(box[a] / rc);
     int n = c > 1024.0 ? 1024 : (int)c;
     g.nc[a] = n < 3 ? 1 : n;
@@ -245,9 +251,10 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
             valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 2, &b.flags) &&
             valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U) && valloc(v, 3 * N, &v->d_F) &&
             valloc(v, MN, &v->bb.nbr) && valloc(v, MN, &v->bb.rev) && valloc(v, N, &v->bb.n_nb) &&
-            valloc(v, N, &v->bb.mask) &&
-            valloc(v, 8, &v->bb.flags);
+            valloc(v, N, &v->bb.mask) && valloc(v, 3 * N, &v->bb.ref) && valloc(v, 12, &v->bb.flags);
   if (!ok) return cleanup(MHC_ERR_OOM, "device allocation failed");
+  v->bb.need = v->bb.flags + 8;
+  v->bond_skin = std::min(rc - (p.R + p.D), 0.5);
   if (hipMemcpyAsync(v->d_mass, mass_amu, N * sizeof(double), hipMemcpyHostToDevice, v->stream) != hipSuccess ||
       hipStreamSynchronize(v->stream) != hipSuccess)
     return cleanup(MHC_ERR_HIP, "copy of the masses failed");
@@ -333,7 +340,7 @@ mhc_status mhc_virial_compute(mhc_virial* v, const double* pos, const double* ve
   TersoffArgs a{};
   a.pos = pos;
   a.N = v->N;
-  for (int q = 0; q < 3; ++q) a.box[q] = v->box[q];
+  for (int q = 0; q < 3; ++q) a.box[q] = v->box[q], a.ibox[q] = 1.0 / v->box[q];
   a.nbr = v->nb.nbr;
   a.n_nb = v->nb.n_nb;
   a.rev = v->nb.rev;
@@ -368,19 +375,28 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
   VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
   const int64_t N = v->N;
   bool any_compact = false;
+  // Evaluation e (0: the entry positions, s + 1: after step s) rebuilds the
+  // bond lists if need[e & 1] != 0, which the drift before it sets when an
+  // atom has moved more than half the bond lists' skin since their build.
+  const double half = 0.5 * v->bond_skin;
+  const double thr2 = half * half * (1.0 - 1e-9);
+  int64_t e_idx = 0;
   auto force = [&](float* w32) -> mhc_status {
     TersoffArgs a{};
     a.pos = pos;
     a.N = N;
-    for (int q = 0; q < 3; ++q) a.box[q] = v->box[q];
+    for (int q = 0; q < 3; ++q) a.box[q] = v->box[q], a.ibox[q] = 1.0 / v->box[q];
     a.nbr = v->nb.nbr;
     a.n_nb = v->nb.n_nb;
     a.rev = v->nb.rev;
     a.max_nb = v->max_nb;
     int lpa = v->lpa;
-    if (v->compact) {   // this configuration's bonds out of the skin lists
+    if (v->compact) {   // bond lists out of the skin lists, rebuilt when the atoms have moved enough
       any_compact = true;
-      VHIP_TRY(launch_bonds(v->stream, pos, N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev, rcut2_of(v), v->max_b, v->bb, false),
+      const int sl = (int)(e_idx & 1);
+      VHIP_TRY(launch_bonds(v->stream, pos, N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev,
+                            v->tp.R + v->tp.D + v->bond_skin, v->max_b, v->bb, false, v->bb.need + sl,
+                            v->bb.need + (sl ^ 1)),
                "bonds");
       a.nbr = v->bb.nbr;
       a.n_nb = v->bb.n_nb;
@@ -405,11 +421,21 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
   const double c = 0.5 * dt / KE_UNIT_EV;   // half kick: dv = dt/2 F / (m KE)
   // overflow and reverse-slot flags of the bond passes accumulate over this call's steps
   VHIP_TRY(launch_zero_i32(v->stream, v->bb.flags, 3), "clear bond flags");
+  VHIP_TRY(launch_set_i32(v->stream, v->bb.need, 1), "bond rebuild flag");   // the entry evaluation builds
   if ((st = force(nullptr))) return st;     // forces at the entry positions
   for (int32_t s = 0; s < n_steps; ++s) {
+    e_idx = s + 1;
     VHIP_TRY(launch_md_kick(v->stream, vel, v->d_F, v->d_mass, c, N, nullptr), "half kick");
-    VHIP_TRY(launch_md_drift(v->stream, pos, vel, dt, v->box, N), "drift");
-    if (rebuild > 0 && (s + 1) % rebuild == 0 && (st = mhc_virial_neighbors(v, pos, nullptr))) return st;
+    if (v->compact)
+      VHIP_TRY(launch_md_drift_track(v->stream, pos, vel, dt, v->box, N, v->bb.ref, thr2, v->bb.need + (e_idx & 1)),
+               "drift");
+    else
+      VHIP_TRY(launch_md_drift(v->stream, pos, vel, dt, v->box, N), "drift");
+    if (rebuild > 0 && (s + 1) % rebuild == 0) {
+      if ((st = mhc_virial_neighbors(v, pos, nullptr))) return st;
+      // new lists (and possibly new bond slots): the bond lists follow them
+      VHIP_TRY(launch_set_i32(v->stream, v->bb.need + (e_idx & 1), 1), "bond rebuild flag");
+    }
     if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr))) return st;
     VHIP_TRY(launch_md_kick(v->stream, vel, v->d_F, v->d_mass, c, N, v32 ? v32 + (int64_t)s * N * 3 : nullptr),
              "half kick");

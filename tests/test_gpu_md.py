@@ -5,7 +5,9 @@ oracle's integrator (oracle.virial.md_nve), through the C ABI:
     differ only by the summation order of the forces) and every step's
     float32 velocities and per-atom virials (the push inputs) within one
     float32 rounding of the oracle's, with the lists rebuilt every step, every
-    5 steps, or never (a skin covers the moves);
+    5 steps, or never (a skin covers the moves); bonds entering and leaving
+    R + D in a stretched crystal; the per-step bond lists' rebuild on
+    displacement in a hot liquid-like cell; the bond-slot overflow error;
   * total energy conserved over 400 steps of 512 atoms;
   * the device trajectory's float32 v and W pushed as one block into HNEMA +
     GKMA against the oracle's modal path on the oracle's trajectory;
@@ -70,6 +72,77 @@ def test_md_matches_oracle(rebuild, skin):
     dv = float(np.abs(got["vel"] - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max())
     e = {"dx_A": dx, "dv_rel": dv, "v32_ulps": _ulps(got["v32"], ref["vel"]), "W32_ulps": _ulps(got["W32"], ref["W"])}
     log(f"md64_rebuild{rebuild}_skin{skin}", **e)
+    assert dx <= 1e-11 and dv <= 1e-11
+    assert e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0
+
+
+def test_md_bonds_crossing_the_cutoff():
+    """A stretched crystal (a = 6.8 A: nearest neighbours at 2.94 A, inside the
+    switching region R - D .. R + D) whose bonds enter and leave R + D during
+    the run: the per-step bond lists (float32 test with a margin above its
+    error) must keep every pair with a nonzero cutoff function."""
+    announce("md bonds crossing R + D")
+    pos, box = synth.diamond((2, 2, 2), a=6.8, sigma=0.03, seed=23)
+    m = synth.masses(len(pos), "natural", 23)
+    vel = synth.thermal_velocities(m, 300.0, 24)
+    p = ov.tersoff_si()
+    r0 = np.linalg.norm(ov.min_image(pos[:, None, :] - pos[None, :, :], box), axis=-1)
+    near = (r0 > p["R"] + p["D"] - 0.05) & (r0 < p["R"] + p["D"] + 0.05)
+    assert near.sum() >= 8                      # pairs within 0.05 A of the cutoff at the start
+    n, dt = 20, 1.0
+    ref = ov.md_nve(pos, vel, m, box, p, dt, n)
+    v, got = _device_md(pos, box, m, vel, dt, n, 0, 1.0)
+    v.close()
+    dx = float(np.abs(ov.min_image(got["pos"] - ref["pos"][-1], box)).max())
+    dv = float(np.abs(got["vel"] - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max())
+    e = {"dx_A": dx, "dv_rel": dv, "v32_ulps": _ulps(got["v32"], ref["vel"]), "W32_ulps": _ulps(got["W32"], ref["W"])}
+    log("md64_stretched_cutoff", **e)
+    assert dx <= 1e-11 and dv <= 1e-11
+    assert e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0
+
+
+def _random_config(n, L, dmin, seed):
+    """n atoms placed uniformly at random in a cube of edge L, each at least
+    dmin from the others (a liquid-like spread of pair distances)."""
+    rng = np.random.default_rng(seed)
+    box = np.array([L, L, L])
+    pos = []
+    while len(pos) < n:
+        x = rng.uniform(0, L, 3)
+        if all(np.linalg.norm(ov.min_image(x - q, box)) >= dmin for q in pos):
+            pos.append(x)
+    return np.array(pos), box
+
+
+def test_md_bond_lists_rebuilt_on_displacement():
+    """The bond lists hold the pairs inside R + D + delta (delta = min(skin,
+    0.5 A)) at their build and are rebuilt on the device once an atom has moved
+    more than delta / 2.  In this hot liquid-like cell (64 atoms, 1500 K) a
+    pair farther than R + D + 0.5 A at the start comes inside R + D during the
+    run (checked on the oracle's trajectory), so the device matches the oracle
+    only if that rebuild happens; the skin lists themselves stay valid (no
+    atom moves half the 1.6 A skin)."""
+    announce("md bond lists rebuilt on displacement")
+    pos, box = _random_config(64, 10.9, 2.2, 8)
+    m = synth.masses(len(pos), "natural", 8)
+    vel = synth.thermal_velocities(m, 1500.0, 9)
+    p = ov.tersoff_si()
+    n, dt, skin = 20, 1.0, 1.6
+    ref = ov.md_nve(pos, vel, m, box, p, dt, n)
+    rc = p["R"] + p["D"]
+    r0 = np.linalg.norm(ov.min_image(pos[:, None] - pos[None], box), axis=-1)
+    crossing, moved = 0, 0.0
+    for x in ref["pos"]:
+        r = np.linalg.norm(ov.min_image(x[:, None] - x[None], box), axis=-1)
+        crossing += int(((r0 > rc + 0.5) & (r < rc)).sum())
+        moved = max(moved, float(np.linalg.norm(ov.min_image(x - pos, box), axis=1).max()))
+    assert crossing > 0 and moved < skin / 2
+    v, got = _device_md(pos, box, m, vel, dt, n, 0, skin, max_nb=48)
+    v.close()
+    dx = float(np.abs(ov.min_image(got["pos"] - ref["pos"][-1], box)).max())
+    dv = float(np.abs(got["vel"] - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max())
+    e = {"dx_A": dx, "dv_rel": dv, "v32_ulps": _ulps(got["v32"], ref["vel"]), "W32_ulps": _ulps(got["W32"], ref["W"])}
+    log("md64_liquid_bond_rebuild", **e)
     assert dx <= 1e-11 and dv <= 1e-11
     assert e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0
 
@@ -169,11 +242,12 @@ def test_md_errors():
 
 
 def test_md_bond_overflow_is_reported():
-    """With a skin the steps evaluate each configuration's bonds (pairs inside
-    R + D) with as many slots as the largest bond count at the last list build
-    plus two.  A centre atom whose seven list neighbours sit outside R + D at
-    the build and inside it at the step has more bonds than slots: the call
-    reports it instead of returning forces with bonds left out."""
+    """With a skin the steps evaluate bond lists (pairs inside R + D + delta,
+    delta = min(skin, 0.5 A)) with as many slots as their largest count at the
+    last list build plus two.  A centre atom whose seven list neighbours sit
+    beyond R + D + delta at the build and inside R + D at the step has more
+    bonds than slots: the call reports it instead of returning forces with
+    bonds left out."""
     import torch
     from paper_2102_03691_amd import MhcError, ModalVirial
     announce("md bond-slot overflow")
@@ -182,8 +256,8 @@ def test_md_bond_overflow_is_reported():
     box = np.array([20.0, 20.0, 20.0])
     c = box / 2
     p = ov.tersoff_si()
-    far = np.vstack([c, c + (p["R"] + p["D"] + 0.3) * dirs])     # no bonds at the list build
-    near = np.vstack([c, c + (p["R"] + p["D"] - 0.1) * dirs])    # 0.4 A later: seven bonds at the centre
+    far = np.vstack([c, c + (p["R"] + p["D"] + 0.9) * dirs])     # listed (rc = R + D + 1), no bonds
+    near = np.vstack([c, c + (p["R"] + p["D"] - 0.1) * dirs])    # seven bonds at the centre
     m = np.full(len(far), 28.0855)
     v = ModalVirial(m, box, p, max_neighbors=24, skin=1.0)
     v.neighbors(torch.as_tensor(far, device="cuda:0"))
