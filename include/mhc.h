@@ -564,11 +564,20 @@ mhc_status mhc_virial_synchronize(mhc_virial *v);
  * inputs of mhc_push / mhc_shc_push for that step, so n_steps MD steps fill
  * a block of n_steps steps.  The last forces go to F (device [N][3], NULL:
  * skip).  No thermostat and no driving force act (the HNEMD force of Eq. 12
- * is an output of mhc_virial_compute).  Queued on the stream, except that
- * every rebuild synchronizes.
+ * is an output of mhc_virial_compute).
+ * Lists built with a skin hold many pairs beyond R + D; the force kernels
+ * then run on bond lists instead: the listed pairs inside R + D + delta
+ * (delta = the smaller of the skin and 0.5 A) at their build, rebuilt on the
+ * device whenever an atom has moved more than delta / 2 since (so they hold
+ * every pair inside R + D), and at every list rebuild.  Their slots per atom
+ * are the largest count found at the last list build plus two; an atom with
+ * more makes the call fail with INVALID_ARG at its end, and the call's
+ * results are then not valid (rebuild the lists more often).
+ * Queued on the stream, except that every rebuild synchronizes, and so does
+ * the end of a call that used bond lists (to read their overflow flag).
  * Errors: INVALID_ARG (NULL pos or vel, n_steps or rebuild < 0, dt not finite
- * and positive, a rebuild finding too many neighbours), STATE (no valid
- * lists), HIP. */
+ * and positive, a rebuild finding too many neighbours, more bonds on an atom
+ * than bond slots), STATE (no valid lists), HIP. */
 mhc_status mhc_virial_md(mhc_virial *v, double *pos, double *vel, double dt, int32_t n_steps, int32_t rebuild,
                          float *v32, float *W32, double *F);
 

@@ -205,7 +205,8 @@ __global__ void __launch_bounds__(256) k_neighbors(const double* __restrict__ po
 }
 
 // rev[s][i] = slot of i in the list of j = nbr[s][i] (-1 if absent, which a
-// symmetric distance test rules out; the host checks).
+// symmetric distance test rules out; the host checks).  Lists are ascending
+// (k_neighbors sorts them), so the slot is found by bisection.
 __global__ void __launch_bounds__(256) k_reverse(int64_t N, const int* __restrict__ nbr, const int* __restrict__ n_nb,
                                                  int* __restrict__ rev, int* __restrict__ missing) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,10 +214,13 @@ __global__ void __launch_bounds__(256) k_reverse(int64_t N, const int* __restric
   const int n = n_nb[i];
   for (int s = 0; s < n; ++s) {
     const int j = nbr[(int64_t)s * N + i];
-    const int nj = n_nb[j];
-    int r = -1;
-    for (int t = 0; t < nj; ++t)
-      if (nbr[(int64_t)t * N + j] == (int)i) r = t;
+    int lo = 0, hi = n_nb[j];   // first slot of j's list whose entry is >= i
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (nbr[(int64_t)mid * N + j] < (int)i) lo = mid + 1;
+      else hi = mid;
+    }
+    const int r = lo < n_nb[j] && nbr[(int64_t)lo * N + j] == (int)i ? lo : -1;
     rev[(int64_t)s * N + i] = r;
     if (r < 0) *missing = 1;
   }
