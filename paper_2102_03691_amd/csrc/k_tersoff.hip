@@ -582,77 +582,69 @@ static hipError_t launch_pair_kernels(hipStream_t s, const TersoffArgs& a, const
 }
 
 // ------------------------------------------------ velocity Verlet (NVE)
-// One thread per atom component.  Half kick: v += c F / m with c = dt / (2 KE)
-// (a = F / (m KE) in A/fs^2); with v32 the kicked velocity is also stored in
-// float32 (the push's velocity input of the step).
-__global__ void __launch_bounds__(256) k_md_kick(double* __restrict__ vel, const double* __restrict__ F,
-                                                 const double* __restrict__ mass, double c, int64_t n3,
-                                                 float* __restrict__ v32) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n3) return;
-  const double v = vel[q] + c * F[q] / mass[q / 3];
-  vel[q] = v;
-  if (v32) v32[q] = (float)v;
-}
+// The work between two force evaluations.  With MD_KICK2: the second half kick of step s, v += c F / m with c = dt / (2 KE)
+// (a = F / (m KE) in A/fs^2), and, with v32, that velocity in float32 (the
+// push's velocity input of step s).  With MD_KICK1_DRIFT: the first half
+// kick of step s + 1 with the same forces, then the drift x += dt v, wrapped
+// into [0, L) per axis (x - floor(x / L) L, then one correction step against
+// rounding at the edges), and, with ref, the bond lists' displacement test:
+// *need = 1 if the atom is farther than sqrt(thr2) from ref (its position at
+// the last bond build).  Each operation is the one the separate kick and
+// drift would make, in the same order.
+enum { MD_KICK2 = 1, MD_KICK1_DRIFT = 2 };
 
-// Drift: x += dt v, wrapped into [0, L) per axis (x - floor(x / L) L, then
-// one correction step against rounding at the edges).
-__global__ void __launch_bounds__(256) k_md_drift(double* __restrict__ pos, const double* __restrict__ vel, double dt,
-                                                  double Lx, double Ly, double Lz, int64_t n3) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n3) return;
-  const int a = (int)(q % 3);
-  const double L = a == 0 ? Lx : (a == 1 ? Ly : Lz);
-  double x = pos[q] + dt * vel[q];
-  x -= floor(x / L) * L;
-  if (x >= L) x -= L;
-  if (x < 0.0) x += L;
-  pos[q] = x;
-}
+// One thread per atom component, 64 atoms (192 components, contiguous in
+// memory) per work-group; the displacement test sums each atom's three
+// squared components in LDS.
+constexpr int MD_ATOMS = 64;
 
-// The drift per atom, with the displacement test of the bond lists: need = 1
-// if any atom moved farther than sqrt(thr2) from ref (its position at the
-// last bond build).  Same arithmetic as k_md_drift.
-__global__ void __launch_bounds__(256) k_md_drift_track(double* __restrict__ pos, const double* __restrict__ vel,
-                                                        double dt, double Lx, double Ly, double Lz, int64_t N,
-                                                        const double* __restrict__ ref, double thr2,
-                                                        int* __restrict__ need) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+__global__ void __launch_bounds__(3 * MD_ATOMS) k_md_step(double* __restrict__ pos, double* __restrict__ vel,
+                                                          const double* __restrict__ F,
+                                                          const double* __restrict__ mass, double c, double dt,
+                                                          double Lx, double Ly, double Lz, int64_t N, int parts,
+                                                          float* __restrict__ v32, const double* __restrict__ ref,
+                                                          double thr2, int* __restrict__ need) {
+  __shared__ double sh[3 * MD_ATOMS];
+  const int t = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * (3 * MD_ATOMS) + t;
   double d2 = 0.0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double L = a == 0 ? Lx : (a == 1 ? Ly : Lz);
-    double x = pos[3 * i + a] + dt * vel[3 * i + a];
-    x -= floor(x / L) * L;
-    if (x >= L) x -= L;
-    if (x < 0.0) x += L;
-    pos[3 * i + a] = x;
-    double d = x - ref[3 * i + a];
-    d -= L * rint(d / L);
-    d2 += d * d;
+  if (q < 3 * N) {
+    const int a = (int)(q % 3);
+    const double m = mass[q / 3];
+    const double f = F[q];
+    double v = vel[q];
+    if (parts & MD_KICK2) {
+      v = v + c * f / m;
+      if (v32) v32[q] = (float)v;
+    }
+    if (parts & MD_KICK1_DRIFT) {
+      v = v + c * f / m;
+      const double L = a == 0 ? Lx : (a == 1 ? Ly : Lz);
+      double x = pos[q] + dt * v;
+      x -= floor(x / L) * L;
+      if (x >= L) x -= L;
+      if (x < 0.0) x += L;
+      pos[q] = x;
+      if (ref) {
+        double d = x - ref[q];
+        d -= L * rint(d / L);
+        d2 = d * d;
+      }
+    }
+    vel[q] = v;
   }
-  if (d2 > thr2) *need = 1;
+  if (!ref || !(parts & MD_KICK1_DRIFT)) return;   // uniform over the launch
+  sh[t] = d2;
+  __syncthreads();
+  if (t < MD_ATOMS && sh[3 * t] + sh[3 * t + 1] + sh[3 * t + 2] > thr2) *need = 1;
 }
 
-hipError_t launch_md_drift_track(hipStream_t s, double* pos, const double* vel, double dt, const double box[3],
-                                 int64_t N, const double* ref, double thr2, int* need) {
-  hipLaunchKernelGGL(k_md_drift_track, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, vel, dt, box[0], box[1], box[2],
-                     N, ref, thr2, need);
-  return hipGetLastError();
-}
-
-hipError_t launch_md_kick(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
-                          float* v32) {
-  const int64_t n3 = 3 * N;
-  hipLaunchKernelGGL(k_md_kick, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, vel, F, mass, c, n3, v32);
-  return hipGetLastError();
-}
-
-hipError_t launch_md_drift(hipStream_t s, double* pos, const double* vel, double dt, const double box[3], int64_t N) {
-  const int64_t n3 = 3 * N;
-  hipLaunchKernelGGL(k_md_drift, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, pos, vel, dt, box[0], box[1],
-                     box[2], n3);
+hipError_t launch_md_step(hipStream_t s, double* pos, double* vel, const double* F, const double* mass, double c,
+                          double dt, const double box[3], int64_t N, bool kick2, bool kick1_drift, float* v32,
+                          const double* ref, double thr2, int* need) {
+  const int parts = (kick2 ? MD_KICK2 : 0) | (kick1_drift ? MD_KICK1_DRIFT : 0);
+  hipLaunchKernelGGL(k_md_step, dim3(blocks_of(N, MD_ATOMS)), dim3(3 * MD_ATOMS), 0, s, pos, vel, F, mass, c, dt,
+                     box[0], box[1], box[2], N, parts, v32, ref, thr2, need);
   return hipGetLastError();
 }
 

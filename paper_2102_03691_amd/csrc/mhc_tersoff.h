@@ -98,10 +98,6 @@ hipError_t launch_bonds(hipStream_t s, const double* pos, int64_t N, const doubl
                         const int* n_nb, const int* rev, double rb, int max_b, BondBufs b, bool reset_flags,
                         const int* need, int* clear);
 hipError_t launch_set_i32(hipStream_t s, int* p, int value);
-// Drift that also sets *need = 1 when an atom is farther than sqrt(thr2) from
-// its position in ref.
-hipError_t launch_md_drift_track(hipStream_t s, double* pos, const double* vel, double dt, const double box[3],
-                                 int64_t N, const double* ref, double thr2, int* need);
 // Lanes per atom of the evaluation kernels for a largest neighbour count:
 // the next power of two, at least 4 (64 at most: max_nb <= 64).
 int tersoff_lanes(int max_count);
@@ -111,11 +107,14 @@ int tersoff_lanes(int max_count);
 hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o, int lpa,
                           hipEvent_t e0, hipEvent_t e1, hipEvent_t e2);
 
-// Velocity Verlet pieces on [N][3] float64 arrays: a half kick
-// vel += c F / mass (v32: the result also in float32, NULL to skip) and a
-// drift pos += dt vel wrapped into the box.
-hipError_t launch_md_kick(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
-                          float* v32);
-hipError_t launch_md_drift(hipStream_t s, double* pos, const double* vel, double dt, const double box[3], int64_t N);
+// Velocity Verlet between two force evaluations on [N][3] float64 arrays:
+// kick2 = the second half kick of a step, vel += c F / mass (v32: the result
+// also in float32, NULL to skip); kick1_drift = the first half kick of the
+// next step with the same F, then the drift pos += dt vel wrapped into the
+// box, and with ref (NULL: none) *need = 1 if an atom is farther than
+// sqrt(thr2) from its position in ref.
+hipError_t launch_md_step(hipStream_t s, double* pos, double* vel, const double* F, const double* mass, double c,
+                          double dt, const double box[3], int64_t N, bool kick2, bool kick1_drift, float* v32,
+                          const double* ref, double thr2, int* need);
 
 }  // namespace mhc

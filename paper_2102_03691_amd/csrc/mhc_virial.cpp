@@ -102,8 +102,9 @@ double rcut2_of(const mhc_virial* v) {
   return rc * rc;
 }
 
-// Largest bond count now (pairs inside R + D, from the current lists), read
-// back; sets the bond slots and lanes of the molecular dynamics.
+// Largest bond-list count now (pairs inside R + D + bond_skin, from the
+// current lists), read back; sets the bond slots and lanes of the molecular
+// dynamics, and whether it uses bond lists at all (only with fewer lanes).
 mhc_status plan_bonds(mhc_virial* v, const double* pos) {
   v->compact = false;
   if (!(v->rc > (v->tp.R + v->tp.D) * (1.0 + 1e-9))) return MHC_OK;   // no skin: the lists are the bonds
@@ -423,23 +424,30 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
   VHIP_TRY(launch_zero_i32(v->stream, v->bb.flags, 3), "clear bond flags");
   VHIP_TRY(launch_set_i32(v->stream, v->bb.need, 1), "bond rebuild flag");   // the entry evaluation builds
   if ((st = force(nullptr))) return st;     // forces at the entry positions
+  // kicks and drifts: before step s's force the first half kick and drift of
+  // step s (fused with the second half kick of step s - 1 from s = 1 on);
+  // after the last force its second half kick alone
+  auto kick_drift = [&](int32_t s) -> mhc_status {
+    e_idx = s + 1;   // the evaluation after this drift
+    const bool track = v->compact;
+    VHIP_TRY(launch_md_step(v->stream, pos, vel, v->d_F, v->d_mass, c, dt, v->box, N, s > 0, true,
+                            s > 0 && v32 ? v32 + (int64_t)(s - 1) * N * 3 : nullptr, track ? v->bb.ref : nullptr,
+                            thr2, v->bb.need + (e_idx & 1)),
+             "kick and drift");
+    return MHC_OK;
+  };
   for (int32_t s = 0; s < n_steps; ++s) {
-    e_idx = s + 1;
-    VHIP_TRY(launch_md_kick(v->stream, vel, v->d_F, v->d_mass, c, N, nullptr), "half kick");
-    if (v->compact)
-      VHIP_TRY(launch_md_drift_track(v->stream, pos, vel, dt, v->box, N, v->bb.ref, thr2, v->bb.need + (e_idx & 1)),
-               "drift");
-    else
-      VHIP_TRY(launch_md_drift(v->stream, pos, vel, dt, v->box, N), "drift");
+    if ((st = kick_drift(s))) return st;
     if (rebuild > 0 && (s + 1) % rebuild == 0) {
       if ((st = mhc_virial_neighbors(v, pos, nullptr))) return st;
       // new lists (and possibly new bond slots): the bond lists follow them
       VHIP_TRY(launch_set_i32(v->stream, v->bb.need + (e_idx & 1), 1), "bond rebuild flag");
     }
     if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr))) return st;
-    VHIP_TRY(launch_md_kick(v->stream, vel, v->d_F, v->d_mass, c, N, v32 ? v32 + (int64_t)s * N * 3 : nullptr),
-             "half kick");
   }
+  VHIP_TRY(launch_md_step(v->stream, pos, vel, v->d_F, v->d_mass, c, dt, v->box, N, true, false,
+                          v32 ? v32 + (int64_t)(n_steps - 1) * N * 3 : nullptr, nullptr, 0.0, nullptr),
+           "half kick");
   if (F) VHIP_TRY(hipMemcpyAsync(F, v->d_F, (size_t)N * 3 * 8, hipMemcpyDeviceToDevice, v->stream), "copy forces");
   if (any_compact) {
     int f[3] = {0, 0, 0};
