@@ -350,111 +350,131 @@ __device__ __forceinline__ void exp_fn(const TersoffParams& p, double x, double*
   *de = *e * p.m * p.l3m * xm1;
 }
 
-// LPA lanes per atom: lane s of the group handles the pair (i, j = nbr[s][i]).
-// Each lane publishes its pair values in LDS (field-major, sh[field][lane]);
-// the others read them after a barrier.
-template <int LPA>
+// LPA lanes per atom, SPL list slots per lane: lane s0 of the group handles
+// the pairs (i, j = nbr[s][i]) of the slots s = s0 + k LPA, k < SPL.  Each
+// pair's values go to LDS (field-major, sh[field][atom base + slot]) and
+// every lane reads them after a barrier.  All sums run over the slots in list
+// order, so the results do not depend on LPA and SPL.  With SPL = 2 a wave
+// whose atoms all have at most LPA pairs skips the second slot of every lane.
+template <int LPA, int SPL>
 __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffParams p) {
-  __shared__ double sh[8][256];
+  __shared__ double sh[8][256 * SPL];
   const int tid = threadIdx.x;
-  const int s = tid & (LPA - 1);
-  const int g0 = tid - s;
+  const int s0 = tid & (LPA - 1);
+  const int gb = (tid - s0) * SPL;   // this atom's slot 0 in LDS
   const int64_t N = a.N;
   const int64_t i = ((int64_t)blockIdx.x * 256 + tid) / LPA;
   const int n = i < N ? a.n_nb[i] : 0;
-  const bool act = s < n;
-  double x = 0.0, y = 0.0, z = 0.0, r = 1.0, ir = 1.0, fc = 0.0, dfc = 0.0, er = 0.0, ea = 0.0;
-  if (act) {
-    const int64_t j = a.nbr[(int64_t)s * N + i];
-    x = min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0], a.ibox[0]);
-    y = min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1], a.ibox[1]);
-    z = min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2], a.ibox[2]);
-    r = sqrt(x * x + y * y + z * z);
-    ir = 1.0 / r;
-    cutoff_fn(p, r, &fc, &dfc);
-    if (fc != 0.0) {                   // a pair beyond R + D (listed with a skin) needs neither
-      er = p.A * exp(-p.l1 * r);       // f_R
-      ea = p.B * exp(-p.l2 * r);       // f_A (the attractive term enters as -b f_A)
+  double x[SPL], y[SPL], z[SPL], r[SPL], ir[SPL], fc[SPL], dfc[SPL], er[SPL], ea[SPL];
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int s = s0 + k * LPA;
+    x[k] = y[k] = z[k] = 0.0;
+    r[k] = ir[k] = 1.0;
+    fc[k] = dfc[k] = er[k] = ea[k] = 0.0;
+    if (s < n) {
+      const int64_t j = a.nbr[(int64_t)s * N + i];
+      x[k] = min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0], a.ibox[0]);
+      y[k] = min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1], a.ibox[1]);
+      z[k] = min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2], a.ibox[2]);
+      r[k] = sqrt(x[k] * x[k] + y[k] * y[k] + z[k] * z[k]);
+      ir[k] = 1.0 / r[k];
+      cutoff_fn(p, r[k], &fc[k], &dfc[k]);
+      if (fc[k] != 0.0) {                    // a pair beyond R + D (listed with a skin) needs neither
+        er[k] = p.A * exp(-p.l1 * r[k]);     // f_R
+        ea[k] = p.B * exp(-p.l2 * r[k]);     // f_A (the attractive term enters as -b f_A)
+      }
     }
+    sh[0][gb + s] = x[k];
+    sh[1][gb + s] = y[k];
+    sh[2][gb + s] = z[k];
+    sh[3][gb + s] = r[k];
+    sh[4][gb + s] = ir[k];
+    sh[5][gb + s] = fc[k];
   }
-  sh[0][tid] = x;
-  sh[1][tid] = y;
-  sh[2][tid] = z;
-  sh[3][tid] = r;
-  sh[4][tid] = ir;
-  sh[5][tid] = fc;
   __syncthreads();
   // Listed pairs beyond R + D (f_C = 0: lists built with a skin) add exact
   // zeros to every sum below, so they are skipped, and such a pair's own
-  // lane has nothing to compute (its energy, bracket weight and partials are
+  // slot has nothing to compute (its energy, bracket weight and partials are
   // zero).
-  const bool bond = act && fc != 0.0;
-  double b = 1.0, adb = 0.0, u = 0.0;
-  if (bond) {
-    double zeta = 0.0;
-    for (int q = 0; q < n; ++q) {
-      if (q == s || sh[5][g0 + q] == 0.0) continue;
-      const int l = g0 + q;
-      const double cs = (x * sh[0][l] + y * sh[1][l] + z * sh[2][l]) * ir * sh[4][l];
-      double g, dg, e, de;
-      angle_fn(p, cs, &g, &dg);
-      exp_fn(p, r - sh[3][l], &e, &de);
-      zeta += sh[5][l] * g * e;
+  double b[SPL], adb[SPL];
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int s = s0 + k * LPA;
+    b[k] = 1.0;
+    adb[k] = 0.0;
+    double u = 0.0;
+    if (s < n && fc[k] != 0.0) {
+      double zeta = 0.0;
+      for (int q = 0; q < n; ++q) {
+        if (q == s || sh[5][gb + q] == 0.0) continue;
+        const int l = gb + q;
+        const double cs = (x[k] * sh[0][l] + y[k] * sh[1][l] + z[k] * sh[2][l]) * ir[k] * sh[4][l];
+        double g, dg, e, de;
+        angle_fn(p, cs, &g, &dg);
+        exp_fn(p, r[k] - sh[3][l], &e, &de);
+        zeta += sh[5][l] * g * e;
+      }
+      // (beta zeta)^n and (1 + bz)^(-1/(2n)) through exp and log (zeta = 0 gives bz = 0)
+      const double bz = exp(p.n * log(p.beta * zeta));
+      b[k] = exp(-0.5 / p.n * log1p(bz));
+      // db/dzeta = -1/2 beta^n zeta^(n-1) (1 + (beta zeta)^n)^(-1/(2n) - 1) = -b bz / (2 zeta (1 + bz))
+      const double db = zeta == 0.0 ? 0.0 : -0.5 * b[k] * bz / (zeta * (1.0 + bz));
+      adb[k] = fc[k] * ea[k] * db;
+      u = fc[k] * (er[k] - b[k] * ea[k]);
     }
-    // (beta zeta)^n and (1 + bz)^(-1/(2n)) through exp and log (zeta = 0 gives bz = 0)
-    const double bz = exp(p.n * log(p.beta * zeta));
-    b = exp(-0.5 / p.n * log1p(bz));
-    // db/dzeta = -1/2 beta^n zeta^(n-1) (1 + (beta zeta)^n)^(-1/(2n) - 1) = -b bz / (2 zeta (1 + bz))
-    const double db = zeta == 0.0 ? 0.0 : -0.5 * b * bz / (zeta * (1.0 + bz));
-    adb = fc * ea * db;
-    u = fc * (er - b * ea);
+    sh[6][gb + s] = adb[k];
+    sh[7][gb + s] = u;
   }
-  sh[6][tid] = adb;
-  sh[7][tid] = u;
   __syncthreads();
-  if (i < N && s == 0) {
+  if (i < N && s0 == 0) {
     double acc = 0.0;
-    for (int q = 0; q < n; ++q) acc += sh[7][g0 + q];
+    for (int q = 0; q < n; ++q) acc += sh[7][gb + q];
     a.U[i] = 0.5 * acc;
   }
-  if (!act) return;
-  const int64_t mn = (int64_t)a.max_nb * N, es = (int64_t)s * N + i;
-  if (!bond) {
-    a.dd[es] = 0.0;
-    a.dd[mn + es] = 0.0;
-    a.dd[2 * mn + es] = 0.0;
-    return;
+  const int64_t mn = (int64_t)a.max_nb * N;
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int s = s0 + k * LPA;
+    if (s >= n) continue;
+    const int64_t es = (int64_t)s * N + i;
+    if (fc[k] == 0.0) {
+      a.dd[es] = 0.0;
+      a.dd[mn + es] = 0.0;
+      a.dd[2 * mn + es] = 0.0;
+      continue;
+    }
+    // dU_i/dr_ij for this slot's pair j
+    const double ux = x[k] * ir[k], uy = y[k] * ir[k], uz = z[k] * ir[k];
+    const double radial = 0.5 * (dfc[k] * (er[k] - b[k] * ea[k]) + fc[k] * (-p.l1 * er[k] + p.l2 * b[k] * ea[k]));
+    double zx = 0.0, zy = 0.0, zz = 0.0;   // d zeta_ij / d r_ij
+    double kx = 0.0, ky = 0.0, kz = 0.0;   // sum_{k != j} a_ik db_ik d zeta_ik / d r_ij
+    for (int q = 0; q < n; ++q) {
+      if (q == s || sh[5][gb + q] == 0.0) continue;
+      const int l = gb + q;
+      const double qx = sh[0][l], qy = sh[1][l], qz = sh[2][l], rq = sh[3][l], irq = sh[4][l];
+      const double cs = (x[k] * qx + y[k] * qy + z[k] * qz) * ir[k] * irq;
+      // d cos theta / d r_ij
+      const double cx = qx * ir[k] * irq - cs * x[k] * ir[k] * ir[k];
+      const double cy = qy * ir[k] * irq - cs * y[k] * ir[k] * ir[k];
+      const double cz = qz * ir[k] * irq - cs * z[k] * ir[k] * ir[k];
+      double g, dg, e1, de1, e2, de2;
+      angle_fn(p, cs, &g, &dg);
+      exp_fn(p, r[k] - rq, &e1, &de1);
+      exp_fn(p, rq - r[k], &e2, &de2);
+      const double fcq = sh[5][l];
+      zx += fcq * (dg * cx * e1 + g * de1 * ux);
+      zy += fcq * (dg * cy * e1 + g * de1 * uy);
+      zz += fcq * (dg * cz * e1 + g * de1 * uz);
+      const double w = sh[6][l];
+      kx += w * (dfc[k] * g * e2 * ux + fc[k] * dg * cx * e2 - fc[k] * g * de2 * ux);
+      ky += w * (dfc[k] * g * e2 * uy + fc[k] * dg * cy * e2 - fc[k] * g * de2 * uy);
+      kz += w * (dfc[k] * g * e2 * uz + fc[k] * dg * cz * e2 - fc[k] * g * de2 * uz);
+    }
+    a.dd[es] = radial * ux - 0.5 * (adb[k] * zx + kx);
+    a.dd[mn + es] = radial * uy - 0.5 * (adb[k] * zy + ky);
+    a.dd[2 * mn + es] = radial * uz - 0.5 * (adb[k] * zz + kz);
   }
-  // dU_i/dr_ij for this lane's pair j
-  const double ux = x * ir, uy = y * ir, uz = z * ir;
-  const double radial = 0.5 * (dfc * (er - b * ea) + fc * (-p.l1 * er + p.l2 * b * ea));
-  double zx = 0.0, zy = 0.0, zz = 0.0;   // d zeta_ij / d r_ij
-  double kx = 0.0, ky = 0.0, kz = 0.0;   // sum_{k != j} a_ik db_ik d zeta_ik / d r_ij
-  for (int q = 0; q < n; ++q) {
-    if (q == s || sh[5][g0 + q] == 0.0) continue;
-    const int l = g0 + q;
-    const double qx = sh[0][l], qy = sh[1][l], qz = sh[2][l], rq = sh[3][l], irq = sh[4][l];
-    const double cs = (x * qx + y * qy + z * qz) * ir * irq;
-    // d cos theta / d r_ij
-    const double cx = qx * ir * irq - cs * x * ir * ir;
-    const double cy = qy * ir * irq - cs * y * ir * ir;
-    const double cz = qz * ir * irq - cs * z * ir * ir;
-    double g, dg, e1, de1, e2, de2;
-    angle_fn(p, cs, &g, &dg);
-    exp_fn(p, r - rq, &e1, &de1);
-    exp_fn(p, rq - r, &e2, &de2);
-    const double fcq = sh[5][l];
-    zx += fcq * (dg * cx * e1 + g * de1 * ux);
-    zy += fcq * (dg * cy * e1 + g * de1 * uy);
-    zz += fcq * (dg * cz * e1 + g * de1 * uz);
-    const double w = sh[6][l];
-    kx += w * (dfc * g * e2 * ux + fc * dg * cx * e2 - fc * g * de2 * ux);
-    ky += w * (dfc * g * e2 * uy + fc * dg * cy * e2 - fc * g * de2 * uy);
-    kz += w * (dfc * g * e2 * uz + fc * dg * cz * e2 - fc * g * de2 * uz);
-  }
-  a.dd[es] = radial * ux - 0.5 * (adb * zx + kx);
-  a.dd[mn + es] = radial * uy - 0.5 * (adb * zy + ky);
-  a.dd[2 * mn + es] = radial * uz - 0.5 * (adb * zz + kz);
 }
 
 // Per pair: dU_i/dr_ij - dU_j/dr_ji (Eq. 4) and r_ij (x) dU_j/dr_ji (Eq. 8);
@@ -571,13 +591,15 @@ hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const C
 template <int LPA>
 static hipError_t launch_pair_kernels(hipStream_t s, const TersoffArgs& a, const TersoffParams& p, const GatherArgs& o,
                                       hipEvent_t e1) {
-  const unsigned grid = blocks_of(a.N * LPA, 256);
-  hipLaunchKernelGGL(k_tersoff_site<LPA>, dim3(grid), dim3(256), 0, s, a, p);
+  // the site kernel for 5..8 pairs: 4 lanes x 2 slots (most atoms of a
+  // crystal have 4 bonds, so most waves run one slot round)
+  constexpr int SL = LPA == 8 ? 4 : LPA, SPL = LPA / SL;
+  hipLaunchKernelGGL((k_tersoff_site<SL, SPL>), dim3(blocks_of(a.N * SL, 256)), dim3(256), 0, s, a, p);
   if (e1) {
     hipError_t e = hipEventRecord(e1, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_tersoff_gather<LPA>, dim3(grid), dim3(256), 0, s, a, o);
+  hipLaunchKernelGGL(k_tersoff_gather<LPA>, dim3(blocks_of(a.N * LPA, 256)), dim3(256), 0, s, a, o);
   return hipSuccess;
 }
 

@@ -8,7 +8,8 @@ through the C ABI:
     rounding of the oracle's W;
   * the displaced crystal, the expanded crystal whose bonds sit inside the
     cutoff's switching shell, the exponential term switched on (m = 3 and 1),
-    a non-cubic box, lists built with a skin (extra pairs contribute zero),
+    a non-cubic box, a liquid-like cell with 2 to 8 bonds per atom, lists
+    built with a skin (extra pairs contribute zero),
     the paper's 8000-atom Si at full size; bitwise repeatability; the
     neighbour-overflow error;
   * the float32 W fed to the modal-current push on the device, against the
@@ -97,6 +98,35 @@ def test_virial_matches_oracle(tag, cells, a, sigma, pk):
     _compare(tag, got, ref)
     # the per-atom tensors are not symmetric (many-body), their sum is
     assert np.abs(got["W"] - got["W"].transpose(0, 2, 1)).max() > 1e-2 * np.abs(got["W"]).max()
+
+
+def test_liquid_like_cell_five_to_eight_bonds():
+    """64 atoms at random (at least 2.2 A apart) in a 10.9 A cube: 2 to 8 pairs
+    inside R + D per atom, 43 atoms with more than 4, so the site kernel runs
+    4 lanes x 2 slots per atom with the second slot round active in some waves
+    and not in others (the sums keep the list order: results as with one slot
+    per lane)."""
+    announce("virial liquid-like cell, 5-8 bonds")
+    rng = np.random.default_rng(1)
+    box = np.array([10.9, 10.9, 10.9])
+    pos = []
+    while len(pos) < 64:
+        x = rng.uniform(0.0, 10.9, 3)
+        if all(np.linalg.norm(ov.min_image(x - q, box)) >= 2.2 for q in pos):
+            pos.append(x)
+    pos = np.array(pos)
+    p = _params("exp3")
+    m = synth.masses(len(pos), "natural", 3)
+    vel = synth.thermal_velocities(m, 300.0, 7)
+    fe = np.array([1e-4, 2e-4, -1e-4])
+    ref = ov.evaluate(pos, box, vel, m, fe, p)
+    want_c = np.array([len(x) for x in ref["nl"]])
+    assert want_c.min() >= 2 and want_c.max() == 8 and (want_c > 4).sum() >= 40
+    outs, counts, _ = _device(pos, box, m, vel, fe, p, runs=2)
+    np.testing.assert_array_equal(counts, want_c)
+    _compare("liquid64", outs[0], ref)
+    for k in outs[0]:
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
 
 
 def test_skin_lists_give_the_same_results():
