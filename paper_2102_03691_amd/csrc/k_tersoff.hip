@@ -17,8 +17,9 @@
 //     the result does not depend on the order the atomics filled the cells),
 //     reverse slots (where i sits in j's list);
 //   per evaluation, LPA lanes per atom (one per neighbour slot, LPA the
-//     next power of two >= the largest neighbour count, at least 4), the
-//     pair values of an atom shared through LDS:
+//     next power of two >= the largest neighbour count, at least 4; the site
+//     kernel runs 4 lanes x 2 slots where LPA is 8), the pair values of an
+//     atom shared through LDS:
 //     k_tersoff_site -- pair vector, f_C, the two exponentials, zeta_ij,
 //       b_ij, db_ij/dzeta_ij; U_i (summed in slot order by the first lane);
 //       the partial dU_i/dr_ij of the lane's pair;
