@@ -149,33 +149,59 @@ __global__ void __launch_bounds__(256) k_cell_fill(int64_t N, const int* __restr
 }
 
 // The list of atom i; returns the number of atoms found inside rc (which may
-// exceed max_nb: only max_nb are kept).
+// exceed max_nb: only max_nb are kept) and, in *n_b, the number inside rb
+// (rb2 = rb^2; the bond lists' cutoff).
 __device__ int neighbors_of(int64_t i, const double* __restrict__ pos, int64_t N, const CellGrid& cg, double rc2,
-                            const int* __restrict__ cell_of, const int* __restrict__ start,
+                            double rb2, const int* __restrict__ cell_of, const int* __restrict__ start,
                             const int* __restrict__ atoms, int max_nb, int* __restrict__ nbr,
-                            int* __restrict__ n_nb) {
+                            int* __restrict__ n_nb, int* n_b) {
   const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
   const int c = cell_of[i];
   const int cz0 = c % cg.nc[2], cy0 = (c / cg.nc[2]) % cg.nc[1], cx0 = c / (cg.nc[2] * cg.nc[1]);
   const int ox = cg.nc[0] >= 3 ? 1 : 0, oy = cg.nc[1] >= 3 ? 1 : 0, oz = cg.nc[2] >= 3 ? 1 : 0;
-  int cnt = 0;
+  int cnt = 0, cb = 0;
+  // the atoms of atoms[q0 .. q1), 8 at a time with every load issued before
+  // the first distance (the padding reads atom i itself, which is skipped)
+  auto scan = [&](int q0, int q1) {
+    constexpr int U = 8;
+    for (int qb = q0; qb < q1; qb += U) {
+      int jj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) jj[u] = qb + u < q1 ? atoms[qb + u] : (int)i;
+      double px[U], py[U], pz[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        px[u] = pos[3 * (int64_t)jj[u]];
+        py[u] = pos[3 * (int64_t)jj[u] + 1];
+        pz[u] = pos[3 * (int64_t)jj[u] + 2];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (jj[u] == (int)i) continue;
+        const double ddx = min_image(px[u] - xi, cg.box[0], cg.ibox[0]);
+        const double ddy = min_image(py[u] - yi, cg.box[1], cg.ibox[1]);
+        const double ddz = min_image(pz[u] - zi, cg.box[2], cg.ibox[2]);
+        const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+        if (d2 < rc2) {
+          if (cnt < max_nb) nbr[(int64_t)cnt * N + i] = jj[u];
+          ++cnt;
+          if (d2 < rb2) ++cb;
+        }
+      }
+    }
+  };
   for (int dx = -ox; dx <= ox; ++dx) {
     const int cx = (cx0 + dx + cg.nc[0]) % cg.nc[0];
     for (int dy = -oy; dy <= oy; ++dy) {
       const int cy = (cy0 + dy + cg.nc[1]) % cg.nc[1];
-      for (int dz = -oz; dz <= oz; ++dz) {
-        const int cz = (cz0 + dz + cg.nc[2]) % cg.nc[2];
-        const int cc = (cx * cg.nc[1] + cy) * cg.nc[2] + cz;
-        for (int q = start[cc]; q < start[cc + 1]; ++q) {
-          const int j = atoms[q];
-          if (j == (int)i) continue;
-          const double ddx = min_image(pos[3 * (int64_t)j] - xi, cg.box[0], cg.ibox[0]);
-          const double ddy = min_image(pos[3 * (int64_t)j + 1] - yi, cg.box[1], cg.ibox[1]);
-          const double ddz = min_image(pos[3 * (int64_t)j + 2] - zi, cg.box[2], cg.ibox[2]);
-          if (ddx * ddx + ddy * ddy + ddz * ddz < rc2) {
-            if (cnt < max_nb) nbr[(int64_t)cnt * N + i] = j;
-            ++cnt;
-          }
+      const int row = (cx * cg.nc[1] + cy) * cg.nc[2];
+      if (oz == 1 && cz0 >= 1 && cz0 + 1 < cg.nc[2]) {
+        // the three cells along z are consecutive, and so are their atoms
+        scan(start[row + cz0 - 1], start[row + cz0 + 2]);
+      } else {
+        for (int dz = -oz; dz <= oz; ++dz) {
+          const int cz = (cz0 + dz + cg.nc[2]) % cg.nc[2];
+          scan(start[row + cz], start[row + cz + 1]);
         }
       }
     }
@@ -192,17 +218,21 @@ __device__ int neighbors_of(int64_t i, const double* __restrict__ pos, int64_t N
     nbr[(int64_t)(b + 1) * N + i] = key;
   }
   n_nb[i] = n;
+  *n_b = cb;
   return cnt;
 }
 
+// flags[0] = largest count inside rc, flags[2] = largest count inside rb.
 __global__ void __launch_bounds__(256) k_neighbors(const double* __restrict__ pos, int64_t N, CellGrid cg,
-                                                   double rc2, const int* __restrict__ cell_of,
+                                                   double rc2, double rb2, const int* __restrict__ cell_of,
                                                    const int* __restrict__ start, const int* __restrict__ atoms,
                                                    int max_nb, int* __restrict__ nbr, int* __restrict__ n_nb,
-                                                   int* __restrict__ max_found) {
+                                                   int* __restrict__ flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int cnt = i < N ? neighbors_of(i, pos, N, cg, rc2, cell_of, start, atoms, max_nb, nbr, n_nb) : 0;
-  wave_atomic_max(max_found, cnt);
+  int cb = 0;
+  const int cnt = i < N ? neighbors_of(i, pos, N, cg, rc2, rb2, cell_of, start, atoms, max_nb, nbr, n_nb, &cb) : 0;
+  wave_atomic_max(&flags[0], cnt);
+  wave_atomic_max(&flags[2], cb);
 }
 
 // rev[s][i] = slot of i in the list of j = nbr[s][i] (-1 if absent, which a
@@ -568,14 +598,14 @@ hipError_t launch_set_i32(hipStream_t s, int* p, int value) {
   return hipGetLastError();
 }
 
-hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, int max_nb,
-                            NeighborBufs b) {
+hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, double rb,
+                            int max_nb, NeighborBufs b) {
   const int n_cells = cg.nc[0] * cg.nc[1] * cg.nc[2];
   const int n_tiles = (n_cells + SCAN_TILE - 1) / SCAN_TILE;
   hipError_t e;
   hipLaunchKernelGGL(k_fill_zero_i32, dim3(blocks_of(n_cells, 256)), dim3(256), 0, s, b.count, n_cells);
   hipLaunchKernelGGL(k_fill_zero_i32, dim3(blocks_of(n_cells, 256)), dim3(256), 0, s, b.fill, n_cells);
-  hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b.flags, 2);
+  hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b.flags, 3);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cell_count, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, cg, b.cell_of, b.count);
   hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)n_tiles), dim3(SCAN_TILE), 0, s, b.count, n_cells, b.tile_sums);
@@ -583,8 +613,8 @@ hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const C
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)n_tiles), dim3(SCAN_TILE), 0, s, b.count, n_cells, b.tile_sums,
                      b.start);
   hipLaunchKernelGGL(k_cell_fill, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, b.cell_of, b.start, b.fill, b.atoms);
-  hipLaunchKernelGGL(k_neighbors, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, cg, rc * rc, b.cell_of, b.start,
-                     b.atoms, max_nb, b.nbr, b.n_nb, b.flags);
+  hipLaunchKernelGGL(k_neighbors, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, cg, rc * rc,
+                     rb * rb * (1.0 + 1e-12), b.cell_of, b.start, b.atoms, max_nb, b.nbr, b.n_nb, b.flags);
   hipLaunchKernelGGL(k_reverse, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, b.nbr, b.n_nb, b.rev, b.flags + 1);
   return hipGetLastError();
 }

@@ -18,7 +18,8 @@ struct CellGrid {
 // Device buffers of the neighbour lists: nbr, rev [max_nb][N] (slot-major),
 // n_nb [N]; cell_of [N], atoms [N]; count, fill [n_cells], start [n_cells + 1];
 // tile_sums [ceil(n_cells / 1024)] (scan workspace); flags[0] = largest
-// neighbour count found, flags[1] = 1 if a reverse slot was missing.
+// neighbour count found, flags[1] = 1 if a reverse slot was missing,
+// flags[2] = largest count inside the bond lists' cutoff.
 struct NeighborBufs {
   int* nbr;
   int* rev;
@@ -85,8 +86,10 @@ struct GatherArgs {
   double* Fext;
 };
 
-hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, int max_nb,
-                            NeighborBufs b);
+// Lists of the pairs closer than rc; also counts, per atom, those closer
+// than rb (flags[2]: the largest such count).
+hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const CellGrid& cg, double rc, double rb,
+                            int max_nb, NeighborBufs b);
 // Zero n ints (n > 0).
 hipError_t launch_zero_i32(hipStream_t s, int* p, int n);
 // Bond lists out of the lists (nbr, n_nb, with reverse slots rev): every

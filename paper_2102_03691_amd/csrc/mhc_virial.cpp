@@ -50,8 +50,7 @@ struct mhc_virial {
   // delta / 2 since their last build (so they hold every pair inside R + D),
   // with max_b slots (the largest count at the last list build plus 2) and
   // lpa_b lanes per atom (compact: fewer lanes than the lists need).
-  // bb.flags[0..2] accumulate over one mhc_virial_md call; [4..6] serve the
-  // count at list builds; bb.need = flags + 8.
+  // bb.flags[0..2] accumulate over one mhc_virial_md call; bb.need = flags + 8.
   BondBufs bb{};
   double bond_skin = 0.0;
   int max_b = 0, lpa_b = 4;
@@ -102,24 +101,15 @@ double rcut2_of(const mhc_virial* v) {
   return rc * rc;
 }
 
-// Largest bond-list count now (pairs inside R + D + bond_skin, from the
-// current lists), read back; sets the bond slots and lanes of the molecular
-// dynamics, and whether it uses bond lists at all (only with fewer lanes).
-mhc_status plan_bonds(mhc_virial* v, const double* pos) {
+// Bond slots and lanes of the molecular dynamics from the largest count of
+// pairs inside R + D + bond_skin at the list build (found), and whether it
+// uses bond lists at all (only with skin lists, and with fewer lanes).
+void plan_bonds(mhc_virial* v, int found) {
   v->compact = false;
-  if (!(v->rc > (v->tp.R + v->tp.D) * (1.0 + 1e-9))) return MHC_OK;   // no skin: the lists are the bonds
-  BondBufs pb = v->bb;
-  pb.flags = v->bb.flags + 4;
-  VHIP_TRY(launch_bonds(v->stream, pos, v->N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev,
-                        v->tp.R + v->tp.D + v->bond_skin, v->max_nb, pb, true, nullptr, nullptr),
-           "bonds");
-  int f[3] = {0, 0, 0};
-  VHIP_TRY(hipMemcpyAsync(f, pb.flags, sizeof(f), hipMemcpyDeviceToHost, v->stream), "read bond flags");
-  VHIP_TRY(hipStreamSynchronize(v->stream), "bonds sync");
-  v->max_b = std::min(v->max_nb, f[0] + 2);
+  if (!(v->rc > (v->tp.R + v->tp.D) * (1.0 + 1e-9))) return;   // no skin: the lists are the bonds
+  v->max_b = std::min(v->max_nb, found + 2);
   v->lpa_b = tersoff_lanes(v->max_b);
   v->compact = v->lpa_b < v->lpa;
-  return MHC_OK;
 }
 
 mhc_status venter(mhc_virial* v) {
@@ -249,7 +239,7 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
   bool ok = valloc(v, N, &v->d_mass) && valloc(v, MN, &b.nbr) && valloc(v, MN, &b.rev) && valloc(v, N, &b.n_nb) &&
             valloc(v, N, &b.cell_of) && valloc(v, N, &b.atoms) && valloc(v, n_cells, &b.count) &&
             valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) &&
-            valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 2, &b.flags) &&
+            valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 3, &b.flags) &&
             valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U) && valloc(v, 3 * N, &v->d_F) &&
             valloc(v, MN, &v->bb.nbr) && valloc(v, MN, &v->bb.rev) && valloc(v, N, &v->bb.n_nb) &&
             valloc(v, N, &v->bb.mask) && valloc(v, 3 * N, &v->bb.ref) && valloc(v, 12, &v->bb.flags);
@@ -285,8 +275,9 @@ mhc_status mhc_virial_neighbors(mhc_virial* v, const double* pos, int32_t* max_f
   if (!pos) return vfail(v, MHC_ERR_INVALID_ARG, "NULL positions");
   VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
   v->lists_ok = false;
-  VHIP_TRY(launch_neighbors(v->stream, pos, v->N, v->cg, v->rc, v->max_nb, v->nb), "neighbour search");
-  int flags[2] = {0, 0};
+  VHIP_TRY(launch_neighbors(v->stream, pos, v->N, v->cg, v->rc, v->tp.R + v->tp.D + v->bond_skin, v->max_nb, v->nb),
+           "neighbour search");
+  int flags[3] = {0, 0, 0};
   VHIP_TRY(hipMemcpyAsync(flags, v->nb.flags, sizeof(flags), hipMemcpyDeviceToHost, v->stream), "read flags");
   VHIP_TRY(hipStreamSynchronize(v->stream), "neighbour search sync");
   if (max_found) *max_found = flags[0];
@@ -297,7 +288,8 @@ mhc_status mhc_virial_neighbors(mhc_virial* v, const double* pos, int32_t* max_f
   if (flags[1]) return vfail(v, MHC_ERR_INVALID_ARG, "neighbour lists are not symmetric (non-finite positions?)");
   v->lpa = tersoff_lanes(flags[0]);
   v->lists_ok = true;
-  return plan_bonds(v, pos);
+  plan_bonds(v, flags[2]);
+  return MHC_OK;
 }
 
 mhc_status mhc_virial_read_neighbors(mhc_virial* v, int32_t* counts, int32_t* lists) {
