@@ -318,34 +318,6 @@ __global__ void __launch_bounds__(256) k_bonds(const double* __restrict__ pos, i
   if (found > max_b) flags[1] = 1;
 }
 
-// Reverse slots of the bond lists from those of the full lists: bond c of i
-// sits at list slot s, which is slot t = rev[s][i] in the list of j; its bond
-// slot in j's bond list is the number of j's bonds at list slots below t.
-// flags[2] = 1 if the pair is not a bond of j (asymmetric test) or has no
-// reverse slot.
-__global__ void __launch_bounds__(256) k_bond_reverse(int64_t N, const int* __restrict__ nbr,
-                                                      const int* __restrict__ rev,
-                                                      const unsigned long long* __restrict__ mask, int max_b,
-                                                      int* __restrict__ brev, int* __restrict__ flags,
-                                                      const int* __restrict__ need) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N || (need && *need == 0)) return;
-  unsigned long long m = mask[i];
-  for (int c = 0; m != 0 && c < max_b; ++c) {
-    const int s = __builtin_ctzll(m);
-    m &= m - 1;
-    const int j = nbr[(int64_t)s * N + i];
-    const int t = rev[(int64_t)s * N + i];
-    int r = -1;
-    if (t >= 0) {
-      const unsigned long long mj = mask[j];
-      if ((mj >> t) & 1ull) r = __builtin_popcountll(mj & ((1ull << t) - 1ull));
-    }
-    brev[(int64_t)c * N + i] = r;
-    if (r < 0) flags[2] = 1;
-  }
-}
-
 // --------------------------------------------------------------- potential
 __device__ __forceinline__ void cutoff_fn(const TersoffParams& p, double r, double* fc, double* dfc) {
   if (r < p.R - p.D) {
@@ -396,6 +368,30 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
   const int64_t N = a.N;
   const int64_t i = ((int64_t)blockIdx.x * 256 + tid) / LPA;
   const int n = i < N ? a.n_nb[i] : 0;
+  if (a.bond_need && *a.bond_need && n > 0) {
+    // reverse slots of freshly built bond lists: bond s of i sits at the
+    // s-th kept slot f of i's skin list, which is slot t = full_rev[f][i] in
+    // the list of j; its bond slot in j's list is the number of j's kept
+    // slots below t
+    const unsigned long long mi = a.bond_mask[i];
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+      const int s = s0 + k * LPA;
+      if (s >= n) continue;
+      unsigned long long m = mi;
+      for (int c = 0; c < s; ++c) m &= m - 1;
+      const int f = __builtin_ctzll(m);
+      const int j = a.full_nbr[(int64_t)f * N + i];
+      const int t = a.full_rev[(int64_t)f * N + i];
+      int rr = -1;
+      if (t >= 0) {
+        const unsigned long long mj = a.bond_mask[j];
+        if ((mj >> t) & 1ull) rr = __builtin_popcountll(mj & ((1ull << t) - 1ull));
+      }
+      a.bond_rev[(int64_t)s * N + i] = rr;
+      if (rr < 0) a.bond_flags[2] = 1;
+    }
+  }
   double x[SPL], y[SPL], z[SPL], r[SPL], ir[SPL], fc[SPL], dfc[SPL], er[SPL], ea[SPL];
 #pragma unroll
   for (int k = 0; k < SPL; ++k) {
@@ -581,15 +577,13 @@ hipError_t launch_zero_i32(hipStream_t s, int* p, int n) {
 }
 
 hipError_t launch_bonds(hipStream_t s, const double* pos, int64_t N, const double box[3], const int* nbr,
-                        const int* n_nb, const int* rev, double rb, int max_b, BondBufs b, bool reset_flags,
-                        const int* need, int* clear) {
+                        const int* n_nb, double rb, int max_b, BondBufs b, bool reset_flags, const int* need,
+                        int* clear) {
   if (reset_flags) hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b.flags, 3);
   const double rb2 = rb * rb * (1.0 + 1e-12);
   hipLaunchKernelGGL(k_bonds, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, box[0], box[1], box[2], 1.0 / box[0],
                      1.0 / box[1], 1.0 / box[2], nbr, n_nb, rb2, max_b, b.nbr, b.n_nb, b.mask, b.ref, b.flags, need,
                      clear);
-  hipLaunchKernelGGL(k_bond_reverse, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, nbr, rev, b.mask, max_b, b.rev,
-                     b.flags, need);
   return hipGetLastError();
 }
 

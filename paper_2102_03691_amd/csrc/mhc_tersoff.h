@@ -69,6 +69,17 @@ struct TersoffArgs {
   int max_nb;
   double* dd;
   double* U;
+  // Bond lists (nbr, n_nb above) just rebuilt from the skin lists: when
+  // bond_need is not null and *bond_need != 0 the site kernel also writes
+  // their reverse slots to bond_rev (which rev must then point to) from the
+  // skin lists' full_nbr / full_rev and the kept-slot masks; bond_flags[2] = 1
+  // if one is missing.
+  const int* bond_need;
+  const unsigned long long* bond_mask;
+  const int* full_nbr;
+  const int* full_rev;
+  int* bond_rev;
+  int* bond_flags;
 };
 
 // Outputs of the gather kernel (any may be null): F [N][3], W [N][3][3] float64
@@ -92,14 +103,15 @@ hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const C
                             int max_nb, NeighborBufs b);
 // Zero n ints (n > 0).
 hipError_t launch_zero_i32(hipStream_t s, int* p, int n);
-// Bond lists out of the lists (nbr, n_nb, with reverse slots rev): every
-// pair closer than rb, at most max_b per atom (max_nb <= 64), and their
-// reverse slots.  The flags accumulate over launches unless reset_flags
-// clears them first.  need (null: always) makes the build conditional on
-// *need != 0, decided on the device; clear (null: none) is zeroed.
+// Bond lists out of the lists (nbr, n_nb): every pair closer than rb, at
+// most max_b per atom (max_nb <= 64), and their kept-slot masks (their
+// reverse slots come from the next site kernel: TersoffArgs.bond_need).  The
+// flags accumulate over launches unless reset_flags clears them first.  need
+// (null: always) makes the build conditional on *need != 0, decided on the
+// device; clear (null: none) is zeroed.
 hipError_t launch_bonds(hipStream_t s, const double* pos, int64_t N, const double box[3], const int* nbr,
-                        const int* n_nb, const int* rev, double rb, int max_b, BondBufs b, bool reset_flags,
-                        const int* need, int* clear);
+                        const int* n_nb, double rb, int max_b, BondBufs b, bool reset_flags, const int* need,
+                        int* clear);
 hipError_t launch_set_i32(hipStream_t s, int* p, int value);
 // Lanes per atom of the evaluation kernels for a largest neighbour count:
 // the next power of two, at least 4 (64 at most: max_nb <= 64).

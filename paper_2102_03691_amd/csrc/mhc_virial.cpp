@@ -387,14 +387,19 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
     if (v->compact) {   // bond lists out of the skin lists, rebuilt when the atoms have moved enough
       any_compact = true;
       const int sl = (int)(e_idx & 1);
-      VHIP_TRY(launch_bonds(v->stream, pos, N, v->box, v->nb.nbr, v->nb.n_nb, v->nb.rev,
-                            v->tp.R + v->tp.D + v->bond_skin, v->max_b, v->bb, false, v->bb.need + sl,
-                            v->bb.need + (sl ^ 1)),
+      VHIP_TRY(launch_bonds(v->stream, pos, N, v->box, v->nb.nbr, v->nb.n_nb, v->tp.R + v->tp.D + v->bond_skin,
+                            v->max_b, v->bb, false, v->bb.need + sl, v->bb.need + (sl ^ 1)),
                "bonds");
       a.nbr = v->bb.nbr;
       a.n_nb = v->bb.n_nb;
       a.rev = v->bb.rev;
       a.max_nb = v->max_b;
+      a.bond_need = v->bb.need + sl;   // the site kernel fills their reverse slots after a rebuild
+      a.bond_mask = v->bb.mask;
+      a.full_nbr = v->nb.nbr;
+      a.full_rev = v->nb.rev;
+      a.bond_rev = v->bb.rev;
+      a.bond_flags = v->bb.flags;
       lpa = v->lpa_b;
     }
     a.dd = v->d_dd;
