@@ -63,6 +63,9 @@ PEAK_FP8_FLOPS = 5.0e15
 # Spectral heat current (no eigenvectors): 8000 atoms (the paper's Si and CNT
 # sizes), 250 lags (500 fs at a 2 fs sample interval), T = 256 steps per block.
 SHC_WORKLOADS = {"shc8000_l250_t256": (8000, 250, 256, 40)}     # atoms, lags, T, default blocks
+# grouped SHC: independent runs of uneven size (seeded draw of 16 sizes in 512 .. 8000 atoms), lags, T, blocks
+SHC_GROUP_WORKLOADS = {"shc_group16_l250_t256": (16, 512, 8000, 250, 256, 20),
+                       "shc_group64_small_l250_t256": (64, 216, 1000, 250, 256, 20)}
 SHC_METRIC = "spectral heat current atom*lag*steps/s (float64 virial-velocity correlation)"
 PEAK_FP64_FLOPS = 78.6e12
 
@@ -368,6 +371,84 @@ def run_shc(args):
     return out
 
 
+def run_shc_group(args):
+    """Grouped SHC (mhc_shc_group_*): 16 independent systems of uneven size, one
+    launch per kernel and block for all of them, inputs resident in HBM; the
+    same systems pushed one after another are timed beside it."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    from paper_2102_03691_amd import ModalSHC, SHCGroup
+    n_sys, n_lo, n_hi, L, T, blocks = SHC_GROUP_WORKLOADS[args.workload]
+    K = args.steps or blocks
+    sizes = [int(x) for x in np.random.default_rng(2102).integers(n_lo, n_hi + 1, n_sys)]
+    n_blocks = max(1, min(K + args.warmup, 8))
+    side = torch.cuda.Stream()
+    stream = side.cuda_stream
+    data = []
+    for q, n in enumerate(sizes):
+        data.append(synth.gen_steps_torch(40 + q, synth.masses(n), n_blocks * T, device="cuda:0"))
+    torch.cuda.synchronize()
+
+    def timed(push_block):
+        for j in range(args.warmup):
+            push_block(j % n_blocks)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(K):
+            push_block((args.warmup + j) % n_blocks)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    hs = [ModalSHC(n, L, T, stream=stream) for n in sizes]
+    g = SHCGroup(hs)
+    wall = timed(lambda b: g.push([v[b * T:(b + 1) * T] for v, _ in data], [W[b * T:(b + 1) * T] for _, W in data]))
+    solo = [ModalSHC(n, L, T, stream=stream) for n in sizes]
+
+    def one_by_one(b):
+        for h, (v, W) in zip(solo, data):
+            h.push(v[b * T:(b + 1) * T], W[b * T:(b + 1) * T])
+    wall_seq = timed(one_by_one)
+    acc = None
+    if not args.no_cpu_baseline:
+        log("accuracy: one seeded block of the smallest system against the FP64 oracle")
+        q = int(np.argmin(sizes))
+        for h in hs:
+            h.reset()
+        vc, Wc = synth.gen_steps(7, synth.masses(sizes[q]), 0, T)
+        ins_v = [v[:T] for v, _ in data]
+        ins_W = [W[:T] for _, W in data]
+        ins_v[q] = torch.as_tensor(vc, device="cuda:0")
+        ins_W[q] = torch.as_tensor(Wc, device="cuda:0")
+        g.push(ins_v, ins_W)
+        acc = {"K": _rel(hs[q].read()[0], oracle.shc_correlation(vc, Wc, L)),
+               "oracle": "shc_correlation (FP64)", "sample": f"{T} seeded samples of the {sizes[q]}-atom system",
+               "norm": "relative L2 per output array"}
+    g.close()
+    for h in hs + solo:
+        h.close()
+    units_per_block = float(sum(sizes)) * L * T
+    flops = 18.0 * units_per_block
+    ms = wall / K * 1e3
+    roof = {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
+            "unit": "TFLOP/s", "traffic": None, "kernel": "k_shc_gram_group",
+            "achieved_from": "wall time per block (ring, products and sums of all systems)"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {"metric": SHC_METRIC, "value": units_per_block * K / wall, "unit": "atom*lag*steps/s", "n_gpus": 1,
+           "steps": K, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "systems": sizes, "lags": L, "md_steps_per_step": T,
+                      "t_block": T, "precision": "float32 inputs, products and sums in float64",
+                      "parallelism": "single GPU"},
+           "roofline": roof,
+           "one_by_one": {"ms_per_step": wall_seq / K * 1e3, "value": units_per_block * K / wall_seq,
+                          "note": "the same systems pushed one after another (mhc_shc_push each)"}}
+    if acc is not None:
+        out["rel_err_vs_oracle"] = acc
+    return out
+
+
 def run_virial(args):
     """Tersoff Si: per-atom virial, forces, site energies, float32 W and HNEMD
     force for every atom per step, inputs resident in HBM."""
@@ -669,6 +750,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS) + sorted(SHC_WORKLOADS)
+                    + sorted(SHC_GROUP_WORKLOADS)
                     + sorted(VIRIAL_WORKLOADS) + sorted(MD_WORKLOADS))
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
@@ -700,6 +782,9 @@ def main():
         return
     if args.workload in SHC_WORKLOADS:
         print(json.dumps(run_shc(args)), flush=True)
+        return
+    if args.workload in SHC_GROUP_WORKLOADS:
+        print(json.dumps(run_shc_group(args)), flush=True)
         return
     if args.workload in VIRIAL_WORKLOADS:
         print(json.dumps(run_virial(args)), flush=True)

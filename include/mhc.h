@@ -470,6 +470,30 @@ mhc_status mhc_shc_synchronize(mhc_shc *shc);
 mhc_status mhc_shc_set_timing(mhc_shc *shc, int enable);
 mhc_status mhc_shc_kernel_timing(mhc_shc *shc, int64_t *launches, double *total_ms);
 
+/* Grouped SHC: several independent systems (the paper averages its spectra
+ * over many independent runs, Sec. III.A) advanced together.  Systems whose
+ * own block launch is short share one launch per kernel and block (launch
+ * overhead and an underfilled GPU dominate them alone); systems large enough
+ * to fill the GPU keep their own launches (fused, they lose cache reuse).
+ * systems: n distinct SHC objects (1..4096) with the same device, stream and
+ * t_block; their sizes and lag counts may differ.  The group borrows them
+ * (destroy it before them); each keeps working on its own (reads, resets,
+ * single pushes) between grouped pushes.
+ * Errors: INVALID_ARG, OOM, HIP (mhc_shc_group_last_error(NULL) tells which). */
+typedef struct mhc_shc_group mhc_shc_group;
+mhc_status mhc_shc_group_create(mhc_shc *const *systems, int32_t n, mhc_shc_group **out);
+mhc_status mhc_shc_group_destroy(mhc_shc_group *group);
+const char *mhc_shc_group_last_error(const mhc_shc_group *group);
+
+/* Push n_steps samples to every system: v[i], W[i] are system i's arrays in
+ * the layout of mhc_shc_push, device pointers (on_device = 1: read on the
+ * stream, the call returns before the GPU finishes) or host (0: staged,
+ * returns when the copies are done).  Each system's sums are the same bits as
+ * pushing its samples alone.
+ * Errors: INVALID_ARG, HIP (sticky for the group). */
+mhc_status mhc_shc_group_push(mhc_shc_group *group, int32_t n_steps, const float *const *v, const float *const *W,
+                              int on_device);
+
 /* ------------------------------------------------------ per-atom virial
  * The inputs of the modal current, from positions (Sec. II.A): for a
  * many-body potential written as site energies U = sum_i U_i, with U_i a

@@ -8,6 +8,6 @@ library is missing, every entry point raises.
 """
 from ._lib import (  # noqa: F401
     HNEMA, GKMA, DIRECTIONAL, CROSS, PREC_FP32, PREC_BF16X3, PREC_FP8, PREC_FP8X3, SCHED_AUTO, SCHED_TILES, SCHED_STREAMK,
-    SCHED_SPLIT, MhcError, ModalGroup, ModalHC, ModalSHC, ModalVirial, TersoffParams, bins_uniform, library, library_path, status_string,
+    SCHED_SPLIT, MhcError, ModalGroup, ModalHC, ModalSHC, ModalVirial, SHCGroup, TersoffParams, bins_uniform, library, library_path, status_string,
 )
 from .physics import gkma_kappa, hnema_kappa, shc_kappa, tersoff_si  # noqa: F401

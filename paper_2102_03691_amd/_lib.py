@@ -106,6 +106,10 @@ def library():
         "mhc_shc_synchronize": (i32, [vp]),
         "mhc_shc_set_timing": (i32, [vp, C.c_int]),
         "mhc_shc_kernel_timing": (i32, [vp, P(i64), P(dbl)]),
+        "mhc_shc_group_create": (i32, [P(vp), i32, P(vp)]),
+        "mhc_shc_group_destroy": (i32, [vp]),
+        "mhc_shc_group_last_error": (C.c_char_p, [vp]),
+        "mhc_shc_group_push": (i32, [vp, i32, P(vp), P(vp), C.c_int]),
         "mhc_virial_create": (i32, [C.c_int, vp, i64, vp, vp, P(TersoffParams), i32, dbl, P(vp)]),
         "mhc_virial_destroy": (i32, [vp]),
         "mhc_virial_last_error": (C.c_char_p, [vp]),
@@ -574,6 +578,63 @@ class ModalSHC:
         ms = C.c_double()
         self._check(self._lib.mhc_shc_kernel_timing(self._h, C.byref(n), C.byref(ms)), "shc kernel_timing")
         return n.value, ms.value
+
+
+class SHCGroup:
+    """Several ModalSHC systems advanced by one launch per kernel and block
+    (mhc_shc_group_*).  The systems must share one device, one stream and
+    t_block; their sizes and lag counts may differ."""
+
+    def __init__(self, systems):
+        self._lib = library()
+        self.systems = list(systems)
+        arr = (C.c_void_p * len(self.systems))(*[s._h.value for s in self.systems])
+        h = C.c_void_p()
+        st = self._lib.mhc_shc_group_create(arr, len(self.systems), C.byref(h))
+        if st:
+            raise MhcError(st, f"mhc_shc_group_create: {self._lib.mhc_shc_group_last_error(None).decode()}")
+        self._h = h
+
+    def _check(self, st, what):
+        if st:
+            raise MhcError(st, f"{what}: {self._lib.mhc_shc_group_last_error(self._h).decode()}")
+
+    def push(self, vs, Ws):
+        """vs[i], Ws[i]: system i's [S, N_i, 3] and [S, N_i, 3, 3] float32 (all torch or all numpy)."""
+        n = len(self.systems)
+        S = vs[0].shape[0]
+        dev = _is_torch(vs[0])
+        keep = []
+        pv = (C.c_void_p * n)()
+        pW = (C.c_void_p * n)()
+        for i, sysm in enumerate(self.systems):
+            v, W = vs[i], Ws[i]
+            assert v.shape[0] == S and W.shape[0] == S
+            if dev:
+                assert v.is_contiguous() and W.is_contiguous() and v.element_size() == 4 and W.element_size() == 4
+            else:
+                v = np.ascontiguousarray(v, dtype=np.float32)
+                W = np.ascontiguousarray(W, dtype=np.float32)
+            n_v = v.numel() if dev else v.size
+            n_W = W.numel() if dev else W.size
+            assert n_v == S * sysm.n_atoms * 3 and n_W == S * sysm.n_atoms * 9
+            keep += [v, W]
+            pv[i] = _ptr(v)
+            pW[i] = _ptr(W)
+        if dev:
+            self.systems[0]._use(*keep)   # one stream: one wait on torch's stream for all inputs
+        self._check(self._lib.mhc_shc_group_push(self._h, S, pv, pW, 1 if dev else 0), "shc group push")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mhc_shc_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class ModalVirial:

@@ -23,11 +23,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // vt[t][nu Np + i] = v[t][i][nu] for the block's steps s = s0 + t, t < t_count
 // (ld = 3 Np).  One thread per (t, i): 12 floats in, 12 out, consecutive
 // atoms to consecutive columns.
-__global__ void __launch_bounds__(256) k_shc_ring(const float* __restrict__ W, const float* __restrict__ v,
-                                                 int t_count, int64_t N, int64_t Np, float* __restrict__ ring,
-                                                 int64_t ring_len, int64_t ld, int64_t s0, float* __restrict__ vt) {
-  const int t = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void shc_ring_atom(const float* __restrict__ W, const float* __restrict__ v,
+                                              int t_count, int64_t N, int64_t Np, float* __restrict__ ring,
+                                              int64_t ring_len, int64_t ld, int64_t s0, float* __restrict__ vt,
+                                              int t, int64_t i) {
   if (t >= t_count || i >= N) return;
   const float* src = W + ((int64_t)t * N + i) * 9;
   float w[9];
@@ -44,6 +43,36 @@ __global__ void __launch_bounds__(256) k_shc_ring(const float* __restrict__ W, c
   vr[0] = v0;
   vr[Np] = v1;
   vr[2 * Np] = v2;
+}
+
+__global__ void __launch_bounds__(256) k_shc_ring(const float* __restrict__ W, const float* __restrict__ v,
+                                                 int t_count, int64_t N, int64_t Np, float* __restrict__ ring,
+                                                 int64_t ring_len, int64_t ld, int64_t s0, float* __restrict__ vt) {
+  shc_ring_atom(W, v, t_count, N, Np, ring, ring_len, ld, s0, vt, blockIdx.y, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// The system of work-group (or block) b of a grouped launch: the last
+// descriptor whose first index is <= b (n_sys is small; a linear scan).
+__device__ __forceinline__ int shc_system_of(const ShcBlockDesc* __restrict__ d, int n_sys, int64_t b, int which) {
+  int q = 0;
+  for (int k = 1; k < n_sys; ++k) {
+    const int64_t f = which == 0 ? d[k].ring_blk0 : (which == 1 ? d[k].gram_wg0 : d[k].acc_blk0);
+    if (f <= b) q = k;
+  }
+  return q;
+}
+
+__global__ void __launch_bounds__(256) k_shc_ring_group(const ShcBlockDesc* __restrict__ d, int n_sys) {
+  const int q = shc_system_of(d, n_sys, blockIdx.x, 0);
+  const ShcBlockDesc& e = d[q];
+  shc_ring_atom(e.W, e.v, e.t_count, e.N, e.Np, e.ring, e.ring_len, e.ld, e.s0, e.vt, blockIdx.y,
+                (int64_t)(blockIdx.x - e.ring_blk0) * 256 + threadIdx.x);
+}
+
+hipError_t launch_shc_ring_group(hipStream_t s, const ShcBlockDesc* d, int n_sys, int64_t n_blocks, int t_count) {
+  if (t_count <= 0 || n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shc_ring_group, dim3((unsigned)n_blocks, (unsigned)t_count), dim3(256), 0, s, d, n_sys);
+  return hipGetLastError();
 }
 
 hipError_t launch_shc_ring(hipStream_t s, const float* W, const float* v, int t_count, int64_t N, int64_t Np,
@@ -82,11 +111,20 @@ constexpr int SM_ROWS = SM_T - 16 + 16 * SM_RB;         // 192 staged rows
 constexpr int SM_WS = SM_DC + 4;                        // LDS row stride (floats)
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+// Loads and stores of the tile go through pointers in the global address
+// space: a pointer read from a descriptor in memory (grouped launches) is
+// otherwise generic to the compiler, whose flat loads also count against the
+// LDS wait counter, so that every LDS wait of the loop would wait for the
+// next chunk's loads as well.
+typedef __attribute__((address_space(1))) const f32x4 gcf32x4;
+typedef __attribute__((address_space(1))) double gdouble;
 
-__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
-k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t ring_len, int64_t ld, int64_t N,
-           int64_t Np, int t_count, int64_t s0, int64_t dk, int n_kcs, int n_ttiles, int n_lags_pad,
-           double* __restrict__ part) {
+// One work-group's tile; v = its index among the launch's work-groups of this
+// system after the XCD remapping.
+__device__ __forceinline__ void shc_gram_tile(const float* __restrict__ vt, const float* __restrict__ ring,
+                                              int64_t ring_len, int64_t ld, int64_t N, int64_t Np, int t_count,
+                                              int64_t s0, int64_t dk, int n_kcs, int n_ttiles, int n_lags_pad,
+                                              double* __restrict__ part, int v) {
   // staging buffers, and after the products the G of the 4 waves
   constexpr int WSH = 2 * SM_ROWS * SM_WS, VSH = 2 * SM_T * SM_WS;          // floats
   constexpr int RED = 4 * 16 * SM_RB * 16;                                  // doubles
@@ -98,8 +136,6 @@ k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t
   __shared__ int64_t roff[SM_ROWS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const int G = gridDim.x;
-  const int v = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
   const int n_ab = n_ttiles * (n_lags_pad / SM_L);
   const int kc = v / (3 * n_ab);
   const int mu = (v / n_ab) % 3;
@@ -130,7 +166,7 @@ k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t
       const int64_t off = roff[r];
       const int64_t j = jc + 4 * q;
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
-      if (off >= 0 && j < j1) x = *reinterpret_cast<const f32x4*>(ring + off + j);
+      if (off >= 0 && j < j1) x = *(gcf32x4*)(ring + off + j);
       wst[k] = x;
     }
 #pragma unroll
@@ -140,7 +176,7 @@ k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t
       const int t = SM_T * a + tr;
       const int64_t j = jc + 4 * q;
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
-      if (t < t_count && j < j1) x = *reinterpret_cast<const f32x4*>(vt + (int64_t)t * ld + j);
+      if (t < t_count && j < j1) x = *(gcf32x4*)(vt + (int64_t)t * ld + j);
       vst[k] = x;
     }
   };
@@ -207,18 +243,41 @@ k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t
     double s = 0.0;
     for (int w = 0; w < 4; ++w)
       for (int cc = 0; cc < 16; ++cc) s += red[w][(SM_L - 1) + cc - lam][cc];
-    part[(((int64_t)kc * n_ttiles + a) * n_lags_pad + (int64_t)SM_L * b + lam) * 3 + mu] = s;
+    ((gdouble*)part)[(((int64_t)kc * n_ttiles + a) * n_lags_pad + (int64_t)SM_L * b + lam) * 3 + mu] = s;
   }
+}
+
+// Consecutive work-group ids go to different XCDs: ids are remapped so that
+// each XCD takes a contiguous range (the tiles of one dof range are adjacent
+// and share that XCD's L2).
+__device__ __forceinline__ int shc_xcd_remap(int b, int G) { return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b; }
+
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+k_shc_gram(const float* __restrict__ vt, const float* __restrict__ ring, int64_t ring_len, int64_t ld, int64_t N,
+           int64_t Np, int t_count, int64_t s0, int64_t dk, int n_kcs, int n_ttiles, int n_lags_pad,
+           double* __restrict__ part) {
+  shc_gram_tile(vt, ring, ring_len, ld, N, Np, t_count, s0, dk, n_kcs, n_ttiles, n_lags_pad, part,
+                shc_xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Several systems' products in one launch: the remapped id picks the system
+// (systems in order, each its work-groups in the single-system order).
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+k_shc_gram_group(const ShcBlockDesc* __restrict__ d, int n_sys) {
+  const int v = shc_xcd_remap(blockIdx.x, gridDim.x);
+  const int q = shc_system_of(d, n_sys, v, 1);
+  const ShcBlockDesc& e = d[q];
+  shc_gram_tile(e.vt, e.ring, e.ring_len, e.ld, e.N, e.Np, e.t_count, e.s0, e.dk, e.n_kcs, e.n_ttiles,
+                e.n_lags_pad, e.part, (int)(v - e.gram_wg0));
 }
 
 // Fixed-order sum of the partials of one block into the running float64 sums
 // of each motion direction (Neumaier): one thread per (nu, tau, mu), summing
 // the n_kcs dof ranges of segment nu and the step tiles in order;
 // ksum[nu][tau][mu].
-__global__ void __launch_bounds__(256) k_shc_accum(const double* __restrict__ part, int n_kcs, int n_ttiles,
-                                                  int n_lags, int n_lags_pad, double* __restrict__ ksum,
-                                                  double* __restrict__ kcomp) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void shc_accum_one(const double* __restrict__ part, int n_kcs, int n_ttiles, int n_lags,
+                                              int n_lags_pad, double* __restrict__ ksum, double* __restrict__ kcomp,
+                                              int q) {
   if (q >= 3 * n_lags * 3) return;
   const int nu = q / (n_lags * 3);
   const int r = q - nu * n_lags * 3;
@@ -239,6 +298,19 @@ __global__ void __launch_bounds__(256) k_shc_accum(const double* __restrict__ pa
   neumaier_add(ksum[q], kcomp[q], s);
 }
 
+__global__ void __launch_bounds__(256) k_shc_accum(const double* __restrict__ part, int n_kcs, int n_ttiles,
+                                                  int n_lags, int n_lags_pad, double* __restrict__ ksum,
+                                                  double* __restrict__ kcomp) {
+  shc_accum_one(part, n_kcs, n_ttiles, n_lags, n_lags_pad, ksum, kcomp, blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_shc_accum_group(const ShcBlockDesc* __restrict__ d, int n_sys) {
+  const int q = shc_system_of(d, n_sys, blockIdx.x, 2);
+  const ShcBlockDesc& e = d[q];
+  shc_accum_one(e.part, e.n_kcs, e.n_ttiles, e.n_lags, e.n_lags_pad, e.ksum, e.kcomp,
+                (int)(blockIdx.x - e.acc_blk0) * 256 + threadIdx.x);
+}
+
 hipError_t launch_shc_products(hipStream_t s, const float* vt, const float* ring, int64_t ring_len, int64_t ld,
                                int64_t N, int64_t Np, int t_count, int64_t s0, int n_lags, int64_t dk, int n_kcs,
                                double* part) {
@@ -250,6 +322,27 @@ hipError_t launch_shc_products(hipStream_t s, const float* vt, const float* ring
                      ring_len, ld, N, Np, t_count, s0, dk, n_kcs, n_ttiles, n_lags_pad, part);
   return hipGetLastError();
 }
+
+hipError_t launch_shc_gram_group(hipStream_t s, const ShcBlockDesc* d, int n_sys, int64_t n_wgs) {
+  if (n_wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shc_gram_group, dim3((unsigned)n_wgs), dim3(256), 0, s, d, n_sys);
+  return hipGetLastError();
+}
+
+hipError_t launch_shc_accum_group(hipStream_t s, const ShcBlockDesc* d, int n_sys, int64_t n_blocks) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shc_accum_group, dim3((unsigned)n_blocks), dim3(256), 0, s, d, n_sys);
+  return hipGetLastError();
+}
+
+// Work-groups of one system's product launch and blocks of its accumulation
+// launch for a block of t_count steps (the grouped launches concatenate them).
+int64_t shc_gram_wgs(int t_count, int n_lags, int n_kcs) {
+  const int n_ttiles = (t_count + SM_T - 1) / SM_T;
+  const int n_ltiles = (n_lags + SM_L - 1) / SM_L;
+  return (int64_t)9 * n_kcs * n_ttiles * n_ltiles;
+}
+int64_t shc_accum_blocks(int n_lags) { return (3 * (int64_t)n_lags * 3 + 255) / 256; }
 
 hipError_t launch_shc_accum(hipStream_t s, const double* part, int t_count, int n_lags, int n_kcs, double* ksum,
                             double* kcomp) {

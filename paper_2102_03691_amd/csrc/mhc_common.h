@@ -231,6 +231,31 @@ hipError_t launch_shc_products(hipStream_t s, const float* vt, const float* ring
 // order (dof ranges, then step tiles), Neumaier.
 hipError_t launch_shc_accum(hipStream_t s, const double* part, int t_count, int n_lags, int n_kcs, double* ksum,
                             double* kcomp);
+// One system's block in the grouped launches of several systems (the same
+// kernels' work, concatenated): the arguments of launch_shc_ring /
+// _products / _accum for that system, and where its part of each launch
+// starts (ring: blocks of 256 atoms; products: work-groups; accumulation:
+// blocks of 256 sums).
+struct ShcBlockDesc {
+  const float* W;
+  const float* v;
+  float* ring;
+  float* vt;
+  double* part;
+  double* ksum;
+  double* kcomp;
+  int64_t N, Np, ring_len, ld, s0, dk;
+  int t_count, n_kcs, n_ttiles, n_lags, n_lags_pad;
+  int64_t ring_blk0, gram_wg0, acc_blk0;
+};
+// Sizes of one system's share of the grouped launches.
+int64_t shc_gram_wgs(int t_count, int n_lags, int n_kcs);
+int64_t shc_accum_blocks(int n_lags);
+// The grouped launches over n_sys descriptors (device memory); n_blocks /
+// n_wgs: the launch's total (the sum over the systems).
+hipError_t launch_shc_ring_group(hipStream_t s, const ShcBlockDesc* d, int n_sys, int64_t n_blocks, int t_count);
+hipError_t launch_shc_gram_group(hipStream_t s, const ShcBlockDesc* d, int n_sys, int64_t n_wgs);
+hipError_t launch_shc_accum_group(hipStream_t s, const ShcBlockDesc* d, int n_sys, int64_t n_blocks);
 // Kd[tau][mu][nu] = (ksum + kcomp)[nu][tau][mu] / (S - tau) (zero where S <= tau) and
 // K[tau][mu] = sum over nu in order.
 hipError_t launch_shc_finish(hipStream_t s, const double* ksum, const double* kcomp, int n_lags, int64_t S,

@@ -31,6 +31,7 @@ struct mhc_shc {
   int64_t ring_len = 0;
   int64_t dk = 0;
   int n_kcs = 0;                       // dof ranges per direction segment
+  int64_t cost = 0;                    // estimated product-launch time of a full block, in chunk-times
   int64_t S = 0;                       // samples pushed since the last reset
   std::vector<void*> allocs;
   float* ring = nullptr;               // [ring_len][3 mu][ld = 3 Np]
@@ -203,6 +204,7 @@ mhc_status mhc_shc_create(int device, void* hip_stream, int64_t n_atoms, int32_t
   }
   c->dk = ((c->N + best - 1) / best + 31) / 32 * 32;
   c->n_kcs = (int)((c->N + c->dk - 1) / c->dk);
+  c->cost = best_cost;
   void *pr, *pvt, *pv, *pW, *pp, *ps, *po;
   const size_t ring_bytes = (size_t)c->ring_len * 3 * c->ld * 4;
   const size_t vt_bytes = (size_t)t_block * c->ld * 4;
@@ -469,6 +471,240 @@ mhc_status mhc_shc_kernel_timing(mhc_shc* c, int64_t* launches, double* total_ms
   *launches = (int64_t)(c->ev_used / 2);
   *total_ms = tot;
   c->ev_used = 0;
+  return MHC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ grouped pushes
+// Several SHC contexts advanced together.  Systems whose own product launch
+// is short (at most SHC_FUSE_COST chunk-times: launch overhead and a partly
+// idle GPU dominate) are fused: the ring, product and accumulation kernels
+// of all of them concatenated into one grid each, driven by a table of
+// per-system descriptors.  Larger systems fill the GPU by themselves and
+// run their own launches, in order: fused into a long grid their work-groups
+// would start staggered instead of together, and the ones that share ring
+// rows would no longer read them at the same time (measured: 16 systems of
+// 0.6k..8k atoms fused 2.97 ms per block against 2.13 ms one by one; 64
+// systems of 0.2k..1k atoms 1.91 against 2.56 ms).  Each system's arithmetic
+// and summation order are those of its own push, so the results are the
+// same bits.  The descriptors of a block go through a ring of pinned
+// host slots and device slots; a host slot is refilled only after the event
+// recorded behind its previous copy (device slots are reused in stream
+// order, after the kernels that read them).
+struct mhc_shc_group {
+  std::vector<mhc_shc*> sys;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int T = 0;
+  std::string err;
+  mhc_status sticky = MHC_OK;
+  static constexpr int SLOTS = 64;
+  ShcBlockDesc* h_desc = nullptr;   // pinned [SLOTS][n]
+  ShcBlockDesc* d_desc = nullptr;   // device [SLOTS][n]
+  hipEvent_t ev[SLOTS] = {};
+  bool ev_pending[SLOTS] = {};
+  int64_t next = 0;
+};
+
+namespace {
+
+thread_local std::string g_shc_group_create_error;
+
+mhc_status gfail(mhc_shc_group* g, mhc_status st, const std::string& msg) {
+  g->err = msg;
+  if (st == MHC_ERR_HIP) g->sticky = MHC_ERR_HIP;
+  return st;
+}
+
+#define GHIP_TRY(call, where)                                                                   \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      (void)hipGetLastError();                                                                  \
+      return gfail(g, MHC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e_));          \
+    }                                                                                           \
+  } while (0)
+
+void gfree(mhc_shc_group* g) {
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  for (hipEvent_t& e : g->ev)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+  if (g->h_desc) (void)hipHostFree(g->h_desc);
+  if (g->d_desc) (void)hipFree(g->d_desc);
+  g->h_desc = nullptr;
+  g->d_desc = nullptr;
+}
+
+constexpr int64_t SHC_FUSE_COST = 8;
+
+// One block of t_count steps for every system; v[q], W[q] are device pointers
+// to system q's block.
+mhc_status group_block(mhc_shc_group* g, const float* const* v, const float* const* W, int t_count) {
+  const int n_all = (int)g->sys.size();
+  // the large systems: their own launches, as a single push makes them
+  for (int q = 0; q < n_all; ++q) {
+    mhc_shc* c = g->sys[q];
+    if (c->cost <= SHC_FUSE_COST) continue;
+    mhc_status st = shc_block(c, v[q], W[q], t_count);
+    if (st) return gfail(g, st, "system " + std::to_string(q) + ": " + c->err);
+  }
+  std::vector<int> fused;
+  for (int q = 0; q < n_all; ++q)
+    if (g->sys[q]->cost <= SHC_FUSE_COST) fused.push_back(q);
+  const int n = (int)fused.size();
+  if (n == 0) return MHC_OK;
+  const int slot = (int)(g->next++ % mhc_shc_group::SLOTS);
+  if (g->ev_pending[slot]) GHIP_TRY(hipEventSynchronize(g->ev[slot]), "descriptor slot wait");
+  ShcBlockDesc* h = g->h_desc + (int64_t)slot * n_all;
+  int64_t rb = 0, wg = 0, ab = 0;
+  for (int k = 0; k < n; ++k) {
+    const int q = fused[k];
+    const mhc_shc* c = g->sys[q];
+    ShcBlockDesc& d = h[k];
+    d = ShcBlockDesc{};
+    d.W = W[q];
+    d.v = v[q];
+    d.ring = c->ring;
+    d.vt = c->vt;
+    d.part = c->part;
+    d.ksum = c->ksum;
+    d.kcomp = c->ksum + 9 * c->n_lags;
+    d.N = c->N;
+    d.Np = c->Np;
+    d.ring_len = c->ring_len;
+    d.ld = c->ld;
+    d.s0 = c->S;
+    d.dk = c->dk;
+    d.t_count = t_count;
+    d.n_kcs = c->n_kcs;
+    d.n_ttiles = (t_count + 63) / 64;
+    d.n_lags = c->n_lags;
+    d.n_lags_pad = lags_pad(c->n_lags);
+    d.ring_blk0 = rb;
+    d.gram_wg0 = wg;
+    d.acc_blk0 = ab;
+    rb += (c->N + 255) / 256;
+    wg += shc_gram_wgs(t_count, c->n_lags, c->n_kcs);
+    ab += shc_accum_blocks(c->n_lags);
+  }
+  ShcBlockDesc* d = g->d_desc + (int64_t)slot * n_all;
+  GHIP_TRY(hipMemcpyAsync(d, h, sizeof(ShcBlockDesc) * n, hipMemcpyHostToDevice, g->stream), "descriptor copy");
+  GHIP_TRY(hipEventRecord(g->ev[slot], g->stream), "event record");
+  g->ev_pending[slot] = true;
+  GHIP_TRY(launch_shc_ring_group(g->stream, d, n, rb, t_count), "virial rings");
+  GHIP_TRY(launch_shc_gram_group(g->stream, d, n, wg), "virial-velocity products");
+  GHIP_TRY(launch_shc_accum_group(g->stream, d, n, ab), "partial sums");
+  for (int q : fused) g->sys[q]->S += t_count;
+  return MHC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhc_status mhc_shc_group_create(mhc_shc* const* systems, int32_t n, mhc_shc_group** out) {
+  if (!out) return MHC_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto bad = [](mhc_status st, const char* why) {
+    g_shc_group_create_error = why;
+    return st;
+  };
+  if (!systems || n < 1 || n > 4096) return bad(MHC_ERR_INVALID_ARG, "need 1 to 4096 systems");
+  for (int32_t q = 0; q < n; ++q) {
+    if (!systems[q]) return bad(MHC_ERR_INVALID_ARG, "NULL system");
+    if (systems[q]->sticky != MHC_OK) return bad(systems[q]->sticky, "a system has a sticky error");
+    for (int32_t r = 0; r < q; ++r)
+      if (systems[r] == systems[q]) return bad(MHC_ERR_INVALID_ARG, "a system appears twice");
+    if (systems[q]->device != systems[0]->device || systems[q]->stream != systems[0]->stream ||
+        systems[q]->T != systems[0]->T)
+      return bad(MHC_ERR_INVALID_ARG, "the systems must share the device, the stream and t_block");
+  }
+  mhc_shc_group* g = new (std::nothrow) mhc_shc_group();
+  if (!g) return bad(MHC_ERR_OOM, "host allocation failed");
+  g->sys.assign(systems, systems + n);
+  g->device = systems[0]->device;
+  g->stream = systems[0]->stream;
+  g->T = systems[0]->T;
+  auto bail = [&](mhc_status st, const char* why) {
+    g_shc_group_create_error = why;
+    gfree(g);
+    delete g;
+    return st;
+  };
+  if (hipSetDevice(g->device) != hipSuccess) return bail(MHC_ERR_HIP, "hipSetDevice");
+  const size_t bytes = sizeof(ShcBlockDesc) * mhc_shc_group::SLOTS * (size_t)n;
+  if (hipHostMalloc((void**)&g->h_desc, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    g->h_desc = nullptr;
+    return bail(MHC_ERR_OOM, "pinned descriptor allocation failed");
+  }
+  if (hipMalloc((void**)&g->d_desc, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    g->d_desc = nullptr;
+    return bail(MHC_ERR_OOM, "device descriptor allocation failed");
+  }
+  for (hipEvent_t& e : g->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+      return bail(MHC_ERR_HIP, "event create");
+    }
+  *out = g;
+  return MHC_OK;
+}
+
+mhc_status mhc_shc_group_destroy(mhc_shc_group* g) {
+  if (!g) return MHC_OK;
+  (void)hipSetDevice(g->device);
+  gfree(g);
+  delete g;
+  return MHC_OK;
+}
+
+const char* mhc_shc_group_last_error(const mhc_shc_group* g) {
+  return g ? g->err.c_str() : g_shc_group_create_error.c_str();
+}
+
+mhc_status mhc_shc_group_push(mhc_shc_group* g, int32_t n_steps, const float* const* v, const float* const* W,
+                              int on_device) {
+  if (!g) return MHC_ERR_INVALID_ARG;
+  if (g->sticky != MHC_OK) return g->sticky;
+  g->err.clear();
+  if (n_steps < 0 || (on_device != 0 && on_device != 1)) return gfail(g, MHC_ERR_INVALID_ARG, "bad arguments");
+  if (n_steps == 0) return MHC_OK;
+  if (!v || !W) return gfail(g, MHC_ERR_INVALID_ARG, "NULL input arrays");
+  const int n = (int)g->sys.size();
+  for (int q = 0; q < n; ++q) {
+    if (!v[q] || !W[q]) return gfail(g, MHC_ERR_INVALID_ARG, "NULL input of system " + std::to_string(q));
+    if (g->sys[q]->sticky != MHC_OK)
+      return gfail(g, g->sys[q]->sticky, "system " + std::to_string(q) + " has a sticky error");
+  }
+  GHIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  std::vector<const float*> bv(n), bW(n);
+  for (int32_t s0 = 0; s0 < n_steps; s0 += g->T) {
+    const int tc = std::min<int32_t>(g->T, n_steps - s0);
+    for (int q = 0; q < n; ++q) {
+      mhc_shc* c = g->sys[q];
+      const float* pv = v[q] + (int64_t)s0 * c->N3;
+      const float* pW = W[q] + (int64_t)s0 * c->N3 * 3;
+      if (on_device) {
+        bv[q] = pv;
+        bW[q] = pW;
+      } else {   // into the system's staging, behind the kernels that last read it
+        GHIP_TRY(hipMemcpyAsync(c->sv, pv, (size_t)tc * c->N3 * 4, hipMemcpyHostToDevice, g->stream), "copy v");
+        GHIP_TRY(hipMemcpyAsync(c->sW, pW, (size_t)tc * c->N3 * 12, hipMemcpyHostToDevice, g->stream), "copy W");
+        bv[q] = c->sv;
+        bW[q] = c->sW;
+      }
+    }
+    mhc_status st = group_block(g, bv.data(), bW.data(), tc);
+    if (st) return st;
+  }
+  if (!on_device) GHIP_TRY(hipStreamSynchronize(g->stream), "push sync");   // the caller may reuse v and W
   return MHC_OK;
 }
 

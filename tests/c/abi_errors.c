@@ -59,6 +59,17 @@ static void host_only(void) {
   EXPECT(mhc_shc_create(0, NULL, 0, 10, 64, NULL), MHC_ERR_INVALID_ARG);
   EXPECT(mhc_shc_push(NULL, 1, NULL, NULL, 0), MHC_ERR_INVALID_ARG);
   EXPECT(mhc_shc_load_state(NULL, NULL, 0), MHC_ERR_INVALID_ARG);
+  {
+    mhc_shc_group* gr = NULL;
+    mhc_shc* none[2] = {NULL, NULL};
+    EXPECT(mhc_shc_group_create(none, 2, NULL), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_create(NULL, 1, &gr), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_create(none, 0, &gr), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_create(none, 2, &gr), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_push(NULL, 1, NULL, NULL, 0), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_destroy(NULL), MHC_OK);
+    if (!mhc_shc_group_last_error(NULL)) ++fails;
+  }
   EXPECT(mhc_virial_compute(NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL), MHC_ERR_INVALID_ARG);
   EXPECT(mhc_virial_destroy(NULL), MHC_OK);
   if (!mhc_last_error(NULL) || !mhc_shc_last_error(NULL) || !mhc_virial_last_error(NULL)) ++fails;
@@ -178,6 +189,21 @@ static void device_part(mhc_ctx* ctx) {
   double Kw[3], om = 0.1;
   EXPECT(mhc_shc_spectrum(sh, 0, &om, 1.0, 0, Kw), MHC_ERR_INVALID_ARG);
   EXPECT(mhc_shc_spectrum(sh, 1, &om, 1.0, 0, Kw), MHC_OK);
+  /* SHC groups: duplicates, arguments, one host push */
+  {
+    mhc_shc* dup[2] = {sh, sh};
+    mhc_shc_group* sg = NULL;
+    const float* gv[1] = {vv};
+    const float* gW[1] = {WW};
+    const float* gnull[1] = {NULL};
+    EXPECT(mhc_shc_group_create(dup, 2, &sg), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_create(dup, 1, &sg), MHC_OK);
+    EXPECT(mhc_shc_group_push(sg, -1, gv, gW, 0), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_push(sg, 1, gnull, gW, 0), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_push(sg, 1, gv, gW, 2), MHC_ERR_INVALID_ARG);
+    EXPECT(mhc_shc_group_push(sg, (int32_t)S, gv, gW, 0), MHC_OK);
+    EXPECT(mhc_shc_group_destroy(sg), MHC_OK);
+  }
   EXPECT(mhc_shc_destroy(sh), MHC_OK);
   free(sb);
   free(buf);

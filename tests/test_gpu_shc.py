@@ -205,3 +205,73 @@ def test_shc_maximum_lags_and_block():
     log("shc_N10_S2100_L4096_T1024", rel_K=e, rel_K_dir=ed)
     assert n == S and K.shape == (L, 3) and e <= TOL and ed <= TOL
     assert not K[S:].any() and not Kd[S:].any()
+
+
+def test_shc_group_same_bits_as_single_pushes():
+    """Grouped SHC (mhc_shc_group_*): five systems of uneven size and lag
+    count (16, 133, 1000, 2051 and 8000 atoms; 7, 64, 250, 130 and 250 lags;
+    T = 256), the small ones fused into one launch per kernel and the
+    8000-atom one on its own launches, pushed together — device inputs in two
+    pushes of 300 and 220 steps (partial blocks), then host inputs of 80
+    steps — end with every system's K and split K bit-equal to pushing it
+    alone, and K within the 1e-12 bar of the oracle (checked on the four
+    smaller systems)."""
+    import torch
+    from paper_2102_03691_amd import ModalSHC, SHCGroup
+    announce("shc group of 5 uneven systems")
+    sizes, lags, T = (16, 133, 1000, 2051, 8000), (7, 64, 250, 130, 250), 256
+    pieces = ((0, 300, True), (300, 520, True), (520, 600, False))
+    data = [_inputs(n, 600, seed=500 + n) for n in sizes]
+    side = torch.cuda.Stream()                   # one stream for all (a null stream would give each its own)
+    stream = side.cuda_stream
+    grouped = [ModalSHC(n, L, T, stream=stream) for n, L in zip(sizes, lags)]
+    alone = [ModalSHC(n, L, T, stream=stream) for n, L in zip(sizes, lags)]
+    g = SHCGroup(grouped)
+    for a, b, dev in pieces:
+        if dev:
+            vs = [torch.as_tensor(v[a:b], device="cuda:0") for v, _ in data]
+            Ws = [torch.as_tensor(W[a:b], device="cuda:0") for _, W in data]
+        else:
+            vs = [v[a:b] for v, _ in data]
+            Ws = [W[a:b] for _, W in data]
+        g.push(vs, Ws)
+        for h, v, W in zip(alone, vs, Ws):
+            h.push(v, W)
+    torch.cuda.synchronize()
+    for k, (n, L) in enumerate(zip(sizes, lags)):
+        Kg, Sg = grouped[k].read()
+        Ka, Sa = alone[k].read()
+        Kdg, _ = grouped[k].read_dir()
+        Kda, _ = alone[k].read_dir()
+        assert Sg == Sa == 600
+        assert np.array_equal(Kg, Ka) and np.array_equal(Kdg, Kda)
+        if n <= 2051:
+            v, W = data[k]
+            e = rel(Kg, oracle.shc_correlation(v, W, L))
+            log(f"shc_group_N{n}_L{L}", rel_K=e)
+            assert e <= TOL
+    g.close()
+    for h in grouped + alone:
+        h.close()
+
+
+def test_shc_group_errors():
+    import torch
+    from paper_2102_03691_amd import MhcError, ModalSHC, SHCGroup
+    announce("shc group errors")
+    side = torch.cuda.Stream()
+    stream = side.cuda_stream
+    a = ModalSHC(50, 10, 64, stream=stream)
+    b = ModalSHC(50, 10, 128, stream=stream)
+    with pytest.raises(MhcError) as ei:          # different t_block
+        SHCGroup([a, b])
+    assert ei.value.status == 1
+    with pytest.raises(MhcError) as ei:          # the same system twice
+        SHCGroup([a, a])
+    assert ei.value.status == 1
+    c = ModalSHC(50, 10, 64, stream=0)           # a null stream: the object owns a stream of its own
+    with pytest.raises(MhcError) as ei:
+        SHCGroup([a, c])
+    assert ei.value.status == 1
+    for h in (a, b, c):
+        h.close()
