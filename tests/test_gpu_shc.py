@@ -275,3 +275,31 @@ def test_shc_group_errors():
     assert ei.value.status == 1
     for h in (a, b, c):
         h.close()
+
+
+def test_shc_group_of_large_systems_only():
+    """A group whose systems all fill the GPU by themselves (two of 8000 atoms,
+    250 lags, T = 256): nothing is fused, each runs its own launches inside the
+    grouped push; the sums equal single pushes bit for bit."""
+    import torch
+    from paper_2102_03691_amd import ModalSHC, SHCGroup
+    announce("shc group of large systems only")
+    side = torch.cuda.Stream()
+    stream = side.cuda_stream
+    data = [_inputs(8000, 300, seed=900 + k) for k in range(2)]
+    grouped = [ModalSHC(8000, 250, 256, stream=stream) for _ in data]
+    alone = [ModalSHC(8000, 250, 256, stream=stream) for _ in data]
+    g = SHCGroup(grouped)
+    vs = [torch.as_tensor(v, device="cuda:0") for v, _ in data]
+    Ws = [torch.as_tensor(W, device="cuda:0") for _, W in data]
+    g.push(vs, Ws)
+    g.push([v[:0] for v in vs], [W[:0] for W in Ws])   # nothing to push
+    for h, v, W in zip(alone, vs, Ws):
+        h.push(v, W)
+    torch.cuda.synchronize()
+    for hg, ha in zip(grouped, alone):
+        (Kg, Sg), (Ka, Sa) = hg.read(), ha.read()
+        assert Sg == Sa == 300 and np.array_equal(Kg, Ka)
+    g.close()
+    for h in grouped + alone:
+        h.close()
