@@ -432,7 +432,8 @@ def run_shc_group(args):
     flops = 18.0 * units_per_block
     ms = wall / K * 1e3
     roof = {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
-            "unit": "TFLOP/s", "traffic": None, "kernel": "k_shc_gram_group",
+            "unit": "TFLOP/s", "traffic": profiled_traffic(args.workload, "k_shc_gram_group"),
+            "kernel": "k_shc_gram_group",
             "achieved_from": "wall time per block (ring, products and sums of all systems)"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {"metric": SHC_METRIC, "value": units_per_block * K / wall, "unit": "atom*lag*steps/s", "n_gpus": 1,
