@@ -365,3 +365,68 @@ def md_nve(pos, vel, mass, box, p, dt: float, n_steps: int) -> dict:
         out["W"].append(per_atom_virial(x, box, p, nl))
         out["E"].append(energy(x, v, nl))
     return {k: np.array(val) for k, val in out.items()}
+
+
+# Boltzmann constant in eV/K (CODATA 2018, exact)
+K_B = 8.617333262e-5
+
+
+def md_nvt_hnemd(pos, vel, mass, box, p, dt: float, n_steps: int, fe, temperature: float, tau: float,
+                 xi: float = 0.0, eta: float = 0.0) -> dict:
+    """NVT molecular dynamics with the HNEMD driving force on every atom, the
+    protocol of the paper's HNEMA and SHC runs (Sec. III.A: 300 K, a 1 fs time
+    step, a Nose-Hoover thermostat; the driving force of Eq. 12).  One
+    thermostat variable xi with mass Q = g k_B T tau^2 (g = 3N), its time
+    integral eta, and a time-reversible splitting of each step:
+        xi += dt/2 G;   v *= exp(-xi dt/2);   eta += dt/2 xi
+        v += dt/2 a;    x += dt v (wrapped);  v += dt/2 a
+        v *= exp(-xi dt/2);   eta += dt/2 xi;   xi += dt/2 G
+    with G = (2K - g k_B T) / Q for the kinetic energy K of the velocities at
+    that point, and a = (F + F_ext) / (m KE_UNIT), F_ext = E_i F_e + F_e . W_i
+    (Eq. 12) with E_i from the velocities at the force evaluation (after the
+    first half kick).  Neighbour lists are rebuilt at every evaluation.
+    Returns, for every step, the positions, velocities and per-atom virials
+    after it, xi and eta after it, and the extended energy
+    K + U + Q xi^2 / 2 + g k_B T eta before the first step (index 0) and after
+    each step: a constant of the motion when fe = 0."""
+    box = np.asarray(box, dtype=np.float64)
+    x = np.mod(np.array(pos, dtype=np.float64), box)
+    v = np.array(vel, dtype=np.float64)
+    m = np.asarray(mass, dtype=np.float64)
+    fe = np.asarray(fe, dtype=np.float64)
+    inv_mk = 1.0 / (m * KE_UNIT)
+    g = 3 * len(m)
+    gkt = g * K_B * temperature
+    Q = gkt * tau * tau
+
+    def kinetic(v):
+        return 0.5 * float((m * (v * v).sum(axis=1)).sum()) * KE_UNIT
+
+    def state(x, v):
+        nl = neighbor_lists(x, box, p["R"] + p["D"])
+        U = site_energies(x, box, p, nl)
+        W = per_atom_virial(x, box, p, nl)
+        F = forces(x, box, p, nl) + hnemd_force_eq12(atom_energies(U, m, v), W, fe)
+        return F, U, W
+
+    F, U, _ = state(x, v)
+    out = {"pos": [], "vel": [], "W": [], "xi": [], "eta": [],
+           "H": [kinetic(v) + float(U.sum()) + 0.5 * Q * xi * xi + gkt * eta]}
+    for _ in range(n_steps):
+        xi += 0.5 * dt * (2.0 * kinetic(v) - gkt) / Q
+        v = v * math.exp(-0.5 * dt * xi)
+        eta += 0.5 * dt * xi
+        v = v + 0.5 * dt * F * inv_mk[:, None]
+        x = np.mod(x + dt * v, box)
+        F, U, W = state(x, v)
+        v = v + 0.5 * dt * F * inv_mk[:, None]
+        v = v * math.exp(-0.5 * dt * xi)
+        eta += 0.5 * dt * xi
+        xi += 0.5 * dt * (2.0 * kinetic(v) - gkt) / Q
+        out["pos"].append(x.copy())
+        out["vel"].append(v.copy())
+        out["W"].append(W)
+        out["xi"].append(xi)
+        out["eta"].append(eta)
+        out["H"].append(kinetic(v) + float(U.sum()) + 0.5 * Q * xi * xi + gkt * eta)
+    return {k: np.array(val) for k, val in out.items()}

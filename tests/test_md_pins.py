@@ -10,7 +10,8 @@ own formulas:
   * free flight: atoms out of each other's range move on straight lines,
     x(t) = x0 + v t (mod the box), at constant velocity;
 mutations (a full kick in place of each half kick; the second half kick with
-the old force) fail a pin each."""
+the old force) fail a pin each.  The NVT integrator with the HNEMD driving
+force (oracle.virial.md_nvt_hnemd) is pinned at the end of the file."""
 import numpy as np
 import pytest
 
@@ -116,3 +117,67 @@ def test_mutations_fail():
     assert not (e1 < 1e-4 and 3.5 < e1 / e2 < 4.5)
     dx, dv = _reversal_error(_mut_stale_force)
     assert dx > 1e-9 or dv > 1e-9
+
+
+# ---------------------------------------------------------------------------
+# NVT with the HNEMD driving force (oracle.virial.md_nvt_hnemd): pins from
+# what the integrator must do, not from its formulas:
+#   * no driving force and a thermostat too slow to act (tau -> infinity):
+#     the NVE trajectory bit for bit;
+#   * no driving force: the extended energy K + U + Q xi^2/2 + g k_B T eta is
+#     a constant of the motion, its error second order in the time step;
+#   * the driving force: Newton's third law makes the interatomic forces sum
+#     to zero, so the total momentum changes only by the summed driving force,
+#     F_e sum_i E_i + F_e . sum_i W_i, whose virial part is the total virial of
+#     Eq. 5 (computed independently of the per-atom tensors);
+#   * the thermostat pulls a hot start towards the set temperature.
+
+def _nvt(dt, T_fs, fe=(0.0, 0.0, 0.0), temp=300.0, tau=20.0, v_temp=300.0, seed=1):
+    p, pos, box, m, _ = _case(seed)
+    v0 = synth.thermal_velocities(m, v_temp, seed + 1)
+    return ov.md_nvt_hnemd(pos, v0, m, box, p, dt, int(round(T_fs / dt)), fe, temp, tau), (p, pos, box, m, v0)
+
+
+def test_nvt_without_thermostat_or_drive_is_nve():
+    out, (p, pos, box, m, v0) = _nvt(1.0, 10, tau=1e30)
+    ref = ov.md_nve(pos, v0, m, box, p, 1.0, 10)
+    assert np.array_equal(out["pos"], ref["pos"]) and np.array_equal(out["vel"], ref["vel"])
+    assert np.all(np.abs(out["xi"]) < 1e-40)
+
+
+def test_nvt_extended_energy_is_conserved_to_second_order():
+    errs = []
+    for dt in (1.0, 0.5):
+        out, (_, pos, _, _, _) = _nvt(dt, 20, tau=10.0, v_temp=600.0)
+        H = out["H"]
+        errs.append(np.abs(H - H[0]).max() / len(pos))
+    assert errs[0] < 5e-4                      # eV per atom, against a cohesive energy of about 4.6 eV
+    assert 3.5 < errs[0] / errs[1] < 4.5, errs
+
+
+def test_nvt_driving_force_moves_the_momentum_by_its_sum():
+    fe = np.array([2e-3, -1e-3, 0.5e-3])
+    out, (p, pos, box, m, v0) = _nvt(1.0, 20, fe=fe, tau=1e30)
+    x = np.concatenate([[np.mod(pos, box)], out["pos"]])
+    v = np.concatenate([[v0], out["vel"]])
+
+    def drive(k):   # F_e sum_i E_i + F_e . (total virial, Eq. 5), at state k
+        nl = ov.neighbor_lists(x[k], box, p["R"] + p["D"])
+        E = float(ov.site_energies(x[k], box, p, nl).sum()) + 0.5 * float((m * (v[k] ** 2).sum(axis=1)).sum()) * ov.KE_UNIT
+        return E * fe + fe @ ov.total_virial_eq5(x[k], box, p, nl)
+
+    d = np.array([drive(k) for k in range(len(x))])
+    dP_pred = (0.5 * (d[:-1] + d[1:])).sum(axis=0) * 1.0 / ov.KE_UNIT     # trapezoid over the steps, amu A/fs
+    dP = (m[:, None] * (v[-1] - v[0])).sum(axis=0)
+    assert np.abs(dP - dP_pred).max() < 2e-2 * np.abs(dP_pred).max(), (dP, dP_pred)
+    # and with the drive reversed the momentum moves the other way
+    out_r, _ = _nvt(1.0, 20, fe=-fe, tau=1e30)
+    dP_r = (m[:, None] * (out_r["vel"][-1] - v[0])).sum(axis=0)
+    assert np.abs(dP_r + dP).max() < 0.1 * np.abs(dP).max()
+
+
+def test_nvt_thermostat_cools_a_hot_start():
+    out, (_, _, _, m, _) = _nvt(1.0, 60, tau=10.0, v_temp=900.0)
+    kin = 0.5 * (m[None, :, None] * out["vel"] ** 2).sum(axis=(1, 2)) * ov.KE_UNIT
+    T_late = 2.0 * kin[30:].mean() / (3 * len(m) * ov.K_B)
+    assert 150.0 < T_late < 500.0, T_late
