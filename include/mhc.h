@@ -605,6 +605,30 @@ mhc_status mhc_virial_synchronize(mhc_virial *v);
 mhc_status mhc_virial_md(mhc_virial *v, double *pos, double *vel, double dt, int32_t n_steps, int32_t rebuild,
                          float *v32, float *W32, double *F);
 
+/* NVT molecular dynamics with the HNEMD driving force, the protocol of the
+ * paper's HNEMA and SHC runs (Sec. III.A: a Nose-Hoover thermostat; the
+ * driving force F_ext = E_i F_e + F_e . W_i of Eq. 12 on every atom, E_i with
+ * the velocities at the force evaluation).  One thermostat variable xi (1/fs)
+ * with mass Q = 3N k_B T tau^2 and its time integral eta; each step is
+ *   xi += dt/2 G;  v *= exp(-xi dt/2);  eta += dt/2 xi;
+ *   velocity-Verlet step with force F + F_ext;
+ *   v *= exp(-xi dt/2);  eta += dt/2 xi;  xi += dt/2 G,
+ * G = (2K - 3N k_B T) / Q with the kinetic energy K at that point (summed on
+ * the device in a fixed order).  Without a drive, K + U + Q xi^2/2 +
+ * 3N k_B T eta is conserved.
+ *   fe [3]         driving force parameter (host, 1/A; NULL: none)
+ *   temperature    set temperature (K, > 0); tau: thermostat time (fs, > 0)
+ *   thermostat [2] (host, in/out) xi and eta: read at entry, written at the
+ *                  end ({0, 0} to start a run)
+ * Everything else (positions, velocities, lists, bond lists, v32, W32, F,
+ * rebuilds) as for mhc_virial_md; the call synchronizes at its end.
+ * Errors: those of mhc_virial_md; INVALID_ARG also for a temperature or tau
+ * that is not finite and positive, a NULL or non-finite thermostat, a
+ * non-finite fe. */
+mhc_status mhc_virial_md_nvt(mhc_virial *v, double *pos, double *vel, double dt, int32_t n_steps, int32_t rebuild,
+                             const double *fe, double temperature, double tau, double *thermostat, float *v32,
+                             float *W32, double *F);
+
 /* HIP-event timing of each evaluation (mhc_virial_compute, and every force
  * evaluation of mhc_virial_md), as mhc_set_timing / mhc_kernel_timing: the
  * summed milliseconds of the per-atom site kernel (bond orders, site

@@ -120,6 +120,7 @@ def library():
         "mhc_virial_set_timing": (i32, [vp, C.c_int]),
         "mhc_virial_kernel_timing": (i32, [vp, P(i64), P(dbl), P(dbl)]),
         "mhc_virial_md": (i32, [vp, vp, vp, dbl, i32, i32, vp, vp, vp]),
+        "mhc_virial_md_nvt": (i32, [vp, vp, vp, dbl, i32, i32, vp, dbl, dbl, vp, vp, vp, vp]),
         "mhc_group_create": (i32, [P(vp), i32, i32, P(vp)]),
         "mhc_group_destroy": (i32, [vp]),
         "mhc_group_last_error": (C.c_char_p, [vp]),
@@ -751,6 +752,35 @@ class ModalVirial:
         self._use(pos, vel, *[t for t in (v32, W32, F) if t is not None])
         self._check(self._lib.mhc_virial_md(self._h, p, vp, float(dt), int(n_steps), int(rebuild), ptr.get("v32"),
                                             ptr.get("W32"), ptr.get("F")), "virial md")
+
+    def md_nvt(self, pos, vel, dt, n_steps, fe, temperature, tau, thermostat=(0.0, 0.0), rebuild=0, v32=None,
+               W32=None, F=None):
+        """As md, under a Nose-Hoover thermostat (temperature K, time tau fs) with
+        the HNEMD driving force fe (1/A, 3 values; None: no drive) on every atom
+        (mhc_virial_md_nvt).  thermostat: (xi, eta) at entry; returns them at the end."""
+        N = self.n_atoms
+        p = self._dev(pos, 8, 3)
+        vp = self._dev(vel, 8, 3)
+        ptr = {}
+        for name, t, es, per in (("v32", v32, 4, 3 * n_steps), ("W32", W32, 4, 9 * n_steps), ("F", F, 8, 3)):
+            if t is not None:
+                if not (_is_torch(t) and t.is_cuda and t.is_contiguous() and t.element_size() == es
+                        and t.numel() == N * per):
+                    raise ValueError(f"{name} must be a contiguous device tensor of {N * per} "
+                                     f"{'float32' if es == 4 else 'float64'} values")
+                ptr[name] = _ptr(t)
+        fe_arr = None if fe is None else np.ascontiguousarray(fe, dtype=np.float64)
+        if fe_arr is not None and fe_arr.size != 3:
+            raise ValueError("fe must hold 3 values")
+        th = np.ascontiguousarray(thermostat, dtype=np.float64).copy()
+        if th.size != 2:
+            raise ValueError("thermostat must hold (xi, eta)")
+        self._use(pos, vel, *[t for t in (v32, W32, F) if t is not None])
+        self._check(self._lib.mhc_virial_md_nvt(self._h, p, vp, float(dt), int(n_steps), int(rebuild),
+                                                None if fe_arr is None else _ptr(fe_arr), float(temperature),
+                                                float(tau), _ptr(th), ptr.get("v32"), ptr.get("W32"), ptr.get("F")),
+                    "virial md_nvt")
+        return float(th[0]), float(th[1])
 
     def synchronize(self):
         self._check(self._lib.mhc_virial_synchronize(self._h), "virial synchronize")

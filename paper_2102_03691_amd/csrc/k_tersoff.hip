@@ -550,13 +550,8 @@ __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArg
 #pragma unroll
     for (int q = 0; q < 12; ++q) t[q] += sh[q][g0 + k];
   const double* w = t + 3;
-  if (o.F)
-    for (int mu = 0; mu < 3; ++mu) o.F[3 * i + mu] = t[mu];
-  if (o.W)
-    for (int q = 0; q < 9; ++q) o.W[9 * i + q] = w[q];
-  if (o.W32)
-    for (int q = 0; q < 9; ++q) o.W32[9 * i + q] = (float)w[q];
-  if (o.Fext) {
+  double fx[3] = {0.0, 0.0, 0.0};
+  if (o.Fext || o.add_ext) {
     double e = a.U[i];
     if (o.vel) {
       const double vx = o.vel[3 * i], vy = o.vel[3 * i + 1], vz = o.vel[3 * i + 2];
@@ -564,8 +559,16 @@ __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArg
     }
 #pragma unroll
     for (int nu = 0; nu < 3; ++nu)
-      o.Fext[3 * i + nu] = e * o.fe[nu] + (o.fe[0] * w[nu] + o.fe[1] * w[3 + nu] + o.fe[2] * w[6 + nu]);
+      fx[nu] = e * o.fe[nu] + (o.fe[0] * w[nu] + o.fe[1] * w[3 + nu] + o.fe[2] * w[6 + nu]);
   }
+  if (o.F)
+    for (int mu = 0; mu < 3; ++mu) o.F[3 * i + mu] = o.add_ext ? t[mu] + fx[mu] : t[mu];
+  if (o.W)
+    for (int q = 0; q < 9; ++q) o.W[9 * i + q] = w[q];
+  if (o.W32)
+    for (int q = 0; q < 9; ++q) o.W32[9 * i + q] = (float)w[q];
+  if (o.Fext)
+    for (int nu = 0; nu < 3; ++nu) o.Fext[3 * i + nu] = fx[nu];
 }
 
 // ------------------------------------------------------------- launchers
@@ -692,6 +695,163 @@ hipError_t launch_md_step(hipStream_t s, double* pos, double* vel, const double*
   const int parts = (kick2 ? MD_KICK2 : 0) | (kick1_drift ? MD_KICK1_DRIFT : 0);
   hipLaunchKernelGGL(k_md_step, dim3(blocks_of(N, MD_ATOMS)), dim3(3 * MD_ATOMS), 0, s, pos, vel, F, mass, c, dt,
                      box[0], box[1], box[2], N, parts, v32, ref, thr2, need);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ Nose-Hoover thermostat
+// Thermostat state on the device: st[0] = xi (1/fs), st[1] = eta (its time
+// integral), st[2] = exp(-xi dt / 2), the velocity scale of the current step,
+// st[3] = the last kinetic energy (eV).  Kinetic energies are summed in a fixed
+// order: per work-group of 64 atoms in an LDS tree, then the work-groups'
+// partials by one work-group.
+
+// Sum of the 3 MD_ATOMS values in sh[] (every thread of the work-group calls it).
+__device__ __forceinline__ double block_sum_192(double* sh) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  if (t < 64) sh[t] += sh[t + 64] + sh[t + 128];
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// End of a step under the thermostat: the second half kick (v += c F / m),
+// the scale st[2], the float32 velocities (v32), and this work-group's
+// partial sum of m v^2 (part, one per work-group); with kick == 0 only the
+// partial sums (the state at entry).
+__global__ void __launch_bounds__(3 * MD_ATOMS) k_md_nvt_end(double* __restrict__ vel, const double* __restrict__ F,
+                                                             const double* __restrict__ mass, double c, int64_t N,
+                                                             int kick, const double* __restrict__ st,
+                                                             float* __restrict__ v32, double* __restrict__ part) {
+  __shared__ double sh[3 * MD_ATOMS];
+  const int t = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * (3 * MD_ATOMS) + t;
+  double mv2 = 0.0;
+  if (q < 3 * N) {
+    const double m = mass[q / 3];
+    double v = vel[q];
+    if (kick) {
+      v = v + c * F[q] / m;
+      v = v * st[2];
+      vel[q] = v;
+      if (v32) v32[q] = (float)v;
+    }
+    mv2 = m * v * v;
+  }
+  sh[t] = mv2;
+  const double s = block_sum_192(sh);
+  if (t == 0) part[blockIdx.x] = s;
+}
+
+// Thermostat update from the kinetic energy K = ke_unit / 2 sum of the
+// partials: mode & 1 (end of a step): eta += dt/2 xi, xi += dt/2 G; mode & 2
+// (start of a step): xi += dt/2 G, scale = exp(-xi dt / 2), eta += dt/2 xi;
+// G = (2K - gkt) / Q.  One work-group of 256 threads.
+__global__ void __launch_bounds__(256) k_thermostat(const double* __restrict__ part, int64_t n_part,
+                                                    double* __restrict__ st, double dt, double Q, double gkt,
+                                                    double ke_unit, int mode) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t k = t; k < n_part; k += 256) acc += part[k];
+  sh[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double K = 0.5 * sh[0] * ke_unit;
+  const double G = (2.0 * K - gkt) / Q;
+  double xi = st[0], eta = st[1];
+  if (mode & 1) {
+    eta += 0.5 * dt * xi;
+    xi += 0.5 * dt * G;
+  }
+  if (mode & 2) {
+    xi += 0.5 * dt * G;
+    st[2] = exp(-0.5 * dt * xi);
+    eta += 0.5 * dt * xi;
+  }
+  st[0] = xi;
+  st[1] = eta;
+  st[3] = K;
+}
+
+// Start of a step under the thermostat: the scale st[2], the first half kick,
+// the drift and the bond lists' displacement test, as k_md_step.
+__global__ void __launch_bounds__(3 * MD_ATOMS) k_md_nvt_start(double* __restrict__ pos, double* __restrict__ vel,
+                                                               const double* __restrict__ F,
+                                                               const double* __restrict__ mass, double c, double dt,
+                                                               double Lx, double Ly, double Lz, int64_t N,
+                                                               const double* __restrict__ st,
+                                                               const double* __restrict__ ref, double thr2,
+                                                               int* __restrict__ need) {
+  __shared__ double sh[3 * MD_ATOMS];
+  const int t = threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * (3 * MD_ATOMS) + t;
+  double d2 = 0.0;
+  if (q < 3 * N) {
+    const int a = (int)(q % 3);
+    const double m = mass[q / 3];
+    double v = vel[q] * st[2];
+    v = v + c * F[q] / m;
+    const double L = a == 0 ? Lx : (a == 1 ? Ly : Lz);
+    double x = pos[q] + dt * v;
+    x -= floor(x / L) * L;
+    if (x >= L) x -= L;
+    if (x < 0.0) x += L;
+    pos[q] = x;
+    vel[q] = v;
+    if (ref) {
+      double d = x - ref[q];
+      d -= L * rint(d / L);
+      d2 = d * d;
+    }
+  }
+  if (!ref) return;   // uniform over the launch
+  sh[t] = d2;
+  __syncthreads();
+  if (t < MD_ATOMS && sh[3 * t] + sh[3 * t + 1] + sh[3 * t + 2] > thr2) *need = 1;
+}
+
+__global__ void k_thermostat_set(double* st, double xi, double eta) {
+  if (threadIdx.x == 0) {
+    st[0] = xi;
+    st[1] = eta;
+    st[2] = 1.0;
+    st[3] = 0.0;
+  }
+}
+
+int64_t md_nvt_parts(int64_t N) { return (N + MD_ATOMS - 1) / MD_ATOMS; }
+
+hipError_t launch_md_nvt_end(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
+                             bool kick, const double* st, float* v32, double* part) {
+  hipLaunchKernelGGL(k_md_nvt_end, dim3((unsigned)md_nvt_parts(N)), dim3(3 * MD_ATOMS), 0, s, vel, F, mass, c, N,
+                     kick ? 1 : 0, st, v32, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_thermostat(hipStream_t s, const double* part, int64_t N, double* st, double dt, double Q,
+                             double gkt, double ke_unit, int mode) {
+  hipLaunchKernelGGL(k_thermostat, dim3(1), dim3(256), 0, s, part, md_nvt_parts(N), st, dt, Q, gkt, ke_unit, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_nvt_start(hipStream_t s, double* pos, double* vel, const double* F, const double* mass, double c,
+                               double dt, const double box[3], int64_t N, const double* st, const double* ref,
+                               double thr2, int* need) {
+  hipLaunchKernelGGL(k_md_nvt_start, dim3((unsigned)md_nvt_parts(N)), dim3(3 * MD_ATOMS), 0, s, pos, vel, F, mass, c,
+                     dt, box[0], box[1], box[2], N, st, ref, thr2, need);
+  return hipGetLastError();
+}
+
+hipError_t launch_thermostat_set(hipStream_t s, double* st, double xi, double eta) {
+  hipLaunchKernelGGL(k_thermostat_set, dim3(1), dim3(64), 0, s, st, xi, eta);
   return hipGetLastError();
 }
 

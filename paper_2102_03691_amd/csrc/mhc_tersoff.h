@@ -95,6 +95,7 @@ struct GatherArgs {
   double* W;
   float* W32;
   double* Fext;
+  bool add_ext;               // F = interatomic force + F_ext (needs fe; vel for E_i)
 };
 
 // Lists of the pairs closer than rc; also counts, per atom, those closer
@@ -131,5 +132,21 @@ hipError_t launch_tersoff(hipStream_t s, const TersoffArgs& a, const TersoffPara
 hipError_t launch_md_step(hipStream_t s, double* pos, double* vel, const double* F, const double* mass, double c,
                           double dt, const double box[3], int64_t N, bool kick2, bool kick1_drift, float* v32,
                           const double* ref, double thr2, int* need);
+
+// Nose-Hoover thermostat steps (state st [4] on the device: xi, eta, the
+// velocity scale exp(-xi dt/2), the last kinetic energy).  part: one double
+// per 64 atoms (md_nvt_parts).  end: the second half kick, the scale, v32 and
+// the kinetic-energy partials (kick false: the partials only); thermostat:
+// mode 1 end-of-step, 2 start-of-step, 3 both; start: the scale, the first
+// half kick and the drift (ref, thr2, need as for launch_md_step).
+int64_t md_nvt_parts(int64_t N);
+hipError_t launch_md_nvt_end(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
+                             bool kick, const double* st, float* v32, double* part);
+hipError_t launch_thermostat(hipStream_t s, const double* part, int64_t N, double* st, double dt, double Q,
+                             double gkt, double ke_unit, int mode);
+hipError_t launch_md_nvt_start(hipStream_t s, double* pos, double* vel, const double* F, const double* mass, double c,
+                               double dt, const double box[3], int64_t N, const double* st, const double* ref,
+                               double thr2, int* need);
+hipError_t launch_thermostat_set(hipStream_t s, double* st, double xi, double eta);
 
 }  // namespace mhc

@@ -21,6 +21,8 @@ thread_local std::string g_virial_create_error;
 
 // 1 amu (A/fs)^2 in eV: 1.66053906660e-27 kg * 1e10 m^2/s^2 / 1.602176634e-19 J
 constexpr double KE_UNIT_EV = 1.66053906660e-27 * 1e10 / 1.602176634e-19;
+// Boltzmann constant in eV/K (CODATA 2018, exact)
+constexpr double K_B_EV = 8.617333262e-5;
 
 }  // namespace
 
@@ -44,6 +46,8 @@ struct mhc_virial {
   NeighborBufs nb{};
   double *d_dd = nullptr, *d_U = nullptr;
   double* d_F = nullptr;  // forces of the molecular dynamics (mhc_virial_md)
+  double* d_thermo = nullptr;   // Nose-Hoover state [4] (mhc_virial_md_nvt)
+  double* d_kepart = nullptr;   // kinetic-energy partials, one per 64 atoms
   // Bond lists of the molecular dynamics when the lists carry a skin: the
   // pairs inside R + D + delta (delta = bond_skin, the smaller of the skin and
   // 0.5 A), rebuilt on the device whenever an atom has moved more than
@@ -241,6 +245,7 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
             valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) &&
             valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 3, &b.flags) &&
             valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U) && valloc(v, 3 * N, &v->d_F) &&
+            valloc(v, 4, &v->d_thermo) && valloc(v, md_nvt_parts(N), &v->d_kepart) &&
             valloc(v, MN, &v->bb.nbr) && valloc(v, MN, &v->bb.rev) && valloc(v, N, &v->bb.n_nb) &&
             valloc(v, N, &v->bb.mask) && valloc(v, 3 * N, &v->bb.ref) && valloc(v, 12, &v->bb.flags);
   if (!ok) return cleanup(MHC_ERR_OOM, "device allocation failed");
@@ -356,15 +361,26 @@ mhc_status mhc_virial_compute(mhc_virial* v, const double* pos, const double* ve
   return MHC_OK;
 }
 
-mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_steps, int32_t rebuild,
-                         float* v32, float* W32, double* F) {
-  mhc_status st = venter(v);
-  if (st) return st;
-  if (!pos || !vel) return vfail(v, MHC_ERR_INVALID_ARG, "NULL positions or velocities");
-  if (n_steps < 0 || rebuild < 0) return vfail(v, MHC_ERR_INVALID_ARG, "n_steps and rebuild must be >= 0");
-  if (!std::isfinite(dt) || !(dt > 0.0)) return vfail(v, MHC_ERR_INVALID_ARG, "dt must be finite and > 0");
-  if (!v->lists_ok) return vfail(v, MHC_ERR_STATE, "no valid neighbour lists (call mhc_virial_neighbors)");
-  if (n_steps == 0) return MHC_OK;
+}  // extern "C"
+
+namespace {
+
+// NVT with the HNEMD driving force: the drive fe (1/A), the thermostat's
+// temperature (K) and mass Q (eV fs^2), g k_B T (eV), and the host state
+// (xi, eta) read at entry and written back at the end.
+struct NvtArgs {
+  double fe[3];
+  bool drive;
+  double Q, gkt;
+  double* state;
+};
+
+// The MD loop of mhc_virial_md (nvt null: NVE velocity Verlet) and
+// mhc_virial_md_nvt (thermostat half steps around each velocity-Verlet step,
+// force + driving force).
+mhc_status md_run(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_steps, int32_t rebuild, float* v32,
+                  float* W32, double* F, const NvtArgs* nvt) {
+  mhc_status st = MHC_OK;
   VHIP_TRY(hipSetDevice(v->device), "hipSetDevice");
   const int64_t N = v->N;
   bool any_compact = false;
@@ -410,6 +426,11 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
     o.rcut2 = rcut2_of(v);
     o.F = v->d_F;
     o.W32 = w32;
+    if (nvt && nvt->drive) {   // F + F_ext (Eq. 12), E_i from the velocities now
+      o.add_ext = true;
+      o.vel = vel;
+      for (int q = 0; q < 3; ++q) o.fe[q] = nvt->fe[q];
+    }
     hipEvent_t e[3] = {nullptr, nullptr, nullptr};
     mhc_status s2 = timing_events(v, e);
     if (s2) return s2;
@@ -421,30 +442,56 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
   VHIP_TRY(launch_zero_i32(v->stream, v->bb.flags, 3), "clear bond flags");
   VHIP_TRY(launch_set_i32(v->stream, v->bb.need, 1), "bond rebuild flag");   // the entry evaluation builds
   if ((st = force(nullptr))) return st;     // forces at the entry positions
-  // kicks and drifts: before step s's force the first half kick and drift of
-  // step s (fused with the second half kick of step s - 1 from s = 1 on);
-  // after the last force its second half kick alone
-  auto kick_drift = [&](int32_t s) -> mhc_status {
-    e_idx = s + 1;   // the evaluation after this drift
-    const bool track = v->compact;
-    VHIP_TRY(launch_md_step(v->stream, pos, vel, v->d_F, v->d_mass, c, dt, v->box, N, s > 0, true,
-                            s > 0 && v32 ? v32 + (int64_t)(s - 1) * N * 3 : nullptr, track ? v->bb.ref : nullptr,
-                            thr2, v->bb.need + (e_idx & 1)),
-             "kick and drift");
-    return MHC_OK;
-  };
-  for (int32_t s = 0; s < n_steps; ++s) {
-    if ((st = kick_drift(s))) return st;
-    if (rebuild > 0 && (s + 1) % rebuild == 0) {
-      if ((st = mhc_virial_neighbors(v, pos, nullptr))) return st;
-      // new lists (and possibly new bond slots): the bond lists follow them
-      VHIP_TRY(launch_set_i32(v->stream, v->bb.need + (e_idx & 1), 1), "bond rebuild flag");
+  if (nvt) {
+    // thermostat half steps around each velocity-Verlet step
+    VHIP_TRY(launch_thermostat_set(v->stream, v->d_thermo, nvt->state[0], nvt->state[1]), "thermostat state");
+    VHIP_TRY(launch_md_nvt_end(v->stream, vel, v->d_F, v->d_mass, c, N, false, v->d_thermo, nullptr, v->d_kepart),
+             "kinetic energy");
+    VHIP_TRY(launch_thermostat(v->stream, v->d_kepart, N, v->d_thermo, dt, nvt->Q, nvt->gkt, KE_UNIT_EV, 2),
+             "thermostat");
+    for (int32_t s = 0; s < n_steps; ++s) {
+      e_idx = s + 1;
+      VHIP_TRY(launch_md_nvt_start(v->stream, pos, vel, v->d_F, v->d_mass, c, dt, v->box, N, v->d_thermo,
+                                   v->compact ? v->bb.ref : nullptr, thr2, v->bb.need + (e_idx & 1)),
+               "kick and drift");
+      if (rebuild > 0 && (s + 1) % rebuild == 0) {
+        if ((st = mhc_virial_neighbors(v, pos, nullptr))) return st;
+        VHIP_TRY(launch_set_i32(v->stream, v->bb.need + (e_idx & 1), 1), "bond rebuild flag");
+      }
+      if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr))) return st;
+      VHIP_TRY(launch_md_nvt_end(v->stream, vel, v->d_F, v->d_mass, c, N, true, v->d_thermo,
+                                 v32 ? v32 + (int64_t)s * N * 3 : nullptr, v->d_kepart),
+               "half kick");
+      VHIP_TRY(launch_thermostat(v->stream, v->d_kepart, N, v->d_thermo, dt, nvt->Q, nvt->gkt, KE_UNIT_EV,
+                                 s + 1 < n_steps ? 3 : 1),
+               "thermostat");
     }
-    if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr))) return st;
+  } else {
+    // kicks and drifts: before step s's force the first half kick and drift of
+    // step s (fused with the second half kick of step s - 1 from s = 1 on);
+    // after the last force its second half kick alone
+    auto kick_drift = [&](int32_t s) -> mhc_status {
+      e_idx = s + 1;   // the evaluation after this drift
+      const bool track = v->compact;
+      VHIP_TRY(launch_md_step(v->stream, pos, vel, v->d_F, v->d_mass, c, dt, v->box, N, s > 0, true,
+                              s > 0 && v32 ? v32 + (int64_t)(s - 1) * N * 3 : nullptr, track ? v->bb.ref : nullptr,
+                              thr2, v->bb.need + (e_idx & 1)),
+               "kick and drift");
+      return MHC_OK;
+    };
+    for (int32_t s = 0; s < n_steps; ++s) {
+      if ((st = kick_drift(s))) return st;
+      if (rebuild > 0 && (s + 1) % rebuild == 0) {
+        if ((st = mhc_virial_neighbors(v, pos, nullptr))) return st;
+        // new lists (and possibly new bond slots): the bond lists follow them
+        VHIP_TRY(launch_set_i32(v->stream, v->bb.need + (e_idx & 1), 1), "bond rebuild flag");
+      }
+      if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr))) return st;
+    }
+    VHIP_TRY(launch_md_step(v->stream, pos, vel, v->d_F, v->d_mass, c, dt, v->box, N, true, false,
+                            v32 ? v32 + (int64_t)(n_steps - 1) * N * 3 : nullptr, nullptr, 0.0, nullptr),
+             "half kick");
   }
-  VHIP_TRY(launch_md_step(v->stream, pos, vel, v->d_F, v->d_mass, c, dt, v->box, N, true, false,
-                          v32 ? v32 + (int64_t)(n_steps - 1) * N * 3 : nullptr, nullptr, 0.0, nullptr),
-           "half kick");
   if (F) VHIP_TRY(hipMemcpyAsync(F, v->d_F, (size_t)N * 3 * 8, hipMemcpyDeviceToDevice, v->stream), "copy forces");
   if (any_compact) {
     int f[3] = {0, 0, 0};
@@ -457,7 +504,59 @@ mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int
                        "not valid");
     if (f[2]) return vfail(v, MHC_ERR_INVALID_ARG, "bond lists are not symmetric (non-finite positions?)");
   }
+  if (nvt) {
+    double th[4] = {0.0, 0.0, 0.0, 0.0};
+    VHIP_TRY(hipMemcpyAsync(th, v->d_thermo, sizeof(th), hipMemcpyDeviceToHost, v->stream), "read thermostat");
+    VHIP_TRY(hipStreamSynchronize(v->stream), "md sync");
+    nvt->state[0] = th[0];
+    nvt->state[1] = th[1];
+  }
   return MHC_OK;
+}
+
+mhc_status md_check(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_steps, int32_t rebuild) {
+  mhc_status st = venter(v);
+  if (st) return st;
+  if (!pos || !vel) return vfail(v, MHC_ERR_INVALID_ARG, "NULL positions or velocities");
+  if (n_steps < 0 || rebuild < 0) return vfail(v, MHC_ERR_INVALID_ARG, "n_steps and rebuild must be >= 0");
+  if (!std::isfinite(dt) || !(dt > 0.0)) return vfail(v, MHC_ERR_INVALID_ARG, "dt must be finite and > 0");
+  if (!v->lists_ok) return vfail(v, MHC_ERR_STATE, "no valid neighbour lists (call mhc_virial_neighbors)");
+  return MHC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhc_status mhc_virial_md(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_steps, int32_t rebuild,
+                         float* v32, float* W32, double* F) {
+  mhc_status st = md_check(v, pos, vel, dt, n_steps, rebuild);
+  if (st || n_steps == 0) return st;
+  return md_run(v, pos, vel, dt, n_steps, rebuild, v32, W32, F, nullptr);
+}
+
+mhc_status mhc_virial_md_nvt(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_steps, int32_t rebuild,
+                             const double* fe, double temperature, double tau, double* thermostat, float* v32,
+                             float* W32, double* F) {
+  mhc_status st = md_check(v, pos, vel, dt, n_steps, rebuild);
+  if (st) return st;
+  if (!std::isfinite(temperature) || !(temperature > 0.0) || !std::isfinite(tau) || !(tau > 0.0))
+    return vfail(v, MHC_ERR_INVALID_ARG, "temperature and tau must be finite and > 0");
+  if (!thermostat || !std::isfinite(thermostat[0]) || !std::isfinite(thermostat[1]))
+    return vfail(v, MHC_ERR_INVALID_ARG, "thermostat must point to two finite numbers (xi, eta)");
+  NvtArgs a{};
+  a.drive = false;
+  for (int q = 0; q < 3; ++q) {
+    a.fe[q] = fe ? fe[q] : 0.0;
+    if (!std::isfinite(a.fe[q])) return vfail(v, MHC_ERR_INVALID_ARG, "fe must be finite");
+    if (a.fe[q] != 0.0) a.drive = true;
+  }
+  a.gkt = 3.0 * (double)v->N * K_B_EV * temperature;
+  a.Q = a.gkt * tau * tau;
+  if (!std::isfinite(a.Q) || !(a.Q > 0.0)) return vfail(v, MHC_ERR_INVALID_ARG, "thermostat mass out of range");
+  a.state = thermostat;
+  if (n_steps == 0) return MHC_OK;
+  return md_run(v, pos, vel, dt, n_steps, rebuild, v32, W32, F, &a);
 }
 
 mhc_status mhc_virial_synchronize(mhc_virial* v) {

@@ -274,3 +274,59 @@ def test_md_bond_overflow_is_reported():
     ref = ov.md_nve(near, np.zeros_like(near), m, box, p, 1.0, 1)
     assert np.abs(pt.cpu().numpy() - ref["pos"][-1]).max() < 1e-12
     v.close()
+
+
+@pytest.mark.parametrize("rebuild,skin,fe", [(1, 0.0, (2e-3, -1e-3, 5e-4)), (5, 1.0, (2e-3, -1e-3, 5e-4)),
+                                             (0, 1.0, (0.0, 0.0, 0.0))])
+def test_md_nvt_hnemd_matches_oracle(rebuild, skin, fe):
+    """mhc_virial_md_nvt (Nose-Hoover thermostat, HNEMD driving force of Eq. 12
+    on every atom: the paper's HNEMA / SHC protocol, Sec. III.A) against the
+    oracle's integrator (oracle.virial.md_nvt_hnemd): 20 steps of 64 atoms
+    from a nonzero thermostat state, positions and velocities within 1e-11,
+    every step's float32 v and W within one float32 rounding, and the
+    thermostat's xi and eta at the end."""
+    import torch
+    from paper_2102_03691_amd import ModalVirial
+    announce(f"md nvt rebuild={rebuild} skin={skin} fe={fe}")
+    pos, box, m, vel = _start((2, 2, 2), 0.05, 31)
+    n, dt, temp, tau, xi0, eta0 = 20, 1.0, 300.0, 20.0, 0.01, 0.5
+    p = ov.tersoff_si()
+    ref = ov.md_nvt_hnemd(pos, vel, m, box, p, dt, n, fe, temp, tau, xi=xi0, eta=eta0)
+    N = len(pos)
+    v = ModalVirial(m, box, p, max_neighbors=24, skin=skin)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    v.neighbors(pt)
+    v32 = torch.empty((n, N, 3), dtype=torch.float32, device="cuda:0")
+    W32 = torch.empty((n, N, 3, 3), dtype=torch.float32, device="cuda:0")
+    xi, eta = v.md_nvt(pt, vt, dt, n, fe, temp, tau, thermostat=(xi0, eta0), rebuild=rebuild, v32=v32, W32=W32)
+    torch.cuda.synchronize()
+    v.close()
+    got_x, got_v = pt.cpu().numpy(), vt.cpu().numpy()
+    dx = float(np.abs(ov.min_image(got_x - ref["pos"][-1], box)).max())
+    dv = float(np.abs(got_v - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max())
+    e = {"dx_A": dx, "dv_rel": dv, "v32_ulps": _ulps(v32.cpu().numpy(), ref["vel"]),
+         "W32_ulps": _ulps(W32.cpu().numpy(), ref["W"]),
+         "xi_rel": abs(xi - ref["xi"][-1]) / abs(ref["xi"][-1]), "eta_rel": abs(eta - ref["eta"][-1]) / abs(ref["eta"][-1])}
+    log(f"md_nvt64_rebuild{rebuild}_skin{skin}_drive{int(any(fe))}", **e)
+    assert dx <= 1e-11 and dv <= 1e-11
+    assert e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0
+    assert e["xi_rel"] <= 1e-10 and e["eta_rel"] <= 1e-10
+
+
+def test_md_nvt_errors():
+    import torch
+    from paper_2102_03691_amd import MhcError, ModalVirial
+    announce("md nvt errors")
+    pos, box, m, vel = _start((2, 2, 2), 0.05, 17)
+    v = ModalVirial(m, box, ov.tersoff_si(), max_neighbors=24)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    v.neighbors(pt)
+    for fe, temp, tau, th in (((0, 0, 0), 0.0, 10.0, (0, 0)), ((0, 0, 0), 300.0, -1.0, (0, 0)),
+                              ((float("nan"), 0, 0), 300.0, 10.0, (0, 0)), ((0, 0, 0), 300.0, 10.0, (float("inf"), 0))):
+        with pytest.raises(MhcError) as ei:
+            v.md_nvt(pt, vt, 1.0, 2, fe, temp, tau, thermostat=th)
+        assert ei.value.status == 1
+    assert v.md_nvt(pt, vt, 1.0, 0, None, 300.0, 10.0, thermostat=(0.1, 0.2)) == (0.1, 0.2)
+    v.close()
