@@ -78,6 +78,9 @@ VIRIAL_WORKLOADS = {"si8000_virial": ((10, 10, 10), 200), "si512k_virial": ((40,
 # NVE velocity-Verlet steps on the device with the same forces, each step writing its
 # float32 v and W (the push inputs); lists with a 1 A skin rebuilt every 50 steps
 MD_WORKLOADS = {"si8000_md": ((10, 10, 10), 400), "si512k_md": ((40, 40, 40), 200)}
+# the paper's SHC run on its 8000-atom Si block (Sec. III.A): NVT at 300 K with the HNEMD driving force
+# |F_e| = 0.1 / um along x, the SHC correlation over 250 lags computed on the fly; blocks of T steps
+HNEMD_WORKLOADS = {"si8000_hnemd_shc": ((10, 10, 10), 250, 256, 4)}     # cells, lags, T, default blocks
 MD_METRIC = "NVE molecular dynamics (velocity Verlet, Tersoff Si, float64) atom*steps/s incl. push inputs"
 VIRIAL_METRIC = "per-atom virial (Eq. 8) + forces + HNEMD force (Eq. 12) atom*steps/s, float64 Tersoff Si"
 
@@ -450,6 +453,111 @@ def run_shc_group(args):
     return out
 
 
+def run_hnemd_shc(args):
+    """The SHC method end to end on the device: NVT molecular dynamics with the
+    HNEMD driving force (Nose-Hoover, Eq. 12 on every atom) writing every
+    step's float32 v and W, pushed block by block into the SHC correlation."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2102_03691_amd import ModalSHC, ModalVirial, tersoff_si
+    cells, L, T, blocks = HNEMD_WORKLOADS[args.workload]
+    K = args.steps or blocks
+    pos, box = synth.diamond(cells, sigma=0.06, seed=1)
+    N = len(pos)
+    m = synth.masses(N, "natural", 1)
+    vel = synth.thermal_velocities(m, 300.0, 1)
+    fe = (1e-5, 0.0, 0.0)                   # 0.1 / um along x
+    TEMP, TAU, REBUILD = 300.0, 100.0, 50
+    vir = ModalVirial(m, box, tersoff_si(), max_neighbors=24, skin=1.0)
+    shc = ModalSHC(N, L, T)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    v32 = torch.empty((T, N, 3), dtype=torch.float32, device="cuda:0")
+    W32 = torch.empty((T, N, 3, 3), dtype=torch.float32, device="cuda:0")
+    vir.neighbors(pt)
+    th = (0.0, 0.0)
+    for _ in range(args.warmup):
+        th = vir.md_nvt(pt, vt, 1.0, T, fe, TEMP, TAU, thermostat=th, rebuild=REBUILD, v32=v32, W32=W32)
+        shc.push(v32, W32)
+    shc.reset()
+    vir.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        th = vir.md_nvt(pt, vt, 1.0, T, fe, TEMP, TAU, thermostat=th, rebuild=REBUILD, v32=v32, W32=W32)
+        shc.push(v32, W32)
+    shc.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, site_ms, gather_ms = vir.kernel_timing()
+    vir.set_timing(False)
+    Kc, n_samples = shc.read()
+    kin = 0.5 * float((torch.as_tensor(m, device="cuda:0") * (vt * vt).sum(dim=1)).sum()) * 103.64269652680505
+    site_avg = site_ms / max(launches, 1)
+    n_b = np.full(N, 4.0)
+    flops = float((65.0 * n_b + 79.0 * n_b * (n_b - 1.0) + n_b).sum())
+    roof = {"bound": "alu", "achieved": flops / (site_avg * 1e-3) / 1e12, "peak": PEAK_FP64_FLOPS / 1e12,
+            "unit": "TFLOP/s", "work": "65 float64 ops per bond + 79 per ordered pair of bonds (4 bonds per Si atom)",
+            "flop_per_launch": flops, "traffic": None, "kernel": "k_tersoff_site", "avg_launch_ms": site_avg,
+            "launches": launches, "gather_kernel_avg_ms": gather_ms / max(launches, 1)}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    res = {"metric": "HNEMD (NVT + driving force) MD with the SHC correlation on the fly, atom*steps/s",
+           "value": N * T * K / wall, "unit": "atom*steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+           "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "atoms": N, "cells": list(cells), "potential": "Tersoff Si",
+                      "dt_fs": 1.0, "md_steps_per_step": T, "lags": L, "fe_per_A": list(fe), "temperature_K": TEMP,
+                      "thermostat_tau_fs": TAU, "skin_A": 1.0, "rebuild_every": REBUILD,
+                      "parallelism": "single GPU"},
+           "roofline": roof,
+           "end_state": {"temperature_K": 2.0 * kin / (3 * N * 8.617333262e-5), "xi_per_fs": th[0],
+                         "K0_x_eV_A_per_fs": float(Kc[0, 0]), "samples": n_samples}}
+    if not args.no_cpu_baseline:
+        import oracle
+        import oracle.virial as ov
+        log("accuracy: NVT + drive and the SHC of its steps against the oracle on a 64-atom cut")
+        spos, sbox = synth.diamond((2, 2, 2), sigma=0.06, seed=1)
+        sm = synth.masses(len(spos), "natural", 1)
+        svel = synth.thermal_velocities(sm, 300.0, 1)
+        sfe = (2e-3, 0.0, 0.0)
+        ref = ov.md_nvt_hnemd(spos, svel, sm, sbox, ov.tersoff_si(), 1.0, 64, sfe, TEMP, 20.0)
+        sv = ModalVirial(sm, sbox, tersoff_si(), max_neighbors=24, skin=1.0)
+        ss = ModalSHC(len(spos), 16, 64)
+        sp = torch.as_tensor(np.mod(spos, sbox), device="cuda:0")
+        svt = torch.as_tensor(svel, device="cuda:0").clone()
+        sv32 = torch.empty((64, len(spos), 3), dtype=torch.float32, device="cuda:0")
+        sW32 = torch.empty((64, len(spos), 3, 3), dtype=torch.float32, device="cuda:0")
+        sv.neighbors(sp)
+        sv.md_nvt(sp, svt, 1.0, 64, sfe, TEMP, 20.0, v32=sv32, W32=sW32)
+        ss.push(sv32, sW32)
+        Kd, _ = ss.read()
+        Kr = oracle.shc_correlation(ref["vel"].astype(np.float32), ref["W"].astype(np.float32), 16)
+        res["rel_err_vs_oracle"] = {
+            "pos_A": float(np.abs(ov.min_image(sp.cpu().numpy() - ref["pos"][-1], sbox)).max()),
+            "vel": float(np.abs(svt.cpu().numpy() - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max()),
+            "shc_K": _rel(Kd, Kr),
+            "oracle": "oracle.virial.md_nvt_hnemd, then oracle.shc_correlation of its float32 v and W",
+            "sample": "64 atoms (2x2x2 cells), 64 steps, 16 lags",
+            "norm": "max |diff| (A) / max |diff| / max |ref| / relative L2"}
+        sv.close()
+        ss.close()
+        log("cpu baseline (oracle)")
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < 12.0:
+            ov.md_nvt_hnemd(spos, svel, sm, sbox, ov.tersoff_si(), 1.0, 10, sfe, TEMP, 20.0)
+            done += 10
+        spent = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(spos) * done / spent, "unit": "atom*steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{done} NVT + drive steps of the 64-atom cut (pure Python float64, lists "
+                                         f"rebuilt every step; the SHC correlation not included), {spent:.1f} s"}
+    vir.close()
+    shc.close()
+    return res
+
+
 def run_virial(args):
     """Tersoff Si: per-atom virial, forces, site energies, float32 W and HNEMD
     force for every atom per step, inputs resident in HBM."""
@@ -752,7 +860,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(GROUP_WORKLOADS) + sorted(SHC_WORKLOADS)
                     + sorted(SHC_GROUP_WORKLOADS)
-                    + sorted(VIRIAL_WORKLOADS) + sorted(MD_WORKLOADS))
+                    + sorted(VIRIAL_WORKLOADS) + sorted(MD_WORKLOADS) + sorted(HNEMD_WORKLOADS))
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="work split of the T-batched contraction: 0 auto, 1 tiles, 2 stream-K, 3 split")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -792,6 +900,9 @@ def main():
         return
     if args.workload in MD_WORKLOADS:
         print(json.dumps(run_md(args)), flush=True)
+        return
+    if args.workload in HNEMD_WORKLOADS:
+        print(json.dumps(run_hnemd_shc(args)), flush=True)
         return
     dims, t_block, prec, methods, nb, L, default_steps = WORKLOADS[args.workload]
     K = args.steps or default_steps
