@@ -504,6 +504,58 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
   }
 }
 
+// Atom i's sums over its pairs (the pair terms of its LPA lanes in sh, slot
+// order) and every output of the gather kernel; with o.kick_vel, also the
+// second half kick and thermostat scale of the step on its velocity (after
+// E_i has read it) and the float32 copy.  Returns m_i |v_i|^2 after the kick
+// (0 without one).
+__device__ __forceinline__ double gather_atom(const TersoffArgs& a, const GatherArgs& o, const double (*sh)[256],
+                                              int g0, int n, int64_t i) {
+  double t[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) t[q] = 0.0;
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int q = 0; q < 12; ++q) t[q] += sh[q][g0 + k];
+  const double* w = t + 3;
+  double fx[3] = {0.0, 0.0, 0.0};
+  if (o.Fext || o.add_ext) {
+    double e = a.U[i];
+    if (o.vel) {
+      const double vx = o.vel[3 * i], vy = o.vel[3 * i + 1], vz = o.vel[3 * i + 2];
+      e += 0.5 * o.mass[i] * (vx * vx + vy * vy + vz * vz) * o.ke_unit;
+    }
+#pragma unroll
+    for (int nu = 0; nu < 3; ++nu)
+      fx[nu] = e * o.fe[nu] + (o.fe[0] * w[nu] + o.fe[1] * w[3 + nu] + o.fe[2] * w[6 + nu]);
+  }
+  double f[3];
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu) f[mu] = o.add_ext ? t[mu] + fx[mu] : t[mu];
+  if (o.F)
+    for (int mu = 0; mu < 3; ++mu) o.F[3 * i + mu] = f[mu];
+  if (o.W)
+    for (int q = 0; q < 9; ++q) o.W[9 * i + q] = w[q];
+  if (o.W32)
+    for (int q = 0; q < 9; ++q) o.W32[9 * i + q] = (float)w[q];
+  if (o.Fext)
+    for (int nu = 0; nu < 3; ++nu) o.Fext[3 * i + nu] = fx[nu];
+  double mv2 = 0.0;
+  if (o.kick_vel) {   // as k_md_nvt_end: v += c F / m, then v *= exp(-xi dt / 2)
+    const double m = o.mass[i];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      double v = o.kick_vel[3 * i + mu];
+      v = v + o.kick_c * f[mu] / m;
+      v = v * o.kick_scale[2];
+      o.kick_vel[3 * i + mu] = v;
+      if (o.kick_v32) o.kick_v32[3 * i + mu] = (float)v;
+      mv2 += m * v * v;
+    }
+  }
+  return mv2;
+}
+
 // Per pair: dU_i/dr_ij - dU_j/dr_ji (Eq. 4) and r_ij (x) dU_j/dr_ji (Eq. 8);
 // the first lane of each atom sums its pairs in slot order and writes F_i,
 // W_i, E_i and F_ext (Eq. 12).
@@ -542,33 +594,20 @@ __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArg
 #pragma unroll
   for (int q = 0; q < 12; ++q) sh[q][tid] = c[q];
   __syncthreads();
-  if (i >= N || s != 0) return;
-  double t[12];
-#pragma unroll
-  for (int q = 0; q < 12; ++q) t[q] = 0.0;
-  for (int k = 0; k < n; ++k)
-#pragma unroll
-    for (int q = 0; q < 12; ++q) t[q] += sh[q][g0 + k];
-  const double* w = t + 3;
-  double fx[3] = {0.0, 0.0, 0.0};
-  if (o.Fext || o.add_ext) {
-    double e = a.U[i];
-    if (o.vel) {
-      const double vx = o.vel[3 * i], vy = o.vel[3 * i + 1], vz = o.vel[3 * i + 2];
-      e += 0.5 * o.mass[i] * (vx * vx + vy * vy + vz * vz) * o.ke_unit;
+  const bool first = i < N && s == 0;
+  double mv2 = 0.0;
+  if (first) mv2 = gather_atom(a, o, sh, g0, n, i);
+  if (o.ke_part) {   // the work-group's partial sum of m v^2 after the kick (uniform over the launch)
+    constexpr int APB = 256 / LPA;   // atoms per work-group
+    __shared__ double kp[APB];
+    if (s == 0) kp[tid / LPA] = mv2;
+    __syncthreads();
+    for (int w = APB / 2; w > 0; w >>= 1) {
+      if (tid < w) kp[tid] += kp[tid + w];
+      __syncthreads();
     }
-#pragma unroll
-    for (int nu = 0; nu < 3; ++nu)
-      fx[nu] = e * o.fe[nu] + (o.fe[0] * w[nu] + o.fe[1] * w[3 + nu] + o.fe[2] * w[6 + nu]);
+    if (tid == 0) o.ke_part[blockIdx.x] = kp[0];
   }
-  if (o.F)
-    for (int mu = 0; mu < 3; ++mu) o.F[3 * i + mu] = o.add_ext ? t[mu] + fx[mu] : t[mu];
-  if (o.W)
-    for (int q = 0; q < 9; ++q) o.W[9 * i + q] = w[q];
-  if (o.W32)
-    for (int q = 0; q < 9; ++q) o.W32[9 * i + q] = (float)w[q];
-  if (o.Fext)
-    for (int nu = 0; nu < 3; ++nu) o.Fext[3 * i + nu] = fx[nu];
 }
 
 // ------------------------------------------------------------- launchers
@@ -836,11 +875,13 @@ hipError_t launch_md_nvt_end(hipStream_t s, double* vel, const double* F, const 
   return hipGetLastError();
 }
 
-hipError_t launch_thermostat(hipStream_t s, const double* part, int64_t N, double* st, double dt, double Q,
+hipError_t launch_thermostat(hipStream_t s, const double* part, int64_t n_part, double* st, double dt, double Q,
                              double gkt, double ke_unit, int mode) {
-  hipLaunchKernelGGL(k_thermostat, dim3(1), dim3(256), 0, s, part, md_nvt_parts(N), st, dt, Q, gkt, ke_unit, mode);
+  hipLaunchKernelGGL(k_thermostat, dim3(1), dim3(256), 0, s, part, n_part, st, dt, Q, gkt, ke_unit, mode);
   return hipGetLastError();
 }
+
+int64_t gather_blocks(int64_t N, int lpa) { return (int64_t)blocks_of(N * lpa, 256); }
 
 hipError_t launch_md_nvt_start(hipStream_t s, double* pos, double* vel, const double* F, const double* mass, double c,
                                double dt, const double box[3], int64_t N, const double* st, const double* ref,

@@ -96,6 +96,14 @@ struct GatherArgs {
   float* W32;
   double* Fext;
   bool add_ext;               // F = interatomic force + F_ext (needs fe; vel for E_i)
+  // The end of an NVT step on the fly (kick_vel null: none): v += kick_c F / m,
+  // v *= kick_scale[2] on kick_vel (after E_i has read vel), its float32 copy to
+  // kick_v32 (may be null), and per work-group the sum of m v^2 to ke_part.
+  double* kick_vel;
+  double kick_c;
+  const double* kick_scale;
+  float* kick_v32;
+  double* ke_part;
 };
 
 // Lists of the pairs closer than rc; also counts, per atom, those closer
@@ -142,8 +150,10 @@ hipError_t launch_md_step(hipStream_t s, double* pos, double* vel, const double*
 int64_t md_nvt_parts(int64_t N);
 hipError_t launch_md_nvt_end(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
                              bool kick, const double* st, float* v32, double* part);
-hipError_t launch_thermostat(hipStream_t s, const double* part, int64_t N, double* st, double dt, double Q,
+hipError_t launch_thermostat(hipStream_t s, const double* part, int64_t n_part, double* st, double dt, double Q,
                              double gkt, double ke_unit, int mode);
+// Work-groups of the gather kernel for lpa lanes per atom (its ke_part count).
+int64_t gather_blocks(int64_t N, int lpa);
 hipError_t launch_md_nvt_start(hipStream_t s, double* pos, double* vel, const double* F, const double* mass, double c,
                                double dt, const double box[3], int64_t N, const double* st, const double* ref,
                                double thr2, int* need);

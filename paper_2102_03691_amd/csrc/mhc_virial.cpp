@@ -47,7 +47,7 @@ struct mhc_virial {
   double *d_dd = nullptr, *d_U = nullptr;
   double* d_F = nullptr;  // forces of the molecular dynamics (mhc_virial_md)
   double* d_thermo = nullptr;   // Nose-Hoover state [4] (mhc_virial_md_nvt)
-  double* d_kepart = nullptr;   // kinetic-energy partials, one per 64 atoms
+  double* d_kepart = nullptr;   // kinetic-energy partials (per 64 atoms, or per gather work-group)
   // Bond lists of the molecular dynamics when the lists carry a skin: the
   // pairs inside R + D + delta (delta = bond_skin, the smaller of the skin and
   // 0.5 A), rebuilt on the device whenever an atom has moved more than
@@ -245,7 +245,8 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
             valloc(v, n_cells, &b.fill) && valloc(v, n_cells + 1, &b.start) &&
             valloc(v, (n_cells + 1023) / 1024, &b.tile_sums) && valloc(v, 3, &b.flags) &&
             valloc(v, 3 * MN, &v->d_dd) && valloc(v, N, &v->d_U) && valloc(v, 3 * N, &v->d_F) &&
-            valloc(v, 4, &v->d_thermo) && valloc(v, md_nvt_parts(N), &v->d_kepart) &&
+            valloc(v, 4, &v->d_thermo) &&
+            valloc(v, std::max(md_nvt_parts(N), gather_blocks(N, 64)), &v->d_kepart) &&
             valloc(v, MN, &v->bb.nbr) && valloc(v, MN, &v->bb.rev) && valloc(v, N, &v->bb.n_nb) &&
             valloc(v, N, &v->bb.mask) && valloc(v, 3 * N, &v->bb.ref) && valloc(v, 12, &v->bb.flags);
   if (!ok) return cleanup(MHC_ERR_OOM, "device allocation failed");
@@ -390,7 +391,11 @@ mhc_status md_run(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_
   const double half = 0.5 * v->bond_skin;
   const double thr2 = half * half * (1.0 - 1e-9);
   int64_t e_idx = 0;
-  auto force = [&](float* w32) -> mhc_status {
+  const double c = 0.5 * dt / KE_UNIT_EV;   // half kick: dv = dt/2 F / (m KE)
+  int64_t gather_parts = 0;   // work-groups of the last gather launch
+  // kick_v32: with nvt, the end of the step on the fly in the gather kernel
+  // (second half kick, thermostat scale, float32 velocities, m v^2 partials)
+  auto force = [&](float* w32, bool kick_end = false, float* kick_v32 = nullptr) -> mhc_status {
     TersoffArgs a{};
     a.pos = pos;
     a.N = N;
@@ -431,13 +436,20 @@ mhc_status md_run(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_
       o.vel = vel;
       for (int q = 0; q < 3; ++q) o.fe[q] = nvt->fe[q];
     }
+    if (kick_end) {
+      o.kick_vel = vel;
+      o.kick_c = c;
+      o.kick_scale = v->d_thermo;
+      o.kick_v32 = kick_v32;
+      o.ke_part = v->d_kepart;
+    }
+    gather_parts = gather_blocks(N, lpa);
     hipEvent_t e[3] = {nullptr, nullptr, nullptr};
     mhc_status s2 = timing_events(v, e);
     if (s2) return s2;
     VHIP_TRY(launch_tersoff(v->stream, a, v->tp, o, lpa, e[0], e[1], e[2]), "force kernels");
     return MHC_OK;
   };
-  const double c = 0.5 * dt / KE_UNIT_EV;   // half kick: dv = dt/2 F / (m KE)
   // overflow and reverse-slot flags of the bond passes accumulate over this call's steps
   VHIP_TRY(launch_zero_i32(v->stream, v->bb.flags, 3), "clear bond flags");
   VHIP_TRY(launch_set_i32(v->stream, v->bb.need, 1), "bond rebuild flag");   // the entry evaluation builds
@@ -447,7 +459,8 @@ mhc_status md_run(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_
     VHIP_TRY(launch_thermostat_set(v->stream, v->d_thermo, nvt->state[0], nvt->state[1]), "thermostat state");
     VHIP_TRY(launch_md_nvt_end(v->stream, vel, v->d_F, v->d_mass, c, N, false, v->d_thermo, nullptr, v->d_kepart),
              "kinetic energy");
-    VHIP_TRY(launch_thermostat(v->stream, v->d_kepart, N, v->d_thermo, dt, nvt->Q, nvt->gkt, KE_UNIT_EV, 2),
+    VHIP_TRY(launch_thermostat(v->stream, v->d_kepart, md_nvt_parts(N), v->d_thermo, dt, nvt->Q, nvt->gkt,
+                               KE_UNIT_EV, 2),
              "thermostat");
     for (int32_t s = 0; s < n_steps; ++s) {
       e_idx = s + 1;
@@ -458,12 +471,11 @@ mhc_status md_run(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_
         if ((st = mhc_virial_neighbors(v, pos, nullptr))) return st;
         VHIP_TRY(launch_set_i32(v->stream, v->bb.need + (e_idx & 1), 1), "bond rebuild flag");
       }
-      if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr))) return st;
-      VHIP_TRY(launch_md_nvt_end(v->stream, vel, v->d_F, v->d_mass, c, N, true, v->d_thermo,
-                                 v32 ? v32 + (int64_t)s * N * 3 : nullptr, v->d_kepart),
-               "half kick");
-      VHIP_TRY(launch_thermostat(v->stream, v->d_kepart, N, v->d_thermo, dt, nvt->Q, nvt->gkt, KE_UNIT_EV,
-                                 s + 1 < n_steps ? 3 : 1),
+      // the force, and the end of the step in the same gather kernel
+      if ((st = force(W32 ? W32 + (int64_t)s * N * 9 : nullptr, true, v32 ? v32 + (int64_t)s * N * 3 : nullptr)))
+        return st;
+      VHIP_TRY(launch_thermostat(v->stream, v->d_kepart, gather_parts, v->d_thermo, dt, nvt->Q, nvt->gkt,
+                                 KE_UNIT_EV, s + 1 < n_steps ? 3 : 1),
                "thermostat");
     }
   } else {
