@@ -541,7 +541,7 @@ __device__ __forceinline__ double gather_atom(const TersoffArgs& a, const Gather
   if (o.Fext)
     for (int nu = 0; nu < 3; ++nu) o.Fext[3 * i + nu] = fx[nu];
   double mv2 = 0.0;
-  if (o.kick_vel) {   // as k_md_nvt_end: v += c F / m, then v *= exp(-xi dt / 2)
+  if (o.kick_vel) {   // end of an NVT step: v += c F / m, then v *= exp(-xi dt / 2)
     const double m = o.mass[i];
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
@@ -757,29 +757,17 @@ __device__ __forceinline__ double block_sum_192(double* sh) {
   return sh[0];
 }
 
-// End of a step under the thermostat: the second half kick (v += c F / m),
-// the scale st[2], the float32 velocities (v32), and this work-group's
-// partial sum of m v^2 (part, one per work-group); with kick == 0 only the
-// partial sums (the state at entry).
-__global__ void __launch_bounds__(3 * MD_ATOMS) k_md_nvt_end(double* __restrict__ vel, const double* __restrict__ F,
-                                                             const double* __restrict__ mass, double c, int64_t N,
-                                                             int kick, const double* __restrict__ st,
-                                                             float* __restrict__ v32, double* __restrict__ part) {
+// Partial sums of m v^2, one per work-group of 64 atoms (the thermostat's
+// kinetic energy at the entry of an NVT call; later steps take theirs from
+// the gather kernel).
+__global__ void __launch_bounds__(3 * MD_ATOMS) k_md_ke_partial(const double* __restrict__ vel,
+                                                                const double* __restrict__ mass, int64_t N,
+                                                                double* __restrict__ part) {
   __shared__ double sh[3 * MD_ATOMS];
   const int t = threadIdx.x;
   const int64_t q = (int64_t)blockIdx.x * (3 * MD_ATOMS) + t;
   double mv2 = 0.0;
-  if (q < 3 * N) {
-    const double m = mass[q / 3];
-    double v = vel[q];
-    if (kick) {
-      v = v + c * F[q] / m;
-      v = v * st[2];
-      vel[q] = v;
-      if (v32) v32[q] = (float)v;
-    }
-    mv2 = m * v * v;
-  }
+  if (q < 3 * N) mv2 = mass[q / 3] * vel[q] * vel[q];
   sh[t] = mv2;
   const double s = block_sum_192(sh);
   if (t == 0) part[blockIdx.x] = s;
@@ -868,10 +856,8 @@ __global__ void k_thermostat_set(double* st, double xi, double eta) {
 
 int64_t md_nvt_parts(int64_t N) { return (N + MD_ATOMS - 1) / MD_ATOMS; }
 
-hipError_t launch_md_nvt_end(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
-                             bool kick, const double* st, float* v32, double* part) {
-  hipLaunchKernelGGL(k_md_nvt_end, dim3((unsigned)md_nvt_parts(N)), dim3(3 * MD_ATOMS), 0, s, vel, F, mass, c, N,
-                     kick ? 1 : 0, st, v32, part);
+hipError_t launch_md_ke_partial(hipStream_t s, const double* vel, const double* mass, int64_t N, double* part) {
+  hipLaunchKernelGGL(k_md_ke_partial, dim3((unsigned)md_nvt_parts(N)), dim3(3 * MD_ATOMS), 0, s, vel, mass, N, part);
   return hipGetLastError();
 }
 

@@ -142,14 +142,14 @@ hipError_t launch_md_step(hipStream_t s, double* pos, double* vel, const double*
                           const double* ref, double thr2, int* need);
 
 // Nose-Hoover thermostat steps (state st [4] on the device: xi, eta, the
-// velocity scale exp(-xi dt/2), the last kinetic energy).  part: one double
-// per 64 atoms (md_nvt_parts).  end: the second half kick, the scale, v32 and
-// the kinetic-energy partials (kick false: the partials only); thermostat:
-// mode 1 end-of-step, 2 start-of-step, 3 both; start: the scale, the first
-// half kick and the drift (ref, thr2, need as for launch_md_step).
+// velocity scale exp(-xi dt/2), the last kinetic energy).  ke_partial: sums
+// of m v^2, one per 64 atoms (md_nvt_parts of them); thermostat: mode 1
+// end-of-step, 2 start-of-step, 3 both, from n_part partials; start: the
+// scale, the first half kick and the drift (ref, thr2, need as for
+// launch_md_step).  The end of a step runs in the gather kernel
+// (GatherArgs.kick_vel).
 int64_t md_nvt_parts(int64_t N);
-hipError_t launch_md_nvt_end(hipStream_t s, double* vel, const double* F, const double* mass, double c, int64_t N,
-                             bool kick, const double* st, float* v32, double* part);
+hipError_t launch_md_ke_partial(hipStream_t s, const double* vel, const double* mass, int64_t N, double* part);
 hipError_t launch_thermostat(hipStream_t s, const double* part, int64_t n_part, double* st, double dt, double Q,
                              double gkt, double ke_unit, int mode);
 // Work-groups of the gather kernel for lpa lanes per atom (its ke_part count).

@@ -457,8 +457,7 @@ mhc_status md_run(mhc_virial* v, double* pos, double* vel, double dt, int32_t n_
   if (nvt) {
     // thermostat half steps around each velocity-Verlet step
     VHIP_TRY(launch_thermostat_set(v->stream, v->d_thermo, nvt->state[0], nvt->state[1]), "thermostat state");
-    VHIP_TRY(launch_md_nvt_end(v->stream, vel, v->d_F, v->d_mass, c, N, false, v->d_thermo, nullptr, v->d_kepart),
-             "kinetic energy");
+    VHIP_TRY(launch_md_ke_partial(v->stream, vel, v->d_mass, N, v->d_kepart), "kinetic energy");
     VHIP_TRY(launch_thermostat(v->stream, v->d_kepart, md_nvt_parts(N), v->d_thermo, dt, nvt->Q, nvt->gkt,
                                KE_UNIT_EV, 2),
              "thermostat");
