@@ -330,3 +330,35 @@ def test_md_nvt_errors():
         assert ei.value.status == 1
     assert v.md_nvt(pt, vt, 1.0, 0, None, 300.0, 10.0, thermostat=(0.1, 0.2)) == (0.1, 0.2)
     v.close()
+
+
+@pytest.mark.timeout(600)
+def test_md_nvt_si8000_full_size():
+    """The paper's 8000-atom Si block under its HNEMD protocol (NVT at 300 K,
+    F_e = 0.1 / um along x; Sec. III.A): 2 steps of 1 fs against the oracle's
+    integrator over every atom, lists with a 1 A skin rebuilt every step (the
+    bond-list path)."""
+    import torch
+    from paper_2102_03691_amd import ModalVirial
+    announce("md nvt si8000 full size")
+    pos, box, m, vel = _start((10, 10, 10), 0.05, 41)
+    n, fe, temp, tau = 2, (1e-5, 0.0, 0.0), 300.0, 100.0
+    p = ov.tersoff_si()
+    ref = ov.md_nvt_hnemd(pos, vel, m, box, p, 1.0, n, fe, temp, tau)
+    N = len(pos)
+    v = ModalVirial(m, box, p, max_neighbors=24, skin=1.0)
+    pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+    vt = torch.as_tensor(vel, device="cuda:0").clone()
+    v.neighbors(pt)
+    v32 = torch.empty((n, N, 3), dtype=torch.float32, device="cuda:0")
+    W32 = torch.empty((n, N, 3, 3), dtype=torch.float32, device="cuda:0")
+    xi, eta = v.md_nvt(pt, vt, 1.0, n, fe, temp, tau, rebuild=1, v32=v32, W32=W32)
+    torch.cuda.synchronize()
+    v.close()
+    dx = float(np.abs(ov.min_image(pt.cpu().numpy() - ref["pos"][-1], box)).max())
+    dv = float(np.abs(vt.cpu().numpy() - ref["vel"][-1]).max() / np.abs(ref["vel"][-1]).max())
+    e = {"dx_A": dx, "dv_rel": dv, "v32_ulps": _ulps(v32.cpu().numpy(), ref["vel"]),
+         "W32_ulps": _ulps(W32.cpu().numpy(), ref["W"]), "xi_rel": abs(xi - ref["xi"][-1]) / abs(ref["xi"][-1])}
+    log("md_nvt_si8000_full", **e)
+    assert dx <= 1e-11 and dv <= 1e-11
+    assert e["v32_ulps"] <= 1.0 and e["W32_ulps"] <= 1.0 and e["xi_rel"] <= 1e-10
