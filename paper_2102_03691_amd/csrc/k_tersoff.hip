@@ -334,11 +334,72 @@ __device__ __forceinline__ void cutoff_fn(const TersoffParams& p, double r, doub
   }
 }
 
+// 1 / x for a positive normal x whose reciprocal is normal too: the hardware
+// estimate refined by two Newton steps, within about an ulp of the rounded
+// quotient (a full IEEE division adds scaling for the extremes of the range
+// and a final correctly rounded step)
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// Natural logarithm of a positive x (normal or subnormal): x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), log m = 2 atanh(s) with s = (m - 1) / (m + 1) summed as
+// its odd power series (Abramowitz and Stegun 4.1.27; |s| < 0.1716, so the
+// terms up to s^23 leave less than 1e-18), e ln 2 with ln 2 in two parts (the
+// first with 21 significant bits, so e times it is exact).  Within 3 ulps of
+// the true value from the subnormals up, at a fraction of the cost of the
+// library routine, which carries double-length sums.
+__device__ __forceinline__ double log_pos(double x) {
+  int e;
+  double m = frexp(x, &e);   // [0.5, 1)
+  if (m < 0.70710678118654752440) {
+    m += m;
+    --e;
+  }
+  const double s = (m - 1.0) * recip(m + 1.0);
+  const double s2 = s * s;
+  double t = 1.0 / 23.0;
+  t = fma(t, s2, 1.0 / 21.0);
+  t = fma(t, s2, 1.0 / 19.0);
+  t = fma(t, s2, 1.0 / 17.0);
+  t = fma(t, s2, 1.0 / 15.0);
+  t = fma(t, s2, 1.0 / 13.0);
+  t = fma(t, s2, 1.0 / 11.0);
+  t = fma(t, s2, 1.0 / 9.0);
+  t = fma(t, s2, 1.0 / 7.0);
+  t = fma(t, s2, 1.0 / 5.0);
+  t = fma(t, s2, 1.0 / 3.0);
+  const double lm = fma(2.0 * s * s2, t, 2.0 * s);
+  const double de = (double)e;
+  return fma(de, 0.6931467056274414, fma(de, 4.7493250390316726e-07, lm));
+}
+
+// log(1 + x) for x >= 0 by Goldberg's form x log(u) / (u - 1), u = 1 + x
+// rounded (exact where u = 1): within 5 ulps for x below 2^1020
+__device__ __forceinline__ double log1p_pos(double x) {
+  const double u = 1.0 + x;
+  return u == 1.0 ? x : (x * recip(u - 1.0)) * log_pos(u);
+}
+
+// g(cos theta) with t = cos theta - h, as gamma (1 + (c^2/d^2) t^2 / (d^2 + t^2)):
+// the same function as gamma (1 + c^2/d^2 - c^2 / (d^2 + t^2)) without the
+// cancellation of its two large terms (c^2/d^2 is about 4e7 for Si, g about 1e4)
+__device__ __forceinline__ double angle_g(const TersoffParams& p, double cs) {
+  const double t = cs - p.h;
+  const double t2 = t * t;
+  return fma(p.gc2d2 * t2, recip(p.d2 + t2), p.gamma);
+}
+
+// g and dg / dcos theta = 2 gamma c^2 t / (d^2 + t^2)^2
 __device__ __forceinline__ void angle_fn(const TersoffParams& p, double cs, double* g, double* dg) {
   const double t = cs - p.h;
-  const double inv = 1.0 / (p.d2 + t * t);
-  *g = p.gamma * (1.0 + p.c2d2 - p.c2 * inv);
-  *dg = p.gamma * p.c2 * 2.0 * t * inv * inv;
+  const double t2 = t * t;
+  const double inv = recip(p.d2 + t2);
+  *g = fma(p.gc2d2 * t2, inv, p.gamma);
+  *dg = p.g2c2 * t * inv * inv;
 }
 
 // exp(l3^m x^m) and its derivative in x (m = 1 or 3)
@@ -436,15 +497,16 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
       for (int q = 0; q < n; ++q) {
         if (q == s || sh[5][gb + q] == 0.0) continue;
         const int l = gb + q;
-        const double cs = (x[k] * sh[0][l] + y[k] * sh[1][l] + z[k] * sh[2][l]) * ir[k] * sh[4][l];
-        double g, dg, e, de;
-        angle_fn(p, cs, &g, &dg);
+        const double cs = (x[k] * sh[0][l] + y[k] * sh[1][l] + z[k] * sh[2][l]) * (ir[k] * sh[4][l]);
+        const double g = angle_g(p, cs);
+        double e, de;
         exp_fn(p, r[k] - sh[3][l], &e, &de);
-        zeta += sh[5][l] * g * e;
+        zeta = fma(sh[5][l] * g, e, zeta);
       }
-      // (beta zeta)^n and (1 + bz)^(-1/(2n)) through exp and log (zeta = 0 gives bz = 0)
-      const double bz = exp(p.n * log(p.beta * zeta));
-      b[k] = exp(-0.5 / p.n * log1p(bz));
+      // (beta zeta)^n and (1 + bz)^(-1/(2n)) through exp and log (bz = 0 where beta zeta = 0)
+      const double bzeta = p.beta * zeta;
+      const double bz = bzeta > 0.0 ? exp(p.n * log_pos(bzeta)) : 0.0;
+      b[k] = exp(p.ninv2 * log1p_pos(bz));
       // db/dzeta = -1/2 beta^n zeta^(n-1) (1 + (beta zeta)^n)^(-1/(2n) - 1) = -b bz / (2 zeta (1 + bz))
       const double db = zeta == 0.0 ? 0.0 : -0.5 * b[k] * bz / (zeta * (1.0 + bz));
       adb[k] = fc[k] * ea[k] * db;
@@ -474,29 +536,36 @@ __global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffPara
     // dU_i/dr_ij for this slot's pair j
     const double ux = x[k] * ir[k], uy = y[k] * ir[k], uz = z[k] * ir[k];
     const double radial = 0.5 * (dfc[k] * (er[k] - b[k] * ea[k]) + fc[k] * (-p.l1 * er[k] + p.l2 * b[k] * ea[k]));
+    const double ir2 = ir[k] * ir[k];
     double zx = 0.0, zy = 0.0, zz = 0.0;   // d zeta_ij / d r_ij
     double kx = 0.0, ky = 0.0, kz = 0.0;   // sum_{k != j} a_ik db_ik d zeta_ik / d r_ij
     for (int q = 0; q < n; ++q) {
       if (q == s || sh[5][gb + q] == 0.0) continue;
       const int l = gb + q;
-      const double qx = sh[0][l], qy = sh[1][l], qz = sh[2][l], rq = sh[3][l], irq = sh[4][l];
-      const double cs = (x[k] * qx + y[k] * qy + z[k] * qz) * ir[k] * irq;
-      // d cos theta / d r_ij
-      const double cx = qx * ir[k] * irq - cs * x[k] * ir[k] * ir[k];
-      const double cy = qy * ir[k] * irq - cs * y[k] * ir[k] * ir[k];
-      const double cz = qz * ir[k] * irq - cs * z[k] * ir[k] * ir[k];
+      const double qx = sh[0][l], qy = sh[1][l], qz = sh[2][l], rq = sh[3][l];
+      const double iri = ir[k] * sh[4][l];   // 1 / (r_ij r_ik)
+      const double cs = (x[k] * qx + y[k] * qy + z[k] * qz) * iri;
+      // d cos theta / d r_ij = r_ik / (r_ij r_ik) - cos theta r_ij / r_ij^2
+      const double cr = cs * ir2;
+      const double cx = fma(qx, iri, -x[k] * cr);
+      const double cy = fma(qy, iri, -y[k] * cr);
+      const double cz = fma(qz, iri, -z[k] * cr);
       double g, dg, e1, de1, e2, de2;
       angle_fn(p, cs, &g, &dg);
       exp_fn(p, r[k] - rq, &e1, &de1);
       exp_fn(p, rq - r[k], &e2, &de2);
+      // zeta_ij's term: f_C(r_ik) (g' e1 dcos/dr_ij + g e1' u_ij)
       const double fcq = sh[5][l];
-      zx += fcq * (dg * cx * e1 + g * de1 * ux);
-      zy += fcq * (dg * cy * e1 + g * de1 * uy);
-      zz += fcq * (dg * cz * e1 + g * de1 * uz);
+      const double za = fcq * dg * e1, zb = fcq * g * de1;
+      zx = fma(za, cx, fma(zb, ux, zx));
+      zy = fma(za, cy, fma(zb, uy, zy));
+      zz = fma(za, cz, fma(zb, uz, zz));
+      // zeta_ik's term through f_C(r_ij), g and e2 = exp(l3^m (r_ik - r_ij)^m), weighted by a_ik db_ik
       const double w = sh[6][l];
-      kx += w * (dfc[k] * g * e2 * ux + fc[k] * dg * cx * e2 - fc[k] * g * de2 * ux);
-      ky += w * (dfc[k] * g * e2 * uy + fc[k] * dg * cy * e2 - fc[k] * g * de2 * uy);
-      kz += w * (dfc[k] * g * e2 * uz + fc[k] * dg * cz * e2 - fc[k] * g * de2 * uz);
+      const double ka = w * fc[k] * dg * e2, kb = w * g * (dfc[k] * e2 - fc[k] * de2);
+      kx = fma(ka, cx, fma(kb, ux, kx));
+      ky = fma(ka, cy, fma(kb, uy, ky));
+      kz = fma(ka, cz, fma(kb, uz, kz));
     }
     a.dd[es] = radial * ux - 0.5 * (adb[k] * zx + kx);
     a.dd[mn + es] = radial * uy - 0.5 * (adb[k] * zy + ky);

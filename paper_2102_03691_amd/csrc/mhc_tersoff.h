@@ -50,9 +50,9 @@ struct BondBufs {
 };
 
 // Tersoff parameters as the kernels use them: l3m = lambda3^m, c2 = c^2, d2 = d^2,
-// c2d2 = c^2 / d^2.
+// c2d2 = c^2 / d^2, gc2d2 = gamma c^2 / d^2, g2c2 = 2 gamma c^2, ninv2 = -1 / (2n).
 struct TersoffParams {
-  double A, B, l1, l2, l3m, beta, n, c2, d2, c2d2, h, gamma, R, D;
+  double A, B, l1, l2, l3m, beta, n, c2, d2, c2d2, h, gamma, R, D, gc2d2, g2c2, ninv2;
   int m;
 };
 

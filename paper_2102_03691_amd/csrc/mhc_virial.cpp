@@ -223,7 +223,8 @@ mhc_status mhc_virial_create(int device, void* hip_stream, int64_t n_atoms, cons
   v->cg = make_grid(box, rc, n_atoms);
   const mhc_tersoff_params& p = *params;
   v->tp = TersoffParams{p.A, p.B, p.lambda1, p.lambda2, std::pow(p.lambda3, (double)p.m), p.beta, p.n, p.c * p.c,
-                        p.d * p.d, (p.c * p.c) / (p.d * p.d), p.h, p.gamma, p.R, p.D, p.m};
+                        p.d * p.d, (p.c * p.c) / (p.d * p.d), p.h, p.gamma, p.R, p.D,
+                        p.gamma * ((p.c * p.c) / (p.d * p.d)), 2.0 * p.gamma * (p.c * p.c), -0.5 / p.n, p.m};
   auto cleanup = [&](mhc_status st, const char* msg) {
     vfree(v);
     if (v->own_stream) (void)hipStreamDestroy(v->stream);
