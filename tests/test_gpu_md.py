@@ -11,7 +11,10 @@ oracle's integrator (oracle.virial.md_nve), through the C ABI:
   * total energy conserved over 400 steps of 512 atoms;
   * the device trajectory's float32 v and W pushed as one block into HNEMA +
     GKMA against the oracle's modal path on the oracle's trajectory;
-  * argument and state errors."""
+  * argument and state errors;
+  * NVT with the HNEMD drive against oracle.virial.md_nvt_hnemd, also at the
+    paper's 8000 atoms, and independent runs on their own streams, advanced by
+    concurrent host threads, in the same bits as each run alone."""
 import numpy as np
 import pytest
 
@@ -330,6 +333,57 @@ def test_md_nvt_errors():
         assert ei.value.status == 1
     assert v.md_nvt(pt, vt, 1.0, 0, None, 300.0, 10.0, thermostat=(0.1, 0.2)) == (0.1, 0.2)
     v.close()
+
+
+def test_md_nvt_independent_runs_on_threads():
+    """Independent runs (the paper averages many per material, Sec. III.A),
+    each with its own context on a stream of its own: three advanced by three
+    host threads at once end in the same bits (positions, velocities,
+    thermostat state, every step's float32 v and W) as each run alone."""
+    import threading
+    import torch
+    from paper_2102_03691_amd import ModalVirial
+    announce("md nvt independent runs on threads")
+    n, fe, R = 24, (1e-4, 0.0, 0.0), 3
+    starts = [_start((3, 3, 3), 0.05, 60 + r) for r in range(R)]
+
+    def run(r, out):
+        pos, box, m, vel = starts[r]
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            v = ModalVirial(m, box, ov.tersoff_si(), max_neighbors=24, skin=1.0, stream=s.cuda_stream)
+            pt = torch.as_tensor(np.mod(pos, box), device="cuda:0")
+            vt = torch.as_tensor(vel, device="cuda:0").clone()
+            v32 = torch.empty((n, len(pos), 3), dtype=torch.float32, device="cuda:0")
+            W32 = torch.empty((n, len(pos), 3, 3), dtype=torch.float32, device="cuda:0")
+            v.neighbors(pt)
+            th = v.md_nvt(pt, vt, 1.0, n, fe, 300.0, 20.0, rebuild=5, v32=v32, W32=W32)
+            s.synchronize()
+            v.close()
+        out[r] = (pt.cpu().numpy(), vt.cpu().numpy(), v32.cpu().numpy(), W32.cpu().numpy(), th)
+
+    alone, together, errors = {}, {}, []
+    for r in range(R):
+        run(r, alone)
+
+    def guarded(r):
+        try:
+            run(r, together)
+        except Exception as e:    # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=guarded, args=(r,)) for r in range(R)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    same = [all(np.array_equal(a, b) for a, b in zip(alone[r][:4], together[r][:4])) and alone[r][4] == together[r][4]
+            for r in range(R)]
+    log("md_nvt_threads", runs=R, same_bits=all(same))
+    assert all(same)
+    # the runs differ from each other (distinct seeds), so a mix-up would show
+    assert not np.array_equal(alone[0][1], alone[1][1])
 
 
 @pytest.mark.timeout(600)
