@@ -420,14 +420,18 @@ __device__ __forceinline__ void exp_fn(const TersoffParams& p, double x, double*
 // every lane reads them after a barrier.  All sums run over the slots in list
 // order, so the results do not depend on LPA and SPL.  With SPL = 2 a wave
 // whose atoms all have at most LPA pairs skips the second slot of every lane.
+// One wavefront per work-group: an atom's lanes never span two (LPA <= 64), so
+// the barriers only order the wave's own LDS traffic, and waves of unequal
+// length (atoms with more pairs) do not wait for each other.
+constexpr int SITE_WG = 64;
 template <int LPA, int SPL>
-__global__ void __launch_bounds__(256) k_tersoff_site(TersoffArgs a, TersoffParams p) {
-  __shared__ double sh[8][256 * SPL];
+__global__ void __launch_bounds__(SITE_WG) k_tersoff_site(TersoffArgs a, TersoffParams p) {
+  __shared__ double sh[8][SITE_WG * SPL];
   const int tid = threadIdx.x;
   const int s0 = tid & (LPA - 1);
   const int gb = (tid - s0) * SPL;   // this atom's slot 0 in LDS
   const int64_t N = a.N;
-  const int64_t i = ((int64_t)blockIdx.x * 256 + tid) / LPA;
+  const int64_t i = ((int64_t)blockIdx.x * SITE_WG + tid) / LPA;
   const int n = i < N ? a.n_nb[i] : 0;
   if (a.bond_need && *a.bond_need && n > 0) {
     // reverse slots of freshly built bond lists: bond s of i sits at the
@@ -730,7 +734,7 @@ static hipError_t launch_pair_kernels(hipStream_t s, const TersoffArgs& a, const
   // the site kernel for 5..8 pairs: 4 lanes x 2 slots (most atoms of a
   // crystal have 4 bonds, so most waves run one slot round)
   constexpr int SL = LPA == 8 ? 4 : LPA, SPL = LPA / SL;
-  hipLaunchKernelGGL((k_tersoff_site<SL, SPL>), dim3(blocks_of(a.N * SL, 256)), dim3(256), 0, s, a, p);
+  hipLaunchKernelGGL((k_tersoff_site<SL, SPL>), dim3(blocks_of(a.N * SL, SITE_WG)), dim3(SITE_WG), 0, s, a, p);
   if (e1) {
     hipError_t e = hipEventRecord(e1, s);
     if (e != hipSuccess) return e;
