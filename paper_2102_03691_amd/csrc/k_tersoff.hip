@@ -238,20 +238,26 @@ __global__ void __launch_bounds__(256) k_neighbors(const double* __restrict__ po
 // rev[s][i] = slot of i in the list of j = nbr[s][i] (-1 if absent, which a
 // symmetric distance test rules out; the host checks).  Lists are ascending
 // (k_neighbors sorts them), so the slot is found by bisection.
-__global__ void __launch_bounds__(256) k_reverse(int64_t N, const int* __restrict__ nbr, const int* __restrict__ n_nb,
-                                                 int* __restrict__ rev, int* __restrict__ missing) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One lane per (atom, slot): threadIdx.x runs over 64 consecutive atoms (so a
+// wave's list reads and writes are contiguous) and threadIdx.y over the slots
+// y, y + REV_SLOTS, ...; each lane finds i in j's sorted list by bisection.
+constexpr int REV_SLOTS = 16;
+__global__ void __launch_bounds__(64 * REV_SLOTS) k_reverse(int64_t N, const int* __restrict__ nbr,
+                                                            const int* __restrict__ n_nb, int* __restrict__ rev,
+                                                            int* __restrict__ missing) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (i >= N) return;
   const int n = n_nb[i];
-  for (int s = 0; s < n; ++s) {
+  for (int s = threadIdx.y; s < n; s += REV_SLOTS) {
     const int j = nbr[(int64_t)s * N + i];
-    int lo = 0, hi = n_nb[j];   // first slot of j's list whose entry is >= i
+    const int nj = n_nb[j];
+    int lo = 0, hi = nj;   // first slot of j's list whose entry is >= i
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (nbr[(int64_t)mid * N + j] < (int)i) lo = mid + 1;
       else hi = mid;
     }
-    const int r = lo < n_nb[j] && nbr[(int64_t)lo * N + j] == (int)i ? lo : -1;
+    const int r = lo < nj && nbr[(int64_t)lo * N + j] == (int)i ? lo : -1;
     rev[(int64_t)s * N + i] = r;
     if (r < 0) *missing = 1;
   }
@@ -724,7 +730,8 @@ hipError_t launch_neighbors(hipStream_t s, const double* pos, int64_t N, const C
   hipLaunchKernelGGL(k_cell_fill, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, b.cell_of, b.start, b.fill, b.atoms);
   hipLaunchKernelGGL(k_neighbors, dim3(blocks_of(N, 256)), dim3(256), 0, s, pos, N, cg, rc * rc,
                      rb * rb * (1.0 + 1e-12), b.cell_of, b.start, b.atoms, max_nb, b.nbr, b.n_nb, b.flags);
-  hipLaunchKernelGGL(k_reverse, dim3(blocks_of(N, 256)), dim3(256), 0, s, N, b.nbr, b.n_nb, b.rev, b.flags + 1);
+  hipLaunchKernelGGL(k_reverse, dim3(blocks_of(N, 64)), dim3(64, REV_SLOTS), 0, s, N, b.nbr, b.n_nb, b.rev,
+                     b.flags + 1);
   return hipGetLastError();
 }
 
