@@ -629,10 +629,15 @@ mhc_status mhc_virial_md_nvt(mhc_virial *v, double *pos, double *vel, double dt,
                              const double *fe, double temperature, double tau, double *thermostat, float *v32,
                              float *W32, double *F);
 
-/* HIP-event timing of each evaluation (mhc_virial_compute, and every force
- * evaluation of mhc_virial_md), as mhc_set_timing / mhc_kernel_timing: the
- * summed milliseconds of the per-atom site kernel (bond orders, site
- * energies, partials) and of the gather kernel (forces, W, F_ext) apart. */
+/* HIP-event timing of evaluations (mhc_virial_compute, and every force
+ * evaluation of mhc_virial_md / _md_nvt), as mhc_set_timing /
+ * mhc_kernel_timing: the summed milliseconds of the per-atom site kernel (bond
+ * orders, site energies, partials) and of the gather kernel (forces, W,
+ * F_ext) apart, and in launches the number of evaluations timed.  enable: 0
+ * off, k >= 1 events around every k-th evaluation from this call on (1: each;
+ * at a few thousand atoms an evaluation takes about as long as recording its
+ * events, so k > 1 keeps them from slowing what they time).  INVALID_ARG for
+ * enable < 0. */
 mhc_status mhc_virial_set_timing(mhc_virial *v, int enable);
 mhc_status mhc_virial_kernel_timing(mhc_virial *v, int64_t *launches, double *site_ms, double *gather_ms);
 

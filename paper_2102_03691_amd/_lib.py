@@ -786,7 +786,8 @@ class ModalVirial:
         self._check(self._lib.mhc_virial_synchronize(self._h), "virial synchronize")
 
     def set_timing(self, enable=True):
-        self._check(self._lib.mhc_virial_set_timing(self._h, int(bool(enable))), "virial set_timing")
+        """False / 0: off; True / 1: time every evaluation; k > 1: every k-th."""
+        self._check(self._lib.mhc_virial_set_timing(self._h, int(enable)), "virial set_timing")
 
     def kernel_timing(self):
         """(evaluations, summed site-kernel ms, summed gather-kernel ms) since the last call."""

@@ -61,7 +61,8 @@ struct mhc_virial {
   bool compact = false;
   int lpa = 4;            // lanes per atom of the evaluation kernels (from the largest neighbour count)
 
-  bool timing = false;
+  int timing_every = 0;    // events around every timing_every-th evaluation (0: none)
+  int64_t n_evals = 0;     // evaluations since timing was set
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
 };
@@ -82,10 +83,10 @@ mhc_status vfail(mhc_virial* v, mhc_status st, const std::string& msg) {
     if (e_ != hipSuccess) return vfail(v, MHC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Three events around the site and gather kernels of one evaluation when
-// timing is on (none otherwise).
+// Three events around the site and gather kernels of every timing_every-th
+// evaluation (none for the others, or with timing off).
 mhc_status timing_events(mhc_virial* v, hipEvent_t e[3]) {
-  if (!v->timing) return MHC_OK;
+  if (v->timing_every <= 0 || v->n_evals++ % v->timing_every != 0) return MHC_OK;
   if (v->ev_used + 3 > v->ev.size())
     for (int q = 0; q < 3; ++q) {
       hipEvent_t ev;
@@ -582,8 +583,9 @@ mhc_status mhc_virial_synchronize(mhc_virial* v) {
 mhc_status mhc_virial_set_timing(mhc_virial* v, int enable) {
   mhc_status st = venter(v);
   if (st) return st;
-  if (enable != 0 && enable != 1) return vfail(v, MHC_ERR_INVALID_ARG, "enable is 0 or 1");
-  v->timing = enable == 1;
+  if (enable < 0) return vfail(v, MHC_ERR_INVALID_ARG, "enable is 0 (off) or k >= 1 (every k-th evaluation)");
+  v->timing_every = enable;
+  v->n_evals = 0;
   return MHC_OK;
 }
 

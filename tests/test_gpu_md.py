@@ -241,6 +241,16 @@ def test_md_errors():
             v.md(pt, vt, dt, n, rebuild=rb)
         assert ei.value.status == 1
     v.md(pt, vt, 1.0, 0)                      # nothing to do
+    # timing events: every k-th evaluation (a 10-step call evaluates 11 times)
+    with pytest.raises(MhcError) as ei:
+        v.set_timing(-1)
+    assert ei.value.status == 1
+    for k, timed in ((3, 4), (1, 11)):
+        v.set_timing(k)
+        v.md(pt, vt, 1.0, 10)
+        launches, site_ms, gather_ms = v.kernel_timing()
+        assert launches == timed and site_ms > 0.0 and gather_ms > 0.0
+    v.set_timing(False)
     v.close()
 
 
