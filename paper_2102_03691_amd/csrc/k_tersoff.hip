@@ -647,13 +647,18 @@ __global__ void __launch_bounds__(256) k_tersoff_gather(TersoffArgs a, GatherArg
   const int64_t N = a.N;
   const int64_t i = ((int64_t)blockIdx.x * 256 + tid) / LPA;
   const int n = i < N ? a.n_nb[i] : 0;
+  // the pair's list entry and reverse slot are loaded with the count, not
+  // after it (the rows below max_nb exist; entries at or past n are not used)
+  const int64_t es = (int64_t)s * N + i;
+  const bool row = i < N && s < a.max_nb;
+  const int jl = row ? a.nbr[es] : 0, rl = row ? a.rev[es] : 0;
   double c[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) c[q] = 0.0;
   if (s < n) {
-    const int64_t mn = (int64_t)a.max_nb * N, es = (int64_t)s * N + i;
-    const int64_t j = a.nbr[es];
-    const int64_t ej = (int64_t)a.rev[es] * N + j;
+    const int64_t mn = (int64_t)a.max_nb * N;
+    const int64_t j = jl;
+    const int64_t ej = (int64_t)rl * N + j;
     const double r[3] = {min_image(a.pos[3 * j] - a.pos[3 * i], a.box[0], a.ibox[0]),
                          min_image(a.pos[3 * j + 1] - a.pos[3 * i + 1], a.box[1], a.ibox[1]),
                          min_image(a.pos[3 * j + 2] - a.pos[3 * i + 2], a.box[2], a.ibox[2])};
