@@ -465,8 +465,10 @@ mhc_status mhc_shc_save_state(mhc_shc *shc, void *buf, size_t *len);
 mhc_status mhc_shc_load_state(mhc_shc *shc, const void *buf, size_t len);
 mhc_status mhc_shc_synchronize(mhc_shc *shc);
 
-/* HIP-event timing of the virial-velocity product kernel of each pushed
- * block, as for mhc_set_timing / mhc_kernel_timing. */
+/* HIP-event timing of the virial-velocity product kernel of pushed blocks,
+ * as for mhc_set_timing / mhc_kernel_timing.  enable: 0 off, k >= 1 events
+ * around every k-th block from this call on (1: each); launches counts the
+ * blocks timed.  INVALID_ARG for enable < 0. */
 mhc_status mhc_shc_set_timing(mhc_shc *shc, int enable);
 mhc_status mhc_shc_kernel_timing(mhc_shc *shc, int64_t *launches, double *total_ms);
 

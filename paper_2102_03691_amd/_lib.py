@@ -571,8 +571,9 @@ class ModalSHC:
     def synchronize(self):
         self._check(self._lib.mhc_shc_synchronize(self._h), "shc synchronize")
 
-    def set_timing(self, enable: bool):
-        self._check(self._lib.mhc_shc_set_timing(self._h, int(bool(enable))), "shc set_timing")
+    def set_timing(self, enable=True):
+        """False / 0: off; True / 1: time every block; k > 1: every k-th."""
+        self._check(self._lib.mhc_shc_set_timing(self._h, int(enable)), "shc set_timing")
 
     def kernel_timing(self):
         n = C.c_int64()

@@ -50,7 +50,8 @@ struct mhc_shc {
   double* omega = nullptr;             // spectrum frequencies (grown on demand)
   double* kw = nullptr;                // [n_omega][3]
   int omega_cap = 0;
-  bool timing = false;
+  int timing_every = 0;                // events around every timing_every-th block (0: none)
+  int64_t n_timed_seen = 0;            // blocks since timing was set
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
 };
@@ -124,7 +125,7 @@ mhc_status shc_block(mhc_shc* c, const float* v, const float* W, int t_count) {
   SHIP_TRY(launch_shc_ring(c->stream, W, v, t_count, c->N, c->Np, c->ring, c->ring_len, c->ld, c->S, c->vt),
            "virial ring");
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing) {
+  if (c->timing_every > 0 && c->n_timed_seen++ % c->timing_every == 0) {
     while (c->ev_used + 2 > c->ev.size()) {
       hipEvent_t e;
       SHIP_TRY(hipEventCreate(&e), "event create");
@@ -451,8 +452,9 @@ mhc_status mhc_shc_synchronize(mhc_shc* c) {
 mhc_status mhc_shc_set_timing(mhc_shc* c, int enable) {
   mhc_status st = senter(c);
   if (st) return st;
-  if (enable != 0 && enable != 1) return sfail(c, MHC_ERR_INVALID_ARG, "enable is 0 or 1");
-  c->timing = enable;
+  if (enable < 0) return sfail(c, MHC_ERR_INVALID_ARG, "enable is 0 (off) or k >= 1 (every k-th block)");
+  c->timing_every = enable;
+  c->n_timed_seen = 0;
   c->ev_used = 0;
   return MHC_OK;
 }

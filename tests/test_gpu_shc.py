@@ -170,6 +170,17 @@ def test_shc_invalid_arguments():
     K, n = h.read()
     assert n == 3 and rel(K, oracle.shc_correlation(v, W, 8)) <= TOL
     assert not K[3:].any()
+    # timing events around every k-th block; k < 0 is an error
+    with pytest.raises(MhcError) as ei:
+        h.set_timing(-1)
+    assert ei.value.status == 1
+    for k, timed in ((3, 3), (1, 7)):
+        h.set_timing(k)
+        for _ in range(7):
+            h.push(v, W)
+        launches, ms = h.kernel_timing()
+        assert launches == timed and ms > 0.0
+    h.set_timing(False)
     h.close()
 
 
